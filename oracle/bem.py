@@ -1,0 +1,224 @@
+"""CPU oracle for the direct collocation BEM -- TEST INFRASTRUCTURE ONLY.
+
+Plain FP64 numpy on top of the C routines in bem_oracle.c.  Used by tests/, the smoke
+check and the benchmark's CPU-baseline leg; never by the product path.
+
+Definitions followed (paper, Sections 2-3):
+  * incident field psi_in = G(r, r_s), unit monopole (Eq. sp6)
+  * impedance condition -zeta dpsi/dn + i k psi = 0 with beta = 1/zeta (Eq. sp3),
+    so k/(i zeta) = -i k beta and gamma = -(dpsi_in/dn) + i k beta psi_in (Eq. sp7)
+  * direct BIE for psi_sc (Eq. dbem4):
+        (A x)_i = 1/2 x_i + sum_j M_ij x_j - i k sum_j L_ij beta_j x_j ,   b = L gamma
+    with the per-element admittance entering as a column scaling of L
+  * field off the surface from Green's representation (Eq. dbem1):
+        psi(r) = psi_in(r) + L[dpsi_sc/dn](r) - M[psi_sc](r),  dpsi_sc/dn = gamma + i k beta psi_sc
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+DEFAULT_ETA = 0.35
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.LIB
+        if not os.path.exists(path):
+            _build.build()
+        L = ctypes.CDLL(path)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int64)
+        i64, f64 = ctypes.c_int64, ctypes.c_double
+        L.oracle_geometry.argtypes = [i64, dp, ip, dp, dp, dp]
+        L.oracle_dense_LM.argtypes = [i64, dp, i64, ip, f64, f64, f64, f64, dp, dp]
+        L.oracle_layer_rows.argtypes = [i64, dp, i64, ip, f64, f64, f64, f64, i64, ip, dp, dp, dp]
+        L.oracle_field.argtypes = [i64, dp, i64, ip, f64, f64, f64, f64, i64, dp, dp, dp, dp]
+        L.oracle_pair.argtypes = [dp, dp, f64, f64, ctypes.c_int, f64, dp]
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _i(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+
+def _mesh(V, T):
+    return np.ascontiguousarray(V, np.float64), np.ascontiguousarray(T, np.int64)
+
+
+def geometry(V, T):
+    """Centroids, unit normals ((v1-v0)x(v2-v0) normalised) and areas of flat triangles."""
+    V, T = _mesh(V, T)
+    n = T.shape[0]
+    c, nrm, a = np.empty((n, 3)), np.empty((n, 3)), np.empty(n)
+    lib().oracle_geometry(n, _d(V), _i(T), _d(c), _d(nrm), _d(a))
+    return c, nrm, a
+
+
+def dense_LM(V, T, k, rc, eta=DEFAULT_ETA):
+    """Dense single- and double-layer matrices L_ij, M_ij (complex, N x N)."""
+    V, T = _mesh(V, T)
+    n = T.shape[0]
+    L = np.empty((n, n), np.complex128)
+    M = np.empty((n, n), np.complex128)
+    k = complex(k)
+    lib().oracle_dense_LM(V.shape[0], _d(V), n, _i(T), k.real, k.imag, float(rc), float(eta), _d(L), _d(M))
+    return L, M
+
+
+def layer_rows(V, T, k, rc, rows, sigma, mu, eta=DEFAULT_ETA):
+    """sum_j L_ij sigma_j + M_ij mu_j for the listed collocation rows (matrix-free)."""
+    V, T = _mesh(V, T)
+    rows = np.ascontiguousarray(rows, np.int64)
+    sigma = np.ascontiguousarray(sigma, np.complex128)
+    mu = np.ascontiguousarray(mu, np.complex128)
+    out = np.empty(rows.shape[0], np.complex128)
+    k = complex(k)
+    lib().oracle_layer_rows(V.shape[0], _d(V), T.shape[0], _i(T), k.real, k.imag, float(rc), float(eta),
+                            rows.shape[0], _i(rows), _d(sigma), _d(mu), _d(out))
+    return out
+
+
+def layer_field(V, T, k, rc, pts, sigma, mu, eta=DEFAULT_ETA):
+    """L[sigma](r) + M[mu](r) at off-surface points."""
+    V, T = _mesh(V, T)
+    pts = np.ascontiguousarray(np.atleast_2d(pts), np.float64)
+    sigma = np.ascontiguousarray(sigma, np.complex128)
+    mu = np.ascontiguousarray(mu, np.complex128)
+    out = np.empty(pts.shape[0], np.complex128)
+    k = complex(k)
+    lib().oracle_field(V.shape[0], _d(V), T.shape[0], _i(T), k.real, k.imag, float(rc), float(eta),
+                       pts.shape[0], _d(pts), _d(sigma), _d(mu), _d(out))
+    return out
+
+
+def pair(x, tri_xyz, k, self=False, eta=DEFAULT_ETA):
+    """Accurate (L_j(x), M_j(x)) for one triangle (3x3 vertex array)."""
+    x = np.ascontiguousarray(x, np.float64)
+    tri = np.ascontiguousarray(tri_xyz, np.float64)
+    out = np.empty(4)
+    k = complex(k)
+    lib().oracle_pair(_d(x), _d(tri), k.real, k.imag, int(self), float(eta), _d(out))
+    return out[0] + 1j * out[1], out[2] + 1j * out[3]
+
+
+# ----------------------------------------------------------------------------- problem data
+def green(x, y, k):
+    r = np.linalg.norm(np.asarray(x) - np.asarray(y), axis=-1)
+    return np.exp(1j * k * r) / (4 * np.pi * r)
+
+
+def incident(c, nrm, k, rs):
+    """psi_in and dpsi_in/dn at the points c with normals nrm (unit monopole at rs, Eq. sp6)."""
+    d = c - np.asarray(rs)[None, :]
+    r = np.linalg.norm(d, axis=1)
+    G = np.exp(1j * k * r) / (4 * np.pi * r)
+    dGdn = G * (1j * k * r - 1.0) * (d * nrm).sum(1) / r ** 2
+    return G, dGdn
+
+
+def gamma(c, nrm, beta, k, rs):
+    """gamma = -(dpsi_in/dn + k/(i zeta) psi_in) = -dpsi_in/dn + i k beta psi_in (Eq. sp7)."""
+    psi, dpsi = incident(c, nrm, k, rs)
+    return -dpsi + 1j * k * beta * psi
+
+
+def direct_system(V, T, k, beta, rs, rc, eta=DEFAULT_ETA):
+    """Dense A and b of Eq. (dbem4); also returns (L, M) and gamma."""
+    L, M = dense_LM(V, T, k, rc, eta)
+    c, nrm, _ = geometry(V, T)
+    n = T.shape[0]
+    A = 0.5 * np.eye(n) + M - 1j * k * L * beta[None, :]
+    g = gamma(c, nrm, beta, k, rs)
+    b = L @ g
+    return A, b, (L, M), g
+
+
+def direct_matvec_rows(V, T, k, beta, rc, x, rows, eta=DEFAULT_ETA):
+    """(A x)_i of Eq. (dbem4) for selected rows, without forming A."""
+    rows = np.asarray(rows, np.int64)
+    y = layer_rows(V, T, k, rc, rows, -1j * k * beta * x, x, eta)
+    return 0.5 * x[rows] + y
+
+
+def direct_rhs_rows(V, T, k, beta, rs, rc, rows, eta=DEFAULT_ETA):
+    c, nrm, _ = geometry(V, T)
+    g = gamma(c, nrm, beta, k, rs)
+    return layer_rows(V, T, k, rc, rows, g, np.zeros_like(g), eta)
+
+
+def direct_receivers(V, T, k, beta, rs, rc, x, pts, eta=DEFAULT_ETA):
+    """psi(r) = G(r, rs) + L[gamma + i k beta x](r) - M[x](r)   (Eq. dbem1)."""
+    c, nrm, _ = geometry(V, T)
+    g = gamma(c, nrm, beta, k, rs)
+    sc = layer_field(V, T, k, rc, pts, g + 1j * k * beta * x, -x, eta)
+    return green(pts, np.asarray(rs)[None, :], k) + sc
+
+
+# ----------------------------------------------------------------------------- dense solvers
+def solve_lu(A, b):
+    return np.linalg.solve(A, b)
+
+
+def gmres(A, b, tol=1e-10, restart=50, maxit=2000, x0=None, precond=None):
+    """Plain restarted (flexible) GMRES with modified Gram-Schmidt and Givens rotations.
+    `A` is a matrix or a callable; `precond` an optional callable z = P(v).
+    Returns (x, iterations, relative residual history)."""
+    mv = A if callable(A) else (lambda v: A @ v)
+    pc = precond if precond is not None else (lambda v: v)
+    n = b.shape[0]
+    x = np.zeros(n, np.complex128) if x0 is None else np.array(x0, np.complex128)
+    bn = np.linalg.norm(b)
+    hist, it = [], 0
+    while it < maxit:
+        r = b - mv(x)
+        beta0 = np.linalg.norm(r)
+        hist.append(beta0 / bn)
+        if beta0 / bn < tol:
+            break
+        Vk = np.zeros((restart + 1, n), np.complex128)
+        Z = np.zeros((restart, n), np.complex128)
+        H = np.zeros((restart + 1, restart), np.complex128)
+        cs, sn = np.zeros(restart, np.complex128), np.zeros(restart, np.complex128)
+        g = np.zeros(restart + 1, np.complex128)
+        g[0] = beta0
+        Vk[0] = r / beta0
+        j_done = 0
+        for j in range(restart):
+            Z[j] = pc(Vk[j])
+            w = mv(Z[j])
+            for i in range(j + 1):
+                H[i, j] = np.vdot(Vk[i], w)
+                w = w - H[i, j] * Vk[i]
+            H[j + 1, j] = np.linalg.norm(w)
+            if H[j + 1, j] != 0:
+                Vk[j + 1] = w / H[j + 1, j]
+            for i in range(j):
+                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+                H[i + 1, j] = -np.conj(sn[i]) * H[i, j] + cs[i] * H[i + 1, j]
+                H[i, j] = t
+            den = np.hypot(abs(H[j, j]), abs(H[j + 1, j]))
+            cs[j] = abs(H[j, j]) / den if den else 1.0
+            sn[j] = (H[j, j] / abs(H[j, j]) if H[j, j] != 0 else 1.0) * np.conj(H[j + 1, j]) / den if den else 0.0
+            H[j, j] = cs[j] * H[j, j] + sn[j] * H[j + 1, j]
+            H[j + 1, j] = 0.0
+            g[j + 1] = -np.conj(sn[j]) * g[j]
+            g[j] = cs[j] * g[j]
+            it += 1
+            j_done = j + 1
+            if abs(g[j + 1]) / bn < tol or it >= maxit:
+                break
+        y = np.linalg.solve(np.triu(H[:j_done, :j_done]), g[:j_done])
+        x = x + Z[:j_done].T @ y
+    return x, it, np.array(hist)
