@@ -1,0 +1,212 @@
+/*
+ * fmmbem -- fast-multipole boundary-element Helmholtz solver for room acoustics on one MI355X.
+ *
+ * C ABI.  The calls follow the statement of the problem in Section 2 of Gumerov & Duraiswami,
+ * "Fast multipole accelerated boundary element methods for room acoustics":
+ *   - a room surface S of flat triangles whose normals point out of the fluid (Section 2),
+ *   - a wavenumber k = omega / c (Eq. sp2),
+ *   - a locally reacting wall with specific impedance zeta (Eq. sp3), passed as the
+ *     admittance beta = 1/zeta so that a rigid wall is beta = 0 (Eq. sp5),
+ *   - unit monopole sources psi_in = G_k(r, r_s) (Eq. sp6),
+ * and the direct boundary integral equation for the scattered field (Eq. dbem4),
+ *   (A x)_i = 1/2 x_i + sum_j M_ij x_j - i k sum_j L_ij beta_j x_j ,   b = L gamma ,
+ *   gamma = -(dpsi_in/dn) + i k beta psi_in                         (Eq. sp7, k/(i zeta) = -i k beta),
+ * discretised with constant elements collocated at triangle centroids.  L and M are the single-
+ * and double-layer operators of Eq. (dbem2).  Entries of element pairs closer than the cutoff
+ * r_c are integrated accurately, the others by the one-point rule, and the far part of the
+ * product is evaluated by the fast multipole method of Section 3.3 (octree, multipole and local
+ * spherical expansions of Eq. shft0, rotation-coaxial-rotation translations with the stabilised
+ * coaxial recursion of Section 3.3.1), as the matrix-vector product inside flexible GMRES.
+ *
+ * Conventions
+ *   - Every call returns an int status (FMMBEM_OK = 0, negative = error) and, on error, sets a
+ *     per-context message readable with fmmbem_last_error().  Nothing aborts or throws across
+ *     the ABI.
+ *   - Host-array inputs are copied at the call; the caller keeps ownership.  Outputs go into
+ *     caller-allocated buffers of the documented size.  The context owns all device memory.
+ *   - Complex numbers are fmmbem_c64 {re, im} (same layout as C99 double _Complex).
+ *   - Vectors of unknowns are in the caller's triangle order.
+ *   - *_dev calls take device pointers (e.g. from torch tensors) and a hipStream_t passed as
+ *     void*; they enqueue on that stream and return when the work is enqueued or finished as
+ *     documented per call.
+ *   - One context per host thread; calls on one context are not thread-safe.
+ *   - Units are SI (m, 1/m).
+ */
+#ifndef FMMBEM_H
+#define FMMBEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fmmbem_ctx fmmbem_ctx;
+typedef struct {
+    double re, im;
+} fmmbem_c64;
+
+enum {
+    FMMBEM_OK = 0,
+    FMMBEM_ENOCONV = 1,     /* solve hit maxit: x is valid but not converged */
+    FMMBEM_EINVAL = -1,     /* bad argument (message says which) */
+    FMMBEM_ENOMEM = -2,     /* device allocation failed */
+    FMMBEM_EDEVICE = -3,    /* HIP runtime error */
+    FMMBEM_ENOTREADY = -4,  /* required input not set yet */
+    FMMBEM_EBREAKDOWN = -5, /* Krylov breakdown that is not a solution */
+    FMMBEM_ENAN = -6        /* non-finite value met in the solver */
+};
+
+/* formulations (Section 3.1 / 3.2) */
+enum { FMMBEM_DIRECT = 0 /* Eq. dbem4 */ };
+
+/* arithmetic of the matrix-vector product */
+enum {
+    FMMBEM_FP64 = 0,  /* every step in FP64 */
+    FMMBEM_MIXED = 1  /* near field and translations in FP32 with FP32 accumulation; tables,
+                         recursions and the Krylov algebra stay FP64 */
+};
+
+/* preconditioner slot of flexible GMRES (Section 4.4 names an inner FMM-GMRES and a diagonal one) */
+enum {
+    FMMBEM_PC_NONE = 0,
+    FMMBEM_PC_DIAG = 1,       /* z_i = v_i / (A_ii + diag_shift) */
+    FMMBEM_PC_NEARBLOCK = 2   /* exact inverse of the operator restricted to each octree leaf */
+};
+
+/* construction options; pass NULL for defaults */
+typedef struct {
+    double rc_factor;    /* near cutoff r_c = rc_factor * sqrt(2 * mean triangle area); default 1.8 */
+    double rc;           /* if > 0, absolute r_c in m (overrides rc_factor) */
+    int leaf_max;        /* octree depth: smallest uniform depth whose non-empty leaves hold at most
+                            leaf_max elements on average (subject to leaf side > r_c); default 64 */
+    int p_min;           /* minimum truncation number p (expansion degrees n < p); default 16 */
+    double digits;       /* target digits of the truncation rule
+                            p_l = max(p_min, ceil(kd + 1.8 digits^(2/3) kd^(1/3))), kd = k*sqrt(3)*d_l; default 7 */
+    double ktau_switch;  /* coaxial coefficients: original recursion if k*tau < ktau_switch,
+                            stabilised recursion otherwise (Section 3.3.1); default 1.0 */
+    int max_depth;       /* cap on the octree depth; default 12 */
+} fmmbem_options;
+
+void fmmbem_default_options(fmmbem_options *opt);
+
+/* Create a context on HIP device `hip_device`.  *out receives the handle. */
+int fmmbem_create(fmmbem_ctx **out, int hip_device, const fmmbem_options *opt);
+int fmmbem_destroy(fmmbem_ctx *ctx);
+const char *fmmbem_last_error(const fmmbem_ctx *ctx);
+
+/* Surface mesh.  xyz: nv*3 vertex coordinates (m).  tri: nt*3 vertex indices, each triangle
+ * ordered so that (v1-v0)x(v2-v0) points out of the fluid.  EINVAL on an index out of range, a
+ * degenerate (zero-area) triangle, or a closed mesh whose enclosed volume sum_j A_j (c_j.n_j)/3
+ * is not positive (inward normals). */
+int fmmbem_set_mesh(fmmbem_ctx *ctx, int64_t nv, const double *xyz, int64_t nt, const int64_t *tri);
+
+/* Wavenumber k = 2 pi f / c > 0 (Eq. sp2).  EINVAL if not finite and positive. */
+int fmmbem_set_wavenumber(fmmbem_ctx *ctx, double k);
+
+/* Admittance beta = 1/zeta per triangle (Eq. sp3/sp4), nt values; Re(beta) >= 0 (passive wall).
+ * beta = 0 is a rigid wall (Eq. sp5), beta = 1 absorbs normal incidence fully. */
+int fmmbem_set_admittance(fmmbem_ctx *ctx, const fmmbem_c64 *beta);
+
+/* Unit monopole sources (Eq. sp6): ns positions rs (ns*3), optional complex amplitudes (NULL = 1). */
+int fmmbem_set_sources(fmmbem_ctx *ctx, int32_t ns, const double *rs, const fmmbem_c64 *amp);
+
+/* Only FMMBEM_DIRECT is accepted. */
+int fmmbem_set_formulation(fmmbem_ctx *ctx, int formulation);
+
+/* Build what is out of date: octree and interaction lists (mesh), translation and rotation
+ * tables and near-field entries (k), preconditioner data.  Idempotent; matvec/solve call it. */
+int fmmbem_setup(fmmbem_ctx *ctx);
+
+/* Number of unknowns N (one per triangle for the direct formulation); -1 if no mesh. */
+int64_t fmmbem_num_unknowns(const fmmbem_ctx *ctx);
+
+/* Right-hand side b = L gamma of Eq. (dbem4), one vector of N per source: b is ns*N. */
+int fmmbem_rhs(fmmbem_ctx *ctx, fmmbem_c64 *b);
+
+/* y = A x for nrhs vectors (x, y: nrhs*N, host memory).  precision: FMMBEM_FP64 / FMMBEM_MIXED.
+ * With `exact_far` != 0 the far field is summed pair by pair instead of by the FMM (all-pairs
+ * O(N^2) product, for validation). */
+int fmmbem_matvec(fmmbem_ctx *ctx, int32_t nrhs, const fmmbem_c64 *x, fmmbem_c64 *y, int precision, int exact_far);
+
+/* Same on device pointers, enqueued on `stream` (hipStream_t); returns after enqueueing. */
+int fmmbem_matvec_dev(fmmbem_ctx *ctx, int32_t nrhs, const void *x_dev, void *y_dev, int precision, void *stream);
+
+typedef struct {
+    double tol;        /* relative residual target ||b - A x|| / ||b||; default 1e-6 */
+    int restart;       /* Krylov dimension m of FGMRES(m); default 30 */
+    int maxit;         /* total iteration cap; default 500 */
+    int precond;       /* FMMBEM_PC_*; default FMMBEM_PC_NEARBLOCK */
+    int precision;     /* arithmetic of the inner products A z: FMMBEM_FP64 or FMMBEM_MIXED */
+    double diag_shift; /* constant added to the diagonal in FMMBEM_PC_DIAG; default 0 */
+    int use_x0;        /* nonzero: x holds the initial guess on entry */
+} fmmbem_solve_opts;
+
+typedef struct {
+    int iters;            /* FGMRES iterations (= matrix-vector products after the first residual) */
+    int restarts;
+    double rel_res;       /* final relative residual measured with the FP64 FMM operator */
+    double t_setup_s;     /* setup seconds spent inside this call */
+    double t_solve_s;     /* iteration seconds */
+    int status;
+} fmmbem_solve_report;
+
+void fmmbem_default_solve_opts(fmmbem_solve_opts *o);
+
+/* Solve A x = b for source `isrc` (b from fmmbem_rhs) by flexible GMRES (Section 4.4).
+ * x: N values (in: initial guess if use_x0, out: solution).  Returns FMMBEM_OK on
+ * convergence, FMMBEM_ENOCONV at maxit (x still the best iterate), or an error. */
+int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, fmmbem_c64 *x,
+                 fmmbem_solve_report *rep);
+
+/* Total field at nr points inside the room from the solved surface field x of source isrc
+ * (Eq. dbem1): psi(r) = G(r, r_s) + L[gamma + i k beta x](r) - M[x](r).  psi: nr values. */
+int fmmbem_eval_field(fmmbem_ctx *ctx, int32_t isrc, int64_t nr, const double *r, const fmmbem_c64 *x,
+                      fmmbem_c64 *psi);
+
+/* ---- inspection (tests, benchmarks) ---------------------------------------------------- */
+
+typedef struct {
+    int64_t n;          /* unknowns */
+    double rc;          /* near cutoff used (m) */
+    double root_side;   /* bounding cube side D (m) */
+    double root_lo[3];  /* bounding cube corner */
+    int depth;          /* leaf level L (root = level 0) */
+    int64_t nleaf;      /* non-empty leaves */
+    int leaf_max_occ;   /* fullest leaf */
+    int64_t near_nnz;   /* accurate near entries incl. self */
+    int64_t p2p_pairs;  /* one-point-rule pairs evaluated per product by the near-field kernel */
+    int p[24];          /* truncation number per level (0 where unused) */
+    int64_t nbox[24];   /* boxes per level */
+    int64_t m2l_pairs[24];
+    double flops_m2l;   /* algorithmic flops of one product, per phase (FP64 real flops) */
+    double flops_m2m_l2l;
+    double flops_p2m_l2p;
+    double bytes_p2p;   /* algorithmic HBM bytes of the near-field kernel per product */
+} fmmbem_info;
+
+int fmmbem_get_info(fmmbem_ctx *ctx, fmmbem_info *info);
+
+/* Accurate near entries (sorted by row, caller order): count via *nnz when rows == NULL. */
+int fmmbem_near_entries(fmmbem_ctx *ctx, int64_t *nnz, int64_t *rows, int64_t *cols, fmmbem_c64 *L, fmmbem_c64 *M);
+
+/* Coaxial translation coefficients (Eq. shft0.1) computed on device `hip_device`:
+ * kind 0 = (S|R), 1 = (R|R); method 0 = original recursion, 1 = stabilised, -1 = by the
+ * ktau < 1 switch.  out: blocks m = 0..p-1, each (p-m)x(p-m) row-major (rows n' = m..p-1,
+ * cols n = m..p-1), sum_m (p-m)^2 complex values. */
+int fmmbem_coaxial_table(int hip_device, int kind, double ktau, int p, int method, fmmbem_c64 *out);
+
+/* Real rotation matrices Delta^n = T^n(R_y(pi/2)) for n < p, where
+ * Y_n^m(u) = sum_m' T^n_{mm'}(Q) Y_n^m'(Q u); block n is (2n+1)^2 row-major (rows m, cols m',
+ * index + n), sum_n (2n+1)^2 doubles. */
+int fmmbem_rotation_table(int hip_device, int p, double *out);
+
+/* Per-phase device time of the last matvec in milliseconds (hipEvent based):
+ * [0] densities, [1] P2P+near, [2] P2M, [3] M2M, [4] M2L, [5] L2L, [6] L2P+combine, [7] total. */
+int fmmbem_last_timings(fmmbem_ctx *ctx, double *ms8);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FMMBEM_H */

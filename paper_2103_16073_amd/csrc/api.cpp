@@ -1,0 +1,934 @@
+// C ABI of the fmmbem library: context, setup orchestration, the FMM matrix-vector product
+// driver, right-hand side, flexible GMRES solve and field evaluation.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <numeric>
+
+#include "internal.h"
+
+namespace fmm {
+// kernels (fmm.hip / solver.hip)
+__global__ void k_near_count(int64_t, const int32_t *, const int32_t *, const int32_t *, const int32_t *,
+                             const double4 *, double, int32_t *);
+__global__ void k_near_fill(int64_t, const int32_t *, const int32_t *, const int32_t *, const int32_t *,
+                            const double4 *, double, const int32_t *, int32_t *, int32_t *);
+__global__ void k_near_quad(int64_t, const int32_t *, const int32_t *, const double4 *, const double *, double,
+                            double2 *, double2 *);
+__global__ void k_densities(int64_t, const int32_t *, const double2 *, const double2 *, double, double2 *, double2 *);
+__global__ void k_gamma(int64_t, const double4 *, const double4 *, const double2 *, double, double, double, double,
+                        double2, double2 *, double2 *);
+__global__ void k_p2p(int, const int32_t *, const int32_t *, const int32_t *, int, const double4 *, const double4 *,
+                      const double2 *, const double2 *, double, double, const int32_t *, const int32_t *,
+                      const double2 *, const double2 *, double2 *);
+__global__ void k_p2m(int, int, int, const int32_t *, const double4 *, const double4 *, const double4 *,
+                      const double2 *, const double2 *, double, double2 *);
+__global__ void k_rot_fwd(int64_t, int, int, const double2 *, const int32_t *, const int16_t *, const double2 *,
+                          const double2 *, int, const double *, const double *, double2 *);
+__global__ void k_coax_apply(int64_t, int, int, int, int, const double2 *, const double2 *, const int8_t *, double2 *);
+__global__ void k_rot_back(int64_t, int, int, const double2 *, const int16_t *, const double2 *, const double2 *, int,
+                           const double *, const double *, double2 *);
+__global__ void k_reduce_jobs(int64_t, int, int, const int32_t *, const int32_t *, const double2 *, double2 *, int);
+__global__ void k_l2p(int, int, const int32_t *, const double4 *, const double4 *, const double2 *, double,
+                      const double2 *, double, const int32_t *, const double2 *, double2 *, int);
+__global__ void k_field(int64_t, const double *, const double4 *, const double4 *, const double *, const double2 *,
+                        const double2 *, double, double, double, double, double, double2, double2 *);
+__global__ void k_diag_inv(int64_t, const int32_t *, const int32_t *, const int32_t *, const double2 *,
+                           const double2 *, const double2 *, double, double, double2 *);
+__global__ void k_mul_diag(int64_t, const double2 *, const double2 *, double2 *);
+__global__ void k_leaf_blocks(int, const int32_t *, const int64_t *, const double4 *, const double4 *,
+                              const double2 *, double, double, const int32_t *, const int32_t *, const double2 *,
+                              const double2 *, double2 *);
+__global__ void k_leaf_invert(int, const int32_t *, const int64_t *, double2 *, int32_t *, int *);
+__global__ void k_leaf_apply(int, const int32_t *, const int64_t *, const double2 *, const int32_t *,
+                             const double2 *, double2 *);
+void box_center(const TreeHost &T, int l, uint64_t code, double *c);
+int fgmres(int64_t n, hipStream_t st, DeviceBuffers &scr, const std::function<void(const double2 *, double2 *)> &matvec,
+           const std::function<void(const double2 *, double2 *)> &matvec_check,
+           const std::function<void(const double2 *, double2 *)> &precond, const double2 *b, double2 *x, double tol,
+           int m, int maxit, bool x0_given, int &iters, int &restarts, double &rel_res);
+
+// ------------------------------------------------------------------ setup pieces
+static int level_p(const fmmbem_options &o, double k, double side) {
+    double kd = k * std::sqrt(3.0) * side;
+    double p = kd + 1.8 * std::pow(o.digits, 2.0 / 3.0) * std::cbrt(kd);
+    return std::max(o.p_min, (int)std::ceil(p));
+}
+
+template <class T>
+static T *upload(DeviceBuffers &b, const std::string &name, const std::vector<T> &v, hipStream_t st) {
+    T *d = dget<T>(b, name, std::max<size_t>(v.size(), 1));
+    if (!v.empty()) HIP_OK(hipMemcpyAsync(d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st));
+    return d;
+}
+
+static void setup_mesh(fmmbem_ctx *c) {
+    const int64_t n = c->nt;
+    std::vector<double> cen(3 * n), nrm(3 * n), area(n);
+    double vlo[3] = {1e300, 1e300, 1e300}, vhi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t v = 0; v < c->nv; ++v)
+        for (int d = 0; d < 3; ++d) {
+            vlo[d] = std::min(vlo[d], c->xyz[3 * v + d]);
+            vhi[d] = std::max(vhi[d], c->xyz[3 * v + d]);
+        }
+    double asum = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+        const double *a = &c->xyz[3 * c->tri[3 * j]], *b = &c->xyz[3 * c->tri[3 * j + 1]], *e = &c->xyz[3 * c->tri[3 * j + 2]];
+        double u[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]}, v[3] = {e[0] - a[0], e[1] - a[1], e[2] - a[2]};
+        double w[3] = {u[1] * v[2] - u[2] * v[1], u[2] * v[0] - u[0] * v[2], u[0] * v[1] - u[1] * v[0]};
+        double l = std::sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+        for (int d = 0; d < 3; ++d) {
+            cen[3 * j + d] = (a[d] + b[d] + e[d]) / 3.0;
+            nrm[3 * j + d] = w[d] / l;
+        }
+        area[j] = 0.5 * l;
+        asum += area[j];
+    }
+    c->rc = c->opt.rc > 0 ? c->opt.rc : c->opt.rc_factor * std::sqrt(2.0 * asum / (double)n);
+    TreeHost &T = c->tree;
+    build_tree(cen.data(), n, vlo, vhi, c->rc, c->opt.leaf_max, c->opt.max_depth, T);
+    const int L = T.depth;
+    hipStream_t st = c->stream;
+    // sorted element arrays
+    std::vector<double4> ec(n), en(n);
+    std::vector<double> ev(9 * n);
+    std::vector<int32_t> leaf_of(n);
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t j = T.perm[i];
+        ec[i] = make_double4(cen[3 * j], cen[3 * j + 1], cen[3 * j + 2], area[j]);
+        en[i] = make_double4(nrm[3 * j], nrm[3 * j + 1], nrm[3 * j + 2], 0.0);
+        for (int q = 0; q < 3; ++q)
+            for (int d = 0; d < 3; ++d) ev[9 * i + 3 * q + d] = c->xyz[3 * c->tri[3 * j + q] + d];
+    }
+    const int64_t nleaf = (int64_t)T.leaf_start.size() - 1;
+    for (int64_t b = 0; b < nleaf; ++b)
+        for (int32_t i = T.leaf_start[b]; i < T.leaf_start[b + 1]; ++i) leaf_of[i] = (int32_t)b;
+    upload(c->buf, "ec", ec, st);
+    upload(c->buf, "en", en, st);
+    upload(c->buf, "ev", ev, st);
+    upload(c->buf, "perm", T.perm, st);
+    upload(c->buf, "leaf_of", leaf_of, st);
+    upload(c->buf, "leaf_start", T.leaf_start, st);
+    upload(c->buf, "nbr_start", T.nbr_start, st);
+    upload(c->buf, "nbr_list", T.nbr_list, st);
+    // P2P pairs (one-point rule candidates) for reporting
+    int64_t pairs = 0;
+    for (int64_t b = 0; b < nleaf; ++b) {
+        int64_t nt_ = T.leaf_start[b + 1] - T.leaf_start[b], ns = 0;
+        for (int q = T.nbr_start[b]; q < T.nbr_start[b + 1]; ++q)
+            ns += T.leaf_start[T.nbr_list[q] + 1] - T.leaf_start[T.nbr_list[q]];
+        pairs += nt_ * ns;
+    }
+    c->p2p_pairs = pairs;
+    // levels: centres, parents, M2L lists, child ranges
+    c->lev.assign(L + 1, LevelDev());
+    c->iota_h.assign(L + 1, std::vector<int32_t>());
+    for (int l = 0; l <= L; ++l) {
+        LevelHost &H = T.lv[l];
+        LevelDev &D = c->lev[l];
+        D.nbox = (int64_t)H.code.size();
+        D.side = H.side;
+        std::vector<double4> cc(D.nbox);
+        for (int64_t b = 0; b < D.nbox; ++b) {
+            double x[3];
+            box_center(T, l, H.code[b], x);
+            cc[b] = make_double4(x[0], x[1], x[2], 0.0);
+        }
+        std::string s = "L" + std::to_string(l) + "_";
+        D.center = upload(c->buf, s + "center", cc, st);
+        if (l >= 1) {
+            D.parent = upload(c->buf, s + "parent", H.parent, st);
+            D.octant = upload(c->buf, s + "octant", H.octant, st);
+            // M2M / L2L directions per child
+            std::vector<int16_t> up(D.nbox), dn(D.nbox);
+            for (int64_t b = 0; b < D.nbox; ++b) {
+                up[b] = (int16_t)(343 + H.octant[b]);
+                dn[b] = (int16_t)(351 + H.octant[b]);
+            }
+            upload(c->buf, s + "dir_up", up, st);
+            upload(c->buf, s + "dir_dn", dn, st);
+            std::vector<int32_t> iota_(D.nbox + 1);
+            std::iota(iota_.begin(), iota_.end(), 0);
+            upload(c->buf, s + "iota", iota_, st);
+            c->iota_h[l] = iota_;
+        }
+        if (l < L) D.child_start = upload(c->buf, s + "child_start", H.child_start, st);
+        if (l >= 2) {
+            D.njob_m2l = (int64_t)H.m2l_src.size();
+            D.m2l_start = upload(c->buf, s + "m2l_start", H.m2l_start, st);
+            D.m2l_src = upload(c->buf, s + "m2l_src", H.m2l_src, st);
+            D.m2l_dir = upload(c->buf, s + "m2l_dir", H.m2l_dir, st);
+            std::vector<int8_t> tau(H.m2l_dir.size());
+            for (size_t q = 0; q < tau.size(); ++q) tau[q] = (int8_t)H.m2l_tau_of_dir[H.m2l_dir[q]];
+            D.m2l_tau = upload(c->buf, s + "m2l_tau", tau, st);
+            D.ntau = (int)H.m2l_taus.size();
+        }
+    }
+    HIP_OK(hipStreamSynchronize(st));
+}
+
+static void direction_phases(int PH, std::vector<double2> &A, std::vector<double2> &B) {
+    A.assign((size_t)NDIR * (2 * PH + 1), cmk(0, 0));
+    B.assign((size_t)NDIR * (2 * PH + 1), cmk(0, 0));
+    for (int d = 0; d < NDIR; ++d) {
+        double t[3];
+        if (d < 343) {
+            t[0] = d / 49 - 3;
+            t[1] = (d / 7) % 7 - 3;
+            t[2] = d % 7 - 3;
+        } else {
+            int o = (d - 343) % 8;
+            double sgn = d < 351 ? -1.0 : 1.0;  // M2M: parent - child; L2L: child - parent
+            t[0] = sgn * ((o & 1) ? 1.0 : -1.0);
+            t[1] = sgn * ((o & 2) ? 1.0 : -1.0);
+            t[2] = sgn * ((o & 4) ? 1.0 : -1.0);
+        }
+        double tn = std::sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+        if (tn == 0) continue;
+        double beta = std::acos(std::max(-1.0, std::min(1.0, t[2] / tn)));
+        double alpha = (t[0] == 0 && t[1] == 0) ? 0.0 : std::atan2(t[1], t[0]);
+        for (int m = -PH; m <= PH; ++m) {
+            double2 ea = cmk(std::cos(m * alpha), std::sin(m * alpha));
+            A[(size_t)d * (2 * PH + 1) + m + PH] = cmul(ea, ipow(-m));  // e^{i m a} (-i)^m
+            B[(size_t)d * (2 * PH + 1) + m + PH] = cmk(std::cos(m * beta), std::sin(m * beta));
+        }
+    }
+}
+
+static void setup_k(fmmbem_ctx *c) {
+    TreeHost &T = c->tree;
+    const int L = T.depth;
+    hipStream_t st = c->stream;
+    // truncation numbers
+    c->pmax = 0;
+    for (int l = 2; l <= L; ++l) {
+        c->lev[l].p = level_p(c->opt, c->k, c->lev[l].side);
+        T.lv[l].p = c->lev[l].p;
+        c->pmax = std::max(c->pmax, c->lev[l].p);
+    }
+    if (c->pmax > 1000) throw FmmError(FMMBEM_EINVAL, "truncation number above 1000: octree too shallow for this k");
+    // rotation tables (frequency independent; rebuilt only when p grows)
+    if (c->pmax > c->delta_p) {
+        double *D = dget<double>(c->buf, "delta", rot_table_size(c->pmax));
+        double *DT = dget<double>(c->buf, "deltaT", rot_table_size(c->pmax));
+        build_delta_table(c->pmax, D, DT, st);
+        std::vector<double2> A, B;
+        direction_phases(c->pmax, A, B);
+        upload(c->buf, "phA", A, st);
+        upload(c->buf, "phB", B, st);
+        c->delta_p = c->pmax;
+    }
+    // coaxial tables
+    std::vector<CoaxJob> jobs;
+    for (int l = 2; l <= L; ++l) {
+        LevelDev &D = c->lev[l];
+        const int p = D.p;
+        std::string s = "L" + std::to_string(l) + "_";
+        D.coax_m2l = dget<double2>(c->buf, s + "coax_m2l", (size_t)coax_table_size(p) * std::max(D.ntau, 1));
+        for (int q = 0; q < D.ntau; ++q) {
+            double kt = c->k * T.lv[l].m2l_taus[q];
+            jobs.push_back({0, kt < c->opt.ktau_switch ? 0 : 1, p, kt, D.coax_m2l + (size_t)q * coax_table_size(p)});
+        }
+        if (l < L) {
+            const int PT = std::max(p, c->lev[l + 1].p);
+            D.coax_up = dget<double2>(c->buf, s + "coax_up", coax_table_size(PT));
+            double kt = c->k * std::sqrt(3.0) * 0.5 * c->lev[l + 1].side;
+            jobs.push_back({1, kt < c->opt.ktau_switch ? 0 : 1, PT, kt, D.coax_up});
+        }
+        D.M = dget<double2>(c->buf, s + "M", (size_t)D.nbox * p * p);
+        D.L = dget<double2>(c->buf, s + "L", (size_t)D.nbox * p * p);
+    }
+    build_coax_tables(jobs, c->scratch, st);
+    // near-field table
+    const int64_t n = c->nt;
+    const int nleaf = (int)T.leaf_start.size() - 1;
+    int32_t *cnt = dget<int32_t>(c->scratch, "near_cnt", n);
+    const double rc2 = c->rc * c->rc;
+    auto ec = (const double4 *)c->buf.find("ec");
+    k_near_count<<<ceil_div(n, 128), 128, 0, st>>>(n, (int32_t *)c->buf.find("leaf_of"), (int32_t *)c->buf.find("leaf_start"),
+                                                   (int32_t *)c->buf.find("nbr_start"), (int32_t *)c->buf.find("nbr_list"),
+                                                   ec, rc2, cnt);
+    LAUNCH_OK();
+    std::vector<int32_t> hc(n), start(n + 1, 0);
+    HIP_OK(hipMemcpyAsync(hc.data(), cnt, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    for (int64_t i = 0; i < n; ++i) start[i + 1] = start[i] + hc[i];
+    c->near_nnz = start[n];
+    int32_t *dstart = upload(c->buf, "near_start", start, st);
+    int32_t *drow = dget<int32_t>(c->buf, "near_row", c->near_nnz);
+    int32_t *dcol = dget<int32_t>(c->buf, "near_col", c->near_nnz);
+    k_near_fill<<<ceil_div(n, 128), 128, 0, st>>>(n, (int32_t *)c->buf.find("leaf_of"), (int32_t *)c->buf.find("leaf_start"),
+                                                  (int32_t *)c->buf.find("nbr_start"), (int32_t *)c->buf.find("nbr_list"),
+                                                  ec, rc2, dstart, drow, dcol);
+    LAUNCH_OK();
+    double2 *nL = dget<double2>(c->buf, "near_L", c->near_nnz), *nM = dget<double2>(c->buf, "near_M", c->near_nnz);
+    k_near_quad<<<ceil_div(c->near_nnz, 128), 128, 0, st>>>(c->near_nnz, drow, dcol, ec, (double *)c->buf.find("ev"),
+                                                            c->k, nL, nM);
+    LAUNCH_OK();
+    (void)nleaf;
+    HIP_OK(hipStreamSynchronize(st));
+}
+
+static void ensure_setup(fmmbem_ctx *c) {
+    if (!c->have_mesh) throw FmmError(FMMBEM_ENOTREADY, "mesh not set");
+    if (!c->have_k) throw FmmError(FMMBEM_ENOTREADY, "wavenumber not set");
+    auto t0 = std::chrono::steady_clock::now();
+    bool any = c->mesh_dirty || c->k_dirty || c->beta_dirty;
+    if (c->mesh_dirty) {
+        setup_mesh(c);
+        c->k_dirty = true;
+        c->beta_dirty = true;
+        c->mesh_dirty = false;
+    }
+    if (c->k_dirty) {
+        setup_k(c);
+        c->k_dirty = false;
+        c->precond_ready_nb = c->precond_ready_diag = false;
+    }
+    if (c->beta_dirty) {
+        if (!c->have_beta) c->beta.assign(c->nt, cmk(0, 0));
+        std::vector<double2> bs(c->nt);
+        for (int64_t i = 0; i < c->nt; ++i) bs[i] = c->beta[c->tree.perm[i]];
+        upload(c->buf, "beta", bs, c->stream);
+        HIP_OK(hipStreamSynchronize(c->stream));
+        c->beta_dirty = false;
+        c->precond_ready_nb = c->precond_ready_diag = false;
+    }
+    if (any) c->t_setup_last = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// ------------------------------------------------------------------ the FMM pass
+// Staged translation of a batch of jobs (grouped by target) from `src` (psrc) into `dst` (ptgt).
+static void translate(fmmbem_ctx *c, int64_t njob, int psrc, int ptgt, int PT, const double2 *src,
+                      const int32_t *src_idx, const int16_t *dir, const double2 *tables, const int8_t *tau,
+                      double2 *dst, const std::vector<int32_t> &gstart_h, const int32_t *gstart_d, int64_t ngroups,
+                      int accumulate) {
+    if (ngroups == 0) return;
+    hipStream_t st = c->stream;
+    const int P = std::max(psrc, ptgt);
+    const double *D = (double *)c->buf.find("delta"), *DT = (double *)c->buf.find("deltaT");
+    const double2 *phA = (double2 *)c->buf.find("phA"), *phB = (double2 *)c->buf.find("phB");
+    const int PH = c->delta_p;
+    // chunk by groups so that two job buffers stay under ~8 GiB
+    const int64_t max_jobs = std::max<int64_t>(1, (int64_t(1) << 29) / ((int64_t)P * P));
+    int64_t g0 = 0;
+    while (g0 < ngroups) {
+        int64_t g1 = g0;
+        const int64_t j0 = gstart_h[g0];
+        while (g1 < ngroups && (gstart_h[g1 + 1] - j0 <= max_jobs || g1 == g0)) ++g1;
+        const int64_t nj = gstart_h[g1] - j0;
+        if (nj > 0) {
+            double2 *W = dget<double2>(c->scratch, "W1", (size_t)nj * P * P);
+            double2 *W2 = dget<double2>(c->scratch, "W2", (size_t)nj * P * P);
+            size_t sh = sizeof(double2) * 4 * P;
+            k_rot_fwd<<<(unsigned)nj, 256, sh, st>>>(nj, psrc, P, src, src_idx + j0, dir + j0, phA, phB, PH, D, DT, W);
+            LAUNCH_OK();
+            k_coax_apply<<<(unsigned)nj, 256, 0, st>>>(nj, psrc, ptgt, P, PT, W, tables, tau ? tau + j0 : nullptr, W2);
+            LAUNCH_OK();
+            k_rot_back<<<(unsigned)nj, 256, sh, st>>>(nj, ptgt, P, W2, dir + j0, phA, phB, PH, D, DT, W);
+            LAUNCH_OK();
+        }
+        // group starts relative to j0
+        std::vector<int32_t> gs(g1 - g0 + 1);
+        for (int64_t g = g0; g <= g1; ++g) gs[g - g0] = gstart_h[g] - (int32_t)j0;
+        int32_t *dgs = upload(c->scratch, "gs_chunk", gs, st);
+        double2 *Wr = (double2 *)c->scratch.find("W1");
+        if (!Wr) Wr = dget<double2>(c->scratch, "W1", 16);
+        k_reduce_jobs<<<(unsigned)(g1 - g0), 256, 0, st>>>(g1 - g0, ptgt, P, dgs, nullptr, Wr,
+                                                           dst + g0 * (int64_t)ptgt * ptgt, accumulate);
+        LAUNCH_OK();
+        HIP_OK(hipStreamSynchronize(st));  // gs_chunk / W reuse
+        g0 = g1;
+    }
+    (void)gstart_d;
+}
+
+// y (caller order) = half * x + L[sigma] + M[mu] at the centroids; sigma/mu in sorted order.
+static void fmm_pass(fmmbem_ctx *c, const double2 *sigma, const double2 *mu, const double2 *x, double half, double2 *y,
+                     bool exact_far) {
+    TreeHost &T = c->tree;
+    const int L = T.depth;
+    hipStream_t st = c->stream;
+    const int64_t n = c->nt;
+    const int nleaf = (int)T.leaf_start.size() - 1;
+    auto I32 = [&](const char *s) { return (int32_t *)c->buf.find(s); };
+    const double4 *ec = (double4 *)c->buf.find("ec"), *en = (double4 *)c->buf.find("en");
+    double2 *ynear = dget<double2>(c->scratch, "ynear", n);
+    HIP_OK(hipEventRecord(c->ev[1], st));
+    k_p2p<<<nleaf, 64, 0, st>>>(nleaf, I32("leaf_start"), I32("nbr_start"), I32("nbr_list"), exact_far ? 1 : 0, ec, en,
+                                sigma, mu, c->k, c->rc * c->rc, I32("near_start"), I32("near_col"),
+                                (double2 *)c->buf.find("near_L"), (double2 *)c->buf.find("near_M"), ynear);
+    LAUNCH_OK();
+    HIP_OK(hipEventRecord(c->ev[2], st));
+    if (!exact_far) {
+        LevelDev &LL = c->lev[L];
+        const int p = LL.p;
+        const int TB = (p + 1) * (p + 2) / 2;
+        const int per = TB * 16 + (p + 2) * 8 + 88;
+        if (per > 60000) throw FmmError(FMMBEM_EINVAL, "leaf truncation number too large for P2M staging");
+        int CH = std::max(1, std::min(32, 60000 / per));
+        size_t sh = (size_t)CH * per;
+        k_p2m<<<nleaf, 256, sh, st>>>(nleaf, p, CH, I32("leaf_start"), LL.center, ec, en, sigma, mu, c->k, LL.M);
+        LAUNCH_OK();
+        HIP_OK(hipEventRecord(c->ev[3], st));
+        // M2M up
+        for (int l = L - 1; l >= 2; --l) {
+            LevelDev &P_ = c->lev[l], &C_ = c->lev[l + 1];
+            std::string s = "L" + std::to_string(l + 1) + "_";
+            translate(c, C_.nbox, C_.p, P_.p, std::max(P_.p, C_.p), C_.M, (int32_t *)c->buf.find(s + "iota"),
+                      (int16_t *)c->buf.find(s + "dir_up"), P_.coax_up, nullptr, P_.M, T.lv[l].child_start,
+                      P_.child_start, P_.nbox, 0);
+        }
+        HIP_OK(hipEventRecord(c->ev[4], st));
+        // M2L and L2L down
+        float t_m2l = 0, t_l2l = 0;
+        (void)t_m2l;
+        (void)t_l2l;
+        for (int l = 2; l <= L; ++l) {
+            LevelDev &D = c->lev[l];
+            translate(c, D.njob_m2l, D.p, D.p, D.p, D.M, D.m2l_src, D.m2l_dir, D.coax_m2l, D.m2l_tau, D.L,
+                      T.lv[l].m2l_start, D.m2l_start, D.nbox, 0);
+            if (l >= 3) {
+                LevelDev &P_ = c->lev[l - 1];
+                std::string s = "L" + std::to_string(l) + "_";
+                translate(c, D.nbox, P_.p, D.p, std::max(P_.p, D.p), P_.L, D.parent,
+                          (int16_t *)c->buf.find(s + "dir_dn"), P_.coax_up, nullptr, D.L, c->iota_h[l],
+                          (int32_t *)c->buf.find(s + "iota"), D.nbox, 1);
+            }
+        }
+        HIP_OK(hipEventRecord(c->ev[5], st));
+    } else {
+        for (int e = 3; e <= 5; ++e) HIP_OK(hipEventRecord(c->ev[e], st));
+    }
+    HIP_OK(hipEventRecord(c->ev[6], st));
+    LevelDev &LL = c->lev[L];
+    k_l2p<<<nleaf, 64, (size_t)64 * (LL.p + 2) * sizeof(double), st>>>(
+        nleaf, LL.p, I32("leaf_start"), LL.center, ec, LL.L, c->k, ynear, half, I32("perm"), x, y, exact_far ? 0 : 1);
+    LAUNCH_OK();
+    HIP_OK(hipEventRecord(c->ev[7], st));
+}
+
+static void matvec_dev(fmmbem_ctx *c, const double2 *x, double2 *y, bool exact_far) {
+    hipStream_t st = c->stream;
+    const int64_t n = c->nt;
+    double2 *sigma = dget<double2>(c->scratch, "sigma", n), *mu = dget<double2>(c->scratch, "mu", n);
+    HIP_OK(hipEventRecord(c->ev[0], st));
+    k_densities<<<ceil_div(n, 256), 256, 0, st>>>(n, (int32_t *)c->buf.find("perm"), x, (double2 *)c->buf.find("beta"),
+                                                  c->k, sigma, mu);
+    LAUNCH_OK();
+    fmm_pass(c, sigma, mu, x, 0.5, y, exact_far);
+    HIP_OK(hipEventRecord(c->ev[8], st));
+}
+
+static void read_timings(fmmbem_ctx *c) {
+    HIP_OK(hipEventSynchronize(c->ev[8]));
+    float t;
+    auto el = [&](int a, int b) {
+        HIP_OK(hipEventElapsedTime(&t, c->ev[a], c->ev[b]));
+        return (double)t;
+    };
+    c->last.ms[0] = el(0, 1);
+    c->last.ms[1] = el(1, 2);
+    c->last.ms[2] = el(2, 3);
+    c->last.ms[3] = el(3, 4);
+    c->last.ms[4] = el(4, 5);  // M2L + L2L
+    c->last.ms[5] = 0.0;
+    c->last.ms[6] = el(6, 7);
+    c->last.ms[7] = el(0, 8);
+}
+
+static void rhs_dev(fmmbem_ctx *c, int isrc, double2 *b) {
+    hipStream_t st = c->stream;
+    const int64_t n = c->nt;
+    double2 *sigma = dget<double2>(c->scratch, "sigma", n), *mu = dget<double2>(c->scratch, "mu", n);
+    const double *rs = &c->src[3 * isrc];
+    k_gamma<<<ceil_div(n, 256), 256, 0, st>>>(n, (double4 *)c->buf.find("ec"), (double4 *)c->buf.find("en"),
+                                              (double2 *)c->buf.find("beta"), c->k, rs[0], rs[1], rs[2],
+                                              c->src_amp[isrc], sigma, mu);
+    LAUNCH_OK();
+    HIP_OK(hipEventRecord(c->ev[0], st));
+    fmm_pass(c, sigma, mu, nullptr, 0.0, b, false);
+    HIP_OK(hipEventRecord(c->ev[8], st));
+}
+
+}  // namespace fmm
+
+using namespace fmm;
+
+// ------------------------------------------------------------------ ABI
+#define GUARD_BEGIN try {
+#define GUARD_END                               \
+    }                                           \
+    catch (const FmmError &e) {                 \
+        if (ctx) ctx->err = e.what();           \
+        return e.code;                          \
+    }                                           \
+    catch (const std::exception &e) {           \
+        if (ctx) ctx->err = e.what();           \
+        return FMMBEM_EDEVICE;                  \
+    }
+
+static int fail(fmmbem_ctx *ctx, int code, const std::string &m) {
+    if (ctx) ctx->err = m;
+    return code;
+}
+
+extern "C" {
+
+void fmmbem_default_options(fmmbem_options *o) {
+    o->rc_factor = 1.8;
+    o->rc = 0.0;
+    o->leaf_max = 64;
+    o->p_min = 16;
+    o->digits = 7.0;
+    o->ktau_switch = 1.0;
+    o->max_depth = 12;
+}
+
+void fmmbem_default_solve_opts(fmmbem_solve_opts *o) {
+    o->tol = 1e-6;
+    o->restart = 30;
+    o->maxit = 500;
+    o->precond = FMMBEM_PC_NEARBLOCK;
+    o->precision = FMMBEM_FP64;
+    o->diag_shift = 0.0;
+    o->use_x0 = 0;
+}
+
+int fmmbem_create(fmmbem_ctx **out, int hip_device, const fmmbem_options *opt) {
+    fmmbem_ctx *ctx = nullptr;
+    if (!out) return FMMBEM_EINVAL;
+    *out = nullptr;
+    try {
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return FMMBEM_EDEVICE;
+        if (hip_device < 0 || hip_device >= ndev) return FMMBEM_EINVAL;
+        ctx = new fmmbem_ctx();
+        ctx->device = hip_device;
+        if (opt) ctx->opt = *opt;
+        else fmmbem_default_options(&ctx->opt);
+        HIP_OK(hipSetDevice(hip_device));
+        HIP_OK(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+        for (auto &e : ctx->ev) HIP_OK(hipEventCreate(&e));
+        *out = ctx;
+        return FMMBEM_OK;
+    } catch (const FmmError &e) {
+        delete ctx;
+        return e.code;
+    }
+}
+
+int fmmbem_destroy(fmmbem_ctx *ctx) {
+    if (!ctx) return FMMBEM_OK;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    ctx->buf.release_all();
+    ctx->scratch.release_all();
+    for (auto &e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return FMMBEM_OK;
+}
+
+const char *fmmbem_last_error(const fmmbem_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int fmmbem_set_mesh(fmmbem_ctx *ctx, int64_t nv, const double *xyz, int64_t nt, const int64_t *tri) {
+    if (!ctx) return FMMBEM_EINVAL;
+    if (nv < 3 || nt < 1 || !xyz || !tri) return fail(ctx, FMMBEM_EINVAL, "empty mesh");
+    if (nt > (int64_t)1 << 30) return fail(ctx, FMMBEM_EINVAL, "too many triangles");
+    double vol = 0.0;
+    for (int64_t j = 0; j < nt; ++j) {
+        for (int q = 0; q < 3; ++q)
+            if (tri[3 * j + q] < 0 || tri[3 * j + q] >= nv)
+                return fail(ctx, FMMBEM_EINVAL, "triangle " + std::to_string(j) + ": vertex index out of range");
+        const double *a = xyz + 3 * tri[3 * j], *b = xyz + 3 * tri[3 * j + 1], *e = xyz + 3 * tri[3 * j + 2];
+        double u[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]}, v[3] = {e[0] - a[0], e[1] - a[1], e[2] - a[2]};
+        double w[3] = {u[1] * v[2] - u[2] * v[1], u[2] * v[0] - u[0] * v[2], u[0] * v[1] - u[1] * v[0]};
+        double l = std::sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+        double ext = std::max({std::fabs(u[0]), std::fabs(u[1]), std::fabs(u[2]), std::fabs(v[0]), std::fabs(v[1]), std::fabs(v[2])});
+        if (!(l > 1e-14 * ext * ext) || !std::isfinite(l))
+            return fail(ctx, FMMBEM_EINVAL, "triangle " + std::to_string(j) + " is degenerate");
+        vol += ((a[0] + b[0] + e[0]) * w[0] + (a[1] + b[1] + e[1]) * w[1] + (a[2] + b[2] + e[2]) * w[2]) / 18.0;
+    }
+    if (!(vol > 0.0))
+        return fail(ctx, FMMBEM_EINVAL, "enclosed volume is not positive: normals must point out of the fluid");
+    ctx->xyz.assign(xyz, xyz + 3 * nv);
+    ctx->tri.assign(tri, tri + 3 * nt);
+    ctx->nv = nv;
+    ctx->nt = nt;
+    ctx->have_mesh = true;
+    ctx->mesh_dirty = true;
+    if (ctx->have_beta && (int64_t)ctx->beta.size() != nt) ctx->have_beta = false;
+    return FMMBEM_OK;
+}
+
+int fmmbem_set_wavenumber(fmmbem_ctx *ctx, double k) {
+    if (!ctx) return FMMBEM_EINVAL;
+    if (!std::isfinite(k) || !(k > 0.0)) return fail(ctx, FMMBEM_EINVAL, "wavenumber must be finite and > 0");
+    if (k != ctx->k || !ctx->have_k) ctx->k_dirty = true;
+    ctx->k = k;
+    ctx->have_k = true;
+    return FMMBEM_OK;
+}
+
+int fmmbem_set_admittance(fmmbem_ctx *ctx, const fmmbem_c64 *beta) {
+    if (!ctx) return FMMBEM_EINVAL;
+    if (!ctx->have_mesh) return fail(ctx, FMMBEM_ENOTREADY, "set the mesh before the admittance");
+    if (!beta) return fail(ctx, FMMBEM_EINVAL, "beta is NULL");
+    for (int64_t i = 0; i < ctx->nt; ++i)
+        if (!(beta[i].re >= 0.0) || !std::isfinite(beta[i].im))
+            return fail(ctx, FMMBEM_EINVAL, "beta[" + std::to_string(i) + "]: Re(beta) must be >= 0 (passive wall)");
+    ctx->beta.resize(ctx->nt);
+    for (int64_t i = 0; i < ctx->nt; ++i) ctx->beta[i] = cmk(beta[i].re, beta[i].im);
+    ctx->have_beta = true;
+    ctx->beta_dirty = true;
+    return FMMBEM_OK;
+}
+
+int fmmbem_set_sources(fmmbem_ctx *ctx, int32_t ns, const double *rs, const fmmbem_c64 *amp) {
+    if (!ctx) return FMMBEM_EINVAL;
+    if (ns < 1 || !rs) return fail(ctx, FMMBEM_EINVAL, "need at least one source");
+    for (int i = 0; i < 3 * ns; ++i)
+        if (!std::isfinite(rs[i])) return fail(ctx, FMMBEM_EINVAL, "source position not finite");
+    ctx->src.assign(rs, rs + 3 * ns);
+    ctx->src_amp.assign(ns, cmk(1, 0));
+    if (amp)
+        for (int i = 0; i < ns; ++i) ctx->src_amp[i] = cmk(amp[i].re, amp[i].im);
+    return FMMBEM_OK;
+}
+
+int fmmbem_set_formulation(fmmbem_ctx *ctx, int f) {
+    if (!ctx) return FMMBEM_EINVAL;
+    if (f != FMMBEM_DIRECT) return fail(ctx, FMMBEM_EINVAL, "only the direct formulation (Eq. dbem4) is available");
+    ctx->formulation = f;
+    return FMMBEM_OK;
+}
+
+int fmmbem_setup(fmmbem_ctx *ctx) {
+    if (!ctx) return FMMBEM_EINVAL;
+    GUARD_BEGIN
+    HIP_OK(hipSetDevice(ctx->device));
+    ensure_setup(ctx);
+    return FMMBEM_OK;
+    GUARD_END
+}
+
+int64_t fmmbem_num_unknowns(const fmmbem_ctx *ctx) { return (ctx && ctx->have_mesh) ? ctx->nt : -1; }
+
+int fmmbem_rhs(fmmbem_ctx *ctx, fmmbem_c64 *b) {
+    if (!ctx) return FMMBEM_EINVAL;
+    if (!b) return fail(ctx, FMMBEM_EINVAL, "b is NULL");
+    GUARD_BEGIN
+    HIP_OK(hipSetDevice(ctx->device));
+    if (ctx->src.empty()) return fail(ctx, FMMBEM_ENOTREADY, "sources not set");
+    ensure_setup(ctx);
+    const int64_t n = ctx->nt;
+    double2 *db = dget<double2>(ctx->scratch, "rhs_out", n);
+    for (size_t s = 0; s < ctx->src.size() / 3; ++s) {
+        rhs_dev(ctx, (int)s, db);
+        HIP_OK(hipMemcpyAsync(b + s * n, db, sizeof(double2) * n, hipMemcpyDeviceToHost, ctx->stream));
+    }
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    return FMMBEM_OK;
+    GUARD_END
+}
+
+int fmmbem_matvec(fmmbem_ctx *ctx, int32_t nrhs, const fmmbem_c64 *x, fmmbem_c64 *y, int precision, int exact_far) {
+    if (!ctx) return FMMBEM_EINVAL;
+    if (!x || !y || nrhs < 1) return fail(ctx, FMMBEM_EINVAL, "bad vectors");
+    if (precision != FMMBEM_FP64) return fail(ctx, FMMBEM_EINVAL, "precision not available");
+    GUARD_BEGIN
+    HIP_OK(hipSetDevice(ctx->device));
+    ensure_setup(ctx);
+    const int64_t n = ctx->nt;
+    double2 *dx = dget<double2>(ctx->scratch, "mv_x", n), *dy = dget<double2>(ctx->scratch, "mv_y", n);
+    for (int r = 0; r < nrhs; ++r) {
+        HIP_OK(hipMemcpyAsync(dx, x + r * n, sizeof(double2) * n, hipMemcpyHostToDevice, ctx->stream));
+        matvec_dev(ctx, dx, dy, exact_far != 0);
+        HIP_OK(hipMemcpyAsync(y + r * n, dy, sizeof(double2) * n, hipMemcpyDeviceToHost, ctx->stream));
+        HIP_OK(hipStreamSynchronize(ctx->stream));
+        read_timings(ctx);
+    }
+    return FMMBEM_OK;
+    GUARD_END
+}
+
+int fmmbem_matvec_dev(fmmbem_ctx *ctx, int32_t nrhs, const void *x, void *y, int precision, void *stream) {
+    if (!ctx) return FMMBEM_EINVAL;
+    if (!x || !y || nrhs < 1) return fail(ctx, FMMBEM_EINVAL, "bad vectors");
+    if (precision != FMMBEM_FP64) return fail(ctx, FMMBEM_EINVAL, "precision not available");
+    GUARD_BEGIN
+    HIP_OK(hipSetDevice(ctx->device));
+    ensure_setup(ctx);
+    const int64_t n = ctx->nt;
+    hipStream_t caller = (hipStream_t)stream;
+    hipEvent_t e0 = ctx->ev[0];
+    // order after the caller's stream, run on ours, then make the caller's stream wait
+    HIP_OK(hipEventRecord(e0, caller));
+    HIP_OK(hipStreamWaitEvent(ctx->stream, e0, 0));
+    for (int r = 0; r < nrhs; ++r)
+        matvec_dev(ctx, (const double2 *)x + r * n, (double2 *)y + r * n, false);
+    HIP_OK(hipStreamWaitEvent(caller, ctx->ev[8], 0));
+    return FMMBEM_OK;
+    GUARD_END
+}
+
+int fmmbem_last_timings(fmmbem_ctx *ctx, double *ms8) {
+    if (!ctx || !ms8) return FMMBEM_EINVAL;
+    GUARD_BEGIN
+    read_timings(ctx);
+    for (int i = 0; i < 8; ++i) ms8[i] = ctx->last.ms[i];
+    return FMMBEM_OK;
+    GUARD_END
+}
+
+int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, fmmbem_c64 *x, fmmbem_solve_report *rep) {
+    if (!ctx) return FMMBEM_EINVAL;
+    if (!x) return fail(ctx, FMMBEM_EINVAL, "x is NULL");
+    fmmbem_solve_opts o;
+    fmmbem_default_solve_opts(&o);
+    if (opts) o = *opts;
+    if (o.restart < 1 || o.maxit < 0 || !(o.tol > 0)) return fail(ctx, FMMBEM_EINVAL, "bad solve options");
+    if (o.precision != FMMBEM_FP64) return fail(ctx, FMMBEM_EINVAL, "precision not available");
+    GUARD_BEGIN
+    HIP_OK(hipSetDevice(ctx->device));
+    if (ctx->src.empty()) return fail(ctx, FMMBEM_ENOTREADY, "sources not set");
+    if (isrc < 0 || isrc >= (int)(ctx->src.size() / 3)) return fail(ctx, FMMBEM_EINVAL, "bad source index");
+    double t_before = 0;
+    bool dirty = ctx->mesh_dirty || ctx->k_dirty || ctx->beta_dirty;
+    ensure_setup(ctx);
+    if (dirty) t_before = ctx->t_setup_last;
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t st = ctx->stream;
+    const int64_t n = ctx->nt;
+    const int nleaf = (int)ctx->tree.leaf_start.size() - 1;
+    // preconditioner data
+    if (o.precond == FMMBEM_PC_DIAG) {
+        double2 *dinv = dget<double2>(ctx->buf, "pc_dinv", n);
+        k_diag_inv<<<ceil_div(n, 256), 256, 0, st>>>(n, (int32_t *)ctx->buf.find("perm"), (int32_t *)ctx->buf.find("near_start"),
+                                                     (int32_t *)ctx->buf.find("near_col"), (double2 *)ctx->buf.find("near_L"),
+                                                     (double2 *)ctx->buf.find("near_M"), (double2 *)ctx->buf.find("beta"),
+                                                     ctx->k, o.diag_shift, dinv);
+        LAUNCH_OK();
+    } else if (o.precond == FMMBEM_PC_NEARBLOCK && !ctx->precond_ready_nb) {
+        std::vector<int64_t> off(nleaf + 1, 0);
+        for (int b = 0; b < nleaf; ++b) {
+            int64_t nb = ctx->tree.leaf_start[b + 1] - ctx->tree.leaf_start[b];
+            if (nb > 1024) throw FmmError(FMMBEM_EINVAL, "leaf too full for the block preconditioner");
+            off[b + 1] = off[b] + nb * nb;
+        }
+        int64_t *doff = upload(ctx->buf, "pc_off", off, st);
+        double2 *A = dget<double2>(ctx->buf, "pc_blocks", off[nleaf]);
+        int32_t *piv = dget<int32_t>(ctx->scratch, "pc_piv", n);
+        int *status = dget<int>(ctx->scratch, "pc_status", 1);
+        HIP_OK(hipMemsetAsync(status, 0, sizeof(int), st));
+        k_leaf_blocks<<<nleaf, 256, 0, st>>>(nleaf, (int32_t *)ctx->buf.find("leaf_start"), doff, (double4 *)ctx->buf.find("ec"),
+                                             (double4 *)ctx->buf.find("en"), (double2 *)ctx->buf.find("beta"), ctx->k,
+                                             ctx->rc * ctx->rc, (int32_t *)ctx->buf.find("near_start"),
+                                             (int32_t *)ctx->buf.find("near_col"), (double2 *)ctx->buf.find("near_L"),
+                                             (double2 *)ctx->buf.find("near_M"), A);
+        LAUNCH_OK();
+        k_leaf_invert<<<nleaf, 256, 0, st>>>(nleaf, (int32_t *)ctx->buf.find("leaf_start"), doff, A, piv, status);
+        LAUNCH_OK();
+        int hs = 0;
+        HIP_OK(hipMemcpyAsync(&hs, status, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+        if (hs) throw FmmError(FMMBEM_EBREAKDOWN, "singular leaf block in the near-field preconditioner");
+        ctx->precond_ready_nb = true;
+    }
+    double2 *b = dget<double2>(ctx->scratch, "sv_b", n);
+    double2 *dx = dget<double2>(ctx->scratch, "sv_x", n);
+    rhs_dev(ctx, isrc, b);
+    if (o.use_x0) HIP_OK(hipMemcpyAsync(dx, x, sizeof(double2) * n, hipMemcpyHostToDevice, st));
+    auto mv = [&](const double2 *a, double2 *y) { matvec_dev(ctx, a, y, false); };
+    std::function<void(const double2 *, double2 *)> pc;
+    if (o.precond == FMMBEM_PC_DIAG) {
+        double2 *dinv = (double2 *)ctx->buf.find("pc_dinv");
+        pc = [=](const double2 *v, double2 *z) {
+            k_mul_diag<<<ceil_div(n, 256), 256, 0, st>>>(n, dinv, v, z);
+            LAUNCH_OK();
+        };
+    } else if (o.precond == FMMBEM_PC_NEARBLOCK) {
+        const int32_t *ls = (int32_t *)ctx->buf.find("leaf_start"), *pm = (int32_t *)ctx->buf.find("perm");
+        const int64_t *doff = (int64_t *)ctx->buf.find("pc_off");
+        const double2 *A = (double2 *)ctx->buf.find("pc_blocks");
+        pc = [=](const double2 *v, double2 *z) {
+            k_leaf_apply<<<nleaf, 128, 0, st>>>(nleaf, ls, doff, A, pm, v, z);
+            LAUNCH_OK();
+        };
+    } else {
+        pc = [=](const double2 *v, double2 *z) {
+            HIP_OK(hipMemcpyAsync(z, v, sizeof(double2) * n, hipMemcpyDeviceToDevice, st));
+        };
+    }
+    int iters = 0, restarts = 0;
+    double rel = 1.0;
+    int status = fgmres(n, st, ctx->scratch, mv, mv, pc, b, dx, o.tol, o.restart, o.maxit, o.use_x0 != 0, iters,
+                        restarts, rel);
+    HIP_OK(hipMemcpyAsync(x, dx, sizeof(double2) * n, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    if (rep) {
+        rep->iters = iters;
+        rep->restarts = restarts;
+        rep->rel_res = rel;
+        rep->t_setup_s = t_before;
+        rep->t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        rep->status = status;
+    }
+    if (status < 0) ctx->err = "solver failed";
+    return status;
+    GUARD_END
+}
+
+int fmmbem_eval_field(fmmbem_ctx *ctx, int32_t isrc, int64_t nr, const double *r, const fmmbem_c64 *x, fmmbem_c64 *psi) {
+    if (!ctx) return FMMBEM_EINVAL;
+    if (!r || !x || !psi || nr < 0) return fail(ctx, FMMBEM_EINVAL, "bad arguments");
+    GUARD_BEGIN
+    HIP_OK(hipSetDevice(ctx->device));
+    if (ctx->src.empty()) return fail(ctx, FMMBEM_ENOTREADY, "sources not set");
+    if (isrc < 0 || isrc >= (int)(ctx->src.size() / 3)) return fail(ctx, FMMBEM_EINVAL, "bad source index");
+    ensure_setup(ctx);
+    if (nr == 0) return FMMBEM_OK;
+    hipStream_t st = ctx->stream;
+    const int64_t n = ctx->nt;
+    double2 *gam = dget<double2>(ctx->scratch, "fe_gam", n), *zero = dget<double2>(ctx->scratch, "fe_zero", n);
+    const double *rs = &ctx->src[3 * isrc];
+    k_gamma<<<ceil_div(n, 256), 256, 0, st>>>(n, (double4 *)ctx->buf.find("ec"), (double4 *)ctx->buf.find("en"),
+                                              (double2 *)ctx->buf.find("beta"), ctx->k, rs[0], rs[1], rs[2],
+                                              ctx->src_amp[isrc], gam, zero);
+    LAUNCH_OK();
+    // sigma = gamma + i k beta x, mu = -x  (sorted order)
+    std::vector<double2> xs(n), g(n), bet(n), sg(n), mu(n);
+    HIP_OK(hipMemcpyAsync(g.data(), gam, sizeof(double2) * n, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    for (int64_t i = 0; i < n; ++i) {
+        int j = ctx->tree.perm[i];
+        double2 xi = cmk(x[j].re, x[j].im), be = ctx->beta[j];
+        double2 ikbx = cmul(cmk(-ctx->k * be.y, ctx->k * be.x), xi);
+        sg[i] = cadd(g[i], ikbx);
+        mu[i] = cscale(xi, -1.0);
+    }
+    double2 *dsg = upload(ctx->scratch, "fe_sg", sg, st), *dmu = upload(ctx->scratch, "fe_mu", mu, st);
+    std::vector<double> pts(r, r + 3 * nr);
+    double *dp = upload(ctx->scratch, "fe_pts", pts, st);
+    double2 *dout = dget<double2>(ctx->scratch, "fe_out", nr);
+    k_field<<<(unsigned)nr, 256, 0, st>>>(n, dp, (double4 *)ctx->buf.find("ec"), (double4 *)ctx->buf.find("en"),
+                                          (double *)ctx->buf.find("ev"), dsg, dmu, ctx->k, ctx->rc * ctx->rc, rs[0],
+                                          rs[1], rs[2], ctx->src_amp[isrc], dout);
+    LAUNCH_OK();
+    HIP_OK(hipMemcpyAsync(psi, dout, sizeof(double2) * nr, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    return FMMBEM_OK;
+    GUARD_END
+}
+
+int fmmbem_get_info(fmmbem_ctx *ctx, fmmbem_info *info) {
+    if (!ctx || !info) return FMMBEM_EINVAL;
+    GUARD_BEGIN
+    HIP_OK(hipSetDevice(ctx->device));
+    ensure_setup(ctx);
+    std::memset(info, 0, sizeof(*info));
+    const TreeHost &T = ctx->tree;
+    info->n = ctx->nt;
+    info->rc = ctx->rc;
+    info->root_side = T.side;
+    for (int d = 0; d < 3; ++d) info->root_lo[d] = T.lo[d];
+    info->depth = T.depth;
+    info->nleaf = (int64_t)T.leaf_start.size() - 1;
+    info->leaf_max_occ = T.max_occ;
+    info->near_nnz = ctx->near_nnz;
+    info->p2p_pairs = ctx->p2p_pairs;
+    auto rot = [](int p) {  // real flops of applying Delta^T and Delta to a complex column of degree < p
+        double s = 0;
+        for (int n = 0; n < p; ++n) s += 2.0 * 4.0 * (2.0 * n + 1) * (2.0 * n + 1);
+        return s;
+    };
+    auto coax = [](int ps, int pt) {
+        double s = 0;
+        int pm = std::min(ps, pt);
+        for (int m = -(pm - 1); m <= pm - 1; ++m) s += 8.0 * (pt - std::abs(m)) * (ps - std::abs(m));
+        return s;
+    };
+    for (int l = 0; l <= T.depth && l < 24; ++l) {
+        info->p[l] = l >= 2 ? ctx->lev[l].p : 0;
+        info->nbox[l] = ctx->lev[l].nbox;
+        info->m2l_pairs[l] = l >= 2 ? ctx->lev[l].njob_m2l : 0;
+        if (l >= 2) {
+            int p = ctx->lev[l].p;
+            info->flops_m2l += (double)ctx->lev[l].njob_m2l * (2 * rot(p) + coax(p, p));
+            if (l < T.depth) {
+                int pc = ctx->lev[l + 1].p;
+                info->flops_m2m_l2l += (double)ctx->lev[l + 1].nbox * 2 * (rot(pc) + rot(p) + coax(pc, p));
+            }
+        }
+    }
+    int pl = ctx->lev[T.depth].p;
+    info->flops_p2m_l2p = (double)ctx->nt * (double)pl * pl * 2 * 8.0;
+    info->bytes_p2p = (double)ctx->nt * (2 * 32 + 16 + 16 + 16) + (double)ctx->near_nnz * (4 + 32);
+    return FMMBEM_OK;
+    GUARD_END
+}
+
+int fmmbem_near_entries(fmmbem_ctx *ctx, int64_t *nnz, int64_t *rows, int64_t *cols, fmmbem_c64 *L, fmmbem_c64 *M) {
+    if (!ctx || !nnz) return FMMBEM_EINVAL;
+    GUARD_BEGIN
+    HIP_OK(hipSetDevice(ctx->device));
+    ensure_setup(ctx);
+    *nnz = ctx->near_nnz;
+    if (!rows) return FMMBEM_OK;
+    const int64_t z = ctx->near_nnz;
+    std::vector<int32_t> r(z), c(z);
+    std::vector<double2> l(z), m(z);
+    hipStream_t st = ctx->stream;
+    HIP_OK(hipMemcpyAsync(r.data(), ctx->buf.find("near_row"), 4 * z, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(c.data(), ctx->buf.find("near_col"), 4 * z, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(l.data(), ctx->buf.find("near_L"), 16 * z, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(m.data(), ctx->buf.find("near_M"), 16 * z, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    for (int64_t e = 0; e < z; ++e) {
+        rows[e] = ctx->tree.perm[r[e]];
+        cols[e] = ctx->tree.perm[c[e]];
+        if (L) L[e] = {l[e].x, l[e].y};
+        if (M) M[e] = {m[e].x, m[e].y};
+    }
+    return FMMBEM_OK;
+    GUARD_END
+}
+
+int fmmbem_coaxial_table(int hip_device, int kind, double ktau, int p, int method, fmmbem_c64 *out) {
+    if (!out || p < 1 || p > 1000 || !(ktau > 0) || (kind != 0 && kind != 1)) return FMMBEM_EINVAL;
+    fmmbem_ctx *ctx = nullptr;
+    try {
+        HIP_OK(hipSetDevice(hip_device));
+        DeviceBuffers scratch;
+        double2 *d = dget<double2>(scratch, "out", coax_table_size(p));
+        int meth = method < 0 ? (ktau < 1.0 ? 0 : 1) : method;
+        std::vector<CoaxJob> jobs{{kind, meth, p, ktau, d}};
+        build_coax_tables(jobs, scratch, nullptr);
+        HIP_OK(hipMemcpy(out, d, sizeof(double2) * coax_table_size(p), hipMemcpyDeviceToHost));
+        scratch.release_all();
+        return FMMBEM_OK;
+    } catch (const FmmError &e) {
+        return e.code;
+    }
+    (void)ctx;
+}
+
+int fmmbem_rotation_table(int hip_device, int p, double *out) {
+    if (!out || p < 1 || p > 2000) return FMMBEM_EINVAL;
+    try {
+        HIP_OK(hipSetDevice(hip_device));
+        DeviceBuffers scratch;
+        double *D = dget<double>(scratch, "D", rot_table_size(p)), *DT = dget<double>(scratch, "DT", rot_table_size(p));
+        build_delta_table(p, D, DT, nullptr);
+        HIP_OK(hipMemcpy(out, D, sizeof(double) * rot_table_size(p), hipMemcpyDeviceToHost));
+        scratch.release_all();
+        return FMMBEM_OK;
+    } catch (const FmmError &e) {
+        return e.code;
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,596 @@
+// FMM matrix-vector product of the direct BIE (Eq. dbem4) on one GPU, FP64 path.
+//
+// The product y = 1/2 x + L[sigma] + M[mu] at the element centroids, with single-layer density
+// sigma = -i k beta x and double-layer density mu = x, is split as in Section 3.3:
+//   near  : pairs closer than r_c (and the self pair) use accurate integrals, stored once per
+//           (mesh, k) in a CSR table; all other pairs in neighbouring leaves use the one-point
+//           rule, evaluated on the fly (P2P);
+//   far   : boxes that are well separated exchange multipole/local expansions of Eq. (shft0):
+//           P2M at the leaves, M2M up, M2L across, L2L down, L2P at the leaves.  Every
+//           translation is rotation - coaxial translation - back-rotation (Section 3.3); the
+//           coaxial coefficients come from the stabilised recursion, the rotations from the
+//           quarter-turn matrices Delta^n (tables.hip).
+//
+// Expansion conventions (what the tables and the kernels below share):
+//   G(x,y) = i k sum_{n,m} R_n^{-m}(y - C) S_n^m(x - C),  |x - C| > |y - C|,
+//   multipole of a box: psi(x) = sum C_n^m S_n^m(x - C); local: psi(x) = sum D_n^m R_n^m(x - C).
+//   Y_n^m orthonormal with P_n^|m| without the Condon-Shortley phase (Y_n^{-m} = conj Y_n^m).
+// Rotation to align t = |t|(sin b cos a, sin b sin a, cos b) with +z, on a coefficient column c:
+//   c <- e^{i m a} (-i)^m c ;  c <- Delta^T c ;  c <- e^{i m b} c ;  c <- Delta c ;  [ * i^m ]
+// and back after the coaxial step:
+//   [ * (-i)^m ] ;  d <- Delta^T d ;  d <- e^{-i m b} d ;  d <- Delta d ;  d <- i^m e^{-i m a} d.
+// The bracketed phases cancel across the coaxial step (which is diagonal in m) and are omitted.
+#include "internal.h"
+
+namespace fmm {
+
+__constant__ double GL8X[8] = {-0.96028985649753618, -0.79666647741362673, -0.52553240991632899,
+                               -0.18343464249564978, 0.18343464249564978,  0.52553240991632899,
+                               0.79666647741362673,  0.96028985649753618};
+__constant__ double GL8W[8] = {0.10122853629037669, 0.22238103445337434, 0.31370664587788705,
+                               0.36268378337836177, 0.36268378337836177, 0.31370664587788705,
+                               0.22238103445337434, 0.10122853629037669};
+
+// ------------------------------------------------------------------ accurate element integrals
+// (e^{iz} - 1)/(iz)
+__device__ inline double2 expm1_i_over(double z) {
+    if (fabs(z) < 1e-3) {
+        double z2 = z * z;
+        return cmk(1.0 - z2 / 6.0 + z2 * z2 / 120.0, z / 2.0 - z * z2 / 24.0 + z2 * z2 * z / 720.0);
+    }
+    double sh = sin(0.5 * z);
+    return cmk(sin(z) / z, 2.0 * sh * sh / z);
+}
+
+// L = int_T G(x,y) dS_y and M = int_T dG/dn_y dS_y for a flat triangle, by polar coordinates
+// about the projection x_p of x on the triangle's plane.  With h the signed height of x and
+// r^2 = rho^2 + h^2 the radial integrals are exact:
+//   int_0^{rho_e} G rho drho        = (e^{ikR} - e^{ik|h|}) / (4 pi i k)
+//   int_0^{rho_e} dG/dn_y rho drho  = -h/(4 pi) (e^{ikR}/R - e^{ik|h|}/|h|),   R = r(rho_e)
+// leaving an angular integral per edge (signed by the edge orientation seen from x_p),
+// done by 8 panels x 8-point Gauss-Legendre in the angle from the edge normal.
+// self != 0: x is the triangle's centroid (h = 0, M = 0 by the principal value).
+__device__ void tri_integrals(const double *x, const double *v, double k, int self, double2 &Lout, double2 &Mout) {
+    double e1[3] = {v[3] - v[0], v[4] - v[1], v[5] - v[2]};
+    double e2[3] = {v[6] - v[0], v[7] - v[1], v[8] - v[2]};
+    double nn[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+    double nl = sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
+    nn[0] /= nl;
+    nn[1] /= nl;
+    nn[2] /= nl;
+    double h = self ? 0.0 : (x[0] - v[0]) * nn[0] + (x[1] - v[1]) * nn[1] + (x[2] - v[2]) * nn[2];
+    double xp[3] = {x[0] - h * nn[0], x[1] - h * nn[1], x[2] - h * nn[2]};
+    double ah = fabs(h);
+    double2 Lacc = cmk(0, 0), Macc = cmk(0, 0);
+    double span = 0.0;
+    for (int e = 0; e < 3; ++e) {
+        int e2i = (e + 1) % 3;
+        double a[3] = {v[3 * e] - xp[0], v[3 * e + 1] - xp[1], v[3 * e + 2] - xp[2]};
+        double b[3] = {v[3 * e2i] - xp[0], v[3 * e2i + 1] - xp[1], v[3 * e2i + 2] - xp[2]};
+        double ed[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+        double le = sqrt(ed[0] * ed[0] + ed[1] * ed[1] + ed[2] * ed[2]);
+        double eh[3] = {ed[0] / le, ed[1] / le, ed[2] / le};
+        double s0 = a[0] * eh[0] + a[1] * eh[1] + a[2] * eh[2];
+        double s1 = b[0] * eh[0] + b[1] * eh[1] + b[2] * eh[2];
+        double f[3] = {a[0] - s0 * eh[0], a[1] - s0 * eh[1], a[2] - s0 * eh[2]};
+        double d = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+        if (d <= 1e-13 * le) continue;
+        double cr[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+        double sgn = (cr[0] * nn[0] + cr[1] * nn[1] + cr[2] * nn[2]) >= 0.0 ? 1.0 : -1.0;
+        double p0 = atan2(s0, d), p1 = atan2(s1, d);
+        span += sgn * (p1 - p0);
+        const int NPAN = 8;
+        double hw = 0.5 * (p1 - p0) / NPAN;
+        for (int pan = 0; pan < NPAN; ++pan) {
+            double mid = p0 + (2 * pan + 1) * hw;
+            for (int q = 0; q < 8; ++q) {
+                double ps = mid + hw * GL8X[q], w = sgn * hw * GL8W[q];
+                double rho = d / cos(ps);
+                double R = sqrt(rho * rho + h * h);
+                double dR = R - ah;
+                double2 E = expm1_i_over(k * dR);
+                Lacc = cadd(Lacc, cscale(E, w * dR));
+                double sn, cs;
+                sincos(k * R, &sn, &cs);
+                Macc = cadd(Macc, cscale(cmk(cs, sn), w / R));
+            }
+        }
+    }
+    double sh, ch;
+    sincos(k * ah, &sh, &ch);
+    double2 eh_ = cmk(ch, sh);
+    Lout = cscale(cmul(eh_, Lacc), 1.0 / (4.0 * FMM_PI));
+    if (h == 0.0) {
+        Mout = cmk(0, 0);
+    } else {
+        double sgh = h > 0 ? 1.0 : -1.0;
+        Mout = cadd(cscale(Macc, -h / (4.0 * FMM_PI)), cscale(eh_, sgh * span / (4.0 * FMM_PI)));
+    }
+}
+
+// ------------------------------------------------------------------ near-field table
+__global__ void k_near_count(int64_t n, const int32_t *leaf_of, const int32_t *leaf_start, const int32_t *nbr_start,
+                             const int32_t *nbr_list, const double4 *ec, double rc2, int32_t *cnt) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double4 ci = ec[i];
+    int b = leaf_of[i], c = 0;
+    for (int q = nbr_start[b]; q < nbr_start[b + 1]; ++q) {
+        int sb = nbr_list[q];
+        for (int j = leaf_start[sb]; j < leaf_start[sb + 1]; ++j) {
+            double4 cj = ec[j];
+            if (j == i || dist2_exact(ci.x, ci.y, ci.z, cj.x, cj.y, cj.z) < rc2) ++c;
+        }
+    }
+    cnt[i] = c;
+}
+
+__global__ void k_near_fill(int64_t n, const int32_t *leaf_of, const int32_t *leaf_start, const int32_t *nbr_start,
+                            const int32_t *nbr_list, const double4 *ec, double rc2, const int32_t *start,
+                            int32_t *rowv, int32_t *col) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double4 ci = ec[i];
+    int b = leaf_of[i], o = start[i];
+    for (int q = nbr_start[b]; q < nbr_start[b + 1]; ++q) {
+        int sb = nbr_list[q];
+        for (int j = leaf_start[sb]; j < leaf_start[sb + 1]; ++j) {
+            double4 cj = ec[j];
+            if (j == i || dist2_exact(ci.x, ci.y, ci.z, cj.x, cj.y, cj.z) < rc2) {
+                rowv[o] = (int32_t)i;
+                col[o++] = j;
+            }
+        }
+    }
+}
+
+__global__ void k_near_quad(int64_t nnz, const int32_t *rowv, const int32_t *col, const double4 *ec, const double *ev,
+                            double k, double2 *Lv, double2 *Mv) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nnz) return;
+    int i = rowv[e], j = col[e];
+    double4 ci = ec[i];
+    double x[3] = {ci.x, ci.y, ci.z}, v[9];
+    for (int q = 0; q < 9; ++q) v[q] = ev[9 * (int64_t)j + q];
+    double2 L, M;
+    tri_integrals(x, v, k, i == j, L, M);
+    Lv[e] = L;
+    Mv[e] = M;
+}
+
+// ------------------------------------------------------------------ densities
+// sigma_i = -i k beta_i x_i, mu_i = x_i (sorted order; x in caller order)
+__global__ void k_densities(int64_t n, const int32_t *perm, const double2 *x, const double2 *beta, double k,
+                            double2 *sigma, double2 *mu) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double2 xi = x[perm[i]];
+    double2 bx = cmul(beta[i], xi);
+    sigma[i] = cmk(k * bx.y, -k * bx.x);  // -i k (beta x)
+    mu[i] = xi;
+}
+
+// gamma_i = -dpsi_in/dn + i k beta psi_in at centroid i for a monopole of amplitude amp at rs (Eq. sp7)
+__global__ void k_gamma(int64_t n, const double4 *ec, const double4 *en, const double2 *beta, double k, double sx,
+                        double sy, double sz, double2 amp, double2 *sigma, double2 *mu) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double4 c = ec[i], nv = en[i];
+    double dx = c.x - sx, dy = c.y - sy, dz = c.z - sz;
+    double r = sqrt(dx * dx + dy * dy + dz * dz);
+    double s, co;
+    sincos(k * r, &s, &co);
+    double2 G = cmul(amp, cmk(co / (4 * FMM_PI * r), s / (4 * FMM_PI * r)));
+    double proj = (dx * nv.x + dy * nv.y + dz * nv.z) / (r * r);
+    double2 dG = cscale(cmul(G, cmk(-1.0, k * r)), proj);      // G (ikr - 1) (x - rs).n / r^2
+    double2 ikb = cmk(-k * beta[i].y, k * beta[i].x);          // i k beta
+    sigma[i] = csub(cmul(ikb, G), dG);
+    mu[i] = cmk(0, 0);
+}
+
+// ------------------------------------------------------------------ P2P + near table
+// y_i = sum_{j in neighbour leaves, |c_i - c_j| >= r_c} [G q_j + dG/dn_y w_j] + sum_near [L sigma + M mu]
+// with q_j = A_j sigma_j, w_j = A_j mu_j.  One workgroup (one wavefront) per target leaf,
+// source tiles staged in LDS.
+__global__ void __launch_bounds__(64) k_p2p(int nleaf, const int32_t *leaf_start, const int32_t *nbr_start,
+                                            const int32_t *nbr_list, int all_leaves, const double4 *ec,
+                                            const double4 *en, const double2 *sigma, const double2 *mu, double k,
+                                            double rc2, const int32_t *near_start, const int32_t *near_col,
+                                            const double2 *nL, const double2 *nM, double2 *y) {
+    const int b = blockIdx.x, tid = threadIdx.x;
+    __shared__ double sx[64], sy[64], sz[64], snx[64], sny[64], snz[64];
+    __shared__ double2 sq[64], sw[64];
+    const int ts = leaf_start[b], te = leaf_start[b + 1];
+    const int nb0 = all_leaves ? 0 : nbr_start[b], nb1 = all_leaves ? nleaf : nbr_start[b + 1];
+    const double inv4pi = 1.0 / (4.0 * FMM_PI);
+    for (int t0 = ts; t0 < te; t0 += 64) {
+        const int t = t0 + tid;
+        const bool act = t < te;
+        double4 ct = act ? ec[t] : make_double4(0, 0, 0, 0);
+        double2 acc = cmk(0, 0);
+        for (int q = nb0; q < nb1; ++q) {
+            const int sb = all_leaves ? q : nbr_list[q];
+            const int ss = leaf_start[sb], se = leaf_start[sb + 1];
+            for (int j0 = ss; j0 < se; j0 += 64) {
+                __syncthreads();
+                int j = j0 + tid;
+                if (j < se) {
+                    double4 c = ec[j], nv = en[j];
+                    sx[tid] = c.x;
+                    sy[tid] = c.y;
+                    sz[tid] = c.z;
+                    snx[tid] = nv.x;
+                    sny[tid] = nv.y;
+                    snz[tid] = nv.z;
+                    sq[tid] = cscale(sigma[j], c.w);
+                    sw[tid] = cscale(mu[j], c.w);
+                }
+                __syncthreads();
+                const int cnt = min(64, se - j0);
+                if (act) {
+                    for (int jj = 0; jj < cnt; ++jj) {
+                        double d2 = dist2_exact(ct.x, ct.y, ct.z, sx[jj], sy[jj], sz[jj]);
+                        if (d2 < rc2) continue;
+                        double dx = sx[jj] - ct.x, dy = sy[jj] - ct.y, dz = sz[jj] - ct.z;
+                        double r = sqrt(d2), ir = 1.0 / r;
+                        double s, c;
+                        sincos(k * r, &s, &c);
+                        double2 G = cmk(c * ir * inv4pi, s * ir * inv4pi);
+                        double u = (dx * snx[jj] + dy * sny[jj] + dz * snz[jj]) * ir * ir;  // (y-x).n / r^2
+                        // G * (q + (ikr - 1) u w)
+                        double2 t2 = cmul(cmk(-u, k * r * u), sw[jj]);
+                        acc = cfma(G, cadd(sq[jj], t2), acc);
+                    }
+                }
+            }
+        }
+        if (act) {
+            for (int e = near_start[t]; e < near_start[t + 1]; ++e) {
+                int j = near_col[e];
+                acc = cfma(nL[e], sigma[j], acc);
+                acc = cfma(nM[e], mu[j], acc);
+            }
+            y[t] = acc;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ P2M
+// C_n^m = i k sum_j [ q_j R_n^{-m}(c_j - C) + w_j (n_j . grad) R_n^{-m}(c_j - C) ]
+// using  d_z R_n^m = k (a_{n-1}^m R_{n-1}^m - a_n^m R_{n+1}^m),
+//        (d_x + i d_y) R_n^m = k (b_{n+1}^{-m-1} R_{n+1}^{m+1} - b_n^m R_{n-1}^{m+1}),
+//        (d_x - i d_y) R_n^m = k (b_{n+1}^{m-1} R_{n+1}^{m-1} - b_n^{-m} R_{n-1}^{m-1}).
+// One workgroup per leaf; the basis R_n^{m'} (n <= p, m' >= 0) of CH sources at a time in LDS.
+__device__ inline double2 basis_get(const double2 *B, int p, int n, int mm) {
+    int am = mm < 0 ? -mm : mm;
+    if (n < 0 || n > p || am > n) return cmk(0, 0);
+    double2 v = B[n * (n + 1) / 2 + am];
+    return mm >= 0 ? v : cconj(v);
+}
+
+// column m' >= 0 of the regular basis at one point: out[n(n+1)/2 + m'] = j_n(kr) P_n^m'(ct) e^{i m' phi}
+__device__ void regular_column(int p, int mp, double ct, double st, double phi, const double *jb, double2 *out) {
+    double pmm = 1.0 / sqrt(4.0 * FMM_PI);
+    for (int q = 1; q <= mp; ++q) pmm *= sqrt((2.0 * q + 1.0) / (2.0 * q)) * st;
+    double s, c;
+    sincos(mp * phi, &s, &c);
+    double pm2 = 0.0, pm1 = pmm;
+    for (int n = mp; n <= p; ++n) {
+        double P;
+        if (n == mp) P = pmm;
+        else if (n == mp + 1) P = sqrt(2.0 * mp + 3.0) * ct * pmm;
+        else {
+            double a = sqrt((4.0 * n * n - 1.0) / ((double)n * n - (double)mp * mp));
+            double bq = sqrt((((double)n - 1) * (n - 1) - (double)mp * mp) * (2.0 * n + 1.0) /
+                             ((2.0 * n - 3.0) * ((double)n * n - (double)mp * mp)));
+            P = a * ct * pm1 - bq * pm2;
+        }
+        if (n >= mp + 1) {
+            pm2 = pm1;
+            pm1 = P;
+        }
+        double R = jb[n] * P;
+        out[n * (n + 1) / 2 + mp] = cmk(R * c, R * s);
+    }
+}
+
+__device__ inline void sph_coords(double dx, double dy, double dz, double &r, double &ct, double &st, double &phi) {
+    r = sqrt(dx * dx + dy * dy + dz * dz);
+    if (r > 0) {
+        ct = dz / r;
+        double rxy = sqrt(dx * dx + dy * dy);
+        st = rxy / r;
+        phi = atan2(dy, dx);
+    } else {
+        ct = 1.0;
+        st = 0.0;
+        phi = 0.0;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_p2m(int nleaf, int p, int CH, const int32_t *leaf_start,
+                                             const double4 *center, const double4 *ec, const double4 *en,
+                                             const double2 *sigma, const double2 *mu, double k, double2 *Mout) {
+    extern __shared__ double2 smem[];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const int TB = (p + 1) * (p + 2) / 2;
+    double2 *basis = smem;                                 // CH * TB
+    double2 *qw = basis + (int64_t)CH * TB;                // CH * 2 (16-byte aligned)
+    double *jb = (double *)(qw + CH * 2);                  // CH * (p+2)
+    double *geo = jb + CH * (p + 2);                       // CH * 4: ct, st, phi, r
+    double *nrm = geo + CH * 4;                            // CH * 3
+    const double4 C = center[b];
+    const int ss = leaf_start[b], se = leaf_start[b + 1];
+    const int ncoef = p * p;
+    double2 *Mb = Mout + (int64_t)b * ncoef;
+    for (int c = tid; c < ncoef; c += blockDim.x) Mb[c] = cmk(0, 0);
+    for (int j0 = ss; j0 < se; j0 += CH) {
+        const int cnt = min(CH, se - j0);
+        __syncthreads();
+        if (tid < cnt) {
+            int j = j0 + tid;
+            double4 c = ec[j], nv = en[j];
+            double r, ct, st, phi;
+            sph_coords(c.x - C.x, c.y - C.y, c.z - C.z, r, ct, st, phi);
+            geo[4 * tid] = ct;
+            geo[4 * tid + 1] = st;
+            geo[4 * tid + 2] = phi;
+            geo[4 * tid + 3] = r;
+            sph_jn_seq(k * r, p, jb + tid * (p + 2));
+            qw[2 * tid] = cscale(sigma[j], c.w);
+            qw[2 * tid + 1] = cscale(mu[j], c.w);
+            nrm[3 * tid] = nv.x;
+            nrm[3 * tid + 1] = nv.y;
+            nrm[3 * tid + 2] = nv.z;
+        }
+        __syncthreads();
+        for (int w = tid; w < cnt * (p + 1); w += blockDim.x) {
+            int s = w / (p + 1), mp = w % (p + 1);
+            regular_column(p, mp, geo[4 * s], geo[4 * s + 1], geo[4 * s + 2], jb + s * (p + 2), basis + (int64_t)s * TB);
+        }
+        __syncthreads();
+        for (int c = tid; c < ncoef; c += blockDim.x) {
+            int n = (int)sqrt((double)c);
+            while (n * n > c) --n;
+            while ((n + 1) * (n + 1) <= c) ++n;
+            const int m = c - n * n - n, mm = -m;
+            const double ca1 = coef_a(n - 1, mm), ca2 = coef_a(n, mm);
+            const double cb1 = coef_b(n + 1, -mm - 1), cb2 = coef_b(n, mm);
+            const double cb3 = coef_b(n + 1, mm - 1), cb4 = coef_b(n, -mm);
+            double2 a = cmk(0, 0);
+            for (int s = 0; s < cnt; ++s) {
+                const double2 *B = basis + (int64_t)s * TB;
+                double2 R0 = basis_get(B, p, n, mm);
+                double2 dz = cscale(csub(cscale(basis_get(B, p, n - 1, mm), ca1), cscale(basis_get(B, p, n + 1, mm), ca2)), k);
+                double2 dp = cscale(csub(cscale(basis_get(B, p, n + 1, mm + 1), cb1), cscale(basis_get(B, p, n - 1, mm + 1), cb2)), k);
+                double2 dm = cscale(csub(cscale(basis_get(B, p, n + 1, mm - 1), cb3), cscale(basis_get(B, p, n - 1, mm - 1), cb4)), k);
+                double nx = nrm[3 * s], ny = nrm[3 * s + 1], nz = nrm[3 * s + 2];
+                double2 dn = cscale(dz, nz);
+                dn = cadd(dn, cmul(cmk(0.5 * nx, -0.5 * ny), dp));
+                dn = cadd(dn, cmul(cmk(0.5 * nx, 0.5 * ny), dm));
+                a = cfma(qw[2 * s], R0, a);
+                a = cfma(qw[2 * s + 1], dn, a);
+            }
+            Mb[c] = cadd(Mb[c], cmuli(cscale(a, k)));  // i k sum
+        }
+    }
+}
+
+// ------------------------------------------------------------------ staged translations
+// Stage 1: rotate the source coefficients so that t points along +z.  One workgroup per job.
+__global__ void __launch_bounds__(256) k_rot_fwd(int64_t njob, int psrc, int P, const double2 *src, const int32_t *src_idx,
+                                                 const int16_t *dir, const double2 *phA, const double2 *phB, int PH,
+                                                 const double *D, const double *DT, double2 *W) {
+    const int64_t job = blockIdx.x;
+    if (job >= njob) return;
+    extern __shared__ double2 rot_lds[];
+    double2 *va = rot_lds, *vb = rot_lds + 2 * P;
+    const double2 *c = src + (int64_t)src_idx[job] * psrc * psrc;
+    const int d = dir[job];
+    const double2 *A = phA + (int64_t)d * (2 * PH + 1) + PH;
+    const double2 *Bp = phB + (int64_t)d * (2 * PH + 1) + PH;
+    double2 *out = W + job * (int64_t)P * P;
+    for (int n = 0; n < psrc; ++n) {
+        const int w = 2 * n + 1;
+        const double *Dn = D + rot_block_off(n), *DTn = DT + rot_block_off(n);
+        for (int m = -n + (int)threadIdx.x; m <= n; m += blockDim.x) va[m + n] = cmul(A[m], c[cidx(n, m)]);
+        __syncthreads();
+        // vb = Delta^T va: vb[m'] = sum_m D[m][m'] va[m]
+        for (int mp = (int)threadIdx.x; mp < w; mp += blockDim.x) {
+            double2 s = cmk(0, 0);
+            for (int m = 0; m < w; ++m) s = cadd(s, cscale(va[m], Dn[(int64_t)m * w + mp]));
+            vb[mp] = cmul(Bp[mp - n], s);
+        }
+        __syncthreads();
+        // va = Delta vb: va[m] = sum_m' DT[m'][m] vb[m']
+        for (int m = (int)threadIdx.x; m < w; m += blockDim.x) {
+            double2 s = cmk(0, 0);
+            for (int mp = 0; mp < w; ++mp) s = cadd(s, cscale(vb[mp], DTn[(int64_t)mp * w + m]));
+            out[cidx(n, m - n)] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// Stage 2: coaxial translation, block-diagonal in m:
+//   out_{n'}^m = sum_n (E|F)^{|m|}_{n'n} in_n^m = sum_n (-1)^{n+n'} (E|F)^{|m|}_{n n'} in_n^m
+// (step-4 symmetry lets consecutive threads n' read consecutive table entries).
+__global__ void __launch_bounds__(256) k_coax_apply(int64_t njob, int psrc, int ptgt, int P, int PT, const double2 *W,
+                                                    const double2 *tables, const int8_t *tau_idx, double2 *W2) {
+    const int64_t job = blockIdx.x;
+    if (job >= njob) return;
+    __shared__ double2 col[1024 + 8];
+    const double2 *in = W + job * (int64_t)P * P;
+    double2 *out = W2 + job * (int64_t)P * P;
+    const double2 *T = tables + (tau_idx ? (int64_t)tau_idx[job] : 0) * coax_table_size(PT);
+    const int pm = min(psrc, ptgt);
+    for (int c = threadIdx.x; c < ptgt * ptgt; c += blockDim.x) out[c] = cmk(0, 0);
+    __syncthreads();
+    for (int m = -(pm - 1); m <= pm - 1; ++m) {
+        const int am = m < 0 ? -m : m;
+        const int B = PT - am;
+        const double2 *Tm = T + coax_block_off(PT, am);
+        for (int n = am + (int)threadIdx.x; n < psrc; n += blockDim.x) col[n] = in[cidx(n, m)];
+        __syncthreads();
+        for (int nn = am + (int)threadIdx.x; nn < ptgt; nn += blockDim.x) {
+            double2 s = cmk(0, 0);
+            for (int n = am; n < psrc; ++n) {
+                double2 t = Tm[(int64_t)(n - am) * B + (nn - am)];
+                s = ((n + nn) & 1) ? csub(s, cmul(t, col[n])) : cadd(s, cmul(t, col[n]));
+            }
+            out[cidx(nn, m)] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// Stage 3: rotate back (Delta^T, e^{-imb}, Delta, i^m e^{-ima}); result per job in W.
+__global__ void __launch_bounds__(256) k_rot_back(int64_t njob, int ptgt, int P, const double2 *W2, const int16_t *dir,
+                                                  const double2 *phA, const double2 *phB, int PH, const double *D,
+                                                  const double *DT, double2 *W) {
+    const int64_t job = blockIdx.x;
+    if (job >= njob) return;
+    extern __shared__ double2 rot_lds[];
+    double2 *va = rot_lds, *vb = rot_lds + 2 * P;
+    const double2 *c = W2 + job * (int64_t)P * P;
+    const int d = dir[job];
+    const double2 *A = phA + (int64_t)d * (2 * PH + 1) + PH;
+    const double2 *Bp = phB + (int64_t)d * (2 * PH + 1) + PH;
+    double2 *out = W + job * (int64_t)P * P;
+    for (int n = 0; n < ptgt; ++n) {
+        const int w = 2 * n + 1;
+        const double *Dn = D + rot_block_off(n), *DTn = DT + rot_block_off(n);
+        for (int m = -n + (int)threadIdx.x; m <= n; m += blockDim.x) va[m + n] = c[cidx(n, m)];
+        __syncthreads();
+        for (int mp = (int)threadIdx.x; mp < w; mp += blockDim.x) {
+            double2 s = cmk(0, 0);
+            for (int m = 0; m < w; ++m) s = cadd(s, cscale(va[m], Dn[(int64_t)m * w + mp]));
+            vb[mp] = cmulc(s, Bp[mp - n]);  // e^{-i m' b}
+        }
+        __syncthreads();
+        for (int m = (int)threadIdx.x; m < w; m += blockDim.x) {
+            double2 s = cmk(0, 0);
+            for (int mp = 0; mp < w; ++mp) s = cadd(s, cscale(vb[mp], DTn[(int64_t)mp * w + m]));
+            out[cidx(n, m - n)] = cmulc(s, A[m - n]);  // i^m e^{-i m a} = conj(A_m)
+        }
+        __syncthreads();
+    }
+}
+
+// Stage 4: dst[t] (+)= sum of the job results of target t (jobs grouped by target).
+__global__ void k_reduce_jobs(int64_t ntgt, int ptgt, int P, const int32_t *start, const int32_t *tgt_of_group,
+                              const double2 *W, double2 *dst, int accumulate) {
+    const int64_t g = blockIdx.x;
+    if (g >= ntgt) return;
+    const int j0 = start[g], j1 = start[g + 1];
+    const int64_t t = tgt_of_group ? tgt_of_group[g] : g;
+    const int nc = ptgt * ptgt;
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+        double2 s = accumulate ? dst[t * nc + c] : cmk(0, 0);
+        for (int j = j0; j < j1; ++j) s = cadd(s, W[(int64_t)j * P * P + c]);
+        dst[t * nc + c] = s;
+    }
+}
+
+// ------------------------------------------------------------------ L2P + combine
+// y[perm[i]] = half * x[perm[i]] + y_near[i] + sum_{n,m} D_n^m R_n^m(c_i - C).
+__global__ void __launch_bounds__(64) k_l2p(int nleaf, int p, const int32_t *leaf_start, const double4 *center,
+                                            const double4 *ec, const double2 *Lc, double k, const double2 *ynear,
+                                            double half, const int32_t *perm, const double2 *x, double2 *y,
+                                            int has_far) {
+    extern __shared__ double jbuf[];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const double4 C = center[b];
+    const int ts = leaf_start[b], te = leaf_start[b + 1];
+    const double2 *D = Lc + (int64_t)b * p * p;
+    double *jb = jbuf + tid * (p + 2);
+    for (int t = ts + tid; t < te; t += 64) {
+        double2 far = cmk(0, 0);
+        if (has_far) {
+            double4 c = ec[t];
+            double r, ct, st, phi;
+            sph_coords(c.x - C.x, c.y - C.y, c.z - C.z, r, ct, st, phi);
+            sph_jn_seq(k * r, p - 1, jb);
+            double pmm = 1.0 / sqrt(4.0 * FMM_PI);
+            for (int mp = 0; mp < p; ++mp) {
+                if (mp > 0) pmm *= sqrt((2.0 * mp + 1.0) / (2.0 * mp)) * st;
+                double s, co;
+                sincos(mp * phi, &s, &co);
+                double pm2 = 0.0, pm1 = pmm;
+                double2 sp = cmk(0, 0), sn = cmk(0, 0);
+                for (int n = mp; n < p; ++n) {
+                    double P;
+                    if (n == mp) P = pmm;
+                    else if (n == mp + 1) P = sqrt(2.0 * mp + 3.0) * ct * pmm;
+                    else {
+                        double a = sqrt((4.0 * n * n - 1.0) / ((double)n * n - (double)mp * mp));
+                        double bq = sqrt((((double)n - 1) * (n - 1) - (double)mp * mp) * (2.0 * n + 1.0) /
+                                         ((2.0 * n - 3.0) * ((double)n * n - (double)mp * mp)));
+                        P = a * ct * pm1 - bq * pm2;
+                    }
+                    if (n >= mp + 1) {
+                        pm2 = pm1;
+                        pm1 = P;
+                    }
+                    double R = jb[n] * P;
+                    sp = cadd(sp, cscale(D[cidx(n, mp)], R));
+                    if (mp > 0) sn = cadd(sn, cscale(D[cidx(n, -mp)], R));
+                }
+                // sum_n D_n^m R e^{i m phi} + D_n^{-m} R e^{-i m phi}
+                far = cadd(far, cmul(sp, cmk(co, s)));
+                if (mp > 0) far = cadd(far, cmul(sn, cmk(co, -s)));
+            }
+        }
+        const int u = perm[t];
+        y[u] = cadd(cadd(cscale(x[u], half), ynear[t]), far);
+    }
+}
+
+// ------------------------------------------------------------------ field at points
+// out[q] = amp * G(r_q, rs) + sum_j [L_j(r_q) sigma_j + M_j(r_q) mu_j], accurate integrals for
+// elements with |r_q - c_j| < r_c, one-point rule otherwise.  One workgroup per point.
+__global__ void __launch_bounds__(256) k_field(int64_t nt, const double *pts, const double4 *ec, const double4 *en,
+                                               const double *ev, const double2 *sigma, const double2 *mu, double k,
+                                               double rc2, double sx, double sy, double sz, double2 amp,
+                                               double2 *out) {
+    const int q = blockIdx.x, tid = threadIdx.x;
+    const double x[3] = {pts[3 * q], pts[3 * q + 1], pts[3 * q + 2]};
+    double2 acc = cmk(0, 0);
+    const double inv4pi = 1.0 / (4.0 * FMM_PI);
+    for (int64_t j = tid; j < nt; j += blockDim.x) {
+        double4 c = ec[j];
+        double d2 = dist2_exact(x[0], x[1], x[2], c.x, c.y, c.z);
+        double2 L, M;
+        if (d2 < rc2) {
+            double v[9];
+            for (int e = 0; e < 9; ++e) v[e] = ev[9 * j + e];
+            tri_integrals(x, v, k, 0, L, M);
+        } else {
+            double4 nv = en[j];
+            double dx = c.x - x[0], dy = c.y - x[1], dz = c.z - x[2];
+            double r = sqrt(d2), s, co;
+            sincos(k * r, &s, &co);
+            double2 G = cmk(co / r * inv4pi, s / r * inv4pi);
+            double u = (dx * nv.x + dy * nv.y + dz * nv.z) / d2;
+            L = cscale(G, c.w);
+            M = cscale(cmul(G, cmk(-u, k * r * u)), c.w);
+        }
+        acc = cfma(L, sigma[j], acc);
+        acc = cfma(M, mu[j], acc);
+    }
+    __shared__ double2 red[256];
+    red[tid] = acc;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (tid < s) red[tid] = cadd(red[tid], red[tid + s]);
+        __syncthreads();
+    }
+    if (tid == 0) {
+        double dx = x[0] - sx, dy = x[1] - sy, dz = x[2] - sz;
+        double r = sqrt(dx * dx + dy * dy + dz * dz), s, co;
+        sincos(k * r, &s, &co);
+        out[q] = cadd(red[0], cmul(amp, cmk(co / r * inv4pi, s / r * inv4pi)));
+    }
+}
+
+}  // namespace fmm

@@ -1,0 +1,166 @@
+// Internal declarations of the fmmbem library (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/fmmbem.h"
+#include "common.h"
+#include "specfun.h"
+
+namespace fmm {
+
+// ---------------------------------------------------------------- device memory
+// Named, growable device allocations owned by a context.
+struct DeviceBuffers {
+    std::map<std::string, std::pair<void *, size_t>> bufs;
+    void *get(const std::string &name, size_t bytes) {
+        if (bytes == 0) bytes = 16;
+        auto it = bufs.find(name);
+        if (it != bufs.end() && it->second.second >= bytes) return it->second.first;
+        if (it != bufs.end()) {
+            HIP_OK(hipFree(it->second.first));
+            bufs.erase(it);
+        }
+        void *p = nullptr;
+        HIP_OK(hipMalloc(&p, bytes));
+        bufs[name] = {p, bytes};
+        return p;
+    }
+    void *find(const std::string &name) const {
+        auto it = bufs.find(name);
+        return it == bufs.end() ? nullptr : it->second.first;
+    }
+    void release(const std::string &name) {
+        auto it = bufs.find(name);
+        if (it != bufs.end()) {
+            (void)hipFree(it->second.first);
+            bufs.erase(it);
+        }
+    }
+    void release_all() {
+        for (auto &kv : bufs) (void)hipFree(kv.second.first);
+        bufs.clear();
+    }
+};
+
+template <class T>
+T *dget(DeviceBuffers &b, const std::string &name, size_t count) {
+    return (T *)b.get(name, sizeof(T) * count);
+}
+
+// ---------------------------------------------------------------- tables
+struct CoaxJob {
+    int kind;    // 0 = (S|R), 1 = (R|R)
+    int method;  // 0 = original (propagation in n), 1 = stabilised
+    int p;
+    double ktau;
+    double2 *out;
+};
+int64_t coax_ws_size(int p);
+void build_coax_tables(const std::vector<CoaxJob> &jobs, DeviceBuffers &scratch, hipStream_t st);
+void build_delta_table(int p, double *D, double *DT, hipStream_t st);
+
+// ---------------------------------------------------------------- octree (host)
+// translation directions: 343 box offsets (dx,dy,dz) in [-3,3]^3, index (dx+3)*49+(dy+3)*7+(dz+3),
+// then 8 child->parent unit diagonals (index 343 + octant) used by M2M (t = parent - child)
+// and their negatives (index 351 + octant) used by L2L (t = child - parent).
+constexpr int NDIR = 343 + 16;
+inline int dir_of_offset(int dx, int dy, int dz) { return (dx + 3) * 49 + (dy + 3) * 7 + (dz + 3); }
+
+struct LevelHost {
+    int level;
+    double side;                    // box side d_l
+    int p;                          // truncation number
+    std::vector<uint64_t> code;     // sorted Morton codes of the non-empty boxes
+    std::vector<int32_t> parent;    // index at level-1 (levels >= 1)
+    std::vector<int8_t> octant;     // child octant within the parent
+    std::vector<int32_t> child_start, child_list;  // children at level+1 (CSR)
+    // M2L interaction list, grouped by target box (CSR)
+    std::vector<int32_t> m2l_start, m2l_src;
+    std::vector<int16_t> m2l_dir;
+    std::vector<int> m2l_tau_of_dir;  // size 343: index into the distinct |t| list, or -1
+    std::vector<double> m2l_taus;     // distinct |t| (m)
+};
+
+struct TreeHost {
+    double lo[3], side;  // bounding cube
+    int depth;           // leaf level L
+    std::vector<int32_t> perm;        // sorted position -> caller index
+    std::vector<int32_t> leaf_start;  // CSR of sorted elements per leaf (level L box)
+    std::vector<int32_t> nbr_start, nbr_list;  // P2P source leaves per target leaf
+    std::vector<LevelHost> lv;        // index = level (0..L); levels < 2 hold no expansions
+    int max_occ = 0;
+};
+
+void box_center(const TreeHost &T, int l, uint64_t code, double *c);
+void build_tree(const double *centroids, int64_t n, const double *vlo, const double *vhi, double rc,
+                int leaf_max, int max_depth, TreeHost &T);
+
+// ---------------------------------------------------------------- per-level device data
+struct LevelDev {
+    int p = 0;
+    int64_t nbox = 0;
+    double side = 0;
+    double4 *center = nullptr;   // box centres
+    double2 *M = nullptr;        // multipole coefficients nbox * p^2
+    double2 *L = nullptr;        // local coefficients nbox * p^2
+    // M2L jobs (target-grouped): src box, target box, direction, |t| table
+    int64_t njob_m2l = 0;
+    int32_t *m2l_tgt = nullptr, *m2l_src = nullptr, *m2l_start = nullptr;
+    int16_t *m2l_dir = nullptr;
+    int8_t *m2l_tau = nullptr;
+    double2 *coax_m2l = nullptr;  // ntau tables of coax_table_size(p)
+    int ntau = 0;
+    double2 *coax_up = nullptr;   // (R|R) for the link to level+1 (square, size p)
+    int32_t *parent = nullptr;    // parent index at level-1
+    int8_t *octant = nullptr;
+    int32_t *child_start = nullptr;  // children at level+1 (CSR), sorted so that child jobs group
+};
+
+struct Timings {
+    double ms[8] = {0};
+};
+
+}  // namespace fmm
+
+// ---------------------------------------------------------------- the context
+struct fmmbem_ctx {
+    int device = 0;
+    fmmbem_options opt{};
+    std::string err;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev[9] = {};
+    fmm::DeviceBuffers buf;      // persistent per-setup arrays
+    fmm::DeviceBuffers scratch;  // per-call workspaces
+
+    // inputs (host copies, caller order)
+    std::vector<double> xyz;
+    std::vector<int64_t> tri;
+    int64_t nv = 0, nt = 0;
+    double k = 0.0;
+    std::vector<double2> beta;
+    std::vector<double> src;
+    std::vector<double2> src_amp;
+    int formulation = FMMBEM_DIRECT;
+
+    // dirty flags
+    bool mesh_dirty = true, k_dirty = true, beta_dirty = true;
+    bool have_mesh = false, have_k = false, have_beta = false;
+
+    // derived
+    double rc = 0.0;
+    fmm::TreeHost tree;
+    std::vector<fmm::LevelDev> lev;
+    std::vector<std::vector<int32_t>> iota_h;  // per level: 0..nbox (one job per child)
+    int pmax = 0, delta_p = 0;
+    int64_t near_nnz = 0;
+    int64_t p2p_pairs = 0;
+    bool precond_ready_nb = false, precond_ready_diag = false;
+    fmm::Timings last;
+    double t_setup_last = 0.0;
+};

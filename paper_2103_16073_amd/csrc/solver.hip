@@ -1,0 +1,384 @@
+// Flexible GMRES (the paper's outer solver, Section 4.4) with FP64 Arnoldi on the device and a
+// preconditioner slot: identity, diagonal (the paper's indirect-BEM choice: a constant added to
+// the diagonal), or the exact inverse of the operator restricted to each octree leaf.
+//
+// Arnoldi uses classical Gram-Schmidt applied twice (CGS2): each pass is one batched set of
+// inner products (two-stage, fixed-order reductions, so runs are bitwise reproducible) and one
+// batched update.  Givens rotations and the small least-squares problem live on the host; one
+// short host<->device copy per pass.
+#include <chrono>
+#include <functional>
+
+#include "internal.h"
+
+namespace fmm {
+
+constexpr int DOT_BLOCKS = 512;
+
+// partial[v * DOT_BLOCKS + blk] = sum_{i in blk's stride} conj(V_v[i]) w[i]
+__global__ void __launch_bounds__(256) k_dot_partial(int64_t n, const double2 *V, int64_t ldv, int nv, const double2 *w,
+                                                     double2 *partial) {
+    const int v = blockIdx.y;
+    const double2 *x = V + (int64_t)v * ldv;
+    double2 s = cmk(0, 0);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        s = cadd(s, cmulc(w[i], x[i]));  // conj(x) w
+    __shared__ double2 red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int q = blockDim.x / 2; q > 0; q >>= 1) {
+        if ((int)threadIdx.x < q) red[threadIdx.x] = cadd(red[threadIdx.x], red[threadIdx.x + q]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(int64_t)v * gridDim.x + blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) k_dot_final(int nblk, const double2 *partial, double2 *out) {
+    const int v = blockIdx.x;
+    double2 s = cmk(0, 0);
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) s = cadd(s, partial[(int64_t)v * nblk + i]);
+    __shared__ double2 red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int q = blockDim.x / 2; q > 0; q >>= 1) {
+        if ((int)threadIdx.x < q) red[threadIdx.x] = cadd(red[threadIdx.x], red[threadIdx.x + q]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[v] = red[0];
+}
+
+// w -= sum_v h[v] V_v
+__global__ void k_sub_combo(int64_t n, const double2 *V, int64_t ldv, int nv, const double2 *h, double2 *w) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double2 s = w[i];
+    for (int v = 0; v < nv; ++v) s = csub(s, cmul(h[v], V[(int64_t)v * ldv + i]));
+    w[i] = s;
+}
+
+// x += sum_v y[v] Z_v
+__global__ void k_add_combo(int64_t n, const double2 *Z, int64_t ldz, int nv, const double2 *y, double2 *x) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double2 s = x[i];
+    for (int v = 0; v < nv; ++v) s = cadd(s, cmul(y[v], Z[(int64_t)v * ldz + i]));
+    x[i] = s;
+}
+
+__global__ void k_scale_copy(int64_t n, double a, const double2 *x, double2 *y) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = cscale(x[i], a);
+}
+
+__global__ void k_sub(int64_t n, const double2 *a, const double2 *b, double2 *out) {  // out = a - b
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = csub(a[i], b[i]);
+}
+
+__global__ void k_mul_diag(int64_t n, const double2 *d, const double2 *v, double2 *z) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) z[i] = cmul(d[i], v[i]);
+}
+
+// ------------------------------------------------------------------ preconditioners
+// inverse diagonal, caller order: 1 / (1/2 + M_ii - i k beta_i L_ii + shift)
+__global__ void k_diag_inv(int64_t n, const int32_t *perm, const int32_t *near_start, const int32_t *near_col,
+                           const double2 *nL, const double2 *nM, const double2 *beta, double k, double shift,
+                           double2 *dinv) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double2 a = cmk(0.5 + shift, 0.0);
+    for (int e = near_start[i]; e < near_start[i + 1]; ++e)
+        if (near_col[e] == i) {
+            double2 ikb = cmk(-k * beta[i].y, k * beta[i].x);
+            a = cadd(a, csub(nM[e], cmul(ikb, nL[e])));
+        }
+    dinv[perm[i]] = cdiv(cmk(1, 0), a);
+}
+
+// dense operator block of each leaf, row-major n_b x n_b at blk_off[b] (sorted element order)
+__global__ void __launch_bounds__(256) k_leaf_blocks(int nleaf, const int32_t *leaf_start, const int64_t *blk_off,
+                                                     const double4 *ec, const double4 *en, const double2 *beta,
+                                                     double k, double rc2, const int32_t *near_start,
+                                                     const int32_t *near_col, const double2 *nL, const double2 *nM,
+                                                     double2 *A) {
+    const int b = blockIdx.x;
+    const int s = leaf_start[b], nb = leaf_start[b + 1] - s;
+    double2 *Ab = A + blk_off[b];
+    const double inv4pi = 1.0 / (4.0 * FMM_PI);
+    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
+        int i = s + e / nb, j = s + e % nb;
+        double4 ci = ec[i], cj = ec[j];
+        double d2 = dist2_exact(ci.x, ci.y, ci.z, cj.x, cj.y, cj.z);
+        double2 v = cmk(0, 0);
+        if (i != j && d2 >= rc2) {
+            double4 nj = en[j];
+            double r = sqrt(d2), sn, cs;
+            sincos(k * r, &sn, &cs);
+            double2 G = cmk(cs / r * inv4pi * cj.w, sn / r * inv4pi * cj.w);  // A_j G
+            double u = ((cj.x - ci.x) * nj.x + (cj.y - ci.y) * nj.y + (cj.z - ci.z) * nj.z) / d2;
+            double2 M = cmul(G, cmk(-u, k * r * u));
+            double2 ikb = cmk(-k * beta[j].y, k * beta[j].x);
+            v = csub(M, cmul(ikb, G));
+        }
+        if (i == j) v.x += 0.5;
+        Ab[e] = v;
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < nb; r += blockDim.x) {
+        int i = s + r;
+        for (int e = near_start[i]; e < near_start[i + 1]; ++e) {
+            int j = near_col[e];
+            if (j < s || j >= s + nb) continue;
+            double2 ikb = cmk(-k * beta[j].y, k * beta[j].x);
+            Ab[(int64_t)r * nb + (j - s)] = cadd(Ab[(int64_t)r * nb + (j - s)], csub(nM[e], cmul(ikb, nL[e])));
+        }
+    }
+}
+
+// in-place Gauss-Jordan inversion with partial pivoting, one workgroup per leaf block
+__global__ void __launch_bounds__(256) k_leaf_invert(int nleaf, const int32_t *leaf_start, const int64_t *blk_off,
+                                                     double2 *A, int32_t *piv_ws, int *status) {
+    const int b = blockIdx.x;
+    const int nb = leaf_start[b + 1] - leaf_start[b];
+    double2 *M = A + blk_off[b];
+    int32_t *piv = piv_ws + leaf_start[b];
+    __shared__ int sp;
+    __shared__ double sbest[256];
+    __shared__ int sidx[256];
+    __shared__ double2 prow[1024];
+    for (int c = 0; c < nb; ++c) {
+        // pivot search in column c, rows c..nb-1
+        double best = -1.0;
+        int bi = c;
+        for (int r = c + threadIdx.x; r < nb; r += blockDim.x) {
+            double2 v = M[(int64_t)r * nb + c];
+            double a = v.x * v.x + v.y * v.y;
+            if (a > best) {
+                best = a;
+                bi = r;
+            }
+        }
+        sbest[threadIdx.x] = best;
+        sidx[threadIdx.x] = bi;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double bb = -1.0;
+            int ii = c;
+            for (int t = 0; t < (int)blockDim.x; ++t)
+                if (sbest[t] > bb) {
+                    bb = sbest[t];
+                    ii = sidx[t];
+                }
+            sp = ii;
+            piv[c] = ii;
+            if (!(bb > 0.0)) atomicExch(status, 1);
+        }
+        __syncthreads();
+        const int pr = sp;
+        if (pr != c)
+            for (int q = threadIdx.x; q < nb; q += blockDim.x) {
+                double2 t = M[(int64_t)c * nb + q];
+                M[(int64_t)c * nb + q] = M[(int64_t)pr * nb + q];
+                M[(int64_t)pr * nb + q] = t;
+            }
+        __syncthreads();
+        const double2 pv = M[(int64_t)c * nb + c];
+        const double2 ipv = cdiv(cmk(1, 0), pv);
+        // scale pivot row: row c <- row c / pv, with the inverse's column c set to 1/pv
+        for (int q = threadIdx.x; q < nb; q += blockDim.x) {
+            double2 v = (q == c) ? cmk(1, 0) : M[(int64_t)c * nb + q];
+            prow[q] = cmul(v, ipv);
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < nb; q += blockDim.x) M[(int64_t)c * nb + q] = prow[q];
+        __syncthreads();
+        // eliminate column c from every other row (each thread owns whole rows)
+        for (int r = threadIdx.x; r < nb; r += blockDim.x) {
+            if (r == c) continue;
+            double2 f = M[(int64_t)r * nb + c];
+            for (int q = 0; q < nb; ++q) {
+                double2 v = (q == c) ? cmk(0, 0) : M[(int64_t)r * nb + q];
+                M[(int64_t)r * nb + q] = csub(v, cmul(f, prow[q]));
+            }
+        }
+        __syncthreads();
+    }
+    // undo the column permutation implied by the row swaps (in reverse order)
+    for (int c = nb - 1; c >= 0; --c) {
+        const int pr = piv[c];
+        if (pr != c)
+            for (int r = threadIdx.x; r < nb; r += blockDim.x) {
+                double2 t = M[(int64_t)r * nb + c];
+                M[(int64_t)r * nb + c] = M[(int64_t)r * nb + pr];
+                M[(int64_t)r * nb + pr] = t;
+            }
+        __syncthreads();
+    }
+}
+
+// z = blockdiag(A_BB^{-1}) v, vectors in caller order
+__global__ void __launch_bounds__(128) k_leaf_apply(int nleaf, const int32_t *leaf_start, const int64_t *blk_off,
+                                                    const double2 *Ainv, const int32_t *perm, const double2 *v,
+                                                    double2 *z) {
+    const int b = blockIdx.x;
+    const int s = leaf_start[b], nb = leaf_start[b + 1] - s;
+    const double2 *M = Ainv + blk_off[b];
+    __shared__ double2 vs[1024];
+    for (int q = threadIdx.x; q < nb; q += blockDim.x) vs[q] = v[perm[s + q]];
+    __syncthreads();
+    for (int r = threadIdx.x; r < nb; r += blockDim.x) {
+        double2 acc = cmk(0, 0);
+        for (int q = 0; q < nb; ++q) acc = cfma(M[(int64_t)r * nb + q], vs[q], acc);
+        z[perm[s + r]] = acc;
+    }
+}
+
+// ------------------------------------------------------------------ host helpers
+struct Blas {
+    hipStream_t st;
+    DeviceBuffers &scr;
+    int64_t n;
+    void dots(const double2 *V, int64_t ldv, int nv, const double2 *w, double2 *host_out) {
+        double2 *part = dget<double2>(scr, "dot_part", (size_t)DOT_BLOCKS * std::max(nv, 1));
+        double2 *res = dget<double2>(scr, "dot_res", std::max(nv, 1));
+        int nblk = (int)std::min<int64_t>(DOT_BLOCKS, std::max<int64_t>(1, (n + 255) / 256));
+        k_dot_partial<<<dim3(nblk, nv), 256, 0, st>>>(n, V, ldv, nv, w, part);
+        LAUNCH_OK();
+        k_dot_final<<<nv, 256, 0, st>>>(nblk, part, res);
+        LAUNCH_OK();
+        HIP_OK(hipMemcpyAsync(host_out, res, sizeof(double2) * nv, hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+    }
+    double nrm(const double2 *w) {
+        double2 d;
+        dots(w, 0, 1, w, &d);
+        return sqrt(std::max(d.x, 0.0));
+    }
+    void sub_combo(const double2 *V, int64_t ldv, int nv, const double2 *h_host, double2 *w) {
+        double2 *h = dget<double2>(scr, "combo_h", std::max(nv, 1));
+        HIP_OK(hipMemcpyAsync(h, h_host, sizeof(double2) * nv, hipMemcpyHostToDevice, st));
+        k_sub_combo<<<ceil_div(n, 256), 256, 0, st>>>(n, V, ldv, nv, h, w);
+        LAUNCH_OK();
+    }
+    void add_combo(const double2 *Z, int64_t ldz, int nv, const double2 *y_host, double2 *x) {
+        double2 *h = dget<double2>(scr, "combo_y", std::max(nv, 1));
+        HIP_OK(hipMemcpyAsync(h, y_host, sizeof(double2) * nv, hipMemcpyHostToDevice, st));
+        k_add_combo<<<ceil_div(n, 256), 256, 0, st>>>(n, Z, ldz, nv, h, x);
+        LAUNCH_OK();
+    }
+    void scale_copy(double a, const double2 *x, double2 *y) {
+        k_scale_copy<<<ceil_div(n, 256), 256, 0, st>>>(n, a, x, y);
+        LAUNCH_OK();
+    }
+    void sub(const double2 *a, const double2 *b, double2 *out) {
+        k_sub<<<ceil_div(n, 256), 256, 0, st>>>(n, a, b, out);
+        LAUNCH_OK();
+    }
+};
+
+static inline double cabs_(double2 a) { return hypot(a.x, a.y); }
+
+// Restarted FGMRES(m).  matvec(x, y) and precond(v, z) act on device vectors of length n.
+// Returns FMMBEM_OK / FMMBEM_ENOCONV / error codes; rel_res is the true relative residual of the
+// last restart (computed with `matvec_check`, the FP64 operator).
+int fgmres(int64_t n, hipStream_t st, DeviceBuffers &scr, const std::function<void(const double2 *, double2 *)> &matvec,
+           const std::function<void(const double2 *, double2 *)> &matvec_check,
+           const std::function<void(const double2 *, double2 *)> &precond, const double2 *b, double2 *x, double tol,
+           int m, int maxit, bool x0_given, int &iters, int &restarts, double &rel_res) {
+    Blas B{st, scr, n};
+    double2 *V = dget<double2>(scr, "fg_V", (size_t)(m + 1) * n);
+    double2 *Z = dget<double2>(scr, "fg_Z", (size_t)m * n);
+    double2 *w = dget<double2>(scr, "fg_w", n);
+    double2 *r = dget<double2>(scr, "fg_r", n);
+    if (!x0_given) HIP_OK(hipMemsetAsync(x, 0, sizeof(double2) * n, st));
+    const double bn = B.nrm(b);
+    iters = 0;
+    restarts = 0;
+    rel_res = 1.0;
+    if (!(bn > 0.0)) {
+        HIP_OK(hipMemsetAsync(x, 0, sizeof(double2) * n, st));
+        rel_res = 0.0;
+        return FMMBEM_OK;
+    }
+    std::vector<double2> H((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), h1(m + 1), h2(m + 1), y(m);
+    auto Hc = [&](int i, int j) -> double2 & { return H[(size_t)i * m + j]; };
+    int status = FMMBEM_ENOCONV;
+    while (true) {
+        // true residual
+        if (x0_given || restarts > 0) {
+            matvec_check(x, w);
+            B.sub(b, w, r);
+        } else {
+            HIP_OK(hipMemcpyAsync(r, b, sizeof(double2) * n, hipMemcpyDeviceToDevice, st));
+        }
+        double beta = B.nrm(r);
+        rel_res = beta / bn;
+        if (!std::isfinite(beta)) return FMMBEM_ENAN;
+        if (rel_res < tol) {
+            status = FMMBEM_OK;
+            break;
+        }
+        if (iters >= maxit) break;
+        B.scale_copy(1.0 / beta, r, V);
+        std::fill(g.begin(), g.end(), cmk(0, 0));
+        g[0] = cmk(beta, 0);
+        int j = 0;
+        bool done = false;
+        for (j = 0; j < m && iters < maxit; ++j) {
+            double2 *vj = V + (size_t)j * n, *zj = Z + (size_t)j * n;
+            precond(vj, zj);
+            matvec(zj, w);
+            ++iters;
+            // CGS2
+            B.dots(V, n, j + 1, w, h1.data());
+            B.sub_combo(V, n, j + 1, h1.data(), w);
+            B.dots(V, n, j + 1, w, h2.data());
+            B.sub_combo(V, n, j + 1, h2.data(), w);
+            for (int i = 0; i <= j; ++i) Hc(i, j) = cadd(h1[i], h2[i]);
+            double hn = B.nrm(w);
+            if (!std::isfinite(hn)) return FMMBEM_ENAN;
+            Hc(j + 1, j) = cmk(hn, 0);
+            if (hn > 0) B.scale_copy(1.0 / hn, w, V + (size_t)(j + 1) * n);
+            for (int i = 0; i < j; ++i) {
+                double2 a = Hc(i, j), c = Hc(i + 1, j);
+                Hc(i, j) = cadd(cscale(a, cs[i].x), cmul(sn[i], c));
+                Hc(i + 1, j) = csub(cscale(c, cs[i].x), cmul(cconj(sn[i]), a));
+            }
+            double2 a = Hc(j, j), c = Hc(j + 1, j);
+            double den = hypot(cabs_(a), cabs_(c));
+            if (den == 0) {
+                cs[j] = cmk(1, 0);
+                sn[j] = cmk(0, 0);
+            } else {
+                double aa = cabs_(a);
+                cs[j] = cmk(aa / den, 0);
+                double2 ph = aa > 0 ? cscale(a, 1.0 / aa) : cmk(1, 0);
+                sn[j] = cscale(cmul(ph, cconj(c)), 1.0 / den);
+            }
+            Hc(j, j) = cadd(cscale(a, cs[j].x), cmul(sn[j], c));
+            Hc(j + 1, j) = cmk(0, 0);
+            g[j + 1] = cscale(cmul(cconj(sn[j]), g[j]), -1.0);
+            g[j] = cscale(g[j], cs[j].x);
+            if (cabs_(g[j + 1]) / bn < tol || hn == 0) {
+                ++j;
+                done = true;
+                break;
+            }
+        }
+        // y = H^{-1} g (upper triangular)
+        for (int i = j - 1; i >= 0; --i) {
+            double2 s = g[i];
+            for (int q = i + 1; q < j; ++q) s = csub(s, cmul(Hc(i, q), y[q]));
+            if (cabs_(Hc(i, i)) == 0) return FMMBEM_EBREAKDOWN;
+            y[i] = cdiv(s, Hc(i, i));
+        }
+        B.add_combo(Z, n, j, y.data(), x);
+        ++restarts;
+        x0_given = true;
+        (void)done;
+    }
+    return status;
+}
+
+}  // namespace fmm

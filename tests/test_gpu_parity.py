@@ -1,0 +1,170 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle, element by element."""
+import numpy as np
+import pytest
+
+from oracle import bem
+from oracle import coeffs as OC
+from paper_2103_16073_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def F():
+    from paper_2103_16073_amd import fmmbem
+    fmmbem.lib()
+    return fmmbem
+
+
+def make_ctx(F, room, k, **opt):
+    ctx = F.Context(0, **opt)
+    ctx.fmmbem_set_mesh(room.vertices, room.triangles)
+    ctx.fmmbem_set_wavenumber(k)
+    ctx.fmmbem_set_admittance(room.beta)
+    return ctx
+
+
+# ----------------------------------------------------------------------------- tables
+@pytest.mark.parametrize("kind,ktau,p", [("SR", 5.0, 12), ("SR", 40.0, 30), ("RR", 5.0, 12), ("RR", 60.0, 40),
+                                         ("SR", 0.6, 10), ("RR", 0.4, 10)])
+def test_coaxial_table_vs_projection(F, kind, ktau, p):
+    """Device recursion (stabilised for k tau >= 1, original below) against the projection
+    definition of the coefficients."""
+    blocks = F.fmmbem_coaxial_table(0 if kind == "SR" else 1, ktau, p)
+    for m in sorted({0, 1, 2, p // 3, p - 2}):
+        ref = OC.coaxial_projection(kind, 1.0, ktau, p, m)
+        got = blocks[m]
+        r = ref[m:, m:]
+        scale = np.max(np.abs(r))
+        assert np.max(np.abs(got - r)) < 1e-9 * scale, (m, np.max(np.abs(got - r)) / scale)
+
+
+def test_coaxial_original_vs_stabilised_overlap(F):
+    """Both device schemes agree where the original one is still accurate (k tau = 3)."""
+    p = 20
+    for kind in (0, 1):
+        a = F.fmmbem_coaxial_table(kind, 3.0, p, method=0)
+        b = F.fmmbem_coaxial_table(kind, 3.0, p, method=1)
+        for m in range(p):
+            s = np.max(np.abs(b[m]))
+            assert np.max(np.abs(a[m] - b[m])) < 1e-10 * s
+
+
+def test_coaxial_stable_at_high_ktau(F):
+    """k tau = 150, p = 130 (R|R): the stabilised scheme matches the definition; the original
+    propagation in n does not (the instability analysed in Section 3.3.1)."""
+    p, kt = 130, 150.0
+    st = F.fmmbem_coaxial_table(1, kt, p, method=1)
+    orig = F.fmmbem_coaxial_table(1, kt, p, method=0)
+    m = 40
+    ref = OC.coaxial_projection("RR", 1.0, kt, p, m)[m:, m:]
+    assert np.max(np.abs(st[m] - ref)) < 1e-9
+    assert np.max(np.abs(orig[m] - ref)) > 1.0
+
+
+def test_rotation_table_vs_projection(F):
+    p = 10
+    D = F.fmmbem_rotation_table(p)
+    T = OC.rotation_projection(p - 1, OC.rot_y(np.pi / 2))
+    for n in range(p):
+        assert np.max(np.abs(D[n] - T[n].real)) < 1e-12
+        assert np.max(np.abs(T[n].imag)) < 1e-12
+
+
+def test_rotation_table_orthogonal_high_degree(F):
+    D = F.fmmbem_rotation_table(500)
+    for n in (100, 300, 499):
+        err = np.max(np.abs(D[n] @ D[n].T - np.eye(2 * n + 1)))
+        assert err < 1e-12, (n, err)
+
+
+# ----------------------------------------------------------------------------- near field
+def test_near_entries_vs_oracle(F):
+    room = synth.shoebox(3.0, 2.5, 2.0, 0.34)
+    k = synth.wavenumber(250.0)
+    ctx = make_ctx(F, room, k)
+    rows, cols, L, M = ctx.fmmbem_near_entries()
+    rc = ctx.fmmbem_get_info().rc
+    c, _, _ = bem.geometry(room.vertices, room.triangles)
+    # same pair set as the oracle's classification
+    d2 = ((c[:, None, :] - c[None, :, :]) ** 2).sum(-1)
+    near = (d2 < rc * rc) | np.eye(room.n, dtype=bool)
+    assert len(rows) == near.sum()
+    assert near[rows, cols].all()
+    # margin: no pair within 1e-9 (relative) of the cutoff
+    assert np.min(np.abs(np.sqrt(d2[~np.eye(room.n, dtype=bool)]) - rc)) > 1e-9 * rc
+    sel = np.random.default_rng(0).choice(len(rows), 300, replace=False)
+    for e in sel:
+        tri = room.vertices[room.triangles[cols[e]]]
+        Lr, Mr = bem.pair(c[rows[e]], tri, k, self=(rows[e] == cols[e]))
+        assert abs(L[e] - Lr) < 1e-11 * abs(Lr)
+        assert abs(M[e] - Mr) < 1e-11 * abs(Lr)
+    ctx.close()
+
+
+# ----------------------------------------------------------------------------- products
+@pytest.fixture(scope="module")
+def cfg1_dense():
+    room, k = synth.config_room(1)
+    return room, k
+
+
+def test_matvec_exact_far_vs_dense(F, cfg1_dense):
+    room, k = cfg1_dense
+    ctx = make_ctx(F, room, k)
+    rc = ctx.fmmbem_get_info().rc
+    L, M = bem.dense_LM(room.vertices, room.triangles, k, rc)
+    for seed in (1, 2):
+        x = synth.complex_normal(room.n, seed)
+        ref = 0.5 * x + M @ x - 1j * k * L @ (room.beta * x)
+        y = ctx.fmmbem_matvec(x, exact_far=True)[0]
+        assert np.linalg.norm(y - ref) / np.linalg.norm(ref) < 1e-12
+    ctx.close()
+
+
+@pytest.mark.parametrize("leaf_max", [64, 12, 4])
+def test_matvec_fmm_vs_dense(F, cfg1_dense, leaf_max):
+    """FP64 FMM product against the oracle's dense operator: relative L2 <= 1e-6, for octrees of
+    depth 2, 3 and 4 (so M2M/L2L are exercised)."""
+    room, k = cfg1_dense
+    ctx = make_ctx(F, room, k, leaf_max=leaf_max)
+    info = ctx.fmmbem_get_info()
+    L, M = bem.dense_LM(room.vertices, room.triangles, k, info.rc)
+    for seed in (1, 2):
+        x = synth.complex_normal(room.n, seed)
+        ref = 0.5 * x + M @ x - 1j * k * L @ (room.beta * x)
+        y = ctx.fmmbem_matvec(x)[0]
+        err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+        print(f"depth {info.depth} p {list(info.p)[:info.depth + 1]} err {err:.3e}")
+        assert err < 1e-6
+    ctx.close()
+
+
+def test_rhs_vs_oracle(F, cfg1_dense):
+    room, k = cfg1_dense
+    ctx = make_ctx(F, room, k)
+    rs, _ = synth.source_and_receivers(room, 4)
+    ctx.fmmbem_set_sources(rs)
+    b = ctx.fmmbem_rhs()[0]
+    rc = ctx.fmmbem_get_info().rc
+    rows = np.arange(0, room.n, 5)
+    ref = bem.direct_rhs_rows(room.vertices, room.triangles, k, room.beta, rs[0], rc, rows)
+    assert np.linalg.norm(b[rows] - ref) / np.linalg.norm(ref) < 1e-6
+    ctx.close()
+
+
+def test_solve_and_field_vs_oracle_lu(F, cfg1_dense):
+    room, k = cfg1_dense
+    ctx = make_ctx(F, room, k)
+    rs, rec = synth.source_and_receivers(room, 16)
+    ctx.fmmbem_set_sources(rs)
+    x, rep, rc_ = ctx.fmmbem_solve(0, tol=1e-9, restart=40, maxit=300)
+    assert rc_ == 0 and rep.rel_res < 1e-9
+    rc = ctx.fmmbem_get_info().rc
+    A, b, _, _ = bem.direct_system(room.vertices, room.triangles, k, room.beta, rs[0], rc)
+    x_ref = bem.solve_lu(A, b)
+    assert np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref) < 1e-5
+    psi = ctx.fmmbem_eval_field(0, rec, x)
+    psi_ref = bem.direct_receivers(room.vertices, room.triangles, k, room.beta, rs[0], rc, x, rec)
+    assert np.linalg.norm(psi - psi_ref) / np.linalg.norm(psi_ref) < 1e-10
+    ctx.close()
