@@ -47,8 +47,8 @@ __device__ inline double2 expm1_i_over(double z) {
 // r^2 = rho^2 + h^2 the radial integrals are exact:
 //   int_0^{rho_e} G rho drho        = (e^{ikR} - e^{ik|h|}) / (4 pi i k)
 //   int_0^{rho_e} dG/dn_y rho drho  = -h/(4 pi) (e^{ikR}/R - e^{ik|h|}/|h|),   R = r(rho_e)
-// leaving an angular integral per edge (signed by the edge orientation seen from x_p),
-// done by 8 panels x 8-point Gauss-Legendre in the angle from the edge normal.
+// leaving an angular integral per edge (signed by the edge orientation seen from x_p), done by
+// 8 panels x 8-point Gauss-Legendre after the substitution tan(psi) = sinh(w).
 // self != 0: x is the triangle's centroid (h = 0, M = 0 by the principal value).
 __device__ void tri_integrals(const double *x, const double *v, double k, int self, double2 &Lout, double2 &Mout) {
     double e1[3] = {v[3] - v[0], v[4] - v[1], v[5] - v[2]};
@@ -77,15 +77,20 @@ __device__ void tri_integrals(const double *x, const double *v, double k, int se
         if (d <= 1e-13 * le) continue;
         double cr[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
         double sgn = (cr[0] * nn[0] + cr[1] * nn[1] + cr[2] * nn[2]) >= 0.0 ? 1.0 : -1.0;
-        double p0 = atan2(s0, d), p1 = atan2(s1, d);
-        span += sgn * (p1 - p0);
+        span += sgn * (atan2(s1, d) - atan2(s0, d));
+        // angle psi from the edge normal, substituted tan(psi) = sinh(w): rho = d cosh(w),
+        // dpsi = dw / cosh(w); this grades the panels logarithmically along edges that are long
+        // compared with their distance d from x_p, where the integrand varies fastest
+        const double w0 = asinh(s0 / d), w1 = asinh(s1 / d);
         const int NPAN = 8;
-        double hw = 0.5 * (p1 - p0) / NPAN;
+        double hw = 0.5 * (w1 - w0) / NPAN;
         for (int pan = 0; pan < NPAN; ++pan) {
-            double mid = p0 + (2 * pan + 1) * hw;
+            double mid = w0 + (2 * pan + 1) * hw;
             for (int q = 0; q < 8; ++q) {
-                double ps = mid + hw * GL8X[q], w = sgn * hw * GL8W[q];
-                double rho = d / cos(ps);
+                double ww = mid + hw * GL8X[q];
+                double ch = cosh(ww);
+                double w = sgn * hw * GL8W[q] / ch;
+                double rho = d * ch;
                 double R = sqrt(rho * rho + h * h);
                 double dR = R - ah;
                 double2 E = expm1_i_over(k * dR);
@@ -542,7 +547,9 @@ __global__ void __launch_bounds__(64) k_l2p(int nleaf, int p, const int32_t *lea
             }
         }
         const int u = perm[t];
-        y[u] = cadd(cadd(cscale(x[u], half), ynear[t]), far);
+        double2 v = cadd(ynear[t], far);
+        if (x) v = cadd(v, cscale(x[u], half));  // the right-hand side pass has no identity term
+        y[u] = v;
     }
 }
 
