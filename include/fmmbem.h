@@ -201,6 +201,23 @@ int fmmbem_coaxial_table(int hip_device, int kind, double ktau, int p, int metho
  * index + n), sum_n (2n+1)^2 doubles. */
 int fmmbem_rotation_table(int hip_device, int p, double *out);
 
+/* Kernel-level profiling.  When enabled, every kernel launch of the matrix-vector product is
+ * bracketed by hipEvents on the library's stream and its algorithmic work (flops, HBM bytes,
+ * counted from the problem sizes, not from hardware counters) is accumulated per kernel class. */
+typedef struct {
+    char name[32];
+    int64_t launches;
+    double ms;     /* summed device time of the launches */
+    double flops;  /* summed algorithmic FP64/FP32 flops */
+    double bytes;  /* summed algorithmic HBM bytes */
+} fmmbem_kstat;
+
+/* enable != 0: reset the statistics and start collecting; 0: stop. */
+int fmmbem_profile(fmmbem_ctx *ctx, int enable);
+/* Copy up to `max` kernel classes into out; *count receives the number of classes.  Waits for
+ * the work enqueued so far. */
+int fmmbem_kernel_stats(fmmbem_ctx *ctx, int max, fmmbem_kstat *out, int *count);
+
 /* Per-phase device time of the last matvec in milliseconds (hipEvent based):
  * [0] densities, [1] P2P+near, [2] P2M, [3] M2M, [4] M2L, [5] L2L, [6] L2P+combine, [7] total. */
 int fmmbem_last_timings(fmmbem_ctx *ctx, double *ms8);

@@ -29,7 +29,7 @@ __global__ void k_rot_fwd(int64_t, int, int, const double2 *, const int32_t *, c
 __global__ void k_coax_apply(int64_t, int, int, int, int, const double2 *, const double2 *, const int8_t *, double2 *);
 __global__ void k_rot_back(int64_t, int, int, const double2 *, const int16_t *, const double2 *, const double2 *, int,
                            const double *, const double *, double2 *);
-__global__ void k_reduce_jobs(int64_t, int, int, const int32_t *, const int32_t *, const double2 *, double2 *, int);
+__global__ void k_reduce_jobs(int64_t, int, int, const int32_t *, int32_t, const double2 *, double2 *, int);
 __global__ void k_l2p(int, int, const int32_t *, const double4 *, const double4 *, const double2 *, double,
                       const double2 *, double, const int32_t *, const double2 *, double2 *, int);
 __global__ void k_field(int64_t, const double *, const double4 *, const double4 *, const double *, const double2 *,
@@ -298,9 +298,64 @@ static void ensure_setup(fmmbem_ctx *c) {
     if (any) c->t_setup_last = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
+// ------------------------------------------------------------------ kernel profiling
+static void prof_flush(fmmbem_ctx *c) {
+    if (c->prof_pend.empty()) return;
+    HIP_OK(hipStreamSynchronize(c->stream));
+    for (auto &r : c->prof_pend) {
+        float ms = 0;
+        HIP_OK(hipEventElapsedTime(&ms, c->prof_ev[r.a], c->prof_ev[r.b]));
+        auto &s = c->prof_stats[r.cls];
+        s.launches += 1;
+        s.ms += ms;
+        s.flops += r.flops;
+        s.bytes += r.bytes;
+    }
+    c->prof_pend.clear();
+    c->prof_used = 0;
+}
+static int prof_begin(fmmbem_ctx *c) {
+    if (!c->prof_on) return -1;
+    if (c->prof_used + 2 > (int)c->prof_ev.size()) prof_flush(c);
+    while ((int)c->prof_ev.size() < c->prof_used + 2) {
+        hipEvent_t e;
+        HIP_OK(hipEventCreate(&e));
+        c->prof_ev.push_back(e);
+    }
+    int a = c->prof_used;
+    c->prof_used += 2;
+    HIP_OK(hipEventRecord(c->prof_ev[a], c->stream));
+    return a;
+}
+static void prof_end(fmmbem_ctx *c, int a, const char *name, double flops, double bytes) {
+    if (a < 0) return;
+    HIP_OK(hipEventRecord(c->prof_ev[a + 1], c->stream));
+    int cls = -1;
+    for (size_t q = 0; q < c->prof_stats.size(); ++q)
+        if (!strcmp(c->prof_stats[q].name, name)) cls = (int)q;
+    if (cls < 0) {
+        fmmbem_kstat s{};
+        std::snprintf(s.name, sizeof(s.name), "%s", name);
+        c->prof_stats.push_back(s);
+        cls = (int)c->prof_stats.size() - 1;
+    }
+    c->prof_pend.push_back({cls, a, a + 1, flops, bytes});
+}
+static double rot_flops(int p) {  // Delta^T and Delta applied to one complex column set of degree < p
+    double s = 0;
+    for (int n = 0; n < p; ++n) s += 2.0 * 4.0 * (2.0 * n + 1) * (2.0 * n + 1);
+    return s;
+}
+static double coax_flops(int ps, int pt) {
+    double s = 0;
+    int pm = std::min(ps, pt);
+    for (int m = -(pm - 1); m <= pm - 1; ++m) s += 8.0 * (pt - std::abs(m)) * (ps - std::abs(m));
+    return s;
+}
+
 // ------------------------------------------------------------------ the FMM pass
 // Staged translation of a batch of jobs (grouped by target) from `src` (psrc) into `dst` (ptgt).
-static void translate(fmmbem_ctx *c, int64_t njob, int psrc, int ptgt, int PT, const double2 *src,
+static void translate(fmmbem_ctx *c, const char *tag, int64_t njob, int psrc, int ptgt, int PT, const double2 *src,
                       const int32_t *src_idx, const int16_t *dir, const double2 *tables, const int8_t *tau,
                       double2 *dst, const std::vector<int32_t> &gstart_h, const int32_t *gstart_d, int64_t ngroups,
                       int accumulate) {
@@ -310,7 +365,8 @@ static void translate(fmmbem_ctx *c, int64_t njob, int psrc, int ptgt, int PT, c
     const double *D = (double *)c->buf.find("delta"), *DT = (double *)c->buf.find("deltaT");
     const double2 *phA = (double2 *)c->buf.find("phA"), *phB = (double2 *)c->buf.find("phB");
     const int PH = c->delta_p;
-    // chunk by groups so that two job buffers stay under ~8 GiB
+    const std::string t(tag);
+    // chunk by groups so that the two job buffers stay bounded (2 x 8 GiB)
     const int64_t max_jobs = std::max<int64_t>(1, (int64_t(1) << 29) / ((int64_t)P * P));
     int64_t g0 = 0;
     while (g0 < ngroups) {
@@ -318,30 +374,31 @@ static void translate(fmmbem_ctx *c, int64_t njob, int psrc, int ptgt, int PT, c
         const int64_t j0 = gstart_h[g0];
         while (g1 < ngroups && (gstart_h[g1 + 1] - j0 <= max_jobs || g1 == g0)) ++g1;
         const int64_t nj = gstart_h[g1] - j0;
+        double2 *W = dget<double2>(c->scratch, "W1", (size_t)std::max<int64_t>(nj, 1) * P * P);
         if (nj > 0) {
-            double2 *W = dget<double2>(c->scratch, "W1", (size_t)nj * P * P);
             double2 *W2 = dget<double2>(c->scratch, "W2", (size_t)nj * P * P);
             size_t sh = sizeof(double2) * 4 * P;
+            const double vb = 16.0 * nj * (double)P * P * 2;  // read + write of the job vectors
+            int e = prof_begin(c);
             k_rot_fwd<<<(unsigned)nj, 256, sh, st>>>(nj, psrc, P, src, src_idx + j0, dir + j0, phA, phB, PH, D, DT, W);
             LAUNCH_OK();
+            prof_end(c, e, (t + "_rot_fwd").c_str(), nj * rot_flops(psrc), vb);
+            e = prof_begin(c);
             k_coax_apply<<<(unsigned)nj, 256, 0, st>>>(nj, psrc, ptgt, P, PT, W, tables, tau ? tau + j0 : nullptr, W2);
             LAUNCH_OK();
+            prof_end(c, e, (t + "_coax").c_str(), nj * coax_flops(psrc, ptgt), vb);
+            e = prof_begin(c);
             k_rot_back<<<(unsigned)nj, 256, sh, st>>>(nj, ptgt, P, W2, dir + j0, phA, phB, PH, D, DT, W);
             LAUNCH_OK();
+            prof_end(c, e, (t + "_rot_back").c_str(), nj * rot_flops(ptgt), vb);
         }
-        // group starts relative to j0
-        std::vector<int32_t> gs(g1 - g0 + 1);
-        for (int64_t g = g0; g <= g1; ++g) gs[g - g0] = gstart_h[g] - (int32_t)j0;
-        int32_t *dgs = upload(c->scratch, "gs_chunk", gs, st);
-        double2 *Wr = (double2 *)c->scratch.find("W1");
-        if (!Wr) Wr = dget<double2>(c->scratch, "W1", 16);
-        k_reduce_jobs<<<(unsigned)(g1 - g0), 256, 0, st>>>(g1 - g0, ptgt, P, dgs, nullptr, Wr,
+        int e = prof_begin(c);
+        k_reduce_jobs<<<(unsigned)(g1 - g0), 256, 0, st>>>(g1 - g0, ptgt, P, gstart_d + g0, (int32_t)j0, W,
                                                            dst + g0 * (int64_t)ptgt * ptgt, accumulate);
         LAUNCH_OK();
-        HIP_OK(hipStreamSynchronize(st));  // gs_chunk / W reuse
+        prof_end(c, e, (t + "_reduce").c_str(), 2.0 * nj * ptgt * ptgt, 16.0 * (nj + 2.0 * (g1 - g0)) * ptgt * ptgt);
         g0 = g1;
     }
-    (void)gstart_d;
 }
 
 // y (caller order) = half * x + L[sigma] + M[mu] at the centroids; sigma/mu in sorted order.
@@ -356,10 +413,17 @@ static void fmm_pass(fmmbem_ctx *c, const double2 *sigma, const double2 *mu, con
     const double4 *ec = (double4 *)c->buf.find("ec"), *en = (double4 *)c->buf.find("en");
     double2 *ynear = dget<double2>(c->scratch, "ynear", n);
     HIP_OK(hipEventRecord(c->ev[1], st));
+    int pe = prof_begin(c);
     k_p2p<<<nleaf, 64, 0, st>>>(nleaf, I32("leaf_start"), I32("nbr_start"), I32("nbr_list"), exact_far ? 1 : 0, ec, en,
                                 sigma, mu, c->k, c->rc * c->rc, I32("near_start"), I32("near_col"),
                                 (double2 *)c->buf.find("near_L"), (double2 *)c->buf.find("near_M"), ynear);
     LAUNCH_OK();
+    {
+        // one-point pairs: ~40 flops each (sincos counted as 20); bytes: element data, densities,
+        // near table and output, each read once
+        double pairs = exact_far ? (double)n * n : (double)c->p2p_pairs;
+        prof_end(c, pe, "p2p", 40.0 * pairs + 16.0 * c->near_nnz, 80.0 * n + 32.0 * n + 16.0 * n + 40.0 * c->near_nnz);
+    }
     HIP_OK(hipEventRecord(c->ev[2], st));
     if (!exact_far) {
         LevelDev &LL = c->lev[L];
@@ -369,14 +433,16 @@ static void fmm_pass(fmmbem_ctx *c, const double2 *sigma, const double2 *mu, con
         if (per > 60000) throw FmmError(FMMBEM_EINVAL, "leaf truncation number too large for P2M staging");
         int CH = std::max(1, std::min(32, 60000 / per));
         size_t sh = (size_t)CH * per;
+        pe = prof_begin(c);
         k_p2m<<<nleaf, 256, sh, st>>>(nleaf, p, CH, I32("leaf_start"), LL.center, ec, en, sigma, mu, c->k, LL.M);
         LAUNCH_OK();
+        prof_end(c, pe, "p2m", (double)n * p * p * 2 * 8.0, 112.0 * n + 16.0 * nleaf * p * p);
         HIP_OK(hipEventRecord(c->ev[3], st));
         // M2M up
         for (int l = L - 1; l >= 2; --l) {
             LevelDev &P_ = c->lev[l], &C_ = c->lev[l + 1];
             std::string s = "L" + std::to_string(l + 1) + "_";
-            translate(c, C_.nbox, C_.p, P_.p, std::max(P_.p, C_.p), C_.M, (int32_t *)c->buf.find(s + "iota"),
+            translate(c, "m2m", C_.nbox, C_.p, P_.p, std::max(P_.p, C_.p), C_.M, (int32_t *)c->buf.find(s + "iota"),
                       (int16_t *)c->buf.find(s + "dir_up"), P_.coax_up, nullptr, P_.M, T.lv[l].child_start,
                       P_.child_start, P_.nbox, 0);
         }
@@ -387,12 +453,12 @@ static void fmm_pass(fmmbem_ctx *c, const double2 *sigma, const double2 *mu, con
         (void)t_l2l;
         for (int l = 2; l <= L; ++l) {
             LevelDev &D = c->lev[l];
-            translate(c, D.njob_m2l, D.p, D.p, D.p, D.M, D.m2l_src, D.m2l_dir, D.coax_m2l, D.m2l_tau, D.L,
+            translate(c, "m2l", D.njob_m2l, D.p, D.p, D.p, D.M, D.m2l_src, D.m2l_dir, D.coax_m2l, D.m2l_tau, D.L,
                       T.lv[l].m2l_start, D.m2l_start, D.nbox, 0);
             if (l >= 3) {
                 LevelDev &P_ = c->lev[l - 1];
                 std::string s = "L" + std::to_string(l) + "_";
-                translate(c, D.nbox, P_.p, D.p, std::max(P_.p, D.p), P_.L, D.parent,
+                translate(c, "l2l", D.nbox, P_.p, D.p, std::max(P_.p, D.p), P_.L, D.parent,
                           (int16_t *)c->buf.find(s + "dir_dn"), P_.coax_up, nullptr, D.L, c->iota_h[l],
                           (int32_t *)c->buf.find(s + "iota"), D.nbox, 1);
             }
@@ -403,9 +469,11 @@ static void fmm_pass(fmmbem_ctx *c, const double2 *sigma, const double2 *mu, con
     }
     HIP_OK(hipEventRecord(c->ev[6], st));
     LevelDev &LL = c->lev[L];
+    pe = prof_begin(c);
     k_l2p<<<nleaf, 64, (size_t)64 * (LL.p + 2) * sizeof(double), st>>>(
         nleaf, LL.p, I32("leaf_start"), LL.center, ec, LL.L, c->k, ynear, half, I32("perm"), x, y, exact_far ? 0 : 1);
     LAUNCH_OK();
+    prof_end(c, pe, "l2p", (double)n * LL.p * LL.p * 8.0, 32.0 * n + 16.0 * n * 3 + 16.0 * nleaf * LL.p * LL.p);
     HIP_OK(hipEventRecord(c->ev[7], st));
 }
 
@@ -527,6 +595,7 @@ int fmmbem_destroy(fmmbem_ctx *ctx) {
     ctx->scratch.release_all();
     for (auto &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
+    for (auto &e : ctx->prof_ev) (void)hipEventDestroy(e);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     return FMMBEM_OK;
@@ -671,6 +740,28 @@ int fmmbem_matvec_dev(fmmbem_ctx *ctx, int32_t nrhs, const void *x, void *y, int
     for (int r = 0; r < nrhs; ++r)
         matvec_dev(ctx, (const double2 *)x + r * n, (double2 *)y + r * n, false);
     HIP_OK(hipStreamWaitEvent(caller, ctx->ev[8], 0));
+    return FMMBEM_OK;
+    GUARD_END
+}
+
+int fmmbem_profile(fmmbem_ctx *ctx, int enable) {
+    if (!ctx) return FMMBEM_EINVAL;
+    GUARD_BEGIN
+    HIP_OK(hipSetDevice(ctx->device));
+    prof_flush(ctx);
+    ctx->prof_stats.clear();
+    ctx->prof_on = enable != 0;
+    return FMMBEM_OK;
+    GUARD_END
+}
+
+int fmmbem_kernel_stats(fmmbem_ctx *ctx, int max, fmmbem_kstat *out, int *count) {
+    if (!ctx || !count) return FMMBEM_EINVAL;
+    GUARD_BEGIN
+    HIP_OK(hipSetDevice(ctx->device));
+    prof_flush(ctx);
+    *count = (int)ctx->prof_stats.size();
+    for (int i = 0; i < max && i < *count; ++i) out[i] = ctx->prof_stats[i];
     return FMMBEM_OK;
     GUARD_END
 }

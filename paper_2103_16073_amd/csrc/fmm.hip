@@ -483,12 +483,12 @@ __global__ void __launch_bounds__(256) k_rot_back(int64_t njob, int ptgt, int P,
 }
 
 // Stage 4: dst[t] (+)= sum of the job results of target t (jobs grouped by target).
-__global__ void k_reduce_jobs(int64_t ntgt, int ptgt, int P, const int32_t *start, const int32_t *tgt_of_group,
-                              const double2 *W, double2 *dst, int accumulate) {
+__global__ void k_reduce_jobs(int64_t ntgt, int ptgt, int P, const int32_t *start, int32_t job0, const double2 *W,
+                              double2 *dst, int accumulate) {
     const int64_t g = blockIdx.x;
     if (g >= ntgt) return;
-    const int j0 = start[g], j1 = start[g + 1];
-    const int64_t t = tgt_of_group ? tgt_of_group[g] : g;
+    const int j0 = start[g] - job0, j1 = start[g + 1] - job0;
+    const int64_t t = g;
     const int nc = ptgt * ptgt;
     for (int c = threadIdx.x; c < nc; c += blockDim.x) {
         double2 s = accumulate ? dst[t * nc + c] : cmk(0, 0);

@@ -163,4 +163,14 @@ struct fmmbem_ctx {
     bool precond_ready_nb = false, precond_ready_diag = false;
     fmm::Timings last;
     double t_setup_last = 0.0;
+    // kernel profiling (fmmbem_profile)
+    bool prof_on = false;
+    std::vector<hipEvent_t> prof_ev;
+    int prof_used = 0;
+    struct ProfRec {
+        int cls, a, b;
+        double flops, bytes;
+    };
+    std::vector<ProfRec> prof_pend;
+    std::vector<fmmbem_kstat> prof_stats;
 };

@@ -56,6 +56,11 @@ class Info(ctypes.Structure):
                 ("flops_p2m_l2p", ctypes.c_double), ("bytes_p2p", ctypes.c_double)]
 
 
+class KStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("ms", ctypes.c_double),
+                ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
 EXPORTS = {
     "fmmbem_default_options": (None, [ctypes.POINTER(Options)]),
     "fmmbem_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.POINTER(Options)]),
@@ -79,6 +84,8 @@ EXPORTS = {
     "fmmbem_coaxial_table": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]),
     "fmmbem_rotation_table": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p]),
     "fmmbem_last_timings": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "fmmbem_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "fmmbem_kernel_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)]),
 }
 
 _lib = None
@@ -229,6 +236,16 @@ class Context:
         M = np.empty(z, np.complex128)
         self._check(lib().fmmbem_near_entries(self.h, ctypes.byref(nnz), _ptr(r), _ptr(c), _ptr(L), _ptr(M)))
         return r, c, L, M
+
+    def fmmbem_profile(self, enable=True):
+        self._check(lib().fmmbem_profile(self.h, int(bool(enable))))
+
+    def fmmbem_kernel_stats(self):
+        arr = (KStat * 128)()
+        cnt = ctypes.c_int()
+        self._check(lib().fmmbem_kernel_stats(self.h, 128, arr, ctypes.byref(cnt)))
+        return [dict(name=arr[i].name.decode(), launches=arr[i].launches, ms=arr[i].ms, flops=arr[i].flops,
+                     bytes=arr[i].bytes) for i in range(cnt.value)]
 
     def fmmbem_last_timings(self):
         t = np.zeros(8)
