@@ -86,6 +86,8 @@ typedef struct {
     double ktau_switch;  /* coaxial coefficients: original recursion if k*tau < ktau_switch,
                             stabilised recursion otherwise (Section 3.3.1); default 1.0 */
     int max_depth;       /* cap on the octree depth; default 12 */
+    int lds_budget;      /* LDS bytes per workgroup for translation tiles (0 = 64 KiB); larger tiles
+                            share tables more but leave fewer workgroups per compute unit */
 } fmmbem_options;
 
 void fmmbem_default_options(fmmbem_options *opt);

@@ -24,12 +24,6 @@ __global__ void k_p2p(int, const int32_t *, const int32_t *, const int32_t *, in
                       const double2 *, const double2 *, double2 *);
 __global__ void k_p2m(int, int, int, const int32_t *, const double4 *, const double4 *, const double4 *,
                       const double2 *, const double2 *, double, double2 *);
-__global__ void k_rot_fwd(int64_t, int, int, const double2 *, const int32_t *, const int16_t *, const double2 *,
-                          const double2 *, int, const double *, const double *, double2 *);
-__global__ void k_coax_apply(int64_t, int, int, int, int, const double2 *, const double2 *, const int8_t *, double2 *);
-__global__ void k_rot_back(int64_t, int, int, const double2 *, const int16_t *, const double2 *, const double2 *, int,
-                           const double *, const double *, double2 *);
-__global__ void k_reduce_jobs(int64_t, int, int, const int32_t *, int32_t, const double2 *, double2 *, int);
 __global__ void k_l2p(int, int, const int32_t *, const double4 *, const double4 *, const double2 *, double,
                       const double2 *, double, const int32_t *, const double2 *, double2 *, int);
 __global__ void k_field(int64_t, const double *, const double4 *, const double4 *, const double *, const double2 *,
@@ -196,6 +190,96 @@ static void direction_phases(int PH, std::vector<double2> &A, std::vector<double
     }
 }
 
+struct JobH {
+    int32_t src, tgt;
+    int16_t dir;
+    int tab;
+};
+
+static void make_batch(fmmbem_ctx *c, const std::string &name, std::vector<JobH> jobs, int psrc, int ptgt, int PT,
+                       TransBatch &b) {
+    hipStream_t st = c->stream;
+    b = TransBatch();
+    b.psrc = psrc;
+    b.ptgt = ptgt;
+    b.PT = PT;
+    b.P = std::max(psrc, ptgt);
+    b.nreal = (int64_t)jobs.size();
+    size_t budget = c->opt.lds_budget > 0 ? (size_t)c->opt.lds_budget : (size_t)65536;
+    budget = std::min(budget, c->lds_max) - 1024;  // headroom for the kernels' static LDS
+    const int jf = trans_pick_jt(1, b.P, budget);
+    b.fused = jf >= 2;
+    b.JT = std::max(1, b.fused ? jf : trans_pick_jt(0, b.P, budget));
+    std::stable_sort(jobs.begin(), jobs.end(), [](const JobH &x, const JobH &y) {
+        return x.tab != y.tab ? x.tab < y.tab : x.tgt < y.tgt;
+    });
+    std::vector<int32_t> s, t, tt;
+    std::vector<int16_t> d;
+    size_t q = 0;
+    while (q < jobs.size()) {
+        size_t e = q;
+        while (e < jobs.size() && jobs[e].tab == jobs[q].tab) ++e;
+        for (size_t r = q; r < e; ++r) {
+            s.push_back(jobs[r].src);
+            t.push_back(jobs[r].tgt);
+            d.push_back(jobs[r].dir);
+        }
+        while (s.size() % b.JT) {  // pad the class to whole tiles
+            s.push_back(jobs[q].src);
+            t.push_back(-1);
+            d.push_back(jobs[q].dir);
+        }
+        q = e;
+    }
+    // table of every tile, in the sorted and padded order
+    {
+        size_t pos = 0;
+        q = 0;
+        while (q < jobs.size()) {
+            size_t e = q;
+            while (e < jobs.size() && jobs[e].tab == jobs[q].tab) ++e;
+            size_t cnt = e - q, tiles = (cnt + b.JT - 1) / b.JT;
+            for (size_t k = 0; k < tiles; ++k) tt.push_back(jobs[q].tab);
+            pos += tiles * b.JT;
+            q = e;
+        }
+        (void)pos;
+    }
+    b.njob = (int64_t)s.size();
+    b.src = upload(c->buf, name + "_src", s, st);
+    b.tgt = upload(c->buf, name + "_tgt", t, st);
+    b.dir = upload(c->buf, name + "_dir", d, st);
+    b.tile_tab = upload(c->buf, name + "_tab", tt, st);
+}
+
+static void build_batches(fmmbem_ctx *c) {
+    TreeHost &T = c->tree;
+    const int L = T.depth;
+    for (int l = 2; l <= L; ++l) {
+        LevelHost &H = T.lv[l];
+        LevelDev &D = c->lev[l];
+        std::string s = "L" + std::to_string(l) + "_";
+        std::vector<JobH> jobs;
+        for (int64_t b = 0; b < D.nbox; ++b)
+            for (int q = H.m2l_start[b]; q < H.m2l_start[b + 1]; ++q)
+                jobs.push_back({H.m2l_src[q], (int32_t)b, H.m2l_dir[q], H.m2l_tau_of_dir[H.m2l_dir[q]]});
+        make_batch(c, s + "m2l", jobs, D.p, D.p, D.p, D.m2l);
+        if (l < L) {
+            LevelHost &Hc = T.lv[l + 1];
+            LevelDev &C = c->lev[l + 1];
+            const int PT = std::max(D.p, C.p);
+            std::vector<JobH> up, dn;
+            for (int64_t ch = 0; ch < C.nbox; ++ch) {
+                up.push_back({(int32_t)ch, Hc.parent[ch], (int16_t)(343 + Hc.octant[ch]), 0});
+                dn.push_back({Hc.parent[ch], (int32_t)ch, (int16_t)(351 + Hc.octant[ch]), 0});
+            }
+            make_batch(c, s + "up", up, C.p, D.p, PT, D.up);
+            make_batch(c, s + "down", dn, D.p, C.p, PT, D.down);
+        }
+    }
+    HIP_OK(hipStreamSynchronize(c->stream));
+}
+
 static void setup_k(fmmbem_ctx *c) {
     TreeHost &T = c->tree;
     const int L = T.depth;
@@ -240,6 +324,7 @@ static void setup_k(fmmbem_ctx *c) {
         D.L = dget<double2>(c->buf, s + "L", (size_t)D.nbox * p * p);
     }
     build_coax_tables(jobs, c->scratch, st);
+    build_batches(c);
     // near-field table
     const int64_t n = c->nt;
     const int nleaf = (int)T.leaf_start.size() - 1;
@@ -355,50 +440,21 @@ static double coax_flops(int ps, int pt) {
 
 // ------------------------------------------------------------------ the FMM pass
 // Staged translation of a batch of jobs (grouped by target) from `src` (psrc) into `dst` (ptgt).
-static void translate(fmmbem_ctx *c, const char *tag, int64_t njob, int psrc, int ptgt, int PT, const double2 *src,
-                      const int32_t *src_idx, const int16_t *dir, const double2 *tables, const int8_t *tau,
-                      double2 *dst, const std::vector<int32_t> &gstart_h, const int32_t *gstart_d, int64_t ngroups,
-                      int accumulate) {
-    if (ngroups == 0) return;
+static void run_batch(fmmbem_ctx *c, const char *tag, const TransBatch &b, const double2 *src, double2 *dst,
+                      const double2 *tables) {
+    if (b.njob == 0) return;
     hipStream_t st = c->stream;
-    const int P = std::max(psrc, ptgt);
-    const double *D = (double *)c->buf.find("delta"), *DT = (double *)c->buf.find("deltaT");
-    const double2 *phA = (double2 *)c->buf.find("phA"), *phB = (double2 *)c->buf.find("phB");
-    const int PH = c->delta_p;
-    const std::string t(tag);
-    // chunk by groups so that the two job buffers stay bounded (2 x 8 GiB)
-    const int64_t max_jobs = std::max<int64_t>(1, (int64_t(1) << 29) / ((int64_t)P * P));
-    int64_t g0 = 0;
-    while (g0 < ngroups) {
-        int64_t g1 = g0;
-        const int64_t j0 = gstart_h[g0];
-        while (g1 < ngroups && (gstart_h[g1 + 1] - j0 <= max_jobs || g1 == g0)) ++g1;
-        const int64_t nj = gstart_h[g1] - j0;
-        double2 *W = dget<double2>(c->scratch, "W1", (size_t)std::max<int64_t>(nj, 1) * P * P);
-        if (nj > 0) {
-            double2 *W2 = dget<double2>(c->scratch, "W2", (size_t)nj * P * P);
-            size_t sh = sizeof(double2) * 4 * P;
-            const double vb = 16.0 * nj * (double)P * P * 2;  // read + write of the job vectors
-            int e = prof_begin(c);
-            k_rot_fwd<<<(unsigned)nj, 256, sh, st>>>(nj, psrc, P, src, src_idx + j0, dir + j0, phA, phB, PH, D, DT, W);
-            LAUNCH_OK();
-            prof_end(c, e, (t + "_rot_fwd").c_str(), nj * rot_flops(psrc), vb);
-            e = prof_begin(c);
-            k_coax_apply<<<(unsigned)nj, 256, 0, st>>>(nj, psrc, ptgt, P, PT, W, tables, tau ? tau + j0 : nullptr, W2);
-            LAUNCH_OK();
-            prof_end(c, e, (t + "_coax").c_str(), nj * coax_flops(psrc, ptgt), vb);
-            e = prof_begin(c);
-            k_rot_back<<<(unsigned)nj, 256, sh, st>>>(nj, ptgt, P, W2, dir + j0, phA, phB, PH, D, DT, W);
-            LAUNCH_OK();
-            prof_end(c, e, (t + "_rot_back").c_str(), nj * rot_flops(ptgt), vb);
-        }
-        int e = prof_begin(c);
-        k_reduce_jobs<<<(unsigned)(g1 - g0), 256, 0, st>>>(g1 - g0, ptgt, P, gstart_d + g0, (int32_t)j0, W,
-                                                           dst + g0 * (int64_t)ptgt * ptgt, accumulate);
-        LAUNCH_OK();
-        prof_end(c, e, (t + "_reduce").c_str(), 2.0 * nj * ptgt * ptgt, 16.0 * (nj + 2.0 * (g1 - g0)) * ptgt * ptgt);
-        g0 = g1;
+    double2 *W1 = nullptr, *W2 = nullptr;
+    if (!b.fused) {
+        W1 = dget<double2>(c->scratch, "W1", (size_t)b.njob * b.P * b.P);
+        W2 = dget<double2>(c->scratch, "W2", (size_t)b.njob * b.P * b.P);
     }
+    int e = prof_begin(c);
+    trans_launch(b, src, dst, tables, (double2 *)c->buf.find("phA"), (double2 *)c->buf.find("phB"), c->delta_p,
+                 (double *)c->buf.find("delta"), (double *)c->buf.find("deltaT"), W1, W2, st);
+    double fl = (double)b.nreal * (rot_flops(b.psrc) + rot_flops(b.ptgt) + coax_flops(b.psrc, b.ptgt));
+    double by = (double)b.nreal * 16.0 * (b.psrc * b.psrc + 2.0 * b.ptgt * b.ptgt);
+    prof_end(c, e, (std::string(tag) + (b.fused ? "_fused" : "_staged")).c_str(), fl, by);
 }
 
 // y (caller order) = half * x + L[sigma] + M[mu] at the centroids; sigma/mu in sorted order.
@@ -441,26 +497,18 @@ static void fmm_pass(fmmbem_ctx *c, const double2 *sigma, const double2 *mu, con
         // M2M up
         for (int l = L - 1; l >= 2; --l) {
             LevelDev &P_ = c->lev[l], &C_ = c->lev[l + 1];
-            std::string s = "L" + std::to_string(l + 1) + "_";
-            translate(c, "m2m", C_.nbox, C_.p, P_.p, std::max(P_.p, C_.p), C_.M, (int32_t *)c->buf.find(s + "iota"),
-                      (int16_t *)c->buf.find(s + "dir_up"), P_.coax_up, nullptr, P_.M, T.lv[l].child_start,
-                      P_.child_start, P_.nbox, 0);
+            HIP_OK(hipMemsetAsync(P_.M, 0, sizeof(double2) * P_.nbox * P_.p * P_.p, st));
+            run_batch(c, "m2m", P_.up, C_.M, P_.M, P_.coax_up);
         }
         HIP_OK(hipEventRecord(c->ev[4], st));
         // M2L and L2L down
-        float t_m2l = 0, t_l2l = 0;
-        (void)t_m2l;
-        (void)t_l2l;
         for (int l = 2; l <= L; ++l) {
             LevelDev &D = c->lev[l];
-            translate(c, "m2l", D.njob_m2l, D.p, D.p, D.p, D.M, D.m2l_src, D.m2l_dir, D.coax_m2l, D.m2l_tau, D.L,
-                      T.lv[l].m2l_start, D.m2l_start, D.nbox, 0);
+            HIP_OK(hipMemsetAsync(D.L, 0, sizeof(double2) * D.nbox * D.p * D.p, st));
+            run_batch(c, "m2l", D.m2l, D.M, D.L, D.coax_m2l);
             if (l >= 3) {
                 LevelDev &P_ = c->lev[l - 1];
-                std::string s = "L" + std::to_string(l) + "_";
-                translate(c, "l2l", D.nbox, P_.p, D.p, std::max(P_.p, D.p), P_.L, D.parent,
-                          (int16_t *)c->buf.find(s + "dir_dn"), P_.coax_up, nullptr, D.L, c->iota_h[l],
-                          (int32_t *)c->buf.find(s + "iota"), D.nbox, 1);
+                run_batch(c, "l2l", P_.down, P_.L, D.L, P_.coax_up);
             }
         }
         HIP_OK(hipEventRecord(c->ev[5], st));
@@ -552,6 +600,7 @@ void fmmbem_default_options(fmmbem_options *o) {
     o->digits = 7.0;
     o->ktau_switch = 1.0;
     o->max_depth = 12;
+    o->lds_budget = 0;
 }
 
 void fmmbem_default_solve_opts(fmmbem_solve_opts *o) {
@@ -578,6 +627,19 @@ int fmmbem_create(fmmbem_ctx **out, int hip_device, const fmmbem_options *opt) {
         else fmmbem_default_options(&ctx->opt);
         HIP_OK(hipSetDevice(hip_device));
         HIP_OK(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+        {
+            hipDeviceProp_t prop;
+            HIP_OK(hipGetDeviceProperties(&prop, hip_device));
+            size_t lds = prop.sharedMemPerBlockOptin > 0 ? prop.sharedMemPerBlockOptin : prop.sharedMemPerBlock;
+            ctx->lds_max = std::max<size_t>(lds, 65536);
+            if (ctx->lds_max > 65536) {
+                try {
+                    trans_configure_lds(ctx->lds_max);
+                } catch (const FmmError &) {
+                    ctx->lds_max = 65536;
+                }
+            }
+        }
         for (auto &e : ctx->ev) HIP_OK(hipEventCreate(&e));
         *out = ctx;
         return FMMBEM_OK;

@@ -381,122 +381,6 @@ __global__ void __launch_bounds__(256) k_p2m(int nleaf, int p, int CH, const int
     }
 }
 
-// ------------------------------------------------------------------ staged translations
-// Stage 1: rotate the source coefficients so that t points along +z.  One workgroup per job.
-__global__ void __launch_bounds__(256) k_rot_fwd(int64_t njob, int psrc, int P, const double2 *src, const int32_t *src_idx,
-                                                 const int16_t *dir, const double2 *phA, const double2 *phB, int PH,
-                                                 const double *D, const double *DT, double2 *W) {
-    const int64_t job = blockIdx.x;
-    if (job >= njob) return;
-    extern __shared__ double2 rot_lds[];
-    double2 *va = rot_lds, *vb = rot_lds + 2 * P;
-    const double2 *c = src + (int64_t)src_idx[job] * psrc * psrc;
-    const int d = dir[job];
-    const double2 *A = phA + (int64_t)d * (2 * PH + 1) + PH;
-    const double2 *Bp = phB + (int64_t)d * (2 * PH + 1) + PH;
-    double2 *out = W + job * (int64_t)P * P;
-    for (int n = 0; n < psrc; ++n) {
-        const int w = 2 * n + 1;
-        const double *Dn = D + rot_block_off(n), *DTn = DT + rot_block_off(n);
-        for (int m = -n + (int)threadIdx.x; m <= n; m += blockDim.x) va[m + n] = cmul(A[m], c[cidx(n, m)]);
-        __syncthreads();
-        // vb = Delta^T va: vb[m'] = sum_m D[m][m'] va[m]
-        for (int mp = (int)threadIdx.x; mp < w; mp += blockDim.x) {
-            double2 s = cmk(0, 0);
-            for (int m = 0; m < w; ++m) s = cadd(s, cscale(va[m], Dn[(int64_t)m * w + mp]));
-            vb[mp] = cmul(Bp[mp - n], s);
-        }
-        __syncthreads();
-        // va = Delta vb: va[m] = sum_m' DT[m'][m] vb[m']
-        for (int m = (int)threadIdx.x; m < w; m += blockDim.x) {
-            double2 s = cmk(0, 0);
-            for (int mp = 0; mp < w; ++mp) s = cadd(s, cscale(vb[mp], DTn[(int64_t)mp * w + m]));
-            out[cidx(n, m - n)] = s;
-        }
-        __syncthreads();
-    }
-}
-
-// Stage 2: coaxial translation, block-diagonal in m:
-//   out_{n'}^m = sum_n (E|F)^{|m|}_{n'n} in_n^m = sum_n (-1)^{n+n'} (E|F)^{|m|}_{n n'} in_n^m
-// (step-4 symmetry lets consecutive threads n' read consecutive table entries).
-__global__ void __launch_bounds__(256) k_coax_apply(int64_t njob, int psrc, int ptgt, int P, int PT, const double2 *W,
-                                                    const double2 *tables, const int8_t *tau_idx, double2 *W2) {
-    const int64_t job = blockIdx.x;
-    if (job >= njob) return;
-    __shared__ double2 col[1024 + 8];
-    const double2 *in = W + job * (int64_t)P * P;
-    double2 *out = W2 + job * (int64_t)P * P;
-    const double2 *T = tables + (tau_idx ? (int64_t)tau_idx[job] : 0) * coax_table_size(PT);
-    const int pm = min(psrc, ptgt);
-    for (int c = threadIdx.x; c < ptgt * ptgt; c += blockDim.x) out[c] = cmk(0, 0);
-    __syncthreads();
-    for (int m = -(pm - 1); m <= pm - 1; ++m) {
-        const int am = m < 0 ? -m : m;
-        const int B = PT - am;
-        const double2 *Tm = T + coax_block_off(PT, am);
-        for (int n = am + (int)threadIdx.x; n < psrc; n += blockDim.x) col[n] = in[cidx(n, m)];
-        __syncthreads();
-        for (int nn = am + (int)threadIdx.x; nn < ptgt; nn += blockDim.x) {
-            double2 s = cmk(0, 0);
-            for (int n = am; n < psrc; ++n) {
-                double2 t = Tm[(int64_t)(n - am) * B + (nn - am)];
-                s = ((n + nn) & 1) ? csub(s, cmul(t, col[n])) : cadd(s, cmul(t, col[n]));
-            }
-            out[cidx(nn, m)] = s;
-        }
-        __syncthreads();
-    }
-}
-
-// Stage 3: rotate back (Delta^T, e^{-imb}, Delta, i^m e^{-ima}); result per job in W.
-__global__ void __launch_bounds__(256) k_rot_back(int64_t njob, int ptgt, int P, const double2 *W2, const int16_t *dir,
-                                                  const double2 *phA, const double2 *phB, int PH, const double *D,
-                                                  const double *DT, double2 *W) {
-    const int64_t job = blockIdx.x;
-    if (job >= njob) return;
-    extern __shared__ double2 rot_lds[];
-    double2 *va = rot_lds, *vb = rot_lds + 2 * P;
-    const double2 *c = W2 + job * (int64_t)P * P;
-    const int d = dir[job];
-    const double2 *A = phA + (int64_t)d * (2 * PH + 1) + PH;
-    const double2 *Bp = phB + (int64_t)d * (2 * PH + 1) + PH;
-    double2 *out = W + job * (int64_t)P * P;
-    for (int n = 0; n < ptgt; ++n) {
-        const int w = 2 * n + 1;
-        const double *Dn = D + rot_block_off(n), *DTn = DT + rot_block_off(n);
-        for (int m = -n + (int)threadIdx.x; m <= n; m += blockDim.x) va[m + n] = c[cidx(n, m)];
-        __syncthreads();
-        for (int mp = (int)threadIdx.x; mp < w; mp += blockDim.x) {
-            double2 s = cmk(0, 0);
-            for (int m = 0; m < w; ++m) s = cadd(s, cscale(va[m], Dn[(int64_t)m * w + mp]));
-            vb[mp] = cmulc(s, Bp[mp - n]);  // e^{-i m' b}
-        }
-        __syncthreads();
-        for (int m = (int)threadIdx.x; m < w; m += blockDim.x) {
-            double2 s = cmk(0, 0);
-            for (int mp = 0; mp < w; ++mp) s = cadd(s, cscale(vb[mp], DTn[(int64_t)mp * w + m]));
-            out[cidx(n, m - n)] = cmulc(s, A[m - n]);  // i^m e^{-i m a} = conj(A_m)
-        }
-        __syncthreads();
-    }
-}
-
-// Stage 4: dst[t] (+)= sum of the job results of target t (jobs grouped by target).
-__global__ void k_reduce_jobs(int64_t ntgt, int ptgt, int P, const int32_t *start, int32_t job0, const double2 *W,
-                              double2 *dst, int accumulate) {
-    const int64_t g = blockIdx.x;
-    if (g >= ntgt) return;
-    const int j0 = start[g] - job0, j1 = start[g + 1] - job0;
-    const int64_t t = g;
-    const int nc = ptgt * ptgt;
-    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
-        double2 s = accumulate ? dst[t * nc + c] : cmk(0, 0);
-        for (int j = j0; j < j1; ++j) s = cadd(s, W[(int64_t)j * P * P + c]);
-        dst[t * nc + c] = s;
-    }
-}
-
 // ------------------------------------------------------------------ L2P + combine
 // y[perm[i]] = half * x[perm[i]] + y_near[i] + sum_{n,m} D_n^m R_n^m(c_i - C).
 __global__ void __launch_bounds__(64) k_l2p(int nleaf, int p, const int32_t *leaf_start, const double4 *center,

@@ -101,6 +101,23 @@ void box_center(const TreeHost &T, int l, uint64_t code, double *c);
 void build_tree(const double *centroids, int64_t n, const double *vlo, const double *vhi, double rc,
                 int leaf_max, int max_depth, TreeHost &T);
 
+// ---------------------------------------------------------------- translation batches
+// One set of translation jobs (a level's M2L, M2M or L2L), sorted by coaxial table and padded
+// so that every tile of JT jobs shares one table (padding jobs have tgt = -1).
+struct TransBatch {
+    int64_t njob = 0, nreal = 0;
+    int JT = 1, psrc = 0, ptgt = 0, P = 0, PT = 0;
+    bool fused = true;
+    int32_t *src = nullptr, *tgt = nullptr, *tile_tab = nullptr;
+    int16_t *dir = nullptr;
+};
+size_t trans_lds_bytes(int fused, int JT, int P);
+int trans_pick_jt(int fused, int P, size_t lds_max);
+void trans_configure_lds(size_t lds_max);
+void trans_launch(const TransBatch &b, const double2 *src, double2 *dst, const double2 *tables, const double2 *phA,
+                  const double2 *phB, int PH, const double *D, const double *DT, double2 *W1, double2 *W2,
+                  hipStream_t st);
+
 // ---------------------------------------------------------------- per-level device data
 struct LevelDev {
     int p = 0;
@@ -120,6 +137,7 @@ struct LevelDev {
     int32_t *parent = nullptr;    // parent index at level-1
     int8_t *octant = nullptr;
     int32_t *child_start = nullptr;  // children at level+1 (CSR), sorted so that child jobs group
+    TransBatch m2l, up, down;        // M2L at this level; M2M from level+1 into this; L2L into level+1
 };
 
 struct Timings {
@@ -158,6 +176,7 @@ struct fmmbem_ctx {
     std::vector<fmm::LevelDev> lev;
     std::vector<std::vector<int32_t>> iota_h;  // per level: 0..nbox (one job per child)
     int pmax = 0, delta_p = 0;
+    size_t lds_max = 65536;
     int64_t near_nnz = 0;
     int64_t p2p_pairs = 0;
     bool precond_ready_nb = false, precond_ready_diag = false;
