@@ -65,7 +65,8 @@ def main():
     t_setup = time.perf_counter() - t0
     info = ctx.fmmbem_get_info()
     ps = [info.p[l] for l in range(info.depth + 1)]
-    log(f"setup {t_setup:.2f}s depth {info.depth} leaves {info.nleaf} p {ps} near_nnz {info.near_nnz}")
+    log(f"setup {t_setup:.2f}s depth {info.depth} leaves {info.nleaf} p {ps} near_nnz {info.near_nnz} "
+        f"lds_max {info.lds_max}")
 
     dev = torch.device("cuda:0")
     x_h = synth.complex_normal(n, 11)

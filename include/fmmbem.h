@@ -185,6 +185,7 @@ typedef struct {
     double flops_m2m_l2l;
     double flops_p2m_l2p;
     double bytes_p2p;   /* algorithmic HBM bytes of the near-field kernel per product */
+    int64_t lds_max;    /* LDS bytes a workgroup may use on this device */
 } fmmbem_info;
 
 int fmmbem_get_info(fmmbem_ctx *ctx, fmmbem_info *info);

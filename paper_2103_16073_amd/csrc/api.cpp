@@ -637,6 +637,7 @@ int fmmbem_create(fmmbem_ctx **out, int hip_device, const fmmbem_options *opt) {
                     trans_configure_lds(ctx->lds_max);
                 } catch (const FmmError &) {
                     ctx->lds_max = 65536;
+                    (void)hipGetLastError();  // clear the failed attribute request
                 }
             }
         }
@@ -1020,6 +1021,7 @@ int fmmbem_get_info(fmmbem_ctx *ctx, fmmbem_info *info) {
     int pl = ctx->lev[T.depth].p;
     info->flops_p2m_l2p = (double)ctx->nt * (double)pl * pl * 2 * 8.0;
     info->bytes_p2p = (double)ctx->nt * (2 * 32 + 16 + 16 + 16) + (double)ctx->near_nnz * (4 + 32);
+    info->lds_max = (int64_t)ctx->lds_max;
     return FMMBEM_OK;
     GUARD_END
 }

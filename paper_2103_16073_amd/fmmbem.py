@@ -53,7 +53,7 @@ class Info(ctypes.Structure):
                 ("leaf_max_occ", ctypes.c_int), ("near_nnz", ctypes.c_int64), ("p2p_pairs", ctypes.c_int64),
                 ("p", ctypes.c_int * 24), ("nbox", ctypes.c_int64 * 24), ("m2l_pairs", ctypes.c_int64 * 24),
                 ("flops_m2l", ctypes.c_double), ("flops_m2m_l2l", ctypes.c_double),
-                ("flops_p2m_l2p", ctypes.c_double), ("bytes_p2p", ctypes.c_double)]
+                ("flops_p2m_l2p", ctypes.c_double), ("bytes_p2p", ctypes.c_double), ("lds_max", ctypes.c_int64)]
 
 
 class KStat(ctypes.Structure):
