@@ -81,8 +81,10 @@ typedef struct {
     int leaf_max;        /* octree depth: smallest uniform depth whose non-empty leaves hold at most
                             leaf_max elements on average (subject to leaf side > r_c); default 64 */
     int p_min;           /* minimum truncation number p (expansion degrees n < p); default 16 */
-    double digits;       /* target digits of the truncation rule
-                            p_l = max(p_min, ceil(kd + 1.8 digits^(2/3) kd^(1/3))), kd = k*sqrt(3)*d_l; default 7 */
+    double p_excess;     /* truncation rule p_l = max(p_min, ceil(kd + p_excess kd^(1/3))), kd = k d_l with
+                            d_l the box side at level l; default 4.2.  Larger p than the one-box-separated
+                            translation supports (n + n' well above k|t|) amplifies round-off through the
+                            growth of h_{n+n'}(k|t|), so p is not raised beyond what the accuracy needs. */
     double ktau_switch;  /* coaxial coefficients: original recursion if k*tau < ktau_switch,
                             stabilised recursion otherwise (Section 3.3.1); default 1.0 */
     int max_depth;       /* cap on the octree depth; default 12 */

@@ -45,8 +45,8 @@ int fgmres(int64_t n, hipStream_t st, DeviceBuffers &scr, const std::function<vo
 
 // ------------------------------------------------------------------ setup pieces
 static int level_p(const fmmbem_options &o, double k, double side) {
-    double kd = k * std::sqrt(3.0) * side;
-    double p = kd + 1.8 * std::pow(o.digits, 2.0 / 3.0) * std::cbrt(kd);
+    double kd = k * side;
+    double p = kd + o.p_excess * std::cbrt(kd);
     return std::max(o.p_min, (int)std::ceil(p));
 }
 
@@ -597,7 +597,7 @@ void fmmbem_default_options(fmmbem_options *o) {
     o->rc = 0.0;
     o->leaf_max = 64;
     o->p_min = 16;
-    o->digits = 7.0;
+    o->p_excess = 4.2;
     o->ktau_switch = 1.0;
     o->max_depth = 12;
     o->lds_budget = 0;

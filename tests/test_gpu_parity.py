@@ -124,12 +124,13 @@ def test_matvec_exact_far_vs_dense(F, cfg1_dense):
     ctx.close()
 
 
-@pytest.mark.parametrize("leaf_max", [64, 12, 4])
-def test_matvec_fmm_vs_dense(F, cfg1_dense, leaf_max):
+@pytest.mark.parametrize("leaf_max,lds_budget", [(64, 0), (12, 0), (12, 8192), (64, 8192)])
+def test_matvec_fmm_vs_dense(F, cfg1_dense, leaf_max, lds_budget):
     """FP64 FMM product against the oracle's dense operator: relative L2 <= 1e-6, for octrees of
-    depth 2, 3 and 4 (so M2M/L2L are exercised)."""
+    depth 2 and 3 (so M2M/L2L are exercised), with the fused translation tiles and, under a small
+    LDS budget, with the staged per-degree kernels."""
     room, k = cfg1_dense
-    ctx = make_ctx(F, room, k, leaf_max=leaf_max)
+    ctx = make_ctx(F, room, k, leaf_max=leaf_max, lds_budget=lds_budget)
     info = ctx.fmmbem_get_info()
     L, M = bem.dense_LM(room.vertices, room.triangles, k, info.rc)
     for seed in (1, 2):
@@ -169,4 +170,21 @@ def test_solve_and_field_vs_oracle_lu(F, cfg1_dense):
     psi = ctx.fmmbem_eval_field(0, rec, x)
     psi_ref = bem.direct_receivers(room.vertices, room.triangles, k, room.beta, rs[0], rc, x, rec)
     assert np.linalg.norm(psi - psi_ref) / np.linalg.norm(psi_ref) < 1e-10
+    ctx.close()
+
+
+@pytest.mark.parametrize("cfg,nrows", [(2, 96), (3, 64)])
+def test_matvec_fmm_sampled_rows_full_size(F, cfg, nrows):
+    """Full-size rooms (N = 90,972 at 1 kHz; N = 1,009,576 at 2.5 kHz): the FP64 FMM product on
+    seeded rows against the oracle's matrix-free rows, relative L2 <= 1e-6."""
+    room, k = synth.config_room(cfg)
+    ctx = make_ctx(F, room, k)
+    info = ctx.fmmbem_get_info()
+    x = synth.complex_normal(room.n, 11)
+    y = ctx.fmmbem_matvec(x)[0]
+    rows = np.random.default_rng(5).choice(room.n, nrows, replace=False)
+    ref = bem.direct_matvec_rows(room.vertices, room.triangles, k, room.beta, info.rc, x, rows)
+    err = np.linalg.norm(y[rows] - ref) / np.linalg.norm(ref)
+    print(f"cfg {cfg} N {room.n} depth {info.depth} p {list(info.p)[:info.depth + 1]} err {err:.3e}")
+    assert err < 1e-6
     ctx.close()
