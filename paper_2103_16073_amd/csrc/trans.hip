@@ -65,12 +65,53 @@ __device__ inline void rot_half(int nj, int w, int n, const double *Dn, const do
     }
 }
 
+// Register-blocked variant: each thread produces column mp for R jobs, so every table value read
+// (from LDS here) feeds 2R fused multiply-adds.
+template <bool CONJ, int R>
+__device__ inline void rot_half_b(int nj, int w, int n, const double *Dn, const double2 *in, int is, double2 *out,
+                                  int os, const double2 *ph, int phs, const int16_t *dirs, int PH) {
+    const int ngrp = (nj + R - 1) / R;
+    for (int e = threadIdx.x; e < ngrp * w; e += blockDim.x) {
+        const int g = e / w, mp = e - g * w;
+        const double2 *x[R];
+        double sr[R], si[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            x[r] = in + min(g * R + r, nj - 1) * is;
+            sr[r] = 0.0;
+            si[r] = 0.0;
+        }
+        for (int m = 0; m < w; ++m) {
+            const double d = Dn[m * w + mp];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double2 v = x[r][m];
+                sr[r] = fma(d, v.x, sr[r]);
+                si[r] = fma(d, v.y, si[r]);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int j = g * R + r;
+            if (j >= nj) break;
+            double2 s = cmk(sr[r], si[r]);
+            if (ph) {
+                const double2 f = ph[(int64_t)dirs[j] * phs + PH + (mp - n)];
+                s = CONJ ? cmulc(s, f) : cmul(s, f);
+            }
+            out[j * os + mp] = s;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ fused kernel
 __global__ void __launch_bounds__(256) k_trans_fused(TransArgs a) {
     extern __shared__ double2 lds[];
     const int JT = a.JT, P2 = a.P * a.P, TW = 2 * a.P;
     double2 *X = lds;                 // JT * P2
     double2 *tmp = X + JT * P2;       // JT * TW
+    double *DL = (double *)(tmp + JT * TW);  // Delta^n and its transpose, (2P-1)^2 each
+    const int DW = (2 * a.P - 1) * (2 * a.P - 1);
     __shared__ int16_t sdir[64];
     __shared__ int32_t stgt[64];
     const int64_t t0 = (int64_t)blockIdx.x * JT;
@@ -96,9 +137,14 @@ __global__ void __launch_bounds__(256) k_trans_fused(TransArgs a) {
     // forward rotation
     for (int n = 0; n < a.psrc; ++n) {
         const int w = 2 * n + 1;
-        rot_half<false>(nj, w, n, a.D + rot_block_off(n), X + n * n, P2, tmp, TW, a.phB, phs, sdir, a.PH);
+        for (int e = threadIdx.x; e < w * w; e += blockDim.x) {
+            DL[e] = a.D[rot_block_off(n) + e];
+            DL[DW + e] = a.DT[rot_block_off(n) + e];
+        }
         __syncthreads();
-        rot_half<false>(nj, w, n, a.DT + rot_block_off(n), tmp, TW, X + n * n, P2, nullptr, 0, sdir, a.PH);
+        rot_half_b<false, 4>(nj, w, n, DL, X + n * n, P2, tmp, TW, a.phB, phs, sdir, a.PH);
+        __syncthreads();
+        rot_half_b<false, 4>(nj, w, n, DL + DW, tmp, TW, X + n * n, P2, nullptr, 0, sdir, a.PH);
         __syncthreads();
     }
     // coaxial translation, order by order (in place through tmp)
@@ -108,18 +154,34 @@ __global__ void __launch_bounds__(256) k_trans_fused(TransArgs a) {
         const int am = m < 0 ? -m : m;
         const int rows = a.ptgt - am, B = a.PT - am;
         const double2 *Tm = T + coax_block_off(a.PT, am);
-        for (int e = threadIdx.x; e < nj * rows; e += blockDim.x) {
-            const int j = e / rows, nn = am + (e - j * rows);
-            const double2 *x = X + j * P2;
-            double sr = 0.0, si = 0.0;
-            for (int n = am; n < a.psrc; ++n) {
-                const double2 t = Tm[(n - am) * B + (nn - am)];
-                const double2 v = x[n * n + n + m];
-                const double sg = ((n + nn) & 1) ? -1.0 : 1.0;
-                sr = fma(sg, t.x * v.x - t.y * v.y, sr);
-                si = fma(sg, t.x * v.y + t.y * v.x, si);
+        constexpr int R = 4;
+        const int ngrp = (nj + R - 1) / R;
+        for (int e = threadIdx.x; e < ngrp * rows; e += blockDim.x) {
+            const int g = e / rows, nn = am + (e - g * rows);
+            const double2 *x[R];
+            double sr[R], si[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                x[r] = X + min(g * R + r, nj - 1) * P2;
+                sr[r] = 0.0;
+                si[r] = 0.0;
             }
-            tmp[j * TW + nn] = cmk(sr, si);
+            for (int n = am; n < a.psrc; ++n) {
+                double2 t = Tm[(n - am) * B + (nn - am)];
+                if ((n + nn) & 1) t = cmk(-t.x, -t.y);
+                const int c = n * n + n + m;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const double2 v = x[r][c];
+                    sr[r] = fma(t.x, v.x, fma(-t.y, v.y, sr[r]));
+                    si[r] = fma(t.x, v.y, fma(t.y, v.x, si[r]));
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int j = g * R + r;
+                if (j < nj) tmp[j * TW + nn] = cmk(sr[r], si[r]);
+            }
         }
         __syncthreads();
         for (int e = threadIdx.x; e < nj * rows; e += blockDim.x) {
@@ -131,9 +193,14 @@ __global__ void __launch_bounds__(256) k_trans_fused(TransArgs a) {
     // back rotation
     for (int n = 0; n < a.ptgt; ++n) {
         const int w = 2 * n + 1;
-        rot_half<true>(nj, w, n, a.D + rot_block_off(n), X + n * n, P2, tmp, TW, a.phB, phs, sdir, a.PH);
+        for (int e = threadIdx.x; e < w * w; e += blockDim.x) {
+            DL[e] = a.D[rot_block_off(n) + e];
+            DL[DW + e] = a.DT[rot_block_off(n) + e];
+        }
         __syncthreads();
-        rot_half<true>(nj, w, n, a.DT + rot_block_off(n), tmp, TW, X + n * n, P2, a.phA, phs, sdir, a.PH);
+        rot_half_b<true, 4>(nj, w, n, DL, X + n * n, P2, tmp, TW, a.phB, phs, sdir, a.PH);
+        __syncthreads();
+        rot_half_b<true, 4>(nj, w, n, DL + DW, tmp, TW, X + n * n, P2, a.phA, phs, sdir, a.PH);
         __syncthreads();
     }
     // accumulate into the targets
@@ -149,8 +216,8 @@ __global__ void __launch_bounds__(256) k_trans_fused(TransArgs a) {
 }
 
 // ------------------------------------------------------------------ staged kernels (large p)
-// Rotation of a tile, degree by degree.  forward: gather from a.src (phase A) -> W (row P^2 per
-// job).  back: W -> atomically into a.dst (final phase conj(A)).
+// Rotation of one degree n (= blockIdx.y) for a tile of jobs.  forward: gather from a.src (phase
+// A) -> W (row P^2 per job).  back: W -> atomically into a.dst (final phase conj(A)).
 __global__ void __launch_bounds__(256) k_stage_rot(TransArgs a, int forward, const double2 *Win, double2 *Wout) {
     extern __shared__ double2 lds[];
     const int JT = a.JT, TW = 2 * a.P, P2 = a.P * a.P;
@@ -158,6 +225,8 @@ __global__ void __launch_bounds__(256) k_stage_rot(TransArgs a, int forward, con
     __shared__ int16_t sdir[64];
     __shared__ int32_t stgt[64];
     __shared__ int32_t ssrc[64];
+    const int n = blockIdx.y;
+    if (n >= (forward ? a.psrc : a.ptgt)) return;
     const int64_t t0 = (int64_t)blockIdx.x * JT;
     const int nj = (int)min((int64_t)JT, a.njob - t0);
     const int phs = 2 * a.PH + 1;
@@ -168,98 +237,100 @@ __global__ void __launch_bounds__(256) k_stage_rot(TransArgs a, int forward, con
         ssrc[j] = a.jsrc[t0 + j];
     }
     __syncthreads();
-    const int nmax = forward ? a.psrc : a.ptgt;
-    for (int n = 0; n < nmax; ++n) {
-        const int w = 2 * n + 1;
-        for (int e = threadIdx.x; e < nj * w; e += blockDim.x) {
-            const int j = e / w, m = e - j * w - n;
-            double2 v;
-            if (forward)
-                v = cmul(a.phA[(int64_t)sdir[j] * phs + a.PH + m], a.src[(int64_t)ssrc[j] * ps2 + n * n + n + m]);
-            else
-                v = Win[(t0 + j) * (int64_t)P2 + n * n + n + m];
-            xs[j * TW + m + n] = v;
-        }
+    const int w = 2 * n + 1;
+    for (int e = threadIdx.x; e < nj * w; e += blockDim.x) {
+        const int j = e / w, m = e - j * w - n;
+        double2 v;
+        if (forward)
+            v = cmul(a.phA[(int64_t)sdir[j] * phs + a.PH + m], a.src[(int64_t)ssrc[j] * ps2 + n * n + n + m]);
+        else
+            v = Win[(t0 + j) * (int64_t)P2 + n * n + n + m];
+        xs[j * TW + m + n] = v;
+    }
+    __syncthreads();
+    if (forward) {
+        rot_half<false>(nj, w, n, a.D + rot_block_off(n), xs, TW, tmp, TW, a.phB, phs, sdir, a.PH);
         __syncthreads();
+        rot_half<false>(nj, w, n, a.DT + rot_block_off(n), tmp, TW, xs, TW, nullptr, 0, sdir, a.PH);
+    } else {
+        rot_half<true>(nj, w, n, a.D + rot_block_off(n), xs, TW, tmp, TW, a.phB, phs, sdir, a.PH);
+        __syncthreads();
+        rot_half<true>(nj, w, n, a.DT + rot_block_off(n), tmp, TW, xs, TW, a.phA, phs, sdir, a.PH);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nj * w; e += blockDim.x) {
+        const int j = e / w, m = e - j * w - n;
+        const double2 v = xs[j * TW + m + n];
         if (forward) {
-            rot_half<false>(nj, w, n, a.D + rot_block_off(n), xs, TW, tmp, TW, a.phB, phs, sdir, a.PH);
-            __syncthreads();
-            rot_half<false>(nj, w, n, a.DT + rot_block_off(n), tmp, TW, xs, TW, nullptr, 0, sdir, a.PH);
+            Wout[(t0 + j) * (int64_t)P2 + n * n + n + m] = v;
         } else {
-            rot_half<true>(nj, w, n, a.D + rot_block_off(n), xs, TW, tmp, TW, a.phB, phs, sdir, a.PH);
-            __syncthreads();
-            rot_half<true>(nj, w, n, a.DT + rot_block_off(n), tmp, TW, xs, TW, a.phA, phs, sdir, a.PH);
-        }
-        __syncthreads();
-        for (int e = threadIdx.x; e < nj * w; e += blockDim.x) {
-            const int j = e / w, m = e - j * w - n;
-            const double2 v = xs[j * TW + m + n];
-            if (forward) {
-                Wout[(t0 + j) * (int64_t)P2 + n * n + n + m] = v;
-            } else {
-                const int t = stgt[j];
-                if (t >= 0) {
-                    double *d = (double *)(a.dst + (int64_t)t * pt2 + n * n + n + m);
-                    unsafeAtomicAdd(d, v.x);
-                    unsafeAtomicAdd(d + 1, v.y);
-                }
+            const int t = stgt[j];
+            if (t >= 0) {
+                double *d = (double *)(a.dst + (int64_t)t * pt2 + n * n + n + m);
+                unsafeAtomicAdd(d, v.x);
+                unsafeAtomicAdd(d + 1, v.y);
             }
         }
-        __syncthreads();
     }
 }
 
-// Coaxial step of a tile, order by order: Wout rows (ptgt^2 valid) from Win rows (psrc^2 valid).
+// Coaxial step of one order m = blockIdx.y - (P-1) for a tile: Wout rows (ptgt^2 valid) from Win
+// rows (psrc^2 valid); orders |m| >= min(psrc, ptgt) have no source and are written as zero.
 __global__ void __launch_bounds__(256) k_stage_coax(TransArgs a, const double2 *Win, double2 *Wout) {
     extern __shared__ double2 lds[];
     const int JT = a.JT, TW = 2 * a.P, P2 = a.P * a.P;
     double2 *col = lds;  // JT * TW
+    const int m = (int)blockIdx.y - (a.P - 1);
+    const int am = m < 0 ? -m : m;
+    if (am >= a.ptgt) return;
     const int64_t t0 = (int64_t)blockIdx.x * JT;
     const int nj = (int)min((int64_t)JT, a.njob - t0);
-    const double2 *T = a.tables + (int64_t)a.tile_tab[blockIdx.x] * coax_table_size(a.PT);
     const int pm = min(a.psrc, a.ptgt);
-    // orders |m| >= pm have no source: zero them in the output
-    for (int e = threadIdx.x; e < nj * a.ptgt * a.ptgt; e += blockDim.x) {
-        const int j = e / (a.ptgt * a.ptgt), c = e - j * a.ptgt * a.ptgt;
-        const int n = isqrt_c(c), m = c - n * n - n;
-        if ((m < 0 ? -m : m) >= pm) Wout[(t0 + j) * (int64_t)P2 + c] = cmk(0, 0);
-    }
-    for (int m = -(pm - 1); m <= pm - 1; ++m) {
-        const int am = m < 0 ? -m : m;
-        const int B = a.PT - am;
-        const double2 *Tm = T + coax_block_off(a.PT, am);
-        const int cin = a.psrc - am;
-        for (int e = threadIdx.x; e < nj * cin; e += blockDim.x) {
-            const int j = e / cin, n = am + (e - j * cin);
-            col[j * TW + n] = Win[(t0 + j) * (int64_t)P2 + n * n + n + m];
-        }
-        __syncthreads();
-        const int rows = a.ptgt - am;
+    const int rows = a.ptgt - am;
+    if (am >= pm) {
         for (int e = threadIdx.x; e < nj * rows; e += blockDim.x) {
             const int j = e / rows, nn = am + (e - j * rows);
-            const double2 *x = col + j * TW;
-            double sr = 0.0, si = 0.0;
-            for (int n = am; n < a.psrc; ++n) {
-                const double2 t = Tm[(int64_t)(n - am) * B + (nn - am)];
-                const double2 v = x[n];
-                const double sg = ((n + nn) & 1) ? -1.0 : 1.0;
-                sr = fma(sg, t.x * v.x - t.y * v.y, sr);
-                si = fma(sg, t.x * v.y + t.y * v.x, si);
-            }
-            Wout[(t0 + j) * (int64_t)P2 + nn * nn + nn + m] = cmk(sr, si);
+            Wout[(t0 + j) * (int64_t)P2 + nn * nn + nn + m] = cmk(0, 0);
         }
-        __syncthreads();
+        return;
+    }
+    const double2 *T = a.tables + (int64_t)a.tile_tab[blockIdx.x] * coax_table_size(a.PT);
+    const int B = a.PT - am;
+    const double2 *Tm = T + coax_block_off(a.PT, am);
+    const int cin = a.psrc - am;
+    for (int e = threadIdx.x; e < nj * cin; e += blockDim.x) {
+        const int j = e / cin, n = am + (e - j * cin);
+        col[j * TW + n] = Win[(t0 + j) * (int64_t)P2 + n * n + n + m];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nj * rows; e += blockDim.x) {
+        const int j = e / rows, nn = am + (e - j * rows);
+        const double2 *x = col + j * TW;
+        double sr = 0.0, si = 0.0;
+        for (int n = am; n < a.psrc; ++n) {
+            const double2 t = Tm[(int64_t)(n - am) * B + (nn - am)];
+            const double2 v = x[n];
+            const double sg = ((n + nn) & 1) ? -1.0 : 1.0;
+            sr = fma(sg, t.x * v.x - t.y * v.y, sr);
+            si = fma(sg, t.x * v.y + t.y * v.x, si);
+        }
+        Wout[(t0 + j) * (int64_t)P2 + nn * nn + nn + m] = cmk(sr, si);
     }
 }
 
 // ------------------------------------------------------------------ host side
+static size_t fused_table_bytes(int P) { return sizeof(double) * 2 * (size_t)(2 * P - 1) * (2 * P - 1); }
+
 size_t trans_lds_bytes(int fused, int JT, int P) {
-    return fused ? sizeof(double2) * (size_t)JT * ((size_t)P * P + 2 * P) : sizeof(double2) * (size_t)JT * 4 * P;
+    return fused ? sizeof(double2) * (size_t)JT * ((size_t)P * P + 2 * P) + fused_table_bytes(P)
+                 : sizeof(double2) * (size_t)JT * 4 * P;
 }
 
 int trans_pick_jt(int fused, int P, size_t lds_max) {
+    const size_t fixed = fused ? fused_table_bytes(P) : 0;
+    if (lds_max <= fixed) return 0;
     const size_t per = fused ? sizeof(double2) * ((size_t)P * P + 2 * P) : sizeof(double2) * 4 * (size_t)P;
-    int jt = (int)std::min<size_t>(64, lds_max / per);
+    int jt = (int)std::min<size_t>(64, (lds_max - fixed) / per);
     if (!fused) jt = std::min(jt, 16);
     return jt;
 }
@@ -281,11 +352,11 @@ void trans_launch(const TransBatch &b, const double2 *src, double2 *dst, const d
         k_trans_fused<<<ntile, 256, trans_lds_bytes(1, b.JT, b.P), st>>>(a);
         LAUNCH_OK();
     } else {
-        k_stage_rot<<<ntile, 256, trans_lds_bytes(0, b.JT, b.P), st>>>(a, 1, nullptr, W1);
+        k_stage_rot<<<dim3(ntile, b.psrc), 256, trans_lds_bytes(0, b.JT, b.P), st>>>(a, 1, nullptr, W1);
         LAUNCH_OK();
-        k_stage_coax<<<ntile, 256, (size_t)sizeof(double2) * b.JT * 2 * b.P, st>>>(a, W1, W2);
+        k_stage_coax<<<dim3(ntile, 2 * b.P - 1), 256, (size_t)sizeof(double2) * b.JT * 2 * b.P, st>>>(a, W1, W2);
         LAUNCH_OK();
-        k_stage_rot<<<ntile, 256, trans_lds_bytes(0, b.JT, b.P), st>>>(a, 0, W2, nullptr);
+        k_stage_rot<<<dim3(ntile, b.ptgt), 256, trans_lds_bytes(0, b.JT, b.P), st>>>(a, 0, W2, nullptr);
         LAUNCH_OK();
     }
 }
