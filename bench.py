@@ -37,6 +37,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--maxit", type=int, default=300)
+    ap.add_argument("--lds-budget", type=int, default=0, help="LDS bytes per translation tile (0 = library default)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -55,7 +56,7 @@ def main():
     rs, rec = synth.source_and_receivers(room, 64)
     n = room.n
     log(f"workload {args.workload}: N={n} k={k:.3f}")
-    ctx = F.Context(0)
+    ctx = F.Context(0, lds_budget=args.lds_budget)
     ctx.fmmbem_set_mesh(room.vertices, room.triangles)
     ctx.fmmbem_set_wavenumber(k)
     ctx.fmmbem_set_admittance(room.beta)

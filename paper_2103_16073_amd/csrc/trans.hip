@@ -249,13 +249,13 @@ __global__ void __launch_bounds__(256) k_stage_rot(TransArgs a, int forward, con
     }
     __syncthreads();
     if (forward) {
-        rot_half<false>(nj, w, n, a.D + rot_block_off(n), xs, TW, tmp, TW, a.phB, phs, sdir, a.PH);
+        rot_half_b<false, 4>(nj, w, n, a.D + rot_block_off(n), xs, TW, tmp, TW, a.phB, phs, sdir, a.PH);
         __syncthreads();
-        rot_half<false>(nj, w, n, a.DT + rot_block_off(n), tmp, TW, xs, TW, nullptr, 0, sdir, a.PH);
+        rot_half_b<false, 4>(nj, w, n, a.DT + rot_block_off(n), tmp, TW, xs, TW, nullptr, 0, sdir, a.PH);
     } else {
-        rot_half<true>(nj, w, n, a.D + rot_block_off(n), xs, TW, tmp, TW, a.phB, phs, sdir, a.PH);
+        rot_half_b<true, 4>(nj, w, n, a.D + rot_block_off(n), xs, TW, tmp, TW, a.phB, phs, sdir, a.PH);
         __syncthreads();
-        rot_half<true>(nj, w, n, a.DT + rot_block_off(n), tmp, TW, xs, TW, a.phA, phs, sdir, a.PH);
+        rot_half_b<true, 4>(nj, w, n, a.DT + rot_block_off(n), tmp, TW, xs, TW, a.phA, phs, sdir, a.PH);
     }
     __syncthreads();
     for (int e = threadIdx.x; e < nj * w; e += blockDim.x) {
@@ -331,7 +331,7 @@ int trans_pick_jt(int fused, int P, size_t lds_max) {
     if (lds_max <= fixed) return 0;
     const size_t per = fused ? sizeof(double2) * ((size_t)P * P + 2 * P) : sizeof(double2) * 4 * (size_t)P;
     int jt = (int)std::min<size_t>(64, (lds_max - fixed) / per);
-    if (!fused) jt = std::min(jt, 16);
+    if (!fused) jt = std::min(jt, 64);
     return jt;
 }
 
