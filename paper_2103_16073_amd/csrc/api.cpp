@@ -162,40 +162,49 @@ static void setup_mesh(fmmbem_ctx *c) {
     HIP_OK(hipStreamSynchronize(st));
 }
 
-static void direction_phases(int PH, std::vector<double2> &A, std::vector<double2> &B) {
+static void direction_vector(int d, double *t) {
+    if (d < 343) {
+        t[0] = d / 49 - 3;
+        t[1] = (d / 7) % 7 - 3;
+        t[2] = d % 7 - 3;
+    } else {
+        int o = (d - 343) % 8;
+        double sgn = d < 351 ? -1.0 : 1.0;  // M2M: parent - child; L2L: child - parent
+        t[0] = sgn * ((o & 1) ? 1.0 : -1.0);
+        t[1] = sgn * ((o & 2) ? 1.0 : -1.0);
+        t[2] = sgn * ((o & 4) ? 1.0 : -1.0);
+    }
+}
+
+static double direction_cos_beta(int d) {
+    double t[3];
+    direction_vector(d, t);
+    return t[2] / std::sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+}
+
+// e^{i m alpha} per direction (alpha = azimuth of t), m = -PH..PH
+static void direction_phases(int PH, std::vector<double2> &A) {
     A.assign((size_t)NDIR * (2 * PH + 1), cmk(0, 0));
-    B.assign((size_t)NDIR * (2 * PH + 1), cmk(0, 0));
     for (int d = 0; d < NDIR; ++d) {
         double t[3];
-        if (d < 343) {
-            t[0] = d / 49 - 3;
-            t[1] = (d / 7) % 7 - 3;
-            t[2] = d % 7 - 3;
-        } else {
-            int o = (d - 343) % 8;
-            double sgn = d < 351 ? -1.0 : 1.0;  // M2M: parent - child; L2L: child - parent
-            t[0] = sgn * ((o & 1) ? 1.0 : -1.0);
-            t[1] = sgn * ((o & 2) ? 1.0 : -1.0);
-            t[2] = sgn * ((o & 4) ? 1.0 : -1.0);
-        }
+        direction_vector(d, t);
         double tn = std::sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
         if (tn == 0) continue;
-        double beta = std::acos(std::max(-1.0, std::min(1.0, t[2] / tn)));
         double alpha = (t[0] == 0 && t[1] == 0) ? 0.0 : std::atan2(t[1], t[0]);
-        for (int m = -PH; m <= PH; ++m) {
-            double2 ea = cmk(std::cos(m * alpha), std::sin(m * alpha));
-            A[(size_t)d * (2 * PH + 1) + m + PH] = cmul(ea, ipow(-m));  // e^{i m a} (-i)^m
-            B[(size_t)d * (2 * PH + 1) + m + PH] = cmk(std::cos(m * beta), std::sin(m * beta));
-        }
+        for (int m = -PH; m <= PH; ++m)
+            A[(size_t)d * (2 * PH + 1) + m + PH] = cmk(std::cos(m * alpha), std::sin(m * alpha));
     }
 }
 
 struct JobH {
     int32_t src, tgt;
     int16_t dir;
-    int tab;
+    int tab;   // coaxial table
+    int rot;   // polar-angle class
 };
 
+// Sort jobs by (coaxial table, polar angle, target), pad every class to whole tiles, build the
+// rotation tables of the batch's distinct polar angles.
 static void make_batch(fmmbem_ctx *c, const std::string &name, std::vector<JobH> jobs, int psrc, int ptgt, int PT,
                        TransBatch &b) {
     hipStream_t st = c->stream;
@@ -205,20 +214,30 @@ static void make_batch(fmmbem_ctx *c, const std::string &name, std::vector<JobH>
     b.PT = PT;
     b.P = std::max(psrc, ptgt);
     b.nreal = (int64_t)jobs.size();
-    size_t budget = c->opt.lds_budget > 0 ? (size_t)c->opt.lds_budget : (size_t)65536;
-    budget = std::min(budget, c->lds_max) - 1024;  // headroom for the kernels' static LDS
-    const int jf = trans_pick_jt(1, b.P, budget);
-    b.fused = jf >= 2;
-    b.JT = std::max(1, b.fused ? jf : trans_pick_jt(0, b.P, budget));
+    size_t budget = c->opt.lds_budget > 0 ? (size_t)c->opt.lds_budget : (size_t)32768;
+    budget = std::min(budget, c->lds_max - 1024);
+    b.JT = trans_pick_jt(b.P, budget);
+    // polar-angle classes
+    std::vector<double> cb;
+    for (auto &j : jobs) cb.push_back(direction_cos_beta(j.dir));
+    std::vector<double> uniq = cb;
+    std::sort(uniq.begin(), uniq.end());
+    std::vector<double> classes;
+    for (double v : uniq)
+        if (classes.empty() || v - classes.back() > 1e-12) classes.push_back(v);
+    for (size_t q = 0; q < jobs.size(); ++q)
+        jobs[q].rot = (int)(std::lower_bound(classes.begin(), classes.end(), cb[q] - 1e-12) - classes.begin());
     std::stable_sort(jobs.begin(), jobs.end(), [](const JobH &x, const JobH &y) {
-        return x.tab != y.tab ? x.tab < y.tab : x.tgt < y.tgt;
+        if (x.tab != y.tab) return x.tab < y.tab;
+        if (x.rot != y.rot) return x.rot < y.rot;
+        return x.tgt < y.tgt;
     });
-    std::vector<int32_t> s, t, tt;
+    std::vector<int32_t> s, t, tc, tr;
     std::vector<int16_t> d;
     size_t q = 0;
     while (q < jobs.size()) {
         size_t e = q;
-        while (e < jobs.size() && jobs[e].tab == jobs[q].tab) ++e;
+        while (e < jobs.size() && jobs[e].tab == jobs[q].tab && jobs[e].rot == jobs[q].rot) ++e;
         for (size_t r = q; r < e; ++r) {
             s.push_back(jobs[r].src);
             t.push_back(jobs[r].tgt);
@@ -229,27 +248,25 @@ static void make_batch(fmmbem_ctx *c, const std::string &name, std::vector<JobH>
             t.push_back(-1);
             d.push_back(jobs[q].dir);
         }
-        q = e;
-    }
-    // table of every tile, in the sorted and padded order
-    {
-        size_t pos = 0;
-        q = 0;
-        while (q < jobs.size()) {
-            size_t e = q;
-            while (e < jobs.size() && jobs[e].tab == jobs[q].tab) ++e;
-            size_t cnt = e - q, tiles = (cnt + b.JT - 1) / b.JT;
-            for (size_t k = 0; k < tiles; ++k) tt.push_back(jobs[q].tab);
-            pos += tiles * b.JT;
-            q = e;
+        const size_t tiles = (e - q + b.JT - 1) / b.JT;
+        for (size_t k = 0; k < tiles; ++k) {
+            tc.push_back(jobs[q].tab);
+            tr.push_back(jobs[q].rot);
         }
-        (void)pos;
+        q = e;
     }
     b.njob = (int64_t)s.size();
     b.src = upload(c->buf, name + "_src", s, st);
     b.tgt = upload(c->buf, name + "_tgt", t, st);
     b.dir = upload(c->buf, name + "_dir", d, st);
-    b.tile_tab = upload(c->buf, name + "_tab", tt, st);
+    b.tile_coax = upload(c->buf, name + "_tcoax", tc, st);
+    b.tile_rot = upload(c->buf, name + "_trot", tr, st);
+    b.nbeta = (int)classes.size();
+    std::vector<double> betas;
+    for (double v : classes) betas.push_back(std::acos(std::max(-1.0, std::min(1.0, v))));
+    b.H = dget<double>(c->buf, name + "_H", std::max<size_t>(1, betas.size()) * rot_table_size(b.P));
+    b.HT = dget<double>(c->buf, name + "_HT", std::max<size_t>(1, betas.size()) * rot_table_size(b.P));
+    build_rot_tables(betas, b.P, (double *)c->buf.find("delta"), b.H, b.HT, c->scratch, st);
 }
 
 static void build_batches(fmmbem_ctx *c) {
@@ -262,7 +279,7 @@ static void build_batches(fmmbem_ctx *c) {
         std::vector<JobH> jobs;
         for (int64_t b = 0; b < D.nbox; ++b)
             for (int q = H.m2l_start[b]; q < H.m2l_start[b + 1]; ++q)
-                jobs.push_back({H.m2l_src[q], (int32_t)b, H.m2l_dir[q], H.m2l_tau_of_dir[H.m2l_dir[q]]});
+                jobs.push_back({H.m2l_src[q], (int32_t)b, H.m2l_dir[q], H.m2l_tau_of_dir[H.m2l_dir[q]], 0});
         make_batch(c, s + "m2l", jobs, D.p, D.p, D.p, D.m2l);
         if (l < L) {
             LevelHost &Hc = T.lv[l + 1];
@@ -270,8 +287,8 @@ static void build_batches(fmmbem_ctx *c) {
             const int PT = std::max(D.p, C.p);
             std::vector<JobH> up, dn;
             for (int64_t ch = 0; ch < C.nbox; ++ch) {
-                up.push_back({(int32_t)ch, Hc.parent[ch], (int16_t)(343 + Hc.octant[ch]), 0});
-                dn.push_back({Hc.parent[ch], (int32_t)ch, (int16_t)(351 + Hc.octant[ch]), 0});
+                up.push_back({(int32_t)ch, Hc.parent[ch], (int16_t)(343 + Hc.octant[ch]), 0, 0});
+                dn.push_back({Hc.parent[ch], (int32_t)ch, (int16_t)(351 + Hc.octant[ch]), 0, 0});
             }
             make_batch(c, s + "up", up, C.p, D.p, PT, D.up);
             make_batch(c, s + "down", dn, D.p, C.p, PT, D.down);
@@ -297,10 +314,9 @@ static void setup_k(fmmbem_ctx *c) {
         double *D = dget<double>(c->buf, "delta", rot_table_size(c->pmax));
         double *DT = dget<double>(c->buf, "deltaT", rot_table_size(c->pmax));
         build_delta_table(c->pmax, D, DT, st);
-        std::vector<double2> A, B;
-        direction_phases(c->pmax, A, B);
+        std::vector<double2> A;
+        direction_phases(c->pmax, A);
         upload(c->buf, "phA", A, st);
-        upload(c->buf, "phB", B, st);
         c->delta_p = c->pmax;
     }
     // coaxial tables
@@ -426,9 +442,9 @@ static void prof_end(fmmbem_ctx *c, int a, const char *name, double flops, doubl
     }
     c->prof_pend.push_back({cls, a, a + 1, flops, bytes});
 }
-static double rot_flops(int p) {  // Delta^T and Delta applied to one complex column set of degree < p
+static double rot_flops(int p) {  // one real (2n+1)^2 rotation per degree applied to a complex vector
     double s = 0;
-    for (int n = 0; n < p; ++n) s += 2.0 * 4.0 * (2.0 * n + 1) * (2.0 * n + 1);
+    for (int n = 0; n < p; ++n) s += 4.0 * (2.0 * n + 1) * (2.0 * n + 1);
     return s;
 }
 static double coax_flops(int ps, int pt) {
@@ -444,17 +460,13 @@ static void run_batch(fmmbem_ctx *c, const char *tag, const TransBatch &b, const
                       const double2 *tables) {
     if (b.njob == 0) return;
     hipStream_t st = c->stream;
-    double2 *W1 = nullptr, *W2 = nullptr;
-    if (!b.fused) {
-        W1 = dget<double2>(c->scratch, "W1", (size_t)b.njob * b.P * b.P);
-        W2 = dget<double2>(c->scratch, "W2", (size_t)b.njob * b.P * b.P);
-    }
+    double2 *W1 = dget<double2>(c->scratch, "W1", (size_t)b.njob * b.P * b.P);
+    double2 *W2 = dget<double2>(c->scratch, "W2", (size_t)b.njob * b.P * b.P);
     int e = prof_begin(c);
-    trans_launch(b, src, dst, tables, (double2 *)c->buf.find("phA"), (double2 *)c->buf.find("phB"), c->delta_p,
-                 (double *)c->buf.find("delta"), (double *)c->buf.find("deltaT"), W1, W2, st);
+    trans_launch(b, src, dst, tables, (double2 *)c->buf.find("phA"), c->delta_p, W1, W2, st);
     double fl = (double)b.nreal * (rot_flops(b.psrc) + rot_flops(b.ptgt) + coax_flops(b.psrc, b.ptgt));
-    double by = (double)b.nreal * 16.0 * (b.psrc * b.psrc + 2.0 * b.ptgt * b.ptgt);
-    prof_end(c, e, (std::string(tag) + (b.fused ? "_fused" : "_staged")).c_str(), fl, by);
+    double by = (double)b.nreal * 16.0 * (b.psrc * b.psrc + 4.0 * b.P * b.P + b.ptgt * b.ptgt);
+    prof_end(c, e, tag, fl, by);
 }
 
 // y (caller order) = half * x + L[sigma] + M[mu] at the centroids; sigma/mu in sorted order.
@@ -994,9 +1006,9 @@ int fmmbem_get_info(fmmbem_ctx *ctx, fmmbem_info *info) {
     info->leaf_max_occ = T.max_occ;
     info->near_nnz = ctx->near_nnz;
     info->p2p_pairs = ctx->p2p_pairs;
-    auto rot = [](int p) {  // real flops of applying Delta^T and Delta to a complex column of degree < p
+    auto rot = [](int p) {  // real flops of one rotation (per degree a real (2n+1)^2 matrix on a complex vector)
         double s = 0;
-        for (int n = 0; n < p; ++n) s += 2.0 * 4.0 * (2.0 * n + 1) * (2.0 * n + 1);
+        for (int n = 0; n < p; ++n) s += 4.0 * (2.0 * n + 1) * (2.0 * n + 1);
         return s;
     };
     auto coax = [](int ps, int pt) {

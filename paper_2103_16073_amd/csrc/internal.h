@@ -106,17 +106,20 @@ void build_tree(const double *centroids, int64_t n, const double *vlo, const dou
 // so that every tile of JT jobs shares one table (padding jobs have tgt = -1).
 struct TransBatch {
     int64_t njob = 0, nreal = 0;
-    int JT = 1, psrc = 0, ptgt = 0, P = 0, PT = 0;
-    bool fused = true;
-    int32_t *src = nullptr, *tgt = nullptr, *tile_tab = nullptr;
+    int JT = 4, psrc = 0, ptgt = 0, P = 0, PT = 0;
+    int32_t *src = nullptr, *tgt = nullptr;
     int16_t *dir = nullptr;
+    int32_t *tile_coax = nullptr, *tile_rot = nullptr;  // tables per tile
+    double *H = nullptr, *HT = nullptr;                 // rotation tables of the batch's polar angles
+    int nbeta = 0;
 };
-size_t trans_lds_bytes(int fused, int JT, int P);
-int trans_pick_jt(int fused, int P, size_t lds_max);
+int trans_pick_jt(int P, size_t lds_budget);
+size_t trans_lds_bytes(int JT, int P);
 void trans_configure_lds(size_t lds_max);
-void trans_launch(const TransBatch &b, const double2 *src, double2 *dst, const double2 *tables, const double2 *phA,
-                  const double2 *phB, int PH, const double *D, const double *DT, double2 *W1, double2 *W2,
-                  hipStream_t st);
+void trans_launch(const TransBatch &b, const double2 *src, double2 *dst, const double2 *coax, const double2 *ph, int PH,
+                  double2 *W1, double2 *W2, hipStream_t st);
+void build_rot_tables(const std::vector<double> &betas, int P, const double *D, double *H, double *HT,
+                      DeviceBuffers &scratch, hipStream_t st);
 
 // ---------------------------------------------------------------- per-level device data
 struct LevelDev {

@@ -282,6 +282,54 @@ __global__ void k_delta(int p, double *D, double *DT) {
     }
 }
 
+// Rotation matrices for polar angle b from the quarter-turn matrices (Fourier-series form of the
+// Wigner matrices): H_n(b)[m'][m] = sum_k Delta_{m'k} Delta_{mk} cos(k b + (m'-m) pi/2), which is
+// the real matrix i^{m'-m} sum_k Delta_{m'k} Delta_{mk} e^{i k b}.  One thread per (b, n, m'),
+// writing row m' of H and column m' of H^T.
+__global__ void k_rot_tables(int nb, const double *betas, int P, const double *D, double *H, double *HT) {
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per = (int64_t)P * P;  // rows over all degrees < P
+    if (gid >= per * nb) return;
+    const int ib = (int)(gid / per);
+    const int64_t r = gid - (int64_t)ib * per;
+    int n = (int)floor(sqrt((double)r));
+    while ((int64_t)n * n > r) --n;
+    while ((int64_t)(n + 1) * (n + 1) <= r) ++n;
+    const int w = 2 * n + 1;
+    const int mpi = (int)(r - (int64_t)n * n);  // row index m' + n
+    const double b = betas[ib];
+    const double *Dn = D + rot_block_off(n);
+    double *Hn = H + (int64_t)ib * rot_table_size(P) + rot_block_off(n);
+    double *HTn = HT + (int64_t)ib * rot_table_size(P) + rot_block_off(n);
+    double sb, cb, s0, c0;
+    sincos(b, &sb, &cb);
+    sincos(-n * b, &s0, &c0);
+    for (int mi = 0; mi < w; ++mi) {
+        const int d = (((mpi - mi) % 4) + 4) % 4;
+        double s = 0.0, cs = c0, sn = s0;  // e^{i k b}, advanced by angle addition
+        for (int ki = 0; ki < w; ++ki) {
+            const double f = d == 0 ? cs : d == 1 ? -sn : d == 2 ? -cs : sn;
+            s = fma(Dn[(int64_t)mpi * w + ki] * Dn[(int64_t)mi * w + ki], f, s);
+            const double nc = cs * cb - sn * sb;
+            sn = cs * sb + sn * cb;
+            cs = nc;
+        }
+        Hn[(int64_t)mpi * w + mi] = s;
+        HTn[(int64_t)mi * w + mpi] = s;
+    }
+}
+
+void build_rot_tables(const std::vector<double> &betas, int P, const double *D, double *H, double *HT,
+                      DeviceBuffers &scratch, hipStream_t st) {
+    if (betas.empty()) return;
+    double *db = (double *)scratch.get("rot_betas", sizeof(double) * betas.size());
+    HIP_OK(hipMemcpyAsync(db, betas.data(), sizeof(double) * betas.size(), hipMemcpyHostToDevice, st));
+    const int64_t nthr = (int64_t)P * P * betas.size();
+    k_rot_tables<<<ceil_div(nthr, 128), 128, 0, st>>>((int)betas.size(), db, P, D, H, HT);
+    LAUNCH_OK();
+    HIP_OK(hipStreamSynchronize(st));  // betas buffer reuse
+}
+
 void build_delta_table(int p, double *D, double *DT, hipStream_t st) {
     int64_t nthreads = (int64_t)p * p;
     k_delta<<<ceil_div(nthreads, 128), 128, 0, st>>>(p, D, DT);
