@@ -206,7 +206,7 @@ struct JobH {
 // Sort jobs by (coaxial table, polar angle, target), pad every class to whole tiles, build the
 // rotation tables of the batch's distinct polar angles.
 static void make_batch(fmmbem_ctx *c, const std::string &name, std::vector<JobH> jobs, int psrc, int ptgt, int PT,
-                       TransBatch &b) {
+                       int64_t ntgt, TransBatch &b) {
     hipStream_t st = c->stream;
     b = TransBatch();
     b.psrc = psrc;
@@ -216,7 +216,10 @@ static void make_batch(fmmbem_ctx *c, const std::string &name, std::vector<JobH>
     b.nreal = (int64_t)jobs.size();
     size_t budget = c->opt.lds_budget > 0 ? (size_t)c->opt.lds_budget : (size_t)32768;
     budget = std::min(budget, c->lds_max - 1024);
-    b.JT = trans_pick_jt(b.P, budget);
+    // whole-vector tiles while at least 8 jobs fit, per-degree slices otherwise
+    b.whole = trans_pick_jt(b.P, budget, 1) >= 8 && (size_t)8 * 16 * b.P * b.P <= budget;
+    b.JT = trans_pick_jt(b.P, budget, b.whole);
+    b.ntgt = ntgt;
     // polar-angle classes
     std::vector<double> cb;
     for (auto &j : jobs) cb.push_back(direction_cos_beta(j.dir));
@@ -256,6 +259,19 @@ static void make_batch(fmmbem_ctx *c, const std::string &name, std::vector<JobH>
         q = e;
     }
     b.njob = (int64_t)s.size();
+    // jobs of every target (CSR over the padded order)
+    {
+        std::vector<int32_t> ts(ntgt + 1, 0), tj;
+        for (int32_t v : t)
+            if (v >= 0) ts[v + 1]++;
+        for (int64_t q2 = 0; q2 < ntgt; ++q2) ts[q2 + 1] += ts[q2];
+        tj.resize(ts[ntgt]);
+        std::vector<int32_t> fill(ts.begin(), ts.end() - 1);
+        for (size_t q2 = 0; q2 < t.size(); ++q2)
+            if (t[q2] >= 0) tj[fill[t[q2]]++] = (int32_t)q2;
+        b.tgt_start = upload(c->buf, name + "_tstart", ts, st);
+        b.tgt_jobs = upload(c->buf, name + "_tjobs", tj, st);
+    }
     b.src = upload(c->buf, name + "_src", s, st);
     b.tgt = upload(c->buf, name + "_tgt", t, st);
     b.dir = upload(c->buf, name + "_dir", d, st);
@@ -280,7 +296,7 @@ static void build_batches(fmmbem_ctx *c) {
         for (int64_t b = 0; b < D.nbox; ++b)
             for (int q = H.m2l_start[b]; q < H.m2l_start[b + 1]; ++q)
                 jobs.push_back({H.m2l_src[q], (int32_t)b, H.m2l_dir[q], H.m2l_tau_of_dir[H.m2l_dir[q]], 0});
-        make_batch(c, s + "m2l", jobs, D.p, D.p, D.p, D.m2l);
+        make_batch(c, s + "m2l", jobs, D.p, D.p, D.p, D.nbox, D.m2l);
         if (l < L) {
             LevelHost &Hc = T.lv[l + 1];
             LevelDev &C = c->lev[l + 1];
@@ -290,8 +306,8 @@ static void build_batches(fmmbem_ctx *c) {
                 up.push_back({(int32_t)ch, Hc.parent[ch], (int16_t)(343 + Hc.octant[ch]), 0, 0});
                 dn.push_back({Hc.parent[ch], (int32_t)ch, (int16_t)(351 + Hc.octant[ch]), 0, 0});
             }
-            make_batch(c, s + "up", up, C.p, D.p, PT, D.up);
-            make_batch(c, s + "down", dn, D.p, C.p, PT, D.down);
+            make_batch(c, s + "up", up, C.p, D.p, PT, D.nbox, D.up);
+            make_batch(c, s + "down", dn, D.p, C.p, PT, C.nbox, D.down);
         }
     }
     HIP_OK(hipStreamSynchronize(c->stream));

@@ -112,9 +112,12 @@ struct TransBatch {
     int32_t *tile_coax = nullptr, *tile_rot = nullptr;  // tables per tile
     double *H = nullptr, *HT = nullptr;                 // rotation tables of the batch's polar angles
     int nbeta = 0;
+    int whole = 0;                                      // whole-vector tiles (small p) or per-degree slices
+    int64_t ntgt = 0;                                   // target boxes
+    int32_t *tgt_start = nullptr, *tgt_jobs = nullptr;  // jobs of each target (CSR, padded job indices)
 };
-int trans_pick_jt(int P, size_t lds_budget);
-size_t trans_lds_bytes(int JT, int P);
+int trans_pick_jt(int P, size_t lds_budget, int whole);
+size_t trans_lds_bytes(int JT, int P, int whole);
 void trans_configure_lds(size_t lds_max);
 void trans_launch(const TransBatch &b, const double2 *src, double2 *dst, const double2 *coax, const double2 *ph, int PH,
                   double2 *W1, double2 *W2, hipStream_t st);

@@ -171,15 +171,11 @@ __global__ void __launch_bounds__(256) k_tr_rot_back(TransArgs a) {
     if (n >= a.ptgt) return;
     const int w = 2 * n + 1, JT = a.JT;
     double2 *ys = lds;  // JT x w
-    __shared__ int32_t stgt[64];
     __shared__ int16_t sdir[64];
     const int64_t t0 = (int64_t)blockIdx.x * JT;
     const int nj = (int)min((int64_t)JT, a.njob - t0);
-    const int pt2 = a.ptgt * a.ptgt, P2 = a.P * a.P, phs = 2 * a.PH + 1;
-    for (int j = threadIdx.x; j < nj; j += blockDim.x) {
-        stgt[j] = a.jtgt[t0 + j];
-        sdir[j] = a.jdir[t0 + j];
-    }
+    const int P2 = a.P * a.P, phs = 2 * a.PH + 1;
+    for (int j = threadIdx.x; j < nj; j += blockDim.x) sdir[j] = a.jdir[t0 + j];
     for (int e = threadIdx.x; e < nj * w; e += blockDim.x) {
         const int j = e / w, q = e - j * w;
         ys[j * w + q] = a.W2[(t0 + j) * (int64_t)P2 + n * n + q];
@@ -216,36 +212,221 @@ __global__ void __launch_bounds__(256) k_tr_rot_back(TransArgs a) {
         for (int u = 0; u < RJ; ++u) {
             const int j = g * RJ + u;
             if (j >= nj) break;
-            const int t = stgt[j];
-            if (t < 0) continue;
-            double2 *out = a.dst + (int64_t)t * pt2 + n * n;
+            double2 *out = a.W1 + (t0 + j) * (int64_t)P2 + n * n;
 #pragma unroll
             for (int v = 0; v < RR; ++v) {
                 const int q = r0 + v;
                 if (q >= w) break;
                 const double2 f = a.ph[(int64_t)sdir[j] * phs + a.PH + (q - n)];
-                const double2 val = cmulc(cmk(ar[u][v], ai[u][v]), f);  // e^{-i m a}
-                unsafeAtomicAdd(&out[q].x, val.x);
-                unsafeAtomicAdd(&out[q].y, val.y);
+                out[q] = cmulc(cmk(ar[u][v], ai[u][v]), f);  // e^{-i m a}
             }
         }
     }
 }
 
+// ------------------------------------------------------------------ whole-vector tiles (small p)
+// The tile's complete coefficient vectors (JT x P^2) are staged in LDS once; one flat work index
+// covers every (degree or order, row group, job group), so a block needs a single barrier.
+// Work items per degree n: ceil((2n+1)/RR) row groups; prefix sums are recomputed on the fly.
+__device__ inline void deg_of_item(int it, int nmax, int &n, int &rg) {
+    // items of degree n: ceil((2n+1)/RR); find n with prefix(n) <= it < prefix(n+1)
+    int acc = 0;
+    for (n = 0; n < nmax; ++n) {
+        const int c = (2 * n + 1 + RR - 1) / RR;
+        if (it < acc + c) {
+            rg = it - acc;
+            return;
+        }
+        acc += c;
+    }
+    n = nmax;
+    rg = 0;
+}
+__host__ __device__ inline int items_rot(int p) {
+    int s = 0;
+    for (int n = 0; n < p; ++n) s += (2 * n + 1 + RR - 1) / RR;
+    return s;
+}
+
+template <bool FWD>
+__global__ void __launch_bounds__(256) k_tw_rot(TransArgs a) {
+    extern __shared__ double2 lds[];
+    const int JT = a.JT, P2 = a.P * a.P, phs = 2 * a.PH + 1;
+    const int pin = FWD ? a.psrc : a.ptgt;  // degrees handled
+    double2 *X = lds;  // JT x P2 (degrees < pin valid)
+    __shared__ int16_t sdir[64];
+    const int64_t t0 = (int64_t)blockIdx.x * JT;
+    const int nj = (int)min((int64_t)JT, a.njob - t0);
+    const int pin2 = pin * pin;
+    for (int j = threadIdx.x; j < nj; j += blockDim.x) sdir[j] = a.jdir[t0 + j];
+    __syncthreads();
+    for (int e = threadIdx.x; e < nj * pin2; e += blockDim.x) {
+        const int j = e / pin2, c = e - j * pin2;
+        double2 v;
+        if (FWD) {
+            const int n = (int)sqrtf((float)c + 0.5f), m = c - n * n - n;
+            v = cmul(a.ph[(int64_t)sdir[j] * phs + a.PH + m], a.src[(int64_t)a.jsrc[t0 + j] * (a.psrc * a.psrc) + c]);
+        } else {
+            v = a.W2[(t0 + j) * (int64_t)P2 + c];
+        }
+        X[j * P2 + c] = v;
+    }
+    __syncthreads();
+    const double *Hb = (FWD ? a.HT : a.H) + (int64_t)a.tile_rot[blockIdx.x] * rot_table_size(a.P);
+    const int ng = (nj + RJ - 1) / RJ, nit = items_rot(pin);
+    for (int e = threadIdx.x; e < ng * nit; e += blockDim.x) {
+        const int g = e / nit;
+        int n, rg;
+        deg_of_item(e - g * nit, pin, n, rg);
+        const int w = 2 * n + 1, r0 = rg * RR;
+        const double *Hn = Hb + rot_block_off(n);
+        double ar[RJ][RR], ai[RJ][RR];
+#pragma unroll
+        for (int u = 0; u < RJ; ++u)
+#pragma unroll
+            for (int v = 0; v < RR; ++v) ar[u][v] = ai[u][v] = 0.0;
+        const double2 *x[RJ];
+#pragma unroll
+        for (int u = 0; u < RJ; ++u) x[u] = X + min(g * RJ + u, nj - 1) * P2 + n * n;
+        for (int k = 0; k < w; ++k) {
+            const double *hrow = Hn + k * w;
+            double h[RR];
+#pragma unroll
+            for (int v = 0; v < RR; ++v) h[v] = (r0 + v < w) ? hrow[r0 + v] : 0.0;
+#pragma unroll
+            for (int u = 0; u < RJ; ++u) {
+                const double2 xv = x[u][k];
+#pragma unroll
+                for (int v = 0; v < RR; ++v) {
+                    ar[u][v] = fma(h[v], xv.x, ar[u][v]);
+                    ai[u][v] = fma(h[v], xv.y, ai[u][v]);
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < RJ; ++u) {
+            const int j = g * RJ + u;
+            if (j >= nj) break;
+            double2 *out = a.W1 + (t0 + j) * (int64_t)P2 + n * n;
+#pragma unroll
+            for (int v = 0; v < RR; ++v) {
+                const int q = r0 + v;
+                if (q >= w) break;
+                double2 val = cmk(ar[u][v], ai[u][v]);
+                if (!FWD) val = cmulc(val, a.ph[(int64_t)sdir[j] * phs + a.PH + (q - n)]);
+                out[q] = val;
+            }
+        }
+    }
+}
+
+// coaxial step, whole vectors: items over (order m, row group) x job groups
+__global__ void __launch_bounds__(256) k_tw_coax(TransArgs a) {
+    extern __shared__ double2 lds[];
+    const int JT = a.JT, P2 = a.P * a.P;
+    double2 *X = lds;  // JT x ps2
+    const int64_t t0 = (int64_t)blockIdx.x * JT;
+    const int nj = (int)min((int64_t)JT, a.njob - t0);
+    const int ps2 = a.psrc * a.psrc, pt = a.ptgt;
+    for (int e = threadIdx.x; e < nj * ps2; e += blockDim.x) {
+        const int j = e / ps2, c = e - j * ps2;
+        X[j * ps2 + c] = a.W1[(t0 + j) * (int64_t)P2 + c];
+    }
+    __syncthreads();
+    const double2 *T = a.coax + (int64_t)a.tile_coax[blockIdx.x] * coax_table_size(a.PT);
+    const int pm = min(a.psrc, a.ptgt);
+    // items: orders m in -(pt-1)..pt-1, row groups ceil((pt-|m|)/RR)
+    int nit = 0;
+    for (int m = -(pt - 1); m <= pt - 1; ++m) nit += (pt - (m < 0 ? -m : m) + RR - 1) / RR;
+    const int ng = (nj + RJ - 1) / RJ;
+    for (int e = threadIdx.x; e < ng * nit; e += blockDim.x) {
+        const int g = e / nit;
+        int it = e - g * nit, m = -(pt - 1);
+        for (;; ++m) {
+            const int c = (pt - (m < 0 ? -m : m) + RR - 1) / RR;
+            if (it < c) break;
+            it -= c;
+        }
+        const int am = m < 0 ? -m : m, r0 = it * RR, rows = pt - am;
+        double ar[RJ][RR], ai[RJ][RR];
+#pragma unroll
+        for (int u = 0; u < RJ; ++u)
+#pragma unroll
+            for (int v = 0; v < RR; ++v) ar[u][v] = ai[u][v] = 0.0;
+        if (am < pm) {
+            const int B = a.PT - am;
+            const double2 *Tm = T + coax_block_off(a.PT, am);
+            const double2 *x[RJ];
+#pragma unroll
+            for (int u = 0; u < RJ; ++u) x[u] = X + min(g * RJ + u, nj - 1) * ps2;
+            for (int n = am; n < a.psrc; ++n) {
+                const int q = n - am;
+                const double2 *trow = Tm + (int64_t)q * B;
+                double2 tt[RR];
+#pragma unroll
+                for (int v = 0; v < RR; ++v) {
+                    const int rr = r0 + v;
+                    double2 tv = rr < rows ? trow[rr] : cmk(0, 0);
+                    if ((q + rr) & 1) tv = cmk(-tv.x, -tv.y);
+                    tt[v] = tv;
+                }
+                const int c = n * n + n + m;
+#pragma unroll
+                for (int u = 0; u < RJ; ++u) {
+                    const double2 xv = x[u][c];
+#pragma unroll
+                    for (int v = 0; v < RR; ++v) {
+                        ar[u][v] = fma(tt[v].x, xv.x, fma(-tt[v].y, xv.y, ar[u][v]));
+                        ai[u][v] = fma(tt[v].x, xv.y, fma(tt[v].y, xv.x, ai[u][v]));
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < RJ; ++u) {
+            const int j = g * RJ + u;
+            if (j >= nj) break;
+            double2 *out = a.W2 + (t0 + j) * (int64_t)P2;
+#pragma unroll
+            for (int v = 0; v < RR; ++v) {
+                const int nn = am + r0 + v;
+                if (r0 + v < rows) out[nn * nn + nn + m] = cmk(ar[u][v], ai[u][v]);
+            }
+        }
+    }
+}
+
+// dst[t] += sum of the job rows of target t (W1, P^2 per job); jobs of t listed in CSR order
+__global__ void __launch_bounds__(256) k_tr_reduce(int64_t ntgt, int ptgt, int P, const int32_t *start,
+                                                   const int32_t *jobs, const double2 *W, double2 *dst) {
+    const int64_t t = blockIdx.x;
+    if (t >= ntgt) return;
+    const int j0 = start[t], j1 = start[t + 1];
+    if (j0 == j1) return;
+    const int pt2 = ptgt * ptgt;
+    for (int c = threadIdx.x; c < pt2; c += blockDim.x) {
+        double2 s = dst[t * pt2 + c];
+        for (int q = j0; q < j1; ++q) s = cadd(s, W[(int64_t)jobs[q] * P * P + c]);
+        dst[t * pt2 + c] = s;
+    }
+}
+
 // ------------------------------------------------------------------ host side
-int trans_pick_jt(int P, size_t lds_budget) {
-    const size_t per = sizeof(double2) * (size_t)std::max(2 * P - 1, P);
+int trans_pick_jt(int P, size_t lds_budget, int whole) {
+    const size_t per = whole ? sizeof(double2) * (size_t)P * P : sizeof(double2) * (size_t)std::max(2 * P - 1, P);
     int jt = (int)std::min<size_t>(64, lds_budget / per);
     jt = std::max(RJ, jt - jt % RJ);
     return jt;
 }
 
-size_t trans_lds_bytes(int JT, int P) { return sizeof(double2) * (size_t)JT * std::max(2 * P - 1, P); }
+size_t trans_lds_bytes(int JT, int P, int whole) {
+    return whole ? sizeof(double2) * (size_t)JT * P * P : sizeof(double2) * (size_t)JT * std::max(2 * P - 1, P);
+}
 
 void trans_configure_lds(size_t lds_max) {
-    HIP_OK(hipFuncSetAttribute((const void *)k_tr_rot_fwd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max));
-    HIP_OK(hipFuncSetAttribute((const void *)k_tr_coax, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max));
-    HIP_OK(hipFuncSetAttribute((const void *)k_tr_rot_back, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max));
+    const void *f[] = {(const void *)k_tr_rot_fwd, (const void *)k_tr_coax, (const void *)k_tr_rot_back,
+                       (const void *)k_tw_rot<true>, (const void *)k_tw_rot<false>, (const void *)k_tw_coax};
+    for (auto fn : f) HIP_OK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max));
 }
 
 void trans_launch(const TransBatch &b, const double2 *src, double2 *dst, const double2 *coax, const double2 *ph, int PH,
@@ -254,12 +435,23 @@ void trans_launch(const TransBatch &b, const double2 *src, double2 *dst, const d
     TransArgs a{b.njob, b.JT, b.psrc, b.ptgt, b.P, b.PT, PH, src, dst, b.src, b.tgt, b.dir, b.tile_coax,
                 b.tile_rot, coax, b.H, b.HT, ph, W1, W2};
     const unsigned ntile = (unsigned)((b.njob + b.JT - 1) / b.JT);
-    const size_t lds = trans_lds_bytes(b.JT, b.P);
-    k_tr_rot_fwd<<<dim3(ntile, b.psrc), 256, lds, st>>>(a);
-    LAUNCH_OK();
-    k_tr_coax<<<dim3(ntile, 2 * b.P - 1), 256, lds, st>>>(a);
-    LAUNCH_OK();
-    k_tr_rot_back<<<dim3(ntile, b.ptgt), 256, lds, st>>>(a);
+    const size_t lds = trans_lds_bytes(b.JT, b.P, b.whole);
+    if (b.whole) {
+        k_tw_rot<true><<<ntile, 256, lds, st>>>(a);
+        LAUNCH_OK();
+        k_tw_coax<<<ntile, 256, lds, st>>>(a);
+        LAUNCH_OK();
+        k_tw_rot<false><<<ntile, 256, lds, st>>>(a);
+        LAUNCH_OK();
+    } else {
+        k_tr_rot_fwd<<<dim3(ntile, b.psrc), 256, lds, st>>>(a);
+        LAUNCH_OK();
+        k_tr_coax<<<dim3(ntile, 2 * b.P - 1), 256, lds, st>>>(a);
+        LAUNCH_OK();
+        k_tr_rot_back<<<dim3(ntile, b.ptgt), 256, lds, st>>>(a);
+        LAUNCH_OK();
+    }
+    k_tr_reduce<<<(unsigned)b.ntgt, 256, 0, st>>>(b.ntgt, b.ptgt, b.P, b.tgt_start, b.tgt_jobs, W1, dst);
     LAUNCH_OK();
 }
 
