@@ -478,11 +478,18 @@ static void run_batch(fmmbem_ctx *c, const char *tag, const TransBatch &b, const
     hipStream_t st = c->stream;
     double2 *W1 = dget<double2>(c->scratch, "W1", (size_t)b.njob * b.P * b.P);
     double2 *W2 = dget<double2>(c->scratch, "W2", (size_t)b.njob * b.P * b.P);
-    int e = prof_begin(c);
-    trans_launch(b, src, dst, tables, (double2 *)c->buf.find("phA"), c->delta_p, W1, W2, st);
-    double fl = (double)b.nreal * (rot_flops(b.psrc) + rot_flops(b.ptgt) + coax_flops(b.psrc, b.ptgt));
-    double by = (double)b.nreal * 16.0 * (b.psrc * b.psrc + 4.0 * b.P * b.P + b.ptgt * b.ptgt);
-    prof_end(c, e, tag, fl, by);
+    (void)tag;
+    const double2 *ph = (double2 *)c->buf.find("phA");
+    const double nr = (double)b.nreal, P2 = (double)b.P * b.P;
+    // algorithmic work per stage: flops of the matrices applied; bytes of the rows moved once
+    const double fl[4] = {nr * rot_flops(b.psrc), nr * coax_flops(b.psrc, b.ptgt), nr * rot_flops(b.ptgt), nr * P2 * 2};
+    const double by[4] = {nr * 16.0 * (b.psrc * b.psrc + P2), nr * 16.0 * 2 * P2, nr * 16.0 * 2 * P2,
+                          16.0 * (nr * P2 + 2.0 * b.ntgt * b.ptgt * b.ptgt)};
+    for (int stage = 0; stage < 4; ++stage) {
+        int e = prof_begin(c);
+        const char *name = trans_launch_stage(b, stage, src, dst, tables, ph, c->delta_p, W1, W2, st);
+        prof_end(c, e, name, fl[stage], by[stage]);
+    }
 }
 
 // y (caller order) = half * x + L[sigma] + M[mu] at the centroids; sigma/mu in sorted order.
@@ -506,7 +513,7 @@ static void fmm_pass(fmmbem_ctx *c, const double2 *sigma, const double2 *mu, con
         // one-point pairs: ~40 flops each (sincos counted as 20); bytes: element data, densities,
         // near table and output, each read once
         double pairs = exact_far ? (double)n * n : (double)c->p2p_pairs;
-        prof_end(c, pe, "p2p", 40.0 * pairs + 16.0 * c->near_nnz, 80.0 * n + 32.0 * n + 16.0 * n + 40.0 * c->near_nnz);
+        prof_end(c, pe, "k_p2p", 40.0 * pairs + 16.0 * c->near_nnz, 80.0 * n + 32.0 * n + 16.0 * n + 40.0 * c->near_nnz);
     }
     HIP_OK(hipEventRecord(c->ev[2], st));
     if (!exact_far) {
@@ -520,7 +527,7 @@ static void fmm_pass(fmmbem_ctx *c, const double2 *sigma, const double2 *mu, con
         pe = prof_begin(c);
         k_p2m<<<nleaf, 256, sh, st>>>(nleaf, p, CH, I32("leaf_start"), LL.center, ec, en, sigma, mu, c->k, LL.M);
         LAUNCH_OK();
-        prof_end(c, pe, "p2m", (double)n * p * p * 2 * 8.0, 112.0 * n + 16.0 * nleaf * p * p);
+        prof_end(c, pe, "k_p2m", (double)n * p * p * 2 * 8.0, 112.0 * n + 16.0 * nleaf * p * p);
         HIP_OK(hipEventRecord(c->ev[3], st));
         // M2M up
         for (int l = L - 1; l >= 2; --l) {
@@ -549,7 +556,7 @@ static void fmm_pass(fmmbem_ctx *c, const double2 *sigma, const double2 *mu, con
     k_l2p<<<nleaf, 64, (size_t)64 * (LL.p + 2) * sizeof(double), st>>>(
         nleaf, LL.p, I32("leaf_start"), LL.center, ec, LL.L, c->k, ynear, half, I32("perm"), x, y, exact_far ? 0 : 1);
     LAUNCH_OK();
-    prof_end(c, pe, "l2p", (double)n * LL.p * LL.p * 8.0, 32.0 * n + 16.0 * n * 3 + 16.0 * nleaf * LL.p * LL.p);
+    prof_end(c, pe, "k_l2p", (double)n * LL.p * LL.p * 8.0, 32.0 * n + 16.0 * n * 3 + 16.0 * nleaf * LL.p * LL.p);
     HIP_OK(hipEventRecord(c->ev[7], st));
 }
 

@@ -119,8 +119,8 @@ struct TransBatch {
 int trans_pick_jt(int P, size_t lds_budget, int whole);
 size_t trans_lds_bytes(int JT, int P, int whole);
 void trans_configure_lds(size_t lds_max);
-void trans_launch(const TransBatch &b, const double2 *src, double2 *dst, const double2 *coax, const double2 *ph, int PH,
-                  double2 *W1, double2 *W2, hipStream_t st);
+const char *trans_launch_stage(const TransBatch &b, int stage, const double2 *src, double2 *dst, const double2 *coax,
+                               const double2 *ph, int PH, double2 *W1, double2 *W2, hipStream_t st);
 void build_rot_tables(const std::vector<double> &betas, int P, const double *D, double *H, double *HT,
                       DeviceBuffers &scratch, hipStream_t st);
 

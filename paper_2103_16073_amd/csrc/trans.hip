@@ -429,30 +429,34 @@ void trans_configure_lds(size_t lds_max) {
     for (auto fn : f) HIP_OK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max));
 }
 
-void trans_launch(const TransBatch &b, const double2 *src, double2 *dst, const double2 *coax, const double2 *ph, int PH,
-                  double2 *W1, double2 *W2, hipStream_t st) {
-    if (b.njob == 0) return;
+// One stage of a batch: 0 forward rotation, 1 coaxial step, 2 back rotation, 3 reduction into
+// the targets.  Returns the HIP kernel's name (for profiling).
+const char *trans_launch_stage(const TransBatch &b, int stage, const double2 *src, double2 *dst, const double2 *coax,
+                               const double2 *ph, int PH, double2 *W1, double2 *W2, hipStream_t st) {
     TransArgs a{b.njob, b.JT, b.psrc, b.ptgt, b.P, b.PT, PH, src, dst, b.src, b.tgt, b.dir, b.tile_coax,
                 b.tile_rot, coax, b.H, b.HT, ph, W1, W2};
     const unsigned ntile = (unsigned)((b.njob + b.JT - 1) / b.JT);
     const size_t lds = trans_lds_bytes(b.JT, b.P, b.whole);
-    if (b.whole) {
-        k_tw_rot<true><<<ntile, 256, lds, st>>>(a);
-        LAUNCH_OK();
-        k_tw_coax<<<ntile, 256, lds, st>>>(a);
-        LAUNCH_OK();
-        k_tw_rot<false><<<ntile, 256, lds, st>>>(a);
-        LAUNCH_OK();
-    } else {
-        k_tr_rot_fwd<<<dim3(ntile, b.psrc), 256, lds, st>>>(a);
-        LAUNCH_OK();
-        k_tr_coax<<<dim3(ntile, 2 * b.P - 1), 256, lds, st>>>(a);
-        LAUNCH_OK();
-        k_tr_rot_back<<<dim3(ntile, b.ptgt), 256, lds, st>>>(a);
-        LAUNCH_OK();
+    const char *name = "";
+    switch (stage) {
+    case 0:
+        if (b.whole) k_tw_rot<true><<<ntile, 256, lds, st>>>(a), name = "k_tw_rot_fwd";
+        else k_tr_rot_fwd<<<dim3(ntile, b.psrc), 256, lds, st>>>(a), name = "k_tr_rot_fwd";
+        break;
+    case 1:
+        if (b.whole) k_tw_coax<<<ntile, 256, lds, st>>>(a), name = "k_tw_coax";
+        else k_tr_coax<<<dim3(ntile, 2 * b.P - 1), 256, lds, st>>>(a), name = "k_tr_coax";
+        break;
+    case 2:
+        if (b.whole) k_tw_rot<false><<<ntile, 256, lds, st>>>(a), name = "k_tw_rot_back";
+        else k_tr_rot_back<<<dim3(ntile, b.ptgt), 256, lds, st>>>(a), name = "k_tr_rot_back";
+        break;
+    default:
+        k_tr_reduce<<<(unsigned)b.ntgt, 256, 0, st>>>(b.ntgt, b.ptgt, b.P, b.tgt_start, b.tgt_jobs, W1, dst);
+        name = "k_tr_reduce";
     }
-    k_tr_reduce<<<(unsigned)b.ntgt, 256, 0, st>>>(b.ntgt, b.ptgt, b.P, b.tgt_start, b.tgt_jobs, W1, dst);
     LAUNCH_OK();
+    return name;
 }
 
 }  // namespace fmm
