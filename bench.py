@@ -110,6 +110,29 @@ def main():
     log(f"dominant kernel {dom['name']}: {avg_ms:.3f} ms/launch, {achieved/1e12:.3f} TFLOP/s")
 
     y_h = y.cpu().numpy()
+
+    # the same product in mixed precision (FP32 near field and translations)
+    ym = torch.empty_like(x)
+    for _ in range(args.warmup):
+        ctx.fmmbem_matvec_dev(x.data_ptr(), ym.data_ptr(), precision=F.FMMBEM_MIXED, stream=sp)
+    ctx.fmmbem_profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.fmmbem_matvec_dev(x.data_ptr(), ym.data_ptr(), precision=F.FMMBEM_MIXED, stream=sp)
+    torch.cuda.synchronize()
+    tm = time.perf_counter() - t0
+    stats_m = ctx.fmmbem_kernel_stats()
+    ctx.fmmbem_profile(False)
+    ym_h = ym.cpu().numpy()
+    mixed = {"ms_per_step": 1e3 * tm / args.steps, "value": args.steps / tm,
+             "rel_l2_vs_fp64_product": float(np.linalg.norm(ym_h - y_h) / np.linalg.norm(y_h)),
+             "phases_ms": {s["name"]: round(s["ms"] / args.steps, 4) for s in stats_m}}
+    log(f"mixed: {mixed['ms_per_step']:.2f} ms/step, {mixed['value']:.3f} matvec/s, "
+        f"rel L2 vs FP64 product {mixed['rel_l2_vs_fp64_product']:.2e}")
+    for s in stats_m:
+        log(f"  {s['name']:20s} {s['ms'] / args.steps:9.3f} ms/step")
+
     result = {
         "metric": "FMM-BEM matvecs/s at N=1M",
         "value": value,
@@ -130,6 +153,7 @@ def main():
         "setup_s": t_setup,
         "phases_ms": phases,
         "roofline": roofline,
+        "mixed_precision": mixed,
     }
 
     if not args.no_solve:
@@ -165,6 +189,7 @@ def main():
         tcpu = time.perf_counter() - tc
         t_matvec = tcpu * n / R
         err = float(np.linalg.norm(y_h[rows] - ref) / np.linalg.norm(ref))
+        mixed["rel_l2_vs_oracle_on_sample"] = float(np.linalg.norm(ym_h[rows] - ref) / np.linalg.norm(ref))
         result["cpu_baseline"] = {"value": 1.0 / t_matvec, "unit": "matvec/s", "cores": cores, "kind": "oracle",
                                   "sample": f"{R} seeded rows x all {n} columns in {tcpu:.1f} s, "
                                             f"scaled by N/R"}

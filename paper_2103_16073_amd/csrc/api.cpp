@@ -22,6 +22,12 @@ __global__ void k_gamma(int64_t, const double4 *, const double4 *, const double2
 __global__ void k_p2p(int, const int32_t *, const int32_t *, const int32_t *, int, const double4 *, const double4 *,
                       const double2 *, const double2 *, double, double, const int32_t *, const int32_t *,
                       const double2 *, const double2 *, double2 *);
+__global__ void k_p2p32(int, const int32_t *, const int32_t *, const int32_t *, const double4 *, const double4 *,
+                        const double2 *, const double2 *, double, double, const int32_t *, const int32_t *,
+                        const float2 *, const float2 *, double2 *);
+__global__ void k_cvt_d2f(int64_t, const double2 *, float2 *);
+__global__ void k_cvt_f2d(int64_t, const float2 *, double2 *);
+__global__ void k_cvt_real_d2f(int64_t, const double *, float *);
 __global__ void k_p2m(int, int, int, const int32_t *, const double4 *, const double4 *, const double4 *,
                       const double2 *, const double2 *, double, double2 *);
 __global__ void k_l2p(int, int, const int32_t *, const double4 *, const double4 *, const double2 *, double,
@@ -399,6 +405,7 @@ static void ensure_setup(fmmbem_ctx *c) {
         c->mesh_dirty = false;
     }
     if (c->k_dirty) {
+        c->mixed_ready = false;
         setup_k(c);
         c->k_dirty = false;
         c->precond_ready_nb = c->precond_ready_diag = false;
@@ -472,29 +479,94 @@ static double coax_flops(int ps, int pt) {
 
 // ------------------------------------------------------------------ the FMM pass
 // Staged translation of a batch of jobs (grouped by target) from `src` (psrc) into `dst` (ptgt).
-static void run_batch(fmmbem_ctx *c, const char *tag, const TransBatch &b, const double2 *src, double2 *dst,
-                      const double2 *tables) {
+template <class R>
+static void run_batch(fmmbem_ctx *c, const TransBatch &b, const typename Cx<R>::T *src, typename Cx<R>::T *dst,
+                      const TransTables<R> &tb, const typename Cx<R>::T *ph) {
+    using C = typename Cx<R>::T;
     if (b.njob == 0) return;
     hipStream_t st = c->stream;
-    double2 *W1 = dget<double2>(c->scratch, "W1", (size_t)b.njob * b.P * b.P);
-    double2 *W2 = dget<double2>(c->scratch, "W2", (size_t)b.njob * b.P * b.P);
-    (void)tag;
-    const double2 *ph = (double2 *)c->buf.find("phA");
-    const double nr = (double)b.nreal, P2 = (double)b.P * b.P;
+    C *W1 = (C *)c->scratch.get("W1", sizeof(C) * (size_t)b.njob * b.P * b.P);
+    C *W2 = (C *)c->scratch.get("W2", sizeof(C) * (size_t)b.njob * b.P * b.P);
+    const double nr = (double)b.nreal, P2 = (double)b.P * b.P, cs = (double)sizeof(C);
     // algorithmic work per stage: flops of the matrices applied; bytes of the rows moved once
     const double fl[4] = {nr * rot_flops(b.psrc), nr * coax_flops(b.psrc, b.ptgt), nr * rot_flops(b.ptgt), nr * P2 * 2};
-    const double by[4] = {nr * 16.0 * (b.psrc * b.psrc + P2), nr * 16.0 * 2 * P2, nr * 16.0 * 2 * P2,
-                          16.0 * (nr * P2 + 2.0 * b.ntgt * b.ptgt * b.ptgt)};
+    const double by[4] = {nr * cs * (b.psrc * b.psrc + P2), nr * cs * 2 * P2, nr * cs * 2 * P2,
+                          cs * (nr * P2 + 2.0 * b.ntgt * b.ptgt * b.ptgt)};
     for (int stage = 0; stage < 4; ++stage) {
         int e = prof_begin(c);
-        const char *name = trans_launch_stage(b, stage, src, dst, tables, ph, c->delta_p, W1, W2, st);
+        const char *name = trans_stage<R>(b, tb, stage, src, dst, ph, c->delta_p, W1, W2, st);
         prof_end(c, e, name, fl[stage], by[stage]);
     }
 }
 
+static TransTables<double> tables64(const TransBatch &b, const double2 *coax) { return {coax, b.H, b.HT}; }
+static TransTables<float> tables32(const TransBatch &b, const float2 *coax) { return {coax, b.H32, b.HT32}; }
+
+template <class S, class D>
+static void convert(fmmbem_ctx *c, int64_t n, const S *a, D *b);
+template <>
+void convert<double2, float2>(fmmbem_ctx *c, int64_t n, const double2 *a, float2 *b) {
+    if (n <= 0) return;
+    k_cvt_d2f<<<ceil_div(n, 256), 256, 0, c->stream>>>(n, a, b);
+    LAUNCH_OK();
+}
+template <>
+void convert<float2, double2>(fmmbem_ctx *c, int64_t n, const float2 *a, double2 *b) {
+    if (n <= 0) return;
+    k_cvt_f2d<<<ceil_div(n, 256), 256, 0, c->stream>>>(n, a, b);
+    LAUNCH_OK();
+}
+template <>
+void convert<double, float>(fmmbem_ctx *c, int64_t n, const double *a, float *b) {
+    if (n <= 0) return;
+    k_cvt_real_d2f<<<ceil_div(n, 256), 256, 0, c->stream>>>(n, a, b);
+    LAUNCH_OK();
+}
+
+// FP32 copies of every table the mixed-precision product reads (made once per wavenumber)
+static void ensure_mixed(fmmbem_ctx *c) {
+    if (c->mixed_ready) return;
+    TreeHost &T = c->tree;
+    const int L = T.depth;
+    for (int l = 2; l <= L; ++l) {
+        LevelDev &D = c->lev[l];
+        const int p = D.p;
+        std::string s = "L" + std::to_string(l) + "_";
+        const int64_t nm = coax_table_size(p) * std::max(D.ntau, 1);
+        D.coax_m2l32 = dget<float2>(c->buf, s + "coax_m2l32", nm);
+        convert(c, nm, (const double2 *)D.coax_m2l, D.coax_m2l32);
+        if (l < L) {
+            const int PT = std::max(p, c->lev[l + 1].p);
+            D.coax_up32 = dget<float2>(c->buf, s + "coax_up32", coax_table_size(PT));
+            convert(c, coax_table_size(PT), (const double2 *)D.coax_up, D.coax_up32);
+        }
+        D.M32 = dget<float2>(c->buf, s + "M32", (size_t)D.nbox * p * p);
+        D.L32 = dget<float2>(c->buf, s + "L32", (size_t)D.nbox * p * p);
+        TransBatch *bs[3] = {&D.m2l, &D.up, &D.down};
+        const char *nm3[3] = {"m2l", "up", "down"};
+        for (int q = 0; q < 3; ++q) {
+            TransBatch &b = *bs[q];
+            if (b.njob == 0) continue;
+            const int64_t nh = (int64_t)std::max(1, b.nbeta) * rot_table_size(b.P);
+            b.H32 = dget<float>(c->buf, s + nm3[q] + "_H32", nh);
+            b.HT32 = dget<float>(c->buf, s + nm3[q] + "_HT32", nh);
+            convert(c, nh, (const double *)b.H, b.H32);
+            convert(c, nh, (const double *)b.HT, b.HT32);
+        }
+    }
+    const int64_t nph = (int64_t)NDIR * (2 * c->delta_p + 1);
+    float2 *ph = dget<float2>(c->buf, "phA32", nph);
+    convert(c, nph, (const double2 *)c->buf.find("phA"), ph);
+    float2 *nL = dget<float2>(c->buf, "near_L32", c->near_nnz), *nM = dget<float2>(c->buf, "near_M32", c->near_nnz);
+    convert(c, c->near_nnz, (const double2 *)c->buf.find("near_L"), nL);
+    convert(c, c->near_nnz, (const double2 *)c->buf.find("near_M"), nM);
+    HIP_OK(hipStreamSynchronize(c->stream));
+    c->mixed_ready = true;
+}
+
 // y (caller order) = half * x + L[sigma] + M[mu] at the centroids; sigma/mu in sorted order.
 static void fmm_pass(fmmbem_ctx *c, const double2 *sigma, const double2 *mu, const double2 *x, double half, double2 *y,
-                     bool exact_far) {
+                     bool exact_far, bool mixed = false) {
     TreeHost &T = c->tree;
     const int L = T.depth;
     hipStream_t st = c->stream;
@@ -505,6 +577,14 @@ static void fmm_pass(fmmbem_ctx *c, const double2 *sigma, const double2 *mu, con
     double2 *ynear = dget<double2>(c->scratch, "ynear", n);
     HIP_OK(hipEventRecord(c->ev[1], st));
     int pe = prof_begin(c);
+    if (mixed) {
+        k_p2p32<<<nleaf, 64, 0, st>>>(nleaf, I32("leaf_start"), I32("nbr_start"), I32("nbr_list"), ec, en, sigma, mu, c->k,
+                                      c->rc * c->rc, I32("near_start"), I32("near_col"),
+                                      (float2 *)c->buf.find("near_L32"), (float2 *)c->buf.find("near_M32"), ynear);
+        LAUNCH_OK();
+        prof_end(c, pe, "k_p2p32", 40.0 * c->p2p_pairs + 16.0 * c->near_nnz,
+                 80.0 * n + 32.0 * n + 16.0 * n + 24.0 * c->near_nnz);
+    } else {
     k_p2p<<<nleaf, 64, 0, st>>>(nleaf, I32("leaf_start"), I32("nbr_start"), I32("nbr_list"), exact_far ? 1 : 0, ec, en,
                                 sigma, mu, c->k, c->rc * c->rc, I32("near_start"), I32("near_col"),
                                 (double2 *)c->buf.find("near_L"), (double2 *)c->buf.find("near_M"), ynear);
@@ -514,6 +594,7 @@ static void fmm_pass(fmmbem_ctx *c, const double2 *sigma, const double2 *mu, con
         // near table and output, each read once
         double pairs = exact_far ? (double)n * n : (double)c->p2p_pairs;
         prof_end(c, pe, "k_p2p", 40.0 * pairs + 16.0 * c->near_nnz, 80.0 * n + 32.0 * n + 16.0 * n + 40.0 * c->near_nnz);
+    }
     }
     HIP_OK(hipEventRecord(c->ev[2], st));
     if (!exact_far) {
@@ -529,21 +610,48 @@ static void fmm_pass(fmmbem_ctx *c, const double2 *sigma, const double2 *mu, con
         LAUNCH_OK();
         prof_end(c, pe, "k_p2m", (double)n * p * p * 2 * 8.0, 112.0 * n + 16.0 * nleaf * p * p);
         HIP_OK(hipEventRecord(c->ev[3], st));
-        // M2M up
-        for (int l = L - 1; l >= 2; --l) {
-            LevelDev &P_ = c->lev[l], &C_ = c->lev[l + 1];
-            HIP_OK(hipMemsetAsync(P_.M, 0, sizeof(double2) * P_.nbox * P_.p * P_.p, st));
-            run_batch(c, "m2m", P_.up, C_.M, P_.M, P_.coax_up);
-        }
-        HIP_OK(hipEventRecord(c->ev[4], st));
-        // M2L and L2L down
-        for (int l = 2; l <= L; ++l) {
-            LevelDev &D = c->lev[l];
-            HIP_OK(hipMemsetAsync(D.L, 0, sizeof(double2) * D.nbox * D.p * D.p, st));
-            run_batch(c, "m2l", D.m2l, D.M, D.L, D.coax_m2l);
-            if (l >= 3) {
-                LevelDev &P_ = c->lev[l - 1];
-                run_batch(c, "l2l", P_.down, P_.L, D.L, P_.coax_up);
+        if (mixed) {
+            // FP32 translations between an FP64 P2M and an FP64 L2P
+            const float2 *ph32 = (float2 *)c->buf.find("phA32");
+            pe = prof_begin(c);
+            convert(c, (int64_t)LL.nbox * p * p, (const double2 *)LL.M, LL.M32);
+            prof_end(c, pe, "k_cvt", 0.0, 24.0 * LL.nbox * p * p);
+            for (int l = L - 1; l >= 2; --l) {
+                LevelDev &P_ = c->lev[l], &C_ = c->lev[l + 1];
+                HIP_OK(hipMemsetAsync(P_.M32, 0, sizeof(float2) * P_.nbox * P_.p * P_.p, st));
+                run_batch<float>(c, P_.up, C_.M32, P_.M32, tables32(P_.up, P_.coax_up32), ph32);
+            }
+            HIP_OK(hipEventRecord(c->ev[4], st));
+            for (int l = 2; l <= L; ++l) {
+                LevelDev &D = c->lev[l];
+                HIP_OK(hipMemsetAsync(D.L32, 0, sizeof(float2) * D.nbox * D.p * D.p, st));
+                run_batch<float>(c, D.m2l, D.M32, D.L32, tables32(D.m2l, D.coax_m2l32), ph32);
+                if (l >= 3) {
+                    LevelDev &P_ = c->lev[l - 1];
+                    run_batch<float>(c, P_.down, P_.L32, D.L32, tables32(P_.down, P_.coax_up32), ph32);
+                }
+            }
+            pe = prof_begin(c);
+            convert(c, (int64_t)LL.nbox * p * p, (const float2 *)LL.L32, LL.L);
+            prof_end(c, pe, "k_cvt", 0.0, 24.0 * LL.nbox * p * p);
+        } else {
+            const double2 *ph = (double2 *)c->buf.find("phA");
+            // M2M up
+            for (int l = L - 1; l >= 2; --l) {
+                LevelDev &P_ = c->lev[l], &C_ = c->lev[l + 1];
+                HIP_OK(hipMemsetAsync(P_.M, 0, sizeof(double2) * P_.nbox * P_.p * P_.p, st));
+                run_batch<double>(c, P_.up, C_.M, P_.M, tables64(P_.up, P_.coax_up), ph);
+            }
+            HIP_OK(hipEventRecord(c->ev[4], st));
+            // M2L and L2L down
+            for (int l = 2; l <= L; ++l) {
+                LevelDev &D = c->lev[l];
+                HIP_OK(hipMemsetAsync(D.L, 0, sizeof(double2) * D.nbox * D.p * D.p, st));
+                run_batch<double>(c, D.m2l, D.M, D.L, tables64(D.m2l, D.coax_m2l), ph);
+                if (l >= 3) {
+                    LevelDev &P_ = c->lev[l - 1];
+                    run_batch<double>(c, P_.down, P_.L, D.L, tables64(P_.down, P_.coax_up), ph);
+                }
             }
         }
         HIP_OK(hipEventRecord(c->ev[5], st));
@@ -560,7 +668,7 @@ static void fmm_pass(fmmbem_ctx *c, const double2 *sigma, const double2 *mu, con
     HIP_OK(hipEventRecord(c->ev[7], st));
 }
 
-static void matvec_dev(fmmbem_ctx *c, const double2 *x, double2 *y, bool exact_far) {
+static void matvec_dev(fmmbem_ctx *c, const double2 *x, double2 *y, bool exact_far, bool mixed = false) {
     hipStream_t st = c->stream;
     const int64_t n = c->nt;
     double2 *sigma = dget<double2>(c->scratch, "sigma", n), *mu = dget<double2>(c->scratch, "mu", n);
@@ -568,7 +676,8 @@ static void matvec_dev(fmmbem_ctx *c, const double2 *x, double2 *y, bool exact_f
     k_densities<<<ceil_div(n, 256), 256, 0, st>>>(n, (int32_t *)c->buf.find("perm"), x, (double2 *)c->buf.find("beta"),
                                                   c->k, sigma, mu);
     LAUNCH_OK();
-    fmm_pass(c, sigma, mu, x, 0.5, y, exact_far);
+    if (mixed) ensure_mixed(c);
+    fmm_pass(c, sigma, mu, x, 0.5, y, exact_far, mixed);
     HIP_OK(hipEventRecord(c->ev[8], st));
 }
 
@@ -805,7 +914,8 @@ int fmmbem_rhs(fmmbem_ctx *ctx, fmmbem_c64 *b) {
 int fmmbem_matvec(fmmbem_ctx *ctx, int32_t nrhs, const fmmbem_c64 *x, fmmbem_c64 *y, int precision, int exact_far) {
     if (!ctx) return FMMBEM_EINVAL;
     if (!x || !y || nrhs < 1) return fail(ctx, FMMBEM_EINVAL, "bad vectors");
-    if (precision != FMMBEM_FP64) return fail(ctx, FMMBEM_EINVAL, "precision not available");
+    if (precision != FMMBEM_FP64 && precision != FMMBEM_MIXED) return fail(ctx, FMMBEM_EINVAL, "unknown precision");
+    if (precision == FMMBEM_MIXED && exact_far) return fail(ctx, FMMBEM_EINVAL, "exact_far is an FP64 product");
     GUARD_BEGIN
     HIP_OK(hipSetDevice(ctx->device));
     ensure_setup(ctx);
@@ -813,7 +923,7 @@ int fmmbem_matvec(fmmbem_ctx *ctx, int32_t nrhs, const fmmbem_c64 *x, fmmbem_c64
     double2 *dx = dget<double2>(ctx->scratch, "mv_x", n), *dy = dget<double2>(ctx->scratch, "mv_y", n);
     for (int r = 0; r < nrhs; ++r) {
         HIP_OK(hipMemcpyAsync(dx, x + r * n, sizeof(double2) * n, hipMemcpyHostToDevice, ctx->stream));
-        matvec_dev(ctx, dx, dy, exact_far != 0);
+        matvec_dev(ctx, dx, dy, exact_far != 0, precision == FMMBEM_MIXED);
         HIP_OK(hipMemcpyAsync(y + r * n, dy, sizeof(double2) * n, hipMemcpyDeviceToHost, ctx->stream));
         HIP_OK(hipStreamSynchronize(ctx->stream));
         read_timings(ctx);
@@ -825,7 +935,7 @@ int fmmbem_matvec(fmmbem_ctx *ctx, int32_t nrhs, const fmmbem_c64 *x, fmmbem_c64
 int fmmbem_matvec_dev(fmmbem_ctx *ctx, int32_t nrhs, const void *x, void *y, int precision, void *stream) {
     if (!ctx) return FMMBEM_EINVAL;
     if (!x || !y || nrhs < 1) return fail(ctx, FMMBEM_EINVAL, "bad vectors");
-    if (precision != FMMBEM_FP64) return fail(ctx, FMMBEM_EINVAL, "precision not available");
+    if (precision != FMMBEM_FP64 && precision != FMMBEM_MIXED) return fail(ctx, FMMBEM_EINVAL, "unknown precision");
     GUARD_BEGIN
     HIP_OK(hipSetDevice(ctx->device));
     ensure_setup(ctx);
@@ -836,7 +946,7 @@ int fmmbem_matvec_dev(fmmbem_ctx *ctx, int32_t nrhs, const void *x, void *y, int
     HIP_OK(hipEventRecord(e0, caller));
     HIP_OK(hipStreamWaitEvent(ctx->stream, e0, 0));
     for (int r = 0; r < nrhs; ++r)
-        matvec_dev(ctx, (const double2 *)x + r * n, (double2 *)y + r * n, false);
+        matvec_dev(ctx, (const double2 *)x + r * n, (double2 *)y + r * n, false, precision == FMMBEM_MIXED);
     HIP_OK(hipStreamWaitEvent(caller, ctx->ev[8], 0));
     return FMMBEM_OK;
     GUARD_END
@@ -880,7 +990,7 @@ int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, f
     fmmbem_default_solve_opts(&o);
     if (opts) o = *opts;
     if (o.restart < 1 || o.maxit < 0 || !(o.tol > 0)) return fail(ctx, FMMBEM_EINVAL, "bad solve options");
-    if (o.precision != FMMBEM_FP64) return fail(ctx, FMMBEM_EINVAL, "precision not available");
+    if (o.precision != FMMBEM_FP64 && o.precision != FMMBEM_MIXED) return fail(ctx, FMMBEM_EINVAL, "unknown precision");
     GUARD_BEGIN
     HIP_OK(hipSetDevice(ctx->device));
     if (ctx->src.empty()) return fail(ctx, FMMBEM_ENOTREADY, "sources not set");
@@ -931,7 +1041,10 @@ int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, f
     double2 *dx = dget<double2>(ctx->scratch, "sv_x", n);
     rhs_dev(ctx, isrc, b);
     if (o.use_x0) HIP_OK(hipMemcpyAsync(dx, x, sizeof(double2) * n, hipMemcpyHostToDevice, st));
-    auto mv = [&](const double2 *a, double2 *y) { matvec_dev(ctx, a, y, false); };
+    // the Krylov products run in the requested arithmetic; restart residuals always in FP64
+    const bool mixed = o.precision == FMMBEM_MIXED;
+    auto mv = [&](const double2 *a, double2 *y) { matvec_dev(ctx, a, y, false, mixed); };
+    auto mv64 = [&](const double2 *a, double2 *y) { matvec_dev(ctx, a, y, false, false); };
     std::function<void(const double2 *, double2 *)> pc;
     if (o.precond == FMMBEM_PC_DIAG) {
         double2 *dinv = (double2 *)ctx->buf.find("pc_dinv");
@@ -954,7 +1067,7 @@ int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, f
     }
     int iters = 0, restarts = 0;
     double rel = 1.0;
-    int status = fgmres(n, st, ctx->scratch, mv, mv, pc, b, dx, o.tol, o.restart, o.maxit, o.use_x0 != 0, iters,
+    int status = fgmres(n, st, ctx->scratch, mv, mv64, pc, b, dx, o.tol, o.restart, o.maxit, o.use_x0 != 0, iters,
                         restarts, rel);
     HIP_OK(hipMemcpyAsync(x, dx, sizeof(double2) * n, hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));

@@ -97,3 +97,14 @@ __device__ inline double dist2_exact(double ax, double ay, double az, double bx,
 }
 
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// scalar-generic complex type: Cx<double>::T = double2, Cx<float>::T = float2
+template <class R> struct Cx;
+template <> struct Cx<double> { using T = double2; };
+template <> struct Cx<float> { using T = float2; };
+
+// tables used by one translation batch in the scalar type R
+template <class R> struct TransTables {
+    const typename Cx<R>::T *coax;
+    const R *H, *HT;
+};

@@ -260,6 +260,99 @@ __global__ void __launch_bounds__(64) k_p2p(int nleaf, const int32_t *leaf_start
     }
 }
 
+// ------------------------------------------------------------------ P2P, FP32 arithmetic
+// Mixed-precision near field: the near/far classification uses the exact FP64 squared distance
+// (so it matches the near table), the kernel evaluation runs in FP32, and the accumulation is
+// Kahan-compensated in FP32.  Near-table entries are stored in FP32.
+__device__ inline void kahan_add(float &s, float &c, float v) {
+    const float y = v - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+__global__ void __launch_bounds__(64) k_p2p32(int nleaf, const int32_t *leaf_start, const int32_t *nbr_start,
+                                              const int32_t *nbr_list, const double4 *ec, const double4 *en,
+                                              const double2 *sigma, const double2 *mu, double k, double rc2,
+                                              const int32_t *near_start, const int32_t *near_col, const float2 *nL,
+                                              const float2 *nM, double2 *y) {
+    const int b = blockIdx.x, tid = threadIdx.x;
+    __shared__ double sx[64], sy[64], sz[64];
+    __shared__ float snx[64], sny[64], snz[64];
+    __shared__ float2 sq[64], sw[64];
+    const int ts = leaf_start[b], te = leaf_start[b + 1];
+    const float kf = (float)k, inv4pi = (float)(1.0 / (4.0 * FMM_PI));
+    for (int t0 = ts; t0 < te; t0 += 64) {
+        const int t = t0 + tid;
+        const bool act = t < te;
+        double4 ct = act ? ec[t] : make_double4(0, 0, 0, 0);
+        float ar = 0.f, ai = 0.f, cr = 0.f, ci = 0.f;
+        for (int q = nbr_start[b]; q < nbr_start[b + 1]; ++q) {
+            const int sb = nbr_list[q];
+            const int ss = leaf_start[sb], se = leaf_start[sb + 1];
+            for (int j0 = ss; j0 < se; j0 += 64) {
+                __syncthreads();
+                int j = j0 + tid;
+                if (j < se) {
+                    double4 c = ec[j], nv = en[j];
+                    sx[tid] = c.x;
+                    sy[tid] = c.y;
+                    sz[tid] = c.z;
+                    snx[tid] = (float)nv.x;
+                    sny[tid] = (float)nv.y;
+                    snz[tid] = (float)nv.z;
+                    double2 s = sigma[j], m = mu[j];
+                    sq[tid] = make_float2((float)(s.x * c.w), (float)(s.y * c.w));
+                    sw[tid] = make_float2((float)(m.x * c.w), (float)(m.y * c.w));
+                }
+                __syncthreads();
+                const int cnt = min(64, se - j0);
+                if (act) {
+                    for (int jj = 0; jj < cnt; ++jj) {
+                        double d2 = dist2_exact(ct.x, ct.y, ct.z, sx[jj], sy[jj], sz[jj]);
+                        if (d2 < rc2) continue;
+                        const float dx = (float)(sx[jj] - ct.x), dy = (float)(sy[jj] - ct.y), dz = (float)(sz[jj] - ct.z);
+                        const float r2 = (float)d2, ir = rsqrtf(r2), r = r2 * ir;
+                        float s, c;
+                        sincosf(kf * r, &s, &c);
+                        const float gr = c * ir * inv4pi, gi = s * ir * inv4pi;
+                        const float u = (dx * snx[jj] + dy * sny[jj] + dz * snz[jj]) * ir * ir;
+                        // G * (q + (ikr - 1) u w)
+                        const float2 w = sw[jj], qq = sq[jj];
+                        const float tr = qq.x - u * w.x - kf * r * u * w.y;
+                        const float ti = qq.y - u * w.y + kf * r * u * w.x;
+                        kahan_add(ar, cr, gr * tr - gi * ti);
+                        kahan_add(ai, ci, gr * ti + gi * tr);
+                    }
+                }
+            }
+        }
+        if (act) {
+            double2 acc = make_double2((double)ar + (double)(-cr), (double)ai + (double)(-ci));
+            for (int e = near_start[t]; e < near_start[t + 1]; ++e) {
+                int j = near_col[e];
+                const float2 l = nL[e], m = nM[e];
+                acc = cfma(make_double2(l.x, l.y), sigma[j], acc);
+                acc = cfma(make_double2(m.x, m.y), mu[j], acc);
+            }
+            y[t] = acc;
+        }
+    }
+}
+
+__global__ void k_cvt_d2f(int64_t n, const double2 *a, float2 *b) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = make_float2((float)a[i].x, (float)a[i].y);
+}
+__global__ void k_cvt_f2d(int64_t n, const float2 *a, double2 *b) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = make_double2(a[i].x, a[i].y);
+}
+__global__ void k_cvt_real_d2f(int64_t n, const double *a, float *b) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
+}
+
 // ------------------------------------------------------------------ P2M
 // C_n^m = i k sum_j [ q_j R_n^{-m}(c_j - C) + w_j (n_j . grad) R_n^{-m}(c_j - C) ]
 // using  d_z R_n^m = k (a_{n-1}^m R_{n-1}^m - a_n^m R_{n+1}^m),

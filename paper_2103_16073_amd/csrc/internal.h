@@ -112,6 +112,7 @@ struct TransBatch {
     int32_t *tile_coax = nullptr, *tile_rot = nullptr;  // tables per tile
     double *H = nullptr, *HT = nullptr;                 // rotation tables of the batch's polar angles
     int nbeta = 0;
+    float *H32 = nullptr, *HT32 = nullptr;              // FP32 copies (mixed precision)
     int whole = 0;                                      // whole-vector tiles (small p) or per-degree slices
     int64_t ntgt = 0;                                   // target boxes
     int32_t *tgt_start = nullptr, *tgt_jobs = nullptr;  // jobs of each target (CSR, padded job indices)
@@ -119,8 +120,10 @@ struct TransBatch {
 int trans_pick_jt(int P, size_t lds_budget, int whole);
 size_t trans_lds_bytes(int JT, int P, int whole);
 void trans_configure_lds(size_t lds_max);
-const char *trans_launch_stage(const TransBatch &b, int stage, const double2 *src, double2 *dst, const double2 *coax,
-                               const double2 *ph, int PH, double2 *W1, double2 *W2, hipStream_t st);
+template <class R>
+const char *trans_stage(const TransBatch &b, const TransTables<R> &tb, int stage, const typename Cx<R>::T *src,
+                        typename Cx<R>::T *dst, const typename Cx<R>::T *ph, int PH, typename Cx<R>::T *W1,
+                        typename Cx<R>::T *W2, hipStream_t st);
 void build_rot_tables(const std::vector<double> &betas, int P, const double *D, double *H, double *HT,
                       DeviceBuffers &scratch, hipStream_t st);
 
@@ -144,6 +147,8 @@ struct LevelDev {
     int8_t *octant = nullptr;
     int32_t *child_start = nullptr;  // children at level+1 (CSR), sorted so that child jobs group
     TransBatch m2l, up, down;        // M2L at this level; M2M from level+1 into this; L2L into level+1
+    // FP32 copies for the mixed-precision product
+    float2 *M32 = nullptr, *L32 = nullptr, *coax_m2l32 = nullptr, *coax_up32 = nullptr;
 };
 
 struct Timings {
@@ -186,6 +191,7 @@ struct fmmbem_ctx {
     int64_t near_nnz = 0;
     int64_t p2p_pairs = 0;
     bool precond_ready_nb = false, precond_ready_diag = false;
+    bool mixed_ready = false;  // FP32 copies of the tables exist for the current wavenumber
     fmm::Timings last;
     double t_setup_last = 0.0;
     // kernel profiling (fmmbem_profile)

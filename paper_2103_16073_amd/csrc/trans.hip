@@ -19,59 +19,70 @@
 
 namespace fmm {
 
-struct TransArgs {
+// Scalar-generic complex helpers: the same kernels run in FP64 and in FP32 (mixed mode).
+template <class C> __device__ inline C mkc(double r, double i) { C v; v.x = r; v.y = i; return v; }
+template <class C> __device__ inline C mulc(C a, C b) { C v; v.x = a.x * b.x - a.y * b.y; v.y = a.x * b.y + a.y * b.x; return v; }
+template <class C> __device__ inline C mulcc(C a, C b) { C v; v.x = a.x * b.x + a.y * b.y; v.y = a.y * b.x - a.x * b.y; return v; }
+template <class C> __device__ inline C addc(C a, C b) { C v; v.x = a.x + b.x; v.y = a.y + b.y; return v; }
+
+template <class R>
+struct TransArgsT {
+    using C = typename Cx<R>::T;
     int64_t njob;
     int JT, psrc, ptgt, P, PT, PH;
-    const double2 *src;         // source expansions (psrc^2 per box)
-    double2 *dst;               // target expansions (ptgt^2 per box), accumulated
+    const C *src;               // source expansions (psrc^2 per box)
+    C *dst;                     // target expansions (ptgt^2 per box), accumulated
     const int32_t *jsrc, *jtgt; // per job; jtgt < 0 marks padding
     const int16_t *jdir;
     const int32_t *tile_coax;   // coaxial table per tile
     const int32_t *tile_rot;    // rotation table per tile
-    const double2 *coax;        // coaxial tables, coax_table_size(PT) each
-    const double *H, *HT;       // rotation tables (rot_table_size(P) each) and their transposes
-    const double2 *ph;          // e^{i m a} per direction, 2*PH+1 per direction
-    double2 *W1, *W2;           // work rows, P^2 per job
+    const C *coax;              // coaxial tables, coax_table_size(PT) each
+    const R *H, *HT;            // rotation tables (rot_table_size(P) each) and their transposes
+    const C *ph;                // e^{i m a} per direction, 2*PH+1 per direction
+    C *W1, *W2;                 // work rows, P^2 per job
 };
 
 constexpr int RJ = 4, RR = 4;
 
 // ------------------------------------------------------------------ forward rotation
-__global__ void __launch_bounds__(256) k_tr_rot_fwd(TransArgs a) {
-    extern __shared__ double2 lds[];
+template <class R>
+__global__ void __launch_bounds__(256) k_tr_rot_fwd(TransArgsT<R> a) {
+    using C = typename Cx<R>::T;
+    extern __shared__ double2 lds_raw[];
+    C *lds = (C *)lds_raw;
     const int n = blockIdx.y;
     if (n >= a.psrc) return;
     const int w = 2 * n + 1, JT = a.JT;
-    double2 *xs = lds;  // JT x w
+    C *xs = lds;  // JT x w
     const int64_t t0 = (int64_t)blockIdx.x * JT;
     const int nj = (int)min((int64_t)JT, a.njob - t0);
     const int ps2 = a.psrc * a.psrc, P2 = a.P * a.P, phs = 2 * a.PH + 1;
     for (int e = threadIdx.x; e < nj * w; e += blockDim.x) {
         const int j = e / w, q = e - j * w, m = q - n;
         const int64_t job = t0 + j;
-        xs[j * w + q] = cmul(a.ph[(int64_t)a.jdir[job] * phs + a.PH + m], a.src[(int64_t)a.jsrc[job] * ps2 + n * n + q]);
+        xs[j * w + q] = mulc(a.ph[(int64_t)a.jdir[job] * phs + a.PH + m], a.src[(int64_t)a.jsrc[job] * ps2 + n * n + q]);
     }
     __syncthreads();
-    const double *HTn = a.HT + (int64_t)a.tile_rot[blockIdx.x] * rot_table_size(a.P) + rot_block_off(n);
+    const R *HTn = a.HT + (int64_t)a.tile_rot[blockIdx.x] * rot_table_size(a.P) + rot_block_off(n);
     const int ng = (nj + RJ - 1) / RJ, nr = (w + RR - 1) / RR;
     for (int e = threadIdx.x; e < ng * nr; e += blockDim.x) {
         const int g = e / nr, r0 = (e - g * nr) * RR;
-        double ar[RJ][RR], ai[RJ][RR];
+        R ar[RJ][RR], ai[RJ][RR];
 #pragma unroll
         for (int u = 0; u < RJ; ++u)
 #pragma unroll
             for (int v = 0; v < RR; ++v) ar[u][v] = ai[u][v] = 0.0;
-        const double2 *x[RJ];
+        const C *x[RJ];
 #pragma unroll
         for (int u = 0; u < RJ; ++u) x[u] = xs + min(g * RJ + u, nj - 1) * w;
         for (int m = 0; m < w; ++m) {
-            const double *hrow = HTn + m * w;  // HT[m][mp] = H[mp][m]
-            double h[RR];
+            const R *hrow = HTn + m * w;  // HT[m][mp] = H[mp][m]
+            R h[RR];
 #pragma unroll
             for (int v = 0; v < RR; ++v) h[v] = (r0 + v < w) ? hrow[r0 + v] : 0.0;
 #pragma unroll
             for (int u = 0; u < RJ; ++u) {
-                const double2 xv = x[u][m];
+                const C xv = x[u][m];
 #pragma unroll
                 for (int v = 0; v < RR; ++v) {
                     ar[u][v] = fma(h[v], xv.x, ar[u][v]);
@@ -83,17 +94,20 @@ __global__ void __launch_bounds__(256) k_tr_rot_fwd(TransArgs a) {
         for (int u = 0; u < RJ; ++u) {
             const int j = g * RJ + u;
             if (j >= nj) break;
-            double2 *out = a.W1 + (t0 + j) * (int64_t)P2 + n * n;
+            C *out = a.W1 + (t0 + j) * (int64_t)P2 + n * n;
 #pragma unroll
             for (int v = 0; v < RR; ++v)
-                if (r0 + v < w) out[r0 + v] = cmk(ar[u][v], ai[u][v]);
+                if (r0 + v < w) out[r0 + v] = mkc<C>(ar[u][v], ai[u][v]);
         }
     }
 }
 
 // ------------------------------------------------------------------ coaxial step
-__global__ void __launch_bounds__(256) k_tr_coax(TransArgs a) {
-    extern __shared__ double2 lds[];
+template <class R>
+__global__ void __launch_bounds__(256) k_tr_coax(TransArgsT<R> a) {
+    using C = typename Cx<R>::T;
+    extern __shared__ double2 lds_raw[];
+    C *lds = (C *)lds_raw;
     const int m = (int)blockIdx.y - (a.P - 1);
     const int am = m < 0 ? -m : m;
     if (am >= a.ptgt) return;
@@ -105,44 +119,44 @@ __global__ void __launch_bounds__(256) k_tr_coax(TransArgs a) {
     if (am >= pm) {  // no source of this order
         for (int e = threadIdx.x; e < nj * rows; e += blockDim.x) {
             const int j = e / rows, nn = am + (e - j * rows);
-            a.W2[(t0 + j) * (int64_t)P2 + nn * nn + nn + m] = cmk(0, 0);
+            a.W2[(t0 + j) * (int64_t)P2 + nn * nn + nn + m] = mkc<C>(0, 0);
         }
         return;
     }
     const int cin = a.psrc - am;
-    double2 *col = lds;  // JT x cin
+    C *col = lds;  // JT x cin
     for (int e = threadIdx.x; e < nj * cin; e += blockDim.x) {
         const int j = e / cin, q = e - j * cin, n = am + q;
         col[j * cin + q] = a.W1[(t0 + j) * (int64_t)P2 + n * n + n + m];
     }
     __syncthreads();
     const int B = a.PT - am;
-    const double2 *Tm = a.coax + (int64_t)a.tile_coax[blockIdx.x] * coax_table_size(a.PT) + coax_block_off(a.PT, am);
+    const C *Tm = a.coax + (int64_t)a.tile_coax[blockIdx.x] * coax_table_size(a.PT) + coax_block_off(a.PT, am);
     const int ng = (nj + RJ - 1) / RJ, nr = (rows + RR - 1) / RR;
     for (int e = threadIdx.x; e < ng * nr; e += blockDim.x) {
         const int g = e / nr, r0 = (e - g * nr) * RR;  // output rows nn = am + r0 + v
-        double ar[RJ][RR], ai[RJ][RR];
+        R ar[RJ][RR], ai[RJ][RR];
 #pragma unroll
         for (int u = 0; u < RJ; ++u)
 #pragma unroll
             for (int v = 0; v < RR; ++v) ar[u][v] = ai[u][v] = 0.0;
-        const double2 *x[RJ];
+        const C *x[RJ];
 #pragma unroll
         for (int u = 0; u < RJ; ++u) x[u] = col + min(g * RJ + u, nj - 1) * cin;
         for (int q = 0; q < cin; ++q) {
             // (E|F)_{n' n} = (-1)^{n+n'} (E|F)_{n n'}: read row n = am + q of the block
-            const double2 *trow = Tm + (int64_t)q * B;
-            double2 t[RR];
+            const C *trow = Tm + (int64_t)q * B;
+            C t[RR];
 #pragma unroll
             for (int v = 0; v < RR; ++v) {
                 const int rr = r0 + v;
-                double2 tv = rr < rows ? trow[rr] : cmk(0, 0);
-                if ((q + rr) & 1) tv = cmk(-tv.x, -tv.y);
+                C tv = rr < rows ? trow[rr] : mkc<C>(0, 0);
+                if ((q + rr) & 1) tv = mkc<C>(-tv.x, -tv.y);
                 t[v] = tv;
             }
 #pragma unroll
             for (int u = 0; u < RJ; ++u) {
-                const double2 xv = x[u][q];
+                const C xv = x[u][q];
 #pragma unroll
                 for (int v = 0; v < RR; ++v) {
                     ar[u][v] = fma(t[v].x, xv.x, fma(-t[v].y, xv.y, ar[u][v]));
@@ -154,23 +168,26 @@ __global__ void __launch_bounds__(256) k_tr_coax(TransArgs a) {
         for (int u = 0; u < RJ; ++u) {
             const int j = g * RJ + u;
             if (j >= nj) break;
-            double2 *out = a.W2 + (t0 + j) * (int64_t)P2;
+            C *out = a.W2 + (t0 + j) * (int64_t)P2;
 #pragma unroll
             for (int v = 0; v < RR; ++v) {
                 const int nn = am + r0 + v;
-                if (r0 + v < rows) out[nn * nn + nn + m] = cmk(ar[u][v], ai[u][v]);
+                if (r0 + v < rows) out[nn * nn + nn + m] = mkc<C>(ar[u][v], ai[u][v]);
             }
         }
     }
 }
 
 // ------------------------------------------------------------------ back rotation
-__global__ void __launch_bounds__(256) k_tr_rot_back(TransArgs a) {
-    extern __shared__ double2 lds[];
+template <class R>
+__global__ void __launch_bounds__(256) k_tr_rot_back(TransArgsT<R> a) {
+    using C = typename Cx<R>::T;
+    extern __shared__ double2 lds_raw[];
+    C *lds = (C *)lds_raw;
     const int n = blockIdx.y;
     if (n >= a.ptgt) return;
     const int w = 2 * n + 1, JT = a.JT;
-    double2 *ys = lds;  // JT x w
+    C *ys = lds;  // JT x w
     __shared__ int16_t sdir[64];
     const int64_t t0 = (int64_t)blockIdx.x * JT;
     const int nj = (int)min((int64_t)JT, a.njob - t0);
@@ -181,26 +198,26 @@ __global__ void __launch_bounds__(256) k_tr_rot_back(TransArgs a) {
         ys[j * w + q] = a.W2[(t0 + j) * (int64_t)P2 + n * n + q];
     }
     __syncthreads();
-    const double *Hn = a.H + (int64_t)a.tile_rot[blockIdx.x] * rot_table_size(a.P) + rot_block_off(n);
+    const R *Hn = a.H + (int64_t)a.tile_rot[blockIdx.x] * rot_table_size(a.P) + rot_block_off(n);
     const int ng = (nj + RJ - 1) / RJ, nr = (w + RR - 1) / RR;
     for (int e = threadIdx.x; e < ng * nr; e += blockDim.x) {
         const int g = e / nr, r0 = (e - g * nr) * RR;
-        double ar[RJ][RR], ai[RJ][RR];
+        R ar[RJ][RR], ai[RJ][RR];
 #pragma unroll
         for (int u = 0; u < RJ; ++u)
 #pragma unroll
             for (int v = 0; v < RR; ++v) ar[u][v] = ai[u][v] = 0.0;
-        const double2 *y[RJ];
+        const C *y[RJ];
 #pragma unroll
         for (int u = 0; u < RJ; ++u) y[u] = ys + min(g * RJ + u, nj - 1) * w;
         for (int mp = 0; mp < w; ++mp) {
-            const double *hrow = Hn + mp * w;  // H[mp][m]: (H^T y)_m = sum_mp H[mp][m] y_mp
-            double h[RR];
+            const R *hrow = Hn + mp * w;  // H[mp][m]: (H^T y)_m = sum_mp H[mp][m] y_mp
+            R h[RR];
 #pragma unroll
             for (int v = 0; v < RR; ++v) h[v] = (r0 + v < w) ? hrow[r0 + v] : 0.0;
 #pragma unroll
             for (int u = 0; u < RJ; ++u) {
-                const double2 yv = y[u][mp];
+                const C yv = y[u][mp];
 #pragma unroll
                 for (int v = 0; v < RR; ++v) {
                     ar[u][v] = fma(h[v], yv.x, ar[u][v]);
@@ -212,13 +229,13 @@ __global__ void __launch_bounds__(256) k_tr_rot_back(TransArgs a) {
         for (int u = 0; u < RJ; ++u) {
             const int j = g * RJ + u;
             if (j >= nj) break;
-            double2 *out = a.W1 + (t0 + j) * (int64_t)P2 + n * n;
+            C *out = a.W1 + (t0 + j) * (int64_t)P2 + n * n;
 #pragma unroll
             for (int v = 0; v < RR; ++v) {
                 const int q = r0 + v;
                 if (q >= w) break;
-                const double2 f = a.ph[(int64_t)sdir[j] * phs + a.PH + (q - n)];
-                out[q] = cmulc(cmk(ar[u][v], ai[u][v]), f);  // e^{-i m a}
+                const C f = a.ph[(int64_t)sdir[j] * phs + a.PH + (q - n)];
+                out[q] = mulcc(mkc<C>(ar[u][v], ai[u][v]), f);  // e^{-i m a}
             }
         }
     }
@@ -248,12 +265,14 @@ __host__ __device__ inline int items_rot(int p) {
     return s;
 }
 
-template <bool FWD>
-__global__ void __launch_bounds__(256) k_tw_rot(TransArgs a) {
-    extern __shared__ double2 lds[];
+template <class R, bool FWD>
+__global__ void __launch_bounds__(256) k_tw_rot(TransArgsT<R> a) {
+    using C = typename Cx<R>::T;
+    extern __shared__ double2 lds_raw[];
+    C *lds = (C *)lds_raw;
     const int JT = a.JT, P2 = a.P * a.P, phs = 2 * a.PH + 1;
     const int pin = FWD ? a.psrc : a.ptgt;  // degrees handled
-    double2 *X = lds;  // JT x P2 (degrees < pin valid)
+    C *X = lds;  // JT x P2 (degrees < pin valid)
     __shared__ int16_t sdir[64];
     const int64_t t0 = (int64_t)blockIdx.x * JT;
     const int nj = (int)min((int64_t)JT, a.njob - t0);
@@ -262,40 +281,40 @@ __global__ void __launch_bounds__(256) k_tw_rot(TransArgs a) {
     __syncthreads();
     for (int e = threadIdx.x; e < nj * pin2; e += blockDim.x) {
         const int j = e / pin2, c = e - j * pin2;
-        double2 v;
+        C v;
         if (FWD) {
             const int n = (int)sqrtf((float)c + 0.5f), m = c - n * n - n;
-            v = cmul(a.ph[(int64_t)sdir[j] * phs + a.PH + m], a.src[(int64_t)a.jsrc[t0 + j] * (a.psrc * a.psrc) + c]);
+            v = mulc(a.ph[(int64_t)sdir[j] * phs + a.PH + m], a.src[(int64_t)a.jsrc[t0 + j] * (a.psrc * a.psrc) + c]);
         } else {
             v = a.W2[(t0 + j) * (int64_t)P2 + c];
         }
         X[j * P2 + c] = v;
     }
     __syncthreads();
-    const double *Hb = (FWD ? a.HT : a.H) + (int64_t)a.tile_rot[blockIdx.x] * rot_table_size(a.P);
+    const R *Hb = (FWD ? a.HT : a.H) + (int64_t)a.tile_rot[blockIdx.x] * rot_table_size(a.P);
     const int ng = (nj + RJ - 1) / RJ, nit = items_rot(pin);
     for (int e = threadIdx.x; e < ng * nit; e += blockDim.x) {
         const int g = e / nit;
         int n, rg;
         deg_of_item(e - g * nit, pin, n, rg);
         const int w = 2 * n + 1, r0 = rg * RR;
-        const double *Hn = Hb + rot_block_off(n);
-        double ar[RJ][RR], ai[RJ][RR];
+        const R *Hn = Hb + rot_block_off(n);
+        R ar[RJ][RR], ai[RJ][RR];
 #pragma unroll
         for (int u = 0; u < RJ; ++u)
 #pragma unroll
             for (int v = 0; v < RR; ++v) ar[u][v] = ai[u][v] = 0.0;
-        const double2 *x[RJ];
+        const C *x[RJ];
 #pragma unroll
         for (int u = 0; u < RJ; ++u) x[u] = X + min(g * RJ + u, nj - 1) * P2 + n * n;
         for (int k = 0; k < w; ++k) {
-            const double *hrow = Hn + k * w;
-            double h[RR];
+            const R *hrow = Hn + k * w;
+            R h[RR];
 #pragma unroll
             for (int v = 0; v < RR; ++v) h[v] = (r0 + v < w) ? hrow[r0 + v] : 0.0;
 #pragma unroll
             for (int u = 0; u < RJ; ++u) {
-                const double2 xv = x[u][k];
+                const C xv = x[u][k];
 #pragma unroll
                 for (int v = 0; v < RR; ++v) {
                     ar[u][v] = fma(h[v], xv.x, ar[u][v]);
@@ -307,13 +326,13 @@ __global__ void __launch_bounds__(256) k_tw_rot(TransArgs a) {
         for (int u = 0; u < RJ; ++u) {
             const int j = g * RJ + u;
             if (j >= nj) break;
-            double2 *out = a.W1 + (t0 + j) * (int64_t)P2 + n * n;
+            C *out = a.W1 + (t0 + j) * (int64_t)P2 + n * n;
 #pragma unroll
             for (int v = 0; v < RR; ++v) {
                 const int q = r0 + v;
                 if (q >= w) break;
-                double2 val = cmk(ar[u][v], ai[u][v]);
-                if (!FWD) val = cmulc(val, a.ph[(int64_t)sdir[j] * phs + a.PH + (q - n)]);
+                C val = mkc<C>(ar[u][v], ai[u][v]);
+                if (!FWD) val = mulcc(val, a.ph[(int64_t)sdir[j] * phs + a.PH + (q - n)]);
                 out[q] = val;
             }
         }
@@ -321,10 +340,13 @@ __global__ void __launch_bounds__(256) k_tw_rot(TransArgs a) {
 }
 
 // coaxial step, whole vectors: items over (order m, row group) x job groups
-__global__ void __launch_bounds__(256) k_tw_coax(TransArgs a) {
-    extern __shared__ double2 lds[];
+template <class R>
+__global__ void __launch_bounds__(256) k_tw_coax(TransArgsT<R> a) {
+    using C = typename Cx<R>::T;
+    extern __shared__ double2 lds_raw[];
+    C *lds = (C *)lds_raw;
     const int JT = a.JT, P2 = a.P * a.P;
-    double2 *X = lds;  // JT x ps2
+    C *X = lds;  // JT x ps2
     const int64_t t0 = (int64_t)blockIdx.x * JT;
     const int nj = (int)min((int64_t)JT, a.njob - t0);
     const int ps2 = a.psrc * a.psrc, pt = a.ptgt;
@@ -333,7 +355,7 @@ __global__ void __launch_bounds__(256) k_tw_coax(TransArgs a) {
         X[j * ps2 + c] = a.W1[(t0 + j) * (int64_t)P2 + c];
     }
     __syncthreads();
-    const double2 *T = a.coax + (int64_t)a.tile_coax[blockIdx.x] * coax_table_size(a.PT);
+    const C *T = a.coax + (int64_t)a.tile_coax[blockIdx.x] * coax_table_size(a.PT);
     const int pm = min(a.psrc, a.ptgt);
     // items: orders m in -(pt-1)..pt-1, row groups ceil((pt-|m|)/RR)
     int nit = 0;
@@ -348,32 +370,32 @@ __global__ void __launch_bounds__(256) k_tw_coax(TransArgs a) {
             it -= c;
         }
         const int am = m < 0 ? -m : m, r0 = it * RR, rows = pt - am;
-        double ar[RJ][RR], ai[RJ][RR];
+        R ar[RJ][RR], ai[RJ][RR];
 #pragma unroll
         for (int u = 0; u < RJ; ++u)
 #pragma unroll
             for (int v = 0; v < RR; ++v) ar[u][v] = ai[u][v] = 0.0;
         if (am < pm) {
             const int B = a.PT - am;
-            const double2 *Tm = T + coax_block_off(a.PT, am);
-            const double2 *x[RJ];
+            const C *Tm = T + coax_block_off(a.PT, am);
+            const C *x[RJ];
 #pragma unroll
             for (int u = 0; u < RJ; ++u) x[u] = X + min(g * RJ + u, nj - 1) * ps2;
             for (int n = am; n < a.psrc; ++n) {
                 const int q = n - am;
-                const double2 *trow = Tm + (int64_t)q * B;
-                double2 tt[RR];
+                const C *trow = Tm + (int64_t)q * B;
+                C tt[RR];
 #pragma unroll
                 for (int v = 0; v < RR; ++v) {
                     const int rr = r0 + v;
-                    double2 tv = rr < rows ? trow[rr] : cmk(0, 0);
-                    if ((q + rr) & 1) tv = cmk(-tv.x, -tv.y);
+                    C tv = rr < rows ? trow[rr] : mkc<C>(0, 0);
+                    if ((q + rr) & 1) tv = mkc<C>(-tv.x, -tv.y);
                     tt[v] = tv;
                 }
                 const int c = n * n + n + m;
 #pragma unroll
                 for (int u = 0; u < RJ; ++u) {
-                    const double2 xv = x[u][c];
+                    const C xv = x[u][c];
 #pragma unroll
                     for (int v = 0; v < RR; ++v) {
                         ar[u][v] = fma(tt[v].x, xv.x, fma(-tt[v].y, xv.y, ar[u][v]));
@@ -386,27 +408,28 @@ __global__ void __launch_bounds__(256) k_tw_coax(TransArgs a) {
         for (int u = 0; u < RJ; ++u) {
             const int j = g * RJ + u;
             if (j >= nj) break;
-            double2 *out = a.W2 + (t0 + j) * (int64_t)P2;
+            C *out = a.W2 + (t0 + j) * (int64_t)P2;
 #pragma unroll
             for (int v = 0; v < RR; ++v) {
                 const int nn = am + r0 + v;
-                if (r0 + v < rows) out[nn * nn + nn + m] = cmk(ar[u][v], ai[u][v]);
+                if (r0 + v < rows) out[nn * nn + nn + m] = mkc<C>(ar[u][v], ai[u][v]);
             }
         }
     }
 }
 
 // dst[t] += sum of the job rows of target t (W1, P^2 per job); jobs of t listed in CSR order
+template <class C>
 __global__ void __launch_bounds__(256) k_tr_reduce(int64_t ntgt, int ptgt, int P, const int32_t *start,
-                                                   const int32_t *jobs, const double2 *W, double2 *dst) {
+                                                   const int32_t *jobs, const C *W, C *dst) {
     const int64_t t = blockIdx.x;
     if (t >= ntgt) return;
     const int j0 = start[t], j1 = start[t + 1];
     if (j0 == j1) return;
     const int pt2 = ptgt * ptgt;
     for (int c = threadIdx.x; c < pt2; c += blockDim.x) {
-        double2 s = dst[t * pt2 + c];
-        for (int q = j0; q < j1; ++q) s = cadd(s, W[(int64_t)jobs[q] * P * P + c]);
+        C s = dst[t * pt2 + c];
+        for (int q = j0; q < j1; ++q) s = addc(s, W[(int64_t)jobs[q] * P * P + c]);
         dst[t * pt2 + c] = s;
     }
 }
@@ -424,39 +447,52 @@ size_t trans_lds_bytes(int JT, int P, int whole) {
 }
 
 void trans_configure_lds(size_t lds_max) {
-    const void *f[] = {(const void *)k_tr_rot_fwd, (const void *)k_tr_coax, (const void *)k_tr_rot_back,
-                       (const void *)k_tw_rot<true>, (const void *)k_tw_rot<false>, (const void *)k_tw_coax};
+    const void *f[] = {(const void *)k_tr_rot_fwd<double>, (const void *)k_tr_coax<double>,
+                       (const void *)k_tr_rot_back<double>, (const void *)k_tw_rot<double, true>,
+                       (const void *)k_tw_rot<double, false>, (const void *)k_tw_coax<double>,
+                       (const void *)k_tr_rot_fwd<float>, (const void *)k_tr_coax<float>,
+                       (const void *)k_tr_rot_back<float>, (const void *)k_tw_rot<float, true>,
+                       (const void *)k_tw_rot<float, false>, (const void *)k_tw_coax<float>};
     for (auto fn : f) HIP_OK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max));
 }
 
 // One stage of a batch: 0 forward rotation, 1 coaxial step, 2 back rotation, 3 reduction into
 // the targets.  Returns the HIP kernel's name (for profiling).
-const char *trans_launch_stage(const TransBatch &b, int stage, const double2 *src, double2 *dst, const double2 *coax,
-                               const double2 *ph, int PH, double2 *W1, double2 *W2, hipStream_t st) {
-    TransArgs a{b.njob, b.JT, b.psrc, b.ptgt, b.P, b.PT, PH, src, dst, b.src, b.tgt, b.dir, b.tile_coax,
-                b.tile_rot, coax, b.H, b.HT, ph, W1, W2};
+template <class R>
+const char *trans_stage(const TransBatch &b, const TransTables<R> &tb, int stage, const typename Cx<R>::T *src,
+                        typename Cx<R>::T *dst, const typename Cx<R>::T *ph, int PH, typename Cx<R>::T *W1,
+                        typename Cx<R>::T *W2, hipStream_t st) {
+    TransArgsT<R> a{b.njob, b.JT, b.psrc, b.ptgt, b.P, b.PT, PH, src, dst, b.src, b.tgt, b.dir, b.tile_coax,
+                    b.tile_rot, tb.coax, tb.H, tb.HT, ph, W1, W2};
     const unsigned ntile = (unsigned)((b.njob + b.JT - 1) / b.JT);
-    const size_t lds = trans_lds_bytes(b.JT, b.P, b.whole);
+    // LDS sized for the scalar type
+    const size_t lds = trans_lds_bytes(b.JT, b.P, b.whole) / (sizeof(double) / sizeof(R));
+    const bool f32 = sizeof(R) == 4;
     const char *name = "";
     switch (stage) {
     case 0:
-        if (b.whole) k_tw_rot<true><<<ntile, 256, lds, st>>>(a), name = "k_tw_rot_fwd";
-        else k_tr_rot_fwd<<<dim3(ntile, b.psrc), 256, lds, st>>>(a), name = "k_tr_rot_fwd";
+        if (b.whole) k_tw_rot<R, true><<<ntile, 256, lds, st>>>(a), name = f32 ? "k_tw_rot_fwd_f32" : "k_tw_rot_fwd";
+        else k_tr_rot_fwd<R><<<dim3(ntile, b.psrc), 256, lds, st>>>(a), name = f32 ? "k_tr_rot_fwd_f32" : "k_tr_rot_fwd";
         break;
     case 1:
-        if (b.whole) k_tw_coax<<<ntile, 256, lds, st>>>(a), name = "k_tw_coax";
-        else k_tr_coax<<<dim3(ntile, 2 * b.P - 1), 256, lds, st>>>(a), name = "k_tr_coax";
+        if (b.whole) k_tw_coax<R><<<ntile, 256, lds, st>>>(a), name = f32 ? "k_tw_coax_f32" : "k_tw_coax";
+        else k_tr_coax<R><<<dim3(ntile, 2 * b.P - 1), 256, lds, st>>>(a), name = f32 ? "k_tr_coax_f32" : "k_tr_coax";
         break;
     case 2:
-        if (b.whole) k_tw_rot<false><<<ntile, 256, lds, st>>>(a), name = "k_tw_rot_back";
-        else k_tr_rot_back<<<dim3(ntile, b.ptgt), 256, lds, st>>>(a), name = "k_tr_rot_back";
+        if (b.whole) k_tw_rot<R, false><<<ntile, 256, lds, st>>>(a), name = f32 ? "k_tw_rot_back_f32" : "k_tw_rot_back";
+        else k_tr_rot_back<R><<<dim3(ntile, b.ptgt), 256, lds, st>>>(a), name = f32 ? "k_tr_rot_back_f32" : "k_tr_rot_back";
         break;
     default:
-        k_tr_reduce<<<(unsigned)b.ntgt, 256, 0, st>>>(b.ntgt, b.ptgt, b.P, b.tgt_start, b.tgt_jobs, W1, dst);
-        name = "k_tr_reduce";
+        k_tr_reduce<typename Cx<R>::T><<<(unsigned)b.ntgt, 256, 0, st>>>(b.ntgt, b.ptgt, b.P, b.tgt_start, b.tgt_jobs, W1, dst);
+        name = f32 ? "k_tr_reduce_f32" : "k_tr_reduce";
     }
     LAUNCH_OK();
     return name;
 }
+
+template const char *trans_stage<double>(const TransBatch &, const TransTables<double> &, int, const double2 *,
+                                         double2 *, const double2 *, int, double2 *, double2 *, hipStream_t);
+template const char *trans_stage<float>(const TransBatch &, const TransTables<float> &, int, const float2 *, float2 *,
+                                        const float2 *, int, float2 *, float2 *, hipStream_t);
 
 }  // namespace fmm

@@ -143,6 +143,46 @@ def test_matvec_fmm_vs_dense(F, cfg1_dense, leaf_max, lds_budget):
     ctx.close()
 
 
+@pytest.mark.parametrize("leaf_max,lds_budget", [(64, 0), (12, 0), (12, 8192)])
+def test_matvec_mixed_vs_dense(F, cfg1_dense, leaf_max, lds_budget):
+    """Mixed-precision product (FP32 near field and translations, FP64 tables converted once,
+    FP64 densities, P2M and L2P) against the oracle's dense operator: relative L2 <= 1e-4."""
+    room, k = cfg1_dense
+    ctx = make_ctx(F, room, k, leaf_max=leaf_max, lds_budget=lds_budget)
+    info = ctx.fmmbem_get_info()
+    L, M = bem.dense_LM(room.vertices, room.triangles, k, info.rc)
+    for seed in (1, 2):
+        x = synth.complex_normal(room.n, seed)
+        ref = 0.5 * x + M @ x - 1j * k * L @ (room.beta * x)
+        y = ctx.fmmbem_matvec(x, precision=F.FMMBEM_MIXED)[0]
+        err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+        print(f"mixed depth {info.depth} err {err:.3e}")
+        assert err < 1e-4
+    # the FP64 product is unaffected by a mixed one before it
+    y64 = ctx.fmmbem_matvec(x)[0]
+    assert np.linalg.norm(y64 - ref) / np.linalg.norm(ref) < 1e-6
+    with pytest.raises(RuntimeError):
+        ctx.fmmbem_matvec(x, precision=F.FMMBEM_MIXED, exact_far=True)
+    ctx.close()
+
+
+def test_solve_mixed_inner_vs_oracle_lu(F, cfg1_dense):
+    """FGMRES with mixed-precision Krylov products and FP64 restart residuals reaches a 1e-8
+    FP64 residual; the solution agrees with the oracle's LU solution."""
+    room, k = cfg1_dense
+    ctx = make_ctx(F, room, k)
+    rs, _ = synth.source_and_receivers(room, 4)
+    ctx.fmmbem_set_sources(rs)
+    x, rep, rc_ = ctx.fmmbem_solve(0, tol=1e-8, restart=40, maxit=400, precision=F.FMMBEM_MIXED)
+    print(f"mixed-inner solve: iters {rep.iters} restarts {rep.restarts} rel {rep.rel_res:.2e}")
+    assert rc_ == 0 and rep.rel_res < 1e-8
+    rc = ctx.fmmbem_get_info().rc
+    A, b, _, _ = bem.direct_system(room.vertices, room.triangles, k, room.beta, rs[0], rc)
+    x_ref = bem.solve_lu(A, b)
+    assert np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref) < 1e-5
+    ctx.close()
+
+
 def test_rhs_vs_oracle(F, cfg1_dense):
     room, k = cfg1_dense
     ctx = make_ctx(F, room, k)
@@ -175,8 +215,8 @@ def test_solve_and_field_vs_oracle_lu(F, cfg1_dense):
 
 @pytest.mark.parametrize("cfg,nrows", [(2, 96), (3, 64)])
 def test_matvec_fmm_sampled_rows_full_size(F, cfg, nrows):
-    """Full-size rooms (N = 90,972 at 1 kHz; N = 1,009,576 at 2.5 kHz): the FP64 FMM product on
-    seeded rows against the oracle's matrix-free rows, relative L2 <= 1e-6."""
+    """Full-size rooms (N = 90,972 at 1 kHz; N = 1,009,576 at 2.5 kHz): the FMM product on seeded
+    rows against the oracle's matrix-free rows, relative L2 <= 1e-6 in FP64 and <= 1e-4 mixed."""
     room, k = synth.config_room(cfg)
     ctx = make_ctx(F, room, k)
     info = ctx.fmmbem_get_info()
@@ -185,6 +225,10 @@ def test_matvec_fmm_sampled_rows_full_size(F, cfg, nrows):
     rows = np.random.default_rng(5).choice(room.n, nrows, replace=False)
     ref = bem.direct_matvec_rows(room.vertices, room.triangles, k, room.beta, info.rc, x, rows)
     err = np.linalg.norm(y[rows] - ref) / np.linalg.norm(ref)
-    print(f"cfg {cfg} N {room.n} depth {info.depth} p {list(info.p)[:info.depth + 1]} err {err:.3e}")
+    ym = ctx.fmmbem_matvec(x, precision=F.FMMBEM_MIXED)[0]
+    err_m = np.linalg.norm(ym[rows] - ref) / np.linalg.norm(ref)
+    print(f"cfg {cfg} N {room.n} depth {info.depth} p {list(info.p)[:info.depth + 1]} err {err:.3e} "
+          f"mixed {err_m:.3e}")
     assert err < 1e-6
+    assert err_m < 1e-4
     ctx.close()
