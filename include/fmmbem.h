@@ -144,6 +144,13 @@ typedef struct {
     int precision;     /* arithmetic of the inner products A z: FMMBEM_FP64 or FMMBEM_MIXED */
     double diag_shift; /* constant added to the diagonal in FMMBEM_PC_DIAG; default 0 */
     int use_x0;        /* nonzero: x holds the initial guess on entry */
+    /* Inner-outer scheme (Section 4.4: flexible GMRES preconditioned by a low-accuracy FMM
+     * GMRES).  inner_iters > 0: every outer preconditioner application runs up to inner_iters
+     * GMRES steps (no restart) on A z = v with products in inner_precision, preconditioned by
+     * `precond`, stopping early at relative residual inner_tol.  Default 0 (off), 1e-2, MIXED. */
+    int inner_iters;
+    double inner_tol;
+    int inner_precision;
 } fmmbem_solve_opts;
 
 typedef struct {
@@ -153,6 +160,9 @@ typedef struct {
     double t_setup_s;     /* setup seconds spent inside this call */
     double t_solve_s;     /* iteration seconds */
     int status;
+    int64_t matvecs_fp64;  /* FMM products of the call, by arithmetic (outer, restart and inner) */
+    int64_t matvecs_mixed;
+    int64_t inner_iters;   /* total inner GMRES steps */
 } fmmbem_solve_report;
 
 void fmmbem_default_solve_opts(fmmbem_solve_opts *o);
@@ -162,6 +172,10 @@ void fmmbem_default_solve_opts(fmmbem_solve_opts *o);
  * convergence, FMMBEM_ENOCONV at maxit (x still the best iterate), or an error. */
 int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, fmmbem_c64 *x,
                  fmmbem_solve_report *rep);
+
+/* Arnoldi estimate of the relative residual after each outer iteration of the last solve:
+ * *count receives the number of iterations, est[0..min(max,count)) the values. */
+int fmmbem_solve_history(fmmbem_ctx *ctx, int32_t max, double *est, int32_t *count);
 
 /* Total field at nr points inside the room from the solved surface field x of source isrc
  * (Eq. dbem1): psi(r) = G(r, r_s) + L[gamma + i k beta x](r) - M[x](r).  psi: nr values. */

@@ -44,10 +44,12 @@ __global__ void k_leaf_invert(int, const int32_t *, const int64_t *, double2 *, 
 __global__ void k_leaf_apply(int, const int32_t *, const int64_t *, const double2 *, const int32_t *,
                              const double2 *, double2 *);
 void box_center(const TreeHost &T, int l, uint64_t code, double *c);
-int fgmres(int64_t n, hipStream_t st, DeviceBuffers &scr, const std::function<void(const double2 *, double2 *)> &matvec,
+int fgmres(int64_t n, hipStream_t st, DeviceBuffers &scr, const char *tag,
+           const std::function<void(const double2 *, double2 *)> &matvec,
            const std::function<void(const double2 *, double2 *)> &matvec_check,
            const std::function<void(const double2 *, double2 *)> &precond, const double2 *b, double2 *x, double tol,
-           int m, int maxit, bool x0_given, int &iters, int &restarts, double &rel_res);
+           int m, int maxit, bool x0_given, bool final_residual, std::vector<double> *history, int &iters,
+           int &restarts, double &rel_res);
 
 // ------------------------------------------------------------------ setup pieces
 static int level_p(const fmmbem_options &o, double k, double side) {
@@ -755,6 +757,16 @@ void fmmbem_default_solve_opts(fmmbem_solve_opts *o) {
     o->precision = FMMBEM_FP64;
     o->diag_shift = 0.0;
     o->use_x0 = 0;
+    o->inner_iters = 0;
+    o->inner_tol = 1e-2;
+    o->inner_precision = FMMBEM_MIXED;
+}
+
+int fmmbem_solve_history(fmmbem_ctx *ctx, int32_t max, double *est, int32_t *count) {
+    if (!ctx || !count || (max > 0 && !est)) return FMMBEM_EINVAL;
+    *count = (int32_t)ctx->history.size();
+    for (int i = 0; i < max && i < *count; ++i) est[i] = ctx->history[i];
+    return FMMBEM_OK;
 }
 
 int fmmbem_create(fmmbem_ctx **out, int hip_device, const fmmbem_options *opt) {
@@ -991,6 +1003,9 @@ int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, f
     if (opts) o = *opts;
     if (o.restart < 1 || o.maxit < 0 || !(o.tol > 0)) return fail(ctx, FMMBEM_EINVAL, "bad solve options");
     if (o.precision != FMMBEM_FP64 && o.precision != FMMBEM_MIXED) return fail(ctx, FMMBEM_EINVAL, "unknown precision");
+    if (o.inner_iters < 0 || (o.inner_iters > 0 && !(o.inner_tol > 0)) ||
+        (o.inner_precision != FMMBEM_FP64 && o.inner_precision != FMMBEM_MIXED))
+        return fail(ctx, FMMBEM_EINVAL, "bad inner solve options");
     GUARD_BEGIN
     HIP_OK(hipSetDevice(ctx->device));
     if (ctx->src.empty()) return fail(ctx, FMMBEM_ENOTREADY, "sources not set");
@@ -1042,9 +1057,14 @@ int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, f
     rhs_dev(ctx, isrc, b);
     if (o.use_x0) HIP_OK(hipMemcpyAsync(dx, x, sizeof(double2) * n, hipMemcpyHostToDevice, st));
     // the Krylov products run in the requested arithmetic; restart residuals always in FP64
+    int64_t n64 = 0, nmx = 0;
+    auto product = [&](const double2 *a, double2 *y, bool mixed) {
+        matvec_dev(ctx, a, y, false, mixed);
+        ++(mixed ? nmx : n64);
+    };
     const bool mixed = o.precision == FMMBEM_MIXED;
-    auto mv = [&](const double2 *a, double2 *y) { matvec_dev(ctx, a, y, false, mixed); };
-    auto mv64 = [&](const double2 *a, double2 *y) { matvec_dev(ctx, a, y, false, false); };
+    auto mv = [&](const double2 *a, double2 *y) { product(a, y, mixed); };
+    auto mv64 = [&](const double2 *a, double2 *y) { product(a, y, false); };
     std::function<void(const double2 *, double2 *)> pc;
     if (o.precond == FMMBEM_PC_DIAG) {
         double2 *dinv = (double2 *)ctx->buf.find("pc_dinv");
@@ -1065,10 +1085,27 @@ int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, f
             HIP_OK(hipMemcpyAsync(z, v, sizeof(double2) * n, hipMemcpyDeviceToDevice, st));
         };
     }
+    // Inner-outer scheme (Section 4.4): the outer flexible GMRES is preconditioned by a short,
+    // low-accuracy GMRES on the same operator (inner_precision), itself preconditioned by `pc`.
+    std::function<void(const double2 *, double2 *)> outer_pc = pc;
+    int64_t inner_its = 0;
+    if (o.inner_iters > 0) {
+        const bool imixed = o.inner_precision == FMMBEM_MIXED;
+        outer_pc = [&, imixed](const double2 *v, double2 *z) {
+            auto imv = [&](const double2 *a, double2 *y) { product(a, y, imixed); };
+            int it = 0, rs = 0;
+            double rr = 1.0;
+            int s = fgmres(n, st, ctx->scratch, "in_", imv, imv, pc, v, z, o.inner_tol, o.inner_iters, o.inner_iters,
+                           false, false, nullptr, it, rs, rr);
+            if (s < 0) throw FmmError(s, "inner GMRES failed");
+            inner_its += it;
+        };
+    }
     int iters = 0, restarts = 0;
     double rel = 1.0;
-    int status = fgmres(n, st, ctx->scratch, mv, mv64, pc, b, dx, o.tol, o.restart, o.maxit, o.use_x0 != 0, iters,
-                        restarts, rel);
+    ctx->history.clear();
+    int status = fgmres(n, st, ctx->scratch, "", mv, mv64, outer_pc, b, dx, o.tol, o.restart, o.maxit, o.use_x0 != 0,
+                        true, &ctx->history, iters, restarts, rel);
     HIP_OK(hipMemcpyAsync(x, dx, sizeof(double2) * n, hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
     if (rep) {
@@ -1078,6 +1115,9 @@ int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, f
         rep->t_setup_s = t_before;
         rep->t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         rep->status = status;
+        rep->matvecs_fp64 = n64;
+        rep->matvecs_mixed = nmx;
+        rep->inner_iters = inner_its;
     }
     if (status < 0) ctx->err = "solver failed";
     return status;

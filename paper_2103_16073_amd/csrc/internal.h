@@ -191,6 +191,7 @@ struct fmmbem_ctx {
     int64_t near_nnz = 0;
     int64_t p2p_pairs = 0;
     bool precond_ready_nb = false, precond_ready_diag = false;
+    std::vector<double> history;  // Arnoldi residual estimate per outer iteration of the last solve
     bool mixed_ready = false;  // FP32 copies of the tables exist for the current wavenumber
     fmm::Timings last;
     double t_setup_last = 0.0;

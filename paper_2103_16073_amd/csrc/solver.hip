@@ -239,9 +239,10 @@ struct Blas {
     hipStream_t st;
     DeviceBuffers &scr;
     int64_t n;
+    std::string tag;  // scratch-name prefix, so nested solves keep separate buffers
     void dots(const double2 *V, int64_t ldv, int nv, const double2 *w, double2 *host_out) {
-        double2 *part = dget<double2>(scr, "dot_part", (size_t)DOT_BLOCKS * std::max(nv, 1));
-        double2 *res = dget<double2>(scr, "dot_res", std::max(nv, 1));
+        double2 *part = dget<double2>(scr, tag + "dot_part", (size_t)DOT_BLOCKS * std::max(nv, 1));
+        double2 *res = dget<double2>(scr, tag + "dot_res", std::max(nv, 1));
         int nblk = (int)std::min<int64_t>(DOT_BLOCKS, std::max<int64_t>(1, (n + 255) / 256));
         k_dot_partial<<<dim3(nblk, nv), 256, 0, st>>>(n, V, ldv, nv, w, part);
         LAUNCH_OK();
@@ -256,13 +257,13 @@ struct Blas {
         return sqrt(std::max(d.x, 0.0));
     }
     void sub_combo(const double2 *V, int64_t ldv, int nv, const double2 *h_host, double2 *w) {
-        double2 *h = dget<double2>(scr, "combo_h", std::max(nv, 1));
+        double2 *h = dget<double2>(scr, tag + "combo_h", std::max(nv, 1));
         HIP_OK(hipMemcpyAsync(h, h_host, sizeof(double2) * nv, hipMemcpyHostToDevice, st));
         k_sub_combo<<<ceil_div(n, 256), 256, 0, st>>>(n, V, ldv, nv, h, w);
         LAUNCH_OK();
     }
     void add_combo(const double2 *Z, int64_t ldz, int nv, const double2 *y_host, double2 *x) {
-        double2 *h = dget<double2>(scr, "combo_y", std::max(nv, 1));
+        double2 *h = dget<double2>(scr, tag + "combo_y", std::max(nv, 1));
         HIP_OK(hipMemcpyAsync(h, y_host, sizeof(double2) * nv, hipMemcpyHostToDevice, st));
         k_add_combo<<<ceil_div(n, 256), 256, 0, st>>>(n, Z, ldz, nv, h, x);
         LAUNCH_OK();
@@ -279,18 +280,24 @@ struct Blas {
 
 static inline double cabs_(double2 a) { return hypot(a.x, a.y); }
 
-// Restarted FGMRES(m).  matvec(x, y) and precond(v, z) act on device vectors of length n.
-// Returns FMMBEM_OK / FMMBEM_ENOCONV / error codes; rel_res is the true relative residual of the
-// last restart (computed with `matvec_check`, the FP64 operator).
-int fgmres(int64_t n, hipStream_t st, DeviceBuffers &scr, const std::function<void(const double2 *, double2 *)> &matvec,
+// Restarted FGMRES(m).  matvec(x, y) and precond(v, z) act on device vectors of length n; the
+// preconditioner may change from one call to the next (an inner solve, a learned map).
+// Returns FMMBEM_OK / FMMBEM_ENOCONV / error codes.  rel_res is the true relative residual of the
+// last restart, computed with `matvec_check` (the FP64 operator); with final_residual false, a
+// solve that stops at maxit skips that last product and reports the Arnoldi estimate instead
+// (inner solves).  history, when given, receives the estimate after every iteration.
+int fgmres(int64_t n, hipStream_t st, DeviceBuffers &scr, const char *tag,
+           const std::function<void(const double2 *, double2 *)> &matvec,
            const std::function<void(const double2 *, double2 *)> &matvec_check,
            const std::function<void(const double2 *, double2 *)> &precond, const double2 *b, double2 *x, double tol,
-           int m, int maxit, bool x0_given, int &iters, int &restarts, double &rel_res) {
-    Blas B{st, scr, n};
-    double2 *V = dget<double2>(scr, "fg_V", (size_t)(m + 1) * n);
-    double2 *Z = dget<double2>(scr, "fg_Z", (size_t)m * n);
-    double2 *w = dget<double2>(scr, "fg_w", n);
-    double2 *r = dget<double2>(scr, "fg_r", n);
+           int m, int maxit, bool x0_given, bool final_residual, std::vector<double> *history, int &iters,
+           int &restarts, double &rel_res) {
+    const std::string tg(tag);
+    Blas B{st, scr, n, tg};
+    double2 *V = dget<double2>(scr, tg + "fg_V", (size_t)(m + 1) * n);
+    double2 *Z = dget<double2>(scr, tg + "fg_Z", (size_t)m * n);
+    double2 *w = dget<double2>(scr, tg + "fg_w", n);
+    double2 *r = dget<double2>(scr, tg + "fg_r", n);
     if (!x0_given) HIP_OK(hipMemsetAsync(x, 0, sizeof(double2) * n, st));
     const double bn = B.nrm(b);
     iters = 0;
@@ -304,7 +311,12 @@ int fgmres(int64_t n, hipStream_t st, DeviceBuffers &scr, const std::function<vo
     std::vector<double2> H((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), h1(m + 1), h2(m + 1), y(m);
     auto Hc = [&](int i, int j) -> double2 & { return H[(size_t)i * m + j]; };
     int status = FMMBEM_ENOCONV;
+    double est = 1.0;
     while (true) {
+        if (!final_residual && restarts > 0 && iters >= maxit) {
+            rel_res = est;
+            break;
+        }
         // true residual
         if (x0_given || restarts > 0) {
             matvec_check(x, w);
@@ -360,7 +372,9 @@ int fgmres(int64_t n, hipStream_t st, DeviceBuffers &scr, const std::function<vo
             Hc(j + 1, j) = cmk(0, 0);
             g[j + 1] = cscale(cmul(cconj(sn[j]), g[j]), -1.0);
             g[j] = cscale(g[j], cs[j].x);
-            if (cabs_(g[j + 1]) / bn < tol || hn == 0) {
+            est = cabs_(g[j + 1]) / bn;
+            if (history) history->push_back(est);
+            if (est < tol || hn == 0) {
                 ++j;
                 done = true;
                 break;

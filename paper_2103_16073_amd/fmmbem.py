@@ -39,12 +39,14 @@ class Options(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("maxit", ctypes.c_int),
                 ("precond", ctypes.c_int), ("precision", ctypes.c_int), ("diag_shift", ctypes.c_double),
-                ("use_x0", ctypes.c_int)]
+                ("use_x0", ctypes.c_int), ("inner_iters", ctypes.c_int), ("inner_tol", ctypes.c_double),
+                ("inner_precision", ctypes.c_int)]
 
 
 class SolveReport(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("restarts", ctypes.c_int), ("rel_res", ctypes.c_double),
-                ("t_setup_s", ctypes.c_double), ("t_solve_s", ctypes.c_double), ("status", ctypes.c_int)]
+                ("t_setup_s", ctypes.c_double), ("t_solve_s", ctypes.c_double), ("status", ctypes.c_int),
+                ("matvecs_fp64", ctypes.c_int64), ("matvecs_mixed", ctypes.c_int64), ("inner_iters", ctypes.c_int64)]
 
 
 class Info(ctypes.Structure):
@@ -74,6 +76,8 @@ EXPORTS = {
     "fmmbem_setup": (ctypes.c_int, [ctypes.c_void_p]),
     "fmmbem_num_unknowns": (ctypes.c_int64, [ctypes.c_void_p]),
     "fmmbem_rhs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "fmmbem_solve_history": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                            ctypes.POINTER(ctypes.c_int32)]),
     "fmmbem_matvec": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
     "fmmbem_matvec_dev": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
     "fmmbem_default_solve_opts": (None, [ctypes.POINTER(SolveOpts)]),
@@ -212,6 +216,13 @@ class Context:
         rep = SolveReport()
         rc = self._check(lib().fmmbem_solve(self.h, isrc, ctypes.byref(o), _ptr(x), ctypes.byref(rep)))
         return x, rep, rc
+
+    def fmmbem_solve_history(self):
+        cnt = ctypes.c_int32()
+        self._check(lib().fmmbem_solve_history(self.h, 0, None, ctypes.byref(cnt)))
+        out = np.empty(cnt.value, np.float64)
+        self._check(lib().fmmbem_solve_history(self.h, cnt.value, _ptr(out), ctypes.byref(cnt)))
+        return out
 
     def fmmbem_eval_field(self, isrc, pts, x):
         pts = np.ascontiguousarray(np.atleast_2d(pts), np.float64)

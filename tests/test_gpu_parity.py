@@ -183,6 +183,28 @@ def test_solve_mixed_inner_vs_oracle_lu(F, cfg1_dense):
     ctx.close()
 
 
+def test_solve_inner_outer_vs_oracle_lu(F, cfg1_dense):
+    """Flexible GMRES preconditioned by an inner mixed-precision GMRES (Section 4.4): converges
+    to the FP64 residual target, agrees with LU, and counts its products by arithmetic."""
+    room, k = cfg1_dense
+    ctx = make_ctx(F, room, k)
+    rs, _ = synth.source_and_receivers(room, 4)
+    ctx.fmmbem_set_sources(rs)
+    x, rep, rc_ = ctx.fmmbem_solve(0, tol=1e-8, restart=20, maxit=60, inner_iters=8, inner_tol=1e-3,
+                                   precision=F.FMMBEM_FP64)
+    hist = ctx.fmmbem_solve_history()
+    print(f"inner-outer: outer {rep.iters} inner {rep.inner_iters} fp64 {rep.matvecs_fp64} "
+          f"mixed {rep.matvecs_mixed} rel {rep.rel_res:.2e}")
+    assert rc_ == 0 and rep.rel_res < 1e-8
+    assert len(hist) == rep.iters and rep.matvecs_mixed == rep.inner_iters > 0
+    assert rep.matvecs_fp64 == rep.iters + rep.restarts
+    rc = ctx.fmmbem_get_info().rc
+    A, b, _, _ = bem.direct_system(room.vertices, room.triangles, k, room.beta, rs[0], rc)
+    x_ref = bem.solve_lu(A, b)
+    assert np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref) < 1e-5
+    ctx.close()
+
+
 def test_rhs_vs_oracle(F, cfg1_dense):
     room, k = cfg1_dense
     ctx = make_ctx(F, room, k)
