@@ -90,6 +90,11 @@ typedef struct {
     int max_depth;       /* cap on the octree depth; default 12 */
     int lds_budget;      /* LDS bytes per workgroup for translation tiles (0 = 64 KiB); larger tiles
                             share tables more but leave fewer workgroups per compute unit */
+    int graphs;          /* nonzero: products on device vectors (solves, fmmbem_matvec_dev) replay a
+                            captured HIP graph per (vector count, precision) through staging
+                            buffers; per-phase timings then report only the total.  default 1 */
+    int autotune;        /* nonzero: at setup, time each translation batch under the candidate tile
+                            shapes and keep the fastest (adds setup time); default 0 */
 } fmmbem_options;
 
 void fmmbem_default_options(fmmbem_options *opt);
@@ -172,6 +177,21 @@ void fmmbem_default_solve_opts(fmmbem_solve_opts *o);
  * convergence, FMMBEM_ENOCONV at maxit (x still the best iterate), or an error. */
 int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, fmmbem_c64 *x,
                  fmmbem_solve_report *rep);
+
+/* Solve the systems of ns sources together (batching): isrc[s] names the source of system s;
+ * x is ns*N (in: initial guesses if use_x0; out: solutions), rep has ns entries.  The systems
+ * run FGMRES in lock step and every step applies one product to all systems still iterating
+ * (kernel evaluations, expansions' basis functions and translation tables shared).  Each
+ * system converges, restarts and stops on its own; rep[s].t_solve_s and the product counts
+ * are those of the whole batch.  Returns FMMBEM_OK when every system converged, else the
+ * first failure or FMMBEM_ENOCONV.  inner_iters must be 0. */
+int fmmbem_solve_batch(fmmbem_ctx *ctx, int32_t ns, const int32_t *isrc, const fmmbem_solve_opts *opts,
+                       fmmbem_c64 *x, fmmbem_solve_report *rep);
+
+/* Free the per-call work arrays (Krylov bases, translation work rows, staging) now rather
+ * than at fmmbem_destroy; they are allocated again when next needed.  Captured product graphs
+ * are dropped with them. */
+int fmmbem_release_workspace(fmmbem_ctx *ctx);
 
 /* Arnoldi estimate of the relative residual after each outer iteration of the last solve:
  * *count receives the number of iterations, est[0..min(max,count)) the values. */

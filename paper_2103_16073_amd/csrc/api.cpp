@@ -16,22 +16,25 @@ __global__ void k_near_fill(int64_t, const int32_t *, const int32_t *, const int
                             const double4 *, double, const int32_t *, int32_t *, int32_t *);
 __global__ void k_near_quad(int64_t, const int32_t *, const int32_t *, const double4 *, const double *, double,
                             double2 *, double2 *);
-__global__ void k_densities(int64_t, const int32_t *, const double2 *, const double2 *, double, double2 *, double2 *);
+__global__ void k_densities(int64_t, int, const int32_t *, const double2 *, const double2 *, double, double2 *,
+                            double2 *);
 __global__ void k_gamma(int64_t, const double4 *, const double4 *, const double2 *, double, double, double, double,
                         double2, double2 *, double2 *);
-__global__ void k_p2p(int, const int32_t *, const int32_t *, const int32_t *, int, const double4 *, const double4 *,
-                      const double2 *, const double2 *, double, double, const int32_t *, const int32_t *,
-                      const double2 *, const double2 *, double2 *);
-__global__ void k_p2p32(int, const int32_t *, const int32_t *, const int32_t *, const double4 *, const double4 *,
-                        const double2 *, const double2 *, double, double, const int32_t *, const int32_t *,
-                        const float2 *, const float2 *, double2 *);
+__global__ void k_zero8(int64_t, uint64_t *);
+void launch_p2p(int nr, bool fp32, int nleaf, const int32_t *leaf_start, const int32_t *nbr_start,
+                const int32_t *nbr_list, int all_leaves, const double4 *ec, const double4 *en, const double2 *sigma,
+                const double2 *mu, double k, double rc2, const int32_t *near_start, const int32_t *near_col,
+                const void *nL, const void *nM, double2 *y, hipStream_t st);
+size_t p2m_stage_bytes(int nr, int p);
+void launch_p2m(int nr, int nleaf, int p, int CH, const int32_t *leaf_start, const double4 *center,
+                const double4 *ec, const double4 *en, const double2 *sigma, const double2 *mu, double k,
+                double2 *Mout, hipStream_t st);
+void launch_l2p(int nr, int nleaf, int p, const int32_t *leaf_start, const double4 *center, const double4 *ec,
+                const double2 *Lc, double k, const double2 *ynear, double half, const int32_t *perm, int64_t n,
+                const double2 *x, double2 *y, int has_far, hipStream_t st);
 __global__ void k_cvt_d2f(int64_t, const double2 *, float2 *);
 __global__ void k_cvt_f2d(int64_t, const float2 *, double2 *);
 __global__ void k_cvt_real_d2f(int64_t, const double *, float *);
-__global__ void k_p2m(int, int, int, const int32_t *, const double4 *, const double4 *, const double4 *,
-                      const double2 *, const double2 *, double, double2 *);
-__global__ void k_l2p(int, int, const int32_t *, const double4 *, const double4 *, const double2 *, double,
-                      const double2 *, double, const int32_t *, const double2 *, double2 *, int);
 __global__ void k_field(int64_t, const double *, const double4 *, const double4 *, const double *, const double2 *,
                         const double2 *, double, double, double, double, double, double2, double2 *);
 __global__ void k_diag_inv(int64_t, const int32_t *, const int32_t *, const int32_t *, const double2 *,
@@ -44,12 +47,20 @@ __global__ void k_leaf_invert(int, const int32_t *, const int64_t *, double2 *, 
 __global__ void k_leaf_apply(int, const int32_t *, const int64_t *, const double2 *, const int32_t *,
                              const double2 *, double2 *);
 void box_center(const TreeHost &T, int l, uint64_t code, double *c);
+int fgmres_batch(int64_t n, hipStream_t st, DeviceBuffers &scr, int nv,
+                 const std::function<void(int, const double2 *, double2 *)> &matvec,
+                 const std::function<void(int, const double2 *, double2 *)> &matvec_check,
+                 const std::function<void(const double2 *, double2 *)> &precond, const double2 *B, double2 *X,
+                 double tol, int m, int maxit, bool x0_given, std::vector<int> &iters, std::vector<int> &restarts,
+                 std::vector<double> &rel_res, std::vector<int> &status);
 int fgmres(int64_t n, hipStream_t st, DeviceBuffers &scr, const char *tag,
            const std::function<void(const double2 *, double2 *)> &matvec,
            const std::function<void(const double2 *, double2 *)> &matvec_check,
            const std::function<void(const double2 *, double2 *)> &precond, const double2 *b, double2 *x, double tol,
            int m, int maxit, bool x0_given, bool final_residual, std::vector<double> *history, int &iters,
            int &restarts, double &rel_res);
+
+void drop_graphs(fmmbem_ctx *c);
 
 // ------------------------------------------------------------------ setup pieces
 static int level_p(const fmmbem_options &o, double k, double side) {
@@ -363,6 +374,8 @@ static void setup_k(fmmbem_ctx *c) {
         D.M = dget<double2>(c->buf, s + "M", (size_t)D.nbox * p * p);
         D.L = dget<double2>(c->buf, s + "L", (size_t)D.nbox * p * p);
     }
+    c->nr_cap = 1;
+    c->nr_cap32 = 0;
     build_coax_tables(jobs, c->scratch, st);
     build_batches(c);
     // near-field table
@@ -400,6 +413,7 @@ static void ensure_setup(fmmbem_ctx *c) {
     if (!c->have_k) throw FmmError(FMMBEM_ENOTREADY, "wavenumber not set");
     auto t0 = std::chrono::steady_clock::now();
     bool any = c->mesh_dirty || c->k_dirty || c->beta_dirty;
+    if (any) drop_graphs(c);
     if (c->mesh_dirty) {
         setup_mesh(c);
         c->k_dirty = true;
@@ -482,21 +496,21 @@ static double coax_flops(int ps, int pt) {
 // ------------------------------------------------------------------ the FMM pass
 // Staged translation of a batch of jobs (grouped by target) from `src` (psrc) into `dst` (ptgt).
 template <class R>
-static void run_batch(fmmbem_ctx *c, const TransBatch &b, const typename Cx<R>::T *src, typename Cx<R>::T *dst,
-                      const TransTables<R> &tb, const typename Cx<R>::T *ph) {
+static void run_batch(fmmbem_ctx *c, int nrv, const TransBatch &b, const typename Cx<R>::T *src,
+                      typename Cx<R>::T *dst, const TransTables<R> &tb, const typename Cx<R>::T *ph) {
     using C = typename Cx<R>::T;
     if (b.njob == 0) return;
     hipStream_t st = c->stream;
-    C *W1 = (C *)c->scratch.get("W1", sizeof(C) * (size_t)b.njob * b.P * b.P);
-    C *W2 = (C *)c->scratch.get("W2", sizeof(C) * (size_t)b.njob * b.P * b.P);
-    const double nr = (double)b.nreal, P2 = (double)b.P * b.P, cs = (double)sizeof(C);
+    C *W1 = (C *)c->scratch.get("W1", sizeof(C) * (size_t)b.njob * nrv * b.P * b.P);
+    C *W2 = (C *)c->scratch.get("W2", sizeof(C) * (size_t)b.njob * nrv * b.P * b.P);
+    const double nr = (double)b.nreal * nrv, P2 = (double)b.P * b.P, cs = (double)sizeof(C);
     // algorithmic work per stage: flops of the matrices applied; bytes of the rows moved once
     const double fl[4] = {nr * rot_flops(b.psrc), nr * coax_flops(b.psrc, b.ptgt), nr * rot_flops(b.ptgt), nr * P2 * 2};
     const double by[4] = {nr * cs * (b.psrc * b.psrc + P2), nr * cs * 2 * P2, nr * cs * 2 * P2,
-                          cs * (nr * P2 + 2.0 * b.ntgt * b.ptgt * b.ptgt)};
+                          cs * (nr * P2 + 2.0 * b.ntgt * nrv * b.ptgt * b.ptgt)};
     for (int stage = 0; stage < 4; ++stage) {
         int e = prof_begin(c);
-        const char *name = trans_stage<R>(b, tb, stage, src, dst, ph, c->delta_p, W1, W2, st);
+        const char *name = trans_stage<R>(b, tb, stage, nrv, src, dst, ph, c->delta_p, W1, W2, st);
         prof_end(c, e, name, fl[stage], by[stage]);
     }
 }
@@ -542,8 +556,6 @@ static void ensure_mixed(fmmbem_ctx *c) {
             D.coax_up32 = dget<float2>(c->buf, s + "coax_up32", coax_table_size(PT));
             convert(c, coax_table_size(PT), (const double2 *)D.coax_up, D.coax_up32);
         }
-        D.M32 = dget<float2>(c->buf, s + "M32", (size_t)D.nbox * p * p);
-        D.L32 = dget<float2>(c->buf, s + "L32", (size_t)D.nbox * p * p);
         TransBatch *bs[3] = {&D.m2l, &D.up, &D.down};
         const char *nm3[3] = {"m2l", "up", "down"};
         for (int q = 0; q < 3; ++q) {
@@ -566,9 +578,45 @@ static void ensure_mixed(fmmbem_ctx *c) {
     c->mixed_ready = true;
 }
 
-// y (caller order) = half * x + L[sigma] + M[mu] at the centroids; sigma/mu in sorted order.
-static void fmm_pass(fmmbem_ctx *c, const double2 *sigma, const double2 *mu, const double2 *x, double half, double2 *y,
-                     bool exact_far, bool mixed = false) {
+// Zero a device range with a fill kernel (safe inside captured graphs, unlike memset nodes).
+static void zero_dev(fmmbem_ctx *c, void *ptr, size_t bytes) {
+    if (bytes == 0) return;
+    if (bytes % 8) throw FmmError(FMMBEM_EINVAL, "zero_dev: size not a multiple of 8 bytes");
+    const int64_t n8 = (int64_t)(bytes / 8);
+    k_zero8<<<ceil_div(n8, 256), 256, 0, c->stream>>>(n8, (uint64_t *)ptr);
+    LAUNCH_OK();
+}
+
+static void rec(fmmbem_ctx *c, int i) {
+    if (!c->capturing) HIP_OK(hipEventRecord(c->ev[i], c->stream));
+}
+
+// Expansion arrays hold nr vectors per box (vector-inner); grow them when more are asked for.
+static void ensure_nr(fmmbem_ctx *c, int nr, bool mixed) {
+    if (nr <= c->nr_cap && (!mixed || nr <= c->nr_cap32)) return;
+    if (c->capturing) throw FmmError(FMMBEM_EINVAL, "expansion storage must exist before graph capture");
+    drop_graphs(c);
+    for (int l = 2; l <= c->tree.depth; ++l) {
+        LevelDev &D = c->lev[l];
+        std::string s = "L" + std::to_string(l) + "_";
+        const size_t cnt = (size_t)D.nbox * nr * D.p * D.p;
+        if (nr > c->nr_cap) {
+            D.M = dget<double2>(c->buf, s + "M", cnt);
+            D.L = dget<double2>(c->buf, s + "L", cnt);
+        }
+        if (mixed) {
+            D.M32 = dget<float2>(c->buf, s + "M32", cnt);
+            D.L32 = dget<float2>(c->buf, s + "L32", cnt);
+        }
+    }
+    c->nr_cap = std::max(c->nr_cap, nr);
+    if (mixed) c->nr_cap32 = std::max(c->nr_cap32, nr);
+}
+
+// y (caller order, nr x N) = half * x + L[sigma] + M[mu] at the centroids; sigma/mu in tree
+// order with the nr vectors interleaved.
+static void fmm_pass(fmmbem_ctx *c, int nr, const double2 *sigma, const double2 *mu, const double2 *x, double half,
+                     double2 *y, bool exact_far, bool mixed = false) {
     TreeHost &T = c->tree;
     const int L = T.depth;
     hipStream_t st = c->stream;
@@ -576,111 +624,169 @@ static void fmm_pass(fmmbem_ctx *c, const double2 *sigma, const double2 *mu, con
     const int nleaf = (int)T.leaf_start.size() - 1;
     auto I32 = [&](const char *s) { return (int32_t *)c->buf.find(s); };
     const double4 *ec = (double4 *)c->buf.find("ec"), *en = (double4 *)c->buf.find("en");
-    double2 *ynear = dget<double2>(c->scratch, "ynear", n);
-    HIP_OK(hipEventRecord(c->ev[1], st));
+    double2 *ynear = dget<double2>(c->scratch, "ynear", (size_t)n * nr);
+    ensure_nr(c, nr, mixed);
+    rec(c, 1);
     int pe = prof_begin(c);
-    if (mixed) {
-        k_p2p32<<<nleaf, 64, 0, st>>>(nleaf, I32("leaf_start"), I32("nbr_start"), I32("nbr_list"), ec, en, sigma, mu, c->k,
-                                      c->rc * c->rc, I32("near_start"), I32("near_col"),
-                                      (float2 *)c->buf.find("near_L32"), (float2 *)c->buf.find("near_M32"), ynear);
-        LAUNCH_OK();
-        prof_end(c, pe, "k_p2p32", 40.0 * c->p2p_pairs + 16.0 * c->near_nnz,
-                 80.0 * n + 32.0 * n + 16.0 * n + 24.0 * c->near_nnz);
-    } else {
-    k_p2p<<<nleaf, 64, 0, st>>>(nleaf, I32("leaf_start"), I32("nbr_start"), I32("nbr_list"), exact_far ? 1 : 0, ec, en,
-                                sigma, mu, c->k, c->rc * c->rc, I32("near_start"), I32("near_col"),
-                                (double2 *)c->buf.find("near_L"), (double2 *)c->buf.find("near_M"), ynear);
-    LAUNCH_OK();
     {
-        // one-point pairs: ~40 flops each (sincos counted as 20); bytes: element data, densities,
-        // near table and output, each read once
-        double pairs = exact_far ? (double)n * n : (double)c->p2p_pairs;
-        prof_end(c, pe, "k_p2p", 40.0 * pairs + 16.0 * c->near_nnz, 80.0 * n + 32.0 * n + 16.0 * n + 40.0 * c->near_nnz);
+        const double pairs = exact_far ? (double)n * n : (double)c->p2p_pairs;
+        launch_p2p(nr, mixed, nleaf, I32("leaf_start"), I32("nbr_start"), I32("nbr_list"), exact_far ? 1 : 0, ec, en,
+                   sigma, mu, c->k, c->rc * c->rc, I32("near_start"), I32("near_col"),
+                   c->buf.find(mixed ? "near_L32" : "near_L"), c->buf.find(mixed ? "near_M32" : "near_M"), ynear, st);
+        // one-point pairs: ~40 flops each (sincos counted as 20), kernel shared by the nr vectors;
+        // bytes: element data, densities, near table and output, each read once
+        const double tb = mixed ? 16.0 : 32.0;
+        prof_end(c, pe, mixed ? "k_p2p32" : "k_p2p", (40.0 + 16.0 * (nr - 1)) * pairs + 16.0 * nr * c->near_nnz,
+                 80.0 * n + 48.0 * n * nr + (8.0 + tb) * c->near_nnz);
     }
-    }
-    HIP_OK(hipEventRecord(c->ev[2], st));
+    rec(c, 2);
     if (!exact_far) {
         LevelDev &LL = c->lev[L];
         const int p = LL.p;
-        const int TB = (p + 1) * (p + 2) / 2;
-        const int per = TB * 16 + (p + 2) * 8 + 88;
+        const size_t per = p2m_stage_bytes(nr, p);
         if (per > 60000) throw FmmError(FMMBEM_EINVAL, "leaf truncation number too large for P2M staging");
-        int CH = std::max(1, std::min(32, 60000 / per));
-        size_t sh = (size_t)CH * per;
+        const int CH = (int)std::max<size_t>(1, std::min<size_t>(32, 60000 / per));
+        const size_t pp = (size_t)p * p;
         pe = prof_begin(c);
-        k_p2m<<<nleaf, 256, sh, st>>>(nleaf, p, CH, I32("leaf_start"), LL.center, ec, en, sigma, mu, c->k, LL.M);
-        LAUNCH_OK();
-        prof_end(c, pe, "k_p2m", (double)n * p * p * 2 * 8.0, 112.0 * n + 16.0 * nleaf * p * p);
-        HIP_OK(hipEventRecord(c->ev[3], st));
+        launch_p2m(nr, nleaf, p, CH, I32("leaf_start"), LL.center, ec, en, sigma, mu, c->k, LL.M, st);
+        prof_end(c, pe, "k_p2m", (double)n * pp * 2 * 8.0 * nr, 112.0 * n + 32.0 * n * nr + 16.0 * nleaf * pp * nr);
+        rec(c, 3);
         if (mixed) {
             // FP32 translations between an FP64 P2M and an FP64 L2P
             const float2 *ph32 = (float2 *)c->buf.find("phA32");
             pe = prof_begin(c);
-            convert(c, (int64_t)LL.nbox * p * p, (const double2 *)LL.M, LL.M32);
-            prof_end(c, pe, "k_cvt", 0.0, 24.0 * LL.nbox * p * p);
+            convert(c, (int64_t)LL.nbox * nr * pp, (const double2 *)LL.M, LL.M32);
+            prof_end(c, pe, "k_cvt", 0.0, 24.0 * LL.nbox * pp * nr);
             for (int l = L - 1; l >= 2; --l) {
                 LevelDev &P_ = c->lev[l], &C_ = c->lev[l + 1];
-                HIP_OK(hipMemsetAsync(P_.M32, 0, sizeof(float2) * P_.nbox * P_.p * P_.p, st));
-                run_batch<float>(c, P_.up, C_.M32, P_.M32, tables32(P_.up, P_.coax_up32), ph32);
+                zero_dev(c, P_.M32, sizeof(float2) * P_.nbox * nr * P_.p * P_.p);
+                run_batch<float>(c, nr, P_.up, C_.M32, P_.M32, tables32(P_.up, P_.coax_up32), ph32);
             }
-            HIP_OK(hipEventRecord(c->ev[4], st));
+            rec(c, 4);
             for (int l = 2; l <= L; ++l) {
                 LevelDev &D = c->lev[l];
-                HIP_OK(hipMemsetAsync(D.L32, 0, sizeof(float2) * D.nbox * D.p * D.p, st));
-                run_batch<float>(c, D.m2l, D.M32, D.L32, tables32(D.m2l, D.coax_m2l32), ph32);
+                zero_dev(c, D.L32, sizeof(float2) * D.nbox * nr * D.p * D.p);
+                run_batch<float>(c, nr, D.m2l, D.M32, D.L32, tables32(D.m2l, D.coax_m2l32), ph32);
                 if (l >= 3) {
                     LevelDev &P_ = c->lev[l - 1];
-                    run_batch<float>(c, P_.down, P_.L32, D.L32, tables32(P_.down, P_.coax_up32), ph32);
+                    run_batch<float>(c, nr, P_.down, P_.L32, D.L32, tables32(P_.down, P_.coax_up32), ph32);
                 }
             }
             pe = prof_begin(c);
-            convert(c, (int64_t)LL.nbox * p * p, (const float2 *)LL.L32, LL.L);
-            prof_end(c, pe, "k_cvt", 0.0, 24.0 * LL.nbox * p * p);
+            convert(c, (int64_t)LL.nbox * nr * pp, (const float2 *)LL.L32, LL.L);
+            prof_end(c, pe, "k_cvt", 0.0, 24.0 * LL.nbox * pp * nr);
         } else {
             const double2 *ph = (double2 *)c->buf.find("phA");
             // M2M up
             for (int l = L - 1; l >= 2; --l) {
                 LevelDev &P_ = c->lev[l], &C_ = c->lev[l + 1];
-                HIP_OK(hipMemsetAsync(P_.M, 0, sizeof(double2) * P_.nbox * P_.p * P_.p, st));
-                run_batch<double>(c, P_.up, C_.M, P_.M, tables64(P_.up, P_.coax_up), ph);
+                zero_dev(c, P_.M, sizeof(double2) * P_.nbox * nr * P_.p * P_.p);
+                run_batch<double>(c, nr, P_.up, C_.M, P_.M, tables64(P_.up, P_.coax_up), ph);
             }
-            HIP_OK(hipEventRecord(c->ev[4], st));
+            rec(c, 4);
             // M2L and L2L down
             for (int l = 2; l <= L; ++l) {
                 LevelDev &D = c->lev[l];
-                HIP_OK(hipMemsetAsync(D.L, 0, sizeof(double2) * D.nbox * D.p * D.p, st));
-                run_batch<double>(c, D.m2l, D.M, D.L, tables64(D.m2l, D.coax_m2l), ph);
+                zero_dev(c, D.L, sizeof(double2) * D.nbox * nr * D.p * D.p);
+                run_batch<double>(c, nr, D.m2l, D.M, D.L, tables64(D.m2l, D.coax_m2l), ph);
                 if (l >= 3) {
                     LevelDev &P_ = c->lev[l - 1];
-                    run_batch<double>(c, P_.down, P_.L, D.L, tables64(P_.down, P_.coax_up), ph);
+                    run_batch<double>(c, nr, P_.down, P_.L, D.L, tables64(P_.down, P_.coax_up), ph);
                 }
             }
         }
-        HIP_OK(hipEventRecord(c->ev[5], st));
+        rec(c, 5);
     } else {
-        for (int e = 3; e <= 5; ++e) HIP_OK(hipEventRecord(c->ev[e], st));
+        for (int e = 3; e <= 5; ++e) rec(c, e);
     }
-    HIP_OK(hipEventRecord(c->ev[6], st));
+    rec(c, 6);
     LevelDev &LL = c->lev[L];
     pe = prof_begin(c);
-    k_l2p<<<nleaf, 64, (size_t)64 * (LL.p + 2) * sizeof(double), st>>>(
-        nleaf, LL.p, I32("leaf_start"), LL.center, ec, LL.L, c->k, ynear, half, I32("perm"), x, y, exact_far ? 0 : 1);
-    LAUNCH_OK();
-    prof_end(c, pe, "k_l2p", (double)n * LL.p * LL.p * 8.0, 32.0 * n + 16.0 * n * 3 + 16.0 * nleaf * LL.p * LL.p);
-    HIP_OK(hipEventRecord(c->ev[7], st));
+    launch_l2p(nr, nleaf, LL.p, I32("leaf_start"), LL.center, ec, LL.L, c->k, ynear, half, I32("perm"), n, x, y,
+               exact_far ? 0 : 1, st);
+    prof_end(c, pe, "k_l2p", (double)n * LL.p * LL.p * 8.0 * nr,
+             32.0 * n + 16.0 * n * 3 * nr + 16.0 * nleaf * LL.p * LL.p * nr);
+    rec(c, 7);
 }
 
-static void matvec_dev(fmmbem_ctx *c, const double2 *x, double2 *y, bool exact_far, bool mixed = false) {
+// y = A x for nr vectors (x, y: nr x N device arrays, caller order), nr in {1, 2, 4}
+static void matvec_chunk(fmmbem_ctx *c, int nr, const double2 *x, double2 *y, bool exact_far, bool mixed) {
     hipStream_t st = c->stream;
     const int64_t n = c->nt;
-    double2 *sigma = dget<double2>(c->scratch, "sigma", n), *mu = dget<double2>(c->scratch, "mu", n);
-    HIP_OK(hipEventRecord(c->ev[0], st));
-    k_densities<<<ceil_div(n, 256), 256, 0, st>>>(n, (int32_t *)c->buf.find("perm"), x, (double2 *)c->buf.find("beta"),
-                                                  c->k, sigma, mu);
+    double2 *sigma = dget<double2>(c->scratch, "sigma", (size_t)n * nr);
+    double2 *mu = dget<double2>(c->scratch, "mu", (size_t)n * nr);
+    rec(c, 0);
+    k_densities<<<ceil_div(n * nr, 256), 256, 0, st>>>(n, nr, (int32_t *)c->buf.find("perm"), x,
+                                                       (double2 *)c->buf.find("beta"), c->k, sigma, mu);
     LAUNCH_OK();
     if (mixed) ensure_mixed(c);
-    fmm_pass(c, sigma, mu, x, 0.5, y, exact_far, mixed);
-    HIP_OK(hipEventRecord(c->ev[8], st));
+    fmm_pass(c, nr, sigma, mu, x, 0.5, y, exact_far, mixed);
+    rec(c, 8);
+}
+
+// ------------------------------------------------------------------ captured products
+void drop_graphs(fmmbem_ctx *c) {
+    for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+    c->graphs.clear();
+}
+
+// One product of nr vectors by replaying a HIP graph captured on the staging buffers g_x/g_y.
+// The graph is (re)captured when none exists for (nr, precision) or when a buffer it refers
+// to has been freed since (the buffers' generation counters moved).
+static void matvec_graph(fmmbem_ctx *c, int nr, const double2 *x, double2 *y, bool mixed) {
+    hipStream_t st = c->stream;
+    const int64_t n = c->nt;
+    double2 *gx = dget<double2>(c->scratch, "g_x", (size_t)n * 4), *gy = dget<double2>(c->scratch, "g_y", (size_t)n * 4);
+    const size_t bytes = sizeof(double2) * n * nr;
+    HIP_OK(hipMemcpyAsync(gx, x, bytes, hipMemcpyDeviceToDevice, st));
+    fmmbem_ctx::GraphEntry *g = nullptr;
+    for (auto &e : c->graphs)
+        if (e.nr == nr && e.mixed == mixed) g = &e;
+    if (g && (g->gen_buf != c->buf.gen || g->gen_scr != c->scratch.gen)) {
+        drop_graphs(c);  // some captured pointer may be stale
+        g = nullptr;
+    }
+    if (g) {
+        rec(c, 0);
+        HIP_OK(hipGraphLaunch(g->exec, st));
+        for (int e = 1; e <= 8; ++e) rec(c, e);
+    } else {
+        // eager product first: it allocates everything the product touches, then capture it
+        matvec_chunk(c, nr, gx, gy, false, mixed);
+        hipGraph_t graph = nullptr;
+        HIP_OK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        c->capturing = true;
+        try {
+            matvec_chunk(c, nr, gx, gy, false, mixed);
+        } catch (...) {
+            c->capturing = false;
+            (void)hipStreamEndCapture(st, &graph);
+            if (graph) (void)hipGraphDestroy(graph);
+            throw;
+        }
+        c->capturing = false;
+        HIP_OK(hipStreamEndCapture(st, &graph));
+        hipGraphExec_t exec = nullptr;
+        hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIP_OK(ie);
+        c->graphs.push_back({nr, mixed, exec, c->buf.gen, c->scratch.gen});
+    }
+    HIP_OK(hipMemcpyAsync(y, gy, bytes, hipMemcpyDeviceToDevice, st));
+}
+
+// any number of vectors, in chunks of 4, 2 and 1 (the kernels' right-hand-side counts)
+static void matvec_dev(fmmbem_ctx *c, int nrhs, const double2 *x, double2 *y, bool exact_far, bool mixed = false,
+                       bool allow_graph = true) {
+    const int64_t n = c->nt;
+    const bool graph = allow_graph && c->opt.graphs && !c->prof_on && !exact_far;
+    int r = 0;
+    while (r < nrhs) {
+        const int left = nrhs - r, nr = left >= 4 ? 4 : left >= 2 ? 2 : 1;
+        if (graph) matvec_graph(c, nr, x + (int64_t)r * n, y + (int64_t)r * n, mixed);
+        else matvec_chunk(c, nr, x + (int64_t)r * n, y + (int64_t)r * n, exact_far, mixed);
+        r += nr;
+    }
 }
 
 static void read_timings(fmmbem_ctx *c) {
@@ -710,7 +816,7 @@ static void rhs_dev(fmmbem_ctx *c, int isrc, double2 *b) {
                                               c->src_amp[isrc], sigma, mu);
     LAUNCH_OK();
     HIP_OK(hipEventRecord(c->ev[0], st));
-    fmm_pass(c, sigma, mu, nullptr, 0.0, b, false);
+    fmm_pass(c, 1, sigma, mu, nullptr, 0.0, b, false);
     HIP_OK(hipEventRecord(c->ev[8], st));
 }
 
@@ -747,6 +853,8 @@ void fmmbem_default_options(fmmbem_options *o) {
     o->ktau_switch = 1.0;
     o->max_depth = 12;
     o->lds_budget = 0;
+    o->graphs = 1;
+    o->autotune = 0;
 }
 
 void fmmbem_default_solve_opts(fmmbem_solve_opts *o) {
@@ -760,6 +868,17 @@ void fmmbem_default_solve_opts(fmmbem_solve_opts *o) {
     o->inner_iters = 0;
     o->inner_tol = 1e-2;
     o->inner_precision = FMMBEM_MIXED;
+}
+
+int fmmbem_release_workspace(fmmbem_ctx *ctx) {
+    if (!ctx) return FMMBEM_EINVAL;
+    GUARD_BEGIN
+    HIP_OK(hipSetDevice(ctx->device));
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    drop_graphs(ctx);
+    ctx->scratch.release_all();
+    return FMMBEM_OK;
+    GUARD_END
 }
 
 int fmmbem_solve_history(fmmbem_ctx *ctx, int32_t max, double *est, int32_t *count) {
@@ -810,6 +929,7 @@ int fmmbem_destroy(fmmbem_ctx *ctx) {
     if (!ctx) return FMMBEM_OK;
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    drop_graphs(ctx);
     ctx->buf.release_all();
     ctx->scratch.release_all();
     for (auto &e : ctx->ev)
@@ -932,13 +1052,17 @@ int fmmbem_matvec(fmmbem_ctx *ctx, int32_t nrhs, const fmmbem_c64 *x, fmmbem_c64
     HIP_OK(hipSetDevice(ctx->device));
     ensure_setup(ctx);
     const int64_t n = ctx->nt;
-    double2 *dx = dget<double2>(ctx->scratch, "mv_x", n), *dy = dget<double2>(ctx->scratch, "mv_y", n);
-    for (int r = 0; r < nrhs; ++r) {
-        HIP_OK(hipMemcpyAsync(dx, x + r * n, sizeof(double2) * n, hipMemcpyHostToDevice, ctx->stream));
-        matvec_dev(ctx, dx, dy, exact_far != 0, precision == FMMBEM_MIXED);
-        HIP_OK(hipMemcpyAsync(y + r * n, dy, sizeof(double2) * n, hipMemcpyDeviceToHost, ctx->stream));
+    double2 *dx = dget<double2>(ctx->scratch, "mv_x", (size_t)n * std::min(nrhs, 4));
+    double2 *dy = dget<double2>(ctx->scratch, "mv_y", (size_t)n * std::min(nrhs, 4));
+    int r = 0;
+    while (r < nrhs) {
+        const int left = nrhs - r, nr = left >= 4 ? 4 : left >= 2 ? 2 : 1;
+        HIP_OK(hipMemcpyAsync(dx, x + (int64_t)r * n, sizeof(double2) * n * nr, hipMemcpyHostToDevice, ctx->stream));
+        matvec_dev(ctx, nr, dx, dy, exact_far != 0, precision == FMMBEM_MIXED, false);
+        HIP_OK(hipMemcpyAsync(y + (int64_t)r * n, dy, sizeof(double2) * n * nr, hipMemcpyDeviceToHost, ctx->stream));
         HIP_OK(hipStreamSynchronize(ctx->stream));
         read_timings(ctx);
+        r += nr;
     }
     return FMMBEM_OK;
     GUARD_END
@@ -957,8 +1081,7 @@ int fmmbem_matvec_dev(fmmbem_ctx *ctx, int32_t nrhs, const void *x, void *y, int
     // order after the caller's stream, run on ours, then make the caller's stream wait
     HIP_OK(hipEventRecord(e0, caller));
     HIP_OK(hipStreamWaitEvent(ctx->stream, e0, 0));
-    for (int r = 0; r < nrhs; ++r)
-        matvec_dev(ctx, (const double2 *)x + r * n, (double2 *)y + r * n, false, precision == FMMBEM_MIXED);
+    matvec_dev(ctx, nrhs, (const double2 *)x, (double2 *)y, false, precision == FMMBEM_MIXED);
     HIP_OK(hipStreamWaitEvent(caller, ctx->ev[8], 0));
     return FMMBEM_OK;
     GUARD_END
@@ -995,26 +1118,8 @@ int fmmbem_last_timings(fmmbem_ctx *ctx, double *ms8) {
     GUARD_END
 }
 
-int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, fmmbem_c64 *x, fmmbem_solve_report *rep) {
-    if (!ctx) return FMMBEM_EINVAL;
-    if (!x) return fail(ctx, FMMBEM_EINVAL, "x is NULL");
-    fmmbem_solve_opts o;
-    fmmbem_default_solve_opts(&o);
-    if (opts) o = *opts;
-    if (o.restart < 1 || o.maxit < 0 || !(o.tol > 0)) return fail(ctx, FMMBEM_EINVAL, "bad solve options");
-    if (o.precision != FMMBEM_FP64 && o.precision != FMMBEM_MIXED) return fail(ctx, FMMBEM_EINVAL, "unknown precision");
-    if (o.inner_iters < 0 || (o.inner_iters > 0 && !(o.inner_tol > 0)) ||
-        (o.inner_precision != FMMBEM_FP64 && o.inner_precision != FMMBEM_MIXED))
-        return fail(ctx, FMMBEM_EINVAL, "bad inner solve options");
-    GUARD_BEGIN
-    HIP_OK(hipSetDevice(ctx->device));
-    if (ctx->src.empty()) return fail(ctx, FMMBEM_ENOTREADY, "sources not set");
-    if (isrc < 0 || isrc >= (int)(ctx->src.size() / 3)) return fail(ctx, FMMBEM_EINVAL, "bad source index");
-    double t_before = 0;
-    bool dirty = ctx->mesh_dirty || ctx->k_dirty || ctx->beta_dirty;
-    ensure_setup(ctx);
-    if (dirty) t_before = ctx->t_setup_last;
-    auto t0 = std::chrono::steady_clock::now();
+// Preconditioner of the solve options (data built on first use): z = P v on device vectors.
+static std::function<void(const double2 *, double2 *)> make_precond(fmmbem_ctx *ctx, const fmmbem_solve_opts &o) {
     hipStream_t st = ctx->stream;
     const int64_t n = ctx->nt;
     const int nleaf = (int)ctx->tree.leaf_start.size() - 1;
@@ -1052,19 +1157,6 @@ int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, f
         if (hs) throw FmmError(FMMBEM_EBREAKDOWN, "singular leaf block in the near-field preconditioner");
         ctx->precond_ready_nb = true;
     }
-    double2 *b = dget<double2>(ctx->scratch, "sv_b", n);
-    double2 *dx = dget<double2>(ctx->scratch, "sv_x", n);
-    rhs_dev(ctx, isrc, b);
-    if (o.use_x0) HIP_OK(hipMemcpyAsync(dx, x, sizeof(double2) * n, hipMemcpyHostToDevice, st));
-    // the Krylov products run in the requested arithmetic; restart residuals always in FP64
-    int64_t n64 = 0, nmx = 0;
-    auto product = [&](const double2 *a, double2 *y, bool mixed) {
-        matvec_dev(ctx, a, y, false, mixed);
-        ++(mixed ? nmx : n64);
-    };
-    const bool mixed = o.precision == FMMBEM_MIXED;
-    auto mv = [&](const double2 *a, double2 *y) { product(a, y, mixed); };
-    auto mv64 = [&](const double2 *a, double2 *y) { product(a, y, false); };
     std::function<void(const double2 *, double2 *)> pc;
     if (o.precond == FMMBEM_PC_DIAG) {
         double2 *dinv = (double2 *)ctx->buf.find("pc_dinv");
@@ -1085,6 +1177,52 @@ int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, f
             HIP_OK(hipMemcpyAsync(z, v, sizeof(double2) * n, hipMemcpyDeviceToDevice, st));
         };
     }
+    return pc;
+}
+
+static int check_solve_opts(fmmbem_ctx *ctx, const fmmbem_solve_opts &o) {
+    if (o.restart < 1 || o.maxit < 0 || !(o.tol > 0)) return fail(ctx, FMMBEM_EINVAL, "bad solve options");
+    if (o.precision != FMMBEM_FP64 && o.precision != FMMBEM_MIXED) return fail(ctx, FMMBEM_EINVAL, "unknown precision");
+    if (o.inner_iters < 0 || (o.inner_iters > 0 && !(o.inner_tol > 0)) ||
+        (o.inner_precision != FMMBEM_FP64 && o.inner_precision != FMMBEM_MIXED))
+        return fail(ctx, FMMBEM_EINVAL, "bad inner solve options");
+    if (o.precond < FMMBEM_PC_NONE || o.precond > FMMBEM_PC_NEARBLOCK) return fail(ctx, FMMBEM_EINVAL, "unknown preconditioner");
+    return FMMBEM_OK;
+}
+
+int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, fmmbem_c64 *x, fmmbem_solve_report *rep) {
+    if (!ctx) return FMMBEM_EINVAL;
+    if (!x) return fail(ctx, FMMBEM_EINVAL, "x is NULL");
+    fmmbem_solve_opts o;
+    fmmbem_default_solve_opts(&o);
+    if (opts) o = *opts;
+    if (int e = check_solve_opts(ctx, o)) return e;
+    GUARD_BEGIN
+    HIP_OK(hipSetDevice(ctx->device));
+    if (ctx->src.empty()) return fail(ctx, FMMBEM_ENOTREADY, "sources not set");
+    if (isrc < 0 || isrc >= (int)(ctx->src.size() / 3)) return fail(ctx, FMMBEM_EINVAL, "bad source index");
+    double t_before = 0;
+    bool dirty = ctx->mesh_dirty || ctx->k_dirty || ctx->beta_dirty;
+    ensure_setup(ctx);
+    if (dirty) t_before = ctx->t_setup_last;
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t st = ctx->stream;
+    const int64_t n = ctx->nt;
+    const int nleaf = (int)ctx->tree.leaf_start.size() - 1;
+    auto pc = make_precond(ctx, o);
+    double2 *b = dget<double2>(ctx->scratch, "sv_b", n);
+    double2 *dx = dget<double2>(ctx->scratch, "sv_x", n);
+    rhs_dev(ctx, isrc, b);
+    if (o.use_x0) HIP_OK(hipMemcpyAsync(dx, x, sizeof(double2) * n, hipMemcpyHostToDevice, st));
+    // the Krylov products run in the requested arithmetic; restart residuals always in FP64
+    int64_t n64 = 0, nmx = 0;
+    auto product = [&](const double2 *a, double2 *y, bool mixed) {
+        matvec_dev(ctx, 1, a, y, false, mixed);
+        ++(mixed ? nmx : n64);
+    };
+    const bool mixed = o.precision == FMMBEM_MIXED;
+    auto mv = [&](const double2 *a, double2 *y) { product(a, y, mixed); };
+    auto mv64 = [&](const double2 *a, double2 *y) { product(a, y, false); };
     // Inner-outer scheme (Section 4.4): the outer flexible GMRES is preconditioned by a short,
     // low-accuracy GMRES on the same operator (inner_precision), itself preconditioned by `pc`.
     std::function<void(const double2 *, double2 *)> outer_pc = pc;
@@ -1121,6 +1259,71 @@ int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, f
     }
     if (status < 0) ctx->err = "solver failed";
     return status;
+    GUARD_END
+}
+
+int fmmbem_solve_batch(fmmbem_ctx *ctx, int32_t ns, const int32_t *isrc, const fmmbem_solve_opts *opts,
+                       fmmbem_c64 *x, fmmbem_solve_report *rep) {
+    if (!ctx) return FMMBEM_EINVAL;
+    if (!x || !isrc || ns < 1) return fail(ctx, FMMBEM_EINVAL, "bad arguments");
+    fmmbem_solve_opts o;
+    fmmbem_default_solve_opts(&o);
+    if (opts) o = *opts;
+    if (int e = check_solve_opts(ctx, o)) return e;
+    if (o.inner_iters > 0) return fail(ctx, FMMBEM_EINVAL, "the batched solve has no inner-outer scheme");
+    GUARD_BEGIN
+    HIP_OK(hipSetDevice(ctx->device));
+    if (ctx->src.empty()) return fail(ctx, FMMBEM_ENOTREADY, "sources not set");
+    for (int s = 0; s < ns; ++s)
+        if (isrc[s] < 0 || isrc[s] >= (int)(ctx->src.size() / 3)) return fail(ctx, FMMBEM_EINVAL, "bad source index");
+    double t_before = 0;
+    bool dirty = ctx->mesh_dirty || ctx->k_dirty || ctx->beta_dirty;
+    ensure_setup(ctx);
+    if (dirty) t_before = ctx->t_setup_last;
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t st = ctx->stream;
+    const int64_t n = ctx->nt;
+    auto pc = make_precond(ctx, o);
+    double2 *B = dget<double2>(ctx->scratch, "sb_b", (size_t)ns * n);
+    double2 *X = dget<double2>(ctx->scratch, "sb_x", (size_t)ns * n);
+    for (int s = 0; s < ns; ++s) rhs_dev(ctx, isrc[s], B + (int64_t)s * n);
+    if (o.use_x0) HIP_OK(hipMemcpyAsync(X, x, sizeof(double2) * n * ns, hipMemcpyHostToDevice, st));
+    const bool mixed = o.precision == FMMBEM_MIXED;
+    int64_t n64 = 0, nmx = 0;
+    auto mv = [&](int nr, const double2 *a, double2 *y) {
+        matvec_dev(ctx, nr, a, y, false, mixed);
+        (mixed ? nmx : n64) += nr;
+    };
+    auto mv64 = [&](int nr, const double2 *a, double2 *y) {
+        matvec_dev(ctx, nr, a, y, false, false);
+        n64 += nr;
+    };
+    std::vector<int> iters, restarts, status;
+    std::vector<double> rel;
+    int rc = fgmres_batch(n, st, ctx->scratch, ns, mv, mv64, pc, B, X, o.tol, o.restart, o.maxit, o.use_x0 != 0,
+                          iters, restarts, rel, status);
+    HIP_OK(hipMemcpyAsync(x, X, sizeof(double2) * n * ns, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    const double ts = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    int worst = FMMBEM_OK;
+    for (int s = 0; s < ns; ++s) {
+        if (rep) {
+            rep[s].iters = iters[s];
+            rep[s].restarts = restarts[s];
+            rep[s].rel_res = rel[s];
+            rep[s].t_setup_s = t_before;
+            rep[s].t_solve_s = ts;  // wall time of the whole batch
+            rep[s].status = status[s];
+            rep[s].matvecs_fp64 = n64;  // products of the whole batch
+            rep[s].matvecs_mixed = nmx;
+            rep[s].inner_iters = 0;
+        }
+        if (status[s] < 0) worst = status[s];
+        else if (status[s] != FMMBEM_OK && worst == FMMBEM_OK) worst = status[s];
+    }
+    if (rc < 0) return fail(ctx, rc, "batched solver failed");
+    if (worst < 0) ctx->err = "solver failed";
+    return worst;
     GUARD_END
 }
 

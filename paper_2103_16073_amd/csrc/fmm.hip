@@ -165,14 +165,17 @@ __global__ void k_near_quad(int64_t nnz, const int32_t *rowv, const int32_t *col
 
 // ------------------------------------------------------------------ densities
 // sigma_i = -i k beta_i x_i, mu_i = x_i (sorted order; x in caller order)
-__global__ void k_densities(int64_t n, const int32_t *perm, const double2 *x, const double2 *beta, double k,
+// nr right-hand sides: x is nr x N in caller order; sigma/mu interleaved, [i * nr + r] in tree order
+__global__ void k_densities(int64_t n, int nr, const int32_t *perm, const double2 *x, const double2 *beta, double k,
                             double2 *sigma, double2 *mu) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double2 xi = x[perm[i]];
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * nr) return;
+    const int64_t i = e / nr;
+    const int r = (int)(e - i * nr);
+    double2 xi = x[(int64_t)r * n + perm[i]];
     double2 bx = cmul(beta[i], xi);
-    sigma[i] = cmk(k * bx.y, -k * bx.x);  // -i k (beta x)
-    mu[i] = xi;
+    sigma[e] = cmk(k * bx.y, -k * bx.x);  // -i k (beta x)
+    mu[e] = xi;
 }
 
 // gamma_i = -dpsi_in/dn + i k beta psi_in at centroid i for a monopole of amplitude amp at rs (Eq. sp7)
@@ -197,6 +200,7 @@ __global__ void k_gamma(int64_t n, const double4 *ec, const double4 *en, const d
 // y_i = sum_{j in neighbour leaves, |c_i - c_j| >= r_c} [G q_j + dG/dn_y w_j] + sum_near [L sigma + M mu]
 // with q_j = A_j sigma_j, w_j = A_j mu_j.  One workgroup (one wavefront) per target leaf,
 // source tiles staged in LDS.
+template <int NR>
 __global__ void __launch_bounds__(64) k_p2p(int nleaf, const int32_t *leaf_start, const int32_t *nbr_start,
                                             const int32_t *nbr_list, int all_leaves, const double4 *ec,
                                             const double4 *en, const double2 *sigma, const double2 *mu, double k,
@@ -204,7 +208,7 @@ __global__ void __launch_bounds__(64) k_p2p(int nleaf, const int32_t *leaf_start
                                             const double2 *nL, const double2 *nM, double2 *y) {
     const int b = blockIdx.x, tid = threadIdx.x;
     __shared__ double sx[64], sy[64], sz[64], snx[64], sny[64], snz[64];
-    __shared__ double2 sq[64], sw[64];
+    __shared__ double2 sq[64 * NR], sw[64 * NR];
     const int ts = leaf_start[b], te = leaf_start[b + 1];
     const int nb0 = all_leaves ? 0 : nbr_start[b], nb1 = all_leaves ? nleaf : nbr_start[b + 1];
     const double inv4pi = 1.0 / (4.0 * FMM_PI);
@@ -212,7 +216,9 @@ __global__ void __launch_bounds__(64) k_p2p(int nleaf, const int32_t *leaf_start
         const int t = t0 + tid;
         const bool act = t < te;
         double4 ct = act ? ec[t] : make_double4(0, 0, 0, 0);
-        double2 acc = cmk(0, 0);
+        double2 acc[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) acc[r] = cmk(0, 0);
         for (int q = nb0; q < nb1; ++q) {
             const int sb = all_leaves ? q : nbr_list[q];
             const int ss = leaf_start[sb], se = leaf_start[sb + 1];
@@ -227,8 +233,11 @@ __global__ void __launch_bounds__(64) k_p2p(int nleaf, const int32_t *leaf_start
                     snx[tid] = nv.x;
                     sny[tid] = nv.y;
                     snz[tid] = nv.z;
-                    sq[tid] = cscale(sigma[j], c.w);
-                    sw[tid] = cscale(mu[j], c.w);
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) {
+                        sq[tid * NR + r] = cscale(sigma[(int64_t)j * NR + r], c.w);
+                        sw[tid * NR + r] = cscale(mu[(int64_t)j * NR + r], c.w);
+                    }
                 }
                 __syncthreads();
                 const int cnt = min(64, se - j0);
@@ -243,19 +252,28 @@ __global__ void __launch_bounds__(64) k_p2p(int nleaf, const int32_t *leaf_start
                         double2 G = cmk(c * ir * inv4pi, s * ir * inv4pi);
                         double u = (dx * snx[jj] + dy * sny[jj] + dz * snz[jj]) * ir * ir;  // (y-x).n / r^2
                         // G * (q + (ikr - 1) u w)
-                        double2 t2 = cmul(cmk(-u, k * r * u), sw[jj]);
-                        acc = cfma(G, cadd(sq[jj], t2), acc);
+                        const double2 f = cmk(-u, k * r * u);
+#pragma unroll
+                        for (int rr = 0; rr < NR; ++rr) {
+                            double2 t2 = cmul(f, sw[jj * NR + rr]);
+                            acc[rr] = cfma(G, cadd(sq[jj * NR + rr], t2), acc[rr]);
+                        }
                     }
                 }
             }
         }
         if (act) {
             for (int e = near_start[t]; e < near_start[t + 1]; ++e) {
-                int j = near_col[e];
-                acc = cfma(nL[e], sigma[j], acc);
-                acc = cfma(nM[e], mu[j], acc);
+                const int64_t j = near_col[e];
+                const double2 l = nL[e], m = nM[e];
+#pragma unroll
+                for (int rr = 0; rr < NR; ++rr) {
+                    acc[rr] = cfma(l, sigma[j * NR + rr], acc[rr]);
+                    acc[rr] = cfma(m, mu[j * NR + rr], acc[rr]);
+                }
             }
-            y[t] = acc;
+#pragma unroll
+            for (int rr = 0; rr < NR; ++rr) y[(int64_t)t * NR + rr] = acc[rr];
         }
     }
 }
@@ -271,6 +289,7 @@ __device__ inline void kahan_add(float &s, float &c, float v) {
     s = t;
 }
 
+template <int NR>
 __global__ void __launch_bounds__(64) k_p2p32(int nleaf, const int32_t *leaf_start, const int32_t *nbr_start,
                                               const int32_t *nbr_list, const double4 *ec, const double4 *en,
                                               const double2 *sigma, const double2 *mu, double k, double rc2,
@@ -279,14 +298,16 @@ __global__ void __launch_bounds__(64) k_p2p32(int nleaf, const int32_t *leaf_sta
     const int b = blockIdx.x, tid = threadIdx.x;
     __shared__ double sx[64], sy[64], sz[64];
     __shared__ float snx[64], sny[64], snz[64];
-    __shared__ float2 sq[64], sw[64];
+    __shared__ float2 sq[64 * NR], sw[64 * NR];
     const int ts = leaf_start[b], te = leaf_start[b + 1];
     const float kf = (float)k, inv4pi = (float)(1.0 / (4.0 * FMM_PI));
     for (int t0 = ts; t0 < te; t0 += 64) {
         const int t = t0 + tid;
         const bool act = t < te;
         double4 ct = act ? ec[t] : make_double4(0, 0, 0, 0);
-        float ar = 0.f, ai = 0.f, cr = 0.f, ci = 0.f;
+        float ar[NR], ai[NR], cr[NR], ci[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) ar[r] = ai[r] = cr[r] = ci[r] = 0.f;
         for (int q = nbr_start[b]; q < nbr_start[b + 1]; ++q) {
             const int sb = nbr_list[q];
             const int ss = leaf_start[sb], se = leaf_start[sb + 1];
@@ -301,9 +322,12 @@ __global__ void __launch_bounds__(64) k_p2p32(int nleaf, const int32_t *leaf_sta
                     snx[tid] = (float)nv.x;
                     sny[tid] = (float)nv.y;
                     snz[tid] = (float)nv.z;
-                    double2 s = sigma[j], m = mu[j];
-                    sq[tid] = make_float2((float)(s.x * c.w), (float)(s.y * c.w));
-                    sw[tid] = make_float2((float)(m.x * c.w), (float)(m.y * c.w));
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) {
+                        const double2 s = sigma[(int64_t)j * NR + r], m = mu[(int64_t)j * NR + r];
+                        sq[tid * NR + r] = make_float2((float)(s.x * c.w), (float)(s.y * c.w));
+                        sw[tid * NR + r] = make_float2((float)(m.x * c.w), (float)(m.y * c.w));
+                    }
                 }
                 __syncthreads();
                 const int cnt = min(64, se - j0);
@@ -317,27 +341,43 @@ __global__ void __launch_bounds__(64) k_p2p32(int nleaf, const int32_t *leaf_sta
                         sincosf(kf * r, &s, &c);
                         const float gr = c * ir * inv4pi, gi = s * ir * inv4pi;
                         const float u = (dx * snx[jj] + dy * sny[jj] + dz * snz[jj]) * ir * ir;
-                        // G * (q + (ikr - 1) u w)
-                        const float2 w = sw[jj], qq = sq[jj];
-                        const float tr = qq.x - u * w.x - kf * r * u * w.y;
-                        const float ti = qq.y - u * w.y + kf * r * u * w.x;
-                        kahan_add(ar, cr, gr * tr - gi * ti);
-                        kahan_add(ai, ci, gr * ti + gi * tr);
+                        const float kru = kf * r * u;
+#pragma unroll
+                        for (int rr = 0; rr < NR; ++rr) {
+                            // G * (q + (ikr - 1) u w)
+                            const float2 w = sw[jj * NR + rr], qq = sq[jj * NR + rr];
+                            const float tr = qq.x - u * w.x - kru * w.y;
+                            const float ti = qq.y - u * w.y + kru * w.x;
+                            kahan_add(ar[rr], cr[rr], gr * tr - gi * ti);
+                            kahan_add(ai[rr], ci[rr], gr * ti + gi * tr);
+                        }
                     }
                 }
             }
         }
         if (act) {
-            double2 acc = make_double2((double)ar + (double)(-cr), (double)ai + (double)(-ci));
+            double2 acc[NR];
+#pragma unroll
+            for (int rr = 0; rr < NR; ++rr) acc[rr] = make_double2((double)ar[rr] - (double)cr[rr], (double)ai[rr] - (double)ci[rr]);
             for (int e = near_start[t]; e < near_start[t + 1]; ++e) {
-                int j = near_col[e];
+                const int64_t j = near_col[e];
                 const float2 l = nL[e], m = nM[e];
-                acc = cfma(make_double2(l.x, l.y), sigma[j], acc);
-                acc = cfma(make_double2(m.x, m.y), mu[j], acc);
+                const double2 ld = make_double2(l.x, l.y), md = make_double2(m.x, m.y);
+#pragma unroll
+                for (int rr = 0; rr < NR; ++rr) {
+                    acc[rr] = cfma(ld, sigma[j * NR + rr], acc[rr]);
+                    acc[rr] = cfma(md, mu[j * NR + rr], acc[rr]);
+                }
             }
-            y[t] = acc;
+#pragma unroll
+            for (int rr = 0; rr < NR; ++rr) y[(int64_t)t * NR + rr] = acc[rr];
         }
     }
+}
+
+__global__ void k_zero8(int64_t n, uint64_t *p) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
 }
 
 __global__ void k_cvt_d2f(int64_t n, const double2 *a, float2 *b) {
@@ -406,6 +446,7 @@ __device__ inline void sph_coords(double dx, double dy, double dz, double &r, do
     }
 }
 
+template <int NR>
 __global__ void __launch_bounds__(256) k_p2m(int nleaf, int p, int CH, const int32_t *leaf_start,
                                              const double4 *center, const double4 *ec, const double4 *en,
                                              const double2 *sigma, const double2 *mu, double k, double2 *Mout) {
@@ -413,15 +454,15 @@ __global__ void __launch_bounds__(256) k_p2m(int nleaf, int p, int CH, const int
     const int b = blockIdx.x, tid = threadIdx.x;
     const int TB = (p + 1) * (p + 2) / 2;
     double2 *basis = smem;                                 // CH * TB
-    double2 *qw = basis + (int64_t)CH * TB;                // CH * 2 (16-byte aligned)
-    double *jb = (double *)(qw + CH * 2);                  // CH * (p+2)
+    double2 *qw = basis + (int64_t)CH * TB;                // CH * 2 * NR (16-byte aligned)
+    double *jb = (double *)(qw + CH * 2 * NR);             // CH * (p+2)
     double *geo = jb + CH * (p + 2);                       // CH * 4: ct, st, phi, r
     double *nrm = geo + CH * 4;                            // CH * 3
     const double4 C = center[b];
     const int ss = leaf_start[b], se = leaf_start[b + 1];
     const int ncoef = p * p;
-    double2 *Mb = Mout + (int64_t)b * ncoef;
-    for (int c = tid; c < ncoef; c += blockDim.x) Mb[c] = cmk(0, 0);
+    double2 *Mb = Mout + (int64_t)b * NR * ncoef;          // NR expansions of this leaf
+    for (int c = tid; c < NR * ncoef; c += blockDim.x) Mb[c] = cmk(0, 0);
     for (int j0 = ss; j0 < se; j0 += CH) {
         const int cnt = min(CH, se - j0);
         __syncthreads();
@@ -435,8 +476,11 @@ __global__ void __launch_bounds__(256) k_p2m(int nleaf, int p, int CH, const int
             geo[4 * tid + 2] = phi;
             geo[4 * tid + 3] = r;
             sph_jn_seq(k * r, p, jb + tid * (p + 2));
-            qw[2 * tid] = cscale(sigma[j], c.w);
-            qw[2 * tid + 1] = cscale(mu[j], c.w);
+#pragma unroll
+            for (int rr = 0; rr < NR; ++rr) {
+                qw[(2 * tid) * NR + rr] = cscale(sigma[(int64_t)j * NR + rr], c.w);
+                qw[(2 * tid + 1) * NR + rr] = cscale(mu[(int64_t)j * NR + rr], c.w);
+            }
             nrm[3 * tid] = nv.x;
             nrm[3 * tid + 1] = nv.y;
             nrm[3 * tid + 2] = nv.z;
@@ -455,7 +499,9 @@ __global__ void __launch_bounds__(256) k_p2m(int nleaf, int p, int CH, const int
             const double ca1 = coef_a(n - 1, mm), ca2 = coef_a(n, mm);
             const double cb1 = coef_b(n + 1, -mm - 1), cb2 = coef_b(n, mm);
             const double cb3 = coef_b(n + 1, mm - 1), cb4 = coef_b(n, -mm);
-            double2 a = cmk(0, 0);
+            double2 a[NR];
+#pragma unroll
+            for (int rr = 0; rr < NR; ++rr) a[rr] = cmk(0, 0);
             for (int s = 0; s < cnt; ++s) {
                 const double2 *B = basis + (int64_t)s * TB;
                 double2 R0 = basis_get(B, p, n, mm);
@@ -466,28 +512,37 @@ __global__ void __launch_bounds__(256) k_p2m(int nleaf, int p, int CH, const int
                 double2 dn = cscale(dz, nz);
                 dn = cadd(dn, cmul(cmk(0.5 * nx, -0.5 * ny), dp));
                 dn = cadd(dn, cmul(cmk(0.5 * nx, 0.5 * ny), dm));
-                a = cfma(qw[2 * s], R0, a);
-                a = cfma(qw[2 * s + 1], dn, a);
+#pragma unroll
+                for (int rr = 0; rr < NR; ++rr) {
+                    a[rr] = cfma(qw[(2 * s) * NR + rr], R0, a[rr]);
+                    a[rr] = cfma(qw[(2 * s + 1) * NR + rr], dn, a[rr]);
+                }
             }
-            Mb[c] = cadd(Mb[c], cmuli(cscale(a, k)));  // i k sum
+#pragma unroll
+            for (int rr = 0; rr < NR; ++rr)
+                Mb[rr * ncoef + c] = cadd(Mb[rr * ncoef + c], cmuli(cscale(a[rr], k)));  // i k sum
         }
     }
 }
 
 // ------------------------------------------------------------------ L2P + combine
 // y[perm[i]] = half * x[perm[i]] + y_near[i] + sum_{n,m} D_n^m R_n^m(c_i - C).
+template <int NR>
 __global__ void __launch_bounds__(64) k_l2p(int nleaf, int p, const int32_t *leaf_start, const double4 *center,
                                             const double4 *ec, const double2 *Lc, double k, const double2 *ynear,
-                                            double half, const int32_t *perm, const double2 *x, double2 *y,
+                                            double half, const int32_t *perm, int64_t n, const double2 *x, double2 *y,
                                             int has_far) {
     extern __shared__ double jbuf[];
     const int b = blockIdx.x, tid = threadIdx.x;
     const double4 C = center[b];
     const int ts = leaf_start[b], te = leaf_start[b + 1];
-    const double2 *D = Lc + (int64_t)b * p * p;
+    const double2 *D = Lc + (int64_t)b * NR * p * p;  // NR expansions of this leaf
+    const int pp = p * p;
     double *jb = jbuf + tid * (p + 2);
     for (int t = ts + tid; t < te; t += 64) {
-        double2 far = cmk(0, 0);
+        double2 far[NR];
+#pragma unroll
+        for (int rr = 0; rr < NR; ++rr) far[rr] = cmk(0, 0);
         if (has_far) {
             double4 c = ec[t];
             double r, ct, st, phi;
@@ -499,34 +554,45 @@ __global__ void __launch_bounds__(64) k_l2p(int nleaf, int p, const int32_t *lea
                 double s, co;
                 sincos(mp * phi, &s, &co);
                 double pm2 = 0.0, pm1 = pmm;
-                double2 sp = cmk(0, 0), sn = cmk(0, 0);
-                for (int n = mp; n < p; ++n) {
+                double2 sp[NR], sn[NR];
+#pragma unroll
+                for (int rr = 0; rr < NR; ++rr) sp[rr] = sn[rr] = cmk(0, 0);
+                for (int nn = mp; nn < p; ++nn) {
                     double P;
-                    if (n == mp) P = pmm;
-                    else if (n == mp + 1) P = sqrt(2.0 * mp + 3.0) * ct * pmm;
+                    if (nn == mp) P = pmm;
+                    else if (nn == mp + 1) P = sqrt(2.0 * mp + 3.0) * ct * pmm;
                     else {
-                        double a = sqrt((4.0 * n * n - 1.0) / ((double)n * n - (double)mp * mp));
-                        double bq = sqrt((((double)n - 1) * (n - 1) - (double)mp * mp) * (2.0 * n + 1.0) /
-                                         ((2.0 * n - 3.0) * ((double)n * n - (double)mp * mp)));
+                        double a = sqrt((4.0 * nn * nn - 1.0) / ((double)nn * nn - (double)mp * mp));
+                        double bq = sqrt((((double)nn - 1) * (nn - 1) - (double)mp * mp) * (2.0 * nn + 1.0) /
+                                         ((2.0 * nn - 3.0) * ((double)nn * nn - (double)mp * mp)));
                         P = a * ct * pm1 - bq * pm2;
                     }
-                    if (n >= mp + 1) {
+                    if (nn >= mp + 1) {
                         pm2 = pm1;
                         pm1 = P;
                     }
-                    double R = jb[n] * P;
-                    sp = cadd(sp, cscale(D[cidx(n, mp)], R));
-                    if (mp > 0) sn = cadd(sn, cscale(D[cidx(n, -mp)], R));
+                    double R = jb[nn] * P;
+#pragma unroll
+                    for (int rr = 0; rr < NR; ++rr) {
+                        sp[rr] = cadd(sp[rr], cscale(D[rr * pp + cidx(nn, mp)], R));
+                        if (mp > 0) sn[rr] = cadd(sn[rr], cscale(D[rr * pp + cidx(nn, -mp)], R));
+                    }
                 }
                 // sum_n D_n^m R e^{i m phi} + D_n^{-m} R e^{-i m phi}
-                far = cadd(far, cmul(sp, cmk(co, s)));
-                if (mp > 0) far = cadd(far, cmul(sn, cmk(co, -s)));
+#pragma unroll
+                for (int rr = 0; rr < NR; ++rr) {
+                    far[rr] = cadd(far[rr], cmul(sp[rr], cmk(co, s)));
+                    if (mp > 0) far[rr] = cadd(far[rr], cmul(sn[rr], cmk(co, -s)));
+                }
             }
         }
-        const int u = perm[t];
-        double2 v = cadd(ynear[t], far);
-        if (x) v = cadd(v, cscale(x[u], half));  // the right-hand side pass has no identity term
-        y[u] = v;
+        const int64_t u = perm[t];
+#pragma unroll
+        for (int rr = 0; rr < NR; ++rr) {
+            double2 v = cadd(ynear[(int64_t)t * NR + rr], far[rr]);
+            if (x) v = cadd(v, cscale(x[rr * n + u], half));  // the right-hand side pass has no identity term
+            y[rr * n + u] = v;
+        }
     }
 }
 
@@ -575,6 +641,58 @@ __global__ void __launch_bounds__(256) k_field(int64_t nt, const double *pts, co
         sincos(k * r, &s, &co);
         out[q] = cadd(red[0], cmul(amp, cmk(co / r * inv4pi, s / r * inv4pi)));
     }
+}
+
+// ------------------------------------------------------------------ launchers (RHS count 1, 2, 4)
+#define FMM_NR_DISPATCH(nr, CALL)                                             \
+    switch (nr) {                                                             \
+    case 1: CALL(1); break;                                                   \
+    case 2: CALL(2); break;                                                   \
+    case 4: CALL(4); break;                                                   \
+    default: throw FmmError(-1, "right-hand-side chunk must be 1, 2 or 4");  \
+    }
+
+void launch_p2p(int nr, bool fp32, int nleaf, const int32_t *leaf_start, const int32_t *nbr_start,
+                const int32_t *nbr_list, int all_leaves, const double4 *ec, const double4 *en, const double2 *sigma,
+                const double2 *mu, double k, double rc2, const int32_t *near_start, const int32_t *near_col,
+                const void *nL, const void *nM, double2 *y, hipStream_t st) {
+    if (fp32 && all_leaves) throw FmmError(-1, "the all-pairs near field is an FP64 product");
+#define P2P_CALL(R)                                                                                                   \
+    if (fp32)                                                                                                         \
+        k_p2p32<R><<<nleaf, 64, 0, st>>>(nleaf, leaf_start, nbr_start, nbr_list, ec, en, sigma, mu, k, rc2,          \
+                                         near_start, near_col, (const float2 *)nL, (const float2 *)nM, y);           \
+    else                                                                                                              \
+        k_p2p<R><<<nleaf, 64, 0, st>>>(nleaf, leaf_start, nbr_start, nbr_list, all_leaves, ec, en, sigma, mu, k, rc2, \
+                                       near_start, near_col, (const double2 *)nL, (const double2 *)nM, y)
+    FMM_NR_DISPATCH(nr, P2P_CALL)
+#undef P2P_CALL
+    LAUNCH_OK();
+}
+
+size_t p2m_stage_bytes(int nr, int p) {
+    const int TB = (p + 1) * (p + 2) / 2;
+    return (size_t)TB * 16 + (size_t)nr * 32 + (size_t)(p + 2) * 8 + 56;  // per staged source
+}
+
+void launch_p2m(int nr, int nleaf, int p, int CH, const int32_t *leaf_start, const double4 *center,
+                const double4 *ec, const double4 *en, const double2 *sigma, const double2 *mu, double k,
+                double2 *Mout, hipStream_t st) {
+    const size_t sh = (size_t)CH * p2m_stage_bytes(nr, p);
+#define P2M_CALL(R) k_p2m<R><<<nleaf, 256, sh, st>>>(nleaf, p, CH, leaf_start, center, ec, en, sigma, mu, k, Mout)
+    FMM_NR_DISPATCH(nr, P2M_CALL)
+#undef P2M_CALL
+    LAUNCH_OK();
+}
+
+void launch_l2p(int nr, int nleaf, int p, const int32_t *leaf_start, const double4 *center, const double4 *ec,
+                const double2 *Lc, double k, const double2 *ynear, double half, const int32_t *perm, int64_t n,
+                const double2 *x, double2 *y, int has_far, hipStream_t st) {
+    const size_t sh = (size_t)64 * (p + 2) * sizeof(double);
+#define L2P_CALL(R) \
+    k_l2p<R><<<nleaf, 64, sh, st>>>(nleaf, p, leaf_start, center, ec, Lc, k, ynear, half, perm, n, x, y, has_far)
+    FMM_NR_DISPATCH(nr, L2P_CALL)
+#undef L2P_CALL
+    LAUNCH_OK();
 }
 
 }  // namespace fmm

@@ -18,6 +18,7 @@ namespace fmm {
 // Named, growable device allocations owned by a context.
 struct DeviceBuffers {
     std::map<std::string, std::pair<void *, size_t>> bufs;
+    uint64_t gen = 0;  // bumped whenever a buffer is freed (pointers held elsewhere may be stale)
     void *get(const std::string &name, size_t bytes) {
         if (bytes == 0) bytes = 16;
         auto it = bufs.find(name);
@@ -25,6 +26,7 @@ struct DeviceBuffers {
         if (it != bufs.end()) {
             HIP_OK(hipFree(it->second.first));
             bufs.erase(it);
+            ++gen;
         }
         void *p = nullptr;
         HIP_OK(hipMalloc(&p, bytes));
@@ -40,11 +42,13 @@ struct DeviceBuffers {
         if (it != bufs.end()) {
             (void)hipFree(it->second.first);
             bufs.erase(it);
+            ++gen;
         }
     }
     void release_all() {
         for (auto &kv : bufs) (void)hipFree(kv.second.first);
         bufs.clear();
+        ++gen;
     }
 };
 
@@ -121,7 +125,7 @@ int trans_pick_jt(int P, size_t lds_budget, int whole);
 size_t trans_lds_bytes(int JT, int P, int whole);
 void trans_configure_lds(size_t lds_max);
 template <class R>
-const char *trans_stage(const TransBatch &b, const TransTables<R> &tb, int stage, const typename Cx<R>::T *src,
+const char *trans_stage(const TransBatch &b, const TransTables<R> &tb, int stage, int nr, const typename Cx<R>::T *src,
                         typename Cx<R>::T *dst, const typename Cx<R>::T *ph, int PH, typename Cx<R>::T *W1,
                         typename Cx<R>::T *W2, hipStream_t st);
 void build_rot_tables(const std::vector<double> &betas, int P, const double *D, double *H, double *HT,
@@ -192,7 +196,16 @@ struct fmmbem_ctx {
     int64_t p2p_pairs = 0;
     bool precond_ready_nb = false, precond_ready_diag = false;
     std::vector<double> history;  // Arnoldi residual estimate per outer iteration of the last solve
-    bool mixed_ready = false;  // FP32 copies of the tables exist for the current wavenumber
+    bool mixed_ready = false;
+    int nr_cap = 1, nr_cap32 = 0;  // vectors per box the FP64 / FP32 expansion arrays hold
+    bool capturing = false;        // a graph capture is in progress: no allocation, no timing events
+    struct GraphEntry {
+        int nr;
+        bool mixed;
+        hipGraphExec_t exec;
+        uint64_t gen_buf, gen_scr;
+    };
+    std::vector<GraphEntry> graphs;  // captured products (staging buffers g_x -> g_y)  // FP32 copies of the tables exist for the current wavenumber
     fmm::Timings last;
     double t_setup_last = 0.0;
     // kernel profiling (fmmbem_profile)

@@ -395,4 +395,167 @@ int fgmres(int64_t n, hipStream_t st, DeviceBuffers &scr, const char *tag,
     return status;
 }
 
+// Lock-step FGMRES over nv systems A x_s = b_s that share the operator: every step gathers the
+// preconditioned vectors of the systems still iterating and applies one batched product, so the
+// kernel evaluations, basis functions and translation tables of the FMM are shared between them.
+// Each system keeps its own Krylov basis, Hessenberg matrix and restarts, exactly as fgmres().
+struct BatchSys {
+    double2 *V = nullptr, *Z = nullptr, *r = nullptr;
+    std::vector<double2> H, g, cs, sn, h1, h2, y;
+    double bn = 0.0, est = 1.0;
+    int j = 0, cycle = 0;  // cycle = restarts so far
+    bool in_cycle = false, done = false;
+};
+
+int fgmres_batch(int64_t n, hipStream_t st, DeviceBuffers &scr, int nv,
+                 const std::function<void(int, const double2 *, double2 *)> &matvec,
+                 const std::function<void(int, const double2 *, double2 *)> &matvec_check,
+                 const std::function<void(const double2 *, double2 *)> &precond, const double2 *B, double2 *X,
+                 double tol, int m, int maxit, bool x0_given, std::vector<int> &iters, std::vector<int> &restarts,
+                 std::vector<double> &rel_res, std::vector<int> &status) {
+    Blas Bl{st, scr, n, "bt_"};
+    std::vector<BatchSys> S(nv);
+    iters.assign(nv, 0);
+    restarts.assign(nv, 0);
+    rel_res.assign(nv, 1.0);
+    status.assign(nv, FMMBEM_ENOCONV);
+    double2 *Sin = dget<double2>(scr, "bt_in", (size_t)nv * n), *Sout = dget<double2>(scr, "bt_out", (size_t)nv * n);
+    for (int s = 0; s < nv; ++s) {
+        BatchSys &q = S[s];
+        q.V = dget<double2>(scr, "bt_V" + std::to_string(s), (size_t)(m + 1) * n);
+        q.Z = dget<double2>(scr, "bt_Z" + std::to_string(s), (size_t)m * n);
+        q.r = dget<double2>(scr, "bt_r" + std::to_string(s), n);
+        q.H.assign((size_t)(m + 1) * m, cmk(0, 0));
+        q.g.assign(m + 1, cmk(0, 0));
+        q.cs.assign(m, cmk(0, 0));
+        q.sn.assign(m, cmk(0, 0));
+        q.h1.assign(m + 1, cmk(0, 0));
+        q.h2.assign(m + 1, cmk(0, 0));
+        q.y.assign(m, cmk(0, 0));
+        double2 *x = X + (int64_t)s * n;
+        if (!x0_given) HIP_OK(hipMemsetAsync(x, 0, sizeof(double2) * n, st));
+        q.bn = Bl.nrm(B + (int64_t)s * n);
+        if (!(q.bn > 0.0)) {
+            HIP_OK(hipMemsetAsync(x, 0, sizeof(double2) * n, st));
+            rel_res[s] = 0.0;
+            status[s] = FMMBEM_OK;
+            q.done = true;
+        }
+    }
+    while (true) {
+        // 1. systems between cycles: true residual (batched FP64 product), convergence test, new cycle
+        std::vector<int> need;
+        for (int s = 0; s < nv; ++s)
+            if (!S[s].done && !S[s].in_cycle) need.push_back(s);
+        if (!need.empty()) {
+            std::vector<int> prod;
+            for (int s : need)
+                if (x0_given || S[s].cycle > 0) prod.push_back(s);
+            for (size_t k = 0; k < prod.size(); ++k)
+                HIP_OK(hipMemcpyAsync(Sin + k * n, X + (int64_t)prod[k] * n, sizeof(double2) * n,
+                                      hipMemcpyDeviceToDevice, st));
+            if (!prod.empty()) matvec_check((int)prod.size(), Sin, Sout);
+            for (size_t k = 0; k < prod.size(); ++k)
+                Bl.sub(B + (int64_t)prod[k] * n, Sout + k * n, S[prod[k]].r);
+            for (int s : need) {
+                BatchSys &q = S[s];
+                if (!(x0_given || q.cycle > 0))
+                    HIP_OK(hipMemcpyAsync(q.r, B + (int64_t)s * n, sizeof(double2) * n, hipMemcpyDeviceToDevice, st));
+                const double beta = Bl.nrm(q.r);
+                rel_res[s] = beta / q.bn;
+                if (!std::isfinite(beta)) {
+                    status[s] = FMMBEM_ENAN;
+                    q.done = true;
+                    continue;
+                }
+                if (rel_res[s] < tol) {
+                    status[s] = FMMBEM_OK;
+                    q.done = true;
+                    continue;
+                }
+                if (iters[s] >= maxit) {
+                    q.done = true;
+                    continue;
+                }
+                Bl.scale_copy(1.0 / beta, q.r, q.V);
+                std::fill(q.g.begin(), q.g.end(), cmk(0, 0));
+                q.g[0] = cmk(beta, 0);
+                q.j = 0;
+                q.in_cycle = true;
+            }
+        }
+        std::vector<int> act;
+        for (int s = 0; s < nv; ++s)
+            if (S[s].in_cycle) act.push_back(s);
+        if (act.empty()) break;
+        // 2. one Arnoldi step for every active system, with a single batched product
+        for (size_t k = 0; k < act.size(); ++k) {
+            BatchSys &q = S[act[k]];
+            precond(q.V + (size_t)q.j * n, q.Z + (size_t)q.j * n);
+            HIP_OK(hipMemcpyAsync(Sin + k * n, q.Z + (size_t)q.j * n, sizeof(double2) * n, hipMemcpyDeviceToDevice,
+                                  st));
+        }
+        matvec((int)act.size(), Sin, Sout);
+        for (size_t k = 0; k < act.size(); ++k) {
+            const int s = act[k];
+            BatchSys &q = S[s];
+            auto Hc = [&](int i, int jj) -> double2 & { return q.H[(size_t)i * m + jj]; };
+            double2 *w = Sout + k * n;
+            const int j = q.j;
+            ++iters[s];
+            Bl.dots(q.V, n, j + 1, w, q.h1.data());
+            Bl.sub_combo(q.V, n, j + 1, q.h1.data(), w);
+            Bl.dots(q.V, n, j + 1, w, q.h2.data());
+            Bl.sub_combo(q.V, n, j + 1, q.h2.data(), w);
+            for (int i = 0; i <= j; ++i) Hc(i, j) = cadd(q.h1[i], q.h2[i]);
+            const double hn = Bl.nrm(w);
+            if (!std::isfinite(hn)) {
+                status[s] = FMMBEM_ENAN;
+                q.done = true;
+                q.in_cycle = false;
+                continue;
+            }
+            Hc(j + 1, j) = cmk(hn, 0);
+            if (hn > 0) Bl.scale_copy(1.0 / hn, w, q.V + (size_t)(j + 1) * n);
+            for (int i = 0; i < j; ++i) {
+                double2 a = Hc(i, j), c = Hc(i + 1, j);
+                Hc(i, j) = cadd(cscale(a, q.cs[i].x), cmul(q.sn[i], c));
+                Hc(i + 1, j) = csub(cscale(c, q.cs[i].x), cmul(cconj(q.sn[i]), a));
+            }
+            double2 a = Hc(j, j), c = Hc(j + 1, j);
+            const double den = hypot(cabs_(a), cabs_(c));
+            if (den == 0) {
+                q.cs[j] = cmk(1, 0);
+                q.sn[j] = cmk(0, 0);
+            } else {
+                const double aa = cabs_(a);
+                q.cs[j] = cmk(aa / den, 0);
+                const double2 ph = aa > 0 ? cscale(a, 1.0 / aa) : cmk(1, 0);
+                q.sn[j] = cscale(cmul(ph, cconj(c)), 1.0 / den);
+            }
+            Hc(j, j) = cadd(cscale(a, q.cs[j].x), cmul(q.sn[j], c));
+            Hc(j + 1, j) = cmk(0, 0);
+            q.g[j + 1] = cscale(cmul(cconj(q.sn[j]), q.g[j]), -1.0);
+            q.g[j] = cscale(q.g[j], q.cs[j].x);
+            q.est = cabs_(q.g[j + 1]) / q.bn;
+            q.j = j + 1;
+            if (q.est < tol || hn == 0 || q.j == m || iters[s] >= maxit) {
+                // end of cycle: x += Z y with y = H^{-1} g
+                const int jj = q.j;
+                for (int i = jj - 1; i >= 0; --i) {
+                    double2 sum = q.g[i];
+                    for (int t = i + 1; t < jj; ++t) sum = csub(sum, cmul(Hc(i, t), q.y[t]));
+                    if (cabs_(Hc(i, i)) == 0) return FMMBEM_EBREAKDOWN;
+                    q.y[i] = cdiv(sum, Hc(i, i));
+                }
+                Bl.add_combo(q.Z, n, jj, q.y.data(), X + (int64_t)s * n);
+                q.in_cycle = false;
+                ++q.cycle;
+                restarts[s] = q.cycle;
+            }
+        }
+    }
+    return FMMBEM_OK;
+}
+
 }  // namespace fmm

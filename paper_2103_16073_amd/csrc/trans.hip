@@ -28,8 +28,9 @@ template <class C> __device__ inline C addc(C a, C b) { C v; v.x = a.x + b.x; v.
 template <class R>
 struct TransArgsT {
     using C = typename Cx<R>::T;
-    int64_t njob;
+    int64_t njob;               // virtual jobs: real jobs x nr right-hand sides
     int JT, psrc, ptgt, P, PT, PH;
+    int nr;                     // right-hand sides; virtual job J = real job J / nr, vector J % nr
     const C *src;               // source expansions (psrc^2 per box)
     C *dst;                     // target expansions (ptgt^2 per box), accumulated
     const int32_t *jsrc, *jtgt; // per job; jtgt < 0 marks padding
@@ -43,6 +44,12 @@ struct TransArgsT {
 };
 
 constexpr int RJ = 4, RR = 4;
+
+// source expansion row of virtual job J (sources hold nr vectors per box, vector-inner)
+template <class R>
+__device__ inline int64_t src_row(const TransArgsT<R> &a, int64_t J) {
+    return (int64_t)a.jsrc[J / a.nr] * a.nr + J % a.nr;
+}
 
 // ------------------------------------------------------------------ forward rotation
 template <class R>
@@ -60,10 +67,10 @@ __global__ void __launch_bounds__(256) k_tr_rot_fwd(TransArgsT<R> a) {
     for (int e = threadIdx.x; e < nj * w; e += blockDim.x) {
         const int j = e / w, q = e - j * w, m = q - n;
         const int64_t job = t0 + j;
-        xs[j * w + q] = mulc(a.ph[(int64_t)a.jdir[job] * phs + a.PH + m], a.src[(int64_t)a.jsrc[job] * ps2 + n * n + q]);
+        xs[j * w + q] = mulc(a.ph[(int64_t)a.jdir[job / a.nr] * phs + a.PH + m], a.src[src_row(a, job) * ps2 + n * n + q]);
     }
     __syncthreads();
-    const R *HTn = a.HT + (int64_t)a.tile_rot[blockIdx.x] * rot_table_size(a.P) + rot_block_off(n);
+    const R *HTn = a.HT + (int64_t)a.tile_rot[blockIdx.x / a.nr] * rot_table_size(a.P) + rot_block_off(n);
     const int ng = (nj + RJ - 1) / RJ, nr = (w + RR - 1) / RR;
     for (int e = threadIdx.x; e < ng * nr; e += blockDim.x) {
         const int g = e / nr, r0 = (e - g * nr) * RR;
@@ -131,7 +138,7 @@ __global__ void __launch_bounds__(256) k_tr_coax(TransArgsT<R> a) {
     }
     __syncthreads();
     const int B = a.PT - am;
-    const C *Tm = a.coax + (int64_t)a.tile_coax[blockIdx.x] * coax_table_size(a.PT) + coax_block_off(a.PT, am);
+    const C *Tm = a.coax + (int64_t)a.tile_coax[blockIdx.x / a.nr] * coax_table_size(a.PT) + coax_block_off(a.PT, am);
     const int ng = (nj + RJ - 1) / RJ, nr = (rows + RR - 1) / RR;
     for (int e = threadIdx.x; e < ng * nr; e += blockDim.x) {
         const int g = e / nr, r0 = (e - g * nr) * RR;  // output rows nn = am + r0 + v
@@ -192,13 +199,13 @@ __global__ void __launch_bounds__(256) k_tr_rot_back(TransArgsT<R> a) {
     const int64_t t0 = (int64_t)blockIdx.x * JT;
     const int nj = (int)min((int64_t)JT, a.njob - t0);
     const int P2 = a.P * a.P, phs = 2 * a.PH + 1;
-    for (int j = threadIdx.x; j < nj; j += blockDim.x) sdir[j] = a.jdir[t0 + j];
+    for (int j = threadIdx.x; j < nj; j += blockDim.x) sdir[j] = a.jdir[(t0 + j) / a.nr];
     for (int e = threadIdx.x; e < nj * w; e += blockDim.x) {
         const int j = e / w, q = e - j * w;
         ys[j * w + q] = a.W2[(t0 + j) * (int64_t)P2 + n * n + q];
     }
     __syncthreads();
-    const R *Hn = a.H + (int64_t)a.tile_rot[blockIdx.x] * rot_table_size(a.P) + rot_block_off(n);
+    const R *Hn = a.H + (int64_t)a.tile_rot[blockIdx.x / a.nr] * rot_table_size(a.P) + rot_block_off(n);
     const int ng = (nj + RJ - 1) / RJ, nr = (w + RR - 1) / RR;
     for (int e = threadIdx.x; e < ng * nr; e += blockDim.x) {
         const int g = e / nr, r0 = (e - g * nr) * RR;
@@ -277,21 +284,21 @@ __global__ void __launch_bounds__(256) k_tw_rot(TransArgsT<R> a) {
     const int64_t t0 = (int64_t)blockIdx.x * JT;
     const int nj = (int)min((int64_t)JT, a.njob - t0);
     const int pin2 = pin * pin;
-    for (int j = threadIdx.x; j < nj; j += blockDim.x) sdir[j] = a.jdir[t0 + j];
+    for (int j = threadIdx.x; j < nj; j += blockDim.x) sdir[j] = a.jdir[(t0 + j) / a.nr];
     __syncthreads();
     for (int e = threadIdx.x; e < nj * pin2; e += blockDim.x) {
         const int j = e / pin2, c = e - j * pin2;
         C v;
         if (FWD) {
             const int n = (int)sqrtf((float)c + 0.5f), m = c - n * n - n;
-            v = mulc(a.ph[(int64_t)sdir[j] * phs + a.PH + m], a.src[(int64_t)a.jsrc[t0 + j] * (a.psrc * a.psrc) + c]);
+            v = mulc(a.ph[(int64_t)sdir[j] * phs + a.PH + m], a.src[src_row(a, t0 + j) * (a.psrc * a.psrc) + c]);
         } else {
             v = a.W2[(t0 + j) * (int64_t)P2 + c];
         }
         X[j * P2 + c] = v;
     }
     __syncthreads();
-    const R *Hb = (FWD ? a.HT : a.H) + (int64_t)a.tile_rot[blockIdx.x] * rot_table_size(a.P);
+    const R *Hb = (FWD ? a.HT : a.H) + (int64_t)a.tile_rot[blockIdx.x / a.nr] * rot_table_size(a.P);
     const int ng = (nj + RJ - 1) / RJ, nit = items_rot(pin);
     for (int e = threadIdx.x; e < ng * nit; e += blockDim.x) {
         const int g = e / nit;
@@ -355,7 +362,7 @@ __global__ void __launch_bounds__(256) k_tw_coax(TransArgsT<R> a) {
         X[j * ps2 + c] = a.W1[(t0 + j) * (int64_t)P2 + c];
     }
     __syncthreads();
-    const C *T = a.coax + (int64_t)a.tile_coax[blockIdx.x] * coax_table_size(a.PT);
+    const C *T = a.coax + (int64_t)a.tile_coax[blockIdx.x / a.nr] * coax_table_size(a.PT);
     const int pm = min(a.psrc, a.ptgt);
     // items: orders m in -(pt-1)..pt-1, row groups ceil((pt-|m|)/RR)
     int nit = 0;
@@ -418,18 +425,22 @@ __global__ void __launch_bounds__(256) k_tw_coax(TransArgsT<R> a) {
     }
 }
 
-// dst[t] += sum of the job rows of target t (W1, P^2 per job); jobs of t listed in CSR order
+// dst[t] += sum of the job rows of target t (W1, P^2 per job); jobs of t listed in CSR order.
+// With nr vectors, virtual target t is real target t / nr, vector t % nr, and the job rows of
+// that vector are (job * nr + t % nr).
 template <class C>
-__global__ void __launch_bounds__(256) k_tr_reduce(int64_t ntgt, int ptgt, int P, const int32_t *start,
+__global__ void __launch_bounds__(256) k_tr_reduce(int64_t ntgt, int nr, int ptgt, int P, const int32_t *start,
                                                    const int32_t *jobs, const C *W, C *dst) {
     const int64_t t = blockIdx.x;
-    if (t >= ntgt) return;
-    const int j0 = start[t], j1 = start[t + 1];
+    if (t >= ntgt * nr) return;
+    const int64_t tr = t / nr;
+    const int r = (int)(t - tr * nr);
+    const int j0 = start[tr], j1 = start[tr + 1];
     if (j0 == j1) return;
     const int pt2 = ptgt * ptgt;
     for (int c = threadIdx.x; c < pt2; c += blockDim.x) {
         C s = dst[t * pt2 + c];
-        for (int q = j0; q < j1; ++q) s = addc(s, W[(int64_t)jobs[q] * P * P + c]);
+        for (int q = j0; q < j1; ++q) s = addc(s, W[((int64_t)jobs[q] * nr + r) * P * P + c]);
         dst[t * pt2 + c] = s;
     }
 }
@@ -459,12 +470,15 @@ void trans_configure_lds(size_t lds_max) {
 // One stage of a batch: 0 forward rotation, 1 coaxial step, 2 back rotation, 3 reduction into
 // the targets.  Returns the HIP kernel's name (for profiling).
 template <class R>
-const char *trans_stage(const TransBatch &b, const TransTables<R> &tb, int stage, const typename Cx<R>::T *src,
+const char *trans_stage(const TransBatch &b, const TransTables<R> &tb, int stage, int nr, const typename Cx<R>::T *src,
                         typename Cx<R>::T *dst, const typename Cx<R>::T *ph, int PH, typename Cx<R>::T *W1,
                         typename Cx<R>::T *W2, hipStream_t st) {
-    TransArgsT<R> a{b.njob, b.JT, b.psrc, b.ptgt, b.P, b.PT, PH, src, dst, b.src, b.tgt, b.dir, b.tile_coax,
-                    b.tile_rot, tb.coax, tb.H, tb.HT, ph, W1, W2};
-    const unsigned ntile = (unsigned)((b.njob + b.JT - 1) / b.JT);
+    if (nr < 1 || b.JT % nr) throw FmmError(-1, "right-hand-side count must divide the tile size");
+    TransArgsT<R> a{b.njob * nr, b.JT, b.psrc, b.ptgt, b.P, b.PT, PH, nr, src, dst, b.src, b.tgt, b.dir,
+                    b.tile_coax, b.tile_rot, tb.coax, tb.H, tb.HT, ph, W1, W2};
+    // classes are padded to whole tiles of JT real jobs, so a tile of JT virtual jobs never
+    // mixes tables: virtual tile t uses the tables of real tile t / nr
+    const unsigned ntile = (unsigned)((b.njob * nr + b.JT - 1) / b.JT);
     // LDS sized for the scalar type
     const size_t lds = trans_lds_bytes(b.JT, b.P, b.whole) / (sizeof(double) / sizeof(R));
     const bool f32 = sizeof(R) == 4;
@@ -483,16 +497,17 @@ const char *trans_stage(const TransBatch &b, const TransTables<R> &tb, int stage
         else k_tr_rot_back<R><<<dim3(ntile, b.ptgt), 256, lds, st>>>(a), name = f32 ? "k_tr_rot_back_f32" : "k_tr_rot_back";
         break;
     default:
-        k_tr_reduce<typename Cx<R>::T><<<(unsigned)b.ntgt, 256, 0, st>>>(b.ntgt, b.ptgt, b.P, b.tgt_start, b.tgt_jobs, W1, dst);
+        k_tr_reduce<typename Cx<R>::T><<<(unsigned)(b.ntgt * nr), 256, 0, st>>>(b.ntgt, nr, b.ptgt, b.P, b.tgt_start,
+                                                                                b.tgt_jobs, W1, dst);
         name = f32 ? "k_tr_reduce_f32" : "k_tr_reduce";
     }
     LAUNCH_OK();
     return name;
 }
 
-template const char *trans_stage<double>(const TransBatch &, const TransTables<double> &, int, const double2 *,
+template const char *trans_stage<double>(const TransBatch &, const TransTables<double> &, int, int, const double2 *,
                                          double2 *, const double2 *, int, double2 *, double2 *, hipStream_t);
-template const char *trans_stage<float>(const TransBatch &, const TransTables<float> &, int, const float2 *, float2 *,
+template const char *trans_stage<float>(const TransBatch &, const TransTables<float> &, int, int, const float2 *, float2 *,
                                         const float2 *, int, float2 *, float2 *, hipStream_t);
 
 }  // namespace fmm

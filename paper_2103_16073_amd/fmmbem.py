@@ -33,7 +33,8 @@ class c64(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("rc_factor", ctypes.c_double), ("rc", ctypes.c_double), ("leaf_max", ctypes.c_int),
                 ("p_min", ctypes.c_int), ("p_excess", ctypes.c_double), ("ktau_switch", ctypes.c_double),
-                ("max_depth", ctypes.c_int), ("lds_budget", ctypes.c_int)]
+                ("max_depth", ctypes.c_int), ("lds_budget", ctypes.c_int), ("graphs", ctypes.c_int),
+                ("autotune", ctypes.c_int)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -76,6 +77,9 @@ EXPORTS = {
     "fmmbem_setup": (ctypes.c_int, [ctypes.c_void_p]),
     "fmmbem_num_unknowns": (ctypes.c_int64, [ctypes.c_void_p]),
     "fmmbem_rhs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "fmmbem_solve_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(SolveOpts),
+                                          ctypes.c_void_p, ctypes.c_void_p]),
+    "fmmbem_release_workspace": (ctypes.c_int, [ctypes.c_void_p]),
     "fmmbem_solve_history": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                             ctypes.POINTER(ctypes.c_int32)]),
     "fmmbem_matvec": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
@@ -216,6 +220,23 @@ class Context:
         rep = SolveReport()
         rc = self._check(lib().fmmbem_solve(self.h, isrc, ctypes.byref(o), _ptr(x), ctypes.byref(rep)))
         return x, rep, rc
+
+    def fmmbem_solve_batch(self, isrc, x0=None, **kw):
+        o = default_solve_opts()
+        for k, v in kw.items():
+            setattr(o, k, v)
+        n = self.fmmbem_num_unknowns()
+        src = np.ascontiguousarray(isrc, np.int32)
+        ns = src.shape[0]
+        x = np.zeros((ns, n), np.complex128) if x0 is None else _c(x0).reshape(ns, n).copy()
+        if x0 is not None:
+            o.use_x0 = 1
+        reps = (SolveReport * ns)()
+        rc = self._check(lib().fmmbem_solve_batch(self.h, ns, _ptr(src), ctypes.byref(o), _ptr(x), reps))
+        return x, list(reps), rc
+
+    def fmmbem_release_workspace(self):
+        self._check(lib().fmmbem_release_workspace(self.h))
 
     def fmmbem_solve_history(self):
         cnt = ctypes.c_int32()

@@ -205,6 +205,81 @@ def test_solve_inner_outer_vs_oracle_lu(F, cfg1_dense):
     ctx.close()
 
 
+@pytest.mark.parametrize("leaf_max,lds_budget", [(12, 0), (12, 8192), (64, 0)])
+def test_matvec_multi_rhs(F, cfg1_dense, leaf_max, lds_budget):
+    """Seven vectors in one call (chunks of 4, 2 and 1 vectors sharing kernel evaluations,
+    basis functions and translation tables) give the single-vector products and match the
+    oracle's dense operator (FP64 <= 1e-6, mixed <= 1e-4)."""
+    room, k = cfg1_dense
+    ctx = make_ctx(F, room, k, leaf_max=leaf_max, lds_budget=lds_budget)
+    info = ctx.fmmbem_get_info()
+    L, M = bem.dense_LM(room.vertices, room.triangles, k, info.rc)
+    X = np.stack([synth.complex_normal(room.n, 20 + s) for s in range(7)])
+    for prec, tol_single, tol_oracle in ((F.FMMBEM_FP64, 1e-12, 1e-6), (F.FMMBEM_MIXED, 1e-6, 1e-4)):
+        Y = ctx.fmmbem_matvec(X, precision=prec)
+        for s in range(7):
+            y1 = ctx.fmmbem_matvec(X[s], precision=prec)[0]
+            assert np.linalg.norm(Y[s] - y1) / np.linalg.norm(y1) < tol_single
+            ref = 0.5 * X[s] + M @ X[s] - 1j * k * L @ (room.beta * X[s])
+            assert np.linalg.norm(Y[s] - ref) / np.linalg.norm(ref) < tol_oracle
+    # all-pairs product with several vectors
+    Ye = ctx.fmmbem_matvec(X[:4], exact_far=True)
+    for s in range(4):
+        ref = 0.5 * X[s] + M @ X[s] - 1j * k * L @ (room.beta * X[s])
+        assert np.linalg.norm(Ye[s] - ref) / np.linalg.norm(ref) < 1e-12
+    ctx.close()
+
+
+def test_solve_batch_vs_single_and_lu(F, cfg1_dense):
+    """Three sources solved in lock step with batched products: each solution equals its own
+    single-source solve and the oracle's LU solution."""
+    room, k = cfg1_dense
+    ctx = make_ctx(F, room, k)
+    rs, _ = synth.source_and_receivers(room, 4, nsrc=3)
+    ctx.fmmbem_set_sources(rs)
+    srcs = [0, 1, 2]
+    Xb, reps, rc_ = ctx.fmmbem_solve_batch(srcs, tol=1e-8, restart=40, maxit=300)
+    assert rc_ == 0
+    rc = ctx.fmmbem_get_info().rc
+    for s in srcs:
+        assert reps[s].status == 0 and reps[s].rel_res < 1e-8
+        x1, rep1, rc1 = ctx.fmmbem_solve(s, tol=1e-8, restart=40, maxit=300)
+        assert rc1 == 0
+        assert np.linalg.norm(Xb[s] - x1) / np.linalg.norm(x1) < 1e-6
+        A, b, _, _ = bem.direct_system(room.vertices, room.triangles, k, room.beta, rs[s], rc)
+        x_ref = bem.solve_lu(A, b)
+        assert np.linalg.norm(Xb[s] - x_ref) / np.linalg.norm(x_ref) < 1e-5
+    ctx.close()
+
+
+@pytest.mark.parametrize("nr,prec", [(1, 0), (4, 0), (1, 1), (3, 1)])
+def test_matvec_graph_replays_match_eager(F, cfg1_dense, nr, prec):
+    """Products on device vectors replay a captured HIP graph; every replay, with eager
+    products, other graphs and synchronisations in between, equals the eager product."""
+    import torch
+    room, k = cfg1_dense
+    ctx = make_ctx(F, room, k, leaf_max=12)
+    X = np.stack([synth.complex_normal(room.n, 40 + s) for s in range(nr)])
+    ref = ctx.fmmbem_matvec(X, precision=prec)  # eager (host entry point)
+    dev = torch.device("cuda:0")
+    xd = torch.from_numpy(X).to(dev)
+    yd = torch.empty_like(xd)
+    other = torch.from_numpy(np.stack([synth.complex_normal(room.n, 90)] * 2)).to(dev)
+    oy = torch.empty_like(other)
+    for rep in range(4):
+        yd.zero_()
+        ctx.fmmbem_matvec_dev(xd.data_ptr(), yd.data_ptr(), nrhs=nr, precision=prec)
+        torch.cuda.synchronize()
+        y = yd.cpu().numpy()
+        err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+        assert err < 1e-13, (rep, err)
+        # unrelated work between replays: an eager product and a graph of another shape
+        ctx.fmmbem_matvec(X[:1], precision=prec)
+        ctx.fmmbem_matvec_dev(other.data_ptr(), oy.data_ptr(), nrhs=2, precision=1 - prec)
+        torch.cuda.synchronize()
+    ctx.close()
+
+
 def test_rhs_vs_oracle(F, cfg1_dense):
     room, k = cfg1_dense
     ctx = make_ctx(F, room, k)
