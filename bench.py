@@ -133,6 +133,31 @@ def main():
     for s in stats_m:
         log(f"  {s['name']:20s} {s['ms'] / args.steps:9.3f} ms/step")
 
+    # several vectors per product (the batched solves' products): 4 seeded vectors at once
+    batched = {}
+    X4 = torch.from_numpy(synth.complex_normal(n, 31, count=4)).to(dev)
+    Y4 = torch.empty_like(X4)
+    for name, prec in (("fp64", F.FMMBEM_FP64), ("mixed", F.FMMBEM_MIXED)):
+        for _ in range(max(1, args.warmup)):
+            ctx.fmmbem_matvec_dev(X4.data_ptr(), Y4.data_ptr(), nrhs=4, precision=prec, stream=sp)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.fmmbem_matvec_dev(X4.data_ptr(), Y4.data_ptr(), nrhs=4, precision=prec, stream=sp)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        # check against single-vector products
+        y1 = torch.empty_like(X4[0])
+        ctx.fmmbem_matvec_dev(X4[3].data_ptr(), y1.data_ptr(), nrhs=1, precision=prec, stream=sp)
+        torch.cuda.synchronize()
+        d = float(torch.linalg.norm(Y4[3] - y1) / torch.linalg.norm(y1))
+        batched[name] = {"vectors": 4, "ms_per_product": 1e3 * tb / args.steps,
+                         "vector_products_per_s": 4 * args.steps / tb, "rel_diff_vs_single": d}
+        log(f"4-vector products {name}: {1e3 * tb / args.steps:.2f} ms, {4 * args.steps / tb:.2f} vector products/s, "
+            f"diff vs single {d:.1e}")
+    del X4, Y4
+    ctx.fmmbem_release_workspace()
+
     result = {
         "metric": "FMM-BEM matvecs/s at N=1M",
         "value": value,
@@ -154,6 +179,7 @@ def main():
         "phases_ms": phases,
         "roofline": roofline,
         "mixed_precision": mixed,
+        "four_vector_products": batched,
     }
 
     if not args.no_solve:

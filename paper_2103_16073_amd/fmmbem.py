@@ -104,6 +104,15 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise FmmbemError(FMMBEM_EDEVICE, f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        # PyTorch (device memory and streams for the *_dev entry points) ships its own HIP
+        # runtime; it has to come up before this library's runtime touches the device, or it
+        # finds no GPU afterwards.
+        try:
+            import torch
+            if torch.cuda.is_available():
+                torch.cuda.init()
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in EXPORTS.items():
             f = getattr(L, name)
