@@ -71,7 +71,10 @@ enum {
 enum {
     FMMBEM_PC_NONE = 0,
     FMMBEM_PC_DIAG = 1,       /* z_i = v_i / (A_ii + diag_shift) */
-    FMMBEM_PC_NEARBLOCK = 2   /* exact inverse of the operator restricted to each octree leaf */
+    FMMBEM_PC_NEARBLOCK = 2,  /* exact inverse of the operator restricted to each octree leaf */
+    FMMBEM_PC_LEARNED = 3     /* NEARBLOCK plus a trained per-leaf MLP correction (fmmbem_learned_train),
+                                 dropped for the rest of the solve when the residual falls behind the
+                                 plain solver's (guard) */
 };
 
 /* construction options; pass NULL for defaults */
@@ -168,6 +171,8 @@ typedef struct {
     int64_t matvecs_fp64;  /* FMM products of the call, by arithmetic (outer, restart and inner) */
     int64_t matvecs_mixed;
     int64_t inner_iters;   /* total inner GMRES steps */
+    int32_t pc_fallback_at; /* FMMBEM_PC_LEARNED: iteration at which the guard dropped the learned
+                               correction, -1 if it acted throughout */
 } fmmbem_solve_report;
 
 void fmmbem_default_solve_opts(fmmbem_solve_opts *o);
@@ -187,6 +192,53 @@ int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, f
  * first failure or FMMBEM_ENOCONV.  inner_iters must be 0. */
 int fmmbem_solve_batch(fmmbem_ctx *ctx, int32_t ns, const int32_t *isrc, const fmmbem_solve_opts *opts,
                        fmmbem_c64 *x, fmmbem_solve_report *rep);
+
+/* ---- learned preconditioner ------------------------------------------------------------
+ * A multilayer perceptron applied to every chunk of <= 64 consecutive unknowns of an octree
+ * leaf: input 140 = the chunk's residual over its norm (64 complex, zero padded), k times the
+ * leaf side, occupancy/64, mean and spread of the normals, mean admittance, a constant 1;
+ * three ReLU layers of 128; output 128 = correction d (64 complex) added as |v_chunk| d to the
+ * near-field block step.  Weights: FP16 in the forward pass, FP32 master copy, FP32
+ * accumulation.  Parameter vector layout: per layer W (in x out, row-major) then b (out). */
+typedef struct {
+    int restart;      /* Krylov dimension of the data-generating plain solve; its restart iterates
+                         x_k with residuals r_k give the pairs (r_k, x* - x_k); default 8 */
+    int max_pairs;    /* pairs kept (earliest first); default 12 */
+    double tol;       /* accuracy of that solve (its final iterate is x*); default 1e-7 */
+    int maxit;        /* its iteration cap; default 400 */
+    int epochs;       /* passes over the samples; default 60 */
+    int batch;        /* samples per Adam step; default 2048 */
+    double lr;        /* Adam step size; default 1e-3 */
+    uint64_t seed;    /* weight initialisation and sample order; default 1 */
+} fmmbem_train_opts;
+
+typedef struct {
+    int64_t samples;      /* chunks x pairs used */
+    int32_t pairs;
+    int32_t solve_iters;  /* iterations of the data-generating solve */
+    double solve_rel_res;
+    double loss_zero;     /* mean squared target (loss of a zero correction) */
+    double loss_first;    /* mean loss over the first epoch */
+    double loss_last;     /* mean loss over the last epoch */
+    double t_data_s, t_train_s;
+} fmmbem_train_report;
+
+void fmmbem_default_train_opts(fmmbem_train_opts *o);
+
+/* Generate residual/error pairs with the plain near-field-block FGMRES on source isrc, then
+ * train the network on them (Adam).  The trained weights stay in the context. */
+int fmmbem_learned_train(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_train_opts *opts, fmmbem_train_report *rep);
+
+/* Direct access to the network for checks: parameter count, seeded initialisation, weights
+ * (host float arrays of fmmbem_mlp_param_count()), forward pass Y = net(X) (X: m x 140,
+ * Y: m x 128, host), and the mean squared error sum_i |net(X_i) - T_i|^2 / m with its
+ * gradient (packed like the weights). */
+int64_t fmmbem_mlp_param_count(void);
+int fmmbem_mlp_init(fmmbem_ctx *ctx, uint64_t seed);
+int fmmbem_mlp_get_weights(fmmbem_ctx *ctx, float *w);
+int fmmbem_mlp_set_weights(fmmbem_ctx *ctx, const float *w);
+int fmmbem_mlp_forward(fmmbem_ctx *ctx, int64_t m, const float *X, float *Y);
+int fmmbem_mlp_loss_grad(fmmbem_ctx *ctx, int64_t m, const float *X, const float *T, float *loss, float *grad);
 
 /* Free the per-call work arrays (Krylov bases, translation work rows, staging) now rather
  * than at fmmbem_destroy; they are allocated again when next needed.  Captured product graphs

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libfmmbem.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["api.cpp", "tree.cpp", "tables.hip", "fmm.hip", "trans.hip", "solver.hip"]
+SOURCES = ["api.cpp", "tree.cpp", "tables.hip", "fmm.hip", "trans.hip", "solver.hip", "learned.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

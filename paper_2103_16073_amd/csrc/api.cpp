@@ -58,7 +58,7 @@ int fgmres(int64_t n, hipStream_t st, DeviceBuffers &scr, const char *tag,
            const std::function<void(const double2 *, double2 *)> &matvec_check,
            const std::function<void(const double2 *, double2 *)> &precond, const double2 *b, double2 *x, double tol,
            int m, int maxit, bool x0_given, bool final_residual, std::vector<double> *history, int &iters,
-           int &restarts, double &rel_res);
+           int &restarts, double &rel_res, const FgmresHooks *hooks);
 
 void drop_graphs(fmmbem_ctx *c);
 
@@ -413,7 +413,10 @@ static void ensure_setup(fmmbem_ctx *c) {
     if (!c->have_k) throw FmmError(FMMBEM_ENOTREADY, "wavenumber not set");
     auto t0 = std::chrono::steady_clock::now();
     bool any = c->mesh_dirty || c->k_dirty || c->beta_dirty;
-    if (any) drop_graphs(c);
+    if (any) {
+        drop_graphs(c);
+        c->chunks_ready = false;
+    }
     if (c->mesh_dirty) {
         setup_mesh(c);
         c->k_dirty = true;
@@ -1119,10 +1122,65 @@ int fmmbem_last_timings(fmmbem_ctx *ctx, double *ms8) {
 }
 
 // Preconditioner of the solve options (data built on first use): z = P v on device vectors.
+// Chunks of at most 64 consecutive unknowns per leaf (the learned preconditioner's samples).
+static void ensure_chunks(fmmbem_ctx *c) {
+    if (c->chunks_ready) return;
+    const TreeHost &T = c->tree;
+    const int nleaf = (int)T.leaf_start.size() - 1;
+    std::vector<int32_t> cs, cn, cl;
+    for (int b = 0; b < nleaf; ++b)
+        for (int s = T.leaf_start[b]; s < T.leaf_start[b + 1]; s += 64) {
+            cs.push_back(s);
+            cn.push_back(std::min(64, T.leaf_start[b + 1] - s));
+            cl.push_back(b);
+        }
+    c->nchunk = (int64_t)cs.size();
+    upload(c->buf, "ch_s", cs, c->stream);
+    upload(c->buf, "ch_n", cn, c->stream);
+    upload(c->buf, "ch_l", cl, c->stream);
+    std::vector<double> ka(nleaf, c->k * c->lev[T.depth].side);
+    upload(c->buf, "leaf_ka", ka, c->stream);
+    HIP_OK(hipStreamSynchronize(c->stream));
+    c->chunks_ready = true;
+}
+
+// features of v on every chunk -> network output, chunk norms (scratch arrays)
+static void mlp_run(fmmbem_ctx *c, const double2 *v, float **out, float **scale) {
+    hipStream_t st = c->stream;
+    const int64_t M = c->nchunk;
+    float *X = dget<float>(c->scratch, "mlp_X", (size_t)M * MLP_IN);
+    float *sc = dget<float>(c->scratch, "mlp_scale", M);
+    float *A[4];
+    for (int l = 0; l < 4; ++l) A[l] = dget<float>(c->scratch, "mlp_A" + std::to_string(l), (size_t)M * MLP_H);
+    mlp_features(M, (int32_t *)c->buf.find("ch_s"), (int32_t *)c->buf.find("ch_n"), (int32_t *)c->buf.find("ch_l"),
+                 (int32_t *)c->buf.find("perm"), v, (double4 *)c->buf.find("en"), (double2 *)c->buf.find("beta"),
+                 (double *)c->buf.find("leaf_ka"), X, sc, st);
+    c->mlp.forward(M, X, A, st);
+    *out = A[3];
+    *scale = sc;
+}
+
 static std::function<void(const double2 *, double2 *)> make_precond(fmmbem_ctx *ctx, const fmmbem_solve_opts &o) {
     hipStream_t st = ctx->stream;
     const int64_t n = ctx->nt;
     const int nleaf = (int)ctx->tree.leaf_start.size() - 1;
+    if (o.precond == FMMBEM_PC_LEARNED) {
+        if (!ctx->mlp.ready) throw FmmError(FMMBEM_ENOTREADY, "learned preconditioner not trained");
+        fmmbem_solve_opts nb = o;
+        nb.precond = FMMBEM_PC_NEARBLOCK;
+        auto base = make_precond(ctx, nb);
+        ensure_chunks(ctx);
+        const int32_t *cs = (int32_t *)ctx->buf.find("ch_s"), *cn = (int32_t *)ctx->buf.find("ch_n");
+        const int32_t *pm = (int32_t *)ctx->buf.find("perm");
+        // z = P_near v + learned correction while the guard keeps it (mlp_active)
+        return [=](const double2 *v, double2 *z) {
+            base(v, z);
+            if (!ctx->mlp_active) return;
+            float *Y, *sc;
+            mlp_run(ctx, v, &Y, &sc);
+            mlp_apply(ctx->nchunk, cs, cn, pm, Y, sc, z, st);
+        };
+    }
     // preconditioner data
     if (o.precond == FMMBEM_PC_DIAG) {
         double2 *dinv = dget<double2>(ctx->buf, "pc_dinv", n);
@@ -1186,7 +1244,7 @@ static int check_solve_opts(fmmbem_ctx *ctx, const fmmbem_solve_opts &o) {
     if (o.inner_iters < 0 || (o.inner_iters > 0 && !(o.inner_tol > 0)) ||
         (o.inner_precision != FMMBEM_FP64 && o.inner_precision != FMMBEM_MIXED))
         return fail(ctx, FMMBEM_EINVAL, "bad inner solve options");
-    if (o.precond < FMMBEM_PC_NONE || o.precond > FMMBEM_PC_NEARBLOCK) return fail(ctx, FMMBEM_EINVAL, "unknown preconditioner");
+    if (o.precond < FMMBEM_PC_NONE || o.precond > FMMBEM_PC_LEARNED) return fail(ctx, FMMBEM_EINVAL, "unknown preconditioner");
     return FMMBEM_OK;
 }
 
@@ -1234,7 +1292,7 @@ int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, f
             int it = 0, rs = 0;
             double rr = 1.0;
             int s = fgmres(n, st, ctx->scratch, "in_", imv, imv, pc, v, z, o.inner_tol, o.inner_iters, o.inner_iters,
-                           false, false, nullptr, it, rs, rr);
+                           false, false, nullptr, it, rs, rr, nullptr);
             if (s < 0) throw FmmError(s, "inner GMRES failed");
             inner_its += it;
         };
@@ -1242,8 +1300,32 @@ int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, f
     int iters = 0, restarts = 0;
     double rel = 1.0;
     ctx->history.clear();
+    // Guard of the learned correction: it stays only while the residual keeps pace with the
+    // plain solver's (3x margin on the training run's estimates, iteration by iteration) and
+    // every restart's true FP64 residual improves on the previous one.
+    int fallback_at = -1;
+    double last_true = 2.0;  // lives as long as the hooks that refer to it
+    FgmresHooks hk;
+    if (o.precond == FMMBEM_PC_LEARNED) {
+        ctx->mlp_active = true;
+        hk.on_iter = [&](int it, double est) {
+            const auto &ref = ctx->mlp_ref_hist;
+            if (ctx->mlp_active && it >= 1 && it <= (int)ref.size() && est > 3.0 * ref[it - 1]) {
+                ctx->mlp_active = false;
+                fallback_at = it;
+            }
+        };
+        hk.on_restart = [&](const double2 *, const double2 *, double r) {
+            if (ctx->mlp_active && r > last_true) {
+                ctx->mlp_active = false;
+                fallback_at = iters;
+            }
+            last_true = r;
+        };
+    }
     int status = fgmres(n, st, ctx->scratch, "", mv, mv64, outer_pc, b, dx, o.tol, o.restart, o.maxit, o.use_x0 != 0,
-                        true, &ctx->history, iters, restarts, rel);
+                        true, &ctx->history, iters, restarts, rel, &hk);
+    ctx->mlp_active = false;
     HIP_OK(hipMemcpyAsync(x, dx, sizeof(double2) * n, hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
     if (rep) {
@@ -1256,6 +1338,7 @@ int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, f
         rep->matvecs_fp64 = n64;
         rep->matvecs_mixed = nmx;
         rep->inner_iters = inner_its;
+        rep->pc_fallback_at = fallback_at;
     }
     if (status < 0) ctx->err = "solver failed";
     return status;
@@ -1271,6 +1354,7 @@ int fmmbem_solve_batch(fmmbem_ctx *ctx, int32_t ns, const int32_t *isrc, const f
     if (opts) o = *opts;
     if (int e = check_solve_opts(ctx, o)) return e;
     if (o.inner_iters > 0) return fail(ctx, FMMBEM_EINVAL, "the batched solve has no inner-outer scheme");
+    if (o.precond == FMMBEM_PC_LEARNED) return fail(ctx, FMMBEM_EINVAL, "the batched solve has no learned guard");
     GUARD_BEGIN
     HIP_OK(hipSetDevice(ctx->device));
     if (ctx->src.empty()) return fail(ctx, FMMBEM_ENOTREADY, "sources not set");
@@ -1317,6 +1401,7 @@ int fmmbem_solve_batch(fmmbem_ctx *ctx, int32_t ns, const int32_t *isrc, const f
             rep[s].matvecs_fp64 = n64;  // products of the whole batch
             rep[s].matvecs_mixed = nmx;
             rep[s].inner_iters = 0;
+            rep[s].pc_fallback_at = -1;
         }
         if (status[s] < 0) worst = status[s];
         else if (status[s] != FMMBEM_OK && worst == FMMBEM_OK) worst = status[s];
@@ -1324,6 +1409,225 @@ int fmmbem_solve_batch(fmmbem_ctx *ctx, int32_t ns, const int32_t *isrc, const f
     if (rc < 0) return fail(ctx, rc, "batched solver failed");
     if (worst < 0) ctx->err = "solver failed";
     return worst;
+    GUARD_END
+}
+
+// ------------------------------------------------------------------ learned preconditioner
+void fmmbem_default_train_opts(fmmbem_train_opts *o) {
+    o->restart = 8;
+    o->max_pairs = 12;
+    o->tol = 1e-7;
+    o->maxit = 400;
+    o->epochs = 60;
+    o->batch = 2048;
+    o->lr = 1e-3;
+    o->seed = 1;
+}
+
+int64_t fmmbem_mlp_param_count(void) { return mlp_param_count(); }
+
+int fmmbem_mlp_init(fmmbem_ctx *ctx, uint64_t seed) {
+    if (!ctx) return FMMBEM_EINVAL;
+    GUARD_BEGIN
+    HIP_OK(hipSetDevice(ctx->device));
+    ctx->mlp.init(ctx->buf, seed, ctx->stream);
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    return FMMBEM_OK;
+    GUARD_END
+}
+
+int fmmbem_mlp_get_weights(fmmbem_ctx *ctx, float *w) {
+    if (!ctx || !w) return FMMBEM_EINVAL;
+    if (!ctx->mlp.ready) return fail(ctx, FMMBEM_ENOTREADY, "network not initialised");
+    GUARD_BEGIN
+    HIP_OK(hipSetDevice(ctx->device));
+    HIP_OK(hipMemcpyAsync(w, ctx->mlp.w32, sizeof(float) * mlp_param_count(), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    return FMMBEM_OK;
+    GUARD_END
+}
+
+int fmmbem_mlp_set_weights(fmmbem_ctx *ctx, const float *w) {
+    if (!ctx || !w) return FMMBEM_EINVAL;
+    GUARD_BEGIN
+    HIP_OK(hipSetDevice(ctx->device));
+    if (!ctx->mlp.ready) ctx->mlp.init(ctx->buf, 1, ctx->stream);
+    HIP_OK(hipMemcpyAsync(ctx->mlp.w32, w, sizeof(float) * mlp_param_count(), hipMemcpyHostToDevice, ctx->stream));
+    ctx->mlp.sync_half(ctx->stream);
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    return FMMBEM_OK;
+    GUARD_END
+}
+
+static void mlp_upload_batch(fmmbem_ctx *ctx, int64_t m, const float *X, const float *T, float **Xd, float **Td,
+                             float *A[4]) {
+    hipStream_t st = ctx->stream;
+    *Xd = dget<float>(ctx->scratch, "mlpt_X", (size_t)m * MLP_IN);
+    HIP_OK(hipMemcpyAsync(*Xd, X, sizeof(float) * m * MLP_IN, hipMemcpyHostToDevice, st));
+    if (T) {
+        *Td = dget<float>(ctx->scratch, "mlpt_T", (size_t)m * MLP_OUT);
+        HIP_OK(hipMemcpyAsync(*Td, T, sizeof(float) * m * MLP_OUT, hipMemcpyHostToDevice, st));
+    }
+    for (int l = 0; l < 4; ++l) A[l] = dget<float>(ctx->scratch, "mlpt_A" + std::to_string(l), (size_t)m * MLP_H);
+}
+
+int fmmbem_mlp_forward(fmmbem_ctx *ctx, int64_t m, const float *X, float *Y) {
+    if (!ctx || !X || !Y || m < 1) return FMMBEM_EINVAL;
+    if (!ctx->mlp.ready) return fail(ctx, FMMBEM_ENOTREADY, "network not initialised");
+    GUARD_BEGIN
+    HIP_OK(hipSetDevice(ctx->device));
+    float *Xd, *A[4];
+    mlp_upload_batch(ctx, m, X, nullptr, &Xd, nullptr, A);
+    ctx->mlp.forward(m, Xd, A, ctx->stream);
+    HIP_OK(hipMemcpyAsync(Y, A[3], sizeof(float) * m * MLP_OUT, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    return FMMBEM_OK;
+    GUARD_END
+}
+
+int fmmbem_mlp_loss_grad(fmmbem_ctx *ctx, int64_t m, const float *X, const float *T, float *loss, float *grad) {
+    if (!ctx || !X || !T || !loss || !grad || m < 1) return FMMBEM_EINVAL;
+    if (!ctx->mlp.ready) return fail(ctx, FMMBEM_ENOTREADY, "network not initialised");
+    GUARD_BEGIN
+    HIP_OK(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    float *Xd, *Td, *A[4];
+    mlp_upload_batch(ctx, m, X, T, &Xd, &Td, A);
+    float *g = dget<float>(ctx->scratch, "mlpt_g", mlp_param_count());
+    float *ld = dget<float>(ctx->scratch, "mlpt_loss", 1);
+    ctx->mlp.forward(m, Xd, A, st);
+    ctx->mlp.backward(m, Xd, A, Td, g, ld, ctx->scratch, st);
+    HIP_OK(hipMemcpyAsync(grad, g, sizeof(float) * mlp_param_count(), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(loss, ld, sizeof(float), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    return FMMBEM_OK;
+    GUARD_END
+}
+
+int fmmbem_learned_train(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_train_opts *opts, fmmbem_train_report *rep) {
+    if (!ctx) return FMMBEM_EINVAL;
+    fmmbem_train_opts o;
+    fmmbem_default_train_opts(&o);
+    if (opts) o = *opts;
+    if (o.restart < 1 || o.max_pairs < 1 || o.maxit < 1 || !(o.tol > 0) || o.epochs < 0 || o.batch < 1 || !(o.lr > 0))
+        return fail(ctx, FMMBEM_EINVAL, "bad training options");
+    GUARD_BEGIN
+    HIP_OK(hipSetDevice(ctx->device));
+    if (ctx->src.empty()) return fail(ctx, FMMBEM_ENOTREADY, "sources not set");
+    if (isrc < 0 || isrc >= (int)(ctx->src.size() / 3)) return fail(ctx, FMMBEM_EINVAL, "bad source index");
+    ensure_setup(ctx);
+    ensure_chunks(ctx);
+    hipStream_t st = ctx->stream;
+    const int64_t n = ctx->nt, nch = ctx->nchunk;
+    auto t0 = std::chrono::steady_clock::now();
+    // 1. the plain solver's restart iterates and residuals
+    fmmbem_solve_opts so;
+    fmmbem_default_solve_opts(&so);
+    so.precond = FMMBEM_PC_NEARBLOCK;
+    auto pc = make_precond(ctx, so);
+    double2 *b = dget<double2>(ctx->scratch, "tr_b", n), *x = dget<double2>(ctx->scratch, "tr_x", n);
+    double2 *XS = dget<double2>(ctx->scratch, "tr_xs", (size_t)o.max_pairs * n);
+    double2 *RS = dget<double2>(ctx->scratch, "tr_rs", (size_t)o.max_pairs * n);
+    rhs_dev(ctx, isrc, b);
+    std::vector<double> prel;
+    FgmresHooks hk;
+    hk.on_restart = [&](const double2 *xk, const double2 *rk, double rel) {
+        if ((int)prel.size() >= o.max_pairs) return;
+        const size_t q = prel.size();
+        HIP_OK(hipMemcpyAsync(XS + q * n, xk, sizeof(double2) * n, hipMemcpyDeviceToDevice, st));
+        HIP_OK(hipMemcpyAsync(RS + q * n, rk, sizeof(double2) * n, hipMemcpyDeviceToDevice, st));
+        prel.push_back(rel);
+    };
+    std::vector<double> hist;
+    auto mv = [&](const double2 *a, double2 *y) { matvec_dev(ctx, 1, a, y, false, false); };
+    int iters = 0, restarts = 0;
+    double rel = 1.0;
+    fgmres(n, st, ctx->scratch, "tr_", mv, mv, pc, b, x, o.tol, o.restart, o.maxit, false, true, &hist, iters, restarts,
+           rel, &hk);
+    ctx->mlp_ref_hist = hist;
+    // 2. samples: features of r_k, targets (x* - x_k - P_near r_k) / |r_k| per chunk
+    std::vector<int> keep;
+    for (size_t q = 0; q < prel.size(); ++q)
+        if (prel[q] > 100.0 * rel) keep.push_back((int)q);
+    if (keep.empty()) throw FmmError(FMMBEM_EINVAL, "no usable residual/error pairs (solve converged too early)");
+    const int64_t M = (int64_t)keep.size() * nch;
+    float *Xall = dget<float>(ctx->scratch, "tr_X", (size_t)M * MLP_IN);
+    float *Tall = dget<float>(ctx->scratch, "tr_T", (size_t)M * MLP_OUT);
+    double2 *e = dget<double2>(ctx->scratch, "tr_e", n), *z0 = dget<double2>(ctx->scratch, "tr_z0", n);
+    float *sc = dget<float>(ctx->scratch, "tr_sc", nch);
+    const int32_t *cs = (int32_t *)ctx->buf.find("ch_s"), *cn = (int32_t *)ctx->buf.find("ch_n");
+    const int32_t *cl = (int32_t *)ctx->buf.find("ch_l"), *pm = (int32_t *)ctx->buf.find("perm");
+    for (size_t q = 0; q < keep.size(); ++q) {
+        const double2 *rk = RS + (size_t)keep[q] * n;
+        vec_sub(n, x, XS + (size_t)keep[q] * n, e, st);
+        pc(rk, z0);
+        mlp_features(nch, cs, cn, cl, pm, rk, (double4 *)ctx->buf.find("en"), (double2 *)ctx->buf.find("beta"),
+                     (double *)ctx->buf.find("leaf_ka"), Xall + q * nch * MLP_IN, sc, st);
+        mlp_target(nch, cs, cn, pm, e, z0, sc, Tall + q * nch * MLP_OUT, st);
+    }
+    HIP_OK(hipStreamSynchronize(st));
+    auto t1 = std::chrono::steady_clock::now();
+    // mean squared target = loss of a zero correction
+    double lz = 0.0;
+    {
+        std::vector<float> th((size_t)M * MLP_OUT);
+        HIP_OK(hipMemcpy(th.data(), Tall, sizeof(float) * th.size(), hipMemcpyDeviceToHost));
+        for (float v : th) lz += (double)v * v;
+        lz /= (double)M;
+    }
+    // 3. Adam over shuffled mini-batches
+    ctx->mlp.init(ctx->buf, o.seed, st);
+    const int64_t B = std::min<int64_t>(o.batch, M);
+    float *Xb = dget<float>(ctx->scratch, "tr_Xb", (size_t)B * MLP_IN), *Tb = dget<float>(ctx->scratch, "tr_Tb", (size_t)B * MLP_OUT);
+    float *A[4];
+    for (int l = 0; l < 4; ++l) A[l] = dget<float>(ctx->scratch, "tr_A" + std::to_string(l), (size_t)B * MLP_H);
+    float *g = dget<float>(ctx->scratch, "tr_g", mlp_param_count()), *ld = dget<float>(ctx->scratch, "tr_loss", 1);
+    int64_t *idx = dget<int64_t>(ctx->scratch, "tr_idx", M);
+    std::vector<int64_t> perm_h(M);
+    std::iota(perm_h.begin(), perm_h.end(), 0);
+    uint64_t state = o.seed * 0x9E3779B97F4A7C15ull + 12345;
+    auto next = [&]() {  // SplitMix64
+        uint64_t z = (state += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    };
+    double lfirst = 0, llast = 0;
+    for (int ep = 0; ep < o.epochs; ++ep) {
+        for (int64_t i = M - 1; i > 0; --i) std::swap(perm_h[i], perm_h[next() % (uint64_t)(i + 1)]);
+        HIP_OK(hipMemcpyAsync(idx, perm_h.data(), sizeof(int64_t) * M, hipMemcpyHostToDevice, st));
+        double sum = 0;
+        int nb = 0;
+        for (int64_t s0 = 0; s0 + B <= M; s0 += B) {  // whole batches only
+            gather_rows(B, MLP_IN, idx + s0, Xall, Xb, st);
+            gather_rows(B, MLP_OUT, idx + s0, Tall, Tb, st);
+            ctx->mlp.forward(B, Xb, A, st);
+            ctx->mlp.backward(B, Xb, A, Tb, g, ld, ctx->scratch, st);
+            ctx->mlp.adam_step(g, (float)o.lr, st);
+            float lh = 0;
+            HIP_OK(hipMemcpyAsync(&lh, ld, sizeof(float), hipMemcpyDeviceToHost, st));
+            HIP_OK(hipStreamSynchronize(st));
+            sum += lh;
+            ++nb;
+        }
+        const double mean = nb ? sum / nb : 0.0;
+        if (ep == 0) lfirst = mean;
+        llast = mean;
+    }
+    HIP_OK(hipStreamSynchronize(st));
+    auto t2 = std::chrono::steady_clock::now();
+    if (rep) {
+        rep->samples = M;
+        rep->pairs = (int32_t)keep.size();
+        rep->solve_iters = iters;
+        rep->solve_rel_res = rel;
+        rep->loss_zero = lz;
+        rep->loss_first = lfirst;
+        rep->loss_last = llast;
+        rep->t_data_s = std::chrono::duration<double>(t1 - t0).count();
+        rep->t_train_s = std::chrono::duration<double>(t2 - t1).count();
+    }
+    return FMMBEM_OK;
     GUARD_END
 }
 

@@ -8,6 +8,10 @@
 #include <string>
 #include <vector>
 
+#include <hip/hip_fp16.h>
+
+#include <functional>
+
 #include "../../include/fmmbem.h"
 #include "common.h"
 #include "specfun.h"
@@ -159,6 +163,38 @@ struct Timings {
     double ms[8] = {0};
 };
 
+// ------------------------------------------------------------------ learned preconditioner
+constexpr int MLP_IN = 140, MLP_H = 128, MLP_OUT = 128;
+struct Mlp {
+    float *w32 = nullptr, *m1 = nullptr, *m2 = nullptr;  // master weights and Adam moments (packed)
+    __half *w16 = nullptr;                                // forward copy
+    int64_t step = 0;
+    bool ready = false;
+    void init(DeviceBuffers &buf, uint64_t seed, hipStream_t st);
+    void sync_half(hipStream_t st);
+    void forward(int64_t M, const float *X, float *const A[4], hipStream_t st) const;
+    void backward(int64_t M, const float *X, float *const A[4], const float *T, float *grad, float *loss_dev,
+                  DeviceBuffers &scr, hipStream_t st) const;
+    void adam_step(const float *grad, float lr, hipStream_t st);
+};
+int64_t mlp_param_count();
+void mlp_features(int64_t nchunk, const int32_t *cs, const int32_t *cn, const int32_t *cl, const int32_t *perm,
+                  const double2 *v, const double4 *en, const double2 *beta, const double *leaf_ka, float *X,
+                  float *scale, hipStream_t st);
+void mlp_apply(int64_t nchunk, const int32_t *cs, const int32_t *cn, const int32_t *perm, const float *Y,
+               const float *scale, double2 *z, hipStream_t st);
+void mlp_target(int64_t nchunk, const int32_t *cs, const int32_t *cn, const int32_t *perm, const double2 *e,
+                const double2 *z0, const float *scale, float *T, hipStream_t st);
+
+void gather_rows(int64_t B, int width, const int64_t *idx, const float *src, float *dst, hipStream_t st);
+void vec_sub(int64_t n, const double2 *a, const double2 *b, double2 *out, hipStream_t st);
+
+// optional observers of a flexible GMRES run
+struct FgmresHooks {
+    std::function<void(const double2 *x, const double2 *r, double rel)> on_restart;  // true residual
+    std::function<void(int it, double est)> on_iter;                                  // Arnoldi estimate
+};
+
 }  // namespace fmm
 
 // ---------------------------------------------------------------- the context
@@ -189,6 +225,12 @@ struct fmmbem_ctx {
     double rc = 0.0;
     fmm::TreeHost tree;
     std::vector<fmm::LevelDev> lev;
+    // learned preconditioner: chunks of <= 64 unknowns per leaf, the network, its reference rate
+    fmm::Mlp mlp;
+    int64_t nchunk = 0;
+    bool chunks_ready = false;
+    std::vector<double> mlp_ref_hist;  // plain solver's residual estimates in the training run
+    bool mlp_active = false;           // the guard still lets the learned correction act
     std::vector<std::vector<int32_t>> iota_h;  // per level: 0..nbox (one job per child)
     int pmax = 0, delta_p = 0;
     size_t lds_max = 65536;

@@ -291,7 +291,7 @@ int fgmres(int64_t n, hipStream_t st, DeviceBuffers &scr, const char *tag,
            const std::function<void(const double2 *, double2 *)> &matvec_check,
            const std::function<void(const double2 *, double2 *)> &precond, const double2 *b, double2 *x, double tol,
            int m, int maxit, bool x0_given, bool final_residual, std::vector<double> *history, int &iters,
-           int &restarts, double &rel_res) {
+           int &restarts, double &rel_res, const FgmresHooks *hooks) {
     const std::string tg(tag);
     Blas B{st, scr, n, tg};
     double2 *V = dget<double2>(scr, tg + "fg_V", (size_t)(m + 1) * n);
@@ -327,6 +327,7 @@ int fgmres(int64_t n, hipStream_t st, DeviceBuffers &scr, const char *tag,
         double beta = B.nrm(r);
         rel_res = beta / bn;
         if (!std::isfinite(beta)) return FMMBEM_ENAN;
+        if (hooks && hooks->on_restart) hooks->on_restart(x, r, rel_res);
         if (rel_res < tol) {
             status = FMMBEM_OK;
             break;
@@ -374,6 +375,7 @@ int fgmres(int64_t n, hipStream_t st, DeviceBuffers &scr, const char *tag,
             g[j] = cscale(g[j], cs[j].x);
             est = cabs_(g[j + 1]) / bn;
             if (history) history->push_back(est);
+            if (hooks && hooks->on_iter) hooks->on_iter(iters, est);
             if (est < tol || hn == 0) {
                 ++j;
                 done = true;

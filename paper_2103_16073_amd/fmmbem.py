@@ -17,7 +17,7 @@ FMMBEM_OK, FMMBEM_ENOCONV = 0, 1
 FMMBEM_EINVAL, FMMBEM_ENOMEM, FMMBEM_EDEVICE, FMMBEM_ENOTREADY, FMMBEM_EBREAKDOWN, FMMBEM_ENAN = -1, -2, -3, -4, -5, -6
 FMMBEM_DIRECT = 0
 FMMBEM_FP64, FMMBEM_MIXED = 0, 1
-FMMBEM_PC_NONE, FMMBEM_PC_DIAG, FMMBEM_PC_NEARBLOCK = 0, 1, 2
+FMMBEM_PC_NONE, FMMBEM_PC_DIAG, FMMBEM_PC_NEARBLOCK, FMMBEM_PC_LEARNED = 0, 1, 2, 3
 
 
 class FmmbemError(RuntimeError):
@@ -47,7 +47,20 @@ class SolveOpts(ctypes.Structure):
 class SolveReport(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("restarts", ctypes.c_int), ("rel_res", ctypes.c_double),
                 ("t_setup_s", ctypes.c_double), ("t_solve_s", ctypes.c_double), ("status", ctypes.c_int),
-                ("matvecs_fp64", ctypes.c_int64), ("matvecs_mixed", ctypes.c_int64), ("inner_iters", ctypes.c_int64)]
+                ("matvecs_fp64", ctypes.c_int64), ("matvecs_mixed", ctypes.c_int64), ("inner_iters", ctypes.c_int64),
+                ("pc_fallback_at", ctypes.c_int32)]
+
+
+class TrainOpts(ctypes.Structure):
+    _fields_ = [("restart", ctypes.c_int), ("max_pairs", ctypes.c_int), ("tol", ctypes.c_double),
+                ("maxit", ctypes.c_int), ("epochs", ctypes.c_int), ("batch", ctypes.c_int), ("lr", ctypes.c_double),
+                ("seed", ctypes.c_uint64)]
+
+
+class TrainReport(ctypes.Structure):
+    _fields_ = [("samples", ctypes.c_int64), ("pairs", ctypes.c_int32), ("solve_iters", ctypes.c_int32),
+                ("solve_rel_res", ctypes.c_double), ("loss_zero", ctypes.c_double), ("loss_first", ctypes.c_double),
+                ("loss_last", ctypes.c_double), ("t_data_s", ctypes.c_double), ("t_train_s", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
@@ -80,6 +93,15 @@ EXPORTS = {
     "fmmbem_solve_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(SolveOpts),
                                           ctypes.c_void_p, ctypes.c_void_p]),
     "fmmbem_release_workspace": (ctypes.c_int, [ctypes.c_void_p]),
+    "fmmbem_default_train_opts": (None, [ctypes.c_void_p]),
+    "fmmbem_learned_train": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "fmmbem_mlp_param_count": (ctypes.c_int64, []),
+    "fmmbem_mlp_init": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "fmmbem_mlp_get_weights": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "fmmbem_mlp_set_weights": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "fmmbem_mlp_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
+    "fmmbem_mlp_loss_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_void_p]),
     "fmmbem_solve_history": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                             ctypes.POINTER(ctypes.c_int32)]),
     "fmmbem_matvec": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
@@ -243,6 +265,47 @@ class Context:
         reps = (SolveReport * ns)()
         rc = self._check(lib().fmmbem_solve_batch(self.h, ns, _ptr(src), ctypes.byref(o), _ptr(x), reps))
         return x, list(reps), rc
+
+    # ---- learned preconditioner
+    def fmmbem_learned_train(self, isrc=0, **kw):
+        o = TrainOpts()
+        lib().fmmbem_default_train_opts(ctypes.byref(o))
+        for k, v in kw.items():
+            setattr(o, k, v)
+        rep = TrainReport()
+        self._check(lib().fmmbem_learned_train(self.h, isrc, ctypes.byref(o), ctypes.byref(rep)))
+        return rep
+
+    @staticmethod
+    def fmmbem_mlp_param_count():
+        return int(lib().fmmbem_mlp_param_count())
+
+    def fmmbem_mlp_init(self, seed=1):
+        self._check(lib().fmmbem_mlp_init(self.h, seed))
+
+    def fmmbem_mlp_get_weights(self):
+        w = np.empty(self.fmmbem_mlp_param_count(), np.float32)
+        self._check(lib().fmmbem_mlp_get_weights(self.h, _ptr(w)))
+        return w
+
+    def fmmbem_mlp_set_weights(self, w):
+        w = np.ascontiguousarray(w, np.float32)
+        assert w.shape == (self.fmmbem_mlp_param_count(),)
+        self._check(lib().fmmbem_mlp_set_weights(self.h, _ptr(w)))
+
+    def fmmbem_mlp_forward(self, X):
+        X = np.ascontiguousarray(X, np.float32)
+        Y = np.empty((X.shape[0], 128), np.float32)
+        self._check(lib().fmmbem_mlp_forward(self.h, X.shape[0], _ptr(X), _ptr(Y)))
+        return Y
+
+    def fmmbem_mlp_loss_grad(self, X, T):
+        X = np.ascontiguousarray(X, np.float32)
+        T = np.ascontiguousarray(T, np.float32)
+        loss = np.zeros(1, np.float32)
+        g = np.empty(self.fmmbem_mlp_param_count(), np.float32)
+        self._check(lib().fmmbem_mlp_loss_grad(self.h, X.shape[0], _ptr(X), _ptr(T), _ptr(loss), _ptr(g)))
+        return float(loss[0]), g
 
     def fmmbem_release_workspace(self):
         self._check(lib().fmmbem_release_workspace(self.h))
