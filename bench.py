@@ -37,6 +37,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--maxit", type=int, default=1200, help="FGMRES iteration cap (= Krylov dimension)")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner solve")
+    ap.add_argument("--train-maxit", type=int, default=300, help="iteration cap of the reference solve for training")
     ap.add_argument("--lds-budget", type=int, default=0, help="LDS bytes per translation tile (0 = library default)")
     args = ap.parse_args()
 
@@ -194,6 +196,26 @@ def main():
             fg[name] = {"status": rc, "iters": rep.iters, "rel_res_fp64": rep.rel_res, "t_solve_s": rep.t_solve_s,
                         "matvecs_fp64": rep.matvecs_fp64, "matvecs_mixed": rep.matvecs_mixed}
             log(f"FGMRES {name}: status {rc} iters {rep.iters} rel_res {rep.rel_res:.3e} t {rep.t_solve_s:.2f}s")
+        if not args.no_learned:
+            # learned preconditioner trained on another source position, mixed products
+            ctx.fmmbem_release_workspace()
+            trep = ctx.fmmbem_learned_train(1, restart=8, maxit=args.train_maxit, tol=1e-3, max_pairs=12,
+                                            epochs=20, batch=4096)
+            log(f"learned PC trained: samples {trep.samples} pairs {trep.pairs} loss zero {trep.loss_zero:.3e} "
+                f"first {trep.loss_first:.3e} last {trep.loss_last:.3e} data {trep.t_data_s:.1f}s "
+                f"train {trep.t_train_s:.1f}s")
+            ctx.fmmbem_release_workspace()
+            xs, rep, rc = ctx.fmmbem_solve(0, tol=1e-4, restart=args.maxit, maxit=args.maxit,
+                                           precond=F.FMMBEM_PC_LEARNED, precision=F.FMMBEM_MIXED)
+            fg["mixed_learned"] = {"status": rc, "iters": rep.iters, "rel_res_fp64": rep.rel_res,
+                                   "t_solve_s": rep.t_solve_s, "matvecs_fp64": rep.matvecs_fp64,
+                                   "matvecs_mixed": rep.matvecs_mixed, "guard_fallback_at": rep.pc_fallback_at,
+                                   "training": {"source": 1, "samples": trep.samples, "pairs": trep.pairs,
+                                                "loss_zero": trep.loss_zero, "loss_first": trep.loss_first,
+                                                "loss_last": trep.loss_last, "t_data_s": trep.t_data_s,
+                                                "t_train_s": trep.t_train_s}}
+            log(f"FGMRES mixed+learned: status {rc} iters {rep.iters} rel_res {rep.rel_res:.3e} "
+                f"t {rep.t_solve_s:.2f}s fallback at {rep.pc_fallback_at}")
         fg["precond"] = "near-field leaf blocks"
         fg["restart"] = args.maxit
         if fg["fp64"]["status"] == 0 and fg["mixed"]["status"] == 0:

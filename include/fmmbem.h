@@ -201,11 +201,14 @@ int fmmbem_solve_batch(fmmbem_ctx *ctx, int32_t ns, const int32_t *isrc, const f
  * near-field block step.  Weights: FP16 in the forward pass, FP32 master copy, FP32
  * accumulation.  Parameter vector layout: per layer W (in x out, row-major) then b (out). */
 typedef struct {
-    int restart;      /* Krylov dimension of the data-generating plain solve; its restart iterates
-                         x_k with residuals r_k give the pairs (r_k, x* - x_k); default 8 */
+    int restart;      /* cycle length of the data-generating plain solve (max_pairs cycles): its
+                         restart iterates x_k and residuals r_k give the pairs (r_k, x* - x_k);
+                         default 8 */
     int max_pairs;    /* pairs kept (earliest first); default 12 */
-    double tol;       /* accuracy of that solve (its final iterate is x*); default 1e-7 */
-    int maxit;        /* its iteration cap; default 400 */
+    double tol;       /* accuracy of the reference solution x*, obtained by continuing from the
+                         last cycle without restarts; pairs whose residual is not 10x above
+                         x*'s are dropped; default 1e-7 */
+    int maxit;        /* iteration cap of that continuation; default 400 */
     int epochs;       /* passes over the samples; default 60 */
     int batch;        /* samples per Adam step; default 2048 */
     double lr;        /* Adam step size; default 1e-3 */
@@ -215,7 +218,7 @@ typedef struct {
 typedef struct {
     int64_t samples;      /* chunks x pairs used */
     int32_t pairs;
-    int32_t solve_iters;  /* iterations of the data-generating solve */
+    int32_t solve_iters;  /* iterations of the data-generating solves (cycles + continuation) */
     double solve_rel_res;
     double loss_zero;     /* mean squared target (loss of a zero correction) */
     double loss_first;    /* mean loss over the first epoch */

@@ -1542,13 +1542,26 @@ int fmmbem_learned_train(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_train_opts 
     auto mv = [&](const double2 *a, double2 *y) { matvec_dev(ctx, 1, a, y, false, false); };
     int iters = 0, restarts = 0;
     double rel = 1.0;
-    fgmres(n, st, ctx->scratch, "tr_", mv, mv, pc, b, x, o.tol, o.restart, o.maxit, false, true, &hist, iters, restarts,
-           rel, &hk);
+    // short cycles give the pairs; the reference solution x* continues from the last of them
+    // without restarts, to the requested accuracy
+    const int pair_its = o.max_pairs * o.restart;
+    fgmres(n, st, ctx->scratch, "tr_", mv, mv, pc, b, x, o.tol, o.restart, pair_its, false, true, &hist, iters,
+           restarts, rel, &hk);
     ctx->mlp_ref_hist = hist;
-    // 2. samples: features of r_k, targets (x* - x_k - P_near r_k) / |r_k| per chunk
+    int iters2 = 0;
+    if (rel >= o.tol) {
+        std::vector<double> hist2;
+        fgmres(n, st, ctx->scratch, "tr_", mv, mv, pc, b, x, o.tol, o.maxit, o.maxit, true, true, &hist2, iters2,
+               restarts, rel, nullptr);
+    }
+    iters += iters2;
+    ctx->scratch.release("tr_fg_V");  // the long solve's basis is not needed any more
+    ctx->scratch.release("tr_fg_Z");
+    // 2. samples: features of r_k, targets (x* - x_k - P_near r_k) / |r_k| per chunk; pairs whose
+    // error is not resolved by x* (residual within 10x of x*'s) are left out
     std::vector<int> keep;
     for (size_t q = 0; q < prel.size(); ++q)
-        if (prel[q] > 100.0 * rel) keep.push_back((int)q);
+        if (prel[q] > 10.0 * rel) keep.push_back((int)q);
     if (keep.empty()) throw FmmError(FMMBEM_EINVAL, "no usable residual/error pairs (solve converged too early)");
     const int64_t M = (int64_t)keep.size() * nch;
     float *Xall = dget<float>(ctx->scratch, "tr_X", (size_t)M * MLP_IN);
