@@ -55,7 +55,7 @@ def main():
     from paper_2103_16073_amd import synth
 
     room, k = synth.config_room(args.workload)
-    rs, rec = synth.source_and_receivers(room, 64)
+    rs, rec = synth.source_and_receivers(room, 64, nsrc=4)
     n = room.n
     log(f"workload {args.workload}: N={n} k={k:.3f}")
     ctx = F.Context(0, lds_budget=args.lds_budget)

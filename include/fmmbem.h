@@ -98,6 +98,10 @@ typedef struct {
                             buffers; per-phase timings then report only the total.  default 1 */
     int autotune;        /* nonzero: at setup, time each translation batch under the candidate tile
                             shapes and keep the fastest (adds setup time); default 0 */
+    int lane_tiles;      /* 1: translation batches whose table classes hold many jobs (padding to
+                            64-job tiles wastes at most a quarter) run one job per lane, tables
+                            read as wave-uniform values; 2: every batch does; 0: LDS tile kernels
+                            everywhere; default 1 */
 } fmmbem_options;
 
 void fmmbem_default_options(fmmbem_options *opt);

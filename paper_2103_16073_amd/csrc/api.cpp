@@ -235,9 +235,6 @@ static void make_batch(fmmbem_ctx *c, const std::string &name, std::vector<JobH>
     b.nreal = (int64_t)jobs.size();
     size_t budget = c->opt.lds_budget > 0 ? (size_t)c->opt.lds_budget : (size_t)32768;
     budget = std::min(budget, c->lds_max - 1024);
-    // whole-vector tiles while at least 8 jobs fit, per-degree slices otherwise
-    b.whole = trans_pick_jt(b.P, budget, 1) >= 8 && (size_t)8 * 16 * b.P * b.P <= budget;
-    b.JT = trans_pick_jt(b.P, budget, b.whole);
     b.ntgt = ntgt;
     // polar-angle classes
     std::vector<double> cb;
@@ -254,6 +251,24 @@ static void make_batch(fmmbem_ctx *c, const std::string &name, std::vector<JobH>
         if (x.rot != y.rot) return x.rot < y.rot;
         return x.tgt < y.tgt;
     });
+    // Tile shape: one job per lane (64-job tiles) when the classes are large enough that padding
+    // them to 64 wastes at most a quarter of the work; otherwise whole-vector tiles while at
+    // least 8 jobs fit the LDS budget, per-degree slices beyond.
+    int64_t pad64 = 0;
+    for (size_t q = 0; q < jobs.size();) {
+        size_t e = q;
+        while (e < jobs.size() && jobs[e].tab == jobs[q].tab && jobs[e].rot == jobs[q].rot) ++e;
+        pad64 += (int64_t)((e - q + 63) / 64) * 64;
+        q = e;
+    }
+    b.lane = !jobs.empty() && (c->opt.lane_tiles == 2 || (c->opt.lane_tiles == 1 && pad64 * 4 <= (int64_t)jobs.size() * 5));
+    if (b.lane) {
+        b.whole = 0;
+        b.JT = 64;
+    } else {
+        b.whole = trans_pick_jt(b.P, budget, 1) >= 8 && (size_t)8 * 16 * b.P * b.P <= budget;
+        b.JT = trans_pick_jt(b.P, budget, b.whole);
+    }
     std::vector<int32_t> s, t, tc, tr;
     std::vector<int16_t> d;
     size_t q = 0;
@@ -299,8 +314,13 @@ static void make_batch(fmmbem_ctx *c, const std::string &name, std::vector<JobH>
     b.nbeta = (int)classes.size();
     std::vector<double> betas;
     for (double v : classes) betas.push_back(std::acos(std::max(-1.0, std::min(1.0, v))));
-    b.H = dget<double>(c->buf, name + "_H", std::max<size_t>(1, betas.size()) * rot_table_size(b.P));
-    b.HT = dget<double>(c->buf, name + "_HT", std::max<size_t>(1, betas.size()) * rot_table_size(b.P));
+    b.H = dget<double>(c->buf, name + "_H", std::max<size_t>(1, betas.size()) * rot_table_size(b.P) + TABLE_PAD);
+    b.HT = dget<double>(c->buf, name + "_HT", std::max<size_t>(1, betas.size()) * rot_table_size(b.P) + TABLE_PAD);
+    {
+        const size_t nt_ = std::max<size_t>(1, betas.size()) * rot_table_size(b.P);
+        HIP_OK(hipMemsetAsync(b.H + nt_, 0, sizeof(double) * TABLE_PAD, st));
+        HIP_OK(hipMemsetAsync(b.HT + nt_, 0, sizeof(double) * TABLE_PAD, st));
+    }
     build_rot_tables(betas, b.P, (double *)c->buf.find("delta"), b.H, b.HT, c->scratch, st);
 }
 
@@ -360,14 +380,17 @@ static void setup_k(fmmbem_ctx *c) {
         LevelDev &D = c->lev[l];
         const int p = D.p;
         std::string s = "L" + std::to_string(l) + "_";
-        D.coax_m2l = dget<double2>(c->buf, s + "coax_m2l", (size_t)coax_table_size(p) * std::max(D.ntau, 1));
+        D.coax_m2l = dget<double2>(c->buf, s + "coax_m2l", (size_t)coax_table_size(p) * std::max(D.ntau, 1) + TABLE_PAD);
+        HIP_OK(hipMemsetAsync(D.coax_m2l + (size_t)coax_table_size(p) * std::max(D.ntau, 1), 0,
+                              sizeof(double2) * TABLE_PAD, st));
         for (int q = 0; q < D.ntau; ++q) {
             double kt = c->k * T.lv[l].m2l_taus[q];
             jobs.push_back({0, kt < c->opt.ktau_switch ? 0 : 1, p, kt, D.coax_m2l + (size_t)q * coax_table_size(p)});
         }
         if (l < L) {
             const int PT = std::max(p, c->lev[l + 1].p);
-            D.coax_up = dget<double2>(c->buf, s + "coax_up", coax_table_size(PT));
+            D.coax_up = dget<double2>(c->buf, s + "coax_up", coax_table_size(PT) + TABLE_PAD);
+            HIP_OK(hipMemsetAsync(D.coax_up + coax_table_size(PT), 0, sizeof(double2) * TABLE_PAD, st));
             double kt = c->k * std::sqrt(3.0) * 0.5 * c->lev[l + 1].side;
             jobs.push_back({1, kt < c->opt.ktau_switch ? 0 : 1, PT, kt, D.coax_up});
         }
@@ -552,12 +575,12 @@ static void ensure_mixed(fmmbem_ctx *c) {
         const int p = D.p;
         std::string s = "L" + std::to_string(l) + "_";
         const int64_t nm = coax_table_size(p) * std::max(D.ntau, 1);
-        D.coax_m2l32 = dget<float2>(c->buf, s + "coax_m2l32", nm);
-        convert(c, nm, (const double2 *)D.coax_m2l, D.coax_m2l32);
+        D.coax_m2l32 = dget<float2>(c->buf, s + "coax_m2l32", nm + TABLE_PAD);
+        convert(c, nm + TABLE_PAD, (const double2 *)D.coax_m2l, D.coax_m2l32);
         if (l < L) {
             const int PT = std::max(p, c->lev[l + 1].p);
-            D.coax_up32 = dget<float2>(c->buf, s + "coax_up32", coax_table_size(PT));
-            convert(c, coax_table_size(PT), (const double2 *)D.coax_up, D.coax_up32);
+            D.coax_up32 = dget<float2>(c->buf, s + "coax_up32", coax_table_size(PT) + TABLE_PAD);
+            convert(c, coax_table_size(PT) + TABLE_PAD, (const double2 *)D.coax_up, D.coax_up32);
         }
         TransBatch *bs[3] = {&D.m2l, &D.up, &D.down};
         const char *nm3[3] = {"m2l", "up", "down"};
@@ -565,10 +588,10 @@ static void ensure_mixed(fmmbem_ctx *c) {
             TransBatch &b = *bs[q];
             if (b.njob == 0) continue;
             const int64_t nh = (int64_t)std::max(1, b.nbeta) * rot_table_size(b.P);
-            b.H32 = dget<float>(c->buf, s + nm3[q] + "_H32", nh);
-            b.HT32 = dget<float>(c->buf, s + nm3[q] + "_HT32", nh);
-            convert(c, nh, (const double *)b.H, b.H32);
-            convert(c, nh, (const double *)b.HT, b.HT32);
+            b.H32 = dget<float>(c->buf, s + nm3[q] + "_H32", nh + TABLE_PAD);
+            b.HT32 = dget<float>(c->buf, s + nm3[q] + "_HT32", nh + TABLE_PAD);
+            convert(c, nh + TABLE_PAD, (const double *)b.H, b.H32);
+            convert(c, nh + TABLE_PAD, (const double *)b.HT, b.HT32);
         }
     }
     const int64_t nph = (int64_t)NDIR * (2 * c->delta_p + 1);
@@ -858,6 +881,7 @@ void fmmbem_default_options(fmmbem_options *o) {
     o->lds_budget = 0;
     o->graphs = 1;
     o->autotune = 0;
+    o->lane_tiles = 1;
 }
 
 void fmmbem_default_solve_opts(fmmbem_solve_opts *o) {

@@ -98,6 +98,9 @@ __device__ inline double dist2_exact(double ax, double ay, double az, double bx,
 
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
+// spare entries allocated after every translation/rotation table (kernels read whole row chunks)
+constexpr int64_t TABLE_PAD = 64;
+
 // scalar-generic complex type: Cx<double>::T = double2, Cx<float>::T = float2
 template <class R> struct Cx;
 template <> struct Cx<double> { using T = double2; };

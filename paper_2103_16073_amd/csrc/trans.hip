@@ -425,6 +425,169 @@ __global__ void __launch_bounds__(256) k_tw_coax(TransArgsT<R> a) {
     }
 }
 
+// ------------------------------------------------------------------ one job per lane (many jobs per class)
+// A wavefront takes 64 consecutive (virtual) jobs of one table class, one job per lane: every
+// table value is then the same for all lanes (scalar loads, an SGPR operand of the FMA) and each
+// lane keeps its own rows in registers, RC output rows at a time.  Job rows stay in job-major
+// layout (P^2 per job), as for the tile kernels.  blockIdx.y picks every nsplit-th degree/order.
+constexpr int LANE_JT = 64;
+
+// Wave-uniform, read-only table rows: read through the constant address space so that they
+// come in with scalar loads (the kernel only reads the tables).
+template <class T> using cst_ptr = const __attribute__((address_space(4))) T *;
+template <class T> __device__ inline cst_ptr<T> as_cst(const T *p, int64_t off) {
+    return (cst_ptr<T>)(p + __builtin_amdgcn_readfirstlane((int)off));
+}
+static_assert(TABLE_PAD >= 32, "lane kernels read up to 31 entries past a table row");
+
+// Intermediate rows of lane batches are tile-interleaved: coefficient c of virtual job J at
+// ((J / 64) P^2 + c) 64 + J % 64, so that a wavefront's 64 lanes touch 64 consecutive values.
+__device__ inline int64_t tl_idx(int64_t J, int c, int P2) { return ((J >> 6) * P2 + c) * LANE_JT + (J & 63); }
+
+// Forward rotation: sources (box-major) -> W1 (interleaved).  Each lane reads its own source
+// row; consecutive columns of a row share cache lines, so the lines are fetched once.
+template <class R, int RC>
+__global__ void __launch_bounds__(64) k_tl_rot_fwd(TransArgsT<R> a, int nsplit) {
+    using C = typename Cx<R>::T;
+    const int64_t J = (int64_t)blockIdx.x * LANE_JT + threadIdx.x;
+    const bool live = J < a.njob;
+    const int64_t Jc = live ? J : a.njob - 1;
+    const int P2 = a.P * a.P, phs = 2 * a.PH + 1, ps2 = a.psrc * a.psrc;
+    const int tr = __builtin_amdgcn_readfirstlane(a.tile_rot[blockIdx.x / a.nr]);
+    const R *Hb = a.HT + (int64_t)tr * rot_table_size(a.P);
+    const C *ph = a.ph + (int64_t)a.jdir[Jc / a.nr] * phs + a.PH;
+    const C *xin = a.src + src_row(a, Jc) * ps2;
+    for (int n = blockIdx.y; n < a.psrc; n += nsplit) {
+        const int w = 2 * n + 1;
+        const R *Hn = Hb + rot_block_off(n);  // HT: row c holds column c of H
+        for (int r0 = 0; r0 < w; r0 += RC) {
+            R ar[RC], ai[RC];
+#pragma unroll
+            for (int v = 0; v < RC; ++v) ar[v] = ai[v] = 0;
+            for (int c = 0; c < w; ++c) {
+                const C xv = mulc(ph[c - n], xin[n * n + c]);  // e^{i m a} c_n^m
+                const cst_ptr<R> hrow = as_cst(Hn, c * w + r0);
+                // rows past w read the next table entries (TABLE_PAD spare); never stored
+#pragma unroll
+                for (int v = 0; v < RC; ++v) {
+                    const R h = hrow[v];
+                    ar[v] = fma(h, xv.x, ar[v]);
+                    ai[v] = fma(h, xv.y, ai[v]);
+                }
+            }
+            if (live) {
+#pragma unroll
+                for (int v = 0; v < RC; ++v)
+                    if (r0 + v < w) a.W1[tl_idx(J, n * n + r0 + v, P2)] = mkc<C>(ar[v], ai[v]);
+            }
+        }
+    }
+}
+
+// Back rotation: W2 (interleaved) -> W1 (job-major, for the per-target reduction), through an
+// LDS transpose RC rows at a time.
+template <class R, int RC>
+__global__ void __launch_bounds__(64) k_tl_rot_back(TransArgsT<R> a, int nsplit) {
+    using C = typename Cx<R>::T;
+    constexpr int OT = 8;  // rows per transpose (small LDS footprint keeps occupancy)
+    __shared__ C O[LANE_JT][OT + 1];
+    const int lane = threadIdx.x;
+    const int64_t J0 = (int64_t)blockIdx.x * LANE_JT, J = J0 + lane;
+    const int64_t Jc = J < a.njob ? J : a.njob - 1;
+    const int P2 = a.P * a.P, phs = 2 * a.PH + 1;
+    const int nlive = (int)min((int64_t)LANE_JT, a.njob - J0);
+    const int tr = __builtin_amdgcn_readfirstlane(a.tile_rot[blockIdx.x / a.nr]);
+    const R *Hb = a.H + (int64_t)tr * rot_table_size(a.P);
+    const C *ph = a.ph + (int64_t)a.jdir[Jc / a.nr] * phs + a.PH;
+    for (int n = blockIdx.y; n < a.ptgt; n += nsplit) {
+        const int w = 2 * n + 1;
+        const R *Hn = Hb + rot_block_off(n);  // (H^T y)_r = sum_c H[c][r] y_c: row c of H
+        for (int r0 = 0; r0 < w; r0 += RC) {
+            R ar[RC], ai[RC];
+#pragma unroll
+            for (int v = 0; v < RC; ++v) ar[v] = ai[v] = 0;
+            for (int c = 0; c < w; ++c) {
+                const C xv = a.W2[tl_idx(Jc, n * n + c, P2)];
+                const cst_ptr<R> hrow = as_cst(Hn, c * w + r0);
+#pragma unroll
+                for (int v = 0; v < RC; ++v) {
+                    const R h = hrow[v];
+                    ar[v] = fma(h, xv.x, ar[v]);
+                    ai[v] = fma(h, xv.y, ai[v]);
+                }
+            }
+            // transpose to job-major rows OT rows at a time
+#pragma unroll
+            for (int h0 = 0; h0 < RC; h0 += OT) {
+                const int rc = min(OT, w - r0 - h0);
+                if (rc <= 0) break;
+                __syncthreads();
+#pragma unroll
+                for (int v = 0; v < OT; ++v)
+                    if (v < rc) O[lane][v] = mulcc(mkc<C>(ar[h0 + v], ai[h0 + v]), ph[r0 + h0 + v - n]);  // e^{-i m a}
+                __syncthreads();
+                for (int e = lane; e < nlive * rc; e += LANE_JT) {
+                    const int j = e / rc, q = e - j * rc;
+                    a.W1[(J0 + j) * (int64_t)P2 + n * n + r0 + h0 + q] = O[j][q];
+                }
+            }
+        }
+    }
+}
+
+// Coaxial step: W1 (interleaved) -> W2 (interleaved), fully coalesced.
+template <class R, int RC>
+__global__ void __launch_bounds__(64) k_tl_coax(TransArgsT<R> a, int nsplit) {
+    using C = typename Cx<R>::T;
+    const int64_t J = (int64_t)blockIdx.x * LANE_JT + threadIdx.x;
+    const bool live = J < a.njob;
+    const int64_t Jc = live ? J : a.njob - 1;
+    const int P2 = a.P * a.P, pt = a.ptgt, pm = min(a.psrc, a.ptgt);
+    const int tc = __builtin_amdgcn_readfirstlane(a.tile_coax[blockIdx.x / a.nr]);
+    const C *T = a.coax + (int64_t)tc * coax_table_size(a.PT);
+    for (int mi = blockIdx.y; mi < 2 * pt - 1; mi += nsplit) {
+        const int m = mi - (pt - 1), am = m < 0 ? -m : m;
+        const int rows = pt - am;
+        if (am >= pm) {  // no source of this order
+            if (live)
+                for (int q = 0; q < rows; ++q) {
+                    const int nn = am + q;
+                    a.W2[tl_idx(J, nn * nn + nn + m, P2)] = mkc<C>(0, 0);
+                }
+            continue;
+        }
+        const int B = a.PT - am, cin = a.psrc - am;
+        const C *Tm = T + coax_block_off(a.PT, am);
+        for (int r0 = 0; r0 < rows; r0 += RC) {
+            R ar[RC], ai[RC];
+#pragma unroll
+            for (int v = 0; v < RC; ++v) ar[v] = ai[v] = 0;
+            for (int q = 0; q < cin; ++q) {
+                const int n = am + q;
+                const C xv = a.W1[tl_idx(Jc, n * n + n + m, P2)];
+                // (E|F)_{n' n} = (-1)^{n+n'} (E|F)_{n n'}: row n of the block, entries n'; rows
+                // past `rows` read spare table entries (TABLE_PAD) and are never stored
+                const cst_ptr<R> trow = as_cst((const R *)Tm, 2 * ((int64_t)q * B + r0));  // re, im pairs
+                const R sg = ((q + r0) & 1) ? R(-1) : R(1);
+#pragma unroll
+                for (int v = 0; v < RC; ++v) {
+                    const R s = (v & 1) ? -sg : sg;
+                    const R tx = s * trow[2 * v], ty = s * trow[2 * v + 1];
+                    ar[v] = fma(tx, xv.x, fma(-ty, xv.y, ar[v]));
+                    ai[v] = fma(tx, xv.y, fma(ty, xv.x, ai[v]));
+                }
+            }
+            if (live) {
+#pragma unroll
+                for (int v = 0; v < RC; ++v) {
+                    const int nn = am + r0 + v;
+                    if (r0 + v < rows) a.W2[tl_idx(J, nn * nn + nn + m, P2)] = mkc<C>(ar[v], ai[v]);
+                }
+            }
+        }
+    }
+}
+
 // dst[t] += sum of the job rows of target t (W1, P^2 per job); jobs of t listed in CSR order.
 // With nr vectors, virtual target t is real target t / nr, vector t % nr, and the job rows of
 // that vector are (job * nr + t % nr).
@@ -483,6 +646,21 @@ const char *trans_stage(const TransBatch &b, const TransTables<R> &tb, int stage
     const size_t lds = trans_lds_bytes(b.JT, b.P, b.whole) / (sizeof(double) / sizeof(R));
     const bool f32 = sizeof(R) == 4;
     const char *name = "";
+    if (b.lane && stage < 3) {
+        if (b.JT != LANE_JT) throw FmmError(-1, "lane batches use 64-job tiles");
+        // enough wavefronts to cover the device: split degrees/orders over blockIdx.y
+        const int nd = stage == 1 ? 2 * b.ptgt - 1 : (stage == 0 ? b.psrc : b.ptgt);
+        const int ns = (int)std::max<int64_t>(1, std::min<int64_t>(nd, (4096 + ntile - 1) / std::max(1u, ntile)));
+        const dim3 grid(ntile, ns);
+        constexpr int RC = sizeof(R) == 8 ? 16 : 32;
+        switch (stage) {
+        case 0: k_tl_rot_fwd<R, RC><<<grid, 64, 0, st>>>(a, ns), name = f32 ? "k_tl_rot_fwd_f32" : "k_tl_rot_fwd"; break;
+        case 1: k_tl_coax<R, RC><<<grid, 64, 0, st>>>(a, ns), name = f32 ? "k_tl_coax_f32" : "k_tl_coax"; break;
+        default: k_tl_rot_back<R, RC><<<grid, 64, 0, st>>>(a, ns), name = f32 ? "k_tl_rot_back_f32" : "k_tl_rot_back";
+        }
+        LAUNCH_OK();
+        return name;
+    }
     switch (stage) {
     case 0:
         if (b.whole) k_tw_rot<R, true><<<ntile, 256, lds, st>>>(a), name = f32 ? "k_tw_rot_fwd_f32" : "k_tw_rot_fwd";

@@ -124,13 +124,14 @@ def test_matvec_exact_far_vs_dense(F, cfg1_dense):
     ctx.close()
 
 
-@pytest.mark.parametrize("leaf_max,lds_budget", [(64, 0), (12, 0), (12, 8192), (64, 8192)])
-def test_matvec_fmm_vs_dense(F, cfg1_dense, leaf_max, lds_budget):
+@pytest.mark.parametrize("leaf_max,lds_budget,lane", [(64, 0, 0), (12, 0, 0), (12, 8192, 0), (64, 8192, 0),
+                                                       (64, 0, 2), (12, 0, 2)])
+def test_matvec_fmm_vs_dense(F, cfg1_dense, leaf_max, lds_budget, lane):
     """FP64 FMM product against the oracle's dense operator: relative L2 <= 1e-6, for octrees of
-    depth 2 and 3 (so M2M/L2L are exercised), with the fused translation tiles and, under a small
-    LDS budget, with the staged per-degree kernels."""
+    depth 2 and 3 (so M2M/L2L are exercised), with the whole-vector LDS tiles, the per-degree
+    kernels (small LDS budget) and the one-job-per-lane kernels (lane=2 forces them)."""
     room, k = cfg1_dense
-    ctx = make_ctx(F, room, k, leaf_max=leaf_max, lds_budget=lds_budget)
+    ctx = make_ctx(F, room, k, leaf_max=leaf_max, lds_budget=lds_budget, lane_tiles=lane)
     info = ctx.fmmbem_get_info()
     L, M = bem.dense_LM(room.vertices, room.triangles, k, info.rc)
     for seed in (1, 2):
@@ -143,12 +144,12 @@ def test_matvec_fmm_vs_dense(F, cfg1_dense, leaf_max, lds_budget):
     ctx.close()
 
 
-@pytest.mark.parametrize("leaf_max,lds_budget", [(64, 0), (12, 0), (12, 8192)])
-def test_matvec_mixed_vs_dense(F, cfg1_dense, leaf_max, lds_budget):
+@pytest.mark.parametrize("leaf_max,lds_budget,lane", [(64, 0, 0), (12, 0, 0), (12, 8192, 0), (12, 0, 2)])
+def test_matvec_mixed_vs_dense(F, cfg1_dense, leaf_max, lds_budget, lane):
     """Mixed-precision product (FP32 near field and translations, FP64 tables converted once,
     FP64 densities, P2M and L2P) against the oracle's dense operator: relative L2 <= 1e-4."""
     room, k = cfg1_dense
-    ctx = make_ctx(F, room, k, leaf_max=leaf_max, lds_budget=lds_budget)
+    ctx = make_ctx(F, room, k, leaf_max=leaf_max, lds_budget=lds_budget, lane_tiles=lane)
     info = ctx.fmmbem_get_info()
     L, M = bem.dense_LM(room.vertices, room.triangles, k, info.rc)
     for seed in (1, 2):
@@ -205,13 +206,13 @@ def test_solve_inner_outer_vs_oracle_lu(F, cfg1_dense):
     ctx.close()
 
 
-@pytest.mark.parametrize("leaf_max,lds_budget", [(12, 0), (12, 8192), (64, 0)])
-def test_matvec_multi_rhs(F, cfg1_dense, leaf_max, lds_budget):
+@pytest.mark.parametrize("leaf_max,lds_budget,lane", [(12, 0, 0), (12, 8192, 0), (64, 0, 0), (12, 0, 2)])
+def test_matvec_multi_rhs(F, cfg1_dense, leaf_max, lds_budget, lane):
     """Seven vectors in one call (chunks of 4, 2 and 1 vectors sharing kernel evaluations,
     basis functions and translation tables) give the single-vector products and match the
     oracle's dense operator (FP64 <= 1e-6, mixed <= 1e-4)."""
     room, k = cfg1_dense
-    ctx = make_ctx(F, room, k, leaf_max=leaf_max, lds_budget=lds_budget)
+    ctx = make_ctx(F, room, k, leaf_max=leaf_max, lds_budget=lds_budget, lane_tiles=lane)
     info = ctx.fmmbem_get_info()
     L, M = bem.dense_LM(room.vertices, room.triangles, k, info.rc)
     X = np.stack([synth.complex_normal(room.n, 20 + s) for s in range(7)])
