@@ -438,25 +438,48 @@ template <class T> using cst_ptr = const __attribute__((address_space(4))) T *;
 template <class T> __device__ inline cst_ptr<T> as_cst(const T *p, int64_t off) {
     return (cst_ptr<T>)(p + __builtin_amdgcn_readfirstlane((int)off));
 }
+template <class R, int N> __device__ inline void load_row(R (&h)[N], cst_ptr<R> row) {
+#pragma unroll
+    for (int v = 0; v < N; ++v) h[v] = row[v];
+}
+// acc_v += s_v T_v x with T_v = (t[2v], t[2v+1]) and s_v = (-1)^v, negated when NEG
+template <class R, class C, int RC, bool NEG>
+__device__ inline void coax_acc(const R (&t)[2 * RC], C x, R (&ar)[RC], R (&ai)[RC]) {
+#pragma unroll
+    for (int v = 0; v < RC; ++v) {
+        const bool neg = ((v & 1) != 0) != NEG;
+        const R tx = neg ? -t[2 * v] : t[2 * v], ty = neg ? -t[2 * v + 1] : t[2 * v + 1];
+        ar[v] = fma(tx, x.x, fma(-ty, x.y, ar[v]));
+        ai[v] = fma(tx, x.y, fma(ty, x.x, ai[v]));
+    }
+}
 static_assert(TABLE_PAD >= 32, "lane kernels read up to 31 entries past a table row");
 
 // Intermediate rows of lane batches are tile-interleaved: coefficient c of virtual job J at
 // ((J / 64) P^2 + c) 64 + J % 64, so that a wavefront's 64 lanes touch 64 consecutive values.
 __device__ inline int64_t tl_idx(int64_t J, int c, int P2) { return ((J >> 6) * P2 + c) * LANE_JT + (J & 63); }
 
-// Forward rotation: sources (box-major) -> W1 (interleaved).  Each lane reads its own source
-// row; consecutive columns of a row share cache lines, so the lines are fetched once.
+// Forward rotation: sources (box-major) -> W1 (interleaved).  The degree-n slices are staged
+// through LDS 8 columns at a time: one load instruction reads 8 jobs x 8 consecutive
+// coefficients, i.e. whole 128-byte lines (a lane reading its own row alone would fetch each
+// line for 16 bytes once the wave's 64 rows no longer fit L1).
 template <class R, int RC>
 __global__ void __launch_bounds__(64) k_tl_rot_fwd(TransArgsT<R> a, int nsplit) {
     using C = typename Cx<R>::T;
-    const int64_t J = (int64_t)blockIdx.x * LANE_JT + threadIdx.x;
+    constexpr int CW = 8;
+    __shared__ C S[LANE_JT][CW + 1];
+    __shared__ int64_t soff[LANE_JT];
+    __shared__ int32_t sdir[LANE_JT];
+    const int lane = threadIdx.x;
+    const int64_t J0 = (int64_t)blockIdx.x * LANE_JT, J = J0 + lane;
     const bool live = J < a.njob;
     const int64_t Jc = live ? J : a.njob - 1;
     const int P2 = a.P * a.P, phs = 2 * a.PH + 1, ps2 = a.psrc * a.psrc;
+    soff[lane] = src_row(a, Jc) * ps2;
+    sdir[lane] = a.jdir[Jc / a.nr] * phs + a.PH;
     const int tr = __builtin_amdgcn_readfirstlane(a.tile_rot[blockIdx.x / a.nr]);
     const R *Hb = a.HT + (int64_t)tr * rot_table_size(a.P);
-    const C *ph = a.ph + (int64_t)a.jdir[Jc / a.nr] * phs + a.PH;
-    const C *xin = a.src + src_row(a, Jc) * ps2;
+    const int sj = lane >> 3, sq = lane & 7;  // staging: job sj + 8 i, column sq
     for (int n = blockIdx.y; n < a.psrc; n += nsplit) {
         const int w = 2 * n + 1;
         const R *Hn = Hb + rot_block_off(n);  // HT: row c holds column c of H
@@ -464,15 +487,37 @@ __global__ void __launch_bounds__(64) k_tl_rot_fwd(TransArgsT<R> a, int nsplit) 
             R ar[RC], ai[RC];
 #pragma unroll
             for (int v = 0; v < RC; ++v) ar[v] = ai[v] = 0;
-            for (int c = 0; c < w; ++c) {
-                const C xv = mulc(ph[c - n], xin[n * n + c]);  // e^{i m a} c_n^m
-                const cst_ptr<R> hrow = as_cst(Hn, c * w + r0);
-                // rows past w read the next table entries (TABLE_PAD spare); never stored
+            for (int c0 = 0; c0 < w; c0 += CW) {
+                const int cw = min(CW, w - c0);
+                __syncthreads();
+                if (sq < cw) {
+                    const int c = c0 + sq;
+                    C xs[LANE_JT / 8], ps[LANE_JT / 8];  // all loads in flight before the first use
 #pragma unroll
-                for (int v = 0; v < RC; ++v) {
-                    const R h = hrow[v];
-                    ar[v] = fma(h, xv.x, ar[v]);
-                    ai[v] = fma(h, xv.y, ai[v]);
+                    for (int i = 0; i < LANE_JT / 8; ++i) {
+                        const int j = sj + 8 * i;
+                        xs[i] = a.src[soff[j] + n * n + c];
+                        ps[i] = a.ph[sdir[j] + c - n];
+                    }
+#pragma unroll
+                    for (int i = 0; i < LANE_JT / 8; ++i) S[sj + 8 * i][sq] = mulc(ps[i], xs[i]);  // e^{i m a} c_n^m
+                }
+                __syncthreads();
+                // rows past w read the next table entries (TABLE_PAD spare); never stored.  The
+                // next table row is loaded before the current one is used.
+                R h[RC];
+                load_row<R, RC>(h, as_cst(Hn, c0 * w + r0));
+                for (int q = 0; q < cw; ++q) {
+                    const C xv = S[lane][q];
+                    R hn[RC];
+                    load_row<R, RC>(hn, as_cst(Hn, (c0 + q + 1) * w + r0));  // spare-padded past the end
+#pragma unroll
+                    for (int v = 0; v < RC; ++v) {
+                        ar[v] = fma(h[v], xv.x, ar[v]);
+                        ai[v] = fma(h[v], xv.y, ai[v]);
+                    }
+#pragma unroll
+                    for (int v = 0; v < RC; ++v) h[v] = hn[v];
                 }
             }
             if (live) {
@@ -489,7 +534,7 @@ __global__ void __launch_bounds__(64) k_tl_rot_fwd(TransArgsT<R> a, int nsplit) 
 template <class R, int RC>
 __global__ void __launch_bounds__(64) k_tl_rot_back(TransArgsT<R> a, int nsplit) {
     using C = typename Cx<R>::T;
-    constexpr int OT = 8;  // rows per transpose (small LDS footprint keeps occupancy)
+    constexpr int OT = 8;  // rows per transpose (small LDS footprint keeps occupancy); 8 x 8 stores
     __shared__ C O[LANE_JT][OT + 1];
     const int lane = threadIdx.x;
     const int64_t J0 = (int64_t)blockIdx.x * LANE_JT, J = J0 + lane;
@@ -506,15 +551,23 @@ __global__ void __launch_bounds__(64) k_tl_rot_back(TransArgsT<R> a, int nsplit)
             R ar[RC], ai[RC];
 #pragma unroll
             for (int v = 0; v < RC; ++v) ar[v] = ai[v] = 0;
+            R h[RC];
+            load_row<R, RC>(h, as_cst(Hn, r0));
+            C xv = a.W2[tl_idx(Jc, n * n, P2)];
             for (int c = 0; c < w; ++c) {
-                const C xv = a.W2[tl_idx(Jc, n * n + c, P2)];
-                const cst_ptr<R> hrow = as_cst(Hn, c * w + r0);
+                // next row of the table and next input value first (spare-padded table; the
+                // input index is clamped)
+                R hn[RC];
+                load_row<R, RC>(hn, as_cst(Hn, (c + 1) * w + r0));
+                const C xn = a.W2[tl_idx(Jc, n * n + min(c + 1, w - 1), P2)];
 #pragma unroll
                 for (int v = 0; v < RC; ++v) {
-                    const R h = hrow[v];
-                    ar[v] = fma(h, xv.x, ar[v]);
-                    ai[v] = fma(h, xv.y, ai[v]);
+                    ar[v] = fma(h[v], xv.x, ar[v]);
+                    ai[v] = fma(h[v], xv.y, ai[v]);
                 }
+#pragma unroll
+                for (int v = 0; v < RC; ++v) h[v] = hn[v];
+                xv = xn;
             }
             // transpose to job-major rows OT rows at a time
 #pragma unroll
@@ -526,9 +579,14 @@ __global__ void __launch_bounds__(64) k_tl_rot_back(TransArgsT<R> a, int nsplit)
                 for (int v = 0; v < OT; ++v)
                     if (v < rc) O[lane][v] = mulcc(mkc<C>(ar[h0 + v], ai[h0 + v]), ph[r0 + h0 + v - n]);  // e^{-i m a}
                 __syncthreads();
-                for (int e = lane; e < nlive * rc; e += LANE_JT) {
-                    const int j = e / rc, q = e - j * rc;
-                    a.W1[(J0 + j) * (int64_t)P2 + n * n + r0 + h0 + q] = O[j][q];
+                // one store instruction: 8 jobs x 8 consecutive coefficients
+                const int q = lane & 7;
+                if (q < rc) {
+#pragma unroll
+                    for (int i = 0; i < LANE_JT / 8; ++i) {
+                        const int j = (lane >> 3) + 8 * i;
+                        if (j < nlive) a.W1[(J0 + j) * (int64_t)P2 + n * n + r0 + h0 + q] = O[j][q];
+                    }
                 }
             }
         }
@@ -562,20 +620,23 @@ __global__ void __launch_bounds__(64) k_tl_coax(TransArgsT<R> a, int nsplit) {
             R ar[RC], ai[RC];
 #pragma unroll
             for (int v = 0; v < RC; ++v) ar[v] = ai[v] = 0;
-            for (int q = 0; q < cin; ++q) {
-                const int n = am + q;
-                const C xv = a.W1[tl_idx(Jc, n * n + n + m, P2)];
-                // (E|F)_{n' n} = (-1)^{n+n'} (E|F)_{n n'}: row n of the block, entries n'; rows
-                // past `rows` read spare table entries (TABLE_PAD) and are never stored
-                const cst_ptr<R> trow = as_cst((const R *)Tm, 2 * ((int64_t)q * B + r0));  // re, im pairs
-                const R sg = ((q + r0) & 1) ? R(-1) : R(1);
+            // (E|F)_{n' n} = (-1)^{n+n'} (E|F)_{n n'}: row n of the block, entries n'; rows past
+            // `rows` read spare table entries (TABLE_PAD) and are never stored.  The sign is fixed
+            // per unrolled row for each parity of q + r0, so it folds into the FMAs.
+            R t[2 * RC];
+            load_row<R, 2 * RC>(t, as_cst((const R *)Tm, 2 * (int64_t)r0));
+            int n = am;
+            C xv = a.W1[tl_idx(Jc, n * n + n + m, P2)];
+            for (int q = 0; q < cin; ++q, ++n) {
+                R tn[2 * RC];
+                load_row<R, 2 * RC>(tn, as_cst((const R *)Tm, 2 * ((int64_t)(q + 1) * B + r0)));
+                const int nn1 = min(n + 1, a.psrc - 1);
+                const C xn = a.W1[tl_idx(Jc, nn1 * nn1 + nn1 + m, P2)];
+                if (((q + r0) & 1) == 0) coax_acc<R, C, RC, false>(t, xv, ar, ai);
+                else coax_acc<R, C, RC, true>(t, xv, ar, ai);
 #pragma unroll
-                for (int v = 0; v < RC; ++v) {
-                    const R s = (v & 1) ? -sg : sg;
-                    const R tx = s * trow[2 * v], ty = s * trow[2 * v + 1];
-                    ar[v] = fma(tx, xv.x, fma(-ty, xv.y, ar[v]));
-                    ai[v] = fma(tx, xv.y, fma(ty, xv.x, ai[v]));
-                }
+                for (int v = 0; v < 2 * RC; ++v) t[v] = tn[v];
+                xv = xn;
             }
             if (live) {
 #pragma unroll
@@ -655,7 +716,9 @@ const char *trans_stage(const TransBatch &b, const TransTables<R> &tb, int stage
         constexpr int RC = sizeof(R) == 8 ? 16 : 32;
         switch (stage) {
         case 0: k_tl_rot_fwd<R, RC><<<grid, 64, 0, st>>>(a, ns), name = f32 ? "k_tl_rot_fwd_f32" : "k_tl_rot_fwd"; break;
-        case 1: k_tl_coax<R, RC><<<grid, 64, 0, st>>>(a, ns), name = f32 ? "k_tl_coax_f32" : "k_tl_coax"; break;
+        case 1:  // half the rows: two complex table rows (current + prefetched) must fit the SGPRs
+            k_tl_coax<R, RC / 2><<<grid, 64, 0, st>>>(a, ns), name = f32 ? "k_tl_coax_f32" : "k_tl_coax";
+            break;
         default: k_tl_rot_back<R, RC><<<grid, 64, 0, st>>>(a, ns), name = f32 ? "k_tl_rot_back_f32" : "k_tl_rot_back";
         }
         LAUNCH_OK();
