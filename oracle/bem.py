@@ -1,4 +1,4 @@
-"""CPU oracle for the direct collocation BEM -- TEST INFRASTRUCTURE ONLY.
+"""CPU oracle for the collocation BEM (direct and indirect) -- TEST INFRASTRUCTURE ONLY.
 
 Plain FP64 numpy on top of the C routines in bem_oracle.c.  Used by tests/, the smoke
 check and the benchmark's CPU-baseline leg; never by the product path.
@@ -12,6 +12,14 @@ Definitions followed (paper, Sections 2-3):
     with the per-element admittance entering as a column scaling of L
   * field off the surface from Green's representation (Eq. dbem1):
         psi(r) = psi_in(r) + L[dpsi_sc/dn](r) - M[psi_sc](r),  dpsi_sc/dn = gamma + i k beta psi_sc
+  * indirect BIE (Eq. ibem5) on two-sided elements, unknowns (psi-, psi+) with the normal
+    pointing from the - side (the room) to the + side, k/(i zeta) = -i k beta on each side:
+        row 1:  (psi- + psi+)/2 + L[s] + M[m]
+        row 2:  (i k beta- psi- - i k beta+ psi+)/2 + L'[s] + M'[m]
+    with s = -i k (beta- psi- + beta+ psi+), m = psi- - psi+; right-hand sides
+        row 1:  L[g- + g+],   row 2: (g+ - g-)/2 + L'[g- + g+],   g-+ = -+ dpsi_in/dn + i k beta-+ psi_in
+    and the field psi = psi_in + L[sigma] + M[mu] (Eq. ibem1) with
+    sigma = g- + g+ + i k (beta- psi- + beta+ psi+), mu = psi+ - psi- (Eq. ibem4)
 """
 from __future__ import annotations
 
@@ -41,6 +49,9 @@ def lib():
         L.oracle_layer_rows.argtypes = [i64, dp, i64, ip, f64, f64, f64, f64, i64, ip, dp, dp, dp]
         L.oracle_field.argtypes = [i64, dp, i64, ip, f64, f64, f64, f64, i64, dp, dp, dp, dp]
         L.oracle_pair.argtypes = [dp, dp, f64, f64, ctypes.c_int, f64, dp]
+        L.oracle_dense_LMn.argtypes = [i64, dp, i64, ip, f64, f64, f64, f64, dp, dp, dp, dp]
+        L.oracle_layer_rows_n.argtypes = [i64, dp, i64, ip, f64, f64, f64, f64, i64, ip, dp, dp, dp, dp]
+        L.oracle_pair4.argtypes = [dp, dp, dp, f64, f64, ctypes.c_int, f64, dp]
         _lib = L
     return _lib
 
@@ -113,6 +124,42 @@ def pair(x, tri_xyz, k, self=False, eta=DEFAULT_ETA):
     return out[0] + 1j * out[1], out[2] + 1j * out[3]
 
 
+def dense_LMn(V, T, k, rc, eta=DEFAULT_ETA):
+    """Dense L, M, L', M' (complex, N x N each); L', M' use the normal of the row element."""
+    V, T = _mesh(V, T)
+    n = T.shape[0]
+    out = [np.empty((n, n), np.complex128) for _ in range(4)]
+    k = complex(k)
+    lib().oracle_dense_LMn(V.shape[0], _d(V), n, _i(T), k.real, k.imag, float(rc), float(eta),
+                           *[_d(o) for o in out])
+    return tuple(out)
+
+
+def layer_rows_n(V, T, k, rc, rows, sigma, mu, eta=DEFAULT_ETA):
+    """Rows of L[sigma] + M[mu] and of L'[sigma] + M'[mu] at the listed collocation points."""
+    V, T = _mesh(V, T)
+    rows = np.ascontiguousarray(rows, np.int64)
+    sigma = np.ascontiguousarray(sigma, np.complex128)
+    mu = np.ascontiguousarray(mu, np.complex128)
+    y = np.empty(rows.shape[0], np.complex128)
+    yn = np.empty(rows.shape[0], np.complex128)
+    k = complex(k)
+    lib().oracle_layer_rows_n(V.shape[0], _d(V), T.shape[0], _i(T), k.real, k.imag, float(rc), float(eta),
+                              rows.shape[0], _i(rows), _d(sigma), _d(mu), _d(y), _d(yn))
+    return y, yn
+
+
+def pair4(x, nx, tri_xyz, k, self=False, eta=DEFAULT_ETA):
+    """Accurate (L, M, L', M') of one triangle at x with normal nx (self: x = centroid)."""
+    x = np.ascontiguousarray(x, np.float64)
+    nx = np.ascontiguousarray(nx, np.float64)
+    tri = np.ascontiguousarray(tri_xyz, np.float64)
+    out = np.empty(8)
+    k = complex(k)
+    lib().oracle_pair4(_d(x), _d(nx), _d(tri), k.real, k.imag, int(self), float(eta), _d(out))
+    return tuple(out[2 * q] + 1j * out[2 * q + 1] for q in range(4))
+
+
 # ----------------------------------------------------------------------------- problem data
 def green(x, y, k):
     r = np.linalg.norm(np.asarray(x) - np.asarray(y), axis=-1)
@@ -163,6 +210,59 @@ def direct_receivers(V, T, k, beta, rs, rc, x, pts, eta=DEFAULT_ETA):
     c, nrm, _ = geometry(V, T)
     g = gamma(c, nrm, beta, k, rs)
     sc = layer_field(V, T, k, rc, pts, g + 1j * k * beta * x, -x, eta)
+    return green(pts, np.asarray(rs)[None, :], k) + sc
+
+
+# ----------------------------------------------------------------------------- indirect formulation
+def gamma_pm(c, nrm, beta_m, beta_p, k, rs):
+    """g- = -dpsi_in/dn + i k beta- psi_in,  g+ = +dpsi_in/dn + i k beta+ psi_in (Eq. ibem4)."""
+    psi, dpsi = incident(c, nrm, k, rs)
+    return -dpsi + 1j * k * beta_m * psi, dpsi + 1j * k * beta_p * psi
+
+
+def indirect_system(V, T, k, beta_m, beta_p, rs, rc, eta=DEFAULT_ETA):
+    """Dense 2N x 2N operator and right-hand side of Eq. (ibem5), unknowns (psi-, psi+)."""
+    L, M, Lp, Mp = dense_LMn(V, T, k, rc, eta)
+    c, nrm, _ = geometry(V, T)
+    n = T.shape[0]
+    I = np.eye(n)
+    bm, bp = beta_m[None, :], beta_p[None, :]
+    # s = -ik(bm psi- + bp psi+), m = psi- - psi+
+    A = np.block([[0.5 * I - 1j * k * L * bm + M, 0.5 * I - 1j * k * L * bp - M],
+                  [np.diag(0.5j * k * beta_m) - 1j * k * Lp * bm + Mp, np.diag(-0.5j * k * beta_p) - 1j * k * Lp * bp - Mp]])
+    gm, gp = gamma_pm(c, nrm, beta_m, beta_p, k, rs)
+    b = np.concatenate([L @ (gm + gp), 0.5 * (gp - gm) + Lp @ (gm + gp)])
+    return A, b
+
+
+def indirect_matvec_rows(V, T, k, beta_m, beta_p, rc, x, rows, eta=DEFAULT_ETA):
+    """Rows (of both blocks) of the Eq. (ibem5) operator applied to x = (psi-, psi+)."""
+    n = T.shape[0]
+    rows = np.asarray(rows, np.int64)
+    pm, pp = x[:n], x[n:]
+    s = -1j * k * (beta_m * pm + beta_p * pp)
+    y, yn = layer_rows_n(V, T, k, rc, rows, s, pm - pp, eta)
+    r1 = 0.5 * (pm[rows] + pp[rows]) + y
+    r2 = 0.5j * k * (beta_m[rows] * pm[rows] - beta_p[rows] * pp[rows]) + yn
+    return r1, r2
+
+
+def indirect_rhs_rows(V, T, k, beta_m, beta_p, rs, rc, rows, eta=DEFAULT_ETA):
+    c, nrm, _ = geometry(V, T)
+    gm, gp = gamma_pm(c, nrm, beta_m, beta_p, k, rs)
+    rows = np.asarray(rows, np.int64)
+    y, yn = layer_rows_n(V, T, k, rc, rows, gm + gp, np.zeros_like(gm), eta)
+    return y, 0.5 * (gp - gm)[rows] + yn
+
+
+def indirect_receivers(V, T, k, beta_m, beta_p, rs, rc, x, pts, eta=DEFAULT_ETA):
+    """psi(r) = G(r, rs) + L[sigma](r) + M[mu](r)  (Eq. ibem1, ibem4)."""
+    n = T.shape[0]
+    c, nrm, _ = geometry(V, T)
+    gm, gp = gamma_pm(c, nrm, beta_m, beta_p, k, rs)
+    pm, pp = x[:n], x[n:]
+    sigma = gm + gp + 1j * k * (beta_m * pm + beta_p * pp)
+    sc = layer_field(V, T, k, rc, pts, sigma, pp - pm, eta)
     return green(pts, np.asarray(rs)[None, :], k) + sc
 
 

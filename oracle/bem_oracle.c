@@ -16,6 +16,14 @@
  * Gauss rule on each piece; the self pair uses three sub-triangles with apex at the centroid
  * and a Duffy map, which removes the 1/r singularity.  M_ii is zero (flat element,
  * in-plane collocation point: the principal value of Eq. dbem3 vanishes).
+ *
+ * For the indirect formulation (Eq. ibem3, ibem5) it also computes, with the normal n_x of the
+ * collocation element,
+ *   L'_j(x)       = int_{T_j} dG(x,y)/dn_x dS_y                      (zero on the element itself)
+ *   M'_j(x)       = d/dn_x int_{T_j} dG(x,y)/dn_y dS_y                (hypersingular)
+ * where for the element's own centroid M' is the Hadamard finite part: the in-plane kernel is
+ * (1 - ikr) e^{ikr} / (4 pi r^3) = 1/(4 pi r^3) + k^2/(8 pi r) + a bounded rest; the first two
+ * parts are integrated in closed form edge by edge, the rest by the same Duffy rule as L.
  */
 #include <complex.h>
 #include <math.h>
@@ -77,6 +85,24 @@ static inline void kern(const double *x, const double *y, const double *ny, cplx
     cplx G = cexp(I * k * r) / (4.0 * PI * r);
     *g = G;
     *dgdny = G * (I * k * r - 1.0) * dot3(d, ny) / (r * r);
+}
+
+/* the two normal-derivative kernels: dG/dn_x and d^2 G / dn_x dn_y (with d = y - x):
+ *   dG/dn_x        = G (ikr - 1) ((x - y).n_x) / r^2
+ *   d2G/dn_x dn_y  = -e^{ikr} (3 - 3ikr - k^2 r^2) (d.n_x)(d.n_y) / (4 pi r^5)
+ *                    - e^{ikr} (ikr - 1) (n_x.n_y) / (4 pi r^3)                              */
+static inline void kern_n(const double *x, const double *nx, const double *y, const double *ny, cplx k, cplx *g,
+                          cplx *dgdny, cplx *dgdnx, cplx *d2g) {
+    double d[3];
+    sub3(y, x, d);
+    double r = norm3(d), r2 = r * r;
+    cplx e = cexp(I * k * r) / (4.0 * PI);
+    cplx G = e / r;
+    double dnx = dot3(d, nx), dny = dot3(d, ny);
+    *g = G;
+    *dgdny = G * (I * k * r - 1.0) * dny / r2;
+    *dgdnx = -G * (I * k * r - 1.0) * dnx / r2;
+    *d2g = -e * (3.0 - 3.0 * I * k * r - k * k * r2) * dnx * dny / (r2 * r2 * r) - e * (I * k * r - 1.0) * dot3(nx, ny) / (r2 * r);
 }
 
 /* ---------------------------------------------------------------- geometry */
@@ -145,6 +171,117 @@ static void adapt_tri(const double *x, const double *a, const double *b, const d
     adapt_tri(x, mab, b, mbe, ny, k, eta, depth + 1, L, M);
     adapt_tri(x, mea, mbe, e, ny, k, eta, depth + 1, L, M);
     adapt_tri(x, mab, mbe, mea, ny, k, eta, depth + 1, L, M);
+}
+
+/* the same conical rule and subdivision for the four kernels (L, M, L', M') */
+static void rule_tri4(const double *x, const double *nx, const double *a, const double *b, const double *e,
+                      const double *ny, cplx k, cplx *out) {
+    double u[3], v[3], w[3];
+    sub3(b, a, u);
+    sub3(e, b, v);
+    cross3(u, v, w);
+    double twoA = norm3(w);
+    cplx s[4] = {0, 0, 0, 0};
+    for (int i = 0; i < QN; ++i) {
+        double sp = gx8[i];
+        for (int j = 0; j < QN; ++j) {
+            double t = gx8[j], y[3];
+            for (int q = 0; q < 3; ++q) y[q] = a[q] + sp * u[q] + sp * t * v[q];
+            cplx g, dg, dgx, d2;
+            kern_n(x, nx, y, ny, k, &g, &dg, &dgx, &d2);
+            double wt = gw8[i] * gw8[j] * twoA * sp;
+            s[0] += wt * g;
+            s[1] += wt * dg;
+            s[2] += wt * dgx;
+            s[3] += wt * d2;
+        }
+    }
+    for (int q = 0; q < 4; ++q) out[q] += s[q];
+}
+
+static void adapt_tri4(const double *x, const double *nx, const double *a, const double *b, const double *e,
+                       const double *ny, cplx k, double eta, int depth, cplx *out) {
+    double cen[3], d[3], ab[3], be[3], ea[3];
+    for (int q = 0; q < 3; ++q) cen[q] = (a[q] + b[q] + e[q]) / 3.0;
+    sub3(cen, x, d);
+    sub3(b, a, ab);
+    sub3(e, b, be);
+    sub3(a, e, ea);
+    double diam = fmax(norm3(ab), fmax(norm3(be), norm3(ea)));
+    if (diam < eta * norm3(d) || depth >= 16) {
+        rule_tri4(x, nx, a, b, e, ny, k, out);
+        return;
+    }
+    double mab[3], mbe[3], mea[3];
+    for (int q = 0; q < 3; ++q) {
+        mab[q] = 0.5 * (a[q] + b[q]);
+        mbe[q] = 0.5 * (b[q] + e[q]);
+        mea[q] = 0.5 * (e[q] + a[q]);
+    }
+    adapt_tri4(x, nx, a, mab, mea, ny, k, eta, depth + 1, out);
+    adapt_tri4(x, nx, mab, b, mbe, ny, k, eta, depth + 1, out);
+    adapt_tri4(x, nx, mea, mbe, e, ny, k, eta, depth + 1, out);
+    adapt_tri4(x, nx, mab, mbe, mea, ny, k, eta, depth + 1, out);
+}
+
+/* Finite part of M' over the collocation element itself (x in the plane of T).
+ *   f.p. int_T dS / (4 pi r^3) = -(1/4pi) oint dtheta / R(theta): for the edge (va, vb) seen
+ *   from x at perpendicular distance h, with signed positions s_a, s_b of va, vb along the
+ *   edge from the foot of the perpendicular, the angular integral is (s_b/|x-vb| - s_a/|x-va|)/h;
+ *   int_T dS / r = sum over edges h (asinh(s_b/h) - asinh(s_a/h));
+ *   the rest [e^{ikr}(1 - ikr) - 1 - k^2 r^2/2] / (4 pi r^3) is bounded and integrated with
+ *   the Duffy rule of self_L (series in ikr for small |kr|, where the difference cancels). */
+static cplx rest_mp(cplx k, double r) {
+    cplx z = I * k * r;
+    if (cabs(z) < 0.5) {
+        /* e^z (1 - z) - 1 + z^2/2 = sum_{n>=3} (1 - n) z^n / n! */
+        cplx term = z * z / 2.0, s = 0;
+        for (int n = 3; n < 30; ++n) {
+            term *= z / n;
+            s += (1.0 - n) * term;
+        }
+        return s / (4.0 * PI * r * r * r);
+    }
+    return (cexp(z) * (1.0 - z) - 1.0 + z * z / 2.0) / (4.0 * PI * r * r * r);
+}
+
+static cplx self_Mp(const double *x, const double *p0, const double *p1, const double *p2, cplx k) {
+    enum { NPT = 8 };
+    const double *P[3] = {p0, p1, p2};
+    double fp_inv_r3 = 0.0, int_inv_r = 0.0;
+    cplx rest = 0;
+    for (int e = 0; e < 3; ++e) {
+        const double *va = P[e], *vb = P[(e + 1) % 3];
+        double ev[3], xa[3];
+        sub3(vb, va, ev);
+        double len = norm3(ev);
+        for (int q = 0; q < 3; ++q) ev[q] /= len;
+        sub3(va, x, xa);
+        double sa = dot3(xa, ev), sb = sa + len, perp[3];
+        for (int q = 0; q < 3; ++q) perp[q] = xa[q] - sa * ev[q];
+        double h = norm3(perp);
+        double ra = sqrt(sa * sa + h * h), rb = sqrt(sb * sb + h * h);
+        fp_inv_r3 += (sb / rb - sa / ra) / h;
+        int_inv_r += h * (asinh(sb / h) - asinh(sa / h));
+        /* Duffy rule for the bounded rest on the sub-triangle (x, va, vb) */
+        double u[3], v[3], w[3];
+        sub3(va, x, u);
+        sub3(vb, va, v);
+        cross3(u, v, w);
+        double twoA = norm3(w);
+        for (int pt = 0; pt < NPT; ++pt) {
+            for (int j = 0; j < QS; ++j) {
+                double t = (pt + gxs[j]) / NPT, wt = gws[j] / NPT, d[3];
+                for (int q = 0; q < 3; ++q) d[q] = u[q] + t * v[q];
+                double rho = norm3(d);
+                for (int i = 0; i < QS; ++i) {
+                    double r = gxs[i] * rho;
+                    rest += gws[i] * wt * twoA * gxs[i] * rest_mp(k, r);  /* dS = twoA s ds dt */
+                }
+            }
+        }
+    }
+    return -fp_inv_r3 / (4.0 * PI) + k * k * int_inv_r / (8.0 * PI) + rest;
 }
 
 /* self integral of G over T with the collocation point x = centroid: three sub-triangles
@@ -318,4 +455,114 @@ void oracle_pair(const double *x, const double *tri_xyz, double kr, double ki, i
     LM[1] = cimag(L);
     LM[2] = creal(M);
     LM[3] = cimag(M);
+}
+
+/* ---------------------------------------------------------------- indirect formulation */
+/* L, M, L', M' of element j at the centroid of element i (normal n_i), with the same near/far
+ * classification as pair_LM */
+static void pair_4(int64_t i, int64_t j, const double *V, const int64_t *T, const double *c, const double *nrm,
+                   const double *area, cplx k, double rc2, double eta, cplx *out) {
+    const double *x = c + 3 * i, *y = c + 3 * j, *nx = nrm + 3 * i, *ny = nrm + 3 * j;
+    double d[3];
+    sub3(y, x, d);
+    double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    const int64_t *tri = T + 3 * j;
+    const double *a = V + 3 * tri[0], *b = V + 3 * tri[1], *e = V + 3 * tri[2];
+    if (i == j) {
+        out[0] = self_L(x, a, b, e, k);
+        out[1] = 0.0;
+        out[2] = 0.0;
+        out[3] = self_Mp(x, a, b, e, k);
+    } else if (r2 < rc2) {
+        for (int q = 0; q < 4; ++q) out[q] = 0;
+        adapt_tri4(x, nx, a, b, e, ny, k, eta, 0, out);
+    } else {
+        cplx g, dg, dgx, d2;
+        kern_n(x, nx, y, ny, k, &g, &dg, &dgx, &d2);
+        out[0] = g * area[j];
+        out[1] = dg * area[j];
+        out[2] = dgx * area[j];
+        out[3] = d2 * area[j];
+    }
+}
+
+/* Dense L, M, L', M' (row-major N x N complex interleaved each). */
+void oracle_dense_LMn(int64_t nv, const double *V, int64_t nt, const int64_t *T, double kr, double ki, double rc,
+                      double eta, double *Lout, double *Mout, double *Lpout, double *Mpout) {
+    (void)nv;
+    init_rules();
+    cplx k = kr + I * ki;
+    double *c = malloc(sizeof(double) * 3 * nt), *nrm = malloc(sizeof(double) * 3 * nt), *area = malloc(sizeof(double) * nt);
+    oracle_geometry(nt, V, T, c, nrm, area);
+    double rc2 = rc * rc;
+    double *outs[4] = {Lout, Mout, Lpout, Mpout};
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < nt; ++i) {
+        for (int64_t j = 0; j < nt; ++j) {
+            cplx v[4];
+            pair_4(i, j, V, T, c, nrm, area, k, rc2, eta, v);
+            for (int q = 0; q < 4; ++q) {
+                outs[q][2 * (i * nt + j)] = creal(v[q]);
+                outs[q][2 * (i * nt + j) + 1] = cimag(v[q]);
+            }
+        }
+    }
+    free(c);
+    free(nrm);
+    free(area);
+}
+
+/* Matrix-free rows of y_i = sum_j [L_ij s_j + M_ij m_j] and yn_i = sum_j [L'_ij s_j + M'_ij m_j]. */
+void oracle_layer_rows_n(int64_t nv, const double *V, int64_t nt, const int64_t *T, double kr, double ki, double rc,
+                         double eta, int64_t nrows, const int64_t *rows, const double *sigma, const double *mu,
+                         double *yout, double *ynout) {
+    (void)nv;
+    init_rules();
+    cplx k = kr + I * ki;
+    double *c = malloc(sizeof(double) * 3 * nt), *nrm = malloc(sizeof(double) * 3 * nt), *area = malloc(sizeof(double) * nt);
+    oracle_geometry(nt, V, T, c, nrm, area);
+    double rc2 = rc * rc;
+    const cplx *sg = (const cplx *)sigma, *m = (const cplx *)mu;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t r = 0; r < nrows; ++r) {
+        int64_t i = rows[r];
+        cplx acc = 0, accn = 0;
+        for (int64_t j = 0; j < nt; ++j) {
+            cplx v[4];
+            pair_4(i, j, V, T, c, nrm, area, k, rc2, eta, v);
+            acc += v[0] * sg[j] + v[1] * m[j];
+            accn += v[2] * sg[j] + v[3] * m[j];
+        }
+        yout[2 * r] = creal(acc);
+        yout[2 * r + 1] = cimag(acc);
+        ynout[2 * r] = creal(accn);
+        ynout[2 * r + 1] = cimag(accn);
+    }
+    free(c);
+    free(nrm);
+    free(area);
+}
+
+/* One accurate pair of all four integrals at x with normal nx (self=1: x is T's centroid and
+ * nx its normal); out = L, M, L', M' interleaved. */
+void oracle_pair4(const double *x, const double *nx, const double *tri_xyz, double kr, double ki, int self,
+                  double eta, double *out) {
+    init_rules();
+    double u[3], v[3], w[3];
+    sub3(tri_xyz + 3, tri_xyz, u);
+    sub3(tri_xyz + 6, tri_xyz, v);
+    cross3(u, v, w);
+    double l = norm3(w), ny[3] = {w[0] / l, w[1] / l, w[2] / l};
+    cplx k = kr + I * ki, r[4] = {0, 0, 0, 0};
+    const double *a = tri_xyz, *b = tri_xyz + 3, *e = tri_xyz + 6;
+    if (self) {
+        r[0] = self_L(x, a, b, e, k);
+        r[3] = self_Mp(x, a, b, e, k);
+    } else {
+        adapt_tri4(x, nx, a, b, e, ny, k, eta, 0, r);
+    }
+    for (int q = 0; q < 4; ++q) {
+        out[2 * q] = creal(r[q]);
+        out[2 * q + 1] = cimag(r[q]);
+    }
 }
