@@ -58,7 +58,12 @@ enum {
 };
 
 /* formulations (Section 3.1 / 3.2) */
-enum { FMMBEM_DIRECT = 0 /* Eq. dbem4 */ };
+enum {
+    FMMBEM_DIRECT = 0,  /* Eq. dbem4: unknown psi_sc at each element (N unknowns) */
+    FMMBEM_INDIRECT = 3 /* Eq. ibem5: every element two-sided, unknowns (psi-, psi+) = the field on
+                           the side the normal leaves (the room) and on the side it points to
+                           (2N unknowns, psi- block first); FP64 products only */
+};
 
 /* arithmetic of the matrix-vector product */
 enum {
@@ -127,17 +132,27 @@ int fmmbem_set_admittance(fmmbem_ctx *ctx, const fmmbem_c64 *beta);
 /* Unit monopole sources (Eq. sp6): ns positions rs (ns*3), optional complex amplitudes (NULL = 1). */
 int fmmbem_set_sources(fmmbem_ctx *ctx, int32_t ns, const double *rs, const fmmbem_c64 *amp);
 
-/* Only FMMBEM_DIRECT is accepted. */
+/* FMMBEM_DIRECT or FMMBEM_INDIRECT.  The indirect formulation adds the near entries of L'
+ * and the hypersingular M' (Eq. ibem3; built on first use) and evaluates the normal derivative
+ * of the far field at every element; preconditioners: FMMBEM_PC_NONE or FMMBEM_PC_DIAG
+ * (2x2 element blocks). */
 int fmmbem_set_formulation(fmmbem_ctx *ctx, int formulation);
+
+/* Admittance of the + faces for the indirect formulation (nt values, Re >= 0); NULL: the same
+ * as fmmbem_set_admittance (one material on both faces).  A hole (open doorway) is modelled by
+ * leaving its elements out of the mesh. */
+int fmmbem_set_admittance_plus(fmmbem_ctx *ctx, const fmmbem_c64 *beta_plus);
 
 /* Build what is out of date: octree and interaction lists (mesh), translation and rotation
  * tables and near-field entries (k), preconditioner data.  Idempotent; matvec/solve call it. */
 int fmmbem_setup(fmmbem_ctx *ctx);
 
-/* Number of unknowns N (one per triangle for the direct formulation); -1 if no mesh. */
+/* Number of unknowns: N for the direct formulation, 2N for the indirect one; -1 if no mesh.
+ * Every vector argument below (x, y, b) has this length per right-hand side. */
 int64_t fmmbem_num_unknowns(const fmmbem_ctx *ctx);
 
-/* Right-hand side b = L gamma of Eq. (dbem4), one vector of N per source: b is ns*N. */
+/* Right-hand side, one vector per source (b is ns x num_unknowns): b = L gamma (Eq. dbem4), or
+ * for Eq. ibem5 (L[g- + g+], (g+ - g-)/2 + L'[g- + g+]) with g-+ = -+ dpsi_in/dn + i k beta-+ psi_in. */
 int fmmbem_rhs(fmmbem_ctx *ctx, fmmbem_c64 *b);
 
 /* y = A x for nrhs vectors (x, y: nrhs*N, host memory).  precision: FMMBEM_FP64 / FMMBEM_MIXED.
@@ -257,7 +272,9 @@ int fmmbem_release_workspace(fmmbem_ctx *ctx);
 int fmmbem_solve_history(fmmbem_ctx *ctx, int32_t max, double *est, int32_t *count);
 
 /* Total field at nr points inside the room from the solved surface field x of source isrc
- * (Eq. dbem1): psi(r) = G(r, r_s) + L[gamma + i k beta x](r) - M[x](r).  psi: nr values. */
+ * (Eq. dbem1): psi(r) = G(r, r_s) + L[gamma + i k beta x](r) - M[x](r); indirect (Eq. ibem1,
+ * ibem4): psi = G(r, r_s) + L[sigma] + M[mu], sigma = g- + g+ + i k (beta- psi- + beta+ psi+),
+ * mu = psi+ - psi-.  psi: nr values. */
 int fmmbem_eval_field(fmmbem_ctx *ctx, int32_t isrc, int64_t nr, const double *r, const fmmbem_c64 *x,
                       fmmbem_c64 *psi);
 
@@ -287,6 +304,10 @@ int fmmbem_get_info(fmmbem_ctx *ctx, fmmbem_info *info);
 
 /* Accurate near entries (sorted by row, caller order): count via *nnz when rows == NULL. */
 int fmmbem_near_entries(fmmbem_ctx *ctx, int64_t *nnz, int64_t *rows, int64_t *cols, fmmbem_c64 *L, fmmbem_c64 *M);
+
+/* The L' and M' near entries (Eq. ibem3) in the order of fmmbem_near_entries (count via *nnz
+ * when both arrays are NULL). */
+int fmmbem_near_entries_n(fmmbem_ctx *ctx, int64_t *nnz, fmmbem_c64 *Lp, fmmbem_c64 *Mp);
 
 /* Coaxial translation coefficients (Eq. shft0.1) computed on device `hip_device`:
  * kind 0 = (S|R), 1 = (R|R); method 0 = original recursion, 1 = stabilised, -1 = by the

@@ -21,6 +21,25 @@ __global__ void k_densities(int64_t, int, const int32_t *, const double2 *, cons
 __global__ void k_gamma(int64_t, const double4 *, const double4 *, const double2 *, double, double, double, double,
                         double2, double2 *, double2 *);
 __global__ void k_zero8(int64_t, uint64_t *);
+__global__ void k_near_quad_n(int64_t, const int32_t *, const int32_t *, const double4 *, const double4 *,
+                              const double *, double, double2 *, double2 *);
+__global__ void k_gamma_pm(int64_t, const double4 *, const double4 *, const double2 *, const double2 *, double, double,
+                           double, double, double2, double2 *, double2 *);
+__global__ void k_densities_ind(int64_t, const int32_t *, const double2 *, const double2 *, const double2 *, double,
+                                double2 *, double2 *);
+__global__ void k_field_dens_ind(int64_t, const int32_t *, const double2 *, const double2 *, const double2 *,
+                                 const double2 *, const double2 *, double, double2 *, double2 *);
+__global__ void k_rhs_ind_local(int64_t, const int32_t *, const double2 *, const double2 *, double2 *);
+__global__ void k_p2p_n(int, const int32_t *, const int32_t *, const int32_t *, int, const double4 *, const double4 *,
+                        const double2 *, const double2 *, double, double, const int32_t *, const int32_t *,
+                        const double2 *, const double2 *, const double2 *, const double2 *, double2 *, double2 *);
+__global__ void k_local_derivs(int64_t, int, const double2 *, double, double2 *, double2 *, double2 *);
+__global__ void k_l2p_n(int, int, const int32_t *, const double4 *, const double4 *, const double4 *, const double2 *,
+                        const double2 *, const double2 *, const double2 *, double, const double2 *, const double2 *,
+                        const int32_t *, int64_t, const double2 *, const double2 *, const double2 *, double2 *, int);
+__global__ void k_diag2_inv(int64_t, const int32_t *, const int32_t *, const double2 *, const double2 *,
+                            const double2 *, const double2 *, double, double, double2 *);
+__global__ void k_mul_diag2(int64_t, const int32_t *, const double2 *, const double2 *, double2 *);
 void launch_p2p(int nr, bool fp32, int nleaf, const int32_t *leaf_start, const int32_t *nbr_start,
                 const int32_t *nbr_list, int all_leaves, const double4 *ec, const double4 *en, const double2 *sigma,
                 const double2 *mu, double k, double rc2, const int32_t *near_start, const int32_t *near_col,
@@ -440,6 +459,7 @@ static void ensure_setup(fmmbem_ctx *c) {
         drop_graphs(c);
         c->chunks_ready = false;
     }
+    if (c->mesh_dirty || c->k_dirty) c->indirect_ready = false;
     if (c->mesh_dirty) {
         setup_mesh(c);
         c->k_dirty = true;
@@ -454,9 +474,13 @@ static void ensure_setup(fmmbem_ctx *c) {
     }
     if (c->beta_dirty) {
         if (!c->have_beta) c->beta.assign(c->nt, cmk(0, 0));
-        std::vector<double2> bs(c->nt);
-        for (int64_t i = 0; i < c->nt; ++i) bs[i] = c->beta[c->tree.perm[i]];
+        std::vector<double2> bs(c->nt), bp(c->nt);
+        for (int64_t i = 0; i < c->nt; ++i) {
+            bs[i] = c->beta[c->tree.perm[i]];
+            bp[i] = c->beta_plus.empty() ? bs[i] : c->beta_plus[c->tree.perm[i]];
+        }
         upload(c->buf, "beta", bs, c->stream);
+        upload(c->buf, "betap", bp, c->stream);
         HIP_OK(hipStreamSynchronize(c->stream));
         c->beta_dirty = false;
         c->precond_ready_nb = c->precond_ready_diag = false;
@@ -846,6 +870,109 @@ static void rhs_dev(fmmbem_ctx *c, int isrc, double2 *b) {
     HIP_OK(hipEventRecord(c->ev[8], st));
 }
 
+// ------------------------------------------------------------------ indirect formulation (Eq. ibem5)
+static bool indirect(const fmmbem_ctx *c) { return c->formulation == FMMBEM_INDIRECT; }
+
+// L' and M' near entries (same CSR as L and M), built once per (mesh, k) when first needed
+static void ensure_indirect(fmmbem_ctx *c) {
+    if (c->indirect_ready) return;
+    hipStream_t st = c->stream;
+    double2 *lp = dget<double2>(c->buf, "near_Lp", c->near_nnz), *mp = dget<double2>(c->buf, "near_Mp", c->near_nnz);
+    if (c->near_nnz > 0) {
+        k_near_quad_n<<<ceil_div(c->near_nnz, 128), 128, 0, st>>>(
+            c->near_nnz, (int32_t *)c->buf.find("near_row"), (int32_t *)c->buf.find("near_col"),
+            (double4 *)c->buf.find("ec"), (double4 *)c->buf.find("en"), (double *)c->buf.find("ev"), c->k, lp, mp);
+        LAUNCH_OK();
+    }
+    HIP_OK(hipStreamSynchronize(st));
+    c->indirect_ready = true;
+}
+
+// potential (row 1) and normal derivative (row 2) of the layers (sigma, mu) at the centroids,
+// plus the local terms of Eq. ibem5 when x (2N, caller order) is given; y is 2N.
+static void fmm_pass_ind(fmmbem_ctx *c, const double2 *sigma, const double2 *mu, const double2 *x, double2 *y,
+                         bool exact_far) {
+    ensure_indirect(c);
+    TreeHost &T = c->tree;
+    const int L = T.depth;
+    hipStream_t st = c->stream;
+    const int64_t n = c->nt;
+    const int nleaf = (int)T.leaf_start.size() - 1;
+    auto I32 = [&](const char *s) { return (int32_t *)c->buf.find(s); };
+    const double4 *ec = (double4 *)c->buf.find("ec"), *en = (double4 *)c->buf.find("en");
+    double2 *yv = dget<double2>(c->scratch, "ynear", n), *yn = dget<double2>(c->scratch, "ynearn", n);
+    int pe = prof_begin(c);
+    k_p2p_n<<<nleaf, 64, 0, st>>>(nleaf, I32("leaf_start"), I32("nbr_start"), I32("nbr_list"), exact_far ? 1 : 0, ec, en,
+                                  sigma, mu, c->k, c->rc * c->rc, I32("near_start"), I32("near_col"),
+                                  (double2 *)c->buf.find("near_L"), (double2 *)c->buf.find("near_M"),
+                                  (double2 *)c->buf.find("near_Lp"), (double2 *)c->buf.find("near_Mp"), yv, yn);
+    LAUNCH_OK();
+    prof_end(c, pe, "k_p2p_n", 100.0 * (exact_far ? (double)n * n : (double)c->p2p_pairs), 0.0);
+    LevelDev &LL = c->lev[L];
+    const int p = LL.p;
+    const size_t q1 = (size_t)(p + 1) * (p + 1);
+    double2 *Dz = dget<double2>(c->scratch, "ind_Dz", LL.nbox * q1), *Dp = dget<double2>(c->scratch, "ind_Dp", LL.nbox * q1),
+            *Dm = dget<double2>(c->scratch, "ind_Dm", LL.nbox * q1);
+    if (!exact_far) {
+        const size_t per = p2m_stage_bytes(1, p);
+        const int CH = (int)std::max<size_t>(1, std::min<size_t>(32, 60000 / per));
+        launch_p2m(1, nleaf, p, CH, I32("leaf_start"), LL.center, ec, en, sigma, mu, c->k, LL.M, st);
+        const double2 *ph = (double2 *)c->buf.find("phA");
+        for (int l = L - 1; l >= 2; --l) {
+            LevelDev &P_ = c->lev[l], &C_ = c->lev[l + 1];
+            zero_dev(c, P_.M, sizeof(double2) * P_.nbox * P_.p * P_.p);
+            run_batch<double>(c, 1, P_.up, C_.M, P_.M, tables64(P_.up, P_.coax_up), ph);
+        }
+        for (int l = 2; l <= L; ++l) {
+            LevelDev &D = c->lev[l];
+            zero_dev(c, D.L, sizeof(double2) * D.nbox * D.p * D.p);
+            run_batch<double>(c, 1, D.m2l, D.M, D.L, tables64(D.m2l, D.coax_m2l), ph);
+            if (l >= 3) {
+                LevelDev &P_ = c->lev[l - 1];
+                run_batch<double>(c, 1, P_.down, P_.L, D.L, tables64(P_.down, P_.coax_up), ph);
+            }
+        }
+        k_local_derivs<<<nleaf, 256, 0, st>>>(nleaf, p, LL.L, c->k, Dz, Dp, Dm);
+        LAUNCH_OK();
+    }
+    pe = prof_begin(c);
+    k_l2p_n<<<nleaf, 64, (size_t)64 * (p + 3) * sizeof(double), st>>>(
+        nleaf, p, I32("leaf_start"), LL.center, ec, en, LL.L, Dz, Dp, Dm, c->k, yv, yn, I32("perm"), n, x,
+        (double2 *)c->buf.find("beta"), (double2 *)c->buf.find("betap"), y, exact_far ? 0 : 1);
+    LAUNCH_OK();
+    prof_end(c, pe, "k_l2p_n", (double)n * q1 * 8.0 * 4, 0.0);
+}
+
+static void matvec_ind(fmmbem_ctx *c, const double2 *x, double2 *y, bool exact_far) {
+    const int64_t n = c->nt;
+    double2 *sigma = dget<double2>(c->scratch, "sigma", n), *mu = dget<double2>(c->scratch, "mu", n);
+    rec(c, 0);
+    k_densities_ind<<<ceil_div(n, 256), 256, 0, c->stream>>>(n, (int32_t *)c->buf.find("perm"), x,
+                                                             (double2 *)c->buf.find("beta"),
+                                                             (double2 *)c->buf.find("betap"), c->k, sigma, mu);
+    LAUNCH_OK();
+    fmm_pass_ind(c, sigma, mu, x, y, exact_far);
+    rec(c, 8);
+}
+
+static void rhs_ind(fmmbem_ctx *c, int isrc, double2 *b) {
+    hipStream_t st = c->stream;
+    const int64_t n = c->nt;
+    double2 *gm = dget<double2>(c->scratch, "ind_gm", n), *gp = dget<double2>(c->scratch, "ind_gp", n);
+    double2 *sigma = dget<double2>(c->scratch, "sigma", n), *mu = dget<double2>(c->scratch, "mu", n);
+    const double *rs = &c->src[3 * isrc];
+    k_gamma_pm<<<ceil_div(n, 256), 256, 0, st>>>(n, (double4 *)c->buf.find("ec"), (double4 *)c->buf.find("en"),
+                                                 (double2 *)c->buf.find("beta"), (double2 *)c->buf.find("betap"), c->k,
+                                                 rs[0], rs[1], rs[2], c->src_amp[isrc], gm, gp);
+    LAUNCH_OK();
+    // sigma = g- + g+, mu = 0; row 2 also gets (g+ - g-)/2
+    vec_add(n, gm, gp, sigma, st);
+    zero_dev(c, mu, sizeof(double2) * n);
+    fmm_pass_ind(c, sigma, mu, nullptr, b, false);
+    k_rhs_ind_local<<<ceil_div(n, 256), 256, 0, st>>>(n, (int32_t *)c->buf.find("perm"), gm, gp, b);
+    LAUNCH_OK();
+}
+
 }  // namespace fmm
 
 using namespace fmm;
@@ -1036,8 +1163,26 @@ int fmmbem_set_sources(fmmbem_ctx *ctx, int32_t ns, const double *rs, const fmmb
 
 int fmmbem_set_formulation(fmmbem_ctx *ctx, int f) {
     if (!ctx) return FMMBEM_EINVAL;
-    if (f != FMMBEM_DIRECT) return fail(ctx, FMMBEM_EINVAL, "only the direct formulation (Eq. dbem4) is available");
+    if (f != FMMBEM_DIRECT && f != FMMBEM_INDIRECT)
+        return fail(ctx, FMMBEM_EINVAL, "formulation must be FMMBEM_DIRECT (Eq. dbem4) or FMMBEM_INDIRECT (Eq. ibem5)");
+    if (f != ctx->formulation) drop_graphs(ctx);
     ctx->formulation = f;
+    return FMMBEM_OK;
+}
+
+int fmmbem_set_admittance_plus(fmmbem_ctx *ctx, const fmmbem_c64 *beta_plus) {
+    if (!ctx) return FMMBEM_EINVAL;
+    if (!ctx->have_mesh) return fail(ctx, FMMBEM_ENOTREADY, "set the mesh before the admittance");
+    if (!beta_plus) {
+        ctx->beta_plus.clear();
+    } else {
+        for (int64_t i = 0; i < ctx->nt; ++i)
+            if (!(beta_plus[i].re >= 0.0) || !std::isfinite(beta_plus[i].im))
+                return fail(ctx, FMMBEM_EINVAL, "beta_plus[" + std::to_string(i) + "]: Re(beta) must be >= 0");
+        ctx->beta_plus.resize(ctx->nt);
+        for (int64_t i = 0; i < ctx->nt; ++i) ctx->beta_plus[i] = cmk(beta_plus[i].re, beta_plus[i].im);
+    }
+    ctx->beta_dirty = true;
     return FMMBEM_OK;
 }
 
@@ -1050,7 +1195,10 @@ int fmmbem_setup(fmmbem_ctx *ctx) {
     GUARD_END
 }
 
-int64_t fmmbem_num_unknowns(const fmmbem_ctx *ctx) { return (ctx && ctx->have_mesh) ? ctx->nt : -1; }
+int64_t fmmbem_num_unknowns(const fmmbem_ctx *ctx) {
+    if (!ctx || !ctx->have_mesh) return -1;
+    return ctx->formulation == FMMBEM_INDIRECT ? 2 * ctx->nt : ctx->nt;
+}
 
 int fmmbem_rhs(fmmbem_ctx *ctx, fmmbem_c64 *b) {
     if (!ctx) return FMMBEM_EINVAL;
@@ -1059,10 +1207,11 @@ int fmmbem_rhs(fmmbem_ctx *ctx, fmmbem_c64 *b) {
     HIP_OK(hipSetDevice(ctx->device));
     if (ctx->src.empty()) return fail(ctx, FMMBEM_ENOTREADY, "sources not set");
     ensure_setup(ctx);
-    const int64_t n = ctx->nt;
+    const int64_t n = fmmbem_num_unknowns(ctx);
     double2 *db = dget<double2>(ctx->scratch, "rhs_out", n);
     for (size_t s = 0; s < ctx->src.size() / 3; ++s) {
-        rhs_dev(ctx, (int)s, db);
+        if (indirect(ctx)) rhs_ind(ctx, (int)s, db);
+        else rhs_dev(ctx, (int)s, db);
         HIP_OK(hipMemcpyAsync(b + s * n, db, sizeof(double2) * n, hipMemcpyDeviceToHost, ctx->stream));
     }
     HIP_OK(hipStreamSynchronize(ctx->stream));
@@ -1078,6 +1227,18 @@ int fmmbem_matvec(fmmbem_ctx *ctx, int32_t nrhs, const fmmbem_c64 *x, fmmbem_c64
     GUARD_BEGIN
     HIP_OK(hipSetDevice(ctx->device));
     ensure_setup(ctx);
+    if (indirect(ctx)) {
+        if (precision != FMMBEM_FP64) return fail(ctx, FMMBEM_EINVAL, "indirect products are FP64");
+        const int64_t n2 = 2 * ctx->nt;
+        double2 *dx = dget<double2>(ctx->scratch, "mv_x", n2), *dy = dget<double2>(ctx->scratch, "mv_y", n2);
+        for (int r = 0; r < nrhs; ++r) {
+            HIP_OK(hipMemcpyAsync(dx, x + (int64_t)r * n2, sizeof(double2) * n2, hipMemcpyHostToDevice, ctx->stream));
+            matvec_ind(ctx, dx, dy, exact_far != 0);
+            HIP_OK(hipMemcpyAsync(y + (int64_t)r * n2, dy, sizeof(double2) * n2, hipMemcpyDeviceToHost, ctx->stream));
+            HIP_OK(hipStreamSynchronize(ctx->stream));
+        }
+        return FMMBEM_OK;
+    }
     const int64_t n = ctx->nt;
     double2 *dx = dget<double2>(ctx->scratch, "mv_x", (size_t)n * std::min(nrhs, 4));
     double2 *dy = dget<double2>(ctx->scratch, "mv_y", (size_t)n * std::min(nrhs, 4));
@@ -1108,7 +1269,13 @@ int fmmbem_matvec_dev(fmmbem_ctx *ctx, int32_t nrhs, const void *x, void *y, int
     // order after the caller's stream, run on ours, then make the caller's stream wait
     HIP_OK(hipEventRecord(e0, caller));
     HIP_OK(hipStreamWaitEvent(ctx->stream, e0, 0));
-    matvec_dev(ctx, nrhs, (const double2 *)x, (double2 *)y, false, precision == FMMBEM_MIXED);
+    if (indirect(ctx)) {
+        if (precision != FMMBEM_FP64) return fail(ctx, FMMBEM_EINVAL, "indirect products are FP64");
+        for (int r = 0; r < nrhs; ++r)
+            matvec_ind(ctx, (const double2 *)x + (int64_t)r * 2 * n, (double2 *)y + (int64_t)r * 2 * n, false);
+    } else {
+        matvec_dev(ctx, nrhs, (const double2 *)x, (double2 *)y, false, precision == FMMBEM_MIXED);
+    }
     HIP_OK(hipStreamWaitEvent(caller, ctx->ev[8], 0));
     return FMMBEM_OK;
     GUARD_END
@@ -1188,6 +1355,28 @@ static std::function<void(const double2 *, double2 *)> make_precond(fmmbem_ctx *
     hipStream_t st = ctx->stream;
     const int64_t n = ctx->nt;
     const int nleaf = (int)ctx->tree.leaf_start.size() - 1;
+    if (ctx->formulation == FMMBEM_INDIRECT) {
+        // the paper's choice for the indirect BEM: a diagonal preconditioner (here the 2x2 blocks
+        // of each element's (psi-, psi+) pair, with the constant diag_shift added)
+        if (o.precond == FMMBEM_PC_NONE)
+            return [=](const double2 *v, double2 *z) {
+                HIP_OK(hipMemcpyAsync(z, v, sizeof(double2) * 2 * n, hipMemcpyDeviceToDevice, st));
+            };
+        if (o.precond != FMMBEM_PC_DIAG)
+            throw FmmError(FMMBEM_EINVAL, "the indirect formulation takes FMMBEM_PC_NONE or FMMBEM_PC_DIAG");
+        ensure_indirect(ctx);
+        double2 *inv = dget<double2>(ctx->buf, "pc_dinv2", 4 * n);
+        k_diag2_inv<<<ceil_div(n, 256), 256, 0, st>>>(n, (int32_t *)ctx->buf.find("near_start"),
+                                                      (int32_t *)ctx->buf.find("near_col"), (double2 *)ctx->buf.find("near_L"),
+                                                      (double2 *)ctx->buf.find("near_Mp"), (double2 *)ctx->buf.find("beta"),
+                                                      (double2 *)ctx->buf.find("betap"), ctx->k, o.diag_shift, inv);
+        LAUNCH_OK();
+        const int32_t *pm = (int32_t *)ctx->buf.find("perm");
+        return [=](const double2 *v, double2 *z) {
+            k_mul_diag2<<<ceil_div(n, 256), 256, 0, st>>>(n, pm, inv, v, z);
+            LAUNCH_OK();
+        };
+    }
     if (o.precond == FMMBEM_PC_LEARNED) {
         if (!ctx->mlp.ready) throw FmmError(FMMBEM_ENOTREADY, "learned preconditioner not trained");
         fmmbem_solve_opts nb = o;
@@ -1289,17 +1478,21 @@ int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, f
     if (dirty) t_before = ctx->t_setup_last;
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = ctx->stream;
-    const int64_t n = ctx->nt;
-    const int nleaf = (int)ctx->tree.leaf_start.size() - 1;
+    const bool ind = indirect(ctx);
+    if (ind && (o.precision != FMMBEM_FP64 || (o.inner_iters > 0 && o.inner_precision != FMMBEM_FP64)))
+        return fail(ctx, FMMBEM_EINVAL, "indirect products are FP64");
+    const int64_t n = fmmbem_num_unknowns(ctx);
     auto pc = make_precond(ctx, o);
     double2 *b = dget<double2>(ctx->scratch, "sv_b", n);
     double2 *dx = dget<double2>(ctx->scratch, "sv_x", n);
-    rhs_dev(ctx, isrc, b);
+    if (ind) rhs_ind(ctx, isrc, b);
+    else rhs_dev(ctx, isrc, b);
     if (o.use_x0) HIP_OK(hipMemcpyAsync(dx, x, sizeof(double2) * n, hipMemcpyHostToDevice, st));
     // the Krylov products run in the requested arithmetic; restart residuals always in FP64
     int64_t n64 = 0, nmx = 0;
     auto product = [&](const double2 *a, double2 *y, bool mixed) {
-        matvec_dev(ctx, 1, a, y, false, mixed);
+        if (ind) matvec_ind(ctx, a, y, false);
+        else matvec_dev(ctx, 1, a, y, false, mixed);
         ++(mixed ? nmx : n64);
     };
     const bool mixed = o.precision == FMMBEM_MIXED;
@@ -1379,6 +1572,7 @@ int fmmbem_solve_batch(fmmbem_ctx *ctx, int32_t ns, const int32_t *isrc, const f
     if (int e = check_solve_opts(ctx, o)) return e;
     if (o.inner_iters > 0) return fail(ctx, FMMBEM_EINVAL, "the batched solve has no inner-outer scheme");
     if (o.precond == FMMBEM_PC_LEARNED) return fail(ctx, FMMBEM_EINVAL, "the batched solve has no learned guard");
+    if (indirect(ctx)) return fail(ctx, FMMBEM_EINVAL, "the batched solve is for the direct formulation");
     GUARD_BEGIN
     HIP_OK(hipSetDevice(ctx->device));
     if (ctx->src.empty()) return fail(ctx, FMMBEM_ENOTREADY, "sources not set");
@@ -1539,6 +1733,7 @@ int fmmbem_learned_train(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_train_opts 
     HIP_OK(hipSetDevice(ctx->device));
     if (ctx->src.empty()) return fail(ctx, FMMBEM_ENOTREADY, "sources not set");
     if (isrc < 0 || isrc >= (int)(ctx->src.size() / 3)) return fail(ctx, FMMBEM_EINVAL, "bad source index");
+    if (indirect(ctx)) return fail(ctx, FMMBEM_EINVAL, "the learned preconditioner is for the direct formulation");
     ensure_setup(ctx);
     ensure_chunks(ctx);
     hipStream_t st = ctx->stream;
@@ -1679,8 +1874,33 @@ int fmmbem_eval_field(fmmbem_ctx *ctx, int32_t isrc, int64_t nr, const double *r
     if (nr == 0) return FMMBEM_OK;
     hipStream_t st = ctx->stream;
     const int64_t n = ctx->nt;
-    double2 *gam = dget<double2>(ctx->scratch, "fe_gam", n), *zero = dget<double2>(ctx->scratch, "fe_zero", n);
     const double *rs = &ctx->src[3 * isrc];
+    if (indirect(ctx)) {
+        // sigma = g- + g+ + i k (beta- psi- + beta+ psi+), mu = psi+ - psi-  (Eq. ibem1, ibem4)
+        double2 *gm = dget<double2>(ctx->scratch, "ind_gm", n), *gp = dget<double2>(ctx->scratch, "ind_gp", n);
+        double2 *dxv = dget<double2>(ctx->scratch, "fe_x", 2 * n);
+        double2 *dsg = dget<double2>(ctx->scratch, "fe_sg", n), *dmu = dget<double2>(ctx->scratch, "fe_mu", n);
+        HIP_OK(hipMemcpyAsync(dxv, x, sizeof(double2) * 2 * n, hipMemcpyHostToDevice, st));
+        k_gamma_pm<<<ceil_div(n, 256), 256, 0, st>>>(n, (double4 *)ctx->buf.find("ec"), (double4 *)ctx->buf.find("en"),
+                                                     (double2 *)ctx->buf.find("beta"), (double2 *)ctx->buf.find("betap"),
+                                                     ctx->k, rs[0], rs[1], rs[2], ctx->src_amp[isrc], gm, gp);
+        LAUNCH_OK();
+        k_field_dens_ind<<<ceil_div(n, 256), 256, 0, st>>>(n, (int32_t *)ctx->buf.find("perm"), dxv, gm, gp,
+                                                           (double2 *)ctx->buf.find("beta"),
+                                                           (double2 *)ctx->buf.find("betap"), ctx->k, dsg, dmu);
+        LAUNCH_OK();
+        std::vector<double> pts(r, r + 3 * nr);
+        double *dp = upload(ctx->scratch, "fe_pts", pts, st);
+        double2 *dout = dget<double2>(ctx->scratch, "fe_out", nr);
+        k_field<<<(unsigned)nr, 256, 0, st>>>(n, dp, (double4 *)ctx->buf.find("ec"), (double4 *)ctx->buf.find("en"),
+                                              (double *)ctx->buf.find("ev"), dsg, dmu, ctx->k, ctx->rc * ctx->rc, rs[0],
+                                              rs[1], rs[2], ctx->src_amp[isrc], dout);
+        LAUNCH_OK();
+        HIP_OK(hipMemcpyAsync(psi, dout, sizeof(double2) * nr, hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+        return FMMBEM_OK;
+    }
+    double2 *gam = dget<double2>(ctx->scratch, "fe_gam", n), *zero = dget<double2>(ctx->scratch, "fe_zero", n);
     k_gamma<<<ceil_div(n, 256), 256, 0, st>>>(n, (double4 *)ctx->buf.find("ec"), (double4 *)ctx->buf.find("en"),
                                               (double2 *)ctx->buf.find("beta"), ctx->k, rs[0], rs[1], rs[2],
                                               ctx->src_amp[isrc], gam, zero);
@@ -1754,6 +1974,28 @@ int fmmbem_get_info(fmmbem_ctx *ctx, fmmbem_info *info) {
     info->flops_p2m_l2p = (double)ctx->nt * (double)pl * pl * 2 * 8.0;
     info->bytes_p2p = (double)ctx->nt * (2 * 32 + 16 + 16 + 16) + (double)ctx->near_nnz * (4 + 32);
     info->lds_max = (int64_t)ctx->lds_max;
+    return FMMBEM_OK;
+    GUARD_END
+}
+
+int fmmbem_near_entries_n(fmmbem_ctx *ctx, int64_t *nnz, fmmbem_c64 *Lp, fmmbem_c64 *Mp) {
+    if (!ctx || !nnz) return FMMBEM_EINVAL;
+    GUARD_BEGIN
+    HIP_OK(hipSetDevice(ctx->device));
+    ensure_setup(ctx);
+    *nnz = ctx->near_nnz;
+    if (!Lp && !Mp) return FMMBEM_OK;
+    ensure_indirect(ctx);
+    const int64_t z = ctx->near_nnz;
+    std::vector<double2> l(z), m(z);
+    hipStream_t st = ctx->stream;
+    HIP_OK(hipMemcpyAsync(l.data(), ctx->buf.find("near_Lp"), 16 * z, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(m.data(), ctx->buf.find("near_Mp"), 16 * z, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    for (int64_t e = 0; e < z; ++e) {
+        if (Lp) Lp[e] = {l[e].x, l[e].y};
+        if (Mp) Mp[e] = {m[e].x, m[e].y};
+    }
     return FMMBEM_OK;
     GUARD_END
 }

@@ -113,6 +113,89 @@ __device__ void tri_integrals(const double *x, const double *v, double k, int se
     }
 }
 
+// L' = int_T dG/dn_x dS and M' = d/dn_x int_T dG/dn_y dS for the indirect formulation
+// (Eq. ibem3), from the surface divergence theorem on the flat triangle (normal n, edges with
+// unit tangent tau running counter-clockwise about n, outward in-plane normal nu = tau x n):
+//   grad_x L = -n M - sum_e nu_e int_e G dl,                so L' = -(n_x.n) M - sum_e (n_x.nu_e) I0_e
+//   n_x.grad_x M = k^2 (n_x.n) L + sum_e c_e int_e G (ikr - 1)/r^2 dl,  c_e = (f_e - x).(tau_e x n_x)
+// with f_e the foot of the perpendicular from x on the edge line; (y - x).(tau x n_x) is constant
+// along the edge, which makes the second line integral scalar.  On the element itself
+// (n_x = n) this is the Hadamard finite part; L' = 0 there.  The edge integrals use
+// s = d sinh(w) (d = distance from x to the edge line, ds = r dw), 8 panels x 8 points.
+__device__ void tri_integrals_n(const double *x, const double *nx, const double *v, double k, int self, double2 &L,
+                                double2 &M, double2 &Lp, double2 &Mp) {
+    tri_integrals(x, v, k, self, L, M);
+    double e1[3] = {v[3] - v[0], v[4] - v[1], v[5] - v[2]};
+    double e2[3] = {v[6] - v[0], v[7] - v[1], v[8] - v[2]};
+    double nn[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+    double nl = sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
+    for (int q = 0; q < 3; ++q) nn[q] /= nl;
+    const double nxn = nx[0] * nn[0] + nx[1] * nn[1] + nx[2] * nn[2];
+    double2 lp = cscale(M, -nxn), mp = cscale(L, k * k * nxn);
+    for (int e = 0; e < 3; ++e) {
+        const int eb = (e + 1) % 3;
+        const double a[3] = {v[3 * e], v[3 * e + 1], v[3 * e + 2]}, b[3] = {v[3 * eb], v[3 * eb + 1], v[3 * eb + 2]};
+        double tau[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+        const double le = sqrt(tau[0] * tau[0] + tau[1] * tau[1] + tau[2] * tau[2]);
+        for (int q = 0; q < 3; ++q) tau[q] /= le;
+        const double nu[3] = {tau[1] * nn[2] - tau[2] * nn[1], tau[2] * nn[0] - tau[0] * nn[2], tau[0] * nn[1] - tau[1] * nn[0]};
+        const double tn[3] = {tau[1] * nx[2] - tau[2] * nx[1], tau[2] * nx[0] - tau[0] * nx[2], tau[0] * nx[1] - tau[1] * nx[0]};
+        const double ax[3] = {a[0] - x[0], a[1] - x[1], a[2] - x[2]};
+        const double s0 = ax[0] * tau[0] + ax[1] * tau[1] + ax[2] * tau[2], s1 = s0 + le;
+        const double fx[3] = {ax[0] - s0 * tau[0], ax[1] - s0 * tau[1], ax[2] - s0 * tau[2]};  // f - x
+        const double d = sqrt(fx[0] * fx[0] + fx[1] * fx[1] + fx[2] * fx[2]);
+        const double ce = fx[0] * tn[0] + fx[1] * tn[1] + fx[2] * tn[2];
+        const double cnu = nx[0] * nu[0] + nx[1] * nu[1] + nx[2] * nu[2];
+        double2 I0 = cmk(0, 0), I2 = cmk(0, 0);
+        const int NPAN = 8;
+        if (d > 1e-9 * le) {
+            const double w0 = asinh(s0 / d), w1 = asinh(s1 / d), hw = 0.5 * (w1 - w0) / NPAN;
+            for (int pan = 0; pan < NPAN; ++pan) {
+                const double mid = w0 + (2 * pan + 1) * hw;
+                for (int q = 0; q < 8; ++q) {
+                    const double r = d * cosh(mid + hw * GL8X[q]);
+                    const double wt = hw * GL8W[q] * r;  // ds = r dw
+                    double sn, cs;
+                    sincos(k * r, &sn, &cs);
+                    const double2 G = cmk(cs / (4.0 * FMM_PI * r), sn / (4.0 * FMM_PI * r));
+                    I0 = cadd(I0, cscale(G, wt));
+                    I2 = cadd(I2, cscale(cmul(G, cmk(-1.0, k * r)), wt / (r * r)));
+                }
+            }
+        } else {
+            // x on the edge's line (outside the segment): c_e = 0; plain panels in s for I0
+            const double hs = 0.5 * (s1 - s0) / NPAN;
+            for (int pan = 0; pan < NPAN; ++pan) {
+                const double mid = s0 + (2 * pan + 1) * hs;
+                for (int q = 0; q < 8; ++q) {
+                    const double r = fabs(mid + hs * GL8X[q]);
+                    double sn, cs;
+                    sincos(k * r, &sn, &cs);
+                    I0 = cadd(I0, cscale(cmk(cs, sn), hs * GL8W[q] / (4.0 * FMM_PI * r)));
+                }
+            }
+        }
+        lp = csub(lp, cscale(I0, cnu));
+        mp = cadd(mp, cscale(I2, ce));
+    }
+    Lp = self ? cmk(0, 0) : lp;
+    Mp = mp;
+}
+
+__global__ void k_near_quad_n(int64_t nnz, const int32_t *rowv, const int32_t *col, const double4 *ec,
+                              const double4 *en, const double *ev, double k, double2 *Lpv, double2 *Mpv) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nnz) return;
+    int i = rowv[e], j = col[e];
+    double4 ci = ec[i], ni = en[i];
+    double x[3] = {ci.x, ci.y, ci.z}, nx[3] = {ni.x, ni.y, ni.z}, v[9];
+    for (int q = 0; q < 9; ++q) v[q] = ev[9 * (int64_t)j + q];
+    double2 L, M, Lp, Mp;
+    tri_integrals_n(x, nx, v, k, i == j, L, M, Lp, Mp);
+    Lpv[e] = Lp;
+    Mpv[e] = Mp;
+}
+
 // ------------------------------------------------------------------ near-field table
 __global__ void k_near_count(int64_t n, const int32_t *leaf_of, const int32_t *leaf_start, const int32_t *nbr_start,
                              const int32_t *nbr_list, const double4 *ec, double rc2, int32_t *cnt) {
@@ -641,6 +724,295 @@ __global__ void __launch_bounds__(256) k_field(int64_t nt, const double *pts, co
         sincos(k * r, &s, &co);
         out[q] = cadd(red[0], cmul(amp, cmk(co / r * inv4pi, s / r * inv4pi)));
     }
+}
+
+// ------------------------------------------------------------------ indirect formulation (Eq. ibem5)
+// Unknowns x = (psi-, psi+), N each in caller order.  Both block rows need the same layer
+// densities s = -i k (beta- psi- + beta+ psi+) (single layer) and m = psi- - psi+ (double layer):
+//   row 1 = (psi- + psi+)/2 + L[s] + M[m],   row 2 = i k (beta- psi- - beta+ psi+)/2 + L'[s] + M'[m],
+// so one FMM pass evaluates the potential and its normal derivative at every collocation point.
+
+// g- = -dpsi_in/dn + i k beta- psi_in, g+ = dpsi_in/dn + i k beta+ psi_in (tree order)
+__global__ void k_gamma_pm(int64_t n, const double4 *ec, const double4 *en, const double2 *bm, const double2 *bp,
+                           double k, double sx, double sy, double sz, double2 amp, double2 *gm, double2 *gp) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double4 c = ec[i], nv = en[i];
+    double dx = c.x - sx, dy = c.y - sy, dz = c.z - sz;
+    double r = sqrt(dx * dx + dy * dy + dz * dz);
+    double s, co;
+    sincos(k * r, &s, &co);
+    double2 G = cmul(amp, cmk(co / (4 * FMM_PI * r), s / (4 * FMM_PI * r)));
+    double proj = (dx * nv.x + dy * nv.y + dz * nv.z) / (r * r);
+    double2 dG = cscale(cmul(G, cmk(-1.0, k * r)), proj);  // dpsi_in/dn
+    gm[i] = csub(cmul(cmk(-k * bm[i].y, k * bm[i].x), G), dG);
+    gp[i] = cadd(cmul(cmk(-k * bp[i].y, k * bp[i].x), G), dG);
+}
+
+__global__ void k_densities_ind(int64_t n, const int32_t *perm, const double2 *x, const double2 *bm,
+                                const double2 *bp, double k, double2 *sigma, double2 *mu) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t u = perm[i];
+    const double2 pm = x[u], pp = x[n + u];
+    const double2 t = cadd(cmul(bm[i], pm), cmul(bp[i], pp));
+    sigma[i] = cmk(k * t.y, -k * t.x);  // -i k (beta- psi- + beta+ psi+)
+    mu[i] = csub(pm, pp);
+}
+
+// densities of the receiver formula (Eq. ibem1, ibem4): sigma = g- + g+ + i k (beta- psi- +
+// beta+ psi+), mu = psi+ - psi-
+__global__ void k_field_dens_ind(int64_t n, const int32_t *perm, const double2 *x, const double2 *gm,
+                                 const double2 *gp, const double2 *bm, const double2 *bp, double k, double2 *sigma,
+                                 double2 *mu) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t u = perm[i];
+    const double2 pm = x[u], pp = x[n + u];
+    const double2 t = cadd(cmul(bm[i], pm), cmul(bp[i], pp));
+    sigma[i] = cadd(cadd(gm[i], gp[i]), cmk(-k * t.y, k * t.x));
+    mu[i] = csub(pp, pm);
+}
+
+// row 2 of the right-hand side gets (g+ - g-)/2
+__global__ void k_rhs_ind_local(int64_t n, const int32_t *perm, const double2 *gm, const double2 *gp, double2 *b) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t u = perm[i];
+    b[n + u] = cadd(b[n + u], cscale(csub(gp[i], gm[i]), 0.5));
+}
+
+// potential and normal derivative at the targets from one-point pairs and the near table
+__global__ void __launch_bounds__(64) k_p2p_n(int nleaf, const int32_t *leaf_start, const int32_t *nbr_start,
+                                              const int32_t *nbr_list, int all_leaves, const double4 *ec,
+                                              const double4 *en, const double2 *sigma, const double2 *mu, double k,
+                                              double rc2, const int32_t *near_start, const int32_t *near_col,
+                                              const double2 *nL, const double2 *nM, const double2 *nLp,
+                                              const double2 *nMp, double2 *y, double2 *yn) {
+    const int b = blockIdx.x, tid = threadIdx.x;
+    __shared__ double sx[64], sy[64], sz[64], snx[64], sny[64], snz[64];
+    __shared__ double2 sq[64], sw[64];
+    const int ts = leaf_start[b], te = leaf_start[b + 1];
+    const int nb0 = all_leaves ? 0 : nbr_start[b], nb1 = all_leaves ? nleaf : nbr_start[b + 1];
+    const double inv4pi = 1.0 / (4.0 * FMM_PI);
+    for (int t0 = ts; t0 < te; t0 += 64) {
+        const int t = t0 + tid;
+        const bool act = t < te;
+        const double4 ct = act ? ec[t] : make_double4(0, 0, 0, 0);
+        const double4 nt = act ? en[t] : make_double4(0, 0, 1, 0);
+        double2 acc = cmk(0, 0), accn = cmk(0, 0);
+        for (int q = nb0; q < nb1; ++q) {
+            const int sb = all_leaves ? q : nbr_list[q];
+            const int ss = leaf_start[sb], se = leaf_start[sb + 1];
+            for (int j0 = ss; j0 < se; j0 += 64) {
+                __syncthreads();
+                int j = j0 + tid;
+                if (j < se) {
+                    double4 c = ec[j], nv = en[j];
+                    sx[tid] = c.x;
+                    sy[tid] = c.y;
+                    sz[tid] = c.z;
+                    snx[tid] = nv.x;
+                    sny[tid] = nv.y;
+                    snz[tid] = nv.z;
+                    sq[tid] = cscale(sigma[j], c.w);
+                    sw[tid] = cscale(mu[j], c.w);
+                }
+                __syncthreads();
+                const int cnt = min(64, se - j0);
+                if (act) {
+                    for (int jj = 0; jj < cnt; ++jj) {
+                        double d2 = dist2_exact(ct.x, ct.y, ct.z, sx[jj], sy[jj], sz[jj]);
+                        if (d2 < rc2) continue;
+                        const double dx = sx[jj] - ct.x, dy = sy[jj] - ct.y, dz = sz[jj] - ct.z;
+                        const double r = sqrt(d2), ir = 1.0 / r, ir2 = ir * ir;
+                        double s, c;
+                        sincos(k * r, &s, &c);
+                        const double2 E = cmk(c * inv4pi, s * inv4pi);  // e^{ikr} / 4 pi
+                        const double2 G = cscale(E, ir);
+                        const double dny = dx * snx[jj] + dy * sny[jj] + dz * snz[jj];
+                        const double dnx = dx * nt.x + dy * nt.y + dz * nt.z;
+                        const double nn = nt.x * snx[jj] + nt.y * sny[jj] + nt.z * snz[jj];
+                        const double2 g1 = cmul(G, cmk(-1.0, k * r));  // G (ikr - 1)
+                        // potential: G q + G (ikr - 1) (d.n_y)/r^2 w
+                        acc = cfma(G, sq[jj], acc);
+                        acc = cfma(cscale(g1, dny * ir2), sw[jj], acc);
+                        // normal derivative: -G (ikr - 1)(d.n_x)/r^2 q + K w
+                        accn = cfma(cscale(g1, -dnx * ir2), sq[jj], accn);
+                        const double2 k3 = cmul(E, cmk(3.0 - k * k * d2, -3.0 * k * r));  // e(3 - 3ikr - k^2 r^2)
+                        const double2 K = csub(cscale(k3, -dnx * dny * ir2 * ir2 * ir), cscale(cmul(E, cmk(-1.0, k * r)), nn * ir2 * ir));
+                        accn = cfma(K, sw[jj], accn);
+                    }
+                }
+            }
+        }
+        if (act) {
+            for (int e = near_start[t]; e < near_start[t + 1]; ++e) {
+                const int j = near_col[e];
+                acc = cfma(nL[e], sigma[j], acc);
+                acc = cfma(nM[e], mu[j], acc);
+                accn = cfma(nLp[e], sigma[j], accn);
+                accn = cfma(nMp[e], mu[j], accn);
+            }
+            y[t] = acc;
+            yn[t] = accn;
+        }
+    }
+}
+
+// derivative local expansions of a leaf (degree p + 1) from its local expansion D (degree p):
+//   d_z R_n^m = k (a_{n-1}^m R_{n-1}^m - a_n^m R_{n+1}^m), etc. (the P2M recurrences), collected
+//   per output coefficient (n, m)
+__device__ inline double2 dget_nm(const double2 *D, int p, int n, int m) {
+    if (n < 0 || n >= p || (m < 0 ? -m : m) > n) return cmk(0, 0);
+    return D[cidx(n, m)];
+}
+__global__ void k_local_derivs(int64_t nleaf, int p, const double2 *D, double k, double2 *Dz, double2 *Dp,
+                               double2 *Dm) {
+    const int64_t b = blockIdx.x;
+    const int q1 = (p + 1) * (p + 1);
+    const double2 *Db = D + b * p * p;
+    for (int c = threadIdx.x; c < q1; c += blockDim.x) {
+        int n = (int)sqrt((double)c);
+        while (n * n > c) --n;
+        while ((n + 1) * (n + 1) <= c) ++n;
+        const int m = c - n * n - n;
+        const double2 z = csub(cscale(dget_nm(Db, p, n + 1, m), coef_a(n, m)), cscale(dget_nm(Db, p, n - 1, m), coef_a(n - 1, m)));
+        const double2 pl = csub(cscale(dget_nm(Db, p, n - 1, m - 1), coef_b(n, -m)),
+                                cscale(dget_nm(Db, p, n + 1, m - 1), coef_b(n + 1, m - 1)));
+        const double2 mi = csub(cscale(dget_nm(Db, p, n - 1, m + 1), coef_b(n, m)),
+                                cscale(dget_nm(Db, p, n + 1, m + 1), coef_b(n + 1, -m - 1)));
+        Dz[b * q1 + c] = cscale(z, k);
+        Dp[b * q1 + c] = cscale(pl, k);
+        Dm[b * q1 + c] = cscale(mi, k);
+    }
+}
+
+// potential (local expansion D, degree p) and normal derivative (derivative expansions, degree
+// p + 1) at the targets, plus the near part and the local terms of both block rows
+__global__ void __launch_bounds__(64) k_l2p_n(int nleaf, int p, const int32_t *leaf_start, const double4 *center,
+                                              const double4 *ec, const double4 *en, const double2 *Lc,
+                                              const double2 *Dz, const double2 *Dp, const double2 *Dm, double k,
+                                              const double2 *ynear, const double2 *ynearn, const int32_t *perm,
+                                              int64_t n, const double2 *x, const double2 *bm, const double2 *bp,
+                                              double2 *y, int has_far) {
+    extern __shared__ double jbuf[];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const double4 C = center[b];
+    const int ts = leaf_start[b], te = leaf_start[b + 1];
+    const int q1 = (p + 1) * (p + 1);
+    const double2 *D = Lc + (int64_t)b * p * p, *Ez = Dz + (int64_t)b * q1, *Ep = Dp + (int64_t)b * q1,
+                  *Em = Dm + (int64_t)b * q1;
+    double *jb = jbuf + tid * (p + 3);
+    for (int t = ts + tid; t < te; t += 64) {
+        double2 far = cmk(0, 0), fz = cmk(0, 0), fp = cmk(0, 0), fm = cmk(0, 0);
+        if (has_far) {
+            double4 c = ec[t];
+            double r, ct, st, phi;
+            sph_coords(c.x - C.x, c.y - C.y, c.z - C.z, r, ct, st, phi);
+            sph_jn_seq(k * r, p, jb);
+            double pmm = 1.0 / sqrt(4.0 * FMM_PI);
+            for (int mp = 0; mp <= p; ++mp) {
+                if (mp > 0) pmm *= sqrt((2.0 * mp + 1.0) / (2.0 * mp)) * st;
+                double s, co;
+                sincos(mp * phi, &s, &co);
+                double pm2 = 0.0, pm1 = pmm;
+                double2 sv[2] = {cmk(0, 0), cmk(0, 0)}, sz_[2] = {cmk(0, 0), cmk(0, 0)},
+                        sp_[2] = {cmk(0, 0), cmk(0, 0)}, sm_[2] = {cmk(0, 0), cmk(0, 0)};
+                for (int nn = mp; nn <= p; ++nn) {
+                    double P;
+                    if (nn == mp) P = pmm;
+                    else if (nn == mp + 1) P = sqrt(2.0 * mp + 3.0) * ct * pmm;
+                    else {
+                        double a = sqrt((4.0 * nn * nn - 1.0) / ((double)nn * nn - (double)mp * mp));
+                        double bq = sqrt((((double)nn - 1) * (nn - 1) - (double)mp * mp) * (2.0 * nn + 1.0) /
+                                         ((2.0 * nn - 3.0) * ((double)nn * nn - (double)mp * mp)));
+                        P = a * ct * pm1 - bq * pm2;
+                    }
+                    if (nn >= mp + 1) {
+                        pm2 = pm1;
+                        pm1 = P;
+                    }
+                    const double R = jb[nn] * P;
+                    if (nn < p) {
+                        sv[0] = cadd(sv[0], cscale(D[cidx(nn, mp)], R));
+                        if (mp > 0) sv[1] = cadd(sv[1], cscale(D[cidx(nn, -mp)], R));
+                    }
+                    sz_[0] = cadd(sz_[0], cscale(Ez[cidx(nn, mp)], R));
+                    sp_[0] = cadd(sp_[0], cscale(Ep[cidx(nn, mp)], R));
+                    sm_[0] = cadd(sm_[0], cscale(Em[cidx(nn, mp)], R));
+                    if (mp > 0) {
+                        sz_[1] = cadd(sz_[1], cscale(Ez[cidx(nn, -mp)], R));
+                        sp_[1] = cadd(sp_[1], cscale(Ep[cidx(nn, -mp)], R));
+                        sm_[1] = cadd(sm_[1], cscale(Em[cidx(nn, -mp)], R));
+                    }
+                }
+                const double2 ep = cmk(co, s), em = cmk(co, -s);
+                far = cadd(far, cmul(sv[0], ep));
+                fz = cadd(fz, cmul(sz_[0], ep));
+                fp = cadd(fp, cmul(sp_[0], ep));
+                fm = cadd(fm, cmul(sm_[0], ep));
+                if (mp > 0) {
+                    far = cadd(far, cmul(sv[1], em));
+                    fz = cadd(fz, cmul(sz_[1], em));
+                    fp = cadd(fp, cmul(sp_[1], em));
+                    fm = cadd(fm, cmul(sm_[1], em));
+                }
+            }
+        }
+        const double4 nt = en[t];
+        // n.grad = n_z d_z + (n_x - i n_y)/2 (d_x + i d_y) + (n_x + i n_y)/2 (d_x - i d_y)
+        double2 farn = cscale(fz, nt.z);
+        farn = cadd(farn, cmul(cmk(0.5 * nt.x, -0.5 * nt.y), fp));
+        farn = cadd(farn, cmul(cmk(0.5 * nt.x, 0.5 * nt.y), fm));
+        const int64_t u = perm[t];
+        double2 v1 = cadd(ynear[t], far), v2 = cadd(ynearn[t], farn);
+        if (x) {
+            const double2 pm = x[u], pp = x[n + u];
+            v1 = cadd(v1, cscale(cadd(pm, pp), 0.5));
+            // i k (beta- psi- - beta+ psi+) / 2
+            const double2 t2 = csub(cmul(bm[t], pm), cmul(bp[t], pp));
+            v2 = cadd(v2, cmk(-0.5 * k * t2.y, 0.5 * k * t2.x));
+        }
+        y[u] = v1;
+        y[n + u] = v2;
+    }
+}
+
+// 2x2 diagonal blocks of the indirect operator (local terms and self entries) and their inverses:
+//   [ 1/2 - i k beta- L_ii          1/2 - i k beta+ L_ii  ]
+//   [ i k beta-/2 + M'_ii          -i k beta+/2 - M'_ii   ]      (M_ii = L'_ii = 0)
+__global__ void k_diag2_inv(int64_t n, const int32_t *near_start, const int32_t *near_col, const double2 *nL,
+                            const double2 *nMp, const double2 *bm, const double2 *bp, double k, double shift,
+                            double2 *inv) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double2 L = cmk(0, 0), Mp = cmk(0, 0);
+    for (int e = near_start[i]; e < near_start[i + 1]; ++e)
+        if (near_col[e] == i) {
+            L = nL[e];
+            Mp = nMp[e];
+        }
+    const double2 ik = cmk(0, k);
+    const double2 a = cadd(cmk(0.5 + shift, 0), cscale(cmul(cmul(ik, bm[i]), L), -1.0));
+    const double2 b = csub(cmk(0.5, 0), cmul(cmul(ik, bp[i]), L));
+    const double2 c = cadd(cscale(cmul(ik, bm[i]), 0.5), Mp);
+    const double2 d = csub(cadd(cscale(cmul(ik, bp[i]), -0.5), cmk(shift, 0)), Mp);
+    const double2 det = csub(cmul(a, d), cmul(b, c));
+    inv[4 * i] = cdiv(d, det);
+    inv[4 * i + 1] = cdiv(cscale(b, -1.0), det);
+    inv[4 * i + 2] = cdiv(cscale(c, -1.0), det);
+    inv[4 * i + 3] = cdiv(a, det);
+}
+
+// z = blockdiag(inv) v on (psi-, psi+) pairs (caller order; inv in tree order)
+__global__ void k_mul_diag2(int64_t n, const int32_t *perm, const double2 *inv, const double2 *v, double2 *z) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t u = perm[i];
+    const double2 a = v[u], b = v[n + u];
+    z[u] = cadd(cmul(inv[4 * i], a), cmul(inv[4 * i + 1], b));
+    z[n + u] = cadd(cmul(inv[4 * i + 2], a), cmul(inv[4 * i + 3], b));
 }
 
 // ------------------------------------------------------------------ launchers (RHS count 1, 2, 4)

@@ -189,6 +189,7 @@ void mlp_target(int64_t nchunk, const int32_t *cs, const int32_t *cn, const int3
 
 void gather_rows(int64_t B, int width, const int64_t *idx, const float *src, float *dst, hipStream_t st);
 void vec_sub(int64_t n, const double2 *a, const double2 *b, double2 *out, hipStream_t st);
+void vec_add(int64_t n, const double2 *a, const double2 *b, double2 *out, hipStream_t st);
 
 // optional observers of a flexible GMRES run
 struct FgmresHooks {
@@ -240,6 +241,8 @@ struct fmmbem_ctx {
     bool precond_ready_nb = false, precond_ready_diag = false;
     std::vector<double> history;  // Arnoldi residual estimate per outer iteration of the last solve
     bool mixed_ready = false;
+    std::vector<double2> beta_plus;  // admittance of the + faces (indirect formulation); empty: = beta
+    bool indirect_ready = false;     // L' and M' near entries exist for the current (mesh, k)
     int nr_cap = 1, nr_cap32 = 0;  // vectors per box the FP64 / FP32 expansion arrays hold
     bool capturing = false;        // a graph capture is in progress: no allocation, no timing events
     struct GraphEntry {

@@ -369,6 +369,16 @@ void gather_rows(int64_t B, int width, const int64_t *idx, const float *src, flo
     LAUNCH_OK();
 }
 
+__global__ void k_vadd(int64_t n, const double2 *a, const double2 *b, double2 *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = cadd(a[i], b[i]);
+}
+
+void vec_add(int64_t n, const double2 *a, const double2 *b, double2 *out, hipStream_t st) {
+    k_vadd<<<ceil_div(n, 256), 256, 0, st>>>(n, a, b, out);
+    LAUNCH_OK();
+}
+
 void vec_sub(int64_t n, const double2 *a, const double2 *b, double2 *out, hipStream_t st) {
     k_vsub<<<ceil_div(n, 256), 256, 0, st>>>(n, a, b, out);
     LAUNCH_OK();

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libfmmbem.so")
 
 FMMBEM_OK, FMMBEM_ENOCONV = 0, 1
 FMMBEM_EINVAL, FMMBEM_ENOMEM, FMMBEM_EDEVICE, FMMBEM_ENOTREADY, FMMBEM_EBREAKDOWN, FMMBEM_ENAN = -1, -2, -3, -4, -5, -6
-FMMBEM_DIRECT = 0
+FMMBEM_DIRECT, FMMBEM_INDIRECT = 0, 3
 FMMBEM_FP64, FMMBEM_MIXED = 0, 1
 FMMBEM_PC_NONE, FMMBEM_PC_DIAG, FMMBEM_PC_NEARBLOCK, FMMBEM_PC_LEARNED = 0, 1, 2, 3
 
@@ -93,6 +93,9 @@ EXPORTS = {
     "fmmbem_solve_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(SolveOpts),
                                           ctypes.c_void_p, ctypes.c_void_p]),
     "fmmbem_release_workspace": (ctypes.c_int, [ctypes.c_void_p]),
+    "fmmbem_set_admittance_plus": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "fmmbem_near_entries_n": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p,
+                                             ctypes.c_void_p]),
     "fmmbem_default_train_opts": (None, [ctypes.c_void_p]),
     "fmmbem_learned_train": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "fmmbem_mlp_param_count": (ctypes.c_int64, []),
@@ -306,6 +309,21 @@ class Context:
         g = np.empty(self.fmmbem_mlp_param_count(), np.float32)
         self._check(lib().fmmbem_mlp_loss_grad(self.h, X.shape[0], _ptr(X), _ptr(T), _ptr(loss), _ptr(g)))
         return float(loss[0]), g
+
+    def fmmbem_set_admittance_plus(self, beta_plus=None):
+        if beta_plus is None:
+            self._check(lib().fmmbem_set_admittance_plus(self.h, None))
+        else:
+            b = _c(beta_plus)
+            self._check(lib().fmmbem_set_admittance_plus(self.h, _ptr(b)))
+
+    def fmmbem_near_entries_n(self):
+        nnz = ctypes.c_int64()
+        self._check(lib().fmmbem_near_entries_n(self.h, ctypes.byref(nnz), None, None))
+        Lp = np.empty(nnz.value, np.complex128)
+        Mp = np.empty(nnz.value, np.complex128)
+        self._check(lib().fmmbem_near_entries_n(self.h, ctypes.byref(nnz), _ptr(Lp), _ptr(Mp)))
+        return Lp, Mp
 
     def fmmbem_release_workspace(self):
         self._check(lib().fmmbem_release_workspace(self.h))
