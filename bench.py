@@ -38,6 +38,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--maxit", type=int, default=1200, help="FGMRES iteration cap (= Krylov dimension)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner solve")
+    ap.add_argument("--no-autotune", action="store_true", help="fixed tile-shape rule instead of measured shapes")
     ap.add_argument("--train-maxit", type=int, default=300, help="iteration cap of the reference solve for training")
     ap.add_argument("--lds-budget", type=int, default=0, help="LDS bytes per translation tile (0 = library default)")
     args = ap.parse_args()
@@ -58,7 +59,7 @@ def main():
     rs, rec = synth.source_and_receivers(room, 64, nsrc=4)
     n = room.n
     log(f"workload {args.workload}: N={n} k={k:.3f}")
-    ctx = F.Context(0, lds_budget=args.lds_budget)
+    ctx = F.Context(0, lds_budget=args.lds_budget, autotune=0 if args.no_autotune else 1)
     ctx.fmmbem_set_mesh(room.vertices, room.triangles)
     ctx.fmmbem_set_wavenumber(k)
     ctx.fmmbem_set_admittance(room.beta)
@@ -70,6 +71,10 @@ def main():
     ps = [info.p[l] for l in range(info.depth + 1)]
     log(f"setup {t_setup:.2f}s depth {info.depth} leaves {info.nleaf} p {ps} near_nnz {info.near_nnz} "
         f"lds_max {info.lds_max}")
+    shapes = ctx.fmmbem_batch_shapes()
+    for s in shapes:
+        log(f"  tiles L{s['level']} {s['kind']}: {'lane' if s['lane'] else ('whole' if s['whole'] else 'degree')} "
+            f"JT {s['jt']} jobs {s['jobs']} {s['ms']:.3f} ms")
 
     dev = torch.device("cuda:0")
     x_h = synth.complex_normal(n, 11)
@@ -178,6 +183,7 @@ def main():
                    "near_nnz": info.near_nnz, "m2l_pairs": [info.m2l_pairs[l] for l in range(info.depth + 1)],
                    "parallelism": "single GPU"},
         "setup_s": t_setup,
+        "tile_shapes": shapes,
         "phases_ms": phases,
         "roofline": roofline,
         "mixed_precision": mixed,

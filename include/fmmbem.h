@@ -305,6 +305,17 @@ int fmmbem_get_info(fmmbem_ctx *ctx, fmmbem_info *info);
 /* Accurate near entries (sorted by row, caller order): count via *nnz when rows == NULL. */
 int fmmbem_near_entries(fmmbem_ctx *ctx, int64_t *nnz, int64_t *rows, int64_t *cols, fmmbem_c64 *L, fmmbem_c64 *M);
 
+/* Tile shape of every translation batch (from the fixed rule, or measured when the options
+ * ask for autotuning): level, kind 0 = M2L at that level, 1 = M2M into it, 2 = L2L out of it,
+ * one-job-per-lane flag, whole-vector flag, jobs per tile, and the measured FP64 time of the
+ * batch's four stages (0 when not measured). */
+typedef struct {
+    int32_t level, kind, lane, whole, jt;
+    int64_t jobs;
+    double ms;
+} fmmbem_batch_shape;
+int fmmbem_batch_shapes(fmmbem_ctx *ctx, int32_t max, fmmbem_batch_shape *out, int32_t *count);
+
 /* The L' and M' near entries (Eq. ibem3) in the order of fmmbem_near_entries (count via *nnz
  * when both arrays are NULL). */
 int fmmbem_near_entries_n(fmmbem_ctx *ctx, int64_t *nnz, fmmbem_c64 *Lp, fmmbem_c64 *Mp);

@@ -80,6 +80,8 @@ int fgmres(int64_t n, hipStream_t st, DeviceBuffers &scr, const char *tag,
            int &restarts, double &rel_res, const FgmresHooks *hooks);
 
 void drop_graphs(fmmbem_ctx *c);
+static void autotune_batches(fmmbem_ctx *c);
+static void record_shapes(fmmbem_ctx *c);
 
 // ------------------------------------------------------------------ setup pieces
 static int level_p(const fmmbem_options &o, double k, double side) {
@@ -234,12 +236,55 @@ static void direction_phases(int PH, std::vector<double2> &A) {
     }
 }
 
-struct JobH {
-    int32_t src, tgt;
-    int16_t dir;
-    int tab;   // coaxial table
-    int rot;   // polar-angle class
-};
+
+// Tile layout of a sorted job list for the batch's shape (JT, whole, lane): classes padded to
+// whole tiles, per-tile table indices, per-target CSR of the (padded) job order.
+static void layout_batch(fmmbem_ctx *c, const std::string &name, const std::vector<JobH> &jobs, TransBatch &b) {
+    hipStream_t st = c->stream;
+    const int64_t ntgt = b.ntgt;
+    std::vector<int32_t> s, t, tc, tr;
+    std::vector<int16_t> d;
+    size_t q = 0;
+    while (q < jobs.size()) {
+        size_t e = q;
+        while (e < jobs.size() && jobs[e].tab == jobs[q].tab && jobs[e].rot == jobs[q].rot) ++e;
+        for (size_t r = q; r < e; ++r) {
+            s.push_back(jobs[r].src);
+            t.push_back(jobs[r].tgt);
+            d.push_back(jobs[r].dir);
+        }
+        while (s.size() % b.JT) {  // pad the class to whole tiles
+            s.push_back(jobs[q].src);
+            t.push_back(-1);
+            d.push_back(jobs[q].dir);
+        }
+        const size_t tiles = (e - q + b.JT - 1) / b.JT;
+        for (size_t k = 0; k < tiles; ++k) {
+            tc.push_back(jobs[q].tab);
+            tr.push_back(jobs[q].rot);
+        }
+        q = e;
+    }
+    b.njob = (int64_t)s.size();
+    // jobs of every target (CSR over the padded order)
+    {
+        std::vector<int32_t> ts(ntgt + 1, 0), tj;
+        for (int32_t v : t)
+            if (v >= 0) ts[v + 1]++;
+        for (int64_t q2 = 0; q2 < ntgt; ++q2) ts[q2 + 1] += ts[q2];
+        tj.resize(ts[ntgt]);
+        std::vector<int32_t> fill(ts.begin(), ts.end() - 1);
+        for (size_t q2 = 0; q2 < t.size(); ++q2)
+            if (t[q2] >= 0) tj[fill[t[q2]]++] = (int32_t)q2;
+        b.tgt_start = upload(c->buf, name + "_tstart", ts, st);
+        b.tgt_jobs = upload(c->buf, name + "_tjobs", tj, st);
+    }
+    b.src = upload(c->buf, name + "_src", s, st);
+    b.tgt = upload(c->buf, name + "_tgt", t, st);
+    b.dir = upload(c->buf, name + "_dir", d, st);
+    b.tile_coax = upload(c->buf, name + "_tcoax", tc, st);
+    b.tile_rot = upload(c->buf, name + "_trot", tr, st);
+}
 
 // Sort jobs by (coaxial table, polar angle, target), pad every class to whole tiles, build the
 // rotation tables of the batch's distinct polar angles.
@@ -288,48 +333,8 @@ static void make_batch(fmmbem_ctx *c, const std::string &name, std::vector<JobH>
         b.whole = trans_pick_jt(b.P, budget, 1) >= 8 && (size_t)8 * 16 * b.P * b.P <= budget;
         b.JT = trans_pick_jt(b.P, budget, b.whole);
     }
-    std::vector<int32_t> s, t, tc, tr;
-    std::vector<int16_t> d;
-    size_t q = 0;
-    while (q < jobs.size()) {
-        size_t e = q;
-        while (e < jobs.size() && jobs[e].tab == jobs[q].tab && jobs[e].rot == jobs[q].rot) ++e;
-        for (size_t r = q; r < e; ++r) {
-            s.push_back(jobs[r].src);
-            t.push_back(jobs[r].tgt);
-            d.push_back(jobs[r].dir);
-        }
-        while (s.size() % b.JT) {  // pad the class to whole tiles
-            s.push_back(jobs[q].src);
-            t.push_back(-1);
-            d.push_back(jobs[q].dir);
-        }
-        const size_t tiles = (e - q + b.JT - 1) / b.JT;
-        for (size_t k = 0; k < tiles; ++k) {
-            tc.push_back(jobs[q].tab);
-            tr.push_back(jobs[q].rot);
-        }
-        q = e;
-    }
-    b.njob = (int64_t)s.size();
-    // jobs of every target (CSR over the padded order)
-    {
-        std::vector<int32_t> ts(ntgt + 1, 0), tj;
-        for (int32_t v : t)
-            if (v >= 0) ts[v + 1]++;
-        for (int64_t q2 = 0; q2 < ntgt; ++q2) ts[q2 + 1] += ts[q2];
-        tj.resize(ts[ntgt]);
-        std::vector<int32_t> fill(ts.begin(), ts.end() - 1);
-        for (size_t q2 = 0; q2 < t.size(); ++q2)
-            if (t[q2] >= 0) tj[fill[t[q2]]++] = (int32_t)q2;
-        b.tgt_start = upload(c->buf, name + "_tstart", ts, st);
-        b.tgt_jobs = upload(c->buf, name + "_tjobs", tj, st);
-    }
-    b.src = upload(c->buf, name + "_src", s, st);
-    b.tgt = upload(c->buf, name + "_tgt", t, st);
-    b.dir = upload(c->buf, name + "_dir", d, st);
-    b.tile_coax = upload(c->buf, name + "_tcoax", tc, st);
-    b.tile_rot = upload(c->buf, name + "_trot", tr, st);
+    c->batch_jobs[name] = jobs;  // kept for re-layout by the autotuner
+    layout_batch(c, name, jobs, b);
     b.nbeta = (int)classes.size();
     std::vector<double> betas;
     for (double v : classes) betas.push_back(std::acos(std::max(-1.0, std::min(1.0, v))));
@@ -469,6 +474,8 @@ static void ensure_setup(fmmbem_ctx *c) {
     if (c->k_dirty) {
         c->mixed_ready = false;
         setup_k(c);
+        if (c->opt.autotune) autotune_batches(c);
+        else record_shapes(c);
         c->k_dirty = false;
         c->precond_ready_nb = c->precond_ready_diag = false;
     }
@@ -567,6 +574,98 @@ static void run_batch(fmmbem_ctx *c, int nrv, const TransBatch &b, const typenam
 
 static TransTables<double> tables64(const TransBatch &b, const double2 *coax) { return {coax, b.H, b.HT}; }
 static TransTables<float> tables32(const TransBatch &b, const float2 *coax) { return {coax, b.H32, b.HT32}; }
+
+// every batch of the product with its source/target expansions and coaxial tables
+struct BatchRef {
+    int level, kind;
+    std::string name;
+    TransBatch *b;
+    const double2 *src, *coax;
+    double2 *dst;
+};
+static std::vector<BatchRef> all_batches(fmmbem_ctx *c) {
+    std::vector<BatchRef> v;
+    const int L = c->tree.depth;
+    for (int l = 2; l <= L; ++l) {
+        LevelDev &D = c->lev[l];
+        const std::string s = "L" + std::to_string(l) + "_";
+        v.push_back({l, 0, s + "m2l", &D.m2l, D.M, D.coax_m2l, D.L});
+        if (l < L) {
+            LevelDev &C = c->lev[l + 1];
+            v.push_back({l, 1, s + "up", &D.up, C.M, D.coax_up, D.M});
+            v.push_back({l, 2, s + "down", &D.down, D.L, D.coax_up, C.L});
+        }
+    }
+    return v;
+}
+
+static void record_shapes(fmmbem_ctx *c) {
+    c->shapes.clear();
+    for (auto &r : all_batches(c))
+        c->shapes.push_back({r.level, r.kind, r.b->lane, r.b->whole, r.b->JT, r.b->nreal, 0.0});
+}
+
+// Tile-shape autotuner: for every batch, time its four stages (FP64, one vector) under each
+// feasible shape -- one job per lane, whole-vector LDS tiles and per-degree LDS tiles with
+// several tile sizes -- on the batch's own expansion arrays, and keep the fastest layout.
+static void autotune_batches(fmmbem_ctx *c) {
+    hipStream_t st = c->stream;
+    const double2 *ph = (double2 *)c->buf.find("phA");
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    const size_t cap = c->lds_max - 1024;
+    c->shapes.clear();
+    for (auto &r : all_batches(c)) {
+        TransBatch &b = *r.b;
+        if (b.njob == 0) continue;
+        const std::vector<JobH> &jobs = c->batch_jobs[r.name];
+        struct Shape {
+            int lane, whole, jt;
+        };
+        std::vector<Shape> cand;
+        int64_t pad64 = 0;
+        for (size_t q = 0; q < jobs.size();) {
+            size_t e = q;
+            while (e < jobs.size() && jobs[e].tab == jobs[q].tab && jobs[e].rot == jobs[q].rot) ++e;
+            pad64 += (int64_t)((e - q + 63) / 64) * 64;
+            q = e;
+        }
+        if (pad64 <= 2 * (int64_t)jobs.size()) cand.push_back({1, 0, 64});
+        for (int whole = 0; whole < 2; ++whole)
+            for (int jt : {4, 8, 12, 16, 24, 32, 48, 64})
+                if (trans_lds_bytes(jt, b.P, whole) <= cap && (whole == 0 || jt >= 4)) cand.push_back({0, whole, jt});
+        double best = 1e300;
+        Shape bs = {b.lane, b.whole, b.JT};
+        for (const Shape &sh : cand) {
+            b.lane = sh.lane;
+            b.whole = sh.whole;
+            b.JT = sh.jt;
+            layout_batch(c, r.name, jobs, b);
+            const TransTables<double> tb{r.coax, b.H, b.HT};
+            run_batch<double>(c, 1, b, r.src, r.dst, tb, ph);  // warm-up (allocates the work rows)
+            HIP_OK(hipEventRecord(e0, st));
+            for (int rep = 0; rep < 2; ++rep) run_batch<double>(c, 1, b, r.src, r.dst, tb, ph);
+            HIP_OK(hipEventRecord(e1, st));
+            HIP_OK(hipEventSynchronize(e1));
+            float ms = 0;
+            HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+            if (ms / 2 < best) {
+                best = ms / 2;
+                bs = sh;
+            }
+        }
+        b.lane = bs.lane;
+        b.whole = bs.whole;
+        b.JT = bs.jt;
+        layout_batch(c, r.name, jobs, b);
+        c->shapes.push_back({r.level, r.kind, b.lane, b.whole, b.JT, b.nreal, best});
+    }
+    HIP_OK(hipStreamSynchronize(st));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    drop_graphs(c);
+}
 
 template <class S, class D>
 static void convert(fmmbem_ctx *c, int64_t n, const S *a, D *b);
@@ -1974,6 +2073,17 @@ int fmmbem_get_info(fmmbem_ctx *ctx, fmmbem_info *info) {
     info->flops_p2m_l2p = (double)ctx->nt * (double)pl * pl * 2 * 8.0;
     info->bytes_p2p = (double)ctx->nt * (2 * 32 + 16 + 16 + 16) + (double)ctx->near_nnz * (4 + 32);
     info->lds_max = (int64_t)ctx->lds_max;
+    return FMMBEM_OK;
+    GUARD_END
+}
+
+int fmmbem_batch_shapes(fmmbem_ctx *ctx, int32_t max, fmmbem_batch_shape *out, int32_t *count) {
+    if (!ctx || !count || (max > 0 && !out)) return FMMBEM_EINVAL;
+    GUARD_BEGIN
+    HIP_OK(hipSetDevice(ctx->device));
+    ensure_setup(ctx);
+    *count = (int32_t)ctx->shapes.size();
+    for (int i = 0; i < max && i < *count; ++i) out[i] = ctx->shapes[i];
     return FMMBEM_OK;
     GUARD_END
 }

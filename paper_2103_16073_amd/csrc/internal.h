@@ -126,6 +126,14 @@ struct TransBatch {
     int64_t ntgt = 0;                                   // target boxes
     int32_t *tgt_start = nullptr, *tgt_jobs = nullptr;  // jobs of each target (CSR, padded job indices)
 };
+// one translation job before tiling
+struct JobH {
+    int32_t src, tgt;
+    int16_t dir;
+    int tab;  // coaxial table
+    int rot;  // polar-angle class
+};
+
 int trans_pick_jt(int P, size_t lds_budget, int whole);
 size_t trans_lds_bytes(int JT, int P, int whole);
 void trans_configure_lds(size_t lds_max);
@@ -241,6 +249,8 @@ struct fmmbem_ctx {
     bool precond_ready_nb = false, precond_ready_diag = false;
     std::vector<double> history;  // Arnoldi residual estimate per outer iteration of the last solve
     bool mixed_ready = false;
+    std::map<std::string, std::vector<fmm::JobH>> batch_jobs;  // sorted jobs per batch (re-layout)
+    std::vector<fmmbem_batch_shape> shapes;                      // tile shape chosen per batch
     std::vector<double2> beta_plus;  // admittance of the + faces (indirect formulation); empty: = beta
     bool indirect_ready = false;     // L' and M' near entries exist for the current (mesh, k)
     int nr_cap = 1, nr_cap32 = 0;  // vectors per box the FP64 / FP32 expansion arrays hold

@@ -51,6 +51,11 @@ class SolveReport(ctypes.Structure):
                 ("pc_fallback_at", ctypes.c_int32)]
 
 
+class BatchShape(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int32), ("kind", ctypes.c_int32), ("lane", ctypes.c_int32),
+                ("whole", ctypes.c_int32), ("jt", ctypes.c_int32), ("jobs", ctypes.c_int64), ("ms", ctypes.c_double)]
+
+
 class TrainOpts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int), ("max_pairs", ctypes.c_int), ("tol", ctypes.c_double),
                 ("maxit", ctypes.c_int), ("epochs", ctypes.c_int), ("batch", ctypes.c_int), ("lr", ctypes.c_double),
@@ -93,6 +98,8 @@ EXPORTS = {
     "fmmbem_solve_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(SolveOpts),
                                           ctypes.c_void_p, ctypes.c_void_p]),
     "fmmbem_release_workspace": (ctypes.c_int, [ctypes.c_void_p]),
+    "fmmbem_batch_shapes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                           ctypes.POINTER(ctypes.c_int32)]),
     "fmmbem_set_admittance_plus": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "fmmbem_near_entries_n": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p,
                                              ctypes.c_void_p]),
@@ -324,6 +331,14 @@ class Context:
         Mp = np.empty(nnz.value, np.complex128)
         self._check(lib().fmmbem_near_entries_n(self.h, ctypes.byref(nnz), _ptr(Lp), _ptr(Mp)))
         return Lp, Mp
+
+    def fmmbem_batch_shapes(self):
+        cnt = ctypes.c_int32()
+        self._check(lib().fmmbem_batch_shapes(self.h, 0, None, ctypes.byref(cnt)))
+        arr = (BatchShape * max(1, cnt.value))()
+        self._check(lib().fmmbem_batch_shapes(self.h, cnt.value, arr, ctypes.byref(cnt)))
+        return [{"level": s.level, "kind": ("m2l", "m2m", "l2l")[s.kind], "lane": s.lane, "whole": s.whole,
+                 "jt": s.jt, "jobs": s.jobs, "ms": s.ms} for s in arr[:cnt.value]]
 
     def fmmbem_release_workspace(self):
         self._check(lib().fmmbem_release_workspace(self.h))

@@ -281,6 +281,25 @@ def test_matvec_graph_replays_match_eager(F, cfg1_dense, nr, prec):
     ctx.close()
 
 
+def test_autotuned_tiles_vs_dense(F, cfg1_dense):
+    """With autotuning, every batch gets the measured-fastest tile shape; the product (FP64,
+    mixed, several vectors) still matches the oracle's dense operator."""
+    room, k = cfg1_dense
+    ctx = make_ctx(F, room, k, leaf_max=12, autotune=1)
+    shapes = ctx.fmmbem_batch_shapes()
+    print("tile shapes:", [(s["level"], s["kind"], s["lane"], s["whole"], s["jt"], round(s["ms"], 3)) for s in shapes])
+    assert len(shapes) > 0 and all(s["ms"] > 0 for s in shapes)
+    info = ctx.fmmbem_get_info()
+    L, M = bem.dense_LM(room.vertices, room.triangles, k, info.rc)
+    X = np.stack([synth.complex_normal(room.n, 60 + s) for s in range(3)])
+    ref = np.stack([0.5 * x + M @ x - 1j * k * L @ (room.beta * x) for x in X])
+    for prec, tol in ((F.FMMBEM_FP64, 1e-6), (F.FMMBEM_MIXED, 1e-4)):
+        Y = ctx.fmmbem_matvec(X, precision=prec)
+        for s in range(3):
+            assert np.linalg.norm(Y[s] - ref[s]) / np.linalg.norm(ref[s]) < tol
+    ctx.close()
+
+
 def test_rhs_vs_oracle(F, cfg1_dense):
     room, k = cfg1_dense
     ctx = make_ctx(F, room, k)
