@@ -39,6 +39,8 @@ def main():
     ap.add_argument("--maxit", type=int, default=1200, help="FGMRES iteration cap (= Krylov dimension)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner solve")
     ap.add_argument("--no-autotune", action="store_true", help="fixed tile-shape rule instead of measured shapes")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run 4 device copies of 512 MiB (calibration of the FETCH_SIZE/WRITE_SIZE counters)")
     ap.add_argument("--train-maxit", type=int, default=300, help="iteration cap of the reference solve for training")
     ap.add_argument("--lds-budget", type=int, default=0, help="LDS bytes per translation tile (0 = library default)")
     args = ap.parse_args()
@@ -86,6 +88,15 @@ def main():
         ctx.fmmbem_matvec_dev(x.data_ptr(), y.data_ptr(), stream=sp)
     torch.cuda.synchronize()
     log("warmup done")
+    if args.copy_calib:
+        a = torch.empty(512 * 2 ** 20 // 4, dtype=torch.float32, device=dev)
+        c = torch.empty_like(a)
+        a.fill_(1.0)
+        for _ in range(4):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        del a, c
+        log("copy calibration: 4 x 512 MiB device copies")
 
     ctx.fmmbem_profile(True)
     torch.cuda.synchronize()
