@@ -442,6 +442,21 @@ template <class R, int N> __device__ inline void load_row(R (&h)[N], cst_ptr<R> 
 #pragma unroll
     for (int v = 0; v < N; ++v) h[v] = row[v];
 }
+// acc_v += h_v x for a table row of RC values, read 16 at a time (bounded scalar registers)
+template <class R, class C, int RC>
+__device__ inline void rot_fma_row(cst_ptr<R> row, C x, R (&ar)[RC], R (&ai)[RC]) {
+#pragma unroll
+    for (int h0 = 0; h0 < RC; h0 += 16) {
+        R h[16];
+#pragma unroll
+        for (int v = 0; v < 16; ++v) h[v] = row[h0 + v];
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            ar[h0 + v] = fma(h[v], x.x, ar[h0 + v]);
+            ai[h0 + v] = fma(h[v], x.y, ai[h0 + v]);
+        }
+    }
+}
 // acc_v += s_v T_v x with T_v = (t[2v], t[2v+1]) and s_v = (-1)^v, negated when NEG
 template <class R, class C, int RC, bool NEG>
 __device__ inline void coax_acc(const R (&t)[2 * RC], C x, R (&ar)[RC], R (&ai)[RC]) {
@@ -463,7 +478,7 @@ __device__ inline int64_t tl_idx(int64_t J, int c, int P2) { return ((J >> 6) * 
 // through LDS 8 columns at a time: one load instruction reads 8 jobs x 8 consecutive
 // coefficients, i.e. whole 128-byte lines (a lane reading its own row alone would fetch each
 // line for 16 bytes once the wave's 64 rows no longer fit L1).
-template <class R, int RC>
+template <class R, int RC, bool PF>
 __global__ void __launch_bounds__(64) k_tl_rot_fwd(TransArgsT<R> a, int nsplit) {
     using C = typename Cx<R>::T;
     constexpr int CW = 8;
@@ -492,32 +507,43 @@ __global__ void __launch_bounds__(64) k_tl_rot_fwd(TransArgsT<R> a, int nsplit) 
                 __syncthreads();
                 if (sq < cw) {
                     const int c = c0 + sq;
-                    C xs[LANE_JT / 8], ps[LANE_JT / 8];  // all loads in flight before the first use
 #pragma unroll
-                    for (int i = 0; i < LANE_JT / 8; ++i) {
-                        const int j = sj + 8 * i;
-                        xs[i] = a.src[soff[j] + n * n + c];
-                        ps[i] = a.ph[sdir[j] + c - n];
+                    for (int i0 = 0; i0 < LANE_JT / 8; i0 += 4) {
+                        C xs[4], ps[4];  // four jobs' loads in flight before the first use
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int j = sj + 8 * (i0 + i);
+                            xs[i] = a.src[soff[j] + n * n + c];
+                            ps[i] = a.ph[sdir[j] + c - n];
+                        }
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) S[sj + 8 * (i0 + i)][sq] = mulc(ps[i], xs[i]);  // e^{i m a} c_n^m
                     }
-#pragma unroll
-                    for (int i = 0; i < LANE_JT / 8; ++i) S[sj + 8 * i][sq] = mulc(ps[i], xs[i]);  // e^{i m a} c_n^m
                 }
                 __syncthreads();
-                // rows past w read the next table entries (TABLE_PAD spare); never stored.  The
-                // next table row is loaded before the current one is used.
-                R h[RC];
-                load_row<R, RC>(h, as_cst(Hn, c0 * w + r0));
-                for (int q = 0; q < cw; ++q) {
-                    const C xv = S[lane][q];
-                    R hn[RC];
-                    load_row<R, RC>(hn, as_cst(Hn, (c0 + q + 1) * w + r0));  // spare-padded past the end
+                // rows past w read the next table entries (TABLE_PAD spare); never stored.  With PF
+                // the next table row is loaded before the current one is used (two rows of RC
+                // values must then fit the scalar registers).
+                if (PF) {
+                    R h[RC];
+                    load_row<R, RC>(h, as_cst(Hn, c0 * w + r0));
+                    for (int q = 0; q < cw; ++q) {
+                        const C xv = S[lane][q];
+                        R hn[RC];
+                        load_row<R, RC>(hn, as_cst(Hn, (c0 + q + 1) * w + r0));  // spare-padded
 #pragma unroll
-                    for (int v = 0; v < RC; ++v) {
-                        ar[v] = fma(h[v], xv.x, ar[v]);
-                        ai[v] = fma(h[v], xv.y, ai[v]);
+                        for (int v = 0; v < RC; ++v) {
+                            ar[v] = fma(h[v], xv.x, ar[v]);
+                            ai[v] = fma(h[v], xv.y, ai[v]);
+                        }
+#pragma unroll
+                        for (int v = 0; v < RC; ++v) h[v] = hn[v];
                     }
-#pragma unroll
-                    for (int v = 0; v < RC; ++v) h[v] = hn[v];
+                } else {
+                    for (int q = 0; q < cw; ++q) {
+                        const C xv = S[lane][q];
+                        rot_fma_row<R, C, RC>(as_cst(Hn, (c0 + q) * w + r0), xv, ar, ai);
+                    }
                 }
             }
             if (live) {
@@ -531,7 +557,7 @@ __global__ void __launch_bounds__(64) k_tl_rot_fwd(TransArgsT<R> a, int nsplit) 
 
 // Back rotation: W2 (interleaved) -> W1 (job-major, for the per-target reduction), through an
 // LDS transpose RC rows at a time.
-template <class R, int RC>
+template <class R, int RC, bool PF>
 __global__ void __launch_bounds__(64) k_tl_rot_back(TransArgsT<R> a, int nsplit) {
     using C = typename Cx<R>::T;
     constexpr int OT = 8;  // rows per transpose (small LDS footprint keeps occupancy); 8 x 8 stores
@@ -551,23 +577,30 @@ __global__ void __launch_bounds__(64) k_tl_rot_back(TransArgsT<R> a, int nsplit)
             R ar[RC], ai[RC];
 #pragma unroll
             for (int v = 0; v < RC; ++v) ar[v] = ai[v] = 0;
-            R h[RC];
-            load_row<R, RC>(h, as_cst(Hn, r0));
             C xv = a.W2[tl_idx(Jc, n * n, P2)];
-            for (int c = 0; c < w; ++c) {
-                // next row of the table and next input value first (spare-padded table; the
-                // input index is clamped)
-                R hn[RC];
-                load_row<R, RC>(hn, as_cst(Hn, (c + 1) * w + r0));
-                const C xn = a.W2[tl_idx(Jc, n * n + min(c + 1, w - 1), P2)];
+            if (PF) {
+                R h[RC];
+                load_row<R, RC>(h, as_cst(Hn, r0));
+                for (int c = 0; c < w; ++c) {
+                    // next table row and next input value first (spare-padded table, clamped index)
+                    R hn[RC];
+                    load_row<R, RC>(hn, as_cst(Hn, (c + 1) * w + r0));
+                    const C xn = a.W2[tl_idx(Jc, n * n + min(c + 1, w - 1), P2)];
 #pragma unroll
-                for (int v = 0; v < RC; ++v) {
-                    ar[v] = fma(h[v], xv.x, ar[v]);
-                    ai[v] = fma(h[v], xv.y, ai[v]);
+                    for (int v = 0; v < RC; ++v) {
+                        ar[v] = fma(h[v], xv.x, ar[v]);
+                        ai[v] = fma(h[v], xv.y, ai[v]);
+                    }
+#pragma unroll
+                    for (int v = 0; v < RC; ++v) h[v] = hn[v];
+                    xv = xn;
                 }
-#pragma unroll
-                for (int v = 0; v < RC; ++v) h[v] = hn[v];
-                xv = xn;
+            } else {
+                for (int c = 0; c < w; ++c) {
+                    const C xn = a.W2[tl_idx(Jc, n * n + min(c + 1, w - 1), P2)];
+                    rot_fma_row<R, C, RC>(as_cst(Hn, c * w + r0), xv, ar, ai);
+                    xv = xn;
+                }
             }
             // transpose to job-major rows OT rows at a time
 #pragma unroll
@@ -594,7 +627,7 @@ __global__ void __launch_bounds__(64) k_tl_rot_back(TransArgsT<R> a, int nsplit)
 }
 
 // Coaxial step: W1 (interleaved) -> W2 (interleaved), fully coalesced.
-template <class R, int RC>
+template <class R, int RC, bool PF>
 __global__ void __launch_bounds__(64) k_tl_coax(TransArgsT<R> a, int nsplit) {
     using C = typename Cx<R>::T;
     const int64_t J = (int64_t)blockIdx.x * LANE_JT + threadIdx.x;
@@ -628,14 +661,18 @@ __global__ void __launch_bounds__(64) k_tl_coax(TransArgsT<R> a, int nsplit) {
             int n = am;
             C xv = a.W1[tl_idx(Jc, n * n + n + m, P2)];
             for (int q = 0; q < cin; ++q, ++n) {
-                R tn[2 * RC];
-                load_row<R, 2 * RC>(tn, as_cst((const R *)Tm, 2 * ((int64_t)(q + 1) * B + r0)));
+                R tn[PF ? 2 * RC : 1];
+                if (PF) load_row<R, PF ? 2 * RC : 1>(tn, as_cst((const R *)Tm, 2 * ((int64_t)(q + 1) * B + r0)));
                 const int nn1 = min(n + 1, a.psrc - 1);
                 const C xn = a.W1[tl_idx(Jc, nn1 * nn1 + nn1 + m, P2)];
                 if (((q + r0) & 1) == 0) coax_acc<R, C, RC, false>(t, xv, ar, ai);
                 else coax_acc<R, C, RC, true>(t, xv, ar, ai);
+                if (PF) {
 #pragma unroll
-                for (int v = 0; v < 2 * RC; ++v) t[v] = tn[v];
+                    for (int v = 0; v < 2 * RC; ++v) t[v] = tn[PF ? v : 0];
+                } else if (q + 1 < cin) {
+                    load_row<R, 2 * RC>(t, as_cst((const R *)Tm, 2 * ((int64_t)(q + 1) * B + r0)));
+                }
                 xv = xn;
             }
             if (live) {
@@ -713,13 +750,15 @@ const char *trans_stage(const TransBatch &b, const TransTables<R> &tb, int stage
         const int nd = stage == 1 ? 2 * b.ptgt - 1 : (stage == 0 ? b.psrc : b.ptgt);
         const int ns = (int)std::max<int64_t>(1, std::min<int64_t>(nd, (4096 + ntile - 1) / std::max(1u, ntile)));
         const dim3 grid(ntile, ns);
-        constexpr int RC = sizeof(R) == 8 ? 16 : 32;
+        // Row chunks: 32 rows for the rotations (a whole degree up to p = 16) and 16 for the
+        // coaxial step (a whole order up to p = 16), so that the inputs are read once per degree
+        // or order; FP32 rows are small enough to double-buffer the table in scalar registers.
+        constexpr bool PF = sizeof(R) == 4;
         switch (stage) {
-        case 0: k_tl_rot_fwd<R, RC><<<grid, 64, 0, st>>>(a, ns), name = f32 ? "k_tl_rot_fwd_f32" : "k_tl_rot_fwd"; break;
-        case 1:  // half the rows: two complex table rows (current + prefetched) must fit the SGPRs
-            k_tl_coax<R, RC / 2><<<grid, 64, 0, st>>>(a, ns), name = f32 ? "k_tl_coax_f32" : "k_tl_coax";
-            break;
-        default: k_tl_rot_back<R, RC><<<grid, 64, 0, st>>>(a, ns), name = f32 ? "k_tl_rot_back_f32" : "k_tl_rot_back";
+        case 0: k_tl_rot_fwd<R, 32, PF><<<grid, 64, 0, st>>>(a, ns), name = f32 ? "k_tl_rot_fwd_f32" : "k_tl_rot_fwd"; break;
+        case 1: k_tl_coax<R, 16, PF><<<grid, 64, 0, st>>>(a, ns), name = f32 ? "k_tl_coax_f32" : "k_tl_coax"; break;
+        default:
+            k_tl_rot_back<R, 32, PF><<<grid, 64, 0, st>>>(a, ns), name = f32 ? "k_tl_rot_back_f32" : "k_tl_rot_back";
         }
         LAUNCH_OK();
         return name;
