@@ -27,6 +27,28 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_lroom_1M_fp64.json")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary (two rocprofv3 --pmc
+    passes, calibrated on a device copy), or None when the summary is missing or the sources it
+    was taken with have changed since."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as fh:
+        t = json.load(fh)
+    for fn, digest in t.get("source_sha256", {}).items():
+        with open(os.path.join(ROOT, "paper_2103_16073_amd", "csrc", fn), "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest() != digest:
+                return None
+    for name, v in t.get("kernels", {}).items():
+        if name.replace("<1>", "") == kernel:
+            return v["hbm_bytes_per_launch"]
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,8 +143,11 @@ def main():
     avg_ms = dom["ms"] / dom["launches"]
     flops_per_launch = dom["flops"] / dom["launches"]
     achieved = flops_per_launch / (avg_ms * 1e-3)
+    traffic = measured_traffic(dom["name"]) if (args.workload == 3 and not args.no_autotune) else None
     roofline = {"kernel": dom["name"], "bound": "alu", "achieved": achieved / 1e12, "peak": PEAKS["fp64"] / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / PEAKS["fp64"], "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / PEAKS["fp64"], "traffic": traffic,
+                "traffic_GBps": None if traffic is None else traffic / (avg_ms * 1e-3) / 1e9,
+                "algorithmic_bytes_per_launch": dom["bytes"] / dom["launches"],
                 "avg_launch_ms": avg_ms, "launches_per_step": dom["launches"] / args.steps,
                 "algorithmic_flops_per_launch": flops_per_launch}
     log(f"dominant kernel {dom['name']}: {avg_ms:.3f} ms/launch, {achieved/1e12:.3f} TFLOP/s")

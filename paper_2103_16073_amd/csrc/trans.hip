@@ -560,8 +560,17 @@ __global__ void __launch_bounds__(64) k_tl_rot_fwd(TransArgsT<R> a, int nsplit) 
 template <class R, int RC, bool PF>
 __global__ void __launch_bounds__(64) k_tl_rot_back(TransArgsT<R> a, int nsplit) {
     using C = typename Cx<R>::T;
-    constexpr int OT = 8;  // rows per transpose (small LDS footprint keeps occupancy); 8 x 8 stores
-    __shared__ C O[LANE_JT][OT + 1];
+    constexpr int OT = 8;  // rows per transpose (small LDS footprint keeps occupancy)
+    // With one block per tile (nsplit == 1) the outputs come in increasing coefficient order; they
+    // pass through a ring of RING coefficients per job and leave in whole 128-byte lines (G
+    // coefficients), so no line of the job-major rows is written in parts.
+    // (FP64 only: in FP32 the ring measured slower and its LDS would cost occupancy)
+    constexpr bool RING_OK = sizeof(R) == 8;
+    constexpr int G = 128 / sizeof(C), RING = 16, OW = RING_OK ? RING : OT;
+    static_assert(!RING_OK || G + OT <= RING, "ring too small for a pending line and a transpose group");
+    __shared__ C O[LANE_JT][OW + 1];
+    const bool ordered = RING_OK && nsplit == 1;
+    int base = 0, cnext = 0;  // first coefficient not yet stored; next coefficient to be produced
     const int lane = threadIdx.x;
     const int64_t J0 = (int64_t)blockIdx.x * LANE_JT, J = J0 + lane;
     const int64_t Jc = J < a.njob ? J : a.njob - 1;
@@ -607,21 +616,45 @@ __global__ void __launch_bounds__(64) k_tl_rot_back(TransArgsT<R> a, int nsplit)
             for (int h0 = 0; h0 < RC; h0 += OT) {
                 const int rc = min(OT, w - r0 - h0);
                 if (rc <= 0) break;
+                const int c0 = n * n + r0 + h0;
                 __syncthreads();
 #pragma unroll
                 for (int v = 0; v < OT; ++v)
-                    if (v < rc) O[lane][v] = mulcc(mkc<C>(ar[h0 + v], ai[h0 + v]), ph[r0 + h0 + v - n]);  // e^{-i m a}
+                    if (v < rc) {
+                        const C val = mulcc(mkc<C>(ar[h0 + v], ai[h0 + v]), ph[r0 + h0 + v - n]);  // e^{-i m a}
+                        O[lane][ordered ? (c0 + v) % RING : v] = val;
+                    }
                 __syncthreads();
-                // one store instruction: 8 jobs x 8 consecutive coefficients
-                const int q = lane & 7;
-                if (q < rc) {
+                if (ordered) {
+                    cnext = c0 + rc;
+                    while (cnext - base >= G) {  // one store instruction: 64/G jobs x one whole line
+                        const int q = lane % G;
 #pragma unroll
-                    for (int i = 0; i < LANE_JT / 8; ++i) {
-                        const int j = (lane >> 3) + 8 * i;
-                        if (j < nlive) a.W1[(J0 + j) * (int64_t)P2 + n * n + r0 + h0 + q] = O[j][q];
+                        for (int i = 0; i < G; ++i) {
+                            const int j = lane / G + (64 / G) * i;
+                            if (j < nlive) a.W1[(J0 + j) * (int64_t)P2 + base + q] = O[j][(base + q) % RING];
+                        }
+                        base += G;
+                    }
+                } else {
+                    // one store instruction: 8 jobs x 8 consecutive coefficients
+                    const int q = lane & 7;
+                    if (q < rc) {
+#pragma unroll
+                        for (int i = 0; i < LANE_JT / 8; ++i) {
+                            const int j = (lane >> 3) + 8 * i;
+                            if (j < nlive) a.W1[(J0 + j) * (int64_t)P2 + c0 + q] = O[j][q];
+                        }
                     }
                 }
             }
+        }
+    }
+    if (ordered && cnext > base) {  // the last, partial line
+        const int cnt = cnext - base;
+        for (int e = lane; e < nlive * G; e += LANE_JT) {
+            const int j = e / G, q = e % G;
+            if (q < cnt) a.W1[(J0 + j) * (int64_t)P2 + base + q] = O[j][(base + q) % RING];
         }
     }
 }
@@ -699,10 +732,21 @@ __global__ void __launch_bounds__(256) k_tr_reduce(int64_t ntgt, int nr, int ptg
     const int j0 = start[tr], j1 = start[tr + 1];
     if (j0 == j1) return;
     const int pt2 = ptgt * ptgt;
+    const int64_t P2 = (int64_t)P * P;
     for (int c = threadIdx.x; c < pt2; c += blockDim.x) {
-        C s = dst[t * pt2 + c];
-        for (int q = j0; q < j1; ++q) s = addc(s, W[((int64_t)jobs[q] * nr + r) * P * P + c]);
-        dst[t * pt2 + c] = s;
+        // four independent partial sums keep four row loads in flight
+        C s0 = dst[t * pt2 + c], s1 = mkc<C>(0, 0), s2 = mkc<C>(0, 0), s3 = mkc<C>(0, 0);
+        int q = j0;
+        for (; q + 4 <= j1; q += 4) {
+            const C a0 = W[((int64_t)jobs[q] * nr + r) * P2 + c], a1 = W[((int64_t)jobs[q + 1] * nr + r) * P2 + c];
+            const C a2 = W[((int64_t)jobs[q + 2] * nr + r) * P2 + c], a3 = W[((int64_t)jobs[q + 3] * nr + r) * P2 + c];
+            s0 = addc(s0, a0);
+            s1 = addc(s1, a1);
+            s2 = addc(s2, a2);
+            s3 = addc(s3, a3);
+        }
+        for (; q < j1; ++q) s0 = addc(s0, W[((int64_t)jobs[q] * nr + r) * P2 + c]);
+        dst[t * pt2 + c] = addc(addc(s0, s1), addc(s2, s3));
     }
 }
 
