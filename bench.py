@@ -60,6 +60,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--maxit", type=int, default=1200, help="FGMRES iteration cap (= Krylov dimension)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner solve")
+    ap.add_argument("--no-batched-solve", action="store_true", help="skip the 4-source batched solve")
+    ap.add_argument("--batch-restart", type=int, default=850, help="Krylov dimension of the batched solve")
     ap.add_argument("--no-autotune", action="store_true", help="fixed tile-shape rule instead of measured shapes")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run 4 device copies of 512 MiB (calibration of the FETCH_SIZE/WRITE_SIZE counters)")
@@ -258,6 +260,20 @@ def main():
                                                 "t_train_s": trep.t_train_s}}
             log(f"FGMRES mixed+learned: status {rc} iters {rep.iters} rel_res {rep.rel_res:.3e} "
                 f"t {rep.t_solve_s:.2f}s fallback at {rep.pc_fallback_at}")
+        if not args.no_batched_solve:
+            # four source positions solved together: one 4-vector mixed product per step
+            ctx.fmmbem_release_workspace()
+            xs4, reps, rc = ctx.fmmbem_solve_batch([0, 1, 2, 3], tol=1e-4, restart=args.batch_restart,
+                                                   maxit=args.maxit, precond=F.FMMBEM_PC_NEARBLOCK,
+                                                   precision=F.FMMBEM_MIXED)
+            tb = reps[0].t_solve_s
+            fg["mixed_batched_4_sources"] = {
+                "status": rc, "iters": [r.iters for r in reps], "rel_res_fp64": [r.rel_res for r in reps],
+                "t_solve_s_total": tb, "t_solve_s_per_source": tb / 4, "restart": args.batch_restart,
+                "matvecs_mixed": reps[0].matvecs_mixed, "matvecs_fp64": reps[0].matvecs_fp64}
+            log(f"FGMRES mixed, 4 sources batched: status {rc} iters {[r.iters for r in reps]} "
+                f"rel_res {[f'{r.rel_res:.2e}' for r in reps]} t {tb:.2f}s ({tb / 4:.2f}s per source)")
+            ctx.fmmbem_release_workspace()
         fg["precond"] = "near-field leaf blocks"
         fg["restart"] = args.maxit
         if fg["fp64"]["status"] == 0 and fg["mixed"]["status"] == 0:
