@@ -35,8 +35,9 @@ __global__ void k_p2p_n(int, const int32_t *, const int32_t *, const int32_t *, 
                         const double2 *, const double2 *, const double2 *, const double2 *, double2 *, double2 *);
 __global__ void k_local_derivs(int64_t, int, const double2 *, double, double2 *, double2 *, double2 *);
 __global__ void k_l2p_n(int, int, const int32_t *, const double4 *, const double4 *, const double4 *, const double2 *,
-                        const double2 *, const double2 *, const double2 *, double, const double2 *, const double2 *,
-                        const int32_t *, int64_t, const double2 *, const double2 *, const double2 *, double2 *, int);
+                        const double2 *, const double2 *, const double2 *, double, const double *, const double2 *,
+                        const double2 *, const int32_t *, int64_t, const double2 *, const double2 *, const double2 *,
+                        double2 *, int);
 __global__ void k_diag2_inv(int64_t, const int32_t *, const int32_t *, const double2 *, const double2 *,
                             const double2 *, const double2 *, double, double, double2 *);
 __global__ void k_mul_diag2(int64_t, const int32_t *, const double2 *, const double2 *, double2 *);
@@ -45,12 +46,13 @@ void launch_p2p(int nr, bool fp32, int nleaf, const int32_t *leaf_start, const i
                 const double2 *mu, double k, double rc2, const int32_t *near_start, const int32_t *near_col,
                 const void *nL, const void *nM, double2 *y, hipStream_t st);
 size_t p2m_stage_bytes(int nr, int p);
+size_t p2m_fixed_bytes(int p);
 void launch_p2m(int nr, int nleaf, int p, int CH, const int32_t *leaf_start, const double4 *center,
                 const double4 *ec, const double4 *en, const double2 *sigma, const double2 *mu, double k,
-                double2 *Mout, hipStream_t st);
+                const double *leg, double2 *Mout, hipStream_t st);
 void launch_l2p(int nr, int nleaf, int p, const int32_t *leaf_start, const double4 *center, const double4 *ec,
-                const double2 *Lc, double k, const double2 *ynear, double half, const int32_t *perm, int64_t n,
-                const double2 *x, double2 *y, int has_far, hipStream_t st);
+                const double2 *Lc, double k, const double *leg, const double2 *ynear, double half,
+                const int32_t *perm, int64_t n, const double2 *x, double2 *y, int has_far, hipStream_t st);
 __global__ void k_cvt_d2f(int64_t, const double2 *, float2 *);
 __global__ void k_cvt_f2d(int64_t, const float2 *, double2 *);
 __global__ void k_cvt_real_d2f(int64_t, const double *, float *);
@@ -95,6 +97,16 @@ static T *upload(DeviceBuffers &b, const std::string &name, const std::vector<T>
     T *d = dget<T>(b, name, std::max<size_t>(v.size(), 1));
     if (!v.empty()) HIP_OK(hipMemcpyAsync(d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st));
     return d;
+}
+
+// Legendre recurrence table (built with the rotation tables, degrees up to the largest p + 1)
+static const double *leg_table(fmmbem_ctx *c) { return (const double *)c->buf.find("legtab"); }
+
+// sources staged per P2M chunk (about 60 KB of LDS per workgroup)
+static int p2m_chunk(int nr, int p) {
+    const size_t per = p2m_stage_bytes(nr, p), fixed = p2m_fixed_bytes(p);
+    if (per + fixed > 60000) throw FmmError(FMMBEM_EINVAL, "leaf truncation number too large for P2M staging");
+    return (int)std::max<size_t>(1, std::min<size_t>(32, (60000 - fixed) / per));
 }
 
 static void setup_mesh(fmmbem_ctx *c) {
@@ -396,6 +408,21 @@ static void setup_k(fmmbem_ctx *c) {
         std::vector<double2> A;
         direction_phases(c->pmax, A);
         upload(c->buf, "phA", A, st);
+        // recurrence table of the normalised Legendre functions, degrees up to pmax + 1
+        const int pl = c->pmax + 1;
+        std::vector<double> lt((size_t)leg_table_len(pl), 0.0);
+        for (int n = 0; n <= pl; ++n)
+            for (int m = 0; m <= n; ++m) {
+                double *e = &lt[3 * (size_t)leg_tri(n, m)];
+                if (n > m) e[0] = std::sqrt((4.0 * n * n - 1.0) / ((double)n * n - (double)m * m));
+                if (n > m + 1)
+                    e[1] = std::sqrt((((double)n - 1) * (n - 1) - (double)m * m) * (2.0 * n + 1.0) /
+                                     ((2.0 * n - 3.0) * ((double)n * n - (double)m * m)));
+                double g = 1.0 / std::sqrt(4.0 * FMM_PI);
+                for (int q = 1; q <= m; ++q) g *= std::sqrt((2.0 * q + 1.0) / (2.0 * q));
+                e[2] = g;
+            }
+        upload(c->buf, "legtab", lt, st);
         c->delta_p = c->pmax;
     }
     // coaxial tables
@@ -792,12 +819,10 @@ static void fmm_pass(fmmbem_ctx *c, int nr, const double2 *sigma, const double2 
     if (!exact_far) {
         LevelDev &LL = c->lev[L];
         const int p = LL.p;
-        const size_t per = p2m_stage_bytes(nr, p);
-        if (per > 60000) throw FmmError(FMMBEM_EINVAL, "leaf truncation number too large for P2M staging");
-        const int CH = (int)std::max<size_t>(1, std::min<size_t>(32, 60000 / per));
+        const int CH = p2m_chunk(nr, p);
         const size_t pp = (size_t)p * p;
         pe = prof_begin(c);
-        launch_p2m(nr, nleaf, p, CH, I32("leaf_start"), LL.center, ec, en, sigma, mu, c->k, LL.M, st);
+        launch_p2m(nr, nleaf, p, CH, I32("leaf_start"), LL.center, ec, en, sigma, mu, c->k, leg_table(c), LL.M, st);
         prof_end(c, pe, "k_p2m", (double)n * pp * 2 * 8.0 * nr, 112.0 * n + 32.0 * n * nr + 16.0 * nleaf * pp * nr);
         rec(c, 3);
         if (mixed) {
@@ -851,8 +876,8 @@ static void fmm_pass(fmmbem_ctx *c, int nr, const double2 *sigma, const double2 
     rec(c, 6);
     LevelDev &LL = c->lev[L];
     pe = prof_begin(c);
-    launch_l2p(nr, nleaf, LL.p, I32("leaf_start"), LL.center, ec, LL.L, c->k, ynear, half, I32("perm"), n, x, y,
-               exact_far ? 0 : 1, st);
+    launch_l2p(nr, nleaf, LL.p, I32("leaf_start"), LL.center, ec, LL.L, c->k, leg_table(c), ynear, half,
+               I32("perm"), n, x, y, exact_far ? 0 : 1, st);
     prof_end(c, pe, "k_l2p", (double)n * LL.p * LL.p * 8.0 * nr,
              32.0 * n + 16.0 * n * 3 * nr + 16.0 * nleaf * LL.p * LL.p * nr);
     rec(c, 7);
@@ -1013,9 +1038,8 @@ static void fmm_pass_ind(fmmbem_ctx *c, const double2 *sigma, const double2 *mu,
     double2 *Dz = dget<double2>(c->scratch, "ind_Dz", LL.nbox * q1), *Dp = dget<double2>(c->scratch, "ind_Dp", LL.nbox * q1),
             *Dm = dget<double2>(c->scratch, "ind_Dm", LL.nbox * q1);
     if (!exact_far) {
-        const size_t per = p2m_stage_bytes(1, p);
-        const int CH = (int)std::max<size_t>(1, std::min<size_t>(32, 60000 / per));
-        launch_p2m(1, nleaf, p, CH, I32("leaf_start"), LL.center, ec, en, sigma, mu, c->k, LL.M, st);
+        launch_p2m(1, nleaf, p, p2m_chunk(1, p), I32("leaf_start"), LL.center, ec, en, sigma, mu, c->k, leg_table(c),
+                   LL.M, st);
         const double2 *ph = (double2 *)c->buf.find("phA");
         for (int l = L - 1; l >= 2; --l) {
             LevelDev &P_ = c->lev[l], &C_ = c->lev[l + 1];
@@ -1035,8 +1059,8 @@ static void fmm_pass_ind(fmmbem_ctx *c, const double2 *sigma, const double2 *mu,
         LAUNCH_OK();
     }
     pe = prof_begin(c);
-    k_l2p_n<<<nleaf, 64, (size_t)64 * (p + 3) * sizeof(double), st>>>(
-        nleaf, p, I32("leaf_start"), LL.center, ec, en, LL.L, Dz, Dp, Dm, c->k, yv, yn, I32("perm"), n, x,
+    k_l2p_n<<<nleaf, 64, ((size_t)64 * (p + 3) + (size_t)3 * (p + 1) * (p + 2) / 2) * sizeof(double), st>>>(
+        nleaf, p, I32("leaf_start"), LL.center, ec, en, LL.L, Dz, Dp, Dm, c->k, leg_table(c), yv, yn, I32("perm"), n, x,
         (double2 *)c->buf.find("beta"), (double2 *)c->buf.find("betap"), y, exact_far ? 0 : 1);
     LAUNCH_OK();
     prof_end(c, pe, "k_l2p_n", (double)n * q1 * 8.0 * 4, 0.0);

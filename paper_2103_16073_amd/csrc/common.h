@@ -89,6 +89,16 @@ __host__ __device__ inline double coef_b(int n, int m) {
     return m >= 0 ? v : -v;
 }
 
+// Recurrence of the normalised associated Legendre functions used by the regular basis
+// (no Condon-Shortley phase), 0 <= m <= n:
+//   P_m^m = g_m sin^m,  g_m = (4 pi)^{-1/2} prod_{q=1}^{m} sqrt((2q+1)/(2q)),
+//   P_n^m = a_nm cos P_{n-1}^m - b_nm P_{n-2}^m  (n > m),
+//   a_nm = sqrt((4n^2-1)/(n^2-m^2)),  b_nm = sqrt(((n-1)^2-m^2)(2n+1)/((2n-3)(n^2-m^2))) (0 for n = m+1).
+// Table entry t = n(n+1)/2 + m holds (a_nm, b_nm, g_m) at 3t .. 3t+2; a table built for pmax holds
+// every smaller one as a prefix.
+__host__ __device__ inline int leg_tri(int n, int m) { return n * (n + 1) / 2 + m; }
+__host__ __device__ inline int64_t leg_table_len(int pmax) { return 3 * (int64_t)(pmax + 1) * (pmax + 2) / 2; }
+
 // squared distance without contraction, so that every kernel and the host classify
 // near pairs identically
 __device__ inline double dist2_exact(double ax, double ay, double az, double bx, double by, double bz) {

@@ -279,6 +279,55 @@ __global__ void k_gamma(int64_t n, const double4 *ec, const double4 *en, const d
     mu[i] = cmk(0, 0);
 }
 
+// ------------------------------------------------------------------ pair-kernel helpers
+// 1/sqrt(d) for a positive, normal d: hardware estimate and two Newton steps (about an ulp)
+__device__ inline double rsq_nr(double d) {
+    double y = __builtin_amdgcn_rsq(d);
+    double e = fma(-d * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-d * y, y, 1.0);
+    return fma(0.5 * y, e, y);
+}
+
+// sin and cos of x for |x| <= 1e5 (k r of element pairs): x = q pi/2 + y with pi/2 split in two
+// parts (Cody-Waite), |y| <= pi/4, then the Taylor polynomials of sin y through y^17 and of cos y
+// through y^16 (truncation below 1e-17); the absolute error is a few 1e-16.  Larger arguments use
+// the library routine.
+__device__ inline void sincos_red(double x, double &s, double &c) {
+    if (!(fabs(x) <= 1e5)) {
+        sincos(x, &s, &c);
+        return;
+    }
+    const double q = rint(x * 0.63661977236758134308);
+    double y = fma(-q, 1.5707963267948966, x);
+    y = fma(-q, 6.123233995736766e-17, y);
+    const double w = -y * y;
+    // sum_i w^i / (2i+1)!  and  sum_i w^i / (2i)!
+    double ts = 1.0 / 355687428096000.0;
+    ts = fma(ts, w, 1.0 / 1307674368000.0);
+    ts = fma(ts, w, 1.0 / 6227020800.0);
+    ts = fma(ts, w, 1.0 / 39916800.0);
+    ts = fma(ts, w, 1.0 / 362880.0);
+    ts = fma(ts, w, 1.0 / 5040.0);
+    ts = fma(ts, w, 1.0 / 120.0);
+    ts = fma(ts, w, 1.0 / 6.0);
+    ts = fma(ts, w, 1.0);
+    double tc = 1.0 / 20922789888000.0;
+    tc = fma(tc, w, 1.0 / 87178291200.0);
+    tc = fma(tc, w, 1.0 / 479001600.0);
+    tc = fma(tc, w, 1.0 / 3628800.0);
+    tc = fma(tc, w, 1.0 / 40320.0);
+    tc = fma(tc, w, 1.0 / 720.0);
+    tc = fma(tc, w, 1.0 / 24.0);
+    tc = fma(tc, w, 0.5);
+    tc = fma(tc, w, 1.0);
+    const double sy = y * ts, cy = tc;
+    const int iq = (int)q & 3;
+    const double a = (iq & 1) ? cy : sy, b = (iq & 1) ? sy : cy;  // sin and cos before the signs
+    s = (iq & 2) ? -a : a;
+    c = ((iq + 1) & 2) ? -b : b;
+}
+
 // ------------------------------------------------------------------ P2P + near table
 // y_i = sum_{j in neighbour leaves, |c_i - c_j| >= r_c} [G q_j + dG/dn_y w_j] + sum_near [L sigma + M mu]
 // with q_j = A_j sigma_j, w_j = A_j mu_j.  One workgroup (one wavefront) per target leaf,
@@ -329,9 +378,9 @@ __global__ void __launch_bounds__(64) k_p2p(int nleaf, const int32_t *leaf_start
                         double d2 = dist2_exact(ct.x, ct.y, ct.z, sx[jj], sy[jj], sz[jj]);
                         if (d2 < rc2) continue;
                         double dx = sx[jj] - ct.x, dy = sy[jj] - ct.y, dz = sz[jj] - ct.z;
-                        double r = sqrt(d2), ir = 1.0 / r;
+                        const double ir = rsq_nr(d2), r = d2 * ir;
                         double s, c;
-                        sincos(k * r, &s, &c);
+                        sincos_red(k * r, s, c);
                         double2 G = cmk(c * ir * inv4pi, s * ir * inv4pi);
                         double u = (dx * snx[jj] + dy * sny[jj] + dz * snz[jj]) * ir * ir;  // (y-x).n / r^2
                         // G * (q + (ikr - 1) u w)
@@ -476,135 +525,251 @@ __global__ void k_cvt_real_d2f(int64_t n, const double *a, float *b) {
     if (i < n) b[i] = (float)a[i];
 }
 
+// ------------------------------------------------------------------ regular-basis helpers
+// reciprocal of a positive, normal double: hardware estimate and two Newton steps (within an ulp)
+__device__ inline double rcp_nr(double d) {
+    double y = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-d, y, 1.0);
+    return fma(y, e, y);
+}
+
+// sum of the power series of x^{-n} (2n+1)!! j_n(x): t_0 = 1, t_k = t_{k-1} h / (k (2n+2k+1)), h = -x^2/2
+__device__ inline double jn_series(int n, double h, int kmax) {
+    double s = 1.0, t = 1.0;
+    for (int q = 1; q <= kmax; ++q) {
+        t *= h * rcp_nr((double)q * (double)(2 * n + 2 * q + 1));
+        s += t;
+        if (fabs(t) <= 1e-17 * fabs(s)) break;
+    }
+    return s;
+}
+
+// j_0(x) .. j_N(x), x >= 0.  Small x: every order from its series (orders that underflow are
+// zero to working precision).  x < 4 and N <= 40: j_N and j_{N-1} from their series, then the
+// downward recurrence j_{n-1} = (2n+1)/x j_n - j_{n+1}, which is stable for this (minimal)
+// solution.  Otherwise Miller's normalised recurrence.
+__device__ inline void bessel_j_seq(double x, int N, double *j) {
+    const double h = -0.5 * x * x;
+    if (x < 1e-2) {
+        double pre = 1.0;  // x^n / (2n+1)!!
+        for (int n = 0; n <= N; ++n) {
+            if (n > 0) pre *= x * rcp_nr(2.0 * n + 1.0);
+            j[n] = pre * jn_series(n, h, 6);
+        }
+        return;
+    }
+    if (x >= 4.0 || N > 40) {
+        sph_jn_seq(x, N, j);
+        return;
+    }
+    if (N == 0) {
+        j[0] = jn_series(0, h, 40);
+        return;
+    }
+    double xn = 1.0, df = 1.0;  // x^{N-1} and (2N-1)!!
+    for (int n = 1; n < N; ++n) {
+        xn *= x;
+        df *= 2.0 * n + 1.0;
+    }
+    const double pre = xn / df;
+    double jh = pre * x / (2.0 * N + 1.0) * jn_series(N, h, 40);
+    double jl = pre * jn_series(N - 1, h, 40);
+    j[N] = jh;
+    j[N - 1] = jl;
+    const double ix = 1.0 / x;
+    for (int n = N - 1; n >= 1; --n) {
+        const double jm = fma((2.0 * n + 1.0) * ix, jl, -jh);
+        j[n - 1] = jm;
+        jh = jl;
+        jl = jm;
+    }
+}
+
+// spherical coordinates of (dx, dy, dz) about the expansion centre: r, cos/sin of the polar
+// angle and e^{i phi} (any unit phase where the point lies on the axis: the orders m != 0 vanish)
+__device__ inline void sph_frame(double dx, double dy, double dz, double &r, double &ct, double &st, double2 &eph) {
+    const double rxy2 = dx * dx + dy * dy;
+    r = sqrt(rxy2 + dz * dz);
+    const double rxy = sqrt(rxy2);
+    if (r > 0) {
+        const double ir = 1.0 / r;
+        ct = dz * ir;
+        st = rxy * ir;
+    } else {
+        ct = 1.0;
+        st = 0.0;
+    }
+    if (rxy > 0) {
+        const double irx = 1.0 / rxy;
+        eph = cmk(dx * irx, dy * irx);
+    } else {
+        eph = cmk(1.0, 0.0);
+    }
+}
+
 // ------------------------------------------------------------------ P2M
 // C_n^m = i k sum_j [ q_j R_n^{-m}(c_j - C) + w_j (n_j . grad) R_n^{-m}(c_j - C) ]
 // using  d_z R_n^m = k (a_{n-1}^m R_{n-1}^m - a_n^m R_{n+1}^m),
 //        (d_x + i d_y) R_n^m = k (b_{n+1}^{-m-1} R_{n+1}^{m+1} - b_n^m R_{n-1}^{m+1}),
 //        (d_x - i d_y) R_n^m = k (b_{n+1}^{m-1} R_{n+1}^{m-1} - b_n^{-m} R_{n-1}^{m-1}).
-// One workgroup per leaf; the basis R_n^{m'} (n <= p, m' >= 0) of CH sources at a time in LDS.
-__device__ inline double2 basis_get(const double2 *B, int p, int n, int mm) {
-    int am = mm < 0 ? -mm : mm;
-    if (n < 0 || n > p || am > n) return cmk(0, 0);
-    double2 v = B[n * (n + 1) / 2 + am];
-    return mm >= 0 ? v : cconj(v);
-}
-
-// column m' >= 0 of the regular basis at one point: out[n(n+1)/2 + m'] = j_n(kr) P_n^m'(ct) e^{i m' phi}
-__device__ void regular_column(int p, int mp, double ct, double st, double phi, const double *jb, double2 *out) {
-    double pmm = 1.0 / sqrt(4.0 * FMM_PI);
-    for (int q = 1; q <= mp; ++q) pmm *= sqrt((2.0 * q + 1.0) / (2.0 * q)) * st;
-    double s, c;
-    sincos(mp * phi, &s, &c);
-    double pm2 = 0.0, pm1 = pmm;
-    for (int n = mp; n <= p; ++n) {
-        double P;
-        if (n == mp) P = pmm;
-        else if (n == mp + 1) P = sqrt(2.0 * mp + 3.0) * ct * pmm;
-        else {
-            double a = sqrt((4.0 * n * n - 1.0) / ((double)n * n - (double)mp * mp));
-            double bq = sqrt((((double)n - 1) * (n - 1) - (double)mp * mp) * (2.0 * n + 1.0) /
-                             ((2.0 * n - 3.0) * ((double)n * n - (double)mp * mp)));
-            P = a * ct * pm1 - bq * pm2;
-        }
-        if (n >= mp + 1) {
-            pm2 = pm1;
-            pm1 = P;
-        }
-        double R = jb[n] * P;
-        out[n * (n + 1) / 2 + mp] = cmk(R * c, R * s);
+// One workgroup per leaf.  Per chunk of CH sources: geometry and j_n(k r) per source, the basis
+// R_n^{m'} (n <= p, m' >= 0, plus a zero slot) per (source, m') in LDS, then each thread adds the
+// sources' terms to its coefficient(s).  The seven basis entries a coefficient reads, with their
+// factors and conjugation signs, are fixed per coefficient and set up once.
+struct P2mTerms {
+    int i[7];          // basis slot (the zero slot where the entry does not exist)
+    double fx[7], fy[7];  // factors of the real and imaginary parts (fy = -fx for conjugated entries)
+};
+__device__ inline void p2m_term(int p, int TB, int nn, int mm, double f, int &i, double &fx, double &fy) {
+    const int am = mm < 0 ? -mm : mm;
+    if (nn < 0 || nn > p || am > nn) {
+        i = TB;
+        fx = fy = 0.0;
+        return;
     }
+    i = leg_tri(nn, am);
+    fx = f;
+    fy = mm < 0 ? -f : f;
 }
-
-__device__ inline void sph_coords(double dx, double dy, double dz, double &r, double &ct, double &st, double &phi) {
-    r = sqrt(dx * dx + dy * dy + dz * dz);
-    if (r > 0) {
-        ct = dz / r;
-        double rxy = sqrt(dx * dx + dy * dy);
-        st = rxy / r;
-        phi = atan2(dy, dx);
-    } else {
-        ct = 1.0;
-        st = 0.0;
-        phi = 0.0;
+__device__ inline void p2m_terms(int p, int TB, int c, double k, P2mTerms &T) {
+    int n = (int)sqrt((double)c);
+    while (n * n > c) --n;
+    while ((n + 1) * (n + 1) <= c) ++n;
+    const int mm = -(c - n * n - n);
+    p2m_term(p, TB, n, mm, 1.0, T.i[0], T.fx[0], T.fy[0]);
+    p2m_term(p, TB, n - 1, mm, k * coef_a(n - 1, mm), T.i[1], T.fx[1], T.fy[1]);
+    p2m_term(p, TB, n + 1, mm, -k * coef_a(n, mm), T.i[2], T.fx[2], T.fy[2]);
+    p2m_term(p, TB, n + 1, mm + 1, k * coef_b(n + 1, -mm - 1), T.i[3], T.fx[3], T.fy[3]);
+    p2m_term(p, TB, n - 1, mm + 1, -k * coef_b(n, mm), T.i[4], T.fx[4], T.fy[4]);
+    p2m_term(p, TB, n + 1, mm - 1, k * coef_b(n + 1, mm - 1), T.i[5], T.fx[5], T.fy[5]);
+    p2m_term(p, TB, n - 1, mm - 1, -k * coef_b(n, -mm), T.i[6], T.fx[6], T.fy[6]);
+}
+template <int NR>
+__device__ inline void p2m_accumulate(const P2mTerms &T, int cnt, int TS, const double2 *basis, const double2 *qw,
+                                      const double *nrm, double2 (&a)[NR]) {
+    for (int s = 0; s < cnt; ++s) {
+        const double2 *B = basis + (int64_t)s * TS;
+        double2 v[7];
+#pragma unroll
+        for (int t = 0; t < 7; ++t) v[t] = B[T.i[t]];
+        const double2 R0 = cmk(T.fx[0] * v[0].x, T.fy[0] * v[0].y);
+        const double2 dz = cmk(fma(T.fx[1], v[1].x, T.fx[2] * v[2].x), fma(T.fy[1], v[1].y, T.fy[2] * v[2].y));
+        const double2 dp = cmk(fma(T.fx[3], v[3].x, T.fx[4] * v[4].x), fma(T.fy[3], v[3].y, T.fy[4] * v[4].y));
+        const double2 dm = cmk(fma(T.fx[5], v[5].x, T.fx[6] * v[6].x), fma(T.fy[5], v[5].y, T.fy[6] * v[6].y));
+        // n.grad = n_z d_z + (n_x - i n_y)/2 (d_x + i d_y) + (n_x + i n_y)/2 (d_x - i d_y); nrm holds
+        // (n_x/2, n_y/2, n_z)
+        const double hx = nrm[3 * s], hy = nrm[3 * s + 1], nz = nrm[3 * s + 2];
+        double2 dn = cscale(dz, nz);
+        dn = cfma(cmk(hx, -hy), dp, dn);
+        dn = cfma(cmk(hx, hy), dm, dn);
+#pragma unroll
+        for (int rr = 0; rr < NR; ++rr) {
+            a[rr] = cfma(qw[(2 * s) * NR + rr], R0, a[rr]);
+            a[rr] = cfma(qw[(2 * s + 1) * NR + rr], dn, a[rr]);
+        }
     }
 }
 
 template <int NR>
 __global__ void __launch_bounds__(256) k_p2m(int nleaf, int p, int CH, const int32_t *leaf_start,
                                              const double4 *center, const double4 *ec, const double4 *en,
-                                             const double2 *sigma, const double2 *mu, double k, double2 *Mout) {
+                                             const double2 *sigma, const double2 *mu, double k, const double *leg,
+                                             double2 *Mout) {
     extern __shared__ double2 smem[];
     const int b = blockIdx.x, tid = threadIdx.x;
-    const int TB = (p + 1) * (p + 2) / 2;
-    double2 *basis = smem;                                 // CH * TB
-    double2 *qw = basis + (int64_t)CH * TB;                // CH * 2 * NR (16-byte aligned)
+    const int TB = (p + 1) * (p + 2) / 2, TS = TB + 1;     // basis entries and the zero slot
+    double2 *basis = smem;                                 // CH * TS
+    double2 *qw = basis + (int64_t)CH * TS;                // CH * 2 * NR
     double *jb = (double *)(qw + CH * 2 * NR);             // CH * (p+2)
-    double *geo = jb + CH * (p + 2);                       // CH * 4: ct, st, phi, r
+    double *geo = jb + CH * (p + 2);                       // CH * 4: cos, sin of the polar angle, e^{i phi}
     double *nrm = geo + CH * 4;                            // CH * 3
+    double *lt = nrm + CH * 3;                             // 3 TB: Legendre recurrence table
+    for (int e = tid; e < 3 * TB; e += blockDim.x) lt[e] = leg[e];
     const double4 C = center[b];
     const int ss = leaf_start[b], se = leaf_start[b + 1];
     const int ncoef = p * p;
     double2 *Mb = Mout + (int64_t)b * NR * ncoef;          // NR expansions of this leaf
-    for (int c = tid; c < NR * ncoef; c += blockDim.x) Mb[c] = cmk(0, 0);
+    // one coefficient per thread stays in registers across chunks; otherwise accumulate in place
+    const bool in_regs = ncoef <= (int)blockDim.x;
+    P2mTerms T;
+    double2 acc[NR];
+#pragma unroll
+    for (int rr = 0; rr < NR; ++rr) acc[rr] = cmk(0, 0);
+    if (in_regs) {
+        if (tid < ncoef) p2m_terms(p, TB, tid, k, T);
+    } else {
+        for (int c = tid; c < NR * ncoef; c += blockDim.x) Mb[c] = cmk(0, 0);
+    }
     for (int j0 = ss; j0 < se; j0 += CH) {
         const int cnt = min(CH, se - j0);
         __syncthreads();
         if (tid < cnt) {
-            int j = j0 + tid;
-            double4 c = ec[j], nv = en[j];
-            double r, ct, st, phi;
-            sph_coords(c.x - C.x, c.y - C.y, c.z - C.z, r, ct, st, phi);
+            const int j = j0 + tid;
+            const double4 c = ec[j], nv = en[j];
+            double r, ct, st;
+            double2 eph;
+            sph_frame(c.x - C.x, c.y - C.y, c.z - C.z, r, ct, st, eph);
             geo[4 * tid] = ct;
             geo[4 * tid + 1] = st;
-            geo[4 * tid + 2] = phi;
-            geo[4 * tid + 3] = r;
-            sph_jn_seq(k * r, p, jb + tid * (p + 2));
+            geo[4 * tid + 2] = eph.x;
+            geo[4 * tid + 3] = eph.y;
+            bessel_j_seq(k * r, p, jb + tid * (p + 2));
 #pragma unroll
             for (int rr = 0; rr < NR; ++rr) {
                 qw[(2 * tid) * NR + rr] = cscale(sigma[(int64_t)j * NR + rr], c.w);
                 qw[(2 * tid + 1) * NR + rr] = cscale(mu[(int64_t)j * NR + rr], c.w);
             }
-            nrm[3 * tid] = nv.x;
-            nrm[3 * tid + 1] = nv.y;
+            nrm[3 * tid] = 0.5 * nv.x;
+            nrm[3 * tid + 1] = 0.5 * nv.y;
             nrm[3 * tid + 2] = nv.z;
         }
         __syncthreads();
+        // basis column m' of source s: R_n^{m'} = j_n(k r) P_n^{m'}(cos) e^{i m' phi}, n = m'..p
         for (int w = tid; w < cnt * (p + 1); w += blockDim.x) {
-            int s = w / (p + 1), mp = w % (p + 1);
-            regular_column(p, mp, geo[4 * s], geo[4 * s + 1], geo[4 * s + 2], jb + s * (p + 2), basis + (int64_t)s * TB);
+            const int s = w / (p + 1), mp = w - s * (p + 1);
+            const double ct = geo[4 * s], st = geo[4 * s + 1];
+            const double2 eph = cmk(geo[4 * s + 2], geo[4 * s + 3]);
+            const double *js = jb + s * (p + 2);
+            double2 *out = basis + (int64_t)s * TS;
+            double2 e = cmk(1.0, 0.0);
+            double sp = 1.0;
+            for (int q = 0; q < mp; ++q) {
+                e = cmul(e, eph);
+                sp *= st;
+            }
+            double P1 = lt[3 * leg_tri(mp, mp) + 2] * sp, P2 = 0.0;
+            out[leg_tri(mp, mp)] = cscale(e, js[mp] * P1);
+            for (int n = mp + 1; n <= p; ++n) {
+                const int t = leg_tri(n, mp);
+                const double P = fma(lt[3 * t] * ct, P1, -lt[3 * t + 1] * P2);
+                P2 = P1;
+                P1 = P;
+                out[t] = cscale(e, js[n] * P);
+            }
+            if (mp == 0) out[TB] = cmk(0, 0);
         }
         __syncthreads();
-        for (int c = tid; c < ncoef; c += blockDim.x) {
-            int n = (int)sqrt((double)c);
-            while (n * n > c) --n;
-            while ((n + 1) * (n + 1) <= c) ++n;
-            const int m = c - n * n - n, mm = -m;
-            const double ca1 = coef_a(n - 1, mm), ca2 = coef_a(n, mm);
-            const double cb1 = coef_b(n + 1, -mm - 1), cb2 = coef_b(n, mm);
-            const double cb3 = coef_b(n + 1, mm - 1), cb4 = coef_b(n, -mm);
-            double2 a[NR];
+        if (in_regs) {
+            if (tid < ncoef) p2m_accumulate<NR>(T, cnt, TS, basis, qw, nrm, acc);
+        } else {
+            for (int c = tid; c < ncoef; c += blockDim.x) {
+                P2mTerms Tc;
+                p2m_terms(p, TB, c, k, Tc);
+                double2 a[NR];
 #pragma unroll
-            for (int rr = 0; rr < NR; ++rr) a[rr] = cmk(0, 0);
-            for (int s = 0; s < cnt; ++s) {
-                const double2 *B = basis + (int64_t)s * TB;
-                double2 R0 = basis_get(B, p, n, mm);
-                double2 dz = cscale(csub(cscale(basis_get(B, p, n - 1, mm), ca1), cscale(basis_get(B, p, n + 1, mm), ca2)), k);
-                double2 dp = cscale(csub(cscale(basis_get(B, p, n + 1, mm + 1), cb1), cscale(basis_get(B, p, n - 1, mm + 1), cb2)), k);
-                double2 dm = cscale(csub(cscale(basis_get(B, p, n + 1, mm - 1), cb3), cscale(basis_get(B, p, n - 1, mm - 1), cb4)), k);
-                double nx = nrm[3 * s], ny = nrm[3 * s + 1], nz = nrm[3 * s + 2];
-                double2 dn = cscale(dz, nz);
-                dn = cadd(dn, cmul(cmk(0.5 * nx, -0.5 * ny), dp));
-                dn = cadd(dn, cmul(cmk(0.5 * nx, 0.5 * ny), dm));
+                for (int rr = 0; rr < NR; ++rr) a[rr] = cmk(0, 0);
+                p2m_accumulate<NR>(Tc, cnt, TS, basis, qw, nrm, a);
 #pragma unroll
-                for (int rr = 0; rr < NR; ++rr) {
-                    a[rr] = cfma(qw[(2 * s) * NR + rr], R0, a[rr]);
-                    a[rr] = cfma(qw[(2 * s + 1) * NR + rr], dn, a[rr]);
-                }
+                for (int rr = 0; rr < NR; ++rr)
+                    Mb[rr * ncoef + c] = cadd(Mb[rr * ncoef + c], cmuli(cscale(a[rr], k)));  // i k sum
             }
-#pragma unroll
-            for (int rr = 0; rr < NR; ++rr)
-                Mb[rr * ncoef + c] = cadd(Mb[rr * ncoef + c], cmuli(cscale(a[rr], k)));  // i k sum
         }
+    }
+    if (in_regs && tid < ncoef) {
+#pragma unroll
+        for (int rr = 0; rr < NR; ++rr) Mb[rr * ncoef + tid] = cmuli(cscale(acc[rr], k));  // i k sum
     }
 }
 
@@ -612,60 +777,61 @@ __global__ void __launch_bounds__(256) k_p2m(int nleaf, int p, int CH, const int
 // y[perm[i]] = half * x[perm[i]] + y_near[i] + sum_{n,m} D_n^m R_n^m(c_i - C).
 template <int NR>
 __global__ void __launch_bounds__(64) k_l2p(int nleaf, int p, const int32_t *leaf_start, const double4 *center,
-                                            const double4 *ec, const double2 *Lc, double k, const double2 *ynear,
-                                            double half, const int32_t *perm, int64_t n, const double2 *x, double2 *y,
-                                            int has_far) {
+                                            const double4 *ec, const double2 *Lc, double k, const double *leg,
+                                            const double2 *ynear, double half, const int32_t *perm, int64_t n,
+                                            const double2 *x, double2 *y, int has_far) {
     extern __shared__ double jbuf[];
     const int b = blockIdx.x, tid = threadIdx.x;
     const double4 C = center[b];
     const int ts = leaf_start[b], te = leaf_start[b + 1];
     const double2 *D = Lc + (int64_t)b * NR * p * p;  // NR expansions of this leaf
-    const int pp = p * p;
-    double *jb = jbuf + tid * (p + 2);
+    const int pp = p * p, TB = p * (p + 1) / 2;
+    double *lt = jbuf;                        // 3 TB: Legendre recurrence table (degrees < p)
+    double *jb = jbuf + 3 * TB + tid * (p + 2);
+    if (has_far) {
+        for (int e = tid; e < 3 * TB; e += blockDim.x) lt[e] = leg[e];
+        __syncthreads();
+    }
     for (int t = ts + tid; t < te; t += 64) {
         double2 far[NR];
 #pragma unroll
         for (int rr = 0; rr < NR; ++rr) far[rr] = cmk(0, 0);
         if (has_far) {
-            double4 c = ec[t];
-            double r, ct, st, phi;
-            sph_coords(c.x - C.x, c.y - C.y, c.z - C.z, r, ct, st, phi);
-            sph_jn_seq(k * r, p - 1, jb);
-            double pmm = 1.0 / sqrt(4.0 * FMM_PI);
+            const double4 c = ec[t];
+            double r, ct, st;
+            double2 eph;
+            sph_frame(c.x - C.x, c.y - C.y, c.z - C.z, r, ct, st, eph);
+            bessel_j_seq(k * r, p - 1, jb);
+            double2 e = cmk(1.0, 0.0);
+            double sp = 1.0;
             for (int mp = 0; mp < p; ++mp) {
-                if (mp > 0) pmm *= sqrt((2.0 * mp + 1.0) / (2.0 * mp)) * st;
-                double s, co;
-                sincos(mp * phi, &s, &co);
-                double pm2 = 0.0, pm1 = pmm;
-                double2 sp[NR], sn[NR];
+                if (mp > 0) {
+                    e = cmul(e, eph);
+                    sp *= st;
+                }
+                double P1 = lt[3 * leg_tri(mp, mp) + 2] * sp, P2 = 0.0;
+                double2 sa[NR], sb[NR];
 #pragma unroll
-                for (int rr = 0; rr < NR; ++rr) sp[rr] = sn[rr] = cmk(0, 0);
+                for (int rr = 0; rr < NR; ++rr) sa[rr] = sb[rr] = cmk(0, 0);
                 for (int nn = mp; nn < p; ++nn) {
-                    double P;
-                    if (nn == mp) P = pmm;
-                    else if (nn == mp + 1) P = sqrt(2.0 * mp + 3.0) * ct * pmm;
-                    else {
-                        double a = sqrt((4.0 * nn * nn - 1.0) / ((double)nn * nn - (double)mp * mp));
-                        double bq = sqrt((((double)nn - 1) * (nn - 1) - (double)mp * mp) * (2.0 * nn + 1.0) /
-                                         ((2.0 * nn - 3.0) * ((double)nn * nn - (double)mp * mp)));
-                        P = a * ct * pm1 - bq * pm2;
+                    if (nn > mp) {
+                        const int q = leg_tri(nn, mp);
+                        const double P = fma(lt[3 * q] * ct, P1, -lt[3 * q + 1] * P2);
+                        P2 = P1;
+                        P1 = P;
                     }
-                    if (nn >= mp + 1) {
-                        pm2 = pm1;
-                        pm1 = P;
-                    }
-                    double R = jb[nn] * P;
+                    const double R = jb[nn] * P1;
 #pragma unroll
                     for (int rr = 0; rr < NR; ++rr) {
-                        sp[rr] = cadd(sp[rr], cscale(D[rr * pp + cidx(nn, mp)], R));
-                        if (mp > 0) sn[rr] = cadd(sn[rr], cscale(D[rr * pp + cidx(nn, -mp)], R));
+                        sa[rr] = cadd(sa[rr], cscale(D[rr * pp + cidx(nn, mp)], R));
+                        if (mp > 0) sb[rr] = cadd(sb[rr], cscale(D[rr * pp + cidx(nn, -mp)], R));
                     }
                 }
                 // sum_n D_n^m R e^{i m phi} + D_n^{-m} R e^{-i m phi}
 #pragma unroll
                 for (int rr = 0; rr < NR; ++rr) {
-                    far[rr] = cadd(far[rr], cmul(sp[rr], cmk(co, s)));
-                    if (mp > 0) far[rr] = cadd(far[rr], cmul(sn[rr], cmk(co, -s)));
+                    far[rr] = cfma(sa[rr], e, far[rr]);
+                    if (mp > 0) far[rr] = cfma(sb[rr], cconj(e), far[rr]);
                 }
             }
         }
@@ -825,9 +991,9 @@ __global__ void __launch_bounds__(64) k_p2p_n(int nleaf, const int32_t *leaf_sta
                         double d2 = dist2_exact(ct.x, ct.y, ct.z, sx[jj], sy[jj], sz[jj]);
                         if (d2 < rc2) continue;
                         const double dx = sx[jj] - ct.x, dy = sy[jj] - ct.y, dz = sz[jj] - ct.z;
-                        const double r = sqrt(d2), ir = 1.0 / r, ir2 = ir * ir;
+                        const double ir = rsq_nr(d2), r = d2 * ir, ir2 = ir * ir;
                         double s, c;
-                        sincos(k * r, &s, &c);
+                        sincos_red(k * r, s, c);
                         const double2 E = cmk(c * inv4pi, s * inv4pi);  // e^{ikr} / 4 pi
                         const double2 G = cscale(E, ir);
                         const double dny = dx * snx[jj] + dy * sny[jj] + dz * snz[jj];
@@ -893,7 +1059,8 @@ __global__ void k_local_derivs(int64_t nleaf, int p, const double2 *D, double k,
 __global__ void __launch_bounds__(64) k_l2p_n(int nleaf, int p, const int32_t *leaf_start, const double4 *center,
                                               const double4 *ec, const double4 *en, const double2 *Lc,
                                               const double2 *Dz, const double2 *Dp, const double2 *Dm, double k,
-                                              const double2 *ynear, const double2 *ynearn, const int32_t *perm,
+                                              const double *leg, const double2 *ynear, const double2 *ynearn,
+                                              const int32_t *perm,
                                               int64_t n, const double2 *x, const double2 *bm, const double2 *bp,
                                               double2 *y, int has_far) {
     extern __shared__ double jbuf[];
@@ -903,37 +1070,39 @@ __global__ void __launch_bounds__(64) k_l2p_n(int nleaf, int p, const int32_t *l
     const int q1 = (p + 1) * (p + 1);
     const double2 *D = Lc + (int64_t)b * p * p, *Ez = Dz + (int64_t)b * q1, *Ep = Dp + (int64_t)b * q1,
                   *Em = Dm + (int64_t)b * q1;
-    double *jb = jbuf + tid * (p + 3);
+    const int TB = (p + 1) * (p + 2) / 2;
+    double *lt = jbuf;  // 3 TB: Legendre recurrence table (degrees <= p)
+    double *jb = jbuf + 3 * TB + tid * (p + 3);
+    if (has_far) {
+        for (int e = tid; e < 3 * TB; e += blockDim.x) lt[e] = leg[e];
+        __syncthreads();
+    }
     for (int t = ts + tid; t < te; t += 64) {
         double2 far = cmk(0, 0), fz = cmk(0, 0), fp = cmk(0, 0), fm = cmk(0, 0);
         if (has_far) {
-            double4 c = ec[t];
-            double r, ct, st, phi;
-            sph_coords(c.x - C.x, c.y - C.y, c.z - C.z, r, ct, st, phi);
-            sph_jn_seq(k * r, p, jb);
-            double pmm = 1.0 / sqrt(4.0 * FMM_PI);
+            const double4 c = ec[t];
+            double r, ct, st;
+            double2 eph;
+            sph_frame(c.x - C.x, c.y - C.y, c.z - C.z, r, ct, st, eph);
+            bessel_j_seq(k * r, p, jb);
+            double2 e = cmk(1.0, 0.0);
+            double spw = 1.0;
             for (int mp = 0; mp <= p; ++mp) {
-                if (mp > 0) pmm *= sqrt((2.0 * mp + 1.0) / (2.0 * mp)) * st;
-                double s, co;
-                sincos(mp * phi, &s, &co);
-                double pm2 = 0.0, pm1 = pmm;
+                if (mp > 0) {
+                    e = cmul(e, eph);
+                    spw *= st;
+                }
+                double pm1 = lt[3 * leg_tri(mp, mp) + 2] * spw, pm2 = 0.0;
                 double2 sv[2] = {cmk(0, 0), cmk(0, 0)}, sz_[2] = {cmk(0, 0), cmk(0, 0)},
                         sp_[2] = {cmk(0, 0), cmk(0, 0)}, sm_[2] = {cmk(0, 0), cmk(0, 0)};
                 for (int nn = mp; nn <= p; ++nn) {
-                    double P;
-                    if (nn == mp) P = pmm;
-                    else if (nn == mp + 1) P = sqrt(2.0 * mp + 3.0) * ct * pmm;
-                    else {
-                        double a = sqrt((4.0 * nn * nn - 1.0) / ((double)nn * nn - (double)mp * mp));
-                        double bq = sqrt((((double)nn - 1) * (nn - 1) - (double)mp * mp) * (2.0 * nn + 1.0) /
-                                         ((2.0 * nn - 3.0) * ((double)nn * nn - (double)mp * mp)));
-                        P = a * ct * pm1 - bq * pm2;
-                    }
-                    if (nn >= mp + 1) {
+                    if (nn > mp) {
+                        const int q = leg_tri(nn, mp);
+                        const double P = fma(lt[3 * q] * ct, pm1, -lt[3 * q + 1] * pm2);
                         pm2 = pm1;
                         pm1 = P;
                     }
-                    const double R = jb[nn] * P;
+                    const double R = jb[nn] * pm1;
                     if (nn < p) {
                         sv[0] = cadd(sv[0], cscale(D[cidx(nn, mp)], R));
                         if (mp > 0) sv[1] = cadd(sv[1], cscale(D[cidx(nn, -mp)], R));
@@ -947,7 +1116,7 @@ __global__ void __launch_bounds__(64) k_l2p_n(int nleaf, int p, const int32_t *l
                         sm_[1] = cadd(sm_[1], cscale(Em[cidx(nn, -mp)], R));
                     }
                 }
-                const double2 ep = cmk(co, s), em = cmk(co, -s);
+                const double2 ep = e, em = cconj(e);
                 far = cadd(far, cmul(sv[0], ep));
                 fz = cadd(fz, cmul(sz_[0], ep));
                 fp = cadd(fp, cmul(sp_[0], ep));
@@ -1043,25 +1212,27 @@ void launch_p2p(int nr, bool fp32, int nleaf, const int32_t *leaf_start, const i
 
 size_t p2m_stage_bytes(int nr, int p) {
     const int TB = (p + 1) * (p + 2) / 2;
-    return (size_t)TB * 16 + (size_t)nr * 32 + (size_t)(p + 2) * 8 + 56;  // per staged source
+    return (size_t)(TB + 1) * 16 + (size_t)nr * 32 + (size_t)(p + 2) * 8 + 56;  // per staged source
 }
+size_t p2m_fixed_bytes(int p) { return (size_t)3 * (p + 1) * (p + 2) / 2 * sizeof(double); }
 
 void launch_p2m(int nr, int nleaf, int p, int CH, const int32_t *leaf_start, const double4 *center,
                 const double4 *ec, const double4 *en, const double2 *sigma, const double2 *mu, double k,
-                double2 *Mout, hipStream_t st) {
-    const size_t sh = (size_t)CH * p2m_stage_bytes(nr, p);
-#define P2M_CALL(R) k_p2m<R><<<nleaf, 256, sh, st>>>(nleaf, p, CH, leaf_start, center, ec, en, sigma, mu, k, Mout)
+                const double *leg, double2 *Mout, hipStream_t st) {
+    const size_t sh = (size_t)CH * p2m_stage_bytes(nr, p) + p2m_fixed_bytes(p);
+#define P2M_CALL(R) \
+    k_p2m<R><<<nleaf, 256, sh, st>>>(nleaf, p, CH, leaf_start, center, ec, en, sigma, mu, k, leg, Mout)
     FMM_NR_DISPATCH(nr, P2M_CALL)
 #undef P2M_CALL
     LAUNCH_OK();
 }
 
 void launch_l2p(int nr, int nleaf, int p, const int32_t *leaf_start, const double4 *center, const double4 *ec,
-                const double2 *Lc, double k, const double2 *ynear, double half, const int32_t *perm, int64_t n,
-                const double2 *x, double2 *y, int has_far, hipStream_t st) {
-    const size_t sh = (size_t)64 * (p + 2) * sizeof(double);
+                const double2 *Lc, double k, const double *leg, const double2 *ynear, double half,
+                const int32_t *perm, int64_t n, const double2 *x, double2 *y, int has_far, hipStream_t st) {
+    const size_t sh = ((size_t)64 * (p + 2) + (size_t)3 * p * (p + 1) / 2) * sizeof(double);
 #define L2P_CALL(R) \
-    k_l2p<R><<<nleaf, 64, sh, st>>>(nleaf, p, leaf_start, center, ec, Lc, k, ynear, half, perm, n, x, y, has_far)
+    k_l2p<R><<<nleaf, 64, sh, st>>>(nleaf, p, leaf_start, center, ec, Lc, k, leg, ynear, half, perm, n, x, y, has_far)
     FMM_NR_DISPATCH(nr, L2P_CALL)
 #undef L2P_CALL
     LAUNCH_OK();

@@ -2,9 +2,10 @@
 // preconditioner slot: identity, diagonal (the paper's indirect-BEM choice: a constant added to
 // the diagonal), or the exact inverse of the operator restricted to each octree leaf.
 //
-// Arnoldi uses classical Gram-Schmidt applied twice (CGS2): each pass is one batched set of
-// inner products (two-stage, fixed-order reductions, so runs are bitwise reproducible) and one
-// batched update.  Givens rotations and the small least-squares problem live on the host; one
+// Arnoldi uses classical Gram-Schmidt with a second pass when the first one cancelled most of the
+// new vector (norm drop below 1/sqrt(2), the Daniel-Gragg-Kaufman-Stewart test): each pass is one
+// batched set of inner products (two-stage, fixed-order reductions, so runs are bitwise
+// reproducible) and one batched update.  Givens rotations and the small least-squares problem live on the host; one
 // short host<->device copy per pass.
 #include <chrono>
 #include <functional>
@@ -343,13 +344,19 @@ int fgmres(int64_t n, hipStream_t st, DeviceBuffers &scr, const char *tag,
             precond(vj, zj);
             matvec(zj, w);
             ++iters;
-            // CGS2
+            // classical Gram-Schmidt, repeated only when the first pass removed most of w
+            // (|w| fell below |w_0|/sqrt(2): the Daniel-Gragg-Kaufman-Stewart criterion)
+            const double w0 = B.nrm(w);
             B.dots(V, n, j + 1, w, h1.data());
             B.sub_combo(V, n, j + 1, h1.data(), w);
-            B.dots(V, n, j + 1, w, h2.data());
-            B.sub_combo(V, n, j + 1, h2.data(), w);
-            for (int i = 0; i <= j; ++i) Hc(i, j) = cadd(h1[i], h2[i]);
             double hn = B.nrm(w);
+            if (!(hn > 0.7071067811865476 * w0)) {
+                B.dots(V, n, j + 1, w, h2.data());
+                B.sub_combo(V, n, j + 1, h2.data(), w);
+                for (int i = 0; i <= j; ++i) h1[i] = cadd(h1[i], h2[i]);
+                hn = B.nrm(w);
+            }
+            for (int i = 0; i <= j; ++i) Hc(i, j) = h1[i];
             if (!std::isfinite(hn)) return FMMBEM_ENAN;
             Hc(j + 1, j) = cmk(hn, 0);
             if (hn > 0) B.scale_copy(1.0 / hn, w, V + (size_t)(j + 1) * n);
@@ -505,12 +512,17 @@ int fgmres_batch(int64_t n, hipStream_t st, DeviceBuffers &scr, int nv,
             double2 *w = Sout + k * n;
             const int j = q.j;
             ++iters[s];
+            const double w0 = Bl.nrm(w);
             Bl.dots(q.V, n, j + 1, w, q.h1.data());
             Bl.sub_combo(q.V, n, j + 1, q.h1.data(), w);
-            Bl.dots(q.V, n, j + 1, w, q.h2.data());
-            Bl.sub_combo(q.V, n, j + 1, q.h2.data(), w);
-            for (int i = 0; i <= j; ++i) Hc(i, j) = cadd(q.h1[i], q.h2[i]);
-            const double hn = Bl.nrm(w);
+            double hn = Bl.nrm(w);
+            if (!(hn > 0.7071067811865476 * w0)) {  // second pass only when needed (as in fgmres)
+                Bl.dots(q.V, n, j + 1, w, q.h2.data());
+                Bl.sub_combo(q.V, n, j + 1, q.h2.data(), w);
+                for (int i = 0; i <= j; ++i) q.h1[i] = cadd(q.h1[i], q.h2[i]);
+                hn = Bl.nrm(w);
+            }
+            for (int i = 0; i <= j; ++i) Hc(i, j) = q.h1[i];
             if (!std::isfinite(hn)) {
                 status[s] = FMMBEM_ENAN;
                 q.done = true;
