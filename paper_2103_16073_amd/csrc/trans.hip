@@ -442,16 +442,18 @@ template <class R, int N> __device__ inline void load_row(R (&h)[N], cst_ptr<R> 
 #pragma unroll
     for (int v = 0; v < N; ++v) h[v] = row[v];
 }
-// acc_v += h_v x for a table row of RC values, read 16 at a time (bounded scalar registers)
+// acc_v += h_v x for a table row of RC values, read 16 (or 8) at a time (bounded scalar registers)
 template <class R, class C, int RC>
 __device__ inline void rot_fma_row(cst_ptr<R> row, C x, R (&ar)[RC], R (&ai)[RC]) {
+    constexpr int HS = RC % 16 == 0 ? 16 : 8;
+    static_assert(RC % HS == 0, "row chunks are multiples of 8");
 #pragma unroll
-    for (int h0 = 0; h0 < RC; h0 += 16) {
-        R h[16];
+    for (int h0 = 0; h0 < RC; h0 += HS) {
+        R h[HS];
 #pragma unroll
-        for (int v = 0; v < 16; ++v) h[v] = row[h0 + v];
+        for (int v = 0; v < HS; ++v) h[v] = row[h0 + v];
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
+        for (int v = 0; v < HS; ++v) {
             ar[h0 + v] = fma(h[v], x.x, ar[h0 + v]);
             ai[h0 + v] = fma(h[v], x.y, ai[h0 + v]);
         }
@@ -470,206 +472,296 @@ __device__ inline void coax_acc(const R (&t)[2 * RC], C x, R (&ar)[RC], R (&ai)[
 }
 static_assert(TABLE_PAD >= 32, "lane kernels read up to 31 entries past a table row");
 
+// XCD-aware block order.  Consecutive workgroups go to the 8 XCDs in turn, and each XCD has its own
+// L2; renumbering the (tile, split) grid so that each XCD takes one contiguous range of the
+// class-sorted tiles keeps every translation table in the L2 of one XCD (and in the scalar caches
+// of the waves that work through that range together).  A bijection of [0, gridDim.x gridDim.y).
+constexpr unsigned NXCD = 8;
+__device__ inline void xcd_block(int &tile, int &split) {
+    const unsigned nx = gridDim.x, ny = gridDim.y, n = nx * ny;
+    const unsigned L = blockIdx.x + blockIdx.y * nx;
+    const unsigned x = L % NXCD, l = L / NXCD, q = n / NXCD, r = n % NXCD;
+    const unsigned p = x * q + min(x, r) + l;
+    tile = (int)(p / ny);
+    split = (int)(p % ny);
+}
+
 // Intermediate rows of lane batches are tile-interleaved: coefficient c of virtual job J at
 // ((J / 64) P^2 + c) 64 + J % 64, so that a wavefront's 64 lanes touch 64 consecutive values.
 __device__ inline int64_t tl_idx(int64_t J, int c, int P2) { return ((J >> 6) * P2 + c) * LANE_JT + (J & 63); }
+
+// Output rows are produced in chunks of RCK rows per lane (accumulators in registers).  The chunk
+// size is picked per degree (per order in the coaxial step) as the smallest of 8, 16, 24, 32 (4, 8,
+// 12, 16) rows that covers the rows left, so that few FMAs fall on rows past the degree.
+#define TL_ROT_CHUNK(rem, CALL)                                                       \
+    if ((rem) <= 8) CALL(8); else if ((rem) <= 16) CALL(16); else if ((rem) <= 24) CALL(24); \
+    else CALL(32)
+#define TL_COAX_CHUNK(rem, CALL) \
+    if ((rem) <= 4) CALL(4); else if ((rem) <= 8) CALL(8); else if ((rem) <= 12) CALL(12); else CALL(16)
 
 // Forward rotation: sources (box-major) -> W1 (interleaved).  The degree-n slices are staged
 // through LDS 8 columns at a time: one load instruction reads 8 jobs x 8 consecutive
 // coefficients, i.e. whole 128-byte lines (a lane reading its own row alone would fetch each
 // line for 16 bytes once the wave's 64 rows no longer fit L1).
-template <class R, int RC, bool PF>
+constexpr int TL_CW = 8;
+template <class R, int RCK, bool PF>
+__device__ inline void tl_rot_fwd_chunk(const TransArgsT<R> &a, typename Cx<R>::T (*S)[TL_CW + 1], const int64_t *soff,
+                                        const int32_t *sdir, const R *Hn, int n, int w, int r0, int64_t J, bool live,
+                                        int P2, int lane) {
+    using C = typename Cx<R>::T;
+    const int sj = lane >> 3, sq = lane & 7;  // staging: job sj + 8 i, column sq
+    R ar[RCK], ai[RCK];
+#pragma unroll
+    for (int v = 0; v < RCK; ++v) ar[v] = ai[v] = 0;
+    for (int c0 = 0; c0 < w; c0 += TL_CW) {
+        const int cw = min(TL_CW, w - c0);
+        __syncthreads();
+        if (sq < cw) {
+            const int c = c0 + sq;
+#pragma unroll
+            for (int i0 = 0; i0 < LANE_JT / 8; i0 += 4) {
+                C xs[4], ps[4];  // four jobs' loads in flight before the first use
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int j = sj + 8 * (i0 + i);
+                    xs[i] = a.src[soff[j] + n * n + c];
+                    ps[i] = a.ph[sdir[j] + c - n];
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) S[sj + 8 * (i0 + i)][sq] = mulc(ps[i], xs[i]);  // e^{i m a} c_n^m
+            }
+        }
+        __syncthreads();
+        // rows past w read the next table entries (TABLE_PAD spare); never stored.  With PF the
+        // next table row is loaded before the current one is used.
+        if (PF) {
+            R h[RCK];
+            load_row<R, RCK>(h, as_cst(Hn, c0 * w + r0));
+            for (int q = 0; q < cw; ++q) {
+                const C xv = S[lane][q];
+                R hn[RCK];
+                load_row<R, RCK>(hn, as_cst(Hn, (c0 + q + 1) * w + r0));  // spare-padded
+#pragma unroll
+                for (int v = 0; v < RCK; ++v) {
+                    ar[v] = fma(h[v], xv.x, ar[v]);
+                    ai[v] = fma(h[v], xv.y, ai[v]);
+                }
+#pragma unroll
+                for (int v = 0; v < RCK; ++v) h[v] = hn[v];
+            }
+        } else {
+            for (int q = 0; q < cw; ++q) {
+                const C xv = S[lane][q];
+                rot_fma_row<R, C, RCK>(as_cst(Hn, (c0 + q) * w + r0), xv, ar, ai);
+            }
+        }
+    }
+    if (live) {
+#pragma unroll
+        for (int v = 0; v < RCK; ++v)
+            if (r0 + v < w) a.W1[tl_idx(J, n * n + r0 + v, P2)] = mkc<C>(ar[v], ai[v]);
+    }
+}
+
+template <class R, bool PF>
 __global__ void __launch_bounds__(64) k_tl_rot_fwd(TransArgsT<R> a, int nsplit) {
     using C = typename Cx<R>::T;
-    constexpr int CW = 8;
-    __shared__ C S[LANE_JT][CW + 1];
+    __shared__ C S[LANE_JT][TL_CW + 1];
     __shared__ int64_t soff[LANE_JT];
     __shared__ int32_t sdir[LANE_JT];
     const int lane = threadIdx.x;
-    const int64_t J0 = (int64_t)blockIdx.x * LANE_JT, J = J0 + lane;
+    int tile, split;
+    xcd_block(tile, split);
+    const int64_t J0 = (int64_t)tile * LANE_JT, J = J0 + lane;
     const bool live = J < a.njob;
     const int64_t Jc = live ? J : a.njob - 1;
     const int P2 = a.P * a.P, phs = 2 * a.PH + 1, ps2 = a.psrc * a.psrc;
     soff[lane] = src_row(a, Jc) * ps2;
     sdir[lane] = a.jdir[Jc / a.nr] * phs + a.PH;
-    const int tr = __builtin_amdgcn_readfirstlane(a.tile_rot[blockIdx.x / a.nr]);
+    const int tr = __builtin_amdgcn_readfirstlane(a.tile_rot[tile / a.nr]);
     const R *Hb = a.HT + (int64_t)tr * rot_table_size(a.P);
-    const int sj = lane >> 3, sq = lane & 7;  // staging: job sj + 8 i, column sq
-    for (int n = blockIdx.y; n < a.psrc; n += nsplit) {
+    for (int n = split; n < a.psrc; n += nsplit) {
         const int w = 2 * n + 1;
         const R *Hn = Hb + rot_block_off(n);  // HT: row c holds column c of H
-        for (int r0 = 0; r0 < w; r0 += RC) {
-            R ar[RC], ai[RC];
-#pragma unroll
-            for (int v = 0; v < RC; ++v) ar[v] = ai[v] = 0;
-            for (int c0 = 0; c0 < w; c0 += CW) {
-                const int cw = min(CW, w - c0);
-                __syncthreads();
-                if (sq < cw) {
-                    const int c = c0 + sq;
-#pragma unroll
-                    for (int i0 = 0; i0 < LANE_JT / 8; i0 += 4) {
-                        C xs[4], ps[4];  // four jobs' loads in flight before the first use
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            const int j = sj + 8 * (i0 + i);
-                            xs[i] = a.src[soff[j] + n * n + c];
-                            ps[i] = a.ph[sdir[j] + c - n];
-                        }
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) S[sj + 8 * (i0 + i)][sq] = mulc(ps[i], xs[i]);  // e^{i m a} c_n^m
-                    }
-                }
-                __syncthreads();
-                // rows past w read the next table entries (TABLE_PAD spare); never stored.  With PF
-                // the next table row is loaded before the current one is used (two rows of RC
-                // values must then fit the scalar registers).
-                if (PF) {
-                    R h[RC];
-                    load_row<R, RC>(h, as_cst(Hn, c0 * w + r0));
-                    for (int q = 0; q < cw; ++q) {
-                        const C xv = S[lane][q];
-                        R hn[RC];
-                        load_row<R, RC>(hn, as_cst(Hn, (c0 + q + 1) * w + r0));  // spare-padded
-#pragma unroll
-                        for (int v = 0; v < RC; ++v) {
-                            ar[v] = fma(h[v], xv.x, ar[v]);
-                            ai[v] = fma(h[v], xv.y, ai[v]);
-                        }
-#pragma unroll
-                        for (int v = 0; v < RC; ++v) h[v] = hn[v];
-                    }
-                } else {
-                    for (int q = 0; q < cw; ++q) {
-                        const C xv = S[lane][q];
-                        rot_fma_row<R, C, RC>(as_cst(Hn, (c0 + q) * w + r0), xv, ar, ai);
-                    }
-                }
-            }
-            if (live) {
-#pragma unroll
-                for (int v = 0; v < RC; ++v)
-                    if (r0 + v < w) a.W1[tl_idx(J, n * n + r0 + v, P2)] = mkc<C>(ar[v], ai[v]);
-            }
+        for (int r0 = 0; r0 < w; r0 += 32) {
+#define TL_FWD(K) tl_rot_fwd_chunk<R, K, PF>(a, S, soff, sdir, Hn, n, w, r0, J, live, P2, lane)
+            TL_ROT_CHUNK(w - r0, TL_FWD);
+#undef TL_FWD
         }
     }
 }
 
 // Back rotation: W2 (interleaved) -> W1 (job-major, for the per-target reduction), through an
-// LDS transpose RC rows at a time.
-template <class R, int RC, bool PF>
-__global__ void __launch_bounds__(64) k_tl_rot_back(TransArgsT<R> a, int nsplit) {
+// LDS transpose 8 rows at a time.  With one block per tile (nsplit == 1) the outputs come in
+// increasing coefficient order; in FP64 they pass through a ring of RING coefficients per job and
+// leave in whole 128-byte lines (G coefficients), so no line of the job-major rows is written in
+// parts (in FP32 the ring measured slower and its LDS would cost occupancy).
+template <class R> struct TlRing {
     using C = typename Cx<R>::T;
-    constexpr int OT = 8;  // rows per transpose (small LDS footprint keeps occupancy)
-    // With one block per tile (nsplit == 1) the outputs come in increasing coefficient order; they
-    // pass through a ring of RING coefficients per job and leave in whole 128-byte lines (G
-    // coefficients), so no line of the job-major rows is written in parts.
-    // (FP64 only: in FP32 the ring measured slower and its LDS would cost occupancy)
-    constexpr bool RING_OK = sizeof(R) == 8;
-    constexpr int G = 128 / sizeof(C), RING = 16, OW = RING_OK ? RING : OT;
-    static_assert(!RING_OK || G + OT <= RING, "ring too small for a pending line and a transpose group");
-    __shared__ C O[LANE_JT][OW + 1];
-    const bool ordered = RING_OK && nsplit == 1;
-    int base = 0, cnext = 0;  // first coefficient not yet stored; next coefficient to be produced
-    const int lane = threadIdx.x;
-    const int64_t J0 = (int64_t)blockIdx.x * LANE_JT, J = J0 + lane;
-    const int64_t Jc = J < a.njob ? J : a.njob - 1;
-    const int P2 = a.P * a.P, phs = 2 * a.PH + 1;
-    const int nlive = (int)min((int64_t)LANE_JT, a.njob - J0);
-    const int tr = __builtin_amdgcn_readfirstlane(a.tile_rot[blockIdx.x / a.nr]);
-    const R *Hb = a.H + (int64_t)tr * rot_table_size(a.P);
-    const C *ph = a.ph + (int64_t)a.jdir[Jc / a.nr] * phs + a.PH;
-    for (int n = blockIdx.y; n < a.ptgt; n += nsplit) {
-        const int w = 2 * n + 1;
-        const R *Hn = Hb + rot_block_off(n);  // (H^T y)_r = sum_c H[c][r] y_c: row c of H
-        for (int r0 = 0; r0 < w; r0 += RC) {
-            R ar[RC], ai[RC];
+    static constexpr bool ON = sizeof(R) == 8;
+    static constexpr int OT = 8, G = 128 / sizeof(C), RING = 16, OW = ON ? RING : OT;
+    static_assert(!ON || G + OT <= RING, "ring too small for a pending line and a transpose group");
+};
+template <class R, int RCK, bool PF>
+__device__ inline void tl_rot_back_chunk(const TransArgsT<R> &a, typename Cx<R>::T (*O)[TlRing<R>::OW + 1], const R *Hn,
+                                         const typename Cx<R>::T *ph, int n, int w, int r0, int64_t J0, int64_t Jc,
+                                         int nlive, int P2, int lane, bool ordered, int &base, int &cnext) {
+    using C = typename Cx<R>::T;
+    using RG = TlRing<R>;
+    R ar[RCK], ai[RCK];
 #pragma unroll
-            for (int v = 0; v < RC; ++v) ar[v] = ai[v] = 0;
-            C xv = a.W2[tl_idx(Jc, n * n, P2)];
-            if (PF) {
-                R h[RC];
-                load_row<R, RC>(h, as_cst(Hn, r0));
-                for (int c = 0; c < w; ++c) {
-                    // next table row and next input value first (spare-padded table, clamped index)
-                    R hn[RC];
-                    load_row<R, RC>(hn, as_cst(Hn, (c + 1) * w + r0));
-                    const C xn = a.W2[tl_idx(Jc, n * n + min(c + 1, w - 1), P2)];
+    for (int v = 0; v < RCK; ++v) ar[v] = ai[v] = 0;
+    if (PF) {
+        C xv = a.W2[tl_idx(Jc, n * n, P2)];
+        R h[RCK];
+        load_row<R, RCK>(h, as_cst(Hn, r0));
+        for (int c = 0; c < w; ++c) {
+            // next table row and next input value first (spare-padded table, clamped index)
+            R hn[RCK];
+            load_row<R, RCK>(hn, as_cst(Hn, (c + 1) * w + r0));
+            const C xn = a.W2[tl_idx(Jc, n * n + min(c + 1, w - 1), P2)];
 #pragma unroll
-                    for (int v = 0; v < RC; ++v) {
-                        ar[v] = fma(h[v], xv.x, ar[v]);
-                        ai[v] = fma(h[v], xv.y, ai[v]);
-                    }
-#pragma unroll
-                    for (int v = 0; v < RC; ++v) h[v] = hn[v];
-                    xv = xn;
-                }
-            } else {
-                for (int c = 0; c < w; ++c) {
-                    const C xn = a.W2[tl_idx(Jc, n * n + min(c + 1, w - 1), P2)];
-                    rot_fma_row<R, C, RC>(as_cst(Hn, c * w + r0), xv, ar, ai);
-                    xv = xn;
-                }
+            for (int v = 0; v < RCK; ++v) {
+                ar[v] = fma(h[v], xv.x, ar[v]);
+                ai[v] = fma(h[v], xv.y, ai[v]);
             }
-            // transpose to job-major rows OT rows at a time
 #pragma unroll
-            for (int h0 = 0; h0 < RC; h0 += OT) {
-                const int rc = min(OT, w - r0 - h0);
-                if (rc <= 0) break;
-                const int c0 = n * n + r0 + h0;
-                __syncthreads();
+            for (int v = 0; v < RCK; ++v) h[v] = hn[v];
+            xv = xn;
+        }
+    } else {
+        C xv = a.W2[tl_idx(Jc, n * n, P2)];
+        for (int c = 0; c < w; ++c) {
+            const C xn = a.W2[tl_idx(Jc, n * n + min(c + 1, w - 1), P2)];
+            rot_fma_row<R, C, RCK>(as_cst(Hn, c * w + r0), xv, ar, ai);
+            xv = xn;
+        }
+    }
+    // transpose to job-major rows OT rows at a time
 #pragma unroll
-                for (int v = 0; v < OT; ++v)
-                    if (v < rc) {
-                        const C val = mulcc(mkc<C>(ar[h0 + v], ai[h0 + v]), ph[r0 + h0 + v - n]);  // e^{-i m a}
-                        O[lane][ordered ? (c0 + v) % RING : v] = val;
-                    }
-                __syncthreads();
-                if (ordered) {
-                    cnext = c0 + rc;
-                    while (cnext - base >= G) {  // one store instruction: 64/G jobs x one whole line
-                        const int q = lane % G;
+    for (int h0 = 0; h0 < RCK; h0 += RG::OT) {
+        const int rc = min(RG::OT, w - r0 - h0);
+        if (rc <= 0) break;
+        const int c0 = n * n + r0 + h0;
+        __syncthreads();
 #pragma unroll
-                        for (int i = 0; i < G; ++i) {
-                            const int j = lane / G + (64 / G) * i;
-                            if (j < nlive) a.W1[(J0 + j) * (int64_t)P2 + base + q] = O[j][(base + q) % RING];
-                        }
-                        base += G;
-                    }
-                } else {
-                    // one store instruction: 8 jobs x 8 consecutive coefficients
-                    const int q = lane & 7;
-                    if (q < rc) {
+        for (int v = 0; v < RG::OT; ++v)
+            if (v < rc) {
+                const C val = mulcc(mkc<C>(ar[h0 + v], ai[h0 + v]), ph[r0 + h0 + v - n]);  // e^{-i m a}
+                O[lane][ordered ? (c0 + v) % RG::RING : v] = val;
+            }
+        __syncthreads();
+        if (ordered) {
+            cnext = c0 + rc;
+            while (cnext - base >= RG::G) {  // one store instruction: 64/G jobs x one whole line
+                const int q = lane % RG::G;
 #pragma unroll
-                        for (int i = 0; i < LANE_JT / 8; ++i) {
-                            const int j = (lane >> 3) + 8 * i;
-                            if (j < nlive) a.W1[(J0 + j) * (int64_t)P2 + c0 + q] = O[j][q];
-                        }
-                    }
+                for (int i = 0; i < RG::G; ++i) {
+                    const int j = lane / RG::G + (64 / RG::G) * i;
+                    if (j < nlive) a.W1[(J0 + j) * (int64_t)P2 + base + q] = O[j][(base + q) % RG::RING];
+                }
+                base += RG::G;
+            }
+        } else {
+            // one store instruction: 8 jobs x 8 consecutive coefficients
+            const int q = lane & 7;
+            if (q < rc) {
+#pragma unroll
+                for (int i = 0; i < LANE_JT / 8; ++i) {
+                    const int j = (lane >> 3) + 8 * i;
+                    if (j < nlive) a.W1[(J0 + j) * (int64_t)P2 + c0 + q] = O[j][q];
                 }
             }
         }
     }
+}
+
+template <class R, bool PF>
+__global__ void __launch_bounds__(64) k_tl_rot_back(TransArgsT<R> a, int nsplit) {
+    using C = typename Cx<R>::T;
+    using RG = TlRing<R>;
+    __shared__ C O[LANE_JT][RG::OW + 1];
+    const bool ordered = RG::ON && nsplit == 1;
+    int base = 0, cnext = 0;  // first coefficient not yet stored; next coefficient to be produced
+    const int lane = threadIdx.x;
+    int tile, split;
+    xcd_block(tile, split);
+    const int64_t J0 = (int64_t)tile * LANE_JT, J = J0 + lane;
+    const int64_t Jc = J < a.njob ? J : a.njob - 1;
+    const int P2 = a.P * a.P, phs = 2 * a.PH + 1;
+    const int nlive = (int)min((int64_t)LANE_JT, a.njob - J0);
+    const int tr = __builtin_amdgcn_readfirstlane(a.tile_rot[tile / a.nr]);
+    const R *Hb = a.H + (int64_t)tr * rot_table_size(a.P);
+    const C *ph = a.ph + (int64_t)a.jdir[Jc / a.nr] * phs + a.PH;
+    for (int n = split; n < a.ptgt; n += nsplit) {
+        const int w = 2 * n + 1;
+        const R *Hn = Hb + rot_block_off(n);  // (H^T y)_r = sum_c H[c][r] y_c: row c of H
+        for (int r0 = 0; r0 < w; r0 += 32) {
+#define TL_BACK(K) tl_rot_back_chunk<R, K, PF>(a, O, Hn, ph, n, w, r0, J0, Jc, nlive, P2, lane, ordered, base, cnext)
+            TL_ROT_CHUNK(w - r0, TL_BACK);
+#undef TL_BACK
+        }
+    }
     if (ordered && cnext > base) {  // the last, partial line
         const int cnt = cnext - base;
-        for (int e = lane; e < nlive * G; e += LANE_JT) {
-            const int j = e / G, q = e % G;
-            if (q < cnt) a.W1[(J0 + j) * (int64_t)P2 + base + q] = O[j][(base + q) % RING];
+        for (int e = lane; e < nlive * RG::G; e += LANE_JT) {
+            const int j = e / RG::G, q = e % RG::G;
+            if (q < cnt) a.W1[(J0 + j) * (int64_t)P2 + base + q] = O[j][(base + q) % RG::RING];
         }
     }
 }
 
 // Coaxial step: W1 (interleaved) -> W2 (interleaved), fully coalesced.
-template <class R, int RC, bool PF>
+template <class R, int RCK, bool PF>
+__device__ inline void tl_coax_chunk(const TransArgsT<R> &a, const typename Cx<R>::T *Tm, int m, int am, int rows,
+                                     int cin, int B, int r0, int64_t J, int64_t Jc, bool live, int P2) {
+    using C = typename Cx<R>::T;
+    R ar[RCK], ai[RCK];
+#pragma unroll
+    for (int v = 0; v < RCK; ++v) ar[v] = ai[v] = 0;
+    // (E|F)_{n' n} = (-1)^{n+n'} (E|F)_{n n'}: row n of the block, entries n'; rows past `rows`
+    // read spare table entries (TABLE_PAD) and are never stored.  The sign is fixed per unrolled
+    // row for each parity of q + r0, so it folds into the FMAs.
+    R t[2 * RCK];
+    load_row<R, 2 * RCK>(t, as_cst((const R *)Tm, 2 * (int64_t)r0));
+    int n = am;
+    C xv = a.W1[tl_idx(Jc, n * n + n + m, P2)];
+    for (int q = 0; q < cin; ++q, ++n) {
+        R tn[PF ? 2 * RCK : 1];
+        if (PF) load_row<R, PF ? 2 * RCK : 1>(tn, as_cst((const R *)Tm, 2 * ((int64_t)(q + 1) * B + r0)));
+        const int nn1 = min(n + 1, a.psrc - 1);
+        const C xn = a.W1[tl_idx(Jc, nn1 * nn1 + nn1 + m, P2)];
+        if (((q + r0) & 1) == 0) coax_acc<R, C, RCK, false>(t, xv, ar, ai);
+        else coax_acc<R, C, RCK, true>(t, xv, ar, ai);
+        if (PF) {
+#pragma unroll
+            for (int v = 0; v < 2 * RCK; ++v) t[v] = tn[PF ? v : 0];
+        } else if (q + 1 < cin) {
+            load_row<R, 2 * RCK>(t, as_cst((const R *)Tm, 2 * ((int64_t)(q + 1) * B + r0)));
+        }
+        xv = xn;
+    }
+    if (live) {
+#pragma unroll
+        for (int v = 0; v < RCK; ++v) {
+            const int nn = am + r0 + v;
+            if (r0 + v < rows) a.W2[tl_idx(J, nn * nn + nn + m, P2)] = mkc<C>(ar[v], ai[v]);
+        }
+    }
+}
+
+template <class R, bool PF>
 __global__ void __launch_bounds__(64) k_tl_coax(TransArgsT<R> a, int nsplit) {
     using C = typename Cx<R>::T;
-    const int64_t J = (int64_t)blockIdx.x * LANE_JT + threadIdx.x;
+    int tile, split;
+    xcd_block(tile, split);
+    const int64_t J = (int64_t)tile * LANE_JT + threadIdx.x;
     const bool live = J < a.njob;
     const int64_t Jc = live ? J : a.njob - 1;
     const int P2 = a.P * a.P, pt = a.ptgt, pm = min(a.psrc, a.ptgt);
-    const int tc = __builtin_amdgcn_readfirstlane(a.tile_coax[blockIdx.x / a.nr]);
+    const int tc = __builtin_amdgcn_readfirstlane(a.tile_coax[tile / a.nr]);
     const C *T = a.coax + (int64_t)tc * coax_table_size(a.PT);
-    for (int mi = blockIdx.y; mi < 2 * pt - 1; mi += nsplit) {
+    for (int mi = split; mi < 2 * pt - 1; mi += nsplit) {
         const int m = mi - (pt - 1), am = m < 0 ? -m : m;
         const int rows = pt - am;
         if (am >= pm) {  // no source of this order
@@ -682,39 +774,10 @@ __global__ void __launch_bounds__(64) k_tl_coax(TransArgsT<R> a, int nsplit) {
         }
         const int B = a.PT - am, cin = a.psrc - am;
         const C *Tm = T + coax_block_off(a.PT, am);
-        for (int r0 = 0; r0 < rows; r0 += RC) {
-            R ar[RC], ai[RC];
-#pragma unroll
-            for (int v = 0; v < RC; ++v) ar[v] = ai[v] = 0;
-            // (E|F)_{n' n} = (-1)^{n+n'} (E|F)_{n n'}: row n of the block, entries n'; rows past
-            // `rows` read spare table entries (TABLE_PAD) and are never stored.  The sign is fixed
-            // per unrolled row for each parity of q + r0, so it folds into the FMAs.
-            R t[2 * RC];
-            load_row<R, 2 * RC>(t, as_cst((const R *)Tm, 2 * (int64_t)r0));
-            int n = am;
-            C xv = a.W1[tl_idx(Jc, n * n + n + m, P2)];
-            for (int q = 0; q < cin; ++q, ++n) {
-                R tn[PF ? 2 * RC : 1];
-                if (PF) load_row<R, PF ? 2 * RC : 1>(tn, as_cst((const R *)Tm, 2 * ((int64_t)(q + 1) * B + r0)));
-                const int nn1 = min(n + 1, a.psrc - 1);
-                const C xn = a.W1[tl_idx(Jc, nn1 * nn1 + nn1 + m, P2)];
-                if (((q + r0) & 1) == 0) coax_acc<R, C, RC, false>(t, xv, ar, ai);
-                else coax_acc<R, C, RC, true>(t, xv, ar, ai);
-                if (PF) {
-#pragma unroll
-                    for (int v = 0; v < 2 * RC; ++v) t[v] = tn[PF ? v : 0];
-                } else if (q + 1 < cin) {
-                    load_row<R, 2 * RC>(t, as_cst((const R *)Tm, 2 * ((int64_t)(q + 1) * B + r0)));
-                }
-                xv = xn;
-            }
-            if (live) {
-#pragma unroll
-                for (int v = 0; v < RC; ++v) {
-                    const int nn = am + r0 + v;
-                    if (r0 + v < rows) a.W2[tl_idx(J, nn * nn + nn + m, P2)] = mkc<C>(ar[v], ai[v]);
-                }
-            }
+        for (int r0 = 0; r0 < rows; r0 += 16) {
+#define TL_CX(K) tl_coax_chunk<R, K, PF>(a, Tm, m, am, rows, cin, B, r0, J, Jc, live, P2)
+            TL_COAX_CHUNK(rows - r0, TL_CX);
+#undef TL_CX
         }
     }
 }
@@ -794,15 +857,15 @@ const char *trans_stage(const TransBatch &b, const TransTables<R> &tb, int stage
         const int nd = stage == 1 ? 2 * b.ptgt - 1 : (stage == 0 ? b.psrc : b.ptgt);
         const int ns = (int)std::max<int64_t>(1, std::min<int64_t>(nd, (4096 + ntile - 1) / std::max(1u, ntile)));
         const dim3 grid(ntile, ns);
-        // Row chunks: 32 rows for the rotations (a whole degree up to p = 16) and 16 for the
-        // coaxial step (a whole order up to p = 16), so that the inputs are read once per degree
-        // or order; FP32 rows are small enough to double-buffer the table in scalar registers.
+        // Row chunks of up to 32 rows for the rotations (a whole degree up to p = 16) and 16 for
+        // the coaxial step (a whole order up to p = 16), so that the inputs are read once per
+        // degree or order; FP32 rows are small enough to double-buffer the table in scalar registers.
         constexpr bool PF = sizeof(R) == 4;
         switch (stage) {
-        case 0: k_tl_rot_fwd<R, 32, PF><<<grid, 64, 0, st>>>(a, ns), name = f32 ? "k_tl_rot_fwd_f32" : "k_tl_rot_fwd"; break;
-        case 1: k_tl_coax<R, 16, PF><<<grid, 64, 0, st>>>(a, ns), name = f32 ? "k_tl_coax_f32" : "k_tl_coax"; break;
+        case 0: k_tl_rot_fwd<R, PF><<<grid, 64, 0, st>>>(a, ns), name = f32 ? "k_tl_rot_fwd_f32" : "k_tl_rot_fwd"; break;
+        case 1: k_tl_coax<R, PF><<<grid, 64, 0, st>>>(a, ns), name = f32 ? "k_tl_coax_f32" : "k_tl_coax"; break;
         default:
-            k_tl_rot_back<R, 32, PF><<<grid, 64, 0, st>>>(a, ns), name = f32 ? "k_tl_rot_back_f32" : "k_tl_rot_back";
+            k_tl_rot_back<R, PF><<<grid, 64, 0, st>>>(a, ns), name = f32 ? "k_tl_rot_back_f32" : "k_tl_rot_back";
         }
         LAUNCH_OK();
         return name;
