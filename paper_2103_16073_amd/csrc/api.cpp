@@ -278,16 +278,33 @@ static void layout_batch(fmmbem_ctx *c, const std::string &name, const std::vect
         q = e;
     }
     b.njob = (int64_t)s.size();
-    // jobs of every target (CSR over the padded order)
+    // lane batches: runs of one target within SEG_ALIGN-job blocks (jobs of a class are sorted
+    // by target); the back rotation sums each run into its first job's row
+    std::vector<int8_t> seg;
+    if (b.lane) {
+        seg.assign(t.size(), 0);
+        for (size_t q2 = 0; q2 < t.size();) {
+            size_t e = q2 + 1;
+            if (t[q2] >= 0)
+                while (e < t.size() && e % SEG_ALIGN != 0 && t[e] == t[q2]) ++e;
+            if (t[q2] >= 0) seg[q2] = (int8_t)(e - q2);
+            q2 = e;
+        }
+        b.seg = upload(c->buf, name + "_seg", seg, st);
+    } else {
+        b.seg = nullptr;
+    }
+    // rows of every target (CSR over the padded order): every job, or the first job of each run
     {
         std::vector<int32_t> ts(ntgt + 1, 0), tj;
-        for (int32_t v : t)
-            if (v >= 0) ts[v + 1]++;
+        auto listed = [&](size_t q2) { return t[q2] >= 0 && (!b.lane || seg[q2] > 0); };
+        for (size_t q2 = 0; q2 < t.size(); ++q2)
+            if (listed(q2)) ts[t[q2] + 1]++;
         for (int64_t q2 = 0; q2 < ntgt; ++q2) ts[q2 + 1] += ts[q2];
         tj.resize(ts[ntgt]);
         std::vector<int32_t> fill(ts.begin(), ts.end() - 1);
         for (size_t q2 = 0; q2 < t.size(); ++q2)
-            if (t[q2] >= 0) tj[fill[t[q2]]++] = (int32_t)q2;
+            if (listed(q2)) tj[fill[t[q2]]++] = (int32_t)q2;
         b.tgt_start = upload(c->buf, name + "_tstart", ts, st);
         b.tgt_jobs = upload(c->buf, name + "_tjobs", tj, st);
     }

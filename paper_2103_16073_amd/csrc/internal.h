@@ -125,7 +125,14 @@ struct TransBatch {
     int lane = 0;                                       // one job per lane, 64-job tiles (many jobs per class)
     int64_t ntgt = 0;                                   // target boxes
     int32_t *tgt_start = nullptr, *tgt_jobs = nullptr;  // jobs of each target (CSR, padded job indices)
+    // lane batches: consecutive jobs of one class with one target form a run (never crossing a
+    // 16-job boundary); seg[j] = run length at the run's first job, 0 elsewhere.  The back
+    // rotation stores each run's sum in the first job's row and the CSR lists first jobs only.
+    int8_t *seg = nullptr;
 };
+// runs of the back-rotation output never cross a multiple of this many (real) jobs, so that a
+// run lies in one 64-lane tile for 1, 2 or 4 right-hand sides
+constexpr int SEG_ALIGN = 16;
 // one translation job before tiling
 struct JobH {
     int32_t src, tgt;

@@ -41,6 +41,7 @@ struct TransArgsT {
     const R *H, *HT;            // rotation tables (rot_table_size(P) each) and their transposes
     const C *ph;                // e^{i m a} per direction, 2*PH+1 per direction
     C *W1, *W2;                 // work rows, P^2 per job
+    const int8_t *jseg;         // lane batches: run length at the first job of a run, else 0
 };
 
 constexpr int RJ = 4, RR = 4;
@@ -602,10 +603,17 @@ template <class R> struct TlRing {
     static constexpr int OT = 8, G = 128 / sizeof(C), RING = 16, OW = ON ? RING : OT;
     static_assert(!ON || G + OT <= RING, "ring too small for a pending line and a transpose group");
 };
+// sum of column q of lanes j, j + nr, ..., j + (len-1) nr (one run of a target, one vector)
+template <class C, int W>
+__device__ inline C run_sum(C (*O)[W], int j, int len, int nr, int q) {
+    C v = O[j][q];
+    for (int k = 1; k < len; ++k) v = addc(v, O[j + k * nr][q]);
+    return v;
+}
 template <class R, int RCK, bool PF>
 __device__ inline void tl_rot_back_chunk(const TransArgsT<R> &a, typename Cx<R>::T (*O)[TlRing<R>::OW + 1], const R *Hn,
                                          const typename Cx<R>::T *ph, int n, int w, int r0, int64_t J0, int64_t Jc,
-                                         int nlive, int P2, int lane, bool ordered, int &base, int &cnext) {
+                                         const int *segl, int P2, int lane, bool ordered, int &base, int &cnext) {
     using C = typename Cx<R>::T;
     using RG = TlRing<R>;
     R ar[RCK], ai[RCK];
@@ -658,7 +666,8 @@ __device__ inline void tl_rot_back_chunk(const TransArgsT<R> &a, typename Cx<R>:
 #pragma unroll
                 for (int i = 0; i < RG::G; ++i) {
                     const int j = lane / RG::G + (64 / RG::G) * i;
-                    if (j < nlive) a.W1[(J0 + j) * (int64_t)P2 + base + q] = O[j][(base + q) % RG::RING];
+                    const int len = segl[j];
+                    if (len > 0) a.W1[(J0 + j) * (int64_t)P2 + base + q] = run_sum(O, j, len, a.nr, (base + q) % RG::RING);
                 }
                 base += RG::G;
             }
@@ -669,7 +678,8 @@ __device__ inline void tl_rot_back_chunk(const TransArgsT<R> &a, typename Cx<R>:
 #pragma unroll
                 for (int i = 0; i < LANE_JT / 8; ++i) {
                     const int j = (lane >> 3) + 8 * i;
-                    if (j < nlive) a.W1[(J0 + j) * (int64_t)P2 + c0 + q] = O[j][q];
+                    const int len = segl[j];
+                    if (len > 0) a.W1[(J0 + j) * (int64_t)P2 + c0 + q] = run_sum(O, j, len, a.nr, q);
                 }
             }
         }
@@ -681,6 +691,7 @@ __global__ void __launch_bounds__(64) k_tl_rot_back(TransArgsT<R> a, int nsplit)
     using C = typename Cx<R>::T;
     using RG = TlRing<R>;
     __shared__ C O[LANE_JT][RG::OW + 1];
+    __shared__ int segl[LANE_JT];  // per lane: run length if the lane's job starts a run, else 0
     const bool ordered = RG::ON && nsplit == 1;
     int base = 0, cnext = 0;  // first coefficient not yet stored; next coefficient to be produced
     const int lane = threadIdx.x;
@@ -690,6 +701,8 @@ __global__ void __launch_bounds__(64) k_tl_rot_back(TransArgsT<R> a, int nsplit)
     const int64_t Jc = J < a.njob ? J : a.njob - 1;
     const int P2 = a.P * a.P, phs = 2 * a.PH + 1;
     const int nlive = (int)min((int64_t)LANE_JT, a.njob - J0);
+    // a run of real jobs h..h+len-1 holds, for vector r, lanes (h - h0) nr + r + k nr
+    segl[lane] = lane < nlive ? a.jseg[J / a.nr] : 0;
     const int tr = __builtin_amdgcn_readfirstlane(a.tile_rot[tile / a.nr]);
     const R *Hb = a.H + (int64_t)tr * rot_table_size(a.P);
     const C *ph = a.ph + (int64_t)a.jdir[Jc / a.nr] * phs + a.PH;
@@ -697,7 +710,7 @@ __global__ void __launch_bounds__(64) k_tl_rot_back(TransArgsT<R> a, int nsplit)
         const int w = 2 * n + 1;
         const R *Hn = Hb + rot_block_off(n);  // (H^T y)_r = sum_c H[c][r] y_c: row c of H
         for (int r0 = 0; r0 < w; r0 += 32) {
-#define TL_BACK(K) tl_rot_back_chunk<R, K, PF>(a, O, Hn, ph, n, w, r0, J0, Jc, nlive, P2, lane, ordered, base, cnext)
+#define TL_BACK(K) tl_rot_back_chunk<R, K, PF>(a, O, Hn, ph, n, w, r0, J0, Jc, segl, P2, lane, ordered, base, cnext)
             TL_ROT_CHUNK(w - r0, TL_BACK);
 #undef TL_BACK
         }
@@ -706,7 +719,8 @@ __global__ void __launch_bounds__(64) k_tl_rot_back(TransArgsT<R> a, int nsplit)
         const int cnt = cnext - base;
         for (int e = lane; e < nlive * RG::G; e += LANE_JT) {
             const int j = e / RG::G, q = e % RG::G;
-            if (q < cnt) a.W1[(J0 + j) * (int64_t)P2 + base + q] = O[j][(base + q) % RG::RING];
+            const int len = segl[j];
+            if (q < cnt && len > 0) a.W1[(J0 + j) * (int64_t)P2 + base + q] = run_sum(O, j, len, a.nr, (base + q) % RG::RING);
         }
     }
 }
@@ -843,7 +857,7 @@ const char *trans_stage(const TransBatch &b, const TransTables<R> &tb, int stage
                         typename Cx<R>::T *W2, hipStream_t st) {
     if (nr < 1 || b.JT % nr) throw FmmError(-1, "right-hand-side count must divide the tile size");
     TransArgsT<R> a{b.njob * nr, b.JT, b.psrc, b.ptgt, b.P, b.PT, PH, nr, src, dst, b.src, b.tgt, b.dir,
-                    b.tile_coax, b.tile_rot, tb.coax, tb.H, tb.HT, ph, W1, W2};
+                    b.tile_coax, b.tile_rot, tb.coax, tb.H, tb.HT, ph, W1, W2, b.seg};
     // classes are padded to whole tiles of JT real jobs, so a tile of JT virtual jobs never
     // mixes tables: virtual tile t uses the tables of real tile t / nr
     const unsigned ntile = (unsigned)((b.njob * nr + b.JT - 1) / b.JT);
