@@ -107,6 +107,9 @@ typedef struct {
                             64-job tiles wastes at most a quarter) run one job per lane, tables
                             read as wave-uniform values; 2: every batch does; 0: LDS tile kernels
                             everywhere; default 1 */
+    int streams;         /* 2: the near field, the M2M chain, the upper levels' M2L and the L2L
+                            chain of a product run on a second stream beside P2M and the leaf
+                            levels' M2L; 1: one stream; default 2 */
 } fmmbem_options;
 
 void fmmbem_default_options(fmmbem_options *opt);
@@ -349,7 +352,11 @@ int fmmbem_profile(fmmbem_ctx *ctx, int enable);
 int fmmbem_kernel_stats(fmmbem_ctx *ctx, int max, fmmbem_kstat *out, int *count);
 
 /* Per-phase device time of the last matvec in milliseconds (hipEvent based):
- * [0] densities, [1] P2P+near, [2] P2M, [3] M2M, [4] M2L, [5] L2L, [6] L2P+combine, [7] total. */
+ * [0] densities, [1] P2P+near, [2] P2M, [3] M2M, [4] M2L, [5] L2L, [6] L2P+combine, [7] total.
+ * The FMM product runs on two streams: the near field and the upper tree levels beside P2M and
+ * the leaf-level translations, so the phases overlap: [1] and [2] both count from the fork after
+ * [0], [3] is the M2M chain from the end of P2M, [4] the remaining translations up to the join
+ * (M2L and L2L together; [5] is 0).  [7] is the wall time of the whole product. */
 int fmmbem_last_timings(fmmbem_ctx *ctx, double *ms8);
 
 #ifdef __cplusplus

@@ -542,7 +542,9 @@ static void ensure_setup(fmmbem_ctx *c) {
 // ------------------------------------------------------------------ kernel profiling
 static void prof_flush(fmmbem_ctx *c) {
     if (c->prof_pend.empty()) return;
+    // the pairs sit on either stream of the product (a flush may come mid-product)
     HIP_OK(hipStreamSynchronize(c->stream));
+    HIP_OK(hipStreamSynchronize(c->side));
     for (auto &r : c->prof_pend) {
         float ms = 0;
         HIP_OK(hipEventElapsedTime(&ms, c->prof_ev[r.a], c->prof_ev[r.b]));
@@ -565,12 +567,12 @@ static int prof_begin(fmmbem_ctx *c) {
     }
     int a = c->prof_used;
     c->prof_used += 2;
-    HIP_OK(hipEventRecord(c->prof_ev[a], c->stream));
+    HIP_OK(hipEventRecord(c->prof_ev[a], c->cur));
     return a;
 }
 static void prof_end(fmmbem_ctx *c, int a, const char *name, double flops, double bytes) {
     if (a < 0) return;
-    HIP_OK(hipEventRecord(c->prof_ev[a + 1], c->stream));
+    HIP_OK(hipEventRecord(c->prof_ev[a + 1], c->cur));
     int cls = -1;
     for (size_t q = 0; q < c->prof_stats.size(); ++q)
         if (!strcmp(c->prof_stats[q].name, name)) cls = (int)q;
@@ -601,9 +603,11 @@ static void run_batch(fmmbem_ctx *c, int nrv, const TransBatch &b, const typenam
                       typename Cx<R>::T *dst, const TransTables<R> &tb, const typename Cx<R>::T *ph) {
     using C = typename Cx<R>::T;
     if (b.njob == 0) return;
-    hipStream_t st = c->stream;
-    C *W1 = (C *)c->scratch.get("W1", sizeof(C) * (size_t)b.njob * nrv * b.P * b.P);
-    C *W2 = (C *)c->scratch.get("W2", sizeof(C) * (size_t)b.njob * nrv * b.P * b.P);
+    hipStream_t st = c->cur;
+    // work rows per stream, so that batches on the two streams never share them
+    const bool side = st == c->side;
+    C *W1 = (C *)c->scratch.get(side ? "W1s" : "W1", sizeof(C) * (size_t)b.njob * nrv * b.P * b.P);
+    C *W2 = (C *)c->scratch.get(side ? "W2s" : "W2", sizeof(C) * (size_t)b.njob * nrv * b.P * b.P);
     const double nr = (double)b.nreal * nrv, P2 = (double)b.P * b.P, cs = (double)sizeof(C);
     // algorithmic work per stage: flops of the matrices applied; bytes of the rows moved once
     const double fl[4] = {nr * rot_flops(b.psrc), nr * coax_flops(b.psrc, b.ptgt), nr * rot_flops(b.ptgt), nr * P2 * 2};
@@ -716,19 +720,19 @@ static void convert(fmmbem_ctx *c, int64_t n, const S *a, D *b);
 template <>
 void convert<double2, float2>(fmmbem_ctx *c, int64_t n, const double2 *a, float2 *b) {
     if (n <= 0) return;
-    k_cvt_d2f<<<ceil_div(n, 256), 256, 0, c->stream>>>(n, a, b);
+    k_cvt_d2f<<<ceil_div(n, 256), 256, 0, c->cur>>>(n, a, b);
     LAUNCH_OK();
 }
 template <>
 void convert<float2, double2>(fmmbem_ctx *c, int64_t n, const float2 *a, double2 *b) {
     if (n <= 0) return;
-    k_cvt_f2d<<<ceil_div(n, 256), 256, 0, c->stream>>>(n, a, b);
+    k_cvt_f2d<<<ceil_div(n, 256), 256, 0, c->cur>>>(n, a, b);
     LAUNCH_OK();
 }
 template <>
 void convert<double, float>(fmmbem_ctx *c, int64_t n, const double *a, float *b) {
     if (n <= 0) return;
-    k_cvt_real_d2f<<<ceil_div(n, 256), 256, 0, c->stream>>>(n, a, b);
+    k_cvt_real_d2f<<<ceil_div(n, 256), 256, 0, c->cur>>>(n, a, b);
     LAUNCH_OK();
 }
 
@@ -776,12 +780,12 @@ static void zero_dev(fmmbem_ctx *c, void *ptr, size_t bytes) {
     if (bytes == 0) return;
     if (bytes % 8) throw FmmError(FMMBEM_EINVAL, "zero_dev: size not a multiple of 8 bytes");
     const int64_t n8 = (int64_t)(bytes / 8);
-    k_zero8<<<ceil_div(n8, 256), 256, 0, c->stream>>>(n8, (uint64_t *)ptr);
+    k_zero8<<<ceil_div(n8, 256), 256, 0, c->cur>>>(n8, (uint64_t *)ptr);
     LAUNCH_OK();
 }
 
 static void rec(fmmbem_ctx *c, int i) {
-    if (!c->capturing) HIP_OK(hipEventRecord(c->ev[i], c->stream));
+    if (!c->capturing) HIP_OK(hipEventRecord(c->ev[i], c->cur));
 }
 
 // Expansion arrays hold nr vectors per box (vector-inner); grow them when more are asked for.
@@ -808,24 +812,114 @@ static void ensure_nr(fmmbem_ctx *c, int nr, bool mixed) {
 
 // y (caller order, nr x N) = half * x + L[sigma] + M[mu] at the centroids; sigma/mu in tree
 // order with the nr vectors interleaved.
+// Fork/join on the product's two streams: events created on first use and reused.  A wait
+// refers to the latest record enqueued on the host before it, so every record below is enqueued
+// before its wait.
+static hipEvent_t fj_event(fmmbem_ctx *c, int slot) {
+    while ((int)c->fj.size() <= slot) {
+        hipEvent_t e;
+        HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        c->fj.push_back(e);
+    }
+    return c->fj[slot];
+}
+static void ev_record(fmmbem_ctx *c, int slot, hipStream_t s) { HIP_OK(hipEventRecord(fj_event(c, slot), s)); }
+static void ev_wait(fmmbem_ctx *c, int slot, hipStream_t s) { HIP_OK(hipStreamWaitEvent(s, fj_event(c, slot), 0)); }
+
+// Far-field translations of one product on two streams.  The main stream A runs the M2L of the
+// deepest levels (l >= L - 2: by far the most jobs), leaf level first, straight after P2M; the
+// side stream B runs the M2M chain, the M2L of the upper levels and then the L2L chain.
+//   M2M chain (B)         waits for P2M (A)
+//   M2L(l), l < L (A)     waits for M(l) from the chain
+//   L2L into l >= lsplit  waits for A's last M2L (level lsplit): A runs its levels in order, so
+//   (B)                   then L(l-1) is complete and no M2L still adds into L(l) (which the
+//                         stream running M2L(l) zeroes first); B's own order covers the rest
+//   join                  A waits for B's last L2L
+template <class R>
+static void far_field(fmmbem_ctx *c, int nr, bool mixed) {
+    using C = typename Cx<R>::T;
+    const int L = c->tree.depth;
+    hipStream_t A = c->stream, B = c->opt.streams >= 2 ? c->side : c->stream;
+    const C *ph = (const C *)c->buf.find(mixed ? "phA32" : "phA");
+    auto M = [&](int l) -> C * { return mixed ? (C *)c->lev[l].M32 : (C *)c->lev[l].M; };
+    auto Lc = [&](int l) -> C * { return mixed ? (C *)c->lev[l].L32 : (C *)c->lev[l].L; };
+    auto tab = [&](const TransBatch &b, const double2 *coax64, const float2 *coax32) -> TransTables<R> {
+        if constexpr (sizeof(R) == 8) return tables64(b, coax64);
+        else return tables32(b, coax32);
+    };
+    auto bytes = [&](int l) { return sizeof(C) * (size_t)c->lev[l].nbox * nr * c->lev[l].p * c->lev[l].p; };
+    const int lsplit = std::max(2, L - 2);  // levels >= lsplit: M2L on A
+    const int EV_P2M = 1, EV_M2L = 2, EV_B = 3, EV_M = 4;  // EV_M + l: M(l) ready
+    ev_record(c, EV_P2M, A);
+    // B: M2M chain
+    c->cur = B;
+    ev_wait(c, EV_P2M, B);
+    for (int l = L - 1; l >= 2; --l) {
+        LevelDev &P_ = c->lev[l];
+        zero_dev(c, M(l), bytes(l));
+        run_batch<R>(c, nr, P_.up, M(l + 1), M(l), tab(P_.up, P_.coax_up, P_.coax_up32), ph);
+        if (l >= lsplit) ev_record(c, EV_M + l, B);
+    }
+    rec(c, 4);
+    // A: M2L of the deep levels
+    c->cur = A;
+    for (int l = L; l >= lsplit; --l) {
+        LevelDev &D = c->lev[l];
+        if (l < L) ev_wait(c, EV_M + l, A);
+        zero_dev(c, Lc(l), bytes(l));
+        run_batch<R>(c, nr, D.m2l, M(l), Lc(l), tab(D.m2l, D.coax_m2l, D.coax_m2l32), ph);
+    }
+    ev_record(c, EV_M2L, A);
+    // B: M2L of the upper levels, then the L2L chain top-down
+    c->cur = B;
+    for (int l = 2; l < lsplit; ++l) {
+        LevelDev &D = c->lev[l];
+        zero_dev(c, Lc(l), bytes(l));
+        run_batch<R>(c, nr, D.m2l, M(l), Lc(l), tab(D.m2l, D.coax_m2l, D.coax_m2l32), ph);
+    }
+    bool a_done = false;
+    for (int l = 3; l <= L; ++l) {
+        LevelDev &P_ = c->lev[l - 1];
+        if (l >= lsplit && !a_done) {
+            ev_wait(c, EV_M2L, B);
+            a_done = true;
+        }
+        run_batch<R>(c, nr, P_.down, Lc(l - 1), Lc(l), tab(P_.down, P_.coax_up, P_.coax_up32), ph);
+    }
+    ev_record(c, EV_B, B);
+    c->cur = A;
+    ev_wait(c, EV_B, A);
+}
+
 static void fmm_pass(fmmbem_ctx *c, int nr, const double2 *sigma, const double2 *mu, const double2 *x, double half,
                      double2 *y, bool exact_far, bool mixed = false) {
     TreeHost &T = c->tree;
     const int L = T.depth;
-    hipStream_t st = c->stream;
+    hipStream_t A = c->stream, B = c->opt.streams >= 2 ? c->side : c->stream;
     const int64_t n = c->nt;
     const int nleaf = (int)T.leaf_start.size() - 1;
     auto I32 = [&](const char *s) { return (int32_t *)c->buf.find(s); };
     const double4 *ec = (double4 *)c->buf.find("ec"), *en = (double4 *)c->buf.find("en");
     double2 *ynear = dget<double2>(c->scratch, "ynear", (size_t)n * nr);
     ensure_nr(c, nr, mixed);
+    struct CurGuard {
+        fmmbem_ctx *c;
+        ~CurGuard() { c->cur = c->stream; }
+    } guard{c};
+    // fork: the near field runs on the side stream beside P2M and the translations
     rec(c, 1);
+    if (!exact_far) {
+        ev_record(c, 0, A);
+        ev_wait(c, 0, B);
+        c->cur = B;
+    }
     int pe = prof_begin(c);
     {
         const double pairs = exact_far ? (double)n * n : (double)c->p2p_pairs;
         launch_p2p(nr, mixed, nleaf, I32("leaf_start"), I32("nbr_start"), I32("nbr_list"), exact_far ? 1 : 0, ec, en,
                    sigma, mu, c->k, c->rc * c->rc, I32("near_start"), I32("near_col"),
-                   c->buf.find(mixed ? "near_L32" : "near_L"), c->buf.find(mixed ? "near_M32" : "near_M"), ynear, st);
+                   c->buf.find(mixed ? "near_L32" : "near_L"), c->buf.find(mixed ? "near_M32" : "near_M"), ynear,
+                   c->cur);
         // one-point pairs: ~40 flops each (sincos counted as 20), kernel shared by the nr vectors;
         // bytes: element data, densities, near table and output, each read once
         const double tb = mixed ? 16.0 : 32.0;
@@ -833,58 +927,28 @@ static void fmm_pass(fmmbem_ctx *c, int nr, const double2 *sigma, const double2 
                  80.0 * n + 48.0 * n * nr + (8.0 + tb) * c->near_nnz);
     }
     rec(c, 2);
+    c->cur = A;
     if (!exact_far) {
         LevelDev &LL = c->lev[L];
         const int p = LL.p;
         const int CH = p2m_chunk(nr, p);
         const size_t pp = (size_t)p * p;
         pe = prof_begin(c);
-        launch_p2m(nr, nleaf, p, CH, I32("leaf_start"), LL.center, ec, en, sigma, mu, c->k, leg_table(c), LL.M, st);
+        launch_p2m(nr, nleaf, p, CH, I32("leaf_start"), LL.center, ec, en, sigma, mu, c->k, leg_table(c), LL.M, A);
         prof_end(c, pe, "k_p2m", (double)n * pp * 2 * 8.0 * nr, 112.0 * n + 32.0 * n * nr + 16.0 * nleaf * pp * nr);
-        rec(c, 3);
         if (mixed) {
             // FP32 translations between an FP64 P2M and an FP64 L2P
-            const float2 *ph32 = (float2 *)c->buf.find("phA32");
             pe = prof_begin(c);
             convert(c, (int64_t)LL.nbox * nr * pp, (const double2 *)LL.M, LL.M32);
             prof_end(c, pe, "k_cvt", 0.0, 24.0 * LL.nbox * pp * nr);
-            for (int l = L - 1; l >= 2; --l) {
-                LevelDev &P_ = c->lev[l], &C_ = c->lev[l + 1];
-                zero_dev(c, P_.M32, sizeof(float2) * P_.nbox * nr * P_.p * P_.p);
-                run_batch<float>(c, nr, P_.up, C_.M32, P_.M32, tables32(P_.up, P_.coax_up32), ph32);
-            }
-            rec(c, 4);
-            for (int l = 2; l <= L; ++l) {
-                LevelDev &D = c->lev[l];
-                zero_dev(c, D.L32, sizeof(float2) * D.nbox * nr * D.p * D.p);
-                run_batch<float>(c, nr, D.m2l, D.M32, D.L32, tables32(D.m2l, D.coax_m2l32), ph32);
-                if (l >= 3) {
-                    LevelDev &P_ = c->lev[l - 1];
-                    run_batch<float>(c, nr, P_.down, P_.L32, D.L32, tables32(P_.down, P_.coax_up32), ph32);
-                }
-            }
+        }
+        rec(c, 3);
+        if (mixed) far_field<float>(c, nr, true);
+        else far_field<double>(c, nr, false);
+        if (mixed) {
             pe = prof_begin(c);
             convert(c, (int64_t)LL.nbox * nr * pp, (const float2 *)LL.L32, LL.L);
             prof_end(c, pe, "k_cvt", 0.0, 24.0 * LL.nbox * pp * nr);
-        } else {
-            const double2 *ph = (double2 *)c->buf.find("phA");
-            // M2M up
-            for (int l = L - 1; l >= 2; --l) {
-                LevelDev &P_ = c->lev[l], &C_ = c->lev[l + 1];
-                zero_dev(c, P_.M, sizeof(double2) * P_.nbox * nr * P_.p * P_.p);
-                run_batch<double>(c, nr, P_.up, C_.M, P_.M, tables64(P_.up, P_.coax_up), ph);
-            }
-            rec(c, 4);
-            // M2L and L2L down
-            for (int l = 2; l <= L; ++l) {
-                LevelDev &D = c->lev[l];
-                zero_dev(c, D.L, sizeof(double2) * D.nbox * nr * D.p * D.p);
-                run_batch<double>(c, nr, D.m2l, D.M, D.L, tables64(D.m2l, D.coax_m2l), ph);
-                if (l >= 3) {
-                    LevelDev &P_ = c->lev[l - 1];
-                    run_batch<double>(c, nr, P_.down, P_.L, D.L, tables64(P_.down, P_.coax_up), ph);
-                }
-            }
         }
         rec(c, 5);
     } else {
@@ -894,10 +958,11 @@ static void fmm_pass(fmmbem_ctx *c, int nr, const double2 *sigma, const double2 
     LevelDev &LL = c->lev[L];
     pe = prof_begin(c);
     launch_l2p(nr, nleaf, LL.p, I32("leaf_start"), LL.center, ec, LL.L, c->k, leg_table(c), ynear, half,
-               I32("perm"), n, x, y, exact_far ? 0 : 1, st);
+               I32("perm"), n, x, y, exact_far ? 0 : 1, A);
     prof_end(c, pe, "k_l2p", (double)n * LL.p * LL.p * 8.0 * nr,
              32.0 * n + 16.0 * n * 3 * nr + 16.0 * nleaf * LL.p * LL.p * nr);
     rec(c, 7);
+    (void)B;
 }
 
 // y = A x for nr vectors (x, y: nr x N device arrays, caller order), nr in {1, 2, 4}
@@ -987,9 +1052,10 @@ static void read_timings(fmmbem_ctx *c) {
         HIP_OK(hipEventElapsedTime(&t, c->ev[a], c->ev[b]));
         return (double)t;
     };
+    // the near field (side stream) and P2M (main stream) both start at the fork (event 1)
     c->last.ms[0] = el(0, 1);
     c->last.ms[1] = el(1, 2);
-    c->last.ms[2] = el(2, 3);
+    c->last.ms[2] = el(1, 3);
     c->last.ms[3] = el(3, 4);
     c->last.ms[4] = el(4, 5);  // M2L + L2L
     c->last.ms[5] = 0.0;
@@ -1149,6 +1215,7 @@ void fmmbem_default_options(fmmbem_options *o) {
     o->graphs = 1;
     o->autotune = 0;
     o->lane_tiles = 1;
+    o->streams = 2;
 }
 
 void fmmbem_default_solve_opts(fmmbem_solve_opts *o) {
@@ -1196,6 +1263,8 @@ int fmmbem_create(fmmbem_ctx **out, int hip_device, const fmmbem_options *opt) {
         else fmmbem_default_options(&ctx->opt);
         HIP_OK(hipSetDevice(hip_device));
         HIP_OK(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+        HIP_OK(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));  // default priority, as the main one
+        ctx->cur = ctx->stream;
         {
             hipDeviceProp_t prop;
             HIP_OK(hipGetDeviceProperties(&prop, hip_device));
@@ -1223,6 +1292,7 @@ int fmmbem_destroy(fmmbem_ctx *ctx) {
     if (!ctx) return FMMBEM_OK;
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->side) (void)hipStreamSynchronize(ctx->side);
     drop_graphs(ctx);
     ctx->buf.release_all();
     ctx->scratch.release_all();
@@ -1230,6 +1300,8 @@ int fmmbem_destroy(fmmbem_ctx *ctx) {
         if (e) (void)hipEventDestroy(e);
     for (auto &e : ctx->prof_ev) (void)hipEventDestroy(e);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
+    for (auto e : ctx->fj) (void)hipEventDestroy(e);
     delete ctx;
     return FMMBEM_OK;
 }

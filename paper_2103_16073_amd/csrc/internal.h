@@ -220,6 +220,10 @@ struct fmmbem_ctx {
     fmmbem_options opt{};
     std::string err;
     hipStream_t stream = nullptr;
+    // second stream of the product (near field and the upper tree levels run beside the leaf
+    // level), the stream the helpers currently enqueue on, and the fork/join events
+    hipStream_t side = nullptr, cur = nullptr;
+    std::vector<hipEvent_t> fj;
     hipEvent_t ev[9] = {};
     fmm::DeviceBuffers buf;      // persistent per-setup arrays
     fmm::DeviceBuffers scratch;  // per-call workspaces

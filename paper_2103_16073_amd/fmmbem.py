@@ -34,7 +34,7 @@ class Options(ctypes.Structure):
     _fields_ = [("rc_factor", ctypes.c_double), ("rc", ctypes.c_double), ("leaf_max", ctypes.c_int),
                 ("p_min", ctypes.c_int), ("p_excess", ctypes.c_double), ("ktau_switch", ctypes.c_double),
                 ("max_depth", ctypes.c_int), ("lds_budget", ctypes.c_int), ("graphs", ctypes.c_int),
-                ("autotune", ctypes.c_int), ("lane_tiles", ctypes.c_int)]
+                ("autotune", ctypes.c_int), ("lane_tiles", ctypes.c_int), ("streams", ctypes.c_int)]
 
 
 class SolveOpts(ctypes.Structure):
