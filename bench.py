@@ -252,7 +252,8 @@ def main():
             xs, rep, rc = ctx.fmmbem_solve(0, tol=1e-4, restart=args.maxit, maxit=args.maxit,
                                            precond=F.FMMBEM_PC_NEARBLOCK, precision=prec)
             fg[name] = {"status": rc, "iters": rep.iters, "rel_res_fp64": rep.rel_res, "t_solve_s": rep.t_solve_s,
-                        "matvecs_fp64": rep.matvecs_fp64, "matvecs_mixed": rep.matvecs_mixed}
+                        "matvecs_fp64": rep.matvecs_fp64, "matvecs_mixed": rep.matvecs_mixed,
+                        "krylov_storage": "fp32" if prec == F.FMMBEM_MIXED else "fp64"}
             log(f"FGMRES {name}: status {rc} iters {rep.iters} rel_res {rep.rel_res:.3e} t {rep.t_solve_s:.2f}s")
         if not args.no_learned:
             # learned preconditioner trained on another source position, mixed products

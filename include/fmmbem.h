@@ -181,6 +181,11 @@ typedef struct {
     int inner_iters;
     double inner_tol;
     int inner_precision;
+    /* Storage of the Krylov vectors (V and the preconditioned Z): 1 FP32 (half the basis traffic
+     * of the Arnoldi steps; inner products, Hessenberg matrix, rotations, iterate and restart
+     * residuals stay FP64), 0 FP64, -1 (default) FP32 exactly when the products are MIXED (for
+     * the inner solves: when inner_precision is). */
+    int basis_fp32;
 } fmmbem_solve_opts;
 
 typedef struct {

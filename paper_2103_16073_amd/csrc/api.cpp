@@ -73,13 +73,13 @@ int fgmres_batch(int64_t n, hipStream_t st, DeviceBuffers &scr, int nv,
                  const std::function<void(int, const double2 *, double2 *)> &matvec_check,
                  const std::function<void(const double2 *, double2 *)> &precond, const double2 *B, double2 *X,
                  double tol, int m, int maxit, bool x0_given, std::vector<int> &iters, std::vector<int> &restarts,
-                 std::vector<double> &rel_res, std::vector<int> &status);
+                 std::vector<double> &rel_res, std::vector<int> &status, bool basis32 = false);
 int fgmres(int64_t n, hipStream_t st, DeviceBuffers &scr, const char *tag,
            const std::function<void(const double2 *, double2 *)> &matvec,
            const std::function<void(const double2 *, double2 *)> &matvec_check,
            const std::function<void(const double2 *, double2 *)> &precond, const double2 *b, double2 *x, double tol,
            int m, int maxit, bool x0_given, bool final_residual, std::vector<double> *history, int &iters,
-           int &restarts, double &rel_res, const FgmresHooks *hooks);
+           int &restarts, double &rel_res, const FgmresHooks *hooks, bool basis32 = false);
 
 void drop_graphs(fmmbem_ctx *c);
 static void autotune_batches(fmmbem_ctx *c);
@@ -1227,6 +1227,7 @@ void fmmbem_default_solve_opts(fmmbem_solve_opts *o) {
     o->diag_shift = 0.0;
     o->use_x0 = 0;
     o->inner_iters = 0;
+    o->basis_fp32 = -1;
     o->inner_tol = 1e-2;
     o->inner_precision = FMMBEM_MIXED;
 }
@@ -1669,6 +1670,7 @@ static int check_solve_opts(fmmbem_ctx *ctx, const fmmbem_solve_opts &o) {
     if (o.inner_iters < 0 || (o.inner_iters > 0 && !(o.inner_tol > 0)) ||
         (o.inner_precision != FMMBEM_FP64 && o.inner_precision != FMMBEM_MIXED))
         return fail(ctx, FMMBEM_EINVAL, "bad inner solve options");
+    if (o.basis_fp32 < -1 || o.basis_fp32 > 1) return fail(ctx, FMMBEM_EINVAL, "basis_fp32 must be -1, 0 or 1");
     if (o.precond < FMMBEM_PC_NONE || o.precond > FMMBEM_PC_LEARNED) return fail(ctx, FMMBEM_EINVAL, "unknown preconditioner");
     return FMMBEM_OK;
 }
@@ -1720,8 +1722,9 @@ int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, f
             auto imv = [&](const double2 *a, double2 *y) { product(a, y, imixed); };
             int it = 0, rs = 0;
             double rr = 1.0;
+            const bool ib32 = o.basis_fp32 < 0 ? imixed : o.basis_fp32 != 0;
             int s = fgmres(n, st, ctx->scratch, "in_", imv, imv, pc, v, z, o.inner_tol, o.inner_iters, o.inner_iters,
-                           false, false, nullptr, it, rs, rr, nullptr);
+                           false, false, nullptr, it, rs, rr, nullptr, ib32);
             if (s < 0) throw FmmError(s, "inner GMRES failed");
             inner_its += it;
         };
@@ -1752,8 +1755,9 @@ int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, f
             last_true = r;
         };
     }
+    const bool b32 = o.basis_fp32 < 0 ? mixed : o.basis_fp32 != 0;
     int status = fgmres(n, st, ctx->scratch, "", mv, mv64, outer_pc, b, dx, o.tol, o.restart, o.maxit, o.use_x0 != 0,
-                        true, &ctx->history, iters, restarts, rel, &hk);
+                        true, &ctx->history, iters, restarts, rel, &hk, b32);
     ctx->mlp_active = false;
     HIP_OK(hipMemcpyAsync(x, dx, sizeof(double2) * n, hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
@@ -1814,8 +1818,9 @@ int fmmbem_solve_batch(fmmbem_ctx *ctx, int32_t ns, const int32_t *isrc, const f
     };
     std::vector<int> iters, restarts, status;
     std::vector<double> rel;
+    const bool b32 = o.basis_fp32 < 0 ? mixed : o.basis_fp32 != 0;
     int rc = fgmres_batch(n, st, ctx->scratch, ns, mv, mv64, pc, B, X, o.tol, o.restart, o.maxit, o.use_x0 != 0,
-                          iters, restarts, rel, status);
+                          iters, restarts, rel, status, b32);
     HIP_OK(hipMemcpyAsync(x, X, sizeof(double2) * n * ns, hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
     const double ts = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -9,6 +9,7 @@
 // short host<->device copy per pass.
 #include <chrono>
 #include <functional>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -16,14 +17,25 @@ namespace fmm {
 
 constexpr int DOT_BLOCKS = 512;
 
+// Krylov vectors are stored as double2 or (mixed-precision solves) float2; every inner product and
+// update is computed in FP64.
+__device__ inline double2 ldc(const double2 *p, int64_t i) { return p[i]; }
+__device__ inline double2 ldc(const float2 *p, int64_t i) {
+    const float2 v = p[i];
+    return make_double2(v.x, v.y);
+}
+__device__ inline void stc(double2 *p, int64_t i, double2 v) { p[i] = v; }
+__device__ inline void stc(float2 *p, int64_t i, double2 v) { p[i] = make_float2((float)v.x, (float)v.y); }
+
 // partial[v * DOT_BLOCKS + blk] = sum_{i in blk's stride} conj(V_v[i]) w[i]
-__global__ void __launch_bounds__(256) k_dot_partial(int64_t n, const double2 *V, int64_t ldv, int nv, const double2 *w,
+template <class S>
+__global__ void __launch_bounds__(256) k_dot_partial(int64_t n, const S *V, int64_t ldv, int nv, const double2 *w,
                                                      double2 *partial) {
     const int v = blockIdx.y;
-    const double2 *x = V + (int64_t)v * ldv;
+    const S *x = V + (int64_t)v * ldv;
     double2 s = cmk(0, 0);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        s = cadd(s, cmulc(w[i], x[i]));  // conj(x) w
+        s = cadd(s, cmulc(w[i], ldc(x, i)));  // conj(x) w
     __shared__ double2 red[256];
     red[threadIdx.x] = s;
     __syncthreads();
@@ -49,26 +61,36 @@ __global__ void __launch_bounds__(256) k_dot_final(int nblk, const double2 *part
 }
 
 // w -= sum_v h[v] V_v
-__global__ void k_sub_combo(int64_t n, const double2 *V, int64_t ldv, int nv, const double2 *h, double2 *w) {
+template <class S>
+__global__ void k_sub_combo(int64_t n, const S *V, int64_t ldv, int nv, const double2 *h, double2 *w) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double2 s = w[i];
-    for (int v = 0; v < nv; ++v) s = csub(s, cmul(h[v], V[(int64_t)v * ldv + i]));
+    for (int v = 0; v < nv; ++v) s = csub(s, cmul(h[v], ldc(V, (int64_t)v * ldv + i)));
     w[i] = s;
 }
 
 // x += sum_v y[v] Z_v
-__global__ void k_add_combo(int64_t n, const double2 *Z, int64_t ldz, int nv, const double2 *y, double2 *x) {
+template <class S>
+__global__ void k_add_combo(int64_t n, const S *Z, int64_t ldz, int nv, const double2 *y, double2 *x) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double2 s = x[i];
-    for (int v = 0; v < nv; ++v) s = cadd(s, cmul(y[v], Z[(int64_t)v * ldz + i]));
+    for (int v = 0; v < nv; ++v) s = cadd(s, cmul(y[v], ldc(Z, (int64_t)v * ldz + i)));
     x[i] = s;
 }
 
-__global__ void k_scale_copy(int64_t n, double a, const double2 *x, double2 *y) {
+// y = a x (stored in y's type)
+template <class S>
+__global__ void k_scale_copy(int64_t n, double a, const double2 *x, S *y) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) y[i] = cscale(x[i], a);
+    if (i < n) stc(y, i, cscale(x[i], a));
+}
+
+template <class S>
+__global__ void k_widen(int64_t n, const S *x, double2 *y) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = ldc(x, i);
 }
 
 __global__ void k_sub(int64_t n, const double2 *a, const double2 *b, double2 *out) {  // out = a - b
@@ -241,11 +263,12 @@ struct Blas {
     DeviceBuffers &scr;
     int64_t n;
     std::string tag;  // scratch-name prefix, so nested solves keep separate buffers
-    void dots(const double2 *V, int64_t ldv, int nv, const double2 *w, double2 *host_out) {
+    template <class S>
+    void dots(const S *V, int64_t ldv, int nv, const double2 *w, double2 *host_out) {
         double2 *part = dget<double2>(scr, tag + "dot_part", (size_t)DOT_BLOCKS * std::max(nv, 1));
         double2 *res = dget<double2>(scr, tag + "dot_res", std::max(nv, 1));
         int nblk = (int)std::min<int64_t>(DOT_BLOCKS, std::max<int64_t>(1, (n + 255) / 256));
-        k_dot_partial<<<dim3(nblk, nv), 256, 0, st>>>(n, V, ldv, nv, w, part);
+        k_dot_partial<S><<<dim3(nblk, nv), 256, 0, st>>>(n, V, ldv, nv, w, part);
         LAUNCH_OK();
         k_dot_final<<<nv, 256, 0, st>>>(nblk, part, res);
         LAUNCH_OK();
@@ -257,20 +280,28 @@ struct Blas {
         dots(w, 0, 1, w, &d);
         return sqrt(std::max(d.x, 0.0));
     }
-    void sub_combo(const double2 *V, int64_t ldv, int nv, const double2 *h_host, double2 *w) {
+    template <class S>
+    void sub_combo(const S *V, int64_t ldv, int nv, const double2 *h_host, double2 *w) {
         double2 *h = dget<double2>(scr, tag + "combo_h", std::max(nv, 1));
         HIP_OK(hipMemcpyAsync(h, h_host, sizeof(double2) * nv, hipMemcpyHostToDevice, st));
-        k_sub_combo<<<ceil_div(n, 256), 256, 0, st>>>(n, V, ldv, nv, h, w);
+        k_sub_combo<S><<<ceil_div(n, 256), 256, 0, st>>>(n, V, ldv, nv, h, w);
         LAUNCH_OK();
     }
-    void add_combo(const double2 *Z, int64_t ldz, int nv, const double2 *y_host, double2 *x) {
+    template <class S>
+    void add_combo(const S *Z, int64_t ldz, int nv, const double2 *y_host, double2 *x) {
         double2 *h = dget<double2>(scr, tag + "combo_y", std::max(nv, 1));
         HIP_OK(hipMemcpyAsync(h, y_host, sizeof(double2) * nv, hipMemcpyHostToDevice, st));
-        k_add_combo<<<ceil_div(n, 256), 256, 0, st>>>(n, Z, ldz, nv, h, x);
+        k_add_combo<S><<<ceil_div(n, 256), 256, 0, st>>>(n, Z, ldz, nv, h, x);
         LAUNCH_OK();
     }
-    void scale_copy(double a, const double2 *x, double2 *y) {
-        k_scale_copy<<<ceil_div(n, 256), 256, 0, st>>>(n, a, x, y);
+    template <class S>
+    void scale_copy(double a, const double2 *x, S *y) {
+        k_scale_copy<S><<<ceil_div(n, 256), 256, 0, st>>>(n, a, x, y);
+        LAUNCH_OK();
+    }
+    template <class S>
+    void widen(const S *x, double2 *y) {
+        k_widen<S><<<ceil_div(n, 256), 256, 0, st>>>(n, x, y);
         LAUNCH_OK();
     }
     void sub(const double2 *a, const double2 *b, double2 *out) {
@@ -287,18 +318,26 @@ static inline double cabs_(double2 a) { return hypot(a.x, a.y); }
 // last restart, computed with `matvec_check` (the FP64 operator); with final_residual false, a
 // solve that stops at maxit skips that last product and reports the Arnoldi estimate instead
 // (inner solves).  history, when given, receives the estimate after every iteration.
-int fgmres(int64_t n, hipStream_t st, DeviceBuffers &scr, const char *tag,
-           const std::function<void(const double2 *, double2 *)> &matvec,
-           const std::function<void(const double2 *, double2 *)> &matvec_check,
-           const std::function<void(const double2 *, double2 *)> &precond, const double2 *b, double2 *x, double tol,
-           int m, int maxit, bool x0_given, bool final_residual, std::vector<double> *history, int &iters,
-           int &restarts, double &rel_res, const FgmresHooks *hooks) {
+// S: storage type of the Krylov vectors V and Z (double2, or float2 for mixed-precision solves:
+// half the basis traffic; inner products, Hessenberg matrix, rotations, the iterate and the
+// restart residual stay FP64).
+template <class S>
+static int fgmres_t(int64_t n, hipStream_t st, DeviceBuffers &scr, const char *tag,
+                    const std::function<void(const double2 *, double2 *)> &matvec,
+                    const std::function<void(const double2 *, double2 *)> &matvec_check,
+                    const std::function<void(const double2 *, double2 *)> &precond, const double2 *b, double2 *x,
+                    double tol, int m, int maxit, bool x0_given, bool final_residual, std::vector<double> *history,
+                    int &iters, int &restarts, double &rel_res, const FgmresHooks *hooks) {
+    constexpr bool wide = std::is_same<S, double2>::value;
     const std::string tg(tag);
     Blas B{st, scr, n, tg};
-    double2 *V = dget<double2>(scr, tg + "fg_V", (size_t)(m + 1) * n);
-    double2 *Z = dget<double2>(scr, tg + "fg_Z", (size_t)m * n);
+    S *V = dget<S>(scr, tg + (wide ? "fg_V" : "fg_V32"), (size_t)(m + 1) * n);
+    S *Z = dget<S>(scr, tg + (wide ? "fg_Z" : "fg_Z32"), (size_t)m * n);
     double2 *w = dget<double2>(scr, tg + "fg_w", n);
     double2 *r = dget<double2>(scr, tg + "fg_r", n);
+    // FP64 copies of the current basis vector and its preconditioned image (narrow storage only)
+    double2 *tv = wide ? nullptr : dget<double2>(scr, tg + "fg_tv", n);
+    double2 *tz = wide ? nullptr : dget<double2>(scr, tg + "fg_tz", n);
     if (!x0_given) HIP_OK(hipMemsetAsync(x, 0, sizeof(double2) * n, st));
     const double bn = B.nrm(b);
     iters = 0;
@@ -340,8 +379,19 @@ int fgmres(int64_t n, hipStream_t st, DeviceBuffers &scr, const char *tag,
         int j = 0;
         bool done = false;
         for (j = 0; j < m && iters < maxit; ++j) {
-            double2 *vj = V + (size_t)j * n, *zj = Z + (size_t)j * n;
+            S *vjs = V + (size_t)j * n, *zjs = Z + (size_t)j * n;
+            const double2 *vj;
+            double2 *zj;
+            if constexpr (wide) {
+                vj = vjs;
+                zj = zjs;
+            } else {
+                B.widen(vjs, tv);
+                vj = tv;
+                zj = tz;
+            }
             precond(vj, zj);
+            if constexpr (!wide) B.scale_copy(1.0, zj, zjs);
             matvec(zj, w);
             ++iters;
             // classical Gram-Schmidt, repeated only when the first pass removed most of w
@@ -404,35 +454,53 @@ int fgmres(int64_t n, hipStream_t st, DeviceBuffers &scr, const char *tag,
     return status;
 }
 
+int fgmres(int64_t n, hipStream_t st, DeviceBuffers &scr, const char *tag,
+           const std::function<void(const double2 *, double2 *)> &matvec,
+           const std::function<void(const double2 *, double2 *)> &matvec_check,
+           const std::function<void(const double2 *, double2 *)> &precond, const double2 *b, double2 *x, double tol,
+           int m, int maxit, bool x0_given, bool final_residual, std::vector<double> *history, int &iters,
+           int &restarts, double &rel_res, const FgmresHooks *hooks, bool basis32) {
+    if (basis32)
+        return fgmres_t<float2>(n, st, scr, tag, matvec, matvec_check, precond, b, x, tol, m, maxit, x0_given,
+                                final_residual, history, iters, restarts, rel_res, hooks);
+    return fgmres_t<double2>(n, st, scr, tag, matvec, matvec_check, precond, b, x, tol, m, maxit, x0_given,
+                             final_residual, history, iters, restarts, rel_res, hooks);
+}
+
 // Lock-step FGMRES over nv systems A x_s = b_s that share the operator: every step gathers the
 // preconditioned vectors of the systems still iterating and applies one batched product, so the
 // kernel evaluations, basis functions and translation tables of the FMM are shared between them.
 // Each system keeps its own Krylov basis, Hessenberg matrix and restarts, exactly as fgmres().
+template <class S>
 struct BatchSys {
-    double2 *V = nullptr, *Z = nullptr, *r = nullptr;
+    S *V = nullptr, *Z = nullptr;
+    double2 *r = nullptr;
     std::vector<double2> H, g, cs, sn, h1, h2, y;
     double bn = 0.0, est = 1.0;
     int j = 0, cycle = 0;  // cycle = restarts so far
     bool in_cycle = false, done = false;
 };
 
-int fgmres_batch(int64_t n, hipStream_t st, DeviceBuffers &scr, int nv,
-                 const std::function<void(int, const double2 *, double2 *)> &matvec,
-                 const std::function<void(int, const double2 *, double2 *)> &matvec_check,
-                 const std::function<void(const double2 *, double2 *)> &precond, const double2 *B, double2 *X,
-                 double tol, int m, int maxit, bool x0_given, std::vector<int> &iters, std::vector<int> &restarts,
-                 std::vector<double> &rel_res, std::vector<int> &status) {
+template <class T>
+static int fgmres_batch_t(int64_t n, hipStream_t st, DeviceBuffers &scr, int nv,
+                          const std::function<void(int, const double2 *, double2 *)> &matvec,
+                          const std::function<void(int, const double2 *, double2 *)> &matvec_check,
+                          const std::function<void(const double2 *, double2 *)> &precond, const double2 *B,
+                          double2 *X, double tol, int m, int maxit, bool x0_given, std::vector<int> &iters,
+                          std::vector<int> &restarts, std::vector<double> &rel_res, std::vector<int> &status) {
+    constexpr bool wide = std::is_same<T, double2>::value;
     Blas Bl{st, scr, n, "bt_"};
-    std::vector<BatchSys> S(nv);
+    std::vector<BatchSys<T>> S(nv);
+    double2 *tv = wide ? nullptr : dget<double2>(scr, "bt_tv", n);
     iters.assign(nv, 0);
     restarts.assign(nv, 0);
     rel_res.assign(nv, 1.0);
     status.assign(nv, FMMBEM_ENOCONV);
     double2 *Sin = dget<double2>(scr, "bt_in", (size_t)nv * n), *Sout = dget<double2>(scr, "bt_out", (size_t)nv * n);
     for (int s = 0; s < nv; ++s) {
-        BatchSys &q = S[s];
-        q.V = dget<double2>(scr, "bt_V" + std::to_string(s), (size_t)(m + 1) * n);
-        q.Z = dget<double2>(scr, "bt_Z" + std::to_string(s), (size_t)m * n);
+        BatchSys<T> &q = S[s];
+        q.V = dget<T>(scr, (wide ? "bt_V" : "bt_V32_") + std::to_string(s), (size_t)(m + 1) * n);
+        q.Z = dget<T>(scr, (wide ? "bt_Z" : "bt_Z32_") + std::to_string(s), (size_t)m * n);
         q.r = dget<double2>(scr, "bt_r" + std::to_string(s), n);
         q.H.assign((size_t)(m + 1) * m, cmk(0, 0));
         q.g.assign(m + 1, cmk(0, 0));
@@ -467,7 +535,7 @@ int fgmres_batch(int64_t n, hipStream_t st, DeviceBuffers &scr, int nv,
             for (size_t k = 0; k < prod.size(); ++k)
                 Bl.sub(B + (int64_t)prod[k] * n, Sout + k * n, S[prod[k]].r);
             for (int s : need) {
-                BatchSys &q = S[s];
+                BatchSys<T> &q = S[s];
                 if (!(x0_given || q.cycle > 0))
                     HIP_OK(hipMemcpyAsync(q.r, B + (int64_t)s * n, sizeof(double2) * n, hipMemcpyDeviceToDevice, st));
                 const double beta = Bl.nrm(q.r);
@@ -499,15 +567,21 @@ int fgmres_batch(int64_t n, hipStream_t st, DeviceBuffers &scr, int nv,
         if (act.empty()) break;
         // 2. one Arnoldi step for every active system, with a single batched product
         for (size_t k = 0; k < act.size(); ++k) {
-            BatchSys &q = S[act[k]];
-            precond(q.V + (size_t)q.j * n, q.Z + (size_t)q.j * n);
-            HIP_OK(hipMemcpyAsync(Sin + k * n, q.Z + (size_t)q.j * n, sizeof(double2) * n, hipMemcpyDeviceToDevice,
-                                  st));
+            BatchSys<T> &q = S[act[k]];
+            if constexpr (wide) {
+                precond(q.V + (size_t)q.j * n, q.Z + (size_t)q.j * n);
+                HIP_OK(hipMemcpyAsync(Sin + k * n, q.Z + (size_t)q.j * n, sizeof(double2) * n,
+                                      hipMemcpyDeviceToDevice, st));
+            } else {
+                Bl.widen(q.V + (size_t)q.j * n, tv);
+                precond(tv, Sin + k * n);
+                Bl.scale_copy(1.0, Sin + k * n, q.Z + (size_t)q.j * n);
+            }
         }
         matvec((int)act.size(), Sin, Sout);
         for (size_t k = 0; k < act.size(); ++k) {
             const int s = act[k];
-            BatchSys &q = S[s];
+            BatchSys<T> &q = S[s];
             auto Hc = [&](int i, int jj) -> double2 & { return q.H[(size_t)i * m + jj]; };
             double2 *w = Sout + k * n;
             const int j = q.j;
@@ -570,6 +644,19 @@ int fgmres_batch(int64_t n, hipStream_t st, DeviceBuffers &scr, int nv,
         }
     }
     return FMMBEM_OK;
+}
+
+int fgmres_batch(int64_t n, hipStream_t st, DeviceBuffers &scr, int nv,
+                 const std::function<void(int, const double2 *, double2 *)> &matvec,
+                 const std::function<void(int, const double2 *, double2 *)> &matvec_check,
+                 const std::function<void(const double2 *, double2 *)> &precond, const double2 *B, double2 *X,
+                 double tol, int m, int maxit, bool x0_given, std::vector<int> &iters, std::vector<int> &restarts,
+                 std::vector<double> &rel_res, std::vector<int> &status, bool basis32) {
+    if (basis32)
+        return fgmres_batch_t<float2>(n, st, scr, nv, matvec, matvec_check, precond, B, X, tol, m, maxit, x0_given,
+                                      iters, restarts, rel_res, status);
+    return fgmres_batch_t<double2>(n, st, scr, nv, matvec, matvec_check, precond, B, X, tol, m, maxit, x0_given,
+                                   iters, restarts, rel_res, status);
 }
 
 }  // namespace fmm

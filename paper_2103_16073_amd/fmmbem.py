@@ -41,7 +41,7 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("maxit", ctypes.c_int),
                 ("precond", ctypes.c_int), ("precision", ctypes.c_int), ("diag_shift", ctypes.c_double),
                 ("use_x0", ctypes.c_int), ("inner_iters", ctypes.c_int), ("inner_tol", ctypes.c_double),
-                ("inner_precision", ctypes.c_int)]
+                ("inner_precision", ctypes.c_int), ("basis_fp32", ctypes.c_int)]
 
 
 class SolveReport(ctypes.Structure):

@@ -184,6 +184,34 @@ def test_solve_mixed_inner_vs_oracle_lu(F, cfg1_dense):
     ctx.close()
 
 
+@pytest.mark.parametrize("batched", [False, True])
+def test_solve_fp32_basis_vs_fp64_basis(F, cfg1_dense, batched):
+    """Mixed-precision solves with the Krylov vectors stored in FP32 (the default for mixed
+    products) and in FP64: both reach the FP64 residual target within a few iterations of each
+    other, and both solutions agree with the oracle's LU solution."""
+    room, k = cfg1_dense
+    ctx = make_ctx(F, room, k)
+    rs, _ = synth.source_and_receivers(room, 4, nsrc=2)
+    ctx.fmmbem_set_sources(rs)
+    rc = ctx.fmmbem_get_info().rc
+    A, b, _, _ = bem.direct_system(room.vertices, room.triangles, k, room.beta, rs[1], rc)
+    x_ref = bem.solve_lu(A, b)
+    its = {}
+    for b32 in (0, 1):
+        kw = dict(tol=1e-6, restart=200, maxit=200, precision=F.FMMBEM_MIXED, basis_fp32=b32)
+        if batched:
+            X, reps, rc_ = ctx.fmmbem_solve_batch([0, 1], **kw)
+            x, rep = X[1], reps[1]
+        else:
+            x, rep, rc_ = ctx.fmmbem_solve(1, **kw)
+        print(f"basis fp32={b32} batched={batched}: iters {rep.iters} rel {rep.rel_res:.2e}")
+        assert rc_ == 0 and rep.rel_res < 1e-6
+        assert np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref) < 1e-4
+        its[b32] = rep.iters
+    assert abs(its[1] - its[0]) <= max(3, its[0] // 10), its
+    ctx.close()
+
+
 def test_solve_inner_outer_vs_oracle_lu(F, cfg1_dense):
     """Flexible GMRES preconditioned by an inner mixed-precision GMRES (Section 4.4): converges
     to the FP64 residual target, agrees with LU, and counts its products by arithmetic."""
