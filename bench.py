@@ -67,6 +67,7 @@ def main():
                     help="also run 4 device copies of 512 MiB (calibration of the FETCH_SIZE/WRITE_SIZE counters)")
     ap.add_argument("--train-maxit", type=int, default=300, help="iteration cap of the reference solve for training")
     ap.add_argument("--lds-budget", type=int, default=0, help="LDS bytes per translation tile (0 = library default)")
+    ap.add_argument("--mfma", type=int, default=1, help="matrix-core tiles: 0 never, 1 library rule/autotuner, 2 every lane batch")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -85,7 +86,7 @@ def main():
     rs, rec = synth.source_and_receivers(room, 64, nsrc=4)
     n = room.n
     log(f"workload {args.workload}: N={n} k={k:.3f}")
-    ctx = F.Context(0, lds_budget=args.lds_budget, autotune=0 if args.no_autotune else 1)
+    ctx = F.Context(0, lds_budget=args.lds_budget, autotune=0 if args.no_autotune else 1, mfma=args.mfma)
     ctx.fmmbem_set_mesh(room.vertices, room.triangles)
     ctx.fmmbem_set_wavenumber(k)
     ctx.fmmbem_set_admittance(room.beta)
@@ -99,7 +100,7 @@ def main():
         f"lds_max {info.lds_max}")
     shapes = ctx.fmmbem_batch_shapes()
     for s in shapes:
-        log(f"  tiles L{s['level']} {s['kind']}: {'lane' if s['lane'] else ('whole' if s['whole'] else 'degree')} "
+        log(f"  tiles L{s['level']} {s['kind']}: {('mfma' if s['mfma'] else 'lane') if s['lane'] else ('whole' if s['whole'] else 'degree')} "
             f"JT {s['jt']} jobs {s['jobs']} {s['ms']:.3f} ms")
 
     dev = torch.device("cuda:0")

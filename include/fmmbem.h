@@ -110,6 +110,11 @@ typedef struct {
     int streams;         /* 2: the near field, the M2M chain, the upper levels' M2L and the L2L
                             chain of a product run on a second stream beside P2M and the leaf
                             levels' M2L; 1: one stream; default 2 */
+    int mfma;            /* matrix-core tiles for the FP64 stages of one-job-per-lane batches
+                            (each degree/order of a 64-job tile as a real GEMM on
+                            v_mfma_f64_16x16x4f64): 1 for batches with p >= 24 under the fixed
+                            rule, and the autotuner measures them for every lane batch; 2 for
+                            every lane batch; 0 never; default 1 */
 } fmmbem_options;
 
 void fmmbem_default_options(fmmbem_options *opt);
@@ -315,10 +320,11 @@ int fmmbem_near_entries(fmmbem_ctx *ctx, int64_t *nnz, int64_t *rows, int64_t *c
 
 /* Tile shape of every translation batch (from the fixed rule, or measured when the options
  * ask for autotuning): level, kind 0 = M2L at that level, 1 = M2M into it, 2 = L2L out of it,
- * one-job-per-lane flag, whole-vector flag, jobs per tile, and the measured FP64 time of the
- * batch's four stages (0 when not measured). */
+ * one-job-per-lane flag, whole-vector flag, jobs per tile, matrix-core flag (FP64 stages of a
+ * lane batch on MFMA), and the measured FP64 time of the batch's four stages (0 when not
+ * measured). */
 typedef struct {
-    int32_t level, kind, lane, whole, jt;
+    int32_t level, kind, lane, whole, jt, mfma;
     int64_t jobs;
     double ms;
 } fmmbem_batch_shape;

@@ -358,6 +358,7 @@ static void make_batch(fmmbem_ctx *c, const std::string &name, std::vector<JobH>
     if (b.lane) {
         b.whole = 0;
         b.JT = 64;
+        b.mfma = c->opt.mfma == 2 || (c->opt.mfma == 1 && b.P >= 24);
     } else {
         b.whole = trans_pick_jt(b.P, budget, 1) >= 8 && (size_t)8 * 16 * b.P * b.P <= budget;
         b.JT = trans_pick_jt(b.P, budget, b.whole);
@@ -650,7 +651,7 @@ static std::vector<BatchRef> all_batches(fmmbem_ctx *c) {
 static void record_shapes(fmmbem_ctx *c) {
     c->shapes.clear();
     for (auto &r : all_batches(c))
-        c->shapes.push_back({r.level, r.kind, r.b->lane, r.b->whole, r.b->JT, r.b->nreal, 0.0});
+        c->shapes.push_back({r.level, r.kind, r.b->lane, r.b->whole, r.b->JT, r.b->mfma, r.b->nreal, 0.0});
 }
 
 // Tile-shape autotuner: for every batch, time its four stages (FP64, one vector) under each
@@ -669,7 +670,7 @@ static void autotune_batches(fmmbem_ctx *c) {
         if (b.njob == 0) continue;
         const std::vector<JobH> &jobs = c->batch_jobs[r.name];
         struct Shape {
-            int lane, whole, jt;
+            int lane, whole, jt, mfma;
         };
         std::vector<Shape> cand;
         int64_t pad64 = 0;
@@ -679,16 +680,20 @@ static void autotune_batches(fmmbem_ctx *c) {
             pad64 += (int64_t)((e - q + 63) / 64) * 64;
             q = e;
         }
-        if (pad64 <= 2 * (int64_t)jobs.size()) cand.push_back({1, 0, 64});
+        if (pad64 <= 2 * (int64_t)jobs.size()) {
+            cand.push_back({1, 0, 64, 0});
+            if (c->opt.mfma != 0) cand.push_back({1, 0, 64, 1});
+        }
         for (int whole = 0; whole < 2; ++whole)
             for (int jt : {4, 8, 12, 16, 24, 32, 48, 64})
-                if (trans_lds_bytes(jt, b.P, whole) <= cap && (whole == 0 || jt >= 4)) cand.push_back({0, whole, jt});
+                if (trans_lds_bytes(jt, b.P, whole) <= cap && (whole == 0 || jt >= 4)) cand.push_back({0, whole, jt, 0});
         double best = 1e300;
-        Shape bs = {b.lane, b.whole, b.JT};
+        Shape bs = {b.lane, b.whole, b.JT, b.mfma};
         for (const Shape &sh : cand) {
             b.lane = sh.lane;
             b.whole = sh.whole;
             b.JT = sh.jt;
+            b.mfma = sh.mfma;
             layout_batch(c, r.name, jobs, b);
             const TransTables<double> tb{r.coax, b.H, b.HT};
             run_batch<double>(c, 1, b, r.src, r.dst, tb, ph);  // warm-up (allocates the work rows)
@@ -706,8 +711,9 @@ static void autotune_batches(fmmbem_ctx *c) {
         b.lane = bs.lane;
         b.whole = bs.whole;
         b.JT = bs.jt;
+        b.mfma = bs.mfma;
         layout_batch(c, r.name, jobs, b);
-        c->shapes.push_back({r.level, r.kind, b.lane, b.whole, b.JT, b.nreal, best});
+        c->shapes.push_back({r.level, r.kind, b.lane, b.whole, b.JT, b.mfma, b.nreal, best});
     }
     HIP_OK(hipStreamSynchronize(st));
     (void)hipEventDestroy(e0);
@@ -1216,6 +1222,7 @@ void fmmbem_default_options(fmmbem_options *o) {
     o->autotune = 0;
     o->lane_tiles = 1;
     o->streams = 2;
+    o->mfma = 1;
 }
 
 void fmmbem_default_solve_opts(fmmbem_solve_opts *o) {

@@ -123,6 +123,7 @@ struct TransBatch {
     float *H32 = nullptr, *HT32 = nullptr;              // FP32 copies (mixed precision)
     int whole = 0;                                      // whole-vector tiles (small p) or per-degree slices
     int lane = 0;                                       // one job per lane, 64-job tiles (many jobs per class)
+    int mfma = 0;                                       // lane batch whose FP64 stages run on matrix cores
     int64_t ntgt = 0;                                   // target boxes
     int32_t *tgt_start = nullptr, *tgt_jobs = nullptr;  // jobs of each target (CSR, padded job indices)
     // lane batches: consecutive jobs of one class with one target form a run (never crossing a

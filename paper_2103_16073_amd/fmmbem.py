@@ -34,7 +34,8 @@ class Options(ctypes.Structure):
     _fields_ = [("rc_factor", ctypes.c_double), ("rc", ctypes.c_double), ("leaf_max", ctypes.c_int),
                 ("p_min", ctypes.c_int), ("p_excess", ctypes.c_double), ("ktau_switch", ctypes.c_double),
                 ("max_depth", ctypes.c_int), ("lds_budget", ctypes.c_int), ("graphs", ctypes.c_int),
-                ("autotune", ctypes.c_int), ("lane_tiles", ctypes.c_int), ("streams", ctypes.c_int)]
+                ("autotune", ctypes.c_int), ("lane_tiles", ctypes.c_int), ("streams", ctypes.c_int),
+                ("mfma", ctypes.c_int)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -53,7 +54,8 @@ class SolveReport(ctypes.Structure):
 
 class BatchShape(ctypes.Structure):
     _fields_ = [("level", ctypes.c_int32), ("kind", ctypes.c_int32), ("lane", ctypes.c_int32),
-                ("whole", ctypes.c_int32), ("jt", ctypes.c_int32), ("jobs", ctypes.c_int64), ("ms", ctypes.c_double)]
+                ("whole", ctypes.c_int32), ("jt", ctypes.c_int32), ("mfma", ctypes.c_int32), ("jobs", ctypes.c_int64),
+                ("ms", ctypes.c_double)]
 
 
 class TrainOpts(ctypes.Structure):
@@ -338,7 +340,7 @@ class Context:
         arr = (BatchShape * max(1, cnt.value))()
         self._check(lib().fmmbem_batch_shapes(self.h, cnt.value, arr, ctypes.byref(cnt)))
         return [{"level": s.level, "kind": ("m2l", "m2m", "l2l")[s.kind], "lane": s.lane, "whole": s.whole,
-                 "jt": s.jt, "jobs": s.jobs, "ms": s.ms} for s in arr[:cnt.value]]
+                 "jt": s.jt, "mfma": s.mfma, "jobs": s.jobs, "ms": s.ms} for s in arr[:cnt.value]]
 
     def fmmbem_release_workspace(self):
         self._check(lib().fmmbem_release_workspace(self.h))

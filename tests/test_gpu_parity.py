@@ -124,14 +124,16 @@ def test_matvec_exact_far_vs_dense(F, cfg1_dense):
     ctx.close()
 
 
-@pytest.mark.parametrize("leaf_max,lds_budget,lane", [(64, 0, 0), (12, 0, 0), (12, 8192, 0), (64, 8192, 0),
-                                                       (64, 0, 2), (12, 0, 2)])
-def test_matvec_fmm_vs_dense(F, cfg1_dense, leaf_max, lds_budget, lane):
+@pytest.mark.parametrize("leaf_max,lds_budget,lane,mfma", [(64, 0, 0, 0), (12, 0, 0, 0), (12, 8192, 0, 0),
+                                                            (64, 8192, 0, 0), (64, 0, 2, 0), (12, 0, 2, 0),
+                                                            (64, 0, 2, 2), (12, 0, 2, 2)])
+def test_matvec_fmm_vs_dense(F, cfg1_dense, leaf_max, lds_budget, lane, mfma):
     """FP64 FMM product against the oracle's dense operator: relative L2 <= 1e-6, for octrees of
     depth 2 and 3 (so M2M/L2L are exercised), with the whole-vector LDS tiles, the per-degree
-    kernels (small LDS budget) and the one-job-per-lane kernels (lane=2 forces them)."""
+    kernels (small LDS budget), the one-job-per-lane kernels (lane=2 forces them) and the
+    matrix-core tiles (mfma=2 puts every lane batch on them)."""
     room, k = cfg1_dense
-    ctx = make_ctx(F, room, k, leaf_max=leaf_max, lds_budget=lds_budget, lane_tiles=lane)
+    ctx = make_ctx(F, room, k, leaf_max=leaf_max, lds_budget=lds_budget, lane_tiles=lane, mfma=mfma)
     info = ctx.fmmbem_get_info()
     L, M = bem.dense_LM(room.vertices, room.triangles, k, info.rc)
     for seed in (1, 2):
@@ -234,13 +236,14 @@ def test_solve_inner_outer_vs_oracle_lu(F, cfg1_dense):
     ctx.close()
 
 
-@pytest.mark.parametrize("leaf_max,lds_budget,lane", [(12, 0, 0), (12, 8192, 0), (64, 0, 0), (12, 0, 2)])
-def test_matvec_multi_rhs(F, cfg1_dense, leaf_max, lds_budget, lane):
+@pytest.mark.parametrize("leaf_max,lds_budget,lane,mfma", [(12, 0, 0, 0), (12, 8192, 0, 0), (64, 0, 0, 0),
+                                                            (12, 0, 2, 0), (12, 0, 2, 2)])
+def test_matvec_multi_rhs(F, cfg1_dense, leaf_max, lds_budget, lane, mfma):
     """Seven vectors in one call (chunks of 4, 2 and 1 vectors sharing kernel evaluations,
     basis functions and translation tables) give the single-vector products and match the
     oracle's dense operator (FP64 <= 1e-6, mixed <= 1e-4)."""
     room, k = cfg1_dense
-    ctx = make_ctx(F, room, k, leaf_max=leaf_max, lds_budget=lds_budget, lane_tiles=lane)
+    ctx = make_ctx(F, room, k, leaf_max=leaf_max, lds_budget=lds_budget, lane_tiles=lane, mfma=mfma)
     info = ctx.fmmbem_get_info()
     L, M = bem.dense_LM(room.vertices, room.triangles, k, info.rc)
     X = np.stack([synth.complex_normal(room.n, 20 + s) for s in range(7)])
