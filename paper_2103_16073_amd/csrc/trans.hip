@@ -803,10 +803,18 @@ __global__ void __launch_bounds__(64) k_tl_coax(TransArgsT<R> a, int nsplit) {
 // D[l/16 + 4i][l%16] (i = 0..3).  A workgroup of 4 wavefronts takes one (tile, degree) or (tile,
 // order); wavefront w owns columns 32w..32w+31 (jobs 16w..16w+15), all rows, in groups of row
 // blocks (16 rows each).  Same tile layout and work rows as the lane kernels.
-typedef double tm_v4d __attribute__((ext_vector_type(4)));
-__device__ inline tm_v4d tm_mfma(double a, double b, tm_v4d c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
+// FP32 (mixed products): v_mfma_f32_16x16x4f32, same A and B fragments, D[4 (l/16) + i][l%16].
+template <class R> struct TmOp;
+template <> struct TmOp<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ inline v4 mma(double a, double b, v4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    static __device__ inline int row(int kq, int i) { return kq + 4 * i; }
+};
+template <> struct TmOp<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static __device__ inline v4 mma(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    static __device__ inline int row(int kq, int i) { return 4 * kq + i; }
+};
 constexpr int TM_KC = 16;   // K rows per LDS chunk (double-buffered)
 constexpr int TM_LD = 130;  // LDS row stride (doubles) of the staged A and B chunks
 // LDS of a rotation block: two A chunks and two B chunks (the back rotation reuses it for 64
@@ -819,16 +827,19 @@ constexpr int TM_LDS = 4 * TM_KC * TM_LD;
 //   FWD:  Y = H X, X = e^{i m a} c_n of the sources, A[r][k] = H[r][k] = HT[k][r]; rows -> W1.
 //   !FWD: Y = H^T X, X = W2 rows, A[r][k] = H[k][r]; the pass's outputs go through LDS, are
 //         phased (e^{-i m a}), summed over the runs of one target and stored job-major in W1.
-template <bool FWD, int RBG>
-__global__ void __launch_bounds__(256) k_tm_rot(TransArgsT<double> a) {
+template <class R, bool FWD, int RBG>
+__global__ void __launch_bounds__(256) k_tm_rot(TransArgsT<R> a) {
+    using C = typename Cx<R>::T;
+    using Op = TmOp<R>;
+    using v4 = typename Op::v4;
     constexpr int RG = 16 * RBG;  // rows per pass
     static_assert(RG <= 128 && (FWD || RG * TM_LD <= TM_LDS), "pass too large for the LDS block");
-    __shared__ double lds[TM_LDS];
+    __shared__ R lds[TM_LDS];
     __shared__ int64_t soff[LANE_JT];
     __shared__ int32_t sdir[LANE_JT];
     __shared__ int segl[LANE_JT];
-    auto As = [&](int buf, int k, int r) -> double & { return lds[(buf * TM_KC + k) * TM_LD + r]; };
-    auto Bs = [&](int buf, int k, int c) -> double & { return lds[((2 + buf) * TM_KC + k) * TM_LD + c]; };
+    auto As = [&](int buf, int k, int r) -> R & { return lds[(buf * TM_KC + k) * TM_LD + r]; };
+    auto Bs = [&](int buf, int k, int c) -> R & { return lds[((2 + buf) * TM_KC + k) * TM_LD + c]; };
     int tile, n;
     xcd_block(tile, n);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -843,26 +854,26 @@ __global__ void __launch_bounds__(256) k_tm_rot(TransArgsT<double> a) {
     __syncthreads();
     const int w = 2 * n + 1, RB = (w + 15) / 16;
     const int tr = a.tile_rot[tile / a.nr];
-    const double *Mn = (FWD ? a.HT : a.H) + (int64_t)tr * rot_table_size(a.P) + rot_block_off(n);
-    const double *Xin = (const double *)a.W2;
+    const R *Mn = (FWD ? a.HT : a.H) + (int64_t)tr * rot_table_size(a.P) + rot_block_off(n);
+    const R *Xin = (const R *)a.W2;
     const int colw = 32 * wv + (lane & 15), kq = lane >> 4;
     const int nch = (w + TM_KC - 1) / TM_KC;
     constexpr int NA = TM_KC * RG / 256;  // A values staged per thread
     for (int rb0 = 0; rb0 < RB; rb0 += RBG) {
         const int r0 = rb0 * 16;
-        double ra[NA], rbv[8];
+        R ra[NA], rbv[8];
         auto gload = [&](int kc) {
 #pragma unroll
             for (int i = 0; i < NA; ++i) {
                 const int e = tid + 256 * i, kk = e / RG, rr = e % RG, k = kc + kk, r = r0 + rr;
-                ra[i] = (k < w && r < w) ? Mn[(int64_t)k * w + r] : 0.0;
+                ra[i] = (k < w && r < w) ? Mn[(int64_t)k * w + r] : R(0);
             }
             if (FWD) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int e = tid + 256 * i, kk = e / LANE_JT, j = e % LANE_JT, k = kc + kk;
-                    double2 x = cmk(0, 0);
-                    if (k < w) x = cmul(a.ph[sdir[j] + k - n], a.src[soff[j] + n * n + k]);  // e^{i m a} c_n^m
+                    C x = mkc<C>(0, 0);
+                    if (k < w) x = mulc(a.ph[sdir[j] + k - n], a.src[soff[j] + n * n + k]);  // e^{i m a} c_n^m
                     rbv[2 * i] = x.x;
                     rbv[2 * i + 1] = x.y;
                 }
@@ -870,7 +881,7 @@ __global__ void __launch_bounds__(256) k_tm_rot(TransArgsT<double> a) {
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
                     const int e = tid + 256 * i, kk = e / 128, col = e % 128, k = kc + kk;
-                    rbv[i] = k < w ? Xin[((int64_t)tile * P2 + n * n + k) * 128 + col] : 0.0;
+                    rbv[i] = k < w ? Xin[((int64_t)tile * P2 + n * n + k) * 128 + col] : R(0);
                 }
             }
         };
@@ -895,9 +906,9 @@ __global__ void __launch_bounds__(256) k_tm_rot(TransArgsT<double> a) {
                 }
             }
         };
-        tm_v4d acc[RBG][2];
+        v4 acc[RBG][2];
 #pragma unroll
-        for (int q = 0; q < RBG; ++q) acc[q][0] = acc[q][1] = tm_v4d{0, 0, 0, 0};
+        for (int q = 0; q < RBG; ++q) acc[q][0] = acc[q][1] = v4{0, 0, 0, 0};
         gload(0);
         __syncthreads();  // the previous pass's readers of the LDS block are done
         lstore(0);
@@ -907,13 +918,13 @@ __global__ void __launch_bounds__(256) k_tm_rot(TransArgsT<double> a) {
             if (c + 1 < nch) gload((c + 1) * TM_KC);
             const int kn = min(TM_KC, w - c * TM_KC);
             for (int ks = 0; ks < kn; ks += 4) {
-                const double b0 = Bs(buf, ks + kq, colw), b1 = Bs(buf, ks + kq, colw + 16);
+                const R b0 = Bs(buf, ks + kq, colw), b1 = Bs(buf, ks + kq, colw + 16);
 #pragma unroll
                 for (int q = 0; q < RBG; ++q) {
                     if (rb0 + q >= RB) break;
-                    const double av = As(buf, ks + kq, q * 16 + (lane & 15));
-                    acc[q][0] = tm_mfma(av, b0, acc[q][0]);
-                    acc[q][1] = tm_mfma(av, b1, acc[q][1]);
+                    const R av = As(buf, ks + kq, q * 16 + (lane & 15));
+                    acc[q][0] = Op::mma(av, b0, acc[q][0]);
+                    acc[q][1] = Op::mma(av, b1, acc[q][1]);
                 }
             }
             if (c + 1 < nch) {
@@ -922,7 +933,7 @@ __global__ void __launch_bounds__(256) k_tm_rot(TransArgsT<double> a) {
             }
         }
         if (FWD) {
-            double *Wout = (double *)a.W1;
+            R *Wout = (R *)a.W1;
 #pragma unroll
             for (int q = 0; q < RBG; ++q) {
                 if (rb0 + q >= RB) break;
@@ -930,7 +941,7 @@ __global__ void __launch_bounds__(256) k_tm_rot(TransArgsT<double> a) {
                 for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        const int r = (rb0 + q) * 16 + kq + 4 * i;
+                        const int r = (rb0 + q) * 16 + Op::row(kq, i);
                         if (r < w) Wout[((int64_t)tile * P2 + n * n + r) * 128 + colw + 16 * cb] = acc[q][cb][i];
                     }
             }
@@ -943,17 +954,17 @@ __global__ void __launch_bounds__(256) k_tm_rot(TransArgsT<double> a) {
 #pragma unroll
                 for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) lds[(q * 16 + kq + 4 * i) * TM_LD + colw + 16 * cb] = acc[q][cb][i];
+                    for (int i = 0; i < 4; ++i) lds[(q * 16 + Op::row(kq, i)) * TM_LD + colw + 16 * cb] = acc[q][cb][i];
             __syncthreads();
             const int nrow = min(RG, w - r0);
             for (int e = tid; e < RG * LANE_JT; e += 256) {
                 const int j = e / RG, rr = e % RG, r = r0 + rr;
                 const int len = segl[j];
                 if (rr >= nrow || len == 0) continue;
-                double2 v = cmk(0, 0);
+                C v = mkc<C>(0, 0);
                 for (int t = 0; t < len; ++t) {
                     const int jj = j + t * a.nr;
-                    v = cadd(v, cmulc(cmk(lds[rr * TM_LD + 2 * jj], lds[rr * TM_LD + 2 * jj + 1]),
+                    v = addc(v, mulcc(mkc<C>(lds[rr * TM_LD + 2 * jj], lds[rr * TM_LD + 2 * jj + 1]),
                                       a.ph[sdir[jj] + r - n]));  // e^{-i m a}
                 }
                 a.W1[(J0 + j) * (int64_t)P2 + n * n + r] = v;
@@ -967,50 +978,54 @@ __global__ void __launch_bounds__(256) k_tm_rot(TransArgsT<double> a) {
 // staged in LDS as for the rotations.  With X' the input with each job's real and imaginary
 // columns swapped and the new real one negated (read from the partner column of X in LDS),
 // Y = Re(T) X + Im(T) X' column by column, so one accumulator set takes both real GEMMs.
-__global__ void __launch_bounds__(256) k_tm_coax(TransArgsT<double> a) {
+template <class R>
+__global__ void __launch_bounds__(256) k_tm_coax(TransArgsT<R> a) {
+    using C = typename Cx<R>::T;
+    using Op = TmOp<R>;
+    using v4 = typename Op::v4;
     constexpr int RBG = 4, RG = 16 * RBG, LA = RG + 2;
     // A: real part (chunks 0, 1) and imaginary part (2, 3), RG + 2 columns; B: X (2 chunks)
-    __shared__ double ldsA[4 * TM_KC * LA];
-    __shared__ double ldsB[2 * TM_KC * TM_LD];
-    auto Ar = [&](int buf, int k, int r) -> double & { return ldsA[(buf * TM_KC + k) * LA + r]; };
-    auto Ai = [&](int buf, int k, int r) -> double & { return ldsA[((2 + buf) * TM_KC + k) * LA + r]; };
-    auto Bs = [&](int buf, int k, int c) -> double & { return ldsB[(buf * TM_KC + k) * TM_LD + c]; };
+    __shared__ R ldsA[4 * TM_KC * LA];
+    __shared__ R ldsB[2 * TM_KC * TM_LD];
+    auto Ar = [&](int buf, int k, int r) -> R & { return ldsA[(buf * TM_KC + k) * LA + r]; };
+    auto Ai = [&](int buf, int k, int r) -> R & { return ldsA[((2 + buf) * TM_KC + k) * LA + r]; };
+    auto Bs = [&](int buf, int k, int c) -> R & { return ldsB[(buf * TM_KC + k) * TM_LD + c]; };
     int tile, mi;
     xcd_block(tile, mi);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int P2 = a.P * a.P, pt = a.ptgt, pm = min(a.psrc, a.ptgt);
     const int m = mi - (pt - 1), am = m < 0 ? -m : m;
     const int rows = pt - am;
-    double *Wout = (double *)a.W2;
-    const double *Xin = (const double *)a.W1;
+    R *Wout = (R *)a.W2;
+    const C *Xin = a.W1;
     if (am >= pm) {  // no source of this order
         for (int e = tid; e < rows * 128; e += 256) {
             const int nn = am + e / 128;
-            Wout[((int64_t)tile * P2 + nn * nn + nn + m) * 128 + e % 128] = 0.0;
+            Wout[((int64_t)tile * P2 + nn * nn + nn + m) * 128 + e % 128] = R(0);
         }
         return;
     }
     const int B = a.PT - am, cin = a.psrc - am, RB = (rows + 15) / 16;
-    const double2 *Tm = a.coax + (int64_t)a.tile_coax[tile / a.nr] * coax_table_size(a.PT) + coax_block_off(a.PT, am);
+    const C *Tm = a.coax + (int64_t)a.tile_coax[tile / a.nr] * coax_table_size(a.PT) + coax_block_off(a.PT, am);
     const int colw = 32 * wv + (lane & 15), kq = lane >> 4;
-    const double swp = (colw & 1) ? 1.0 : -1.0;
+    const R swp = (colw & 1) ? R(1) : R(-1);
     const int nch = (cin + TM_KC - 1) / TM_KC;
     for (int rb0 = 0; rb0 < RB; rb0 += RBG) {
         const int r0 = rb0 * 16;
-        double2 ta[TM_KC * RG / 256];
-        double2 xb[4];  // (re, im) of 4 (k, job) inputs
+        C ta[TM_KC * RG / 256];
+        C xb[4];  // (re, im) of 4 (k, job) inputs
         auto gload = [&](int kc) {
 #pragma unroll
             for (int i = 0; i < TM_KC * RG / 256; ++i) {
                 const int e = tid + 256 * i, kk = e / RG, rr = e % RG, k = kc + kk, r = r0 + rr;
-                double2 t = (k < cin && r < rows) ? Tm[(int64_t)k * B + r] : cmk(0, 0);
-                if ((k + r) & 1) t = cmk(-t.x, -t.y);
+                C t = (k < cin && r < rows) ? Tm[(int64_t)k * B + r] : mkc<C>(0, 0);
+                if ((k + r) & 1) t = mkc<C>(-t.x, -t.y);
                 ta[i] = t;
             }
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int e = tid + 256 * i, kk = e / LANE_JT, j = e % LANE_JT, k = kc + kk, nb = am + k;
-                xb[i] = k < cin ? ((const double2 *)Xin)[((int64_t)tile * P2 + nb * nb + nb + m) * 64 + j] : cmk(0, 0);
+                xb[i] = k < cin ? Xin[((int64_t)tile * P2 + nb * nb + nb + m) * 64 + j] : mkc<C>(0, 0);
             }
         };
         auto lstore = [&](int buf) {
@@ -1027,9 +1042,9 @@ __global__ void __launch_bounds__(256) k_tm_coax(TransArgsT<double> a) {
                 Bs(buf, kk, 2 * j + 1) = xb[i].y;
             }
         };
-        tm_v4d acc[RBG][2];
+        v4 acc[RBG][2];
 #pragma unroll
-        for (int q = 0; q < RBG; ++q) acc[q][0] = acc[q][1] = tm_v4d{0, 0, 0, 0};
+        for (int q = 0; q < RBG; ++q) acc[q][0] = acc[q][1] = v4{0, 0, 0, 0};
         gload(0);
         __syncthreads();
         lstore(0);
@@ -1039,18 +1054,18 @@ __global__ void __launch_bounds__(256) k_tm_coax(TransArgsT<double> a) {
             if (c + 1 < nch) gload((c + 1) * TM_KC);
             const int kn = min(TM_KC, cin - c * TM_KC);
             for (int ks = 0; ks < kn; ks += 4) {
-                const double b0 = Bs(buf, ks + kq, colw), b1 = Bs(buf, ks + kq, colw + 16);
+                const R b0 = Bs(buf, ks + kq, colw), b1 = Bs(buf, ks + kq, colw + 16);
                 // X': column 2j holds -Im x_j, column 2j+1 holds Re x_j (the partner column)
-                const double w0 = swp * Bs(buf, ks + kq, colw ^ 1), w1 = swp * Bs(buf, ks + kq, (colw + 16) ^ 1);
+                const R w0 = swp * Bs(buf, ks + kq, colw ^ 1), w1 = swp * Bs(buf, ks + kq, (colw + 16) ^ 1);
 #pragma unroll
                 for (int q = 0; q < RBG; ++q) {
                     if (rb0 + q >= RB) break;
-                    const double ar = Ar(buf, ks + kq, q * 16 + (lane & 15));
-                    const double ai = Ai(buf, ks + kq, q * 16 + (lane & 15));
-                    acc[q][0] = tm_mfma(ar, b0, acc[q][0]);
-                    acc[q][1] = tm_mfma(ar, b1, acc[q][1]);
-                    acc[q][0] = tm_mfma(ai, w0, acc[q][0]);
-                    acc[q][1] = tm_mfma(ai, w1, acc[q][1]);
+                    const R ar = Ar(buf, ks + kq, q * 16 + (lane & 15));
+                    const R ai = Ai(buf, ks + kq, q * 16 + (lane & 15));
+                    acc[q][0] = Op::mma(ar, b0, acc[q][0]);
+                    acc[q][1] = Op::mma(ar, b1, acc[q][1]);
+                    acc[q][0] = Op::mma(ai, w0, acc[q][0]);
+                    acc[q][1] = Op::mma(ai, w1, acc[q][1]);
                 }
             }
             if (c + 1 < nch) {
@@ -1065,7 +1080,7 @@ __global__ void __launch_bounds__(256) k_tm_coax(TransArgsT<double> a) {
             for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const int r = (rb0 + q) * 16 + kq + 4 * i, nn = am + r;
+                    const int r = (rb0 + q) * 16 + Op::row(kq, i), nn = am + r;
                     if (r < rows) Wout[((int64_t)tile * P2 + nn * nn + nn + m) * 128 + colw + 16 * cb] = acc[q][cb][i];
                 }
         }
@@ -1141,18 +1156,16 @@ const char *trans_stage(const TransBatch &b, const TransTables<R> &tb, int stage
     const size_t lds = trans_lds_bytes(b.JT, b.P, b.whole) / (sizeof(double) / sizeof(R));
     const bool f32 = sizeof(R) == 4;
     const char *name = "";
-    if constexpr (sizeof(R) == 8) {
-        // FP64 stages of a lane batch on matrix cores (the FP32 stages keep the lane kernels)
-        if (b.lane && b.mfma && stage < 3) {
-            if (b.JT != LANE_JT) throw FmmError(-1, "lane batches use 64-job tiles");
-            switch (stage) {
-            case 0: k_tm_rot<true, 8><<<dim3(ntile, b.psrc), 256, 0, st>>>(a), name = "k_tm_rot_fwd"; break;
-            case 1: k_tm_coax<<<dim3(ntile, 2 * b.ptgt - 1), 256, 0, st>>>(a), name = "k_tm_coax"; break;
-            default: k_tm_rot<false, 4><<<dim3(ntile, b.ptgt), 256, 0, st>>>(a), name = "k_tm_rot_back";
-            }
-            LAUNCH_OK();
-            return name;
+    if (b.lane && b.mfma && stage < 3) {
+        // stages of a lane batch on matrix cores (FP64, or FP32 for mixed products)
+        if (b.JT != LANE_JT) throw FmmError(-1, "lane batches use 64-job tiles");
+        switch (stage) {
+        case 0: k_tm_rot<R, true, 8><<<dim3(ntile, b.psrc), 256, 0, st>>>(a), name = f32 ? "k_tm_rot_fwd_f32" : "k_tm_rot_fwd"; break;
+        case 1: k_tm_coax<R><<<dim3(ntile, 2 * b.ptgt - 1), 256, 0, st>>>(a), name = f32 ? "k_tm_coax_f32" : "k_tm_coax"; break;
+        default: k_tm_rot<R, false, 4><<<dim3(ntile, b.ptgt), 256, 0, st>>>(a), name = f32 ? "k_tm_rot_back_f32" : "k_tm_rot_back";
         }
+        LAUNCH_OK();
+        return name;
     }
     if (b.lane && stage < 3) {
         if (b.JT != LANE_JT) throw FmmError(-1, "lane batches use 64-job tiles");

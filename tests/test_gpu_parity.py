@@ -146,12 +146,14 @@ def test_matvec_fmm_vs_dense(F, cfg1_dense, leaf_max, lds_budget, lane, mfma):
     ctx.close()
 
 
-@pytest.mark.parametrize("leaf_max,lds_budget,lane", [(64, 0, 0), (12, 0, 0), (12, 8192, 0), (12, 0, 2)])
-def test_matvec_mixed_vs_dense(F, cfg1_dense, leaf_max, lds_budget, lane):
+@pytest.mark.parametrize("leaf_max,lds_budget,lane,mfma", [(64, 0, 0, 0), (12, 0, 0, 0), (12, 8192, 0, 0),
+                                                            (12, 0, 2, 0), (12, 0, 2, 2)])
+def test_matvec_mixed_vs_dense(F, cfg1_dense, leaf_max, lds_budget, lane, mfma):
     """Mixed-precision product (FP32 near field and translations, FP64 tables converted once,
-    FP64 densities, P2M and L2P) against the oracle's dense operator: relative L2 <= 1e-4."""
+    FP64 densities, P2M and L2P) against the oracle's dense operator: relative L2 <= 1e-4, with
+    the LDS tiles, the one-job-per-lane kernels and the FP32 matrix-core tiles."""
     room, k = cfg1_dense
-    ctx = make_ctx(F, room, k, leaf_max=leaf_max, lds_budget=lds_budget, lane_tiles=lane)
+    ctx = make_ctx(F, room, k, leaf_max=leaf_max, lds_budget=lds_budget, lane_tiles=lane, mfma=mfma)
     info = ctx.fmmbem_get_info()
     L, M = bem.dense_LM(room.vertices, room.triangles, k, info.rc)
     for seed in (1, 2):
