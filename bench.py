@@ -158,13 +158,27 @@ def main():
     flops_per_launch = dom["flops"] / dom["launches"]
     achieved = flops_per_launch / (avg_ms * 1e-3)
     traffic = measured_traffic(dom["name"]) if (args.workload == 3 and not args.no_autotune) else None
-    roofline = {"kernel": dom["name"], "bound": "alu", "achieved": achieved / 1e12, "peak": PEAKS["fp64"] / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / PEAKS["fp64"], "traffic": traffic,
-                "traffic_GBps": None if traffic is None else traffic / (avg_ms * 1e-3) / 1e9,
-                "algorithmic_bytes_per_launch": dom["bytes"] / dom["launches"],
-                "avg_launch_ms": avg_ms, "launches_per_step": dom["launches"] / args.steps,
-                "algorithmic_flops_per_launch": flops_per_launch}
-    log(f"dominant kernel {dom['name']}: {avg_ms:.3f} ms/launch, {achieved/1e12:.3f} TFLOP/s")
+    # bound from the kernel's arithmetic intensity against the FP64 ridge point (peak flops over
+    # peak HBM bandwidth): below it the HBM roofline is the one that bounds the kernel
+    bytes_per_launch = dom["bytes"] / dom["launches"]
+    intensity = flops_per_launch / bytes_per_launch
+    ridge = PEAKS["fp64"] / PEAKS["hbm"]
+    bw = bytes_per_launch / (avg_ms * 1e-3)
+    if intensity < ridge:
+        roofline = {"kernel": dom["name"], "bound": "hbm", "achieved": bw / 1e9, "peak": PEAKS["hbm"] / 1e9,
+                    "unit": "GB/s", "frac": bw / PEAKS["hbm"]}
+    else:
+        roofline = {"kernel": dom["name"], "bound": "alu", "achieved": achieved / 1e12,
+                    "peak": PEAKS["fp64"] / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAKS["fp64"]}
+    roofline.update({"traffic": traffic,
+                     "traffic_GBps": None if traffic is None else traffic / (avg_ms * 1e-3) / 1e9,
+                     "algorithmic_bytes_per_launch": bytes_per_launch,
+                     "algorithmic_flops_per_launch": flops_per_launch,
+                     "arithmetic_intensity_flop_per_byte": intensity, "fp64_ridge_flop_per_byte": ridge,
+                     "alu_frac": achieved / PEAKS["fp64"], "hbm_frac": bw / PEAKS["hbm"],
+                     "avg_launch_ms": avg_ms, "launches_per_step": dom["launches"] / args.steps})
+    log(f"dominant kernel {dom['name']}: {avg_ms:.3f} ms/launch, {achieved/1e12:.3f} TFLOP/s, {bw/1e9:.0f} GB/s "
+        f"(intensity {intensity:.2f} flop/B, ridge {ridge:.2f}): {roofline['bound']} bound, frac {roofline['frac']:.3f}")
 
     y_h = y.cpu().numpy()
 

@@ -291,8 +291,11 @@ static void layout_batch(fmmbem_ctx *c, const std::string &name, const std::vect
             q2 = e;
         }
         b.seg = upload(c->buf, name + "_seg", seg, st);
+        b.nout = 0;
+        for (int8_t v : seg) b.nout += v > 0;
     } else {
         b.seg = nullptr;
+        b.nout = (int64_t)jobs.size();
     }
     // rows of every target (CSR over the padded order): every job, or the first job of each run
     {
@@ -610,10 +613,11 @@ static void run_batch(fmmbem_ctx *c, int nrv, const TransBatch &b, const typenam
     C *W1 = (C *)c->scratch.get(side ? "W1s" : "W1", sizeof(C) * (size_t)b.njob * nrv * b.P * b.P);
     C *W2 = (C *)c->scratch.get(side ? "W2s" : "W2", sizeof(C) * (size_t)b.njob * nrv * b.P * b.P);
     const double nr = (double)b.nreal * nrv, P2 = (double)b.P * b.P, cs = (double)sizeof(C);
+    const double no = (double)b.nout * nrv;  // output rows of the back rotation (runs or jobs)
     // algorithmic work per stage: flops of the matrices applied; bytes of the rows moved once
     const double fl[4] = {nr * rot_flops(b.psrc), nr * coax_flops(b.psrc, b.ptgt), nr * rot_flops(b.ptgt), nr * P2 * 2};
-    const double by[4] = {nr * cs * (b.psrc * b.psrc + P2), nr * cs * 2 * P2, nr * cs * 2 * P2,
-                          cs * (nr * P2 + 2.0 * b.ntgt * nrv * b.ptgt * b.ptgt)};
+    const double by[4] = {nr * cs * (b.psrc * b.psrc + P2), nr * cs * 2 * P2, cs * P2 * (nr + no),
+                          cs * (no * P2 + 2.0 * b.ntgt * nrv * b.ptgt * b.ptgt)};
     for (int stage = 0; stage < 4; ++stage) {
         int e = prof_begin(c);
         const char *name = trans_stage<R>(b, tb, stage, nrv, src, dst, ph, c->delta_p, W1, W2, st);

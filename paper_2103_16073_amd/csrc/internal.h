@@ -130,6 +130,7 @@ struct TransBatch {
     // 16-job boundary); seg[j] = run length at the run's first job, 0 elsewhere.  The back
     // rotation stores each run's sum in the first job's row and the CSR lists first jobs only.
     int8_t *seg = nullptr;
+    int64_t nout = 0;  // rows the back rotation stores (runs of lane batches, else jobs)
 };
 // runs of the back-rotation output never cross a multiple of this many (real) jobs, so that a
 // run lies in one 64-lane tile for 1, 2 or 4 right-hand sides
