@@ -331,7 +331,10 @@ __device__ inline void sincos_red(double x, double &s, double &c) {
 // ------------------------------------------------------------------ P2P + near table
 // y_i = sum_{j in neighbour leaves, |c_i - c_j| >= r_c} [G q_j + dG/dn_y w_j] + sum_near [L sigma + M mu]
 // with q_j = A_j sigma_j, w_j = A_j mu_j.  One workgroup (one wavefront) per target leaf,
-// source tiles staged in LDS.
+// source tiles staged in LDS.  A leaf of at most 32 (16) targets splits every source tile over
+// 2 (4) groups of lanes, one target per lane of a group, and adds the groups' sums at the end.
+__device__ inline int p2p_splits(int nt) { return nt <= 16 ? 4 : nt <= 32 ? 2 : 1; }
+
 template <int NR>
 __global__ void __launch_bounds__(64) k_p2p(int nleaf, const int32_t *leaf_start, const int32_t *nbr_start,
                                             const int32_t *nbr_list, int all_leaves, const double4 *ec,
@@ -341,11 +344,14 @@ __global__ void __launch_bounds__(64) k_p2p(int nleaf, const int32_t *leaf_start
     const int b = blockIdx.x, tid = threadIdx.x;
     __shared__ double sx[64], sy[64], sz[64], snx[64], sny[64], snz[64];
     __shared__ double2 sq[64 * NR], sw[64 * NR];
+    __shared__ double2 red[64 * NR];
     const int ts = leaf_start[b], te = leaf_start[b + 1];
     const int nb0 = all_leaves ? 0 : nbr_start[b], nb1 = all_leaves ? nleaf : nbr_start[b + 1];
     const double inv4pi = 1.0 / (4.0 * FMM_PI);
-    for (int t0 = ts; t0 < te; t0 += 64) {
-        const int t = t0 + tid;
+    const int S = p2p_splits(te - ts), TP = 64 / S;  // source splits, targets per pass
+    const int h = tid / TP;
+    for (int t0 = ts; t0 < te; t0 += TP) {
+        const int t = t0 + tid % TP;
         const bool act = t < te;
         double4 ct = act ? ec[t] : make_double4(0, 0, 0, 0);
         double2 acc[NR];
@@ -374,7 +380,7 @@ __global__ void __launch_bounds__(64) k_p2p(int nleaf, const int32_t *leaf_start
                 __syncthreads();
                 const int cnt = min(64, se - j0);
                 if (act) {
-                    for (int jj = 0; jj < cnt; ++jj) {
+                    for (int jj = h; jj < cnt; jj += S) {
                         double d2 = dist2_exact(ct.x, ct.y, ct.z, sx[jj], sy[jj], sz[jj]);
                         if (d2 < rc2) continue;
                         double dx = sx[jj] - ct.x, dy = sy[jj] - ct.y, dz = sz[jj] - ct.z;
@@ -395,7 +401,7 @@ __global__ void __launch_bounds__(64) k_p2p(int nleaf, const int32_t *leaf_start
             }
         }
         if (act) {
-            for (int e = near_start[t]; e < near_start[t + 1]; ++e) {
+            for (int e = near_start[t] + h; e < near_start[t + 1]; e += S) {
                 const int64_t j = near_col[e];
                 const double2 l = nL[e], m = nM[e];
 #pragma unroll
@@ -404,6 +410,18 @@ __global__ void __launch_bounds__(64) k_p2p(int nleaf, const int32_t *leaf_start
                     acc[rr] = cfma(m, mu[j * NR + rr], acc[rr]);
                 }
             }
+        }
+        if (S > 1) {  // add the groups' partial sums (group 0 keeps the result)
+            __syncthreads();
+#pragma unroll
+            for (int rr = 0; rr < NR; ++rr) red[tid * NR + rr] = acc[rr];
+            __syncthreads();
+            if (h == 0)
+                for (int g = 1; g < S; ++g)
+#pragma unroll
+                    for (int rr = 0; rr < NR; ++rr) acc[rr] = cadd(acc[rr], red[(tid + g * TP) * NR + rr]);
+        }
+        if (act && h == 0) {
 #pragma unroll
             for (int rr = 0; rr < NR; ++rr) y[(int64_t)t * NR + rr] = acc[rr];
         }
@@ -431,10 +449,13 @@ __global__ void __launch_bounds__(64) k_p2p32(int nleaf, const int32_t *leaf_sta
     __shared__ double sx[64], sy[64], sz[64];
     __shared__ float snx[64], sny[64], snz[64];
     __shared__ float2 sq[64 * NR], sw[64 * NR];
+    __shared__ double2 red[64 * NR];
     const int ts = leaf_start[b], te = leaf_start[b + 1];
     const float kf = (float)k, inv4pi = (float)(1.0 / (4.0 * FMM_PI));
-    for (int t0 = ts; t0 < te; t0 += 64) {
-        const int t = t0 + tid;
+    const int S = p2p_splits(te - ts), TP = 64 / S;  // source splits, targets per pass (as in k_p2p)
+    const int h = tid / TP;
+    for (int t0 = ts; t0 < te; t0 += TP) {
+        const int t = t0 + tid % TP;
         const bool act = t < te;
         double4 ct = act ? ec[t] : make_double4(0, 0, 0, 0);
         float ar[NR], ai[NR], cr[NR], ci[NR];
@@ -464,7 +485,7 @@ __global__ void __launch_bounds__(64) k_p2p32(int nleaf, const int32_t *leaf_sta
                 __syncthreads();
                 const int cnt = min(64, se - j0);
                 if (act) {
-                    for (int jj = 0; jj < cnt; ++jj) {
+                    for (int jj = h; jj < cnt; jj += S) {
                         double d2 = dist2_exact(ct.x, ct.y, ct.z, sx[jj], sy[jj], sz[jj]);
                         if (d2 < rc2) continue;
                         const float dx = (float)(sx[jj] - ct.x), dy = (float)(sy[jj] - ct.y), dz = (float)(sz[jj] - ct.z);
@@ -487,11 +508,11 @@ __global__ void __launch_bounds__(64) k_p2p32(int nleaf, const int32_t *leaf_sta
                 }
             }
         }
-        if (act) {
-            double2 acc[NR];
+        double2 acc[NR];
 #pragma unroll
-            for (int rr = 0; rr < NR; ++rr) acc[rr] = make_double2((double)ar[rr] - (double)cr[rr], (double)ai[rr] - (double)ci[rr]);
-            for (int e = near_start[t]; e < near_start[t + 1]; ++e) {
+        for (int rr = 0; rr < NR; ++rr) acc[rr] = make_double2((double)ar[rr] - (double)cr[rr], (double)ai[rr] - (double)ci[rr]);
+        if (act) {
+            for (int e = near_start[t] + h; e < near_start[t + 1]; e += S) {
                 const int64_t j = near_col[e];
                 const float2 l = nL[e], m = nM[e];
                 const double2 ld = make_double2(l.x, l.y), md = make_double2(m.x, m.y);
@@ -501,6 +522,18 @@ __global__ void __launch_bounds__(64) k_p2p32(int nleaf, const int32_t *leaf_sta
                     acc[rr] = cfma(md, mu[j * NR + rr], acc[rr]);
                 }
             }
+        }
+        if (S > 1) {  // add the groups' partial sums (group 0 keeps the result)
+            __syncthreads();
+#pragma unroll
+            for (int rr = 0; rr < NR; ++rr) red[tid * NR + rr] = acc[rr];
+            __syncthreads();
+            if (h == 0)
+                for (int g = 1; g < S; ++g)
+#pragma unroll
+                    for (int rr = 0; rr < NR; ++rr) acc[rr] = cadd(acc[rr], red[(tid + g * TP) * NR + rr]);
+        }
+        if (act && h == 0) {
 #pragma unroll
             for (int rr = 0; rr < NR; ++rr) y[(int64_t)t * NR + rr] = acc[rr];
         }
