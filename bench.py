@@ -68,11 +68,12 @@ def main():
     ap.add_argument("--train-maxit", type=int, default=300, help="iteration cap of the reference solve for training")
     ap.add_argument("--lds-budget", type=int, default=0, help="LDS bytes per translation tile (0 = library default)")
     ap.add_argument("--mfma", type=int, default=1, help="matrix-core tiles: 0 never, 1 library rule/autotuner, 2 every lane batch")
+    ap.add_argument("--fused", type=int, default=1, help="fused LDS-resident translation tiles for p <= 16: 0 never, 1 allowed")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(frequency/source sharding across GPUs is a design note only)", file=sys.stderr)
         sys.exit(2)
 
@@ -86,7 +87,8 @@ def main():
     rs, rec = synth.source_and_receivers(room, 64, nsrc=4)
     n = room.n
     log(f"workload {args.workload}: N={n} k={k:.3f}")
-    ctx = F.Context(0, lds_budget=args.lds_budget, autotune=0 if args.no_autotune else 1, mfma=args.mfma)
+    ctx = F.Context(0, lds_budget=args.lds_budget, autotune=0 if args.no_autotune else 1, mfma=args.mfma,
+                    fused=args.fused)
     ctx.fmmbem_set_mesh(room.vertices, room.triangles)
     ctx.fmmbem_set_wavenumber(k)
     ctx.fmmbem_set_admittance(room.beta)
@@ -100,7 +102,7 @@ def main():
         f"lds_max {info.lds_max}")
     shapes = ctx.fmmbem_batch_shapes()
     for s in shapes:
-        log(f"  tiles L{s['level']} {s['kind']}: {('mfma' if s['mfma'] else 'lane') if s['lane'] else ('whole' if s['whole'] else 'degree')} "
+        log(f"  tiles L{s['level']} {s['kind']}: {(('mfma', 'fused')[s['mfma'] - 1] if s['mfma'] else 'lane') if s['lane'] else ('whole' if s['whole'] else 'degree')} "
             f"JT {s['jt']} jobs {s['jobs']} {s['ms']:.3f} ms")
 
     dev = torch.device("cuda:0")

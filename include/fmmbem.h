@@ -115,6 +115,10 @@ typedef struct {
                             v_mfma_f64_16x16x4f64): 1 for batches with p >= 24 under the fixed
                             rule, and the autotuner measures them for every lane batch; 2 for
                             every lane batch; 0 never; default 1 */
+    int fused;           /* lane batches with p_src = p_tgt = p <= 16 may run all three stages in
+                            one kernel, the 32-job vectors resident in LDS and transformed on
+                            matrix cores: 1 under the fixed rule and as an autotuner candidate,
+                            0 never; default 1 */
 } fmmbem_options;
 
 void fmmbem_default_options(fmmbem_options *opt);
@@ -320,8 +324,9 @@ int fmmbem_near_entries(fmmbem_ctx *ctx, int64_t *nnz, int64_t *rows, int64_t *c
 
 /* Tile shape of every translation batch (from the fixed rule, or measured when the options
  * ask for autotuning): level, kind 0 = M2L at that level, 1 = M2M into it, 2 = L2L out of it,
- * one-job-per-lane flag, whole-vector flag, jobs per tile, matrix-core flag (FP64 stages of a
- * lane batch on MFMA), and the measured FP64 time of the batch's four stages (0 when not
+ * one-job-per-lane flag, whole-vector flag, jobs per tile, matrix-core mode of a lane batch (0
+ * lane kernels, 1 matrix-core tiles stage by stage, 2 the fused LDS-resident kernel), and the
+ * measured FP64 time of the batch's four stages (0 when not
  * measured). */
 typedef struct {
     int32_t level, kind, lane, whole, jt, mfma;

@@ -249,6 +249,12 @@ static void direction_phases(int PH, std::vector<double2> &A) {
 }
 
 
+// the fused translation kernel takes lane batches with p_src = p_tgt = p (coaxial tables of that
+// p) up to the p whose 32-job vectors fit the LDS
+static bool fused_ok(const TransBatch &b) {
+    return b.psrc == b.ptgt && b.PT == b.P && b.P <= trans_fused_pmax();
+}
+
 // Tile layout of a sorted job list for the batch's shape (JT, whole, lane): classes padded to
 // whole tiles, per-tile table indices, per-target CSR of the (padded) job order.
 static void layout_batch(fmmbem_ctx *c, const std::string &name, const std::vector<JobH> &jobs, TransBatch &b) {
@@ -362,6 +368,7 @@ static void make_batch(fmmbem_ctx *c, const std::string &name, std::vector<JobH>
         b.whole = 0;
         b.JT = 64;
         b.mfma = c->opt.mfma == 2 || (c->opt.mfma == 1 && b.P >= 24);
+        if (c->opt.fused && fused_ok(b)) b.mfma = 2;
     } else {
         b.whole = trans_pick_jt(b.P, budget, 1) >= 8 && (size_t)8 * 16 * b.P * b.P <= budget;
         b.JT = trans_pick_jt(b.P, budget, b.whole);
@@ -619,9 +626,15 @@ static void run_batch(fmmbem_ctx *c, int nrv, const TransBatch &b, const typenam
     const double by[4] = {nr * cs * (b.psrc * b.psrc + P2), nr * cs * 2 * P2, cs * P2 * (nr + no),
                           cs * (no * P2 + 2.0 * b.ntgt * nrv * b.ptgt * b.ptgt)};
     for (int stage = 0; stage < 4; ++stage) {
+        if (b.lane && b.mfma == 2 && (stage == 1 || stage == 2)) continue;  // inside the fused kernel
         int e = prof_begin(c);
         const char *name = trans_stage<R>(b, tb, stage, nrv, src, dst, ph, c->delta_p, W1, W2, st);
-        prof_end(c, e, name, fl[stage], by[stage]);
+        double f = fl[stage], y = by[stage];
+        if (b.lane && b.mfma == 2 && stage == 0) {  // fused: all three stages; sources in, run rows out
+            f = fl[0] + fl[1] + fl[2];
+            y = nr * cs * b.psrc * b.psrc + no * cs * P2;
+        }
+        prof_end(c, e, name, f, y);
     }
 }
 
@@ -687,6 +700,7 @@ static void autotune_batches(fmmbem_ctx *c) {
         if (pad64 <= 2 * (int64_t)jobs.size()) {
             cand.push_back({1, 0, 64, 0});
             if (c->opt.mfma != 0) cand.push_back({1, 0, 64, 1});
+            if (c->opt.fused && fused_ok(b)) cand.push_back({1, 0, 64, 2});
         }
         for (int whole = 0; whole < 2; ++whole)
             for (int jt : {4, 8, 12, 16, 24, 32, 48, 64})
@@ -1227,6 +1241,7 @@ void fmmbem_default_options(fmmbem_options *o) {
     o->lane_tiles = 1;
     o->streams = 2;
     o->mfma = 1;
+    o->fused = 1;
 }
 
 void fmmbem_default_solve_opts(fmmbem_solve_opts *o) {

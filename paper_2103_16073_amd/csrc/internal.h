@@ -123,18 +123,18 @@ struct TransBatch {
     float *H32 = nullptr, *HT32 = nullptr;              // FP32 copies (mixed precision)
     int whole = 0;                                      // whole-vector tiles (small p) or per-degree slices
     int lane = 0;                                       // one job per lane, 64-job tiles (many jobs per class)
-    int mfma = 0;                                       // lane batch whose FP64 stages run on matrix cores
+    int mfma = 0;                                       // lane batch on matrix cores: 1 stage by stage, 2 fused (p <= 16)
     int64_t ntgt = 0;                                   // target boxes
     int32_t *tgt_start = nullptr, *tgt_jobs = nullptr;  // jobs of each target (CSR, padded job indices)
     // lane batches: consecutive jobs of one class with one target form a run (never crossing a
-    // 16-job boundary); seg[j] = run length at the run's first job, 0 elsewhere.  The back
+    // SEG_ALIGN-job boundary); seg[j] = run length at the run's first job, 0 elsewhere.  The back
     // rotation stores each run's sum in the first job's row and the CSR lists first jobs only.
     int8_t *seg = nullptr;
     int64_t nout = 0;  // rows the back rotation stores (runs of lane batches, else jobs)
 };
 // runs of the back-rotation output never cross a multiple of this many (real) jobs, so that a
-// run lies in one 64-lane tile for 1, 2 or 4 right-hand sides
-constexpr int SEG_ALIGN = 16;
+// run lies in one 32-lane half tile (the fused kernel's block) for 1, 2 or 4 right-hand sides
+constexpr int SEG_ALIGN = 8;
 // one translation job before tiling
 struct JobH {
     int32_t src, tgt;
@@ -144,6 +144,7 @@ struct JobH {
 };
 
 int trans_pick_jt(int P, size_t lds_budget, int whole);
+int trans_fused_pmax();
 size_t trans_lds_bytes(int JT, int P, int whole);
 void trans_configure_lds(size_t lds_max);
 template <class R>

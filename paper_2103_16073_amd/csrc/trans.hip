@@ -1087,6 +1087,283 @@ __global__ void __launch_bounds__(256) k_tm_coax(TransArgsT<R> a) {
     }
 }
 
+// ------------------------------------------------------------------ fused translation tiles (p <= 16)
+// All three stages for 32 (virtual) jobs of a 64-job tile in one workgroup.  The jobs' coefficient
+// vectors stay in LDS (row c holds 32 jobs x real/imaginary part); each of the 4 wavefronts owns
+// 16 columns (8 jobs) and transforms them in place on matrix cores -- forward rotation degree by
+// degree, coaxial step order by order, back rotation degree by degree -- with no workgroup
+// barrier between steps: every wavefront reads its own fragments of the step's table block from
+// memory (L2-resident, shared by the tile's jobs) into registers, one step ahead.  HBM sees the
+// source gather and the back-rotated rows (one per run of one target), not the work rows of the
+// three-pass kernels.  psrc = ptgt = P <= TF_PMAX.
+constexpr int TF_PMAX = 16, TF_PH = 2 * TF_PMAX - 1;
+constexpr int TF_GU = 8;  // source loads in flight per thread
+
+// Steps of the fused kernel: pairs of degrees (2k, 2k + 1) of the forward rotation, then the
+// coaxial orders +-|m| (one table block serves both), then pairs of degrees of the back rotation;
+// the two halves of a step are independent, so each wavefront keeps two matrix-core chains in
+// flight.
+//
+// A fragments of one step for one lane: TfRot v[d][i][b] = A[16 b + (lane & 15)][4 i + (lane >> 4)]
+// of the rotation block of degree 2k + d (b: row block); TfCoax v[i][b] the same entry of the
+// coaxial block of |m| (b = 0 real part, b = 1 imaginary part; the step applies the sign
+// (-1)^{k+r}).  Entries past a block are clamped copies that the step masks to zero, so the loads
+// are unconditional and nothing waits for them before the step that needs them.
+template <class R> struct TfRot { R v[2][8][2]; };
+template <class R> struct TfCoax { R v[4][2]; };
+
+// M: the table's rotation blocks (HT for the forward rotation, H for the back rotation)
+template <class R>
+__device__ __forceinline__ void tf_load_rot(TfRot<R> &f, const R *M, int k, int P, int lane) {
+    const int kq = lane >> 4, rl = lane & 15;
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+        const int n = min(2 * k + d, P - 1), w = 2 * n + 1;
+        const R *Mn = M + rot_block_off(n);  // A[r][k] = Mn[k w + r]
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) f.v[d][i][b] = Mn[min(4 * i + kq, w - 1) * w + min(16 * b + rl, w - 1)];
+    }
+}
+
+template <class R>
+__device__ __forceinline__ void tf_load_coax(TfCoax<R> &f, const typename Cx<R>::T *T, int am, int P, int PT, int lane) {
+    using C = typename Cx<R>::T;
+    const int kq = lane >> 4, rl = lane & 15, rows = P - am, B = PT - am;
+    const C *Tm = T + coax_block_off(PT, am);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const C t = Tm[min(4 * i + kq, rows - 1) * B + min(rl, rows - 1)];
+        f.v[i][0] = t.x;
+        f.v[i][1] = t.y;
+    }
+}
+
+// rotation of degrees n0 and n0 + 1 (if TWO; rows n^2 .. n^2 + 2n) on the wavefront's 16 columns,
+// in place; KS K steps of 4 rows (the same for both degrees), RB row blocks of 16
+template <class R, int LD, int KS, int RB, bool TWO>
+__device__ __forceinline__ void tf_rot_pair(R *X, const TfRot<R> &f, int n0, int colw, int kq) {
+    using Op = TmOp<R>;
+    using v4 = typename Op::v4;
+    constexpr int ND = TWO ? 2 : 1;
+    const int rl = colw & 15;
+    R b[ND][KS];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        const int n = n0 + d, w = 2 * n + 1;
+#pragma unroll
+        for (int i = 0; i < KS; ++i) b[d][i] = X[(n * n + min(4 * i + kq, w - 1)) * LD + colw];  // A is 0 past w
+    }
+    v4 acc[ND][RB];
+#pragma unroll
+    for (int d = 0; d < ND; ++d)
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) acc[d][rb] = v4{0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < KS; ++i)
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int d = 0; d < ND; ++d) {
+                const int w = 2 * (n0 + d) + 1;
+                const R av = (4 * i + kq < w && 16 * rb + rl < w) ? f.v[d][i][rb] : R(0);
+                acc[d][rb] = Op::mma(av, b[d][i], acc[d][rb]);
+            }
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        const int n = n0 + d, w = 2 * n + 1;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = 16 * rb + Op::row(kq, i);
+                if (r < w) X[(n * n + r) * LD + colw] = acc[d][rb][i];
+            }
+    }
+}
+
+// coaxial step of orders am and -am (if TWO) on the wavefront's 16 columns, in place: rows and
+// columns are the degrees am .. P - 1 of the order; the imaginary part of the table meets the
+// partner column (re <-> im)
+template <class R, int LD, int KS, bool TWO>
+__device__ __forceinline__ void tf_coax_pair(R *X, const TfCoax<R> &f, int am, int P, int colw, int kq, R swp) {
+    using Op = TmOp<R>;
+    using v4 = typename Op::v4;
+    constexpr int ND = TWO ? 2 : 1;
+    const int rows = P - am, rl = colw & 15;
+    R b[ND][KS], bw[ND][KS];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        const int m = d ? -am : am;
+#pragma unroll
+        for (int i = 0; i < KS; ++i) {
+            const int nk = am + min(4 * i + kq, rows - 1), ck = nk * nk + nk + m;
+            b[d][i] = X[ck * LD + colw];
+            bw[d][i] = swp * X[ck * LD + (colw ^ 1)];
+        }
+    }
+    v4 acc[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) acc[d] = v4{0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < KS; ++i) {
+        const int k = 4 * i + kq;
+        const R sg = (k < rows && rl < rows) ? (((k + rl) & 1) ? R(-1) : R(1)) : R(0);
+        const R ar = sg * f.v[i][0], ai = sg * f.v[i][1];
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            acc[d] = Op::mma(ar, b[d][i], acc[d]);
+            acc[d] = Op::mma(ai, bw[d][i], acc[d]);
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        const int m = d ? -am : am;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = Op::row(kq, i), nn = am + r;
+            if (r < rows) X[(nn * nn + nn + m) * LD + colw] = acc[d][i];
+        }
+    }
+}
+
+// rotation step k (degrees 2k, 2k + 1): K steps k + 1, two row blocks from degree 8 on
+template <class R, int LD>
+__device__ __forceinline__ void tf_rot_step(R *X, const TfRot<R> &f, int k, int P, int colw, int kq) {
+    const int n0 = 2 * k;
+    const bool two = n0 + 1 < P;
+#define TF_ROT(KS, RB) \
+    (two ? tf_rot_pair<R, LD, KS, RB, true>(X, f, n0, colw, kq) : tf_rot_pair<R, LD, KS, RB, false>(X, f, n0, colw, kq))
+    switch (k) {
+    case 0: TF_ROT(1, 1); break;
+    case 1: TF_ROT(2, 1); break;
+    case 2: TF_ROT(3, 1); break;
+    case 3: TF_ROT(4, 1); break;
+    case 4: TF_ROT(5, 2); break;
+    case 5: TF_ROT(6, 2); break;
+    case 6: TF_ROT(7, 2); break;
+    default: TF_ROT(8, 2); break;
+    }
+#undef TF_ROT
+}
+
+template <class R, int LD>
+__device__ __forceinline__ void tf_coax_step(R *X, const TfCoax<R> &f, int am, int P, int colw, int kq, R swp) {
+    const int ks = (P - am + 3) / 4;
+#define TF_COAX(KS) \
+    (am > 0 ? tf_coax_pair<R, LD, KS, true>(X, f, am, P, colw, kq, swp) : tf_coax_pair<R, LD, KS, false>(X, f, am, P, colw, kq, swp))
+    switch (ks) {
+    case 1: TF_COAX(1); break;
+    case 2: TF_COAX(2); break;
+    case 3: TF_COAX(3); break;
+    default: TF_COAX(4); break;
+    }
+#undef TF_COAX
+}
+
+// one rotation stage (all degree pairs) with the tables M; two fragment sets, each loaded one step
+// before the step that uses it
+template <class R, int LD>
+__device__ __forceinline__ void tf_rot_stage(R *X, const R *M, int P, int colw, int kq, int lane) {
+    const int QR = (P + 1) / 2;
+    TfRot<R> fa, fb;
+    tf_load_rot(fa, M, 0, P, lane);
+    for (int k = 0; k < QR; k += 2) {
+        tf_load_rot(fb, M, min(k + 1, QR - 1), P, lane);
+        tf_rot_step<R, LD>(X, fa, k, P, colw, kq);
+        if (k + 2 < QR) tf_load_rot(fa, M, k + 2, P, lane);
+        if (k + 1 < QR) tf_rot_step<R, LD>(X, fb, k + 1, P, colw, kq);
+    }
+}
+
+// J jobs per workgroup (J / 8 wavefronts): 16 (two workgroups share a CU in FP64) or 32 (runs of
+// one target over 4 vectors span 32 virtual jobs)
+template <class R, int J>
+__global__ void __launch_bounds__(8 * J) k_tf_trans(TransArgsT<R> a) {
+    using C = typename Cx<R>::T;
+    constexpr int LD = 2 * J + 2, NT = 8 * J;
+    __shared__ __align__(16) R X[TF_PMAX * TF_PMAX * LD];
+    __shared__ C phl[J * TF_PH];  // e^{i m a_j}, m = -(P-1) .. P-1, per job
+    __shared__ int64_t soff[J];
+    __shared__ int32_t sdir[J];
+    __shared__ int segl[J];
+    int tile, part;
+    xcd_block(tile, part);
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t J0 = (int64_t)tile * LANE_JT + part * J;
+    const int P = a.P, P2 = P * P, phs = 2 * a.PH + 1, nph = 2 * P - 1;
+    if (tid < J) {
+        const int64_t Jv = J0 + tid, Jc = Jv < a.njob ? Jv : a.njob - 1;
+        soff[tid] = src_row(a, Jc) * P2;
+        sdir[tid] = a.jdir[Jc / a.nr] * phs + a.PH - (P - 1);
+        segl[tid] = Jv < a.njob ? a.jseg[Jv / a.nr] : 0;
+    }
+    __syncthreads();
+    for (int e = tid; e < J * nph; e += NT) {
+        const int j = e / nph, q = e - j * nph;
+        phl[j * TF_PH + q] = a.ph[sdir[j] + q];
+    }
+    __syncthreads();
+    // sources, phased: X[c][2j..2j+1] = e^{i m a_j} c_j  (coefficient c = n^2 + n + m); TF_GU loads
+    // in flight per thread
+    const int tot = J * P2;
+    const float inv = 1.0f / (float)P2;
+    // (indices past the end are clamped to the last element: those threads store the same value
+    // to the same place, so no store is conditional and no load waits for a branch)
+    for (int e0 = 0; e0 < tot; e0 += NT * TF_GU) {
+        C s[TF_GU];
+        int jj[TF_GU], cc[TF_GU];
+#pragma unroll
+        for (int u = 0; u < TF_GU; ++u) {
+            const int e = min(e0 + tid + NT * u, tot - 1), j = (int)(((float)e + 0.5f) * inv);
+            jj[u] = j;
+            cc[u] = e - j * P2;
+            s[u] = a.src[soff[j] + cc[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < TF_GU; ++u) {
+            const int c = cc[u], n = (int)sqrtf((float)c + 0.5f), m = c - n * n - n;
+            const C x = mulc(phl[jj[u] * TF_PH + m + P - 1], s[u]);
+            X[c * LD + 2 * jj[u]] = x.x;
+            X[c * LD + 2 * jj[u] + 1] = x.y;
+        }
+    }
+    __syncthreads();
+    {
+        const int tr = a.tile_rot[tile / a.nr], tc = a.tile_coax[tile / a.nr];
+        const R *HT = a.HT + (int64_t)tr * rot_table_size(P), *H = a.H + (int64_t)tr * rot_table_size(P);
+        const C *T = a.coax + (int64_t)tc * coax_table_size(a.PT);
+        const int colw = 16 * wv + (lane & 15), kq = lane >> 4;
+        const R swp = (colw & 1) ? R(1) : R(-1);
+        tf_rot_stage<R, LD>(X, HT, P, colw, kq, lane);
+        {
+            TfCoax<R> ca, cb;
+            tf_load_coax(ca, T, 0, P, a.PT, lane);
+            for (int am = 0; am < P; am += 2) {
+                tf_load_coax(cb, T, min(am + 1, P - 1), P, a.PT, lane);
+                tf_coax_step<R, LD>(X, ca, am, P, colw, kq, swp);
+                if (am + 2 < P) tf_load_coax(ca, T, am + 2, P, a.PT, lane);
+                if (am + 1 < P) tf_coax_step<R, LD>(X, cb, am + 1, P, colw, kq, swp);
+            }
+        }
+        tf_rot_stage<R, LD>(X, H, P, colw, kq, lane);
+    }
+    __syncthreads();
+    // back-rotated rows, phased (e^{-i m a}) and summed over the runs of one target, job-major
+    for (int e = tid; e < tot; e += NT) {
+        const int j = (int)(((float)e + 0.5f) * inv), c = e - j * P2, len = segl[j];
+        if (len == 0) continue;
+        const int n = (int)sqrtf((float)c + 0.5f), m = c - n * n - n;
+        C v = mkc<C>(0, 0);
+        for (int t = 0; t < len; ++t) {
+            const int jj = j + t * a.nr;
+            v = addc(v, mulcc(mkc<C>(X[c * LD + 2 * jj], X[c * LD + 2 * jj + 1]), phl[jj * TF_PH + m + P - 1]));
+        }
+        a.W1[(J0 + j) * (int64_t)P2 + c] = v;
+    }
+}
+
 // dst[t] += sum of the job rows of target t (W1, P^2 per job); jobs of t listed in CSR order.
 // With nr vectors, virtual target t is real target t / nr, vector t % nr, and the job rows of
 // that vector are (job * nr + t % nr).
@@ -1119,6 +1396,8 @@ __global__ void __launch_bounds__(256) k_tr_reduce(int64_t ntgt, int nr, int ptg
 }
 
 // ------------------------------------------------------------------ host side
+int trans_fused_pmax() { return TF_PMAX; }
+
 int trans_pick_jt(int P, size_t lds_budget, int whole) {
     const size_t per = whole ? sizeof(double2) * (size_t)P * P : sizeof(double2) * (size_t)std::max(2 * P - 1, P);
     int jt = (int)std::min<size_t>(64, lds_budget / per);
@@ -1156,7 +1435,20 @@ const char *trans_stage(const TransBatch &b, const TransTables<R> &tb, int stage
     const size_t lds = trans_lds_bytes(b.JT, b.P, b.whole) / (sizeof(double) / sizeof(R));
     const bool f32 = sizeof(R) == 4;
     const char *name = "";
-    if (b.lane && b.mfma && stage < 3) {
+    if (b.lane && b.mfma == 2 && stage < 3) {
+        // the fused kernel takes the three stages at stage 0
+        // a run of one target (at most SEG_ALIGN real jobs, aligned) lies in one workgroup's jobs
+        if (b.JT != LANE_JT || b.psrc != b.ptgt || b.PT != b.P || b.P > TF_PMAX || 32 / nr < SEG_ALIGN)
+            throw FmmError(-1, "fused translation tiles need 64-job tiles, p_src = p_tgt <= 16, <= 4 vectors");
+        if (stage != 0) return nullptr;
+        if (16 / nr >= SEG_ALIGN)
+            k_tf_trans<R, 16><<<dim3(ntile, LANE_JT / 16), 128, 0, st>>>(a);
+        else
+            k_tf_trans<R, 32><<<dim3(ntile, LANE_JT / 32), 256, 0, st>>>(a);
+        LAUNCH_OK();
+        return f32 ? "k_tf_trans_f32" : "k_tf_trans";
+    }
+    if (b.lane && b.mfma == 1 && stage < 3) {
         // stages of a lane batch on matrix cores (FP64, or FP32 for mixed products)
         if (b.JT != LANE_JT) throw FmmError(-1, "lane batches use 64-job tiles");
         switch (stage) {

@@ -124,16 +124,19 @@ def test_matvec_exact_far_vs_dense(F, cfg1_dense):
     ctx.close()
 
 
-@pytest.mark.parametrize("leaf_max,lds_budget,lane,mfma", [(64, 0, 0, 0), (12, 0, 0, 0), (12, 8192, 0, 0),
-                                                            (64, 8192, 0, 0), (64, 0, 2, 0), (12, 0, 2, 0),
-                                                            (64, 0, 2, 2), (12, 0, 2, 2)])
-def test_matvec_fmm_vs_dense(F, cfg1_dense, leaf_max, lds_budget, lane, mfma):
+@pytest.mark.parametrize("leaf_max,lds_budget,lane,mfma,fused", [
+    (64, 0, 0, 0, 0), (12, 0, 0, 0, 0), (12, 8192, 0, 0, 0), (64, 8192, 0, 0, 0), (64, 0, 2, 0, 0),
+    (12, 0, 2, 0, 0), (64, 0, 2, 2, 0), (12, 0, 2, 2, 0), (64, 0, 2, 0, 1), (12, 0, 2, 0, 1)])
+def test_matvec_fmm_vs_dense(F, cfg1_dense, leaf_max, lds_budget, lane, mfma, fused):
     """FP64 FMM product against the oracle's dense operator: relative L2 <= 1e-6, for octrees of
     depth 2 and 3 (so M2M/L2L are exercised), with the whole-vector LDS tiles, the per-degree
-    kernels (small LDS budget), the one-job-per-lane kernels (lane=2 forces them) and the
-    matrix-core tiles (mfma=2 puts every lane batch on them)."""
+    kernels (small LDS budget), the one-job-per-lane kernels (lane=2 forces them), the
+    matrix-core tiles (mfma=2 puts every lane batch on them) and the fused LDS-resident tiles
+    (fused=1, every lane batch with p_src = p_tgt <= 16)."""
     room, k = cfg1_dense
-    ctx = make_ctx(F, room, k, leaf_max=leaf_max, lds_budget=lds_budget, lane_tiles=lane, mfma=mfma)
+    ctx = make_ctx(F, room, k, leaf_max=leaf_max, lds_budget=lds_budget, lane_tiles=lane, mfma=mfma, fused=fused)
+    if fused:
+        assert any(s["mfma"] == 2 for s in ctx.fmmbem_batch_shapes())
     info = ctx.fmmbem_get_info()
     L, M = bem.dense_LM(room.vertices, room.triangles, k, info.rc)
     for seed in (1, 2):
@@ -146,14 +149,14 @@ def test_matvec_fmm_vs_dense(F, cfg1_dense, leaf_max, lds_budget, lane, mfma):
     ctx.close()
 
 
-@pytest.mark.parametrize("leaf_max,lds_budget,lane,mfma", [(64, 0, 0, 0), (12, 0, 0, 0), (12, 8192, 0, 0),
-                                                            (12, 0, 2, 0), (12, 0, 2, 2)])
-def test_matvec_mixed_vs_dense(F, cfg1_dense, leaf_max, lds_budget, lane, mfma):
+@pytest.mark.parametrize("leaf_max,lds_budget,lane,mfma,fused", [
+    (64, 0, 0, 0, 0), (12, 0, 0, 0, 0), (12, 8192, 0, 0, 0), (12, 0, 2, 0, 0), (12, 0, 2, 2, 0), (12, 0, 2, 0, 1)])
+def test_matvec_mixed_vs_dense(F, cfg1_dense, leaf_max, lds_budget, lane, mfma, fused):
     """Mixed-precision product (FP32 near field and translations, FP64 tables converted once,
     FP64 densities, P2M and L2P) against the oracle's dense operator: relative L2 <= 1e-4, with
-    the LDS tiles, the one-job-per-lane kernels and the FP32 matrix-core tiles."""
+    the LDS tiles, the one-job-per-lane kernels, the FP32 matrix-core tiles and the fused tiles."""
     room, k = cfg1_dense
-    ctx = make_ctx(F, room, k, leaf_max=leaf_max, lds_budget=lds_budget, lane_tiles=lane, mfma=mfma)
+    ctx = make_ctx(F, room, k, leaf_max=leaf_max, lds_budget=lds_budget, lane_tiles=lane, mfma=mfma, fused=fused)
     info = ctx.fmmbem_get_info()
     L, M = bem.dense_LM(room.vertices, room.triangles, k, info.rc)
     for seed in (1, 2):
@@ -238,14 +241,14 @@ def test_solve_inner_outer_vs_oracle_lu(F, cfg1_dense):
     ctx.close()
 
 
-@pytest.mark.parametrize("leaf_max,lds_budget,lane,mfma", [(12, 0, 0, 0), (12, 8192, 0, 0), (64, 0, 0, 0),
-                                                            (12, 0, 2, 0), (12, 0, 2, 2)])
-def test_matvec_multi_rhs(F, cfg1_dense, leaf_max, lds_budget, lane, mfma):
+@pytest.mark.parametrize("leaf_max,lds_budget,lane,mfma,fused", [
+    (12, 0, 0, 0, 0), (12, 8192, 0, 0, 0), (64, 0, 0, 0, 0), (12, 0, 2, 0, 0), (12, 0, 2, 2, 0), (12, 0, 2, 0, 1)])
+def test_matvec_multi_rhs(F, cfg1_dense, leaf_max, lds_budget, lane, mfma, fused):
     """Seven vectors in one call (chunks of 4, 2 and 1 vectors sharing kernel evaluations,
     basis functions and translation tables) give the single-vector products and match the
     oracle's dense operator (FP64 <= 1e-6, mixed <= 1e-4)."""
     room, k = cfg1_dense
-    ctx = make_ctx(F, room, k, leaf_max=leaf_max, lds_budget=lds_budget, lane_tiles=lane, mfma=mfma)
+    ctx = make_ctx(F, room, k, leaf_max=leaf_max, lds_budget=lds_budget, lane_tiles=lane, mfma=mfma, fused=fused)
     info = ctx.fmmbem_get_info()
     L, M = bem.dense_LM(room.vertices, room.triangles, k, info.rc)
     X = np.stack([synth.complex_normal(room.n, 20 + s) for s in range(7)])
@@ -341,6 +344,30 @@ def test_two_streams_match_one_stream(F, prec):
             assert np.array_equal(yd.cpu().numpy().reshape(y1.shape), y1), nr
     ctx1.close()
     ctx2.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_fused_tiles_match_lane_tiles(F, prec):
+    """The fused LDS-resident translation tiles against the three-pass lane kernels on the 6x5x3 m
+    room at 1 kHz (depth >= 5, runs of several jobs per target at the leaf levels), for 1, 2 and 4
+    vectors: FP64 products agree to rounding (1e-12), mixed ones to FP32 rounding (1e-5)."""
+    room, k = synth.config_room(2)
+    ctx0 = make_ctx(F, room, k, lane_tiles=2, mfma=0, fused=0)
+    ctx1 = make_ctx(F, room, k, lane_tiles=2, mfma=0, fused=1)
+    sh = ctx1.fmmbem_batch_shapes()
+    print("fused batches:", [(s["level"], s["kind"], s["jobs"]) for s in sh if s["mfma"] == 2])
+    assert sum(s["mfma"] == 2 for s in sh) >= 3
+    X = np.stack([synth.complex_normal(room.n, 90 + s) for s in range(4)])
+    tol = 1e-12 if prec == 0 else 1e-5
+    for nr in (1, 2, 4):
+        y0 = ctx0.fmmbem_matvec(X[:nr], precision=prec)
+        y1 = ctx1.fmmbem_matvec(X[:nr], precision=prec)
+        for s in range(nr):
+            err = np.linalg.norm(y1[s] - y0[s]) / np.linalg.norm(y0[s])
+            print(f"prec {prec} nr {nr} vector {s}: {err:.2e}")
+            assert err < tol
+    ctx0.close()
+    ctx1.close()
 
 
 def test_autotuned_tiles_vs_dense(F, cfg1_dense):
