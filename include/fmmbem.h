@@ -167,9 +167,11 @@ int64_t fmmbem_num_unknowns(const fmmbem_ctx *ctx);
  * for Eq. ibem5 (L[g- + g+], (g+ - g-)/2 + L'[g- + g+]) with g-+ = -+ dpsi_in/dn + i k beta-+ psi_in. */
 int fmmbem_rhs(fmmbem_ctx *ctx, fmmbem_c64 *b);
 
-/* y = A x for nrhs vectors (x, y: nrhs*N, host memory).  precision: FMMBEM_FP64 / FMMBEM_MIXED.
+/* y = A x for nrhs vectors (x, y: nrhs*N, host memory).  precision: FMMBEM_FP64 / FMMBEM_MIXED
+ * (direct: FP32 near-field kernel and translations; indirect: FP32 translations, FP64 near field;
+ * both keep densities, P2M, L2P and the output FP64).
  * With `exact_far` != 0 the far field is summed pair by pair instead of by the FMM (all-pairs
- * O(N^2) product, for validation). */
+ * O(N^2) product, for validation; FP64 only). */
 int fmmbem_matvec(fmmbem_ctx *ctx, int32_t nrhs, const fmmbem_c64 *x, fmmbem_c64 *y, int precision, int exact_far);
 
 /* Same on device pointers, enqueued on `stream` (hipStream_t); returns after enqueueing. */

@@ -1120,60 +1120,74 @@ static void ensure_indirect(fmmbem_ctx *c) {
 }
 
 // potential (row 1) and normal derivative (row 2) of the layers (sigma, mu) at the centroids,
-// plus the local terms of Eq. ibem5 when x (2N, caller order) is given; y is 2N.
+// plus the local terms of Eq. ibem5 when x (2N, caller order) is given; y is 2N.  The near field
+// runs on the side stream beside P2M and the translations (the same two-stream far field as the
+// direct products); with `mixed` the translations run in FP32 between an FP64 P2M and the FP64
+// local derivatives and L2P, and the near field stays FP64.
 static void fmm_pass_ind(fmmbem_ctx *c, const double2 *sigma, const double2 *mu, const double2 *x, double2 *y,
-                         bool exact_far) {
+                         bool exact_far, bool mixed = false) {
     ensure_indirect(c);
+    if (mixed) ensure_mixed(c);
+    ensure_nr(c, 1, mixed);
     TreeHost &T = c->tree;
     const int L = T.depth;
-    hipStream_t st = c->stream;
+    hipStream_t A = c->stream, B = c->opt.streams >= 2 ? c->side : c->stream;
     const int64_t n = c->nt;
     const int nleaf = (int)T.leaf_start.size() - 1;
     auto I32 = [&](const char *s) { return (int32_t *)c->buf.find(s); };
     const double4 *ec = (double4 *)c->buf.find("ec"), *en = (double4 *)c->buf.find("en");
     double2 *yv = dget<double2>(c->scratch, "ynear", n), *yn = dget<double2>(c->scratch, "ynearn", n);
+    struct CurGuard {
+        fmmbem_ctx *c;
+        ~CurGuard() { c->cur = c->stream; }
+    } guard{c};
+    if (!exact_far) {  // fork
+        ev_record(c, 0, A);
+        ev_wait(c, 0, B);
+        c->cur = B;
+    }
     int pe = prof_begin(c);
-    k_p2p_n<<<nleaf, 64, 0, st>>>(nleaf, I32("leaf_start"), I32("nbr_start"), I32("nbr_list"), exact_far ? 1 : 0, ec, en,
-                                  sigma, mu, c->k, c->rc * c->rc, I32("near_start"), I32("near_col"),
-                                  (double2 *)c->buf.find("near_L"), (double2 *)c->buf.find("near_M"),
-                                  (double2 *)c->buf.find("near_Lp"), (double2 *)c->buf.find("near_Mp"), yv, yn);
+    k_p2p_n<<<nleaf, 64, 0, c->cur>>>(nleaf, I32("leaf_start"), I32("nbr_start"), I32("nbr_list"), exact_far ? 1 : 0,
+                                      ec, en, sigma, mu, c->k, c->rc * c->rc, I32("near_start"), I32("near_col"),
+                                      (double2 *)c->buf.find("near_L"), (double2 *)c->buf.find("near_M"),
+                                      (double2 *)c->buf.find("near_Lp"), (double2 *)c->buf.find("near_Mp"), yv, yn);
     LAUNCH_OK();
     prof_end(c, pe, "k_p2p_n", 100.0 * (exact_far ? (double)n * n : (double)c->p2p_pairs), 0.0);
+    c->cur = A;
     LevelDev &LL = c->lev[L];
     const int p = LL.p;
-    const size_t q1 = (size_t)(p + 1) * (p + 1);
+    const size_t q1 = (size_t)(p + 1) * (p + 1), pp = (size_t)p * p;
     double2 *Dz = dget<double2>(c->scratch, "ind_Dz", LL.nbox * q1), *Dp = dget<double2>(c->scratch, "ind_Dp", LL.nbox * q1),
             *Dm = dget<double2>(c->scratch, "ind_Dm", LL.nbox * q1);
     if (!exact_far) {
+        pe = prof_begin(c);
         launch_p2m(1, nleaf, p, p2m_chunk(1, p), I32("leaf_start"), LL.center, ec, en, sigma, mu, c->k, leg_table(c),
-                   LL.M, st);
-        const double2 *ph = (double2 *)c->buf.find("phA");
-        for (int l = L - 1; l >= 2; --l) {
-            LevelDev &P_ = c->lev[l], &C_ = c->lev[l + 1];
-            zero_dev(c, P_.M, sizeof(double2) * P_.nbox * P_.p * P_.p);
-            run_batch<double>(c, 1, P_.up, C_.M, P_.M, tables64(P_.up, P_.coax_up), ph);
+                   LL.M, A);
+        prof_end(c, pe, "k_p2m", (double)n * pp * 2 * 8.0, 112.0 * n + 32.0 * n + 16.0 * nleaf * pp);
+        if (mixed) {
+            pe = prof_begin(c);
+            convert(c, (int64_t)LL.nbox * pp, (const double2 *)LL.M, LL.M32);
+            prof_end(c, pe, "k_cvt", 0.0, 24.0 * LL.nbox * pp);
+            far_field<float>(c, 1, true);
+            pe = prof_begin(c);
+            convert(c, (int64_t)LL.nbox * pp, (const float2 *)LL.L32, LL.L);
+            prof_end(c, pe, "k_cvt", 0.0, 24.0 * LL.nbox * pp);
+        } else {
+            far_field<double>(c, 1, false);
         }
-        for (int l = 2; l <= L; ++l) {
-            LevelDev &D = c->lev[l];
-            zero_dev(c, D.L, sizeof(double2) * D.nbox * D.p * D.p);
-            run_batch<double>(c, 1, D.m2l, D.M, D.L, tables64(D.m2l, D.coax_m2l), ph);
-            if (l >= 3) {
-                LevelDev &P_ = c->lev[l - 1];
-                run_batch<double>(c, 1, P_.down, P_.L, D.L, tables64(P_.down, P_.coax_up), ph);
-            }
-        }
-        k_local_derivs<<<nleaf, 256, 0, st>>>(nleaf, p, LL.L, c->k, Dz, Dp, Dm);
+        // the far field's join made the main stream wait for the side stream (near field included)
+        k_local_derivs<<<nleaf, 256, 0, A>>>(nleaf, p, LL.L, c->k, Dz, Dp, Dm);
         LAUNCH_OK();
     }
     pe = prof_begin(c);
-    k_l2p_n<<<nleaf, 64, ((size_t)64 * (p + 3) + (size_t)3 * (p + 1) * (p + 2) / 2) * sizeof(double), st>>>(
+    k_l2p_n<<<nleaf, 64, ((size_t)64 * (p + 3) + (size_t)3 * (p + 1) * (p + 2) / 2) * sizeof(double), A>>>(
         nleaf, p, I32("leaf_start"), LL.center, ec, en, LL.L, Dz, Dp, Dm, c->k, leg_table(c), yv, yn, I32("perm"), n, x,
         (double2 *)c->buf.find("beta"), (double2 *)c->buf.find("betap"), y, exact_far ? 0 : 1);
     LAUNCH_OK();
     prof_end(c, pe, "k_l2p_n", (double)n * q1 * 8.0 * 4, 0.0);
 }
 
-static void matvec_ind(fmmbem_ctx *c, const double2 *x, double2 *y, bool exact_far) {
+static void matvec_ind(fmmbem_ctx *c, const double2 *x, double2 *y, bool exact_far, bool mixed = false) {
     const int64_t n = c->nt;
     double2 *sigma = dget<double2>(c->scratch, "sigma", n), *mu = dget<double2>(c->scratch, "mu", n);
     rec(c, 0);
@@ -1181,7 +1195,7 @@ static void matvec_ind(fmmbem_ctx *c, const double2 *x, double2 *y, bool exact_f
                                                              (double2 *)c->buf.find("beta"),
                                                              (double2 *)c->buf.find("betap"), c->k, sigma, mu);
     LAUNCH_OK();
-    fmm_pass_ind(c, sigma, mu, x, y, exact_far);
+    fmm_pass_ind(c, sigma, mu, x, y, exact_far, mixed);
     rec(c, 8);
 }
 
@@ -1467,12 +1481,11 @@ int fmmbem_matvec(fmmbem_ctx *ctx, int32_t nrhs, const fmmbem_c64 *x, fmmbem_c64
     HIP_OK(hipSetDevice(ctx->device));
     ensure_setup(ctx);
     if (indirect(ctx)) {
-        if (precision != FMMBEM_FP64) return fail(ctx, FMMBEM_EINVAL, "indirect products are FP64");
         const int64_t n2 = 2 * ctx->nt;
         double2 *dx = dget<double2>(ctx->scratch, "mv_x", n2), *dy = dget<double2>(ctx->scratch, "mv_y", n2);
         for (int r = 0; r < nrhs; ++r) {
             HIP_OK(hipMemcpyAsync(dx, x + (int64_t)r * n2, sizeof(double2) * n2, hipMemcpyHostToDevice, ctx->stream));
-            matvec_ind(ctx, dx, dy, exact_far != 0);
+            matvec_ind(ctx, dx, dy, exact_far != 0, precision == FMMBEM_MIXED);
             HIP_OK(hipMemcpyAsync(y + (int64_t)r * n2, dy, sizeof(double2) * n2, hipMemcpyDeviceToHost, ctx->stream));
             HIP_OK(hipStreamSynchronize(ctx->stream));
         }
@@ -1509,9 +1522,9 @@ int fmmbem_matvec_dev(fmmbem_ctx *ctx, int32_t nrhs, const void *x, void *y, int
     HIP_OK(hipEventRecord(e0, caller));
     HIP_OK(hipStreamWaitEvent(ctx->stream, e0, 0));
     if (indirect(ctx)) {
-        if (precision != FMMBEM_FP64) return fail(ctx, FMMBEM_EINVAL, "indirect products are FP64");
         for (int r = 0; r < nrhs; ++r)
-            matvec_ind(ctx, (const double2 *)x + (int64_t)r * 2 * n, (double2 *)y + (int64_t)r * 2 * n, false);
+            matvec_ind(ctx, (const double2 *)x + (int64_t)r * 2 * n, (double2 *)y + (int64_t)r * 2 * n, false,
+                       precision == FMMBEM_MIXED);
     } else {
         matvec_dev(ctx, nrhs, (const double2 *)x, (double2 *)y, false, precision == FMMBEM_MIXED);
     }
@@ -1719,8 +1732,6 @@ int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, f
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = ctx->stream;
     const bool ind = indirect(ctx);
-    if (ind && (o.precision != FMMBEM_FP64 || (o.inner_iters > 0 && o.inner_precision != FMMBEM_FP64)))
-        return fail(ctx, FMMBEM_EINVAL, "indirect products are FP64");
     const int64_t n = fmmbem_num_unknowns(ctx);
     auto pc = make_precond(ctx, o);
     double2 *b = dget<double2>(ctx->scratch, "sv_b", n);
@@ -1731,7 +1742,7 @@ int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, f
     // the Krylov products run in the requested arithmetic; restart residuals always in FP64
     int64_t n64 = 0, nmx = 0;
     auto product = [&](const double2 *a, double2 *y, bool mixed) {
-        if (ind) matvec_ind(ctx, a, y, false);
+        if (ind) matvec_ind(ctx, a, y, false, mixed);
         else matvec_dev(ctx, 1, a, y, false, mixed);
         ++(mixed ? nmx : n64);
     };

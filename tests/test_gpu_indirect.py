@@ -106,9 +106,33 @@ def test_indirect_product_vs_dense(F, dense_ind, leaf_max):
         e2 = np.linalg.norm(y[room.n:] - ref[room.n:]) / np.linalg.norm(ref[room.n:])
         print(f"leaf_max {leaf_max}: row-1 err {e1:.3e}, row-2 err {e2:.3e}")
         assert e1 < 1e-6 and e2 < 1e-6
+        # mixed precision: FP32 translations between FP64 P2M and FP64 local derivatives / L2P
+        ym = ctx.fmmbem_matvec(x, precision=F.FMMBEM_MIXED)[0]
+        m1 = np.linalg.norm(ym[:room.n] - ref[:room.n]) / np.linalg.norm(ref[:room.n])
+        m2 = np.linalg.norm(ym[room.n:] - ref[room.n:]) / np.linalg.norm(ref[room.n:])
+        print(f"leaf_max {leaf_max}: mixed row-1 err {m1:.3e}, row-2 err {m2:.3e}")
+        assert m1 < 1e-4 and m2 < 1e-4
+    # the FP64 product is unaffected by a mixed one before it
+    y2 = ctx.fmmbem_matvec(x)[0]
+    assert np.array_equal(y2, y)
     with pytest.raises(RuntimeError):
-        ctx.fmmbem_matvec(x, precision=F.FMMBEM_MIXED)
+        ctx.fmmbem_matvec(x, precision=F.FMMBEM_MIXED, exact_far=True)
     ctx.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_indirect_two_streams_match_one_stream(F, prec):
+    """The indirect product on two streams (near field beside P2M and the translations) adds every
+    contribution in the same order as on one stream: bitwise equal results (6x5x3 m room at 1 kHz,
+    octree depth >= 5)."""
+    room, k = synth.config_room(2)
+    ctxs = [make_ctx(F, room.vertices, room.triangles, k, room.beta, None, streams=s) for s in (1, 2)]
+    x = synth.complex_normal(2 * room.n, 31)
+    y1, y2 = (c.fmmbem_matvec(x, precision=prec)[0] for c in ctxs)
+    assert ctxs[1].fmmbem_get_info().depth >= 5
+    assert np.array_equal(y1, y2)
+    for c in ctxs:
+        c.close()
 
 
 def test_indirect_rhs_vs_oracle(F, dense_ind):
@@ -143,4 +167,12 @@ def test_indirect_open_room_solve_and_field_vs_lu(F):
     psi = ctx.fmmbem_eval_field(0, rec, x)
     psi_ref = bem.indirect_receivers(V, T, k, beta, beta, rs[0], rc, x_ref, rec)
     assert np.linalg.norm(psi - psi_ref) / np.linalg.norm(psi_ref) < 1e-5
+    # mixed-precision Krylov products (FP32 translations, FP32 Krylov storage) with FP64 restart
+    # residuals reach the same FP64 residual target and the same solution
+    xm, repm, rcm = ctx.fmmbem_solve(0, tol=1e-7, restart=200, maxit=600, precond=F.FMMBEM_PC_DIAG,
+                                     precision=F.FMMBEM_MIXED)
+    print(f"open room mixed: iters {repm.iters} restarts {repm.restarts} rel {repm.rel_res:.2e} "
+          f"mixed products {repm.matvecs_mixed}")
+    assert rcm == 0 and repm.rel_res < 1e-7 and repm.matvecs_mixed > 0
+    assert np.linalg.norm(xm - x_ref) / np.linalg.norm(x_ref) < 1e-5
     ctx.close()
