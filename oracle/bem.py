@@ -20,6 +20,8 @@ Definitions followed (paper, Sections 2-3):
         row 1:  L[g- + g+],   row 2: (g+ - g-)/2 + L'[g- + g+],   g-+ = -+ dpsi_in/dn + i k beta-+ psi_in
     and the field psi = psi_in + L[sigma] + M[mu] (Eq. ibem1) with
     sigma = g- + g+ + i k (beta- psi- + beta+ psi+), mu = psi+ - psi- (Eq. ibem4)
+  * combined (Burton-Miller) direct equation: Eq. (dbem3) plus alpha = i/k times its normal
+    derivative (see bm_system), same unknown and field as Eq. (dbem4)
 """
 from __future__ import annotations
 
@@ -264,6 +266,51 @@ def indirect_receivers(V, T, k, beta_m, beta_p, rs, rc, x, pts, eta=DEFAULT_ETA)
     sigma = gm + gp + 1j * k * (beta_m * pm + beta_p * pp)
     sc = layer_field(V, T, k, rc, pts, sigma, pp - pm, eta)
     return green(pts, np.asarray(rs)[None, :], k) + sc
+
+
+# ----------------------------------------------------------------------------- combined direct form
+# Burton-Miller combination of the direct equation (reading: coupling alpha = i/k).  For the
+# scattered field psi on S with v = dpsi/dn = gamma + i k beta psi, Green's representation taken
+# to S from the room gives the surface equation of Eq. (dbem3)
+#       psi/2 + M[psi] - L[v] = 0,
+# and its normal derivative, with the single-layer jump dL[v]/dn -> L'[v] + v/2 from the room side
+# (Section 3.2), gives
+#       v/2 - L'[v] + M'[psi] = 0.
+# The combined equation is the first plus alpha times the second; with v substituted:
+#   A psi = psi/2 + (alpha i k / 2) beta psi + M psi - i k L[beta psi] + alpha (M'[psi] - i k L'[beta psi])
+#   b     = L[gamma] + alpha (L'[gamma] - gamma / 2)
+def bm_alpha(k):
+    """Coupling constant of the combined direct equation (reading: alpha = i/k)."""
+    return 1j / k
+
+
+def bm_system(V, T, k, beta, rs, rc, eta=DEFAULT_ETA):
+    """Dense A and b of the combined (Burton-Miller) direct equation; also returns gamma."""
+    L, M, Lp, Mp = dense_LMn(V, T, k, rc, eta)
+    c, nrm, _ = geometry(V, T)
+    a = bm_alpha(k)
+    A = (np.diag(0.5 + 0.5j * a * k * beta) + M - 1j * k * L * beta[None, :]
+         + a * (Mp - 1j * k * Lp * beta[None, :]))
+    g = gamma(c, nrm, beta, k, rs)
+    b = L @ g + a * (Lp @ g - 0.5 * g)
+    return A, b, g
+
+
+def bm_matvec_rows(V, T, k, beta, rc, x, rows, eta=DEFAULT_ETA):
+    """Rows of the combined direct operator applied to x, without forming it."""
+    rows = np.asarray(rows, np.int64)
+    a = bm_alpha(k)
+    y, yn = layer_rows_n(V, T, k, rc, rows, -1j * k * beta * x, x, eta)
+    return (0.5 + 0.5j * a * k * beta[rows]) * x[rows] + y + a * yn
+
+
+def bm_rhs_rows(V, T, k, beta, rs, rc, rows, eta=DEFAULT_ETA):
+    c, nrm, _ = geometry(V, T)
+    g = gamma(c, nrm, beta, k, rs)
+    rows = np.asarray(rows, np.int64)
+    a = bm_alpha(k)
+    y, yn = layer_rows_n(V, T, k, rc, rows, g, np.zeros_like(g), eta)
+    return y + a * (yn - 0.5 * g[rows])
 
 
 # ----------------------------------------------------------------------------- dense solvers
