@@ -60,6 +60,10 @@ enum {
 /* formulations (Section 3.1 / 3.2) */
 enum {
     FMMBEM_DIRECT = 0,  /* Eq. dbem4: unknown psi_sc at each element (N unknowns) */
+    FMMBEM_DIRECT_BM = 2, /* combined (Burton-Miller) direct equation: Eq. dbem3 plus alpha = i/k
+                             times its normal derivative (Section 3.2 jump relations), the same
+                             unknown and field as Eq. dbem4; adds the near entries of L' and M';
+                             preconditioners FMMBEM_PC_NONE or FMMBEM_PC_DIAG; one vector per pass */
     FMMBEM_INDIRECT = 3 /* Eq. ibem5: every element two-sided, unknowns (psi-, psi+) = the field on
                            the side the normal leaves (the room) and on the side it points to
                            (2N unknowns, psi- block first); FP64 products only */
@@ -144,7 +148,7 @@ int fmmbem_set_admittance(fmmbem_ctx *ctx, const fmmbem_c64 *beta);
 /* Unit monopole sources (Eq. sp6): ns positions rs (ns*3), optional complex amplitudes (NULL = 1). */
 int fmmbem_set_sources(fmmbem_ctx *ctx, int32_t ns, const double *rs, const fmmbem_c64 *amp);
 
-/* FMMBEM_DIRECT or FMMBEM_INDIRECT.  The indirect formulation adds the near entries of L'
+/* FMMBEM_DIRECT, FMMBEM_DIRECT_BM or FMMBEM_INDIRECT.  The indirect formulation adds the near entries of L'
  * and the hypersingular M' (Eq. ibem3; built on first use) and evaluates the normal derivative
  * of the far field at every element; preconditioners: FMMBEM_PC_NONE or FMMBEM_PC_DIAG
  * (2x2 element blocks). */

@@ -30,6 +30,12 @@ __global__ void k_densities_ind(int64_t, const int32_t *, const double2 *, const
 __global__ void k_field_dens_ind(int64_t, const int32_t *, const double2 *, const double2 *, const double2 *,
                                  const double2 *, const double2 *, double, double2 *, double2 *);
 __global__ void k_rhs_ind_local(int64_t, const int32_t *, const double2 *, const double2 *, double2 *);
+__global__ void k_bm_combine(int64_t, const int32_t *, const double2 *, const double2 *, double, double2,
+                             const double2 *, double2 *);
+__global__ void k_bm_rhs(int64_t, const int32_t *, const double2 *, double2, const double2 *, double2 *);
+__global__ void k_diag_bm_inv(int64_t, const int32_t *, const int32_t *, const int32_t *, const double2 *,
+                              const double2 *, const double2 *, const double2 *, const double2 *, double, double2,
+                              double, double2 *);
 __global__ void k_p2p_n(int, const int32_t *, const int32_t *, const int32_t *, int, const double4 *, const double4 *,
                         const double2 *, const double2 *, double, double, const int32_t *, const int32_t *,
                         const double2 *, const double2 *, const double2 *, const double2 *, double2 *, double2 *);
@@ -1217,6 +1223,45 @@ static void rhs_ind(fmmbem_ctx *c, int isrc, double2 *b) {
     LAUNCH_OK();
 }
 
+// ------------------------------------------------------------------ combined (Burton-Miller) direct form
+// Eq. (dbem3) plus alpha = i/k times its normal derivative; the same unknown (psi_sc per element)
+// and field (Eq. dbem1) as Eq. (dbem4).  Both halves come from one pass of the indirect
+// machinery (potential and normal derivative of the layers sigma = -i k beta x, mu = x).
+static bool burton_miller(const fmmbem_ctx *c) { return c->formulation == FMMBEM_DIRECT_BM; }
+static double2 bm_alpha(const fmmbem_ctx *c) { return cmk(0.0, 1.0 / c->k); }
+
+static void matvec_bm(fmmbem_ctx *c, const double2 *x, double2 *y, bool exact_far, bool mixed = false) {
+    const int64_t n = c->nt;
+    hipStream_t st = c->stream;
+    double2 *sigma = dget<double2>(c->scratch, "sigma", n), *mu = dget<double2>(c->scratch, "mu", n);
+    double2 *pq = dget<double2>(c->scratch, "bm_pq", 2 * n);
+    rec(c, 0);
+    k_densities<<<ceil_div(n, 256), 256, 0, st>>>(n, 1, (int32_t *)c->buf.find("perm"), x,
+                                                  (double2 *)c->buf.find("beta"), c->k, sigma, mu);
+    LAUNCH_OK();
+    fmm_pass_ind(c, sigma, mu, nullptr, pq, exact_far, mixed);
+    k_bm_combine<<<ceil_div(n, 256), 256, 0, st>>>(n, (int32_t *)c->buf.find("perm"), x,
+                                                   (double2 *)c->buf.find("beta"), c->k, bm_alpha(c), pq, y);
+    LAUNCH_OK();
+    rec(c, 8);
+}
+
+static void rhs_bm(fmmbem_ctx *c, int isrc, double2 *b) {
+    hipStream_t st = c->stream;
+    const int64_t n = c->nt;
+    double2 *sigma = dget<double2>(c->scratch, "sigma", n), *mu = dget<double2>(c->scratch, "mu", n);
+    double2 *pq = dget<double2>(c->scratch, "bm_pq", 2 * n);
+    const double *rs = &c->src[3 * isrc];
+    // sigma = gamma (tree order), mu = 0
+    k_gamma<<<ceil_div(n, 256), 256, 0, st>>>(n, (double4 *)c->buf.find("ec"), (double4 *)c->buf.find("en"),
+                                              (double2 *)c->buf.find("beta"), c->k, rs[0], rs[1], rs[2],
+                                              c->src_amp[isrc], sigma, mu);
+    LAUNCH_OK();
+    fmm_pass_ind(c, sigma, mu, nullptr, pq, false);
+    k_bm_rhs<<<ceil_div(n, 256), 256, 0, st>>>(n, (int32_t *)c->buf.find("perm"), sigma, bm_alpha(c), pq, b);
+    LAUNCH_OK();
+}
+
 }  // namespace fmm
 
 using namespace fmm;
@@ -1416,8 +1461,9 @@ int fmmbem_set_sources(fmmbem_ctx *ctx, int32_t ns, const double *rs, const fmmb
 
 int fmmbem_set_formulation(fmmbem_ctx *ctx, int f) {
     if (!ctx) return FMMBEM_EINVAL;
-    if (f != FMMBEM_DIRECT && f != FMMBEM_INDIRECT)
-        return fail(ctx, FMMBEM_EINVAL, "formulation must be FMMBEM_DIRECT (Eq. dbem4) or FMMBEM_INDIRECT (Eq. ibem5)");
+    if (f != FMMBEM_DIRECT && f != FMMBEM_DIRECT_BM && f != FMMBEM_INDIRECT)
+        return fail(ctx, FMMBEM_EINVAL,
+                    "formulation must be FMMBEM_DIRECT (Eq. dbem4), FMMBEM_DIRECT_BM or FMMBEM_INDIRECT (Eq. ibem5)");
     if (f != ctx->formulation) drop_graphs(ctx);
     ctx->formulation = f;
     return FMMBEM_OK;
@@ -1464,6 +1510,7 @@ int fmmbem_rhs(fmmbem_ctx *ctx, fmmbem_c64 *b) {
     double2 *db = dget<double2>(ctx->scratch, "rhs_out", n);
     for (size_t s = 0; s < ctx->src.size() / 3; ++s) {
         if (indirect(ctx)) rhs_ind(ctx, (int)s, db);
+        else if (burton_miller(ctx)) rhs_bm(ctx, (int)s, db);
         else rhs_dev(ctx, (int)s, db);
         HIP_OK(hipMemcpyAsync(b + s * n, db, sizeof(double2) * n, hipMemcpyDeviceToHost, ctx->stream));
     }
@@ -1487,6 +1534,17 @@ int fmmbem_matvec(fmmbem_ctx *ctx, int32_t nrhs, const fmmbem_c64 *x, fmmbem_c64
             HIP_OK(hipMemcpyAsync(dx, x + (int64_t)r * n2, sizeof(double2) * n2, hipMemcpyHostToDevice, ctx->stream));
             matvec_ind(ctx, dx, dy, exact_far != 0, precision == FMMBEM_MIXED);
             HIP_OK(hipMemcpyAsync(y + (int64_t)r * n2, dy, sizeof(double2) * n2, hipMemcpyDeviceToHost, ctx->stream));
+            HIP_OK(hipStreamSynchronize(ctx->stream));
+        }
+        return FMMBEM_OK;
+    }
+    if (burton_miller(ctx)) {
+        const int64_t n = ctx->nt;
+        double2 *dx = dget<double2>(ctx->scratch, "mv_x", n), *dy = dget<double2>(ctx->scratch, "mv_y", n);
+        for (int r = 0; r < nrhs; ++r) {
+            HIP_OK(hipMemcpyAsync(dx, x + (int64_t)r * n, sizeof(double2) * n, hipMemcpyHostToDevice, ctx->stream));
+            matvec_bm(ctx, dx, dy, exact_far != 0, precision == FMMBEM_MIXED);
+            HIP_OK(hipMemcpyAsync(y + (int64_t)r * n, dy, sizeof(double2) * n, hipMemcpyDeviceToHost, ctx->stream));
             HIP_OK(hipStreamSynchronize(ctx->stream));
         }
         return FMMBEM_OK;
@@ -1525,6 +1583,10 @@ int fmmbem_matvec_dev(fmmbem_ctx *ctx, int32_t nrhs, const void *x, void *y, int
         for (int r = 0; r < nrhs; ++r)
             matvec_ind(ctx, (const double2 *)x + (int64_t)r * 2 * n, (double2 *)y + (int64_t)r * 2 * n, false,
                        precision == FMMBEM_MIXED);
+    } else if (burton_miller(ctx)) {
+        for (int r = 0; r < nrhs; ++r)
+            matvec_bm(ctx, (const double2 *)x + (int64_t)r * n, (double2 *)y + (int64_t)r * n, false,
+                      precision == FMMBEM_MIXED);
     } else {
         matvec_dev(ctx, nrhs, (const double2 *)x, (double2 *)y, false, precision == FMMBEM_MIXED);
     }
@@ -1626,6 +1688,26 @@ static std::function<void(const double2 *, double2 *)> make_precond(fmmbem_ctx *
         const int32_t *pm = (int32_t *)ctx->buf.find("perm");
         return [=](const double2 *v, double2 *z) {
             k_mul_diag2<<<ceil_div(n, 256), 256, 0, st>>>(n, pm, inv, v, z);
+            LAUNCH_OK();
+        };
+    }
+    if (ctx->formulation == FMMBEM_DIRECT_BM) {
+        if (o.precond == FMMBEM_PC_NONE)
+            return [=](const double2 *v, double2 *z) {
+                HIP_OK(hipMemcpyAsync(z, v, sizeof(double2) * n, hipMemcpyDeviceToDevice, st));
+            };
+        if (o.precond != FMMBEM_PC_DIAG)
+            throw FmmError(FMMBEM_EINVAL, "the combined direct formulation takes FMMBEM_PC_NONE or FMMBEM_PC_DIAG");
+        ensure_indirect(ctx);
+        double2 *dinv = dget<double2>(ctx->buf, "pc_dinv_bm", n);
+        k_diag_bm_inv<<<ceil_div(n, 256), 256, 0, st>>>(
+            n, (int32_t *)ctx->buf.find("perm"), (int32_t *)ctx->buf.find("near_start"),
+            (int32_t *)ctx->buf.find("near_col"), (double2 *)ctx->buf.find("near_L"), (double2 *)ctx->buf.find("near_M"),
+            (double2 *)ctx->buf.find("near_Lp"), (double2 *)ctx->buf.find("near_Mp"), (double2 *)ctx->buf.find("beta"),
+            ctx->k, bm_alpha(ctx), o.diag_shift, dinv);
+        LAUNCH_OK();
+        return [=](const double2 *v, double2 *z) {
+            k_mul_diag<<<ceil_div(n, 256), 256, 0, st>>>(n, dinv, v, z);
             LAUNCH_OK();
         };
     }
@@ -1736,13 +1818,16 @@ int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, f
     auto pc = make_precond(ctx, o);
     double2 *b = dget<double2>(ctx->scratch, "sv_b", n);
     double2 *dx = dget<double2>(ctx->scratch, "sv_x", n);
+    const bool bm = burton_miller(ctx);
     if (ind) rhs_ind(ctx, isrc, b);
+    else if (bm) rhs_bm(ctx, isrc, b);
     else rhs_dev(ctx, isrc, b);
     if (o.use_x0) HIP_OK(hipMemcpyAsync(dx, x, sizeof(double2) * n, hipMemcpyHostToDevice, st));
     // the Krylov products run in the requested arithmetic; restart residuals always in FP64
     int64_t n64 = 0, nmx = 0;
     auto product = [&](const double2 *a, double2 *y, bool mixed) {
         if (ind) matvec_ind(ctx, a, y, false, mixed);
+        else if (bm) matvec_bm(ctx, a, y, false, mixed);
         else matvec_dev(ctx, 1, a, y, false, mixed);
         ++(mixed ? nmx : n64);
     };
@@ -1825,7 +1910,8 @@ int fmmbem_solve_batch(fmmbem_ctx *ctx, int32_t ns, const int32_t *isrc, const f
     if (int e = check_solve_opts(ctx, o)) return e;
     if (o.inner_iters > 0) return fail(ctx, FMMBEM_EINVAL, "the batched solve has no inner-outer scheme");
     if (o.precond == FMMBEM_PC_LEARNED) return fail(ctx, FMMBEM_EINVAL, "the batched solve has no learned guard");
-    if (indirect(ctx)) return fail(ctx, FMMBEM_EINVAL, "the batched solve is for the direct formulation");
+    if (indirect(ctx) || burton_miller(ctx))
+        return fail(ctx, FMMBEM_EINVAL, "the batched solve is for the direct formulation (Eq. dbem4)");
     GUARD_BEGIN
     HIP_OK(hipSetDevice(ctx->device));
     if (ctx->src.empty()) return fail(ctx, FMMBEM_ENOTREADY, "sources not set");
@@ -1987,7 +2073,8 @@ int fmmbem_learned_train(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_train_opts 
     HIP_OK(hipSetDevice(ctx->device));
     if (ctx->src.empty()) return fail(ctx, FMMBEM_ENOTREADY, "sources not set");
     if (isrc < 0 || isrc >= (int)(ctx->src.size() / 3)) return fail(ctx, FMMBEM_EINVAL, "bad source index");
-    if (indirect(ctx)) return fail(ctx, FMMBEM_EINVAL, "the learned preconditioner is for the direct formulation");
+    if (indirect(ctx) || burton_miller(ctx))
+        return fail(ctx, FMMBEM_EINVAL, "the learned preconditioner is for the direct formulation (Eq. dbem4)");
     ensure_setup(ctx);
     ensure_chunks(ctx);
     hipStream_t st = ctx->stream;

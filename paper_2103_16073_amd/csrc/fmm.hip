@@ -981,6 +981,32 @@ __global__ void k_rhs_ind_local(int64_t n, const int32_t *perm, const double2 *g
     b[n + u] = cadd(b[n + u], cscale(csub(gp[i], gm[i]), 0.5));
 }
 
+// Combined (Burton-Miller) direct equation: Eq. (dbem3) plus alpha times its normal derivative
+// (Section 3.2 jump relations; v = dpsi/dn = gamma + i k beta psi).  From the potential P and the
+// normal derivative Q of the layers sigma = -i k beta x, mu = x (caller order, pq[0..n) and
+// pq[n..2n)):  y = x/2 + (alpha i k / 2) beta x + P + alpha Q.
+__global__ void k_bm_combine(int64_t n, const int32_t *perm, const double2 *x, const double2 *beta, double k,
+                             double2 alpha, const double2 *pq, double2 *y) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t u = perm[i];
+    const double2 xu = x[u];
+    const double2 half_aikb = cscale(cmul(alpha, cmuli(beta[i])), 0.5 * k);  // alpha i k beta / 2
+    double2 v = cadd(cscale(xu, 0.5), cmul(half_aikb, xu));
+    v = cadd(v, pq[u]);
+    y[u] = cadd(v, cmul(alpha, pq[n + u]));
+}
+
+// Right-hand side of the combined equation: b = P + alpha (Q - gamma / 2), (P, Q) of the layer
+// sigma = gamma (gamma in tree order).
+__global__ void k_bm_rhs(int64_t n, const int32_t *perm, const double2 *gam, double2 alpha, const double2 *pq,
+                         double2 *b) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t u = perm[i];
+    b[u] = cadd(pq[u], cmul(alpha, csub(pq[n + u], cscale(gam[i], 0.5))));
+}
+
 // potential and normal derivative at the targets from one-point pairs and the near table
 __global__ void __launch_bounds__(64) k_p2p_n(int nleaf, const int32_t *leaf_start, const int32_t *nbr_start,
                                               const int32_t *nbr_list, int all_leaves, const double4 *ec,

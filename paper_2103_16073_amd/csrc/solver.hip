@@ -119,6 +119,23 @@ __global__ void k_diag_inv(int64_t n, const int32_t *perm, const int32_t *near_s
     dinv[perm[i]] = cdiv(cmk(1, 0), a);
 }
 
+// inverse diagonal of the combined (Burton-Miller) direct operator, caller order:
+//   1/2 + shift + (alpha i k / 2) beta_i + M_ii - i k beta_i L_ii + alpha (M'_ii - i k beta_i L'_ii)
+__global__ void k_diag_bm_inv(int64_t n, const int32_t *perm, const int32_t *near_start, const int32_t *near_col,
+                              const double2 *nL, const double2 *nM, const double2 *nLp, const double2 *nMp,
+                              const double2 *beta, double k, double2 alpha, double shift, double2 *dinv) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double2 ikb = cscale(cmuli(beta[i]), k);
+    double2 a = cadd(cmk(0.5 + shift, 0.0), cscale(cmul(alpha, ikb), 0.5));
+    for (int e = near_start[i]; e < near_start[i + 1]; ++e)
+        if (near_col[e] == i) {
+            a = cadd(a, csub(nM[e], cmul(ikb, nL[e])));
+            a = cadd(a, cmul(alpha, csub(nMp[e], cmul(ikb, nLp[e]))));
+        }
+    dinv[perm[i]] = cdiv(cmk(1, 0), a);
+}
+
 // dense operator block of each leaf, row-major n_b x n_b at blk_off[b] (sorted element order)
 __global__ void __launch_bounds__(256) k_leaf_blocks(int nleaf, const int32_t *leaf_start, const int64_t *blk_off,
                                                      const double4 *ec, const double4 *en, const double2 *beta,
