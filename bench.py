@@ -30,10 +30,12 @@ def log(*a):
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_lroom_1M_fp64.json")
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, launches_per_product):
     """HBM bytes per launch of `kernel` from the committed counter summary (two rocprofv3 --pmc
-    passes, calibrated on a device copy), or None when the summary is missing or the sources it
-    was taken with have changed since."""
+    passes, calibrated on a device copy), or None when the summary is missing, the sources it
+    was taken with have changed since, or its run put a different number of batches on the
+    kernel (the tile-shape autotuner chose otherwise there), so that a launch there is not the
+    launch timed here."""
     import hashlib
     if not os.path.exists(TRAFFIC_FILE):
         return None
@@ -45,6 +47,8 @@ def measured_traffic(kernel):
                 return None
     for name, v in t.get("kernels", {}).items():
         if name.replace("<1>", "") == kernel:
+            if abs(v.get("launches_per_product", -1) - launches_per_product) > 1e-9:
+                return None
             return v["hbm_bytes_per_launch"]
     return None
 
@@ -159,7 +163,8 @@ def main():
     avg_ms = dom["ms"] / dom["launches"]
     flops_per_launch = dom["flops"] / dom["launches"]
     achieved = flops_per_launch / (avg_ms * 1e-3)
-    traffic = measured_traffic(dom["name"]) if (args.workload == 3 and not args.no_autotune) else None
+    traffic = (measured_traffic(dom["name"], dom["launches"] / args.steps)
+               if (args.workload == 3 and not args.no_autotune) else None)
     # bound from the kernel's arithmetic intensity against the FP64 ridge point (peak flops over
     # peak HBM bandwidth): below it the HBM roofline is the one that bounds the kernel
     bytes_per_launch = dom["bytes"] / dom["launches"]

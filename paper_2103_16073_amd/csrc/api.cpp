@@ -721,14 +721,20 @@ static void autotune_batches(fmmbem_ctx *c) {
             layout_batch(c, r.name, jobs, b);
             const TransTables<double> tb{r.coax, b.H, b.HT};
             run_batch<double>(c, 1, b, r.src, r.dst, tb, ph);  // warm-up (allocates the work rows)
-            HIP_OK(hipEventRecord(e0, st));
-            for (int rep = 0; rep < 2; ++rep) run_batch<double>(c, 1, b, r.src, r.dst, tb, ph);
-            HIP_OK(hipEventRecord(e1, st));
-            HIP_OK(hipEventSynchronize(e1));
-            float ms = 0;
-            HIP_OK(hipEventElapsedTime(&ms, e0, e1));
-            if (ms / 2 < best) {
-                best = ms / 2;
+            // best of three repetitions: shapes within a few per cent of each other would
+            // otherwise trade places from run to run
+            float ms = 1e30f;
+            for (int rep = 0; rep < 3; ++rep) {
+                HIP_OK(hipEventRecord(e0, st));
+                run_batch<double>(c, 1, b, r.src, r.dst, tb, ph);
+                HIP_OK(hipEventRecord(e1, st));
+                HIP_OK(hipEventSynchronize(e1));
+                float m1 = 0;
+                HIP_OK(hipEventElapsedTime(&m1, e0, e1));
+                ms = std::min(ms, m1);
+            }
+            if (ms < best) {
+                best = ms;
                 bs = sh;
             }
         }
