@@ -73,6 +73,9 @@ def main():
     ap.add_argument("--lds-budget", type=int, default=0, help="LDS bytes per translation tile (0 = library default)")
     ap.add_argument("--mfma", type=int, default=1, help="matrix-core tiles: 0 never, 1 library rule/autotuner, 2 every lane batch")
     ap.add_argument("--fused", type=int, default=1, help="fused LDS-resident translation tiles for p <= 16: 0 never, 1 allowed")
+    ap.add_argument("--shapes-out", default=None, help="write the batches' tile shapes (JSON) after setup")
+    ap.add_argument("--shapes-in", default=None,
+                    help="replay tile shapes written by --shapes-out (no autotuning: the same launches as that run)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -91,8 +94,8 @@ def main():
     rs, rec = synth.source_and_receivers(room, 64, nsrc=4)
     n = room.n
     log(f"workload {args.workload}: N={n} k={k:.3f}")
-    ctx = F.Context(0, lds_budget=args.lds_budget, autotune=0 if args.no_autotune else 1, mfma=args.mfma,
-                    fused=args.fused)
+    ctx = F.Context(0, lds_budget=args.lds_budget, autotune=0 if (args.no_autotune or args.shapes_in) else 1,
+                    mfma=args.mfma, fused=args.fused)
     ctx.fmmbem_set_mesh(room.vertices, room.triangles)
     ctx.fmmbem_set_wavenumber(k)
     ctx.fmmbem_set_admittance(room.beta)
@@ -104,7 +107,14 @@ def main():
     ps = [info.p[l] for l in range(info.depth + 1)]
     log(f"setup {t_setup:.2f}s depth {info.depth} leaves {info.nleaf} p {ps} near_nnz {info.near_nnz} "
         f"lds_max {info.lds_max}")
+    if args.shapes_in:
+        with open(args.shapes_in) as fh:
+            ctx.fmmbem_set_batch_shapes(json.load(fh))
+        log(f"tile shapes replayed from {args.shapes_in}")
     shapes = ctx.fmmbem_batch_shapes()
+    if args.shapes_out:
+        with open(args.shapes_out, "w") as fh:
+            json.dump(shapes, fh)
     for s in shapes:
         log(f"  tiles L{s['level']} {s['kind']}: {(('mfma', 'fused')[s['mfma'] - 1] if s['mfma'] else 'lane') if s['lane'] else ('whole' if s['whole'] else 'degree')} "
             f"JT {s['jt']} jobs {s['jobs']} {s['ms']:.3f} ms")
@@ -165,6 +175,8 @@ def main():
     achieved = flops_per_launch / (avg_ms * 1e-3)
     traffic = (measured_traffic(dom["name"], dom["launches"] / args.steps)
                if (args.workload == 3 and not args.no_autotune) else None)
+    if traffic is None and args.workload == 3:
+        log(f"traffic of {dom['name']}: none for these launches in the committed counter summary")
     # bound from the kernel's arithmetic intensity against the FP64 ridge point (peak flops over
     # peak HBM bandwidth): below it the HBM roofline is the one that bounds the kernel
     bytes_per_launch = dom["bytes"] / dom["launches"]

@@ -341,6 +341,17 @@ typedef struct {
 } fmmbem_batch_shape;
 int fmmbem_batch_shapes(fmmbem_ctx *ctx, int32_t max, fmmbem_batch_shape *out, int32_t *count);
 
+/* Set the tile shape of translation batches, for instance to replay the shapes that
+ * fmmbem_batch_shapes reported for the same mesh, wavenumber and options in an earlier run (the
+ * autotuner's choice, so that a second process times or profiles exactly the same launches).
+ * Each entry names its batch by (level, kind) and gives lane, whole, jt and mfma; jobs and ms are
+ * ignored; batches not listed keep their shape.  Lane shapes need jt = 64 and whole = 0 (mfma 2
+ * only where p_src = p_tgt <= 16); LDS tiles need mfma = 0, jt a multiple of 4 in [4, 64] and
+ * tiles that fit the LDS.  Every entry is checked before any is applied: an unknown batch or a
+ * shape that does not fit returns FMMBEM_EINVAL and changes nothing.  Shapes hold until the
+ * tables are rebuilt (a new mesh or wavenumber). */
+int fmmbem_set_batch_shapes(fmmbem_ctx *ctx, int32_t count, const fmmbem_batch_shape *shapes);
+
 /* The L' and M' near entries (Eq. ibem3) in the order of fmmbem_near_entries (count via *nnz
  * when both arrays are NULL). */
 int fmmbem_near_entries_n(fmmbem_ctx *ctx, int64_t *nnz, fmmbem_c64 *Lp, fmmbem_c64 *Mp);

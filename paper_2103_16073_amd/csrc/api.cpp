@@ -2336,6 +2336,58 @@ int fmmbem_batch_shapes(fmmbem_ctx *ctx, int32_t max, fmmbem_batch_shape *out, i
     GUARD_END
 }
 
+int fmmbem_set_batch_shapes(fmmbem_ctx *ctx, int32_t count, const fmmbem_batch_shape *shapes) {
+    if (!ctx || count < 0 || (count > 0 && !shapes)) return FMMBEM_EINVAL;
+    GUARD_BEGIN
+    HIP_OK(hipSetDevice(ctx->device));
+    ensure_setup(ctx);
+    std::vector<BatchRef> refs = all_batches(ctx);
+    const size_t cap = ctx->lds_max - 1024;
+    std::vector<std::pair<size_t, int32_t>> todo;  // (batch, shape index)
+    for (int32_t i = 0; i < count; ++i) {
+        const fmmbem_batch_shape &sh = shapes[i];
+        size_t q = 0;
+        while (q < refs.size() && !(refs[q].level == sh.level && refs[q].kind == sh.kind)) ++q;
+        if (q == refs.size())
+            return fail(ctx, FMMBEM_EINVAL, "no translation batch at level " + std::to_string(sh.level) + ", kind " +
+                                                std::to_string(sh.kind));
+        const TransBatch &b = *refs[q].b;
+        bool ok;
+        if (sh.lane)
+            ok = sh.jt == 64 && sh.whole == 0 &&
+                 (sh.mfma == 0 || sh.mfma == 1 || (sh.mfma == 2 && fused_ok(b)));
+        else
+            ok = sh.mfma == 0 && (sh.whole == 0 || sh.whole == 1) && sh.jt >= 4 && sh.jt <= 64 && sh.jt % 4 == 0 &&
+                 trans_lds_bytes(sh.jt, b.P, sh.whole) <= cap;
+        if (!ok)
+            return fail(ctx, FMMBEM_EINVAL, "shape does not fit the batch at level " + std::to_string(sh.level) +
+                                                ", kind " + std::to_string(sh.kind));
+        todo.push_back({q, i});
+    }
+    for (auto &t : todo) {
+        const BatchRef &r = refs[t.first];
+        const fmmbem_batch_shape &sh = shapes[t.second];
+        TransBatch &b = *r.b;
+        b.lane = sh.lane;
+        b.whole = sh.whole;
+        b.JT = sh.jt;
+        b.mfma = sh.mfma;
+        layout_batch(ctx, r.name, ctx->batch_jobs[r.name], b);
+        for (auto &cs : ctx->shapes)
+            if (cs.level == r.level && cs.kind == r.kind) {
+                cs.lane = b.lane;
+                cs.whole = b.whole;
+                cs.jt = b.JT;
+                cs.mfma = b.mfma;
+                cs.ms = 0.0;
+            }
+    }
+    drop_graphs(ctx);
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    return FMMBEM_OK;
+    GUARD_END
+}
+
 int fmmbem_near_entries_n(fmmbem_ctx *ctx, int64_t *nnz, fmmbem_c64 *Lp, fmmbem_c64 *Mp) {
     if (!ctx || !nnz) return FMMBEM_EINVAL;
     GUARD_BEGIN

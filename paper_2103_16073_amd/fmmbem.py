@@ -102,6 +102,7 @@ EXPORTS = {
     "fmmbem_release_workspace": (ctypes.c_int, [ctypes.c_void_p]),
     "fmmbem_batch_shapes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                            ctypes.POINTER(ctypes.c_int32)]),
+    "fmmbem_set_batch_shapes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "fmmbem_set_admittance_plus": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "fmmbem_near_entries_n": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p,
                                              ctypes.c_void_p]),
@@ -341,6 +342,15 @@ class Context:
         self._check(lib().fmmbem_batch_shapes(self.h, cnt.value, arr, ctypes.byref(cnt)))
         return [{"level": s.level, "kind": ("m2l", "m2m", "l2l")[s.kind], "lane": s.lane, "whole": s.whole,
                  "jt": s.jt, "mfma": s.mfma, "jobs": s.jobs, "ms": s.ms} for s in arr[:cnt.value]]
+
+    def fmmbem_set_batch_shapes(self, shapes):
+        """shapes: dicts as returned by fmmbem_batch_shapes (level, kind, lane, whole, jt, mfma)."""
+        kinds = {"m2l": 0, "m2m": 1, "l2l": 2}
+        arr = (BatchShape * max(1, len(shapes)))()
+        for q, d in enumerate(shapes):
+            kind = kinds[d["kind"]] if isinstance(d["kind"], str) else int(d["kind"])
+            arr[q] = BatchShape(d["level"], kind, d["lane"], d["whole"], d["jt"], d["mfma"], d.get("jobs", 0), 0.0)
+        self._check(lib().fmmbem_set_batch_shapes(self.h, len(shapes), arr))
 
     def fmmbem_release_workspace(self):
         self._check(lib().fmmbem_release_workspace(self.h))

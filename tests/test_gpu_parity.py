@@ -370,6 +370,29 @@ def test_fused_tiles_match_lane_tiles(F, prec):
     ctx1.close()
 
 
+def test_replayed_tile_shapes_match_autotuned(F):
+    """Tile shapes recorded from an autotuned context and replayed on a fixed-rule one give the
+    same launches and bitwise the same products (FP64 and mixed); a shape that does not fit its
+    batch is rejected and changes nothing."""
+    room, k = synth.config_room(2)
+    ctx_a = make_ctx(F, room, k, autotune=1)
+    ctx_r = make_ctx(F, room, k, autotune=0)
+    shapes = ctx_a.fmmbem_batch_shapes()
+    ctx_r.fmmbem_set_batch_shapes(shapes)
+    got = ctx_r.fmmbem_batch_shapes()
+    key = lambda d: (d["level"], d["kind"], d["lane"], d["whole"], d["jt"], d["mfma"])
+    assert [key(d) for d in got] == [key(d) for d in shapes]
+    x = synth.complex_normal(room.n, 41)
+    for prec in (0, 1):
+        assert np.array_equal(ctx_a.fmmbem_matvec(x, precision=prec), ctx_r.fmmbem_matvec(x, precision=prec))
+    bad = dict(shapes[0], lane=1, jt=48, whole=0, mfma=0)
+    with pytest.raises(RuntimeError):
+        ctx_r.fmmbem_set_batch_shapes([bad])
+    assert [key(d) for d in ctx_r.fmmbem_batch_shapes()] == [key(d) for d in shapes]
+    ctx_a.close()
+    ctx_r.close()
+
+
 def test_autotuned_tiles_vs_dense(F, cfg1_dense):
     """With autotuning, every batch gets the measured-fastest tile shape; the product (FP64,
     mixed, several vectors) still matches the oracle's dense operator."""
