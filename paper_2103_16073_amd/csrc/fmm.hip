@@ -705,6 +705,16 @@ __device__ inline void p2m_accumulate(const P2mTerms &T, int cnt, int TS, const 
     }
 }
 
+// Slot sums: the derivative relations are linear with source-independent factors, so with
+// per-source weights al_0 = q, al_1 = w n_z, al_2 = w (n_x - i n_y)/2, al_3 = w (n_x + i n_y)/2,
+//   sum_s al_k,s B_s[t] (P) and sum_s conj(al_k,s) B_s[t] (Q)
+// over the basis slots t (m' >= 0) give every coefficient as seven factor-weighted sums: an entry
+// read conjugated (negative order) is conj(Q[t]).  One thread per slot keeps the eight sums per
+// vector in registers across the leaf's chunks; each basis value is read once per source.
+struct P2mSlotSums {
+    static constexpr int K = 4;
+};
+
 template <int NR>
 __global__ void __launch_bounds__(256) k_p2m(int nleaf, int p, int CH, const int32_t *leaf_start,
                                              const double4 *center, const double4 *ec, const double4 *en,
@@ -715,7 +725,8 @@ __global__ void __launch_bounds__(256) k_p2m(int nleaf, int p, int CH, const int
     const int TB = (p + 1) * (p + 2) / 2, TS = TB + 1;     // basis entries and the zero slot
     double2 *basis = smem;                                 // CH * TS
     double2 *qw = basis + (int64_t)CH * TS;                // CH * 2 * NR
-    double *jb = (double *)(qw + CH * 2 * NR);             // CH * (p+2)
+    double2 *W = qw + CH * 2 * NR;                         // CH * 4 * NR: slot-sum weights al_k
+    double *jb = (double *)(W + CH * 4 * NR);              // CH * (p+2)
     double *geo = jb + CH * (p + 2);                       // CH * 4: cos, sin of the polar angle, e^{i phi}
     double *nrm = geo + CH * 4;                            // CH * 3
     double *lt = nrm + CH * 3;                             // 3 TB: Legendre recurrence table
@@ -724,17 +735,17 @@ __global__ void __launch_bounds__(256) k_p2m(int nleaf, int p, int CH, const int
     const int ss = leaf_start[b], se = leaf_start[b + 1];
     const int ncoef = p * p;
     double2 *Mb = Mout + (int64_t)b * NR * ncoef;          // NR expansions of this leaf
-    // one coefficient per thread stays in registers across chunks; otherwise accumulate in place
-    const bool in_regs = ncoef <= (int)blockDim.x;
-    P2mTerms T;
-    double2 acc[NR];
+    // slot sums in registers (one slot per thread, the zero slot included) when the slots fit the
+    // workgroup and the staged basis can hold the eight sums of one vector at the end; otherwise
+    // each thread accumulates whole coefficients in place
+    const bool slots = TS <= (int)blockDim.x && CH * TS >= 8 * TS;
+    double2 S[2 * P2mSlotSums::K][NR];
 #pragma unroll
-    for (int rr = 0; rr < NR; ++rr) acc[rr] = cmk(0, 0);
-    if (in_regs) {
-        if (tid < ncoef) p2m_terms(p, TB, tid, k, T);
-    } else {
+    for (int q = 0; q < 2 * P2mSlotSums::K; ++q)
+#pragma unroll
+        for (int rr = 0; rr < NR; ++rr) S[q][rr] = cmk(0, 0);
+    if (!slots)
         for (int c = tid; c < NR * ncoef; c += blockDim.x) Mb[c] = cmk(0, 0);
-    }
     for (int j0 = ss; j0 < se; j0 += CH) {
         const int cnt = min(CH, se - j0);
         __syncthreads();
@@ -757,6 +768,14 @@ __global__ void __launch_bounds__(256) k_p2m(int nleaf, int p, int CH, const int
             nrm[3 * tid] = 0.5 * nv.x;
             nrm[3 * tid + 1] = 0.5 * nv.y;
             nrm[3 * tid + 2] = nv.z;
+#pragma unroll
+            for (int rr = 0; rr < NR; ++rr) {
+                const double2 q = qw[(2 * tid) * NR + rr], w = qw[(2 * tid + 1) * NR + rr];
+                W[(4 * tid) * NR + rr] = q;
+                W[(4 * tid + 1) * NR + rr] = cscale(w, nv.z);
+                W[(4 * tid + 2) * NR + rr] = cmul(w, cmk(0.5 * nv.x, -0.5 * nv.y));
+                W[(4 * tid + 3) * NR + rr] = cmul(w, cmk(0.5 * nv.x, 0.5 * nv.y));
+            }
         }
         __syncthreads();
         // basis column m' of source s: R_n^{m'} = j_n(k r) P_n^{m'}(cos) e^{i m' phi}, n = m'..p
@@ -784,8 +803,19 @@ __global__ void __launch_bounds__(256) k_p2m(int nleaf, int p, int CH, const int
             if (mp == 0) out[TB] = cmk(0, 0);
         }
         __syncthreads();
-        if (in_regs) {
-            if (tid < ncoef) p2m_accumulate<NR>(T, cnt, TS, basis, qw, nrm, acc);
+        if (slots) {
+            if (tid < TS)
+                for (int s2 = 0; s2 < cnt; ++s2) {
+                    const double2 B = basis[(int64_t)s2 * TS + tid];
+#pragma unroll
+                    for (int kk = 0; kk < P2mSlotSums::K; ++kk)
+#pragma unroll
+                        for (int rr = 0; rr < NR; ++rr) {
+                            const double2 al = W[(4 * s2 + kk) * NR + rr];
+                            S[2 * kk][rr] = cfma(al, B, S[2 * kk][rr]);
+                            S[2 * kk + 1][rr] = cfma(cmk(al.x, -al.y), B, S[2 * kk + 1][rr]);
+                        }
+                }
         } else {
             for (int c = tid; c < ncoef; c += blockDim.x) {
                 P2mTerms Tc;
@@ -800,9 +830,32 @@ __global__ void __launch_bounds__(256) k_p2m(int nleaf, int p, int CH, const int
             }
         }
     }
-    if (in_regs && tid < ncoef) {
+    if (slots) {
+        // coefficient c = seven factor-weighted slot sums (entry i of term t from sum type k(t):
+        // t = 0 monopole, 1-2 n_z d_z, 3-4 (d_x + i d_y), 5-6 (d_x - i d_y)), one vector at a time
+        // through the staged basis region
+        const int kt[7] = {0, 1, 1, 2, 2, 3, 3};
+        double2 *SL = basis;  // [8][TS]
 #pragma unroll
-        for (int rr = 0; rr < NR; ++rr) Mb[rr * ncoef + tid] = cmuli(cscale(acc[rr], k));  // i k sum
+        for (int rr = 0; rr < NR; ++rr) {
+            __syncthreads();
+            if (tid < TS)
+#pragma unroll
+                for (int q = 0; q < 2 * P2mSlotSums::K; ++q) SL[q * TS + tid] = S[q][rr];
+            __syncthreads();
+            for (int c = tid; c < ncoef; c += blockDim.x) {
+                P2mTerms T;
+                p2m_terms(p, TB, c, k, T);
+                double2 a = cmk(0, 0);
+#pragma unroll
+                for (int t = 0; t < 7; ++t) {
+                    const bool cj = T.fy[t] != T.fx[t];  // conjugated entry: conj of the Q sum
+                    const double2 v = SL[(2 * kt[t] + (cj ? 1 : 0)) * TS + T.i[t]];
+                    a = cadd(a, cmk(T.fx[t] * v.x, T.fy[t] * v.y));
+                }
+                Mb[rr * ncoef + c] = cmuli(cscale(a, k));  // i k sum
+            }
+        }
     }
 }
 
@@ -1271,7 +1324,7 @@ void launch_p2p(int nr, bool fp32, int nleaf, const int32_t *leaf_start, const i
 
 size_t p2m_stage_bytes(int nr, int p) {
     const int TB = (p + 1) * (p + 2) / 2;
-    return (size_t)(TB + 1) * 16 + (size_t)nr * 32 + (size_t)(p + 2) * 8 + 56;  // per staged source
+    return (size_t)(TB + 1) * 16 + (size_t)nr * 96 + (size_t)(p + 2) * 8 + 56;  // per staged source
 }
 size_t p2m_fixed_bytes(int p) { return (size_t)3 * (p + 1) * (p + 2) / 2 * sizeof(double); }
 

@@ -174,6 +174,32 @@ def test_matvec_mixed_vs_dense(F, cfg1_dense, leaf_max, lds_budget, lane, mfma, 
     ctx.close()
 
 
+@pytest.mark.parametrize("kk,leaf_max,p_min,p_leaf", [(None, 12, 20, 20), (16.0, 64, 16, 22)])
+def test_matvec_large_leaf_p_vs_dense(F, cfg1_dense, kk, leaf_max, p_min, p_leaf):
+    """Leaf truncation above 16: p = 20 takes the slot-sum P2M with more coefficients than threads;
+    at k = 16 (leaf kd = 12) the truncation rule itself gives p >= 22 at the leaves, more basis
+    slots than threads, and the per-coefficient P2M.  (A p far above what kd needs is not a valid
+    test: the singular translation coefficients then amplify round-off, which is why the rule never
+    raises p beyond need.)  1 and 4 vectors against the oracle's dense operator (1e-6)."""
+    room, k = cfg1_dense
+    if kk is not None:
+        k = kk
+    ctx = make_ctx(F, room, k, leaf_max=leaf_max, p_min=p_min)
+    info = ctx.fmmbem_get_info()
+    assert info.p[info.depth] >= p_leaf
+    L, M = bem.dense_LM(room.vertices, room.triangles, k, info.rc)
+    X = np.stack([synth.complex_normal(room.n, 60 + s) for s in range(4)])
+    Y = ctx.fmmbem_matvec(X)
+    y1 = ctx.fmmbem_matvec(X[0])[0]
+    for s in range(4):
+        ref = 0.5 * X[s] + M @ X[s] - 1j * k * L @ (room.beta * X[s])
+        err = np.linalg.norm(Y[s] - ref) / np.linalg.norm(ref)
+        print(f"k {k:.2f} depth {info.depth} p {list(info.p)[:info.depth + 1]} vector {s}: {err:.2e}")
+        assert err < 1e-6
+    assert np.linalg.norm(Y[0] - y1) <= 1e-12 * np.linalg.norm(y1)
+    ctx.close()
+
+
 def test_solve_mixed_inner_vs_oracle_lu(F, cfg1_dense):
     """FGMRES with mixed-precision Krylov products and FP64 restart residuals reaches a 1e-8
     FP64 residual; the solution agrees with the oracle's LU solution."""
