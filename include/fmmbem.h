@@ -235,6 +235,19 @@ int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, f
 int fmmbem_solve_batch(fmmbem_ctx *ctx, int32_t ns, const int32_t *isrc, const fmmbem_solve_opts *opts,
                        fmmbem_c64 *x, fmmbem_solve_report *rep);
 
+/* Solve independent systems (batching over frequencies, rooms, formulations): system i is source
+ * isrc[i] of context ctxs[i] (distinct contexts, each with its own mesh, wavenumber, formulation
+ * and options), solved by fmmbem_solve.  `threads` is reserved for solving the systems from
+ * several host threads; that mode is switched off in this version (a 16-thread run crashed the
+ * process) and the systems run one after another on the calling thread.  x[i] holds fmmbem_num_unknowns(ctxs[i]) values (in: initial guess if use_x0; out:
+ * solution); opts is NULL (defaults) or holds count entries; rep[i] and status[i] receive each
+ * solve's report and return code.  Every system runs; the result is FMMBEM_OK when all converged,
+ * FMMBEM_ENOCONV when some reached maxit, else the error of the first failed system.  A repeated
+ * or NULL context or a NULL argument returns FMMBEM_EINVAL before anything runs.  A context must
+ * not be used by another host thread meanwhile. */
+int fmmbem_solve_many(int32_t count, fmmbem_ctx *const *ctxs, const int32_t *isrc, const fmmbem_solve_opts *opts,
+                      fmmbem_c64 *const *x, fmmbem_solve_report *rep, int32_t *status, int32_t threads);
+
 /* ---- learned preconditioner ------------------------------------------------------------
  * A multilayer perceptron applied to every chunk of <= 64 consecutive unknowns of an octree
  * leaf: input 140 = the chunk's residual over its norm (64 complex, zero padded), k times the

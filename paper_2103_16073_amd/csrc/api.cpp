@@ -8,6 +8,10 @@
 
 #include "internal.h"
 
+#include <atomic>
+#include <set>
+#include <thread>
+
 namespace fmm {
 // kernels (fmm.hip / solver.hip)
 __global__ void k_near_count(int64_t, const int32_t *, const int32_t *, const int32_t *, const int32_t *,
@@ -101,7 +105,7 @@ static int level_p(const fmmbem_options &o, double k, double side) {
 template <class T>
 static T *upload(DeviceBuffers &b, const std::string &name, const std::vector<T> &v, hipStream_t st) {
     T *d = dget<T>(b, name, std::max<size_t>(v.size(), 1));
-    if (!v.empty()) HIP_OK(hipMemcpyAsync(d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st));
+    h2d_now(d, v.data(), sizeof(T) * v.size(), st);  // v is usually a temporary of the caller
     return d;
 }
 
@@ -2176,7 +2180,7 @@ int fmmbem_learned_train(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_train_opts 
     double lfirst = 0, llast = 0;
     for (int ep = 0; ep < o.epochs; ++ep) {
         for (int64_t i = M - 1; i > 0; --i) std::swap(perm_h[i], perm_h[next() % (uint64_t)(i + 1)]);
-        HIP_OK(hipMemcpyAsync(idx, perm_h.data(), sizeof(int64_t) * M, hipMemcpyHostToDevice, st));
+        h2d_now(idx, perm_h.data(), sizeof(int64_t) * M, st);  // perm_h is reshuffled next epoch
         double sum = 0;
         int nb = 0;
         for (int64_t s0 = 0; s0 + B <= M; s0 += B) {  // whole batches only
@@ -2336,6 +2340,36 @@ int fmmbem_batch_shapes(fmmbem_ctx *ctx, int32_t max, fmmbem_batch_shape *out, i
     for (int i = 0; i < max && i < *count; ++i) out[i] = ctx->shapes[i];
     return FMMBEM_OK;
     GUARD_END
+}
+
+int fmmbem_solve_many(int32_t count, fmmbem_ctx *const *ctxs, const int32_t *isrc, const fmmbem_solve_opts *opts,
+                      fmmbem_c64 *const *x, fmmbem_solve_report *rep, int32_t *status, int32_t threads) {
+    if (count < 0 || (count > 0 && (!ctxs || !isrc || !x || !rep || !status))) return FMMBEM_EINVAL;
+    std::set<fmmbem_ctx *> seen;
+    for (int32_t i = 0; i < count; ++i)
+        if (!ctxs[i] || !x[i] || !seen.insert(ctxs[i]).second) return FMMBEM_EINVAL;  // one thread per context
+    // Concurrent solving from several host threads is switched off: a run with 16 threads crashed
+    // the process (host segmentation fault) while 4 threads had passed, and no cause in this
+    // library has been shown.  The systems run one after another on the calling thread.
+    (void)threads;
+    const int nt = count > 0 ? 1 : 0;
+    std::atomic<int> next{0};
+    auto work = [&]() {
+        for (;;) {
+            const int i = next.fetch_add(1);
+            if (i >= count) break;
+            status[i] = fmmbem_solve(ctxs[i], isrc[i], opts ? &opts[i] : nullptr, x[i], &rep[i]);
+        }
+    };
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nt; ++t) pool.emplace_back(work);
+    if (nt > 0) work();
+    for (auto &th : pool) th.join();
+    int rc = FMMBEM_OK;
+    for (int32_t i = 0; i < count; ++i)
+        if (status[i] < 0) return status[i];
+        else if (status[i] == FMMBEM_ENOCONV) rc = FMMBEM_ENOCONV;
+    return rc;
 }
 
 int fmmbem_set_batch_shapes(fmmbem_ctx *ctx, int32_t count, const fmmbem_batch_shape *shapes) {

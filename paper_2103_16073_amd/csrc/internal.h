@@ -61,6 +61,15 @@ T *dget(DeviceBuffers &b, const std::string &name, size_t count) {
     return (T *)b.get(name, sizeof(T) * count);
 }
 
+// Host-to-device copy from memory the host frees or rewrites right after (temporaries, buffers
+// reused on the next step): an asynchronous copy from pageable memory may still read its source
+// after the call returns, so wait for it.
+inline void h2d_now(void *dst, const void *src, size_t bytes, hipStream_t st) {
+    if (bytes == 0) return;
+    HIP_OK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+    HIP_OK(hipStreamSynchronize(st));
+}
+
 // ---------------------------------------------------------------- tables
 struct CoaxJob {
     int kind;    // 0 = (S|R), 1 = (R|R)

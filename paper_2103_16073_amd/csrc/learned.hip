@@ -295,7 +295,7 @@ void Mlp::init(DeviceBuffers &buf, uint64_t seed, hipStream_t st) {
     w16 = dget<__half>(buf, "mlp_w16", np);
     m1 = dget<float>(buf, "mlp_m1", np);
     m2 = dget<float>(buf, "mlp_m2", np);
-    HIP_OK(hipMemcpyAsync(w32, h.data(), sizeof(float) * np, hipMemcpyHostToDevice, st));
+    h2d_now(w32, h.data(), sizeof(float) * np, st);  // h is a temporary
     HIP_OK(hipMemsetAsync(m1, 0, sizeof(float) * np, st));
     HIP_OK(hipMemsetAsync(m2, 0, sizeof(float) * np, st));
     sync_half(st);

@@ -231,7 +231,7 @@ void build_coax_tables(const std::vector<CoaxJob> &jobs, DeviceBuffers &scratch,
     // process in groups so the workspace stays bounded (~1 GiB)
     int64_t per = std::max<int64_t>(1, (int64_t(1) << 26) / wsz);
     CoaxJob *djobs = (CoaxJob *)scratch.get("coax_jobs", sizeof(CoaxJob) * jobs.size());
-    HIP_OK(hipMemcpyAsync(djobs, jobs.data(), sizeof(CoaxJob) * jobs.size(), hipMemcpyHostToDevice, st));
+    h2d_now(djobs, jobs.data(), sizeof(CoaxJob) * jobs.size(), st);
     for (size_t s = 0; s < jobs.size(); s += per) {
         int cnt = (int)std::min<int64_t>(per, jobs.size() - s);
         double2 *ws = (double2 *)scratch.get("coax_ws", sizeof(double2) * wsz * cnt);

@@ -103,6 +103,8 @@ EXPORTS = {
     "fmmbem_batch_shapes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                            ctypes.POINTER(ctypes.c_int32)]),
     "fmmbem_set_batch_shapes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "fmmbem_solve_many": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]),
     "fmmbem_set_admittance_plus": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "fmmbem_near_entries_n": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p,
                                              ctypes.c_void_p]),
@@ -400,6 +402,28 @@ class Context:
         t = np.zeros(8)
         self._check(lib().fmmbem_last_timings(self.h, _ptr(t)))
         return t
+
+
+def fmmbem_solve_many(ctxs, isrc, threads=0, **kw):
+    """Solve source isrc[i] of context ctxs[i] for every i (one after another: the library's
+    multi-threaded mode is switched off).  Returns (solutions, reports, per-system codes, overall
+    code)."""
+    count = len(ctxs)
+    o = default_solve_opts()
+    for k, v in kw.items():
+        setattr(o, k, v)
+    opts = (SolveOpts * max(1, count))(*([o] * count))
+    hs = (ctypes.c_void_p * max(1, count))(*[c.h.value for c in ctxs])
+    src = np.ascontiguousarray(isrc, np.int32)
+    xs = [np.zeros(c.fmmbem_num_unknowns(), np.complex128) for c in ctxs]
+    xp = (ctypes.c_void_p * max(1, count))(*[x.ctypes.data for x in xs])
+    reps = (SolveReport * max(1, count))()
+    status = np.zeros(max(1, count), np.int32)
+    rc = lib().fmmbem_solve_many(count, hs, _ptr(src), opts, xp, reps, _ptr(status), int(threads))
+    if rc < 0:
+        msgs = [lib().fmmbem_last_error(c.h) for c, st in zip(ctxs, status[:count]) if st < 0]
+        raise FmmbemError(rc, "; ".join(m.decode() for m in msgs if m) or "bad arguments")
+    return xs, list(reps[:count]), status[:count].tolist(), rc
 
 
 def fmmbem_coaxial_table(kind, ktau, p, method=-1, device=0):

@@ -487,3 +487,43 @@ def test_matvec_fmm_sampled_rows_full_size(F, cfg, nrows):
     assert err < 1e-6
     assert err_m < 1e-4
     ctx.close()
+
+
+def test_solve_many_frequencies_match_sequential(F):
+    """Several frequencies of one room, each with its own mesh (about six elements per wavelength,
+    so N and the octree differ), solved through fmmbem_solve_many give bitwise the solutions of
+    fmmbem_solve one system at a time; a repeated context is rejected before anything runs.
+    (fmmbem_solve_many runs its systems one after another: its multi-threaded mode is switched
+    off, see the skipped test below.)"""
+    import time
+    fr = [150.0, 200.0, 250.0, 300.0]
+    ctxs = []
+    for f in fr:
+        room = synth.shoebox(3.0, 2.5, 2.0, synth.SOUND_SPEED / (6.0 * f))
+        rs, _ = synth.source_and_receivers(room, 2)
+        ctx = make_ctx(F, room, synth.wavenumber(f))
+        ctx.fmmbem_set_sources(rs)
+        ctxs.append(ctx)
+    kw = dict(tol=1e-6, restart=100, maxit=300)
+    t0 = time.perf_counter()
+    seq = [c.fmmbem_solve(0, **kw) for c in ctxs]
+    t_seq = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    xs, reps, status, rc = F.fmmbem_solve_many(ctxs, [0] * len(ctxs), **kw)
+    t_par = time.perf_counter() - t0
+    print(f"N {[c.fmmbem_num_unknowns() for c in ctxs]}: one by one {t_seq:.3f} s, solve_many {t_par:.3f} s, "
+          f"iterations {[r.iters for r in reps]}")
+    assert rc == 0 and status == [0] * len(ctxs)
+    for (x1, rep1, _), x2, rep2 in zip(seq, xs, reps):
+        assert rep1.iters == rep2.iters and np.array_equal(x1, x2)
+    with pytest.raises(F.FmmbemError):
+        F.fmmbem_solve_many([ctxs[0], ctxs[0]], [0, 0], **kw)
+    for c in ctxs:
+        c.close()
+
+
+@pytest.mark.skip(reason="multi-threaded fmmbem_solve_many is switched off: a 16-thread sweep of 16 L-room "
+                         "contexts (mixed precision) crashed the process with a host segmentation fault; "
+                         "no cause in the library has been shown, so the case stays off the GPU")
+def test_solve_many_concurrent_threads(F):
+    """Concurrent solving from several host threads (kept for when the cause is found)."""
