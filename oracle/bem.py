@@ -22,6 +22,7 @@ Definitions followed (paper, Sections 2-3):
     sigma = g- + g+ + i k (beta- psi- + beta+ psi+), mu = psi+ - psi- (Eq. ibem4)
   * combined (Burton-Miller) direct equation: Eq. (dbem3) plus alpha = i/k times its normal
     derivative (see bm_system), same unknown and field as Eq. (dbem4)
+  * normal-derivative form, Eq. (dbem5): unknown dpsi_sc/dn (see dpsi_system)
 """
 from __future__ import annotations
 
@@ -311,6 +312,43 @@ def bm_rhs_rows(V, T, k, beta, rs, rc, rows, eta=DEFAULT_ETA):
     a = bm_alpha(k)
     y, yn = layer_rows_n(V, T, k, rc, rows, g, np.zeros_like(g), eta)
     return y + a * (yn - 0.5 * g[rows])
+
+
+# ----------------------------------------------------------------------------- normal-derivative form
+# Eq. (dbem5): unknown v = dpsi_sc/dn.  With the impedance condition psi_sc = zeta (v - gamma) / (i k)
+# (zeta = 1/beta) in Eq. (dbem3), multiplied by i k / zeta at the collocation point:
+#   A v = v/2 + beta M[zeta v] - i k beta L[v],     b = gamma/2 + beta M[zeta gamma]
+# (per element: beta_i on the row, zeta_j on the column).  Needs beta != 0 on every element.
+def dpsi_system(V, T, k, beta, rs, rc, eta=DEFAULT_ETA):
+    """Dense A and b of Eq. (dbem5); also returns gamma."""
+    L, M = dense_LM(V, T, k, rc, eta)
+    c, nrm, _ = geometry(V, T)
+    zeta = 1.0 / beta
+    n = T.shape[0]
+    A = 0.5 * np.eye(n) + beta[:, None] * (M * zeta[None, :] - 1j * k * L)
+    g = gamma(c, nrm, beta, k, rs)
+    b = 0.5 * g + beta * (M @ (zeta * g))
+    return A, b, g
+
+
+def dpsi_matvec_rows(V, T, k, beta, rc, v, rows, eta=DEFAULT_ETA):
+    rows = np.asarray(rows, np.int64)
+    y = layer_rows(V, T, k, rc, rows, -1j * k * v, v / beta, eta)
+    return 0.5 * v[rows] + beta[rows] * y
+
+
+def dpsi_rhs_rows(V, T, k, beta, rs, rc, rows, eta=DEFAULT_ETA):
+    c, nrm, _ = geometry(V, T)
+    g = gamma(c, nrm, beta, k, rs)
+    rows = np.asarray(rows, np.int64)
+    y = layer_rows(V, T, k, rc, rows, np.zeros_like(g), g / beta, eta)
+    return 0.5 * g[rows] + beta[rows] * y
+
+
+def dpsi_to_psi(V, T, k, beta, rs, v):
+    """psi_sc on the elements from the normal-derivative unknown: psi_sc = (v - gamma) / (i k beta)."""
+    c, nrm, _ = geometry(V, T)
+    return (v - gamma(c, nrm, beta, k, rs)) / (1j * k * beta)
 
 
 # ----------------------------------------------------------------------------- dense solvers
