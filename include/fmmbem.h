@@ -60,6 +60,11 @@ enum {
 /* formulations (Section 3.1 / 3.2) */
 enum {
     FMMBEM_DIRECT = 0,  /* Eq. dbem4: unknown psi_sc at each element (N unknowns) */
+    FMMBEM_DIRECT_DPSI = 1, /* Eq. dbem5: unknown dpsi_sc/dn at each element (N unknowns); needs
+                               beta != 0 everywhere (zeta = 1/beta); fmmbem_eval_field takes this
+                               unknown; preconditioners none, diagonal, leaf blocks; one vector per
+                               pass.  Its operator is Eq. dbem4's similarity transform by
+                               diag(beta), with slower FGMRES convergence for large zeta (Sec. 3.1) */
     FMMBEM_DIRECT_BM = 2, /* combined (Burton-Miller) direct equation: Eq. dbem3 plus alpha = i/k
                              times its normal derivative (Section 3.2 jump relations), the same
                              unknown and field as Eq. dbem4; adds the near entries of L' and M';
@@ -148,7 +153,7 @@ int fmmbem_set_admittance(fmmbem_ctx *ctx, const fmmbem_c64 *beta);
 /* Unit monopole sources (Eq. sp6): ns positions rs (ns*3), optional complex amplitudes (NULL = 1). */
 int fmmbem_set_sources(fmmbem_ctx *ctx, int32_t ns, const double *rs, const fmmbem_c64 *amp);
 
-/* FMMBEM_DIRECT, FMMBEM_DIRECT_BM or FMMBEM_INDIRECT.  The indirect formulation adds the near entries of L'
+/* FMMBEM_DIRECT, FMMBEM_DIRECT_DPSI, FMMBEM_DIRECT_BM or FMMBEM_INDIRECT.  The indirect formulation adds the near entries of L'
  * and the hypersingular M' (Eq. ibem3; built on first use) and evaluates the normal derivative
  * of the far field at every element; preconditioners: FMMBEM_PC_NONE or FMMBEM_PC_DIAG
  * (2x2 element blocks). */

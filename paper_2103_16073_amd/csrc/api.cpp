@@ -37,6 +37,11 @@ __global__ void k_rhs_ind_local(int64_t, const int32_t *, const double2 *, const
 __global__ void k_bm_combine(int64_t, const int32_t *, const double2 *, const double2 *, double, double2,
                              const double2 *, double2 *);
 __global__ void k_bm_rhs(int64_t, const int32_t *, const double2 *, double2, const double2 *, double2 *);
+__global__ void k_densities_dpsi(int64_t, const int32_t *, const double2 *, const double2 *, double, double2 *,
+                                 double2 *);
+__global__ void k_dpsi_combine(int64_t, const int32_t *, const double2 *, const double2 *, const double2 *, double2 *);
+__global__ void k_rhs_dpsi_dens(int64_t, const int32_t *, const double2 *, double2 *, double2 *, double2 *);
+__global__ void k_scale_beta(int64_t, const int32_t *, const double2 *, int, const double2 *, double2 *);
 __global__ void k_diag_bm_inv(int64_t, const int32_t *, const int32_t *, const int32_t *, const double2 *,
                               const double2 *, const double2 *, const double2 *, const double2 *, double, double2,
                               double, double2 *);
@@ -1274,6 +1279,53 @@ static void rhs_bm(fmmbem_ctx *c, int isrc, double2 *b) {
     LAUNCH_OK();
 }
 
+// ------------------------------------------------------------------ normal-derivative form (Eq. dbem5)
+// Unknown v = dpsi_sc/dn; A v = v/2 + beta (L[-i k v] + M[zeta v]) through the direct FMM pass;
+// b = gamma/2 + beta M[zeta gamma].  zeta = 1/beta: every element needs beta != 0.
+static bool dpsi(const fmmbem_ctx *c) { return c->formulation == FMMBEM_DIRECT_DPSI; }
+static void check_dpsi_beta(const fmmbem_ctx *c) {
+    for (const double2 &b : c->beta)
+        if (b.x == 0.0 && b.y == 0.0)
+            throw FmmError(FMMBEM_EINVAL, "Eq. dbem5 needs beta != 0 on every element (zeta = 1/beta)");
+}
+
+static void matvec_dpsi(fmmbem_ctx *c, const double2 *v, double2 *y, bool exact_far, bool mixed = false) {
+    const int64_t n = c->nt;
+    hipStream_t st = c->stream;
+    if (mixed) ensure_mixed(c);
+    double2 *sigma = dget<double2>(c->scratch, "sigma", n), *mu = dget<double2>(c->scratch, "mu", n);
+    double2 *P = dget<double2>(c->scratch, "d5_p", n);
+    const int32_t *perm = (int32_t *)c->buf.find("perm");
+    const double2 *beta = (double2 *)c->buf.find("beta");
+    rec(c, 0);
+    k_densities_dpsi<<<ceil_div(n, 256), 256, 0, st>>>(n, perm, v, beta, c->k, sigma, mu);
+    LAUNCH_OK();
+    fmm_pass(c, 1, sigma, mu, nullptr, 0.0, P, exact_far, mixed);
+    k_dpsi_combine<<<ceil_div(n, 256), 256, 0, st>>>(n, perm, v, beta, P, y);
+    LAUNCH_OK();
+    rec(c, 8);
+}
+
+static void rhs_dpsi(fmmbem_ctx *c, int isrc, double2 *b) {
+    hipStream_t st = c->stream;
+    const int64_t n = c->nt;
+    double2 *sigma = dget<double2>(c->scratch, "sigma", n), *mu = dget<double2>(c->scratch, "mu", n);
+    double2 *P = dget<double2>(c->scratch, "d5_p", n), *gam = dget<double2>(c->scratch, "d5_gam", n);
+    const int32_t *perm = (int32_t *)c->buf.find("perm");
+    const double2 *beta = (double2 *)c->buf.find("beta");
+    const double *rs = &c->src[3 * isrc];
+    k_gamma<<<ceil_div(n, 256), 256, 0, st>>>(n, (double4 *)c->buf.find("ec"), (double4 *)c->buf.find("en"), beta,
+                                              c->k, rs[0], rs[1], rs[2], c->src_amp[isrc], sigma, mu);
+    LAUNCH_OK();
+    k_rhs_dpsi_dens<<<ceil_div(n, 256), 256, 0, st>>>(n, perm, beta, sigma, mu, gam);
+    LAUNCH_OK();
+    HIP_OK(hipEventRecord(c->ev[0], st));
+    fmm_pass(c, 1, sigma, mu, nullptr, 0.0, P, false);
+    HIP_OK(hipEventRecord(c->ev[8], st));
+    k_dpsi_combine<<<ceil_div(n, 256), 256, 0, st>>>(n, perm, gam, beta, P, b);
+    LAUNCH_OK();
+}
+
 }  // namespace fmm
 
 using namespace fmm;
@@ -1473,9 +1525,10 @@ int fmmbem_set_sources(fmmbem_ctx *ctx, int32_t ns, const double *rs, const fmmb
 
 int fmmbem_set_formulation(fmmbem_ctx *ctx, int f) {
     if (!ctx) return FMMBEM_EINVAL;
-    if (f != FMMBEM_DIRECT && f != FMMBEM_DIRECT_BM && f != FMMBEM_INDIRECT)
+    if (f != FMMBEM_DIRECT && f != FMMBEM_DIRECT_DPSI && f != FMMBEM_DIRECT_BM && f != FMMBEM_INDIRECT)
         return fail(ctx, FMMBEM_EINVAL,
-                    "formulation must be FMMBEM_DIRECT (Eq. dbem4), FMMBEM_DIRECT_BM or FMMBEM_INDIRECT (Eq. ibem5)");
+                    "formulation must be FMMBEM_DIRECT (Eq. dbem4), FMMBEM_DIRECT_DPSI (Eq. dbem5), "
+                    "FMMBEM_DIRECT_BM or FMMBEM_INDIRECT (Eq. ibem5)");
     if (f != ctx->formulation) drop_graphs(ctx);
     ctx->formulation = f;
     return FMMBEM_OK;
@@ -1523,6 +1576,10 @@ int fmmbem_rhs(fmmbem_ctx *ctx, fmmbem_c64 *b) {
     for (size_t s = 0; s < ctx->src.size() / 3; ++s) {
         if (indirect(ctx)) rhs_ind(ctx, (int)s, db);
         else if (burton_miller(ctx)) rhs_bm(ctx, (int)s, db);
+        else if (dpsi(ctx)) {
+            check_dpsi_beta(ctx);
+            rhs_dpsi(ctx, (int)s, db);
+        }
         else rhs_dev(ctx, (int)s, db);
         HIP_OK(hipMemcpyAsync(b + s * n, db, sizeof(double2) * n, hipMemcpyDeviceToHost, ctx->stream));
     }
@@ -1550,12 +1607,14 @@ int fmmbem_matvec(fmmbem_ctx *ctx, int32_t nrhs, const fmmbem_c64 *x, fmmbem_c64
         }
         return FMMBEM_OK;
     }
-    if (burton_miller(ctx)) {
+    if (burton_miller(ctx) || dpsi(ctx)) {
         const int64_t n = ctx->nt;
+        if (dpsi(ctx)) check_dpsi_beta(ctx);
         double2 *dx = dget<double2>(ctx->scratch, "mv_x", n), *dy = dget<double2>(ctx->scratch, "mv_y", n);
         for (int r = 0; r < nrhs; ++r) {
             HIP_OK(hipMemcpyAsync(dx, x + (int64_t)r * n, sizeof(double2) * n, hipMemcpyHostToDevice, ctx->stream));
-            matvec_bm(ctx, dx, dy, exact_far != 0, precision == FMMBEM_MIXED);
+            if (dpsi(ctx)) matvec_dpsi(ctx, dx, dy, exact_far != 0, precision == FMMBEM_MIXED);
+            else matvec_bm(ctx, dx, dy, exact_far != 0, precision == FMMBEM_MIXED);
             HIP_OK(hipMemcpyAsync(y + (int64_t)r * n, dy, sizeof(double2) * n, hipMemcpyDeviceToHost, ctx->stream));
             HIP_OK(hipStreamSynchronize(ctx->stream));
         }
@@ -1599,6 +1658,11 @@ int fmmbem_matvec_dev(fmmbem_ctx *ctx, int32_t nrhs, const void *x, void *y, int
         for (int r = 0; r < nrhs; ++r)
             matvec_bm(ctx, (const double2 *)x + (int64_t)r * n, (double2 *)y + (int64_t)r * n, false,
                       precision == FMMBEM_MIXED);
+    } else if (dpsi(ctx)) {
+        check_dpsi_beta(ctx);
+        for (int r = 0; r < nrhs; ++r)
+            matvec_dpsi(ctx, (const double2 *)x + (int64_t)r * n, (double2 *)y + (int64_t)r * n, false,
+                        precision == FMMBEM_MIXED);
     } else {
         matvec_dev(ctx, nrhs, (const double2 *)x, (double2 *)y, false, precision == FMMBEM_MIXED);
     }
@@ -1724,6 +1788,8 @@ static std::function<void(const double2 *, double2 *)> make_precond(fmmbem_ctx *
         };
     }
     if (o.precond == FMMBEM_PC_LEARNED) {
+        if (ctx->formulation != FMMBEM_DIRECT)
+            throw FmmError(FMMBEM_EINVAL, "the learned preconditioner is for the direct formulation (Eq. dbem4)");
         if (!ctx->mlp.ready) throw FmmError(FMMBEM_ENOTREADY, "learned preconditioner not trained");
         fmmbem_solve_opts nb = o;
         nb.precond = FMMBEM_PC_NEARBLOCK;
@@ -1825,14 +1891,30 @@ int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, f
     if (dirty) t_before = ctx->t_setup_last;
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = ctx->stream;
-    const bool ind = indirect(ctx);
+    const bool ind = indirect(ctx), bm = burton_miller(ctx), dp = dpsi(ctx);
     const int64_t n = fmmbem_num_unknowns(ctx);
     auto pc = make_precond(ctx, o);
+    if (dp && o.precond == FMMBEM_PC_NEARBLOCK) {
+        // Eq. (dbem5)'s operator is Eq. (dbem4)'s similarity transform by diag(beta): its leaf-block
+        // inverse is beta P4 zeta (the diagonal preconditioner is the same for both)
+        auto p4 = pc;
+        double2 *tmp = dget<double2>(ctx->scratch, "d5_pc", n);
+        const int32_t *pm = (int32_t *)ctx->buf.find("perm");
+        const double2 *be = (double2 *)ctx->buf.find("beta");
+        pc = [=](const double2 *v, double2 *z) {
+            k_scale_beta<<<ceil_div(n, 256), 256, 0, st>>>(n, pm, be, 1, v, tmp);
+            LAUNCH_OK();
+            p4(tmp, z);
+            k_scale_beta<<<ceil_div(n, 256), 256, 0, st>>>(n, pm, be, 0, z, z);
+            LAUNCH_OK();
+        };
+    }
     double2 *b = dget<double2>(ctx->scratch, "sv_b", n);
     double2 *dx = dget<double2>(ctx->scratch, "sv_x", n);
-    const bool bm = burton_miller(ctx);
+    if (dp) check_dpsi_beta(ctx);
     if (ind) rhs_ind(ctx, isrc, b);
     else if (bm) rhs_bm(ctx, isrc, b);
+    else if (dp) rhs_dpsi(ctx, isrc, b);
     else rhs_dev(ctx, isrc, b);
     if (o.use_x0) HIP_OK(hipMemcpyAsync(dx, x, sizeof(double2) * n, hipMemcpyHostToDevice, st));
     // the Krylov products run in the requested arithmetic; restart residuals always in FP64
@@ -1840,6 +1922,7 @@ int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, f
     auto product = [&](const double2 *a, double2 *y, bool mixed) {
         if (ind) matvec_ind(ctx, a, y, false, mixed);
         else if (bm) matvec_bm(ctx, a, y, false, mixed);
+        else if (dp) matvec_dpsi(ctx, a, y, false, mixed);
         else matvec_dev(ctx, 1, a, y, false, mixed);
         ++(mixed ? nmx : n64);
     };
@@ -1922,7 +2005,7 @@ int fmmbem_solve_batch(fmmbem_ctx *ctx, int32_t ns, const int32_t *isrc, const f
     if (int e = check_solve_opts(ctx, o)) return e;
     if (o.inner_iters > 0) return fail(ctx, FMMBEM_EINVAL, "the batched solve has no inner-outer scheme");
     if (o.precond == FMMBEM_PC_LEARNED) return fail(ctx, FMMBEM_EINVAL, "the batched solve has no learned guard");
-    if (indirect(ctx) || burton_miller(ctx))
+    if (indirect(ctx) || burton_miller(ctx) || dpsi(ctx))
         return fail(ctx, FMMBEM_EINVAL, "the batched solve is for the direct formulation (Eq. dbem4)");
     GUARD_BEGIN
     HIP_OK(hipSetDevice(ctx->device));
@@ -2085,7 +2168,7 @@ int fmmbem_learned_train(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_train_opts 
     HIP_OK(hipSetDevice(ctx->device));
     if (ctx->src.empty()) return fail(ctx, FMMBEM_ENOTREADY, "sources not set");
     if (isrc < 0 || isrc >= (int)(ctx->src.size() / 3)) return fail(ctx, FMMBEM_EINVAL, "bad source index");
-    if (indirect(ctx) || burton_miller(ctx))
+    if (indirect(ctx) || burton_miller(ctx) || dpsi(ctx))
         return fail(ctx, FMMBEM_EINVAL, "the learned preconditioner is for the direct formulation (Eq. dbem4)");
     ensure_setup(ctx);
     ensure_chunks(ctx);
@@ -2258,16 +2341,23 @@ int fmmbem_eval_field(fmmbem_ctx *ctx, int32_t isrc, int64_t nr, const double *r
                                               (double2 *)ctx->buf.find("beta"), ctx->k, rs[0], rs[1], rs[2],
                                               ctx->src_amp[isrc], gam, zero);
     LAUNCH_OK();
-    // sigma = gamma + i k beta x, mu = -x  (sorted order)
+    // sigma = gamma + i k beta x, mu = -x  (sorted order); Eq. (dbem5)'s unknown is the normal
+    // derivative v = sigma itself, with x = psi_sc = (v - gamma) / (i k beta)
     std::vector<double2> xs(n), g(n), bet(n), sg(n), mu(n);
     HIP_OK(hipMemcpyAsync(g.data(), gam, sizeof(double2) * n, hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
+    if (dpsi(ctx)) check_dpsi_beta(ctx);
     for (int64_t i = 0; i < n; ++i) {
         int j = ctx->tree.perm[i];
         double2 xi = cmk(x[j].re, x[j].im), be = ctx->beta[j];
-        double2 ikbx = cmul(cmk(-ctx->k * be.y, ctx->k * be.x), xi);
-        sg[i] = cadd(g[i], ikbx);
-        mu[i] = cscale(xi, -1.0);
+        const double2 ikb = cmk(-ctx->k * be.y, ctx->k * be.x);
+        if (dpsi(ctx)) {
+            sg[i] = xi;
+            mu[i] = cscale(cdiv(csub(xi, g[i]), ikb), -1.0);
+        } else {
+            sg[i] = cadd(g[i], cmul(ikb, xi));
+            mu[i] = cscale(xi, -1.0);
+        }
     }
     double2 *dsg = upload(ctx->scratch, "fe_sg", sg, st), *dmu = upload(ctx->scratch, "fe_mu", mu, st);
     std::vector<double> pts(r, r + 3 * nr);

@@ -1034,6 +1034,45 @@ __global__ void k_rhs_ind_local(int64_t n, const int32_t *perm, const double2 *g
     b[n + u] = cadd(b[n + u], cscale(csub(gp[i], gm[i]), 0.5));
 }
 
+// Eq. (dbem5), unknown v = dpsi_sc/dn (caller order): densities sigma = -i k v, mu = zeta v with
+// zeta = 1/beta (tree order); the product is v/2 + beta (L[sigma] + M[mu]).
+__global__ void k_densities_dpsi(int64_t n, const int32_t *perm, const double2 *v, const double2 *beta, double k,
+                                 double2 *sigma, double2 *mu) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double2 vi = v[perm[i]];
+    sigma[i] = cmk(k * vi.y, -k * vi.x);  // -i k v
+    mu[i] = cdiv(vi, beta[i]);
+}
+// y = half h + beta P (h, P, y caller order; beta tree order): the product (h = v) and the
+// right-hand side (h = gamma in caller order)
+__global__ void k_dpsi_combine(int64_t n, const int32_t *perm, const double2 *h, const double2 *beta, const double2 *P,
+                               double2 *y) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t u = perm[i];
+    y[u] = cadd(cscale(h[u], 0.5), cmul(beta[i], P[u]));
+}
+// right-hand side densities of Eq. (dbem5): gamma (in sigma, tree order) -> gamma in caller order,
+// mu = zeta gamma, sigma = 0
+__global__ void k_rhs_dpsi_dens(int64_t n, const int32_t *perm, const double2 *beta, double2 *sigma, double2 *mu,
+                                double2 *gam_caller) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double2 g = sigma[i];
+    gam_caller[perm[i]] = g;
+    mu[i] = cdiv(g, beta[i]);
+    sigma[i] = cmk(0, 0);
+}
+// z = v * beta (inv = 0) or v / beta (inv = 1), caller order
+__global__ void k_scale_beta(int64_t n, const int32_t *perm, const double2 *beta, int inv, const double2 *v,
+                             double2 *z) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t u = perm[i];
+    z[u] = inv ? cdiv(v[u], beta[i]) : cmul(v[u], beta[i]);
+}
+
 // Combined (Burton-Miller) direct equation: Eq. (dbem3) plus alpha times its normal derivative
 // (Section 3.2 jump relations; v = dpsi/dn = gamma + i k beta psi).  From the potential P and the
 // normal derivative Q of the layers sigma = -i k beta x, mu = x (caller order, pq[0..n) and

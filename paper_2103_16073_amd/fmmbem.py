@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libfmmbem.so")
 
 FMMBEM_OK, FMMBEM_ENOCONV = 0, 1
 FMMBEM_EINVAL, FMMBEM_ENOMEM, FMMBEM_EDEVICE, FMMBEM_ENOTREADY, FMMBEM_EBREAKDOWN, FMMBEM_ENAN = -1, -2, -3, -4, -5, -6
-FMMBEM_DIRECT, FMMBEM_DIRECT_BM, FMMBEM_INDIRECT = 0, 2, 3
+FMMBEM_DIRECT, FMMBEM_DIRECT_DPSI, FMMBEM_DIRECT_BM, FMMBEM_INDIRECT = 0, 1, 2, 3
 FMMBEM_FP64, FMMBEM_MIXED = 0, 1
 FMMBEM_PC_NONE, FMMBEM_PC_DIAG, FMMBEM_PC_NEARBLOCK, FMMBEM_PC_LEARNED = 0, 1, 2, 3
 

@@ -1,0 +1,117 @@
+"""Normal-derivative form, Eq. (dbem5), through the C ABI against the oracle: the product (all-pairs,
+FMM in FP64 and mixed precision), the right-hand side, the solve with the field at receivers, the
+beta != 0 requirement, and FGMRES iteration counts against Eq. (dbem4) for small and large zeta
+(the 3 x 2.5 x 2 m room at 250 Hz, 2,664 elements)."""
+import numpy as np
+import pytest
+
+from oracle import bem
+from paper_2103_16073_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def F():
+    from paper_2103_16073_amd import fmmbem
+    return fmmbem
+
+
+@pytest.fixture(scope="module")
+def room1():
+    return synth.config_room(1)
+
+
+def make_ctx(F, room, k, beta, form, rs=None, **opt):
+    ctx = F.Context(0, **opt)
+    ctx.fmmbem_set_mesh(room.vertices, room.triangles)
+    ctx.fmmbem_set_wavenumber(k)
+    ctx.fmmbem_set_admittance(beta)
+    ctx.fmmbem_set_formulation(form)
+    if rs is not None:
+        ctx.fmmbem_set_sources(rs)
+    return ctx
+
+
+@pytest.mark.parametrize("leaf_max", [64, 12])
+def test_dpsi_product_vs_dense(F, room1, leaf_max):
+    room, k = room1
+    ctx = make_ctx(F, room, k, room.beta, F.FMMBEM_DIRECT_DPSI, leaf_max=leaf_max)
+    rc = ctx.fmmbem_get_info().rc
+    A, _, _ = bem.dpsi_system(room.vertices, room.triangles, k, room.beta, np.array([1.0, 1.0, 1.0]), rc)
+    for seed in (1, 2):
+        v = synth.complex_normal(room.n, seed)
+        ref = A @ v
+        ye = ctx.fmmbem_matvec(v, exact_far=True)[0]
+        y = ctx.fmmbem_matvec(v)[0]
+        ym = ctx.fmmbem_matvec(v, precision=F.FMMBEM_MIXED)[0]
+        e = [np.linalg.norm(z - ref) / np.linalg.norm(ref) for z in (ye, y, ym)]
+        print(f"leaf_max {leaf_max} seed {seed}: all-pairs {e[0]:.2e} fmm {e[1]:.2e} mixed {e[2]:.2e}")
+        assert e[0] < 1e-10 and e[1] < 1e-6 and e[2] < 1e-4
+    ctx.close()
+
+
+def test_dpsi_rhs_vs_oracle_and_zero_beta_rejected(F, room1):
+    room, k = room1
+    rs, _ = synth.source_and_receivers(room, 4)
+    ctx = make_ctx(F, room, k, room.beta, F.FMMBEM_DIRECT_DPSI, rs=rs)
+    b = ctx.fmmbem_rhs()[0]
+    rc = ctx.fmmbem_get_info().rc
+    rows = np.arange(0, room.n, 7)
+    ref = bem.dpsi_rhs_rows(room.vertices, room.triangles, k, room.beta, rs[0], rc, rows)
+    assert np.linalg.norm(b[rows] - ref) / np.linalg.norm(ref) < 1e-6
+    beta0 = room.beta.copy()
+    beta0[5] = 0.0
+    ctx.fmmbem_set_admittance(beta0)
+    with pytest.raises(F.FmmbemError):
+        ctx.fmmbem_matvec(synth.complex_normal(room.n, 3))
+    ctx.close()
+
+
+@pytest.mark.parametrize("precond,precision", [(1, 0), (2, 0), (2, 1)])
+def test_dpsi_solve_and_field_vs_lu(F, room1, precond, precision):
+    """FGMRES (diagonal or leaf-block preconditioner -- the leaf blocks of Eq. dbem4 transformed by
+    diag(beta) --, FP64 or mixed products) to 1e-8 agrees with the LU solution of the oracle's dense
+    system, and the field at receivers with the oracle's.  Condition number 13.6 here, so FMM
+    products within 1e-6 bound the deviation by 13.6 (1e-6 + 1e-8) < 2e-5."""
+    room, k = room1
+    rs, rec = synth.source_and_receivers(room, 16)
+    ctx = make_ctx(F, room, k, room.beta, F.FMMBEM_DIRECT_DPSI, rs=rs)
+    v, rep, rc_ = ctx.fmmbem_solve(0, tol=1e-8, restart=200, maxit=600, precond=precond, precision=precision)
+    rc = ctx.fmmbem_get_info().rc
+    A, b, _ = bem.dpsi_system(room.vertices, room.triangles, k, room.beta, rs[0], rc)
+    v_ref = bem.solve_lu(A, b)
+    ev = np.linalg.norm(v - v_ref) / np.linalg.norm(v_ref)
+    psi = ctx.fmmbem_eval_field(0, rec, v)
+    x_ref = bem.dpsi_to_psi(room.vertices, room.triangles, k, room.beta, rs[0], v_ref)
+    psi_ref = bem.direct_receivers(room.vertices, room.triangles, k, room.beta, rs[0], rc, x_ref, rec)
+    ef = np.linalg.norm(psi - psi_ref) / np.linalg.norm(psi_ref)
+    print(f"precond {precond} precision {precision}: iters {rep.iters} rel {rep.rel_res:.2e}; vs LU {ev:.2e}, "
+          f"field {ef:.2e}")
+    assert rc_ == 0 and rep.rel_res < 1e-8 and ev < 2e-5 and ef < 2e-5
+    ctx.close()
+
+
+@pytest.mark.parametrize("precond", [0, 2])
+def test_dpsi_vs_dbem4_iterations(F, room1, precond):
+    """Iteration counts of FGMRES (FP64, to 1e-6, no preconditioner or leaf blocks) for Eq. (dbem4)
+    and Eq. (dbem5) at the room's admittance and at a tenth of it (zeta ten times larger), and
+    agreement of the two solutions' fields (the operators are similar, so the discrete solutions
+    coincide).  With leaf blocks the preconditioned operators are similar too."""
+    room, k = room1
+    rs, rec = synth.source_and_receivers(room, 16)
+    out = {}
+    for scale in (1.0, 0.1):
+        beta = room.beta * scale
+        fields = []
+        for form in (F.FMMBEM_DIRECT, F.FMMBEM_DIRECT_DPSI):
+            ctx = make_ctx(F, room, k, beta, form, rs=rs)
+            x, rep, rc_ = ctx.fmmbem_solve(0, tol=1e-6, restart=600, maxit=600, precond=precond)
+            assert rc_ == 0
+            fields.append(ctx.fmmbem_eval_field(0, rec, x))
+            out[(scale, form)] = rep.iters
+            ctx.close()
+        d = np.linalg.norm(fields[1] - fields[0]) / np.linalg.norm(fields[0])
+        print(f"precond {precond} beta x {scale}: iterations dbem4 {out[(scale, 0)]}, dbem5 {out[(scale, 1)]}; "
+              f"field diff {d:.1e}")
+        assert d < 1e-4
