@@ -128,6 +128,13 @@ typedef struct {
                             one kernel, the 32-job vectors resident in LDS and transformed on
                             matrix cores: 1 under the fixed rule and as an autotuner candidate,
                             0 never; default 1 */
+    double kd_leaf_min;  /* lower bound on k times the leaf side: the octree stops refining before
+                            its leaves get smaller than kd_leaf_min / k, because at small k tau the
+                            singular coaxial tables lose their small entries to round-off (the
+                            product's error rises to 3e-4 at k d = 0.37 and to O(1) at 0.18 with
+                            p = 16); low frequencies then take larger leaves and more near-field
+                            pairs.  The depth follows k: a change of wavenumber that moves the bound
+                            rebuilds the octree.  0 disables; default 0.75 */
 } fmmbem_options;
 
 void fmmbem_default_options(fmmbem_options *opt);

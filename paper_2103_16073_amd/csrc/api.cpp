@@ -148,7 +148,8 @@ static void setup_mesh(fmmbem_ctx *c) {
     }
     c->rc = c->opt.rc > 0 ? c->opt.rc : c->opt.rc_factor * std::sqrt(2.0 * asum / (double)n);
     TreeHost &T = c->tree;
-    build_tree(cen.data(), n, vlo, vhi, c->rc, c->opt.leaf_max, c->opt.max_depth, T);
+    c->tree_min_leaf = c->opt.kd_leaf_min > 0 ? c->opt.kd_leaf_min / c->k : 0.0;
+    build_tree(cen.data(), n, vlo, vhi, c->rc, c->opt.leaf_max, c->opt.max_depth, c->tree_min_leaf, T);
     const int L = T.depth;
     hipStream_t st = c->stream;
     // sorted element arrays
@@ -535,6 +536,17 @@ static void ensure_setup(fmmbem_ctx *c) {
         c->chunks_ready = false;
     }
     if (c->mesh_dirty || c->k_dirty) c->indirect_ready = false;
+    if (!c->mesh_dirty && c->k_dirty && c->opt.kd_leaf_min > 0) {
+        // the leaf-size bound follows k: rebuild the octree when it would now allow a different depth
+        const double nb = c->opt.kd_leaf_min / c->k, side = c->tree.side;
+        auto cap = [&](double ml) {  // deepest level whose boxes are not smaller than ml
+            int L = 2;
+            while (L < 21 && side / (double)(1u << (L + 1)) >= ml) ++L;
+            return L;
+        };
+        const int d = c->tree.depth, c_old = cap(c->tree_min_leaf), c_new = cap(nb);
+        if (c_old != c_new && (d >= std::min(c_old, c_new))) c->mesh_dirty = true;
+    }
     if (c->mesh_dirty) {
         setup_mesh(c);
         c->k_dirty = true;
@@ -1365,6 +1377,7 @@ void fmmbem_default_options(fmmbem_options *o) {
     o->streams = 2;
     o->mfma = 1;
     o->fused = 1;
+    o->kd_leaf_min = 0.75;
 }
 
 void fmmbem_default_solve_opts(fmmbem_solve_opts *o) {

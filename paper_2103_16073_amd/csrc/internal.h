@@ -116,7 +116,7 @@ struct TreeHost {
 
 void box_center(const TreeHost &T, int l, uint64_t code, double *c);
 void build_tree(const double *centroids, int64_t n, const double *vlo, const double *vhi, double rc,
-                int leaf_max, int max_depth, TreeHost &T);
+                int leaf_max, int max_depth, double min_leaf, TreeHost &T);
 
 // ---------------------------------------------------------------- translation batches
 // One set of translation jobs (a level's M2L, M2M or L2L), sorted by coaxial table and padded
@@ -229,6 +229,7 @@ struct FgmresHooks {
 // ---------------------------------------------------------------- the context
 struct fmmbem_ctx {
     int device = 0;
+    double tree_min_leaf = 0.0;  // smallest leaf side the octree was allowed (kd_leaf_min / k at build)
     fmmbem_options opt{};
     std::string err;
     hipStream_t stream = nullptr;

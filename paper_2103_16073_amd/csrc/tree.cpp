@@ -49,7 +49,7 @@ static int64_t find_code(const std::vector<uint64_t> &codes, uint64_t c) {
 }
 
 void build_tree(const double *cen, int64_t n, const double *vlo, const double *vhi, double rc, int leaf_max,
-                int max_depth, TreeHost &T) {
+                int max_depth, double min_leaf, TreeHost &T) {
     const int DMAX = 21;
     max_depth = std::min(std::max(max_depth, 2), DMAX);
     double ext = 0.0, mid[3];
@@ -81,6 +81,7 @@ void build_tree(const double *cen, int64_t n, const double *vlo, const double *v
     for (L = 2; L <= max_depth; ++L) {
         double dl = T.side / (double)(1u << L);
         if (dl <= rc && L > 2) break;
+        if (dl < min_leaf && L > 2) break;  // leaves no smaller than min_leaf (the wavelength bound)
         int shift = 3 * (DMAX - L), occ = 0, run = 0;
         int64_t nbox = 0;
         uint64_t prev = ~0ULL;

@@ -35,7 +35,7 @@ class Options(ctypes.Structure):
                 ("p_min", ctypes.c_int), ("p_excess", ctypes.c_double), ("ktau_switch", ctypes.c_double),
                 ("max_depth", ctypes.c_int), ("lds_budget", ctypes.c_int), ("graphs", ctypes.c_int),
                 ("autotune", ctypes.c_int), ("lane_tiles", ctypes.c_int), ("streams", ctypes.c_int),
-                ("mfma", ctypes.c_int), ("fused", ctypes.c_int)]
+                ("mfma", ctypes.c_int), ("fused", ctypes.c_int), ("kd_leaf_min", ctypes.c_double)]
 
 
 class SolveOpts(ctypes.Structure):

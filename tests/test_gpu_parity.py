@@ -527,3 +527,29 @@ def test_solve_many_frequencies_match_sequential(F):
                          "no cause in the library has been shown, so the case stays off the GPU")
 def test_solve_many_concurrent_threads(F):
     """Concurrent solving from several host threads (kept for when the cause is found)."""
+
+
+def test_low_frequency_products_follow_k(F):
+    """Low frequencies (the 8 x 6 x 3 m room, 20-320 Hz, one mesh): the octree's leaves stay at least
+    kd_leaf_min / k wide, so the FMM product matches the all-pairs product (1e-6) where leaves of
+    k d = 0.18 gave an O(1) error; on one context the octree is rebuilt when a new wavenumber moves
+    that bound (20 -> 320 -> 20 Hz)."""
+    room = synth.shoebox(8.0, 6.0, 3.0, synth.SOUND_SPEED / (6.7 * 320.0))
+    ctx = F.Context(0)
+    ctx.fmmbem_set_mesh(room.vertices, room.triangles)
+    ctx.fmmbem_set_admittance(np.full(room.n, 1.0 / 9.0))
+    x = synth.complex_normal(room.n, 11)
+    depths = []
+    for f in (20.0, 320.0, 20.0, 60.0):
+        ctx.fmmbem_set_wavenumber(synth.wavenumber(f))
+        info = ctx.fmmbem_get_info()
+        depths.append(info.depth)
+        leaf = 8.0 * (1 + 1e-6) / 2 ** info.depth
+        assert info.depth == 2 or synth.wavenumber(f) * leaf >= 0.75
+        y = ctx.fmmbem_matvec(x)[0]
+        ye = ctx.fmmbem_matvec(x, exact_far=True)[0]
+        err = np.linalg.norm(y - ye) / np.linalg.norm(ye)
+        print(f"{f:5.0f} Hz: depth {info.depth}, FMM vs all-pairs {err:.2e}")
+        assert err < 1e-6
+    assert depths[0] == depths[2] < depths[1]
+    ctx.close()
