@@ -81,7 +81,7 @@ enum {
                          recursions and the Krylov algebra stay FP64 */
 };
 
-/* preconditioner slot of flexible GMRES (Section 4.4 names an inner FMM-GMRES and a diagonal one) */
+/* preconditioner slot of flexible GMRES (Section 4.3 names an inner FMM-GMRES and a diagonal one) */
 enum {
     FMMBEM_PC_NONE = 0,
     FMMBEM_PC_DIAG = 1,       /* z_i = v_i / (A_ii + diag_shift) */
@@ -201,7 +201,7 @@ typedef struct {
     int precision;     /* arithmetic of the inner products A z: FMMBEM_FP64 or FMMBEM_MIXED */
     double diag_shift; /* constant added to the diagonal in FMMBEM_PC_DIAG; default 0 */
     int use_x0;        /* nonzero: x holds the initial guess on entry */
-    /* Inner-outer scheme (Section 4.4: flexible GMRES preconditioned by a low-accuracy FMM
+    /* Inner-outer scheme (Section 4.3: flexible GMRES preconditioned by a low-accuracy FMM
      * GMRES).  inner_iters > 0: every outer preconditioner application runs up to inner_iters
      * GMRES steps (no restart) on A z = v with products in inner_precision, preconditioned by
      * `precond`, stopping early at relative residual inner_tol.  Default 0 (off), 1e-2, MIXED. */
@@ -213,6 +213,13 @@ typedef struct {
      * residuals stay FP64), 0 FP64, -1 (default) FP32 exactly when the products are MIXED (for
      * the inner solves: when inner_precision is). */
     int basis_fp32;
+    /* Coarser inner operator (Section 4.3: the inner GMRES uses a low-accuracy FMM).  inner_p_min
+     * > 0 (with inner_iters > 0): the inner GMRES applies an FMM with the truncation rule's p_min
+     * and excess replaced by inner_p_min and inner_p_excess, set up once on the same mesh,
+     * wavenumber, admittance and formulation (its own tables and near-field entries, kept until
+     * one of those changes); 0 (default): the inner GMRES applies the solve's own operator. */
+    int inner_p_min;
+    double inner_p_excess;
 } fmmbem_solve_opts;
 
 typedef struct {
@@ -227,11 +234,12 @@ typedef struct {
     int64_t inner_iters;   /* total inner GMRES steps */
     int32_t pc_fallback_at; /* FMMBEM_PC_LEARNED: iteration at which the guard dropped the learned
                                correction, -1 if it acted throughout */
+    int64_t matvecs_coarse; /* products of the coarser inner operator (inner_p_min > 0) */
 } fmmbem_solve_report;
 
 void fmmbem_default_solve_opts(fmmbem_solve_opts *o);
 
-/* Solve A x = b for source `isrc` (b from fmmbem_rhs) by flexible GMRES (Section 4.4).
+/* Solve A x = b for source `isrc` (b from fmmbem_rhs) by flexible GMRES (Section 4.3).
  * x: N values (in: initial guess if use_x0, out: solution).  Returns FMMBEM_OK on
  * convergence, FMMBEM_ENOCONV at maxit (x still the best iterate), or an error. */
 int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, fmmbem_c64 *x,

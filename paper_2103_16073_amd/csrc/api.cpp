@@ -1338,9 +1338,59 @@ static void rhs_dpsi(fmmbem_ctx *c, int isrc, double2 *b) {
     LAUNCH_OK();
 }
 
+// ------------------------------------------------------------------ operator dispatch, coarser inner FMM
+// y = A x (device vectors, caller order) for the context's formulation
+static void apply_operator(fmmbem_ctx *c, const double2 *x, double2 *y, bool mixed) {
+    if (indirect(c)) matvec_ind(c, x, y, false, mixed);
+    else if (burton_miller(c)) matvec_bm(c, x, y, false, mixed);
+    else if (dpsi(c)) matvec_dpsi(c, x, y, false, mixed);
+    else matvec_dev(c, 1, x, y, false, mixed);
+}
+
 }  // namespace fmm
 
 using namespace fmm;
+
+// The coarser FMM of the inner GMRES (Section 4.3): a context of its own with the truncation rule's
+// p_min and excess replaced, on the same inputs; rebuilt when those change.
+static fmmbem_ctx *ensure_inner(fmmbem_ctx *c, int p_min, double p_excess) {
+    const bool inputs = c->inner_gen != c->input_gen;
+    if (c->inner && !inputs && c->inner_pmin == p_min && c->inner_pexc == p_excess) return c->inner;
+    fmmbem_options o = c->opt;
+    o.p_min = p_min;
+    o.p_excess = p_excess;
+    if (!c->inner) {
+        if (int rc = fmmbem_create(&c->inner, c->device, &o)) throw FmmError(rc, "inner context");
+    } else {
+        c->inner->opt = o;
+        c->inner->k_dirty = true;  // new truncation: tables and batches again
+    }
+    fmmbem_ctx *in = c->inner;
+    auto chk = [&](int rc) {
+        if (rc < 0) throw FmmError(rc, "inner context: " + in->err);
+    };
+    if (inputs) {
+        chk(fmmbem_set_mesh(in, c->nv, c->xyz.data(), c->nt, c->tri.data()));
+        chk(fmmbem_set_wavenumber(in, c->k));
+        std::vector<fmmbem_c64> b(c->nt), bp;
+        for (int64_t i = 0; i < c->nt; ++i) b[i] = {c->beta[i].x, c->beta[i].y};
+        chk(fmmbem_set_admittance(in, b.data()));
+        if (!c->beta_plus.empty()) {
+            bp.resize(c->nt);
+            for (int64_t i = 0; i < c->nt; ++i) bp[i] = {c->beta_plus[i].x, c->beta_plus[i].y};
+        }
+        chk(fmmbem_set_admittance_plus(in, bp.empty() ? nullptr : bp.data()));
+        chk(fmmbem_set_formulation(in, c->formulation));
+    }
+    ensure_setup(in);
+    HIP_OK(hipSetDevice(c->device));
+    c->inner_gen = c->input_gen;
+    c->inner_pmin = p_min;
+    c->inner_pexc = p_excess;
+    for (auto &e : c->xev)
+        if (!e) HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    return in;
+}
 
 // ------------------------------------------------------------------ ABI
 #define GUARD_BEGIN try {
@@ -1392,6 +1442,8 @@ void fmmbem_default_solve_opts(fmmbem_solve_opts *o) {
     o->basis_fp32 = -1;
     o->inner_tol = 1e-2;
     o->inner_precision = FMMBEM_MIXED;
+    o->inner_p_min = 0;
+    o->inner_p_excess = 1.0;
 }
 
 int fmmbem_release_workspace(fmmbem_ctx *ctx) {
@@ -1454,6 +1506,9 @@ int fmmbem_create(fmmbem_ctx **out, int hip_device, const fmmbem_options *opt) {
 int fmmbem_destroy(fmmbem_ctx *ctx) {
     if (!ctx) return FMMBEM_OK;
     (void)hipSetDevice(ctx->device);
+    if (ctx->inner) (void)fmmbem_destroy(ctx->inner);
+    for (auto &e : ctx->xev)
+        if (e) (void)hipEventDestroy(e);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     if (ctx->side) (void)hipStreamSynchronize(ctx->side);
     drop_graphs(ctx);
@@ -1497,6 +1552,7 @@ int fmmbem_set_mesh(fmmbem_ctx *ctx, int64_t nv, const double *xyz, int64_t nt, 
     ctx->nt = nt;
     ctx->have_mesh = true;
     ctx->mesh_dirty = true;
+    ++ctx->input_gen;
     if (ctx->have_beta && (int64_t)ctx->beta.size() != nt) ctx->have_beta = false;
     return FMMBEM_OK;
 }
@@ -1504,7 +1560,10 @@ int fmmbem_set_mesh(fmmbem_ctx *ctx, int64_t nv, const double *xyz, int64_t nt, 
 int fmmbem_set_wavenumber(fmmbem_ctx *ctx, double k) {
     if (!ctx) return FMMBEM_EINVAL;
     if (!std::isfinite(k) || !(k > 0.0)) return fail(ctx, FMMBEM_EINVAL, "wavenumber must be finite and > 0");
-    if (k != ctx->k || !ctx->have_k) ctx->k_dirty = true;
+    if (k != ctx->k || !ctx->have_k) {
+        ctx->k_dirty = true;
+        ++ctx->input_gen;
+    }
     ctx->k = k;
     ctx->have_k = true;
     return FMMBEM_OK;
@@ -1521,6 +1580,7 @@ int fmmbem_set_admittance(fmmbem_ctx *ctx, const fmmbem_c64 *beta) {
     for (int64_t i = 0; i < ctx->nt; ++i) ctx->beta[i] = cmk(beta[i].re, beta[i].im);
     ctx->have_beta = true;
     ctx->beta_dirty = true;
+    ++ctx->input_gen;
     return FMMBEM_OK;
 }
 
@@ -1542,7 +1602,10 @@ int fmmbem_set_formulation(fmmbem_ctx *ctx, int f) {
         return fail(ctx, FMMBEM_EINVAL,
                     "formulation must be FMMBEM_DIRECT (Eq. dbem4), FMMBEM_DIRECT_DPSI (Eq. dbem5), "
                     "FMMBEM_DIRECT_BM or FMMBEM_INDIRECT (Eq. ibem5)");
-    if (f != ctx->formulation) drop_graphs(ctx);
+    if (f != ctx->formulation) {
+        drop_graphs(ctx);
+        ++ctx->input_gen;
+    }
     ctx->formulation = f;
     return FMMBEM_OK;
 }
@@ -1560,6 +1623,7 @@ int fmmbem_set_admittance_plus(fmmbem_ctx *ctx, const fmmbem_c64 *beta_plus) {
         for (int64_t i = 0; i < ctx->nt; ++i) ctx->beta_plus[i] = cmk(beta_plus[i].re, beta_plus[i].im);
     }
     ctx->beta_dirty = true;
+    ++ctx->input_gen;
     return FMMBEM_OK;
 }
 
@@ -1883,6 +1947,8 @@ static int check_solve_opts(fmmbem_ctx *ctx, const fmmbem_solve_opts &o) {
         (o.inner_precision != FMMBEM_FP64 && o.inner_precision != FMMBEM_MIXED))
         return fail(ctx, FMMBEM_EINVAL, "bad inner solve options");
     if (o.basis_fp32 < -1 || o.basis_fp32 > 1) return fail(ctx, FMMBEM_EINVAL, "basis_fp32 must be -1, 0 or 1");
+    if (o.inner_p_min < 0 || (o.inner_p_min > 0 && !(o.inner_p_excess >= 0)))
+        return fail(ctx, FMMBEM_EINVAL, "inner_p_min must be >= 0 and inner_p_excess >= 0");
     if (o.precond < FMMBEM_PC_NONE || o.precond > FMMBEM_PC_LEARNED) return fail(ctx, FMMBEM_EINVAL, "unknown preconditioner");
     return FMMBEM_OK;
 }
@@ -1902,6 +1968,12 @@ int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, f
     bool dirty = ctx->mesh_dirty || ctx->k_dirty || ctx->beta_dirty;
     ensure_setup(ctx);
     if (dirty) t_before = ctx->t_setup_last;
+    fmmbem_ctx *coarse = nullptr;
+    if (o.inner_iters > 0 && o.inner_p_min > 0) {
+        auto ti = std::chrono::steady_clock::now();
+        coarse = ensure_inner(ctx, o.inner_p_min, o.inner_p_excess);
+        t_before += std::chrono::duration<double>(std::chrono::steady_clock::now() - ti).count();
+    }
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = ctx->stream;
     const bool ind = indirect(ctx), bm = burton_miller(ctx), dp = dpsi(ctx);
@@ -1933,23 +2005,34 @@ int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, f
     // the Krylov products run in the requested arithmetic; restart residuals always in FP64
     int64_t n64 = 0, nmx = 0;
     auto product = [&](const double2 *a, double2 *y, bool mixed) {
-        if (ind) matvec_ind(ctx, a, y, false, mixed);
-        else if (bm) matvec_bm(ctx, a, y, false, mixed);
-        else if (dp) matvec_dpsi(ctx, a, y, false, mixed);
-        else matvec_dev(ctx, 1, a, y, false, mixed);
+        apply_operator(ctx, a, y, mixed);
         ++(mixed ? nmx : n64);
     };
     const bool mixed = o.precision == FMMBEM_MIXED;
     auto mv = [&](const double2 *a, double2 *y) { product(a, y, mixed); };
     auto mv64 = [&](const double2 *a, double2 *y) { product(a, y, false); };
-    // Inner-outer scheme (Section 4.4): the outer flexible GMRES is preconditioned by a short,
-    // low-accuracy GMRES on the same operator (inner_precision), itself preconditioned by `pc`.
+    // Inner-outer scheme (Section 4.3): the outer flexible GMRES is preconditioned by a short,
+    // low-accuracy GMRES on the same operator (inner_precision), itself preconditioned by `pc`; with
+    // inner_p_min > 0 that operator is a second FMM with a smaller truncation number.
     std::function<void(const double2 *, double2 *)> outer_pc = pc;
-    int64_t inner_its = 0;
+    int64_t inner_its = 0, ncoarse = 0;
     if (o.inner_iters > 0) {
         const bool imixed = o.inner_precision == FMMBEM_MIXED;
         outer_pc = [&, imixed](const double2 *v, double2 *z) {
-            auto imv = [&](const double2 *a, double2 *y) { product(a, y, imixed); };
+            auto imv = [&](const double2 *a, double2 *y) {
+                if (!coarse) {
+                    product(a, y, imixed);
+                    return;
+                }
+                // the coarser operator runs on its own context's streams: order it after this
+                // solve's stream and this stream after it
+                HIP_OK(hipEventRecord(ctx->xev[0], st));
+                HIP_OK(hipStreamWaitEvent(coarse->stream, ctx->xev[0], 0));
+                apply_operator(coarse, a, y, imixed);
+                HIP_OK(hipEventRecord(ctx->xev[1], coarse->stream));
+                HIP_OK(hipStreamWaitEvent(st, ctx->xev[1], 0));
+                ++ncoarse;
+            };
             int it = 0, rs = 0;
             double rr = 1.0;
             const bool ib32 = o.basis_fp32 < 0 ? imixed : o.basis_fp32 != 0;
@@ -2000,6 +2083,7 @@ int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, f
         rep->status = status;
         rep->matvecs_fp64 = n64;
         rep->matvecs_mixed = nmx;
+        rep->matvecs_coarse = ncoarse;
         rep->inner_iters = inner_its;
         rep->pc_fallback_at = fallback_at;
     }

@@ -229,6 +229,13 @@ struct FgmresHooks {
 // ---------------------------------------------------------------- the context
 struct fmmbem_ctx {
     int device = 0;
+    // coarser FMM for inner GMRES solves (same inputs, smaller truncation), owned; rebuilt when the
+    // inputs change (input_gen counts the setters' calls)
+    fmmbem_ctx *inner = nullptr;
+    uint64_t input_gen = 0, inner_gen = ~0ULL;
+    int inner_pmin = 0;
+    double inner_pexc = 0.0;
+    hipEvent_t xev[2] = {};
     double tree_min_leaf = 0.0;  // smallest leaf side the octree was allowed (kd_leaf_min / k at build)
     fmmbem_options opt{};
     std::string err;

@@ -1,6 +1,6 @@
 // Learned preconditioner: a small MLP applied per chunk of up to 64 consecutive unknowns of one
 // octree leaf, on top of the near-field block inverse.  FGMRES admits it because its
-// preconditioner may change from step to step (Section 4.4 uses flexible GMRES).
+// preconditioner may change from step to step (Section 4.3 uses flexible GMRES).
 //
 //   input  (140): the chunk's residual divided by its norm (64 complex, zero padded), k times
 //                 the leaf side, occupancy, mean and spread of the element normals, mean

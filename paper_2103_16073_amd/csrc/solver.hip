@@ -1,4 +1,4 @@
-// Flexible GMRES (the paper's outer solver, Section 4.4) with FP64 Arnoldi on the device and a
+// Flexible GMRES (the paper's outer solver, Section 4.3) with FP64 Arnoldi on the device and a
 // preconditioner slot: identity, diagonal (the paper's indirect-BEM choice: a constant added to
 // the diagonal), or the exact inverse of the operator restricted to each octree leaf.
 //

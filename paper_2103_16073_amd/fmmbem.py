@@ -42,14 +42,15 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("maxit", ctypes.c_int),
                 ("precond", ctypes.c_int), ("precision", ctypes.c_int), ("diag_shift", ctypes.c_double),
                 ("use_x0", ctypes.c_int), ("inner_iters", ctypes.c_int), ("inner_tol", ctypes.c_double),
-                ("inner_precision", ctypes.c_int), ("basis_fp32", ctypes.c_int)]
+                ("inner_precision", ctypes.c_int), ("basis_fp32", ctypes.c_int), ("inner_p_min", ctypes.c_int),
+                ("inner_p_excess", ctypes.c_double)]
 
 
 class SolveReport(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("restarts", ctypes.c_int), ("rel_res", ctypes.c_double),
                 ("t_setup_s", ctypes.c_double), ("t_solve_s", ctypes.c_double), ("status", ctypes.c_int),
                 ("matvecs_fp64", ctypes.c_int64), ("matvecs_mixed", ctypes.c_int64), ("inner_iters", ctypes.c_int64),
-                ("pc_fallback_at", ctypes.c_int32)]
+                ("pc_fallback_at", ctypes.c_int32), ("matvecs_coarse", ctypes.c_int64)]
 
 
 class BatchShape(ctypes.Structure):

@@ -124,6 +124,42 @@ def test_matvec_exact_far_vs_dense(F, cfg1_dense):
     ctx.close()
 
 
+def test_solve_inner_coarse_fmm_vs_oracle_lu(F, cfg1_dense):
+    """The inner GMRES on a second FMM with a smaller truncation number (Section 4.3): the outer
+    solve still reaches its FP64 target and agrees with LU; every inner product runs on the
+    coarser operator; a new admittance reaches that operator before the next solve."""
+    room, k = cfg1_dense
+    ctx = make_ctx(F, room, k)
+    rs, _ = synth.source_and_receivers(room, 4)
+    ctx.fmmbem_set_sources(rs)
+    rc = ctx.fmmbem_get_info().rc
+    for beta in (room.beta, 0.5 * room.beta + 0.05):
+        ctx.fmmbem_set_admittance(beta)
+        x, rep, rc_ = ctx.fmmbem_solve(0, tol=1e-8, restart=20, maxit=60, inner_iters=8, inner_tol=1e-2,
+                                       precision=F.FMMBEM_FP64, inner_p_min=6, inner_p_excess=0.5)
+        print(f"coarse inner: outer {rep.iters} inner {rep.inner_iters} coarse {rep.matvecs_coarse} "
+              f"fp64 {rep.matvecs_fp64} rel {rep.rel_res:.2e}")
+        assert rc_ == 0 and rep.rel_res < 1e-8
+        # an inner solve that ends on its iteration cap spends one more product on its true residual
+        assert rep.inner_iters <= rep.matvecs_coarse <= rep.inner_iters + rep.iters
+        assert rep.inner_iters > 0 and rep.matvecs_mixed == 0
+        A, b, _, _ = bem.direct_system(room.vertices, room.triangles, k, beta, rs[0], rc)
+        x_ref = bem.solve_lu(A, b)
+        assert np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref) < 1e-5
+    ctx.close()
+
+
+def test_solve_inner_coarse_fmm_rejects_bad_opts(F, cfg1_dense):
+    room, k = cfg1_dense
+    ctx = make_ctx(F, room, k)
+    rs, _ = synth.source_and_receivers(room, 4)
+    ctx.fmmbem_set_sources(rs)
+    with pytest.raises(F.FmmbemError) as e:
+        ctx.fmmbem_solve(0, tol=1e-4, inner_iters=4, inner_p_min=-1)
+    assert e.value.code == F.FMMBEM_EINVAL
+    ctx.close()
+
+
 @pytest.mark.parametrize("leaf_max,lds_budget,lane,mfma,fused", [
     (64, 0, 0, 0, 0), (12, 0, 0, 0, 0), (12, 8192, 0, 0, 0), (64, 8192, 0, 0, 0), (64, 0, 2, 0, 0),
     (12, 0, 2, 0, 0), (64, 0, 2, 2, 0), (12, 0, 2, 2, 0), (64, 0, 2, 0, 1), (12, 0, 2, 0, 1)])
@@ -246,7 +282,7 @@ def test_solve_fp32_basis_vs_fp64_basis(F, cfg1_dense, batched):
 
 
 def test_solve_inner_outer_vs_oracle_lu(F, cfg1_dense):
-    """Flexible GMRES preconditioned by an inner mixed-precision GMRES (Section 4.4): converges
+    """Flexible GMRES preconditioned by an inner mixed-precision GMRES (Section 4.3): converges
     to the FP64 residual target, agrees with LU, and counts its products by arithmetic."""
     room, k = cfg1_dense
     ctx = make_ctx(F, room, k)
