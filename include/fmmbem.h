@@ -126,8 +126,9 @@ typedef struct {
                             every lane batch; 0 never; default 1 */
     int fused;           /* lane batches with p_src = p_tgt = p <= 16 may run all three stages in
                             one kernel, the 32-job vectors resident in LDS and transformed on
-                            matrix cores: 1 under the fixed rule and as an autotuner candidate,
-                            0 never; default 1 */
+                            matrix cores: 1 under the fixed rule and as an autotuner candidate
+                            (timed in FP64), and in mixed-precision products for every such lane
+                            batch (faster in FP32 wherever measured); 0 never; default 1 */
     double kd_leaf_min;  /* lower bound on k times the leaf side: the octree stops refining before
                             its leaves get smaller than kd_leaf_min / k, because at small k tau the
                             singular coaxial tables lose their small entries to round-off (the

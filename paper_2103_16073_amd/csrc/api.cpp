@@ -404,6 +404,17 @@ static void make_batch(fmmbem_ctx *c, const std::string &name, std::vector<JobH>
     build_rot_tables(betas, b.P, (double *)c->buf.find("delta"), b.H, b.HT, c->scratch, st);
 }
 
+// the batch's tables in the fused tiles' fragment order (coax: its ncoax coaxial tables)
+static void fused_tables(fmmbem_ctx *c, const std::string &name, TransBatch &b, const double2 *coax, int ncoax) {
+    if (b.njob == 0 || !fused_ok(b)) return;
+    const size_t nr = (size_t)std::max(1, b.nbeta) * TF_FR_ROT, nc = (size_t)std::max(1, ncoax) * TF_FR_COAX;
+    b.frH = dget<double>(c->buf, name + "_frH", nr);
+    b.frHT = dget<double>(c->buf, name + "_frHT", nr);
+    b.frC = dget<double>(c->buf, name + "_frC", nc);
+    b.nfrc = std::max(1, ncoax);
+    build_fused_tables(b.P, b.PT, b.nbeta, b.H, b.HT, ncoax, coax, b.frH, b.frHT, b.frC, c->stream);
+}
+
 static void build_batches(fmmbem_ctx *c) {
     TreeHost &T = c->tree;
     const int L = T.depth;
@@ -416,6 +427,7 @@ static void build_batches(fmmbem_ctx *c) {
             for (int q = H.m2l_start[b]; q < H.m2l_start[b + 1]; ++q)
                 jobs.push_back({H.m2l_src[q], (int32_t)b, H.m2l_dir[q], H.m2l_tau_of_dir[H.m2l_dir[q]], 0});
         make_batch(c, s + "m2l", jobs, D.p, D.p, D.p, D.nbox, D.m2l);
+        fused_tables(c, s + "m2l", D.m2l, D.coax_m2l, D.ntau);
         if (l < L) {
             LevelHost &Hc = T.lv[l + 1];
             LevelDev &C = c->lev[l + 1];
@@ -427,6 +439,8 @@ static void build_batches(fmmbem_ctx *c) {
             }
             make_batch(c, s + "up", up, C.p, D.p, PT, D.nbox, D.up);
             make_batch(c, s + "down", dn, D.p, C.p, PT, C.nbox, D.down);
+            fused_tables(c, s + "up", D.up, D.coax_up, 1);
+            fused_tables(c, s + "down", D.down, D.coax_up, 1);
         }
     }
     HIP_OK(hipStreamSynchronize(c->stream));
@@ -636,11 +650,20 @@ static double coax_flops(int ps, int pt) {
 
 // ------------------------------------------------------------------ the FMM pass
 // Staged translation of a batch of jobs (grouped by target) from `src` (psrc) into `dst` (ptgt).
+// In FP32 the fused tiles beat the three lane passes at every batch that may use them (they are
+// issue-bound there, not bound by the LDS-limited occupancy of FP64), so mixed products run such
+// batches fused whatever the FP64 shape chosen for them, unless `fused` is off.
 template <class R>
-static void run_batch(fmmbem_ctx *c, int nrv, const TransBatch &b, const typename Cx<R>::T *src,
+static void run_batch(fmmbem_ctx *c, int nrv, const TransBatch &b0, const typename Cx<R>::T *src,
                       typename Cx<R>::T *dst, const TransTables<R> &tb, const typename Cx<R>::T *ph) {
     using C = typename Cx<R>::T;
-    if (b.njob == 0) return;
+    if (b0.njob == 0) return;
+    TransBatch b32;
+    if (sizeof(R) == 4 && c->opt.fused && b0.lane && b0.mfma == 0 && fused_ok(b0) && tb.frH) {
+        b32 = b0;
+        b32.mfma = 2;
+    }
+    const TransBatch &b = b32.njob ? b32 : b0;
     hipStream_t st = c->cur;
     // work rows per stream, so that batches on the two streams never share them
     const bool side = st == c->side;
@@ -665,8 +688,12 @@ static void run_batch(fmmbem_ctx *c, int nrv, const TransBatch &b, const typenam
     }
 }
 
-static TransTables<double> tables64(const TransBatch &b, const double2 *coax) { return {coax, b.H, b.HT}; }
-static TransTables<float> tables32(const TransBatch &b, const float2 *coax) { return {coax, b.H32, b.HT32}; }
+static TransTables<double> tables64(const TransBatch &b, const double2 *coax) {
+    return {coax, b.H, b.HT, b.frH, b.frHT, b.frC};
+}
+static TransTables<float> tables32(const TransBatch &b, const float2 *coax) {
+    return {coax, b.H32, b.HT32, b.frH32, b.frHT32, b.frC32};
+}
 
 // every batch of the product with its source/target expansions and coaxial tables
 struct BatchRef {
@@ -740,7 +767,7 @@ static void autotune_batches(fmmbem_ctx *c) {
             b.JT = sh.jt;
             b.mfma = sh.mfma;
             layout_batch(c, r.name, jobs, b);
-            const TransTables<double> tb{r.coax, b.H, b.HT};
+            const TransTables<double> tb = tables64(b, r.coax);
             run_batch<double>(c, 1, b, r.src, r.dst, tb, ph);  // warm-up (allocates the work rows)
             // best of three repetitions: shapes within a few per cent of each other would
             // otherwise trade places from run to run
@@ -822,6 +849,15 @@ static void ensure_mixed(fmmbem_ctx *c) {
             b.HT32 = dget<float>(c->buf, s + nm3[q] + "_HT32", nh + TABLE_PAD);
             convert(c, nh + TABLE_PAD, (const double *)b.H, b.H32);
             convert(c, nh + TABLE_PAD, (const double *)b.HT, b.HT32);
+            if (b.frH) {
+                const int64_t nr = (int64_t)std::max(1, b.nbeta) * TF_FR_ROT, nc = (int64_t)b.nfrc * TF_FR_COAX;
+                b.frH32 = dget<float>(c->buf, s + nm3[q] + "_frH32", nr);
+                b.frHT32 = dget<float>(c->buf, s + nm3[q] + "_frHT32", nr);
+                b.frC32 = dget<float>(c->buf, s + nm3[q] + "_frC32", nc);
+                convert(c, nr, (const double *)b.frH, b.frH32);
+                convert(c, nr, (const double *)b.frHT, b.frHT32);
+                convert(c, nc, (const double *)b.frC, b.frC32);
+            }
         }
     }
     const int64_t nph = (int64_t)NDIR * (2 * c->delta_p + 1);

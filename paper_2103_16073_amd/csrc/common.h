@@ -120,4 +120,6 @@ template <> struct Cx<float> { using T = float2; };
 template <class R> struct TransTables {
     const typename Cx<R>::T *coax;
     const R *H, *HT;
+    // the same tables in the fused tiles' fragment order (batches with p_src = p_tgt <= 16)
+    const R *frH = nullptr, *frHT = nullptr, *frC = nullptr;
 };

@@ -140,6 +140,11 @@ struct TransBatch {
     // rotation stores each run's sum in the first job's row and the CSR lists first jobs only.
     int8_t *seg = nullptr;
     int64_t nout = 0;  // rows the back rotation stores (runs of lane batches, else jobs)
+    // fused tiles: the rotation tables and the batch's coaxial tables in the order in which the
+    // lanes hold matrix-core fragments, zero past every block (built when p_src = p_tgt <= 16)
+    double *frH = nullptr, *frHT = nullptr, *frC = nullptr;
+    float *frH32 = nullptr, *frHT32 = nullptr, *frC32 = nullptr;
+    int nfrc = 0;  // coaxial classes in frC
 };
 // runs of the back-rotation output never cross a multiple of this many (real) jobs, so that a
 // run lies in one 32-lane half tile (the fused kernel's block) for 1, 2 or 4 right-hand sides
@@ -154,6 +159,12 @@ struct JobH {
 
 int trans_pick_jt(int P, size_t lds_budget, int whole);
 int trans_fused_pmax();
+// fragment-order tables of the fused tiles, per class: rotation 8 degree pairs x 2 degrees x
+// 8 K chunks x 2 row blocks x 64 lanes; coaxial 16 orders x 4 K chunks x (re, im) x 64 lanes
+constexpr int TF_FR_STEP = 2 * 8 * 2 * 64, TF_FR_ROT = 8 * TF_FR_STEP;
+constexpr int TF_FR_ORDER = 4 * 2 * 64, TF_FR_COAX = 16 * TF_FR_ORDER;
+void build_fused_tables(int P, int PT, int nbeta, const double *H, const double *HT, int ncoax, const double2 *coax,
+                        double *frH, double *frHT, double *frC, hipStream_t st);
 size_t trans_lds_bytes(int JT, int P, int whole);
 void trans_configure_lds(size_t lds_max);
 template <class R>

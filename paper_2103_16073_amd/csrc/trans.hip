@@ -42,6 +42,7 @@ struct TransArgsT {
     const C *ph;                // e^{i m a} per direction, 2*PH+1 per direction
     C *W1, *W2;                 // work rows, P^2 per job
     const int8_t *jseg;         // lane batches: run length at the first job of a run, else 0
+    const R *frH, *frHT, *frC;  // fused tiles: fragment-order tables (TF_FR_ROT, TF_FR_COAX per class)
 };
 
 constexpr int RJ = 4, RR = 4;
@@ -1106,37 +1107,59 @@ constexpr int TF_GU = 8;  // source loads in flight per thread
 //
 // A fragments of one step for one lane: TfRot v[d][i][b] = A[16 b + (lane & 15)][4 i + (lane >> 4)]
 // of the rotation block of degree 2k + d (b: row block); TfCoax v[i][b] the same entry of the
-// coaxial block of |m| (b = 0 real part, b = 1 imaginary part; the step applies the sign
-// (-1)^{k+r}).  Entries past a block are clamped copies that the step masks to zero, so the loads
-// are unconditional and nothing waits for them before the step that needs them.
+// coaxial block of |m| times (-1)^{k+r} (b = 0 real part, b = 1 imaginary part).  They come from
+// tables stored in exactly this order (k_fr_rot, k_fr_coax: one contiguous value per lane, zero
+// past each block), so a step's loads need no index arithmetic and its operands no masks; only
+// the slots a step uses are loaded, one step before it.
 template <class R> struct TfRot { R v[2][8][2]; };
 template <class R> struct TfCoax { R v[4][2]; };
 
-// M: the table's rotation blocks (HT for the forward rotation, H for the back rotation)
+template <class R, int KS, int RB>
+__device__ __forceinline__ void tf_load_rot_k(TfRot<R> &f, const R *M) {
+#pragma unroll
+    for (int d = 0; d < 2; ++d)
+#pragma unroll
+        for (int i = 0; i < KS; ++i)
+#pragma unroll
+            for (int b = 0; b < RB; ++b) f.v[d][i][b] = M[((d * 8 + i) * 2 + b) * 64];
+}
+
+// M: the class's fragment-order rotation table (of HT for the forward rotation, of H for the
+// back rotation) offset by the lane; step k uses K chunks 0..k and row blocks 0..(k >= 4)
 template <class R>
-__device__ __forceinline__ void tf_load_rot(TfRot<R> &f, const R *M, int k, int P, int lane) {
-    const int kq = lane >> 4, rl = lane & 15;
-#pragma unroll
-    for (int d = 0; d < 2; ++d) {
-        const int n = min(2 * k + d, P - 1), w = 2 * n + 1;
-        const R *Mn = M + rot_block_off(n);  // A[r][k] = Mn[k w + r]
-#pragma unroll
-        for (int i = 0; i < 8; ++i)
-#pragma unroll
-            for (int b = 0; b < 2; ++b) f.v[d][i][b] = Mn[min(4 * i + kq, w - 1) * w + min(16 * b + rl, w - 1)];
+__device__ __forceinline__ void tf_load_rot(TfRot<R> &f, const R *M, int k) {
+    M += (int64_t)k * TF_FR_STEP;
+    switch (k) {
+    case 0: tf_load_rot_k<R, 1, 1>(f, M); break;
+    case 1: tf_load_rot_k<R, 2, 1>(f, M); break;
+    case 2: tf_load_rot_k<R, 3, 1>(f, M); break;
+    case 3: tf_load_rot_k<R, 4, 1>(f, M); break;
+    case 4: tf_load_rot_k<R, 5, 2>(f, M); break;
+    case 5: tf_load_rot_k<R, 6, 2>(f, M); break;
+    case 6: tf_load_rot_k<R, 7, 2>(f, M); break;
+    default: tf_load_rot_k<R, 8, 2>(f, M); break;
     }
 }
 
-template <class R>
-__device__ __forceinline__ void tf_load_coax(TfCoax<R> &f, const typename Cx<R>::T *T, int am, int P, int PT, int lane) {
-    using C = typename Cx<R>::T;
-    const int kq = lane >> 4, rl = lane & 15, rows = P - am, B = PT - am;
-    const C *Tm = T + coax_block_off(PT, am);
+template <class R, int KS>
+__device__ __forceinline__ void tf_load_coax_k(TfCoax<R> &f, const R *T) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const C t = Tm[min(4 * i + kq, rows - 1) * B + min(rl, rows - 1)];
-        f.v[i][0] = t.x;
-        f.v[i][1] = t.y;
+    for (int i = 0; i < KS; ++i) {
+        f.v[i][0] = T[(2 * i) * 64];
+        f.v[i][1] = T[(2 * i + 1) * 64];
+    }
+}
+
+// T: the class's fragment-order coaxial table offset by the lane; order |m| = am uses
+// ceil((P - am) / 4) K chunks
+template <class R>
+__device__ __forceinline__ void tf_load_coax(TfCoax<R> &f, const R *T, int am, int P) {
+    T += (int64_t)am * TF_FR_ORDER;
+    switch ((P - am + 3) / 4) {
+    case 1: tf_load_coax_k<R, 1>(f, T); break;
+    case 2: tf_load_coax_k<R, 2>(f, T); break;
+    case 3: tf_load_coax_k<R, 3>(f, T); break;
+    default: tf_load_coax_k<R, 4>(f, T); break;
     }
 }
 
@@ -1147,7 +1170,6 @@ __device__ __forceinline__ void tf_rot_pair(R *X, const TfRot<R> &f, int n0, int
     using Op = TmOp<R>;
     using v4 = typename Op::v4;
     constexpr int ND = TWO ? 2 : 1;
-    const int rl = colw & 15;
     R b[ND][KS];
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
@@ -1165,11 +1187,7 @@ __device__ __forceinline__ void tf_rot_pair(R *X, const TfRot<R> &f, int n0, int
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-            for (int d = 0; d < ND; ++d) {
-                const int w = 2 * (n0 + d) + 1;
-                const R av = (4 * i + kq < w && 16 * rb + rl < w) ? f.v[d][i][rb] : R(0);
-                acc[d][rb] = Op::mma(av, b[d][i], acc[d][rb]);
-            }
+            for (int d = 0; d < ND; ++d) acc[d][rb] = Op::mma(f.v[d][i][rb], b[d][i], acc[d][rb]);
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
         const int n = n0 + d, w = 2 * n + 1;
@@ -1191,7 +1209,7 @@ __device__ __forceinline__ void tf_coax_pair(R *X, const TfCoax<R> &f, int am, i
     using Op = TmOp<R>;
     using v4 = typename Op::v4;
     constexpr int ND = TWO ? 2 : 1;
-    const int rows = P - am, rl = colw & 15;
+    const int rows = P - am;
     R b[ND][KS], bw[ND][KS];
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
@@ -1207,16 +1225,12 @@ __device__ __forceinline__ void tf_coax_pair(R *X, const TfCoax<R> &f, int am, i
 #pragma unroll
     for (int d = 0; d < ND; ++d) acc[d] = v4{0, 0, 0, 0};
 #pragma unroll
-    for (int i = 0; i < KS; ++i) {
-        const int k = 4 * i + kq;
-        const R sg = (k < rows && rl < rows) ? (((k + rl) & 1) ? R(-1) : R(1)) : R(0);
-        const R ar = sg * f.v[i][0], ai = sg * f.v[i][1];
+    for (int i = 0; i < KS; ++i)
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
-            acc[d] = Op::mma(ar, b[d][i], acc[d]);
-            acc[d] = Op::mma(ai, bw[d][i], acc[d]);
+            acc[d] = Op::mma(f.v[i][0], b[d][i], acc[d]);
+            acc[d] = Op::mma(f.v[i][1], bw[d][i], acc[d]);
         }
-    }
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
         const int m = d ? -am : am;
@@ -1265,14 +1279,14 @@ __device__ __forceinline__ void tf_coax_step(R *X, const TfCoax<R> &f, int am, i
 // one rotation stage (all degree pairs) with the tables M; two fragment sets, each loaded one step
 // before the step that uses it
 template <class R, int LD>
-__device__ __forceinline__ void tf_rot_stage(R *X, const R *M, int P, int colw, int kq, int lane) {
+__device__ __forceinline__ void tf_rot_stage(R *X, const R *M, int P, int colw, int kq) {
     const int QR = (P + 1) / 2;
     TfRot<R> fa, fb;
-    tf_load_rot(fa, M, 0, P, lane);
+    tf_load_rot(fa, M, 0);
     for (int k = 0; k < QR; k += 2) {
-        tf_load_rot(fb, M, min(k + 1, QR - 1), P, lane);
+        if (k + 1 < QR) tf_load_rot(fb, M, k + 1);
         tf_rot_step<R, LD>(X, fa, k, P, colw, kq);
-        if (k + 2 < QR) tf_load_rot(fa, M, k + 2, P, lane);
+        if (k + 2 < QR) tf_load_rot(fa, M, k + 2);
         if (k + 1 < QR) tf_rot_step<R, LD>(X, fb, k + 1, P, colw, kq);
     }
 }
@@ -1332,22 +1346,22 @@ __global__ void __launch_bounds__(8 * J) k_tf_trans(TransArgsT<R> a) {
     __syncthreads();
     {
         const int tr = a.tile_rot[tile / a.nr], tc = a.tile_coax[tile / a.nr];
-        const R *HT = a.HT + (int64_t)tr * rot_table_size(P), *H = a.H + (int64_t)tr * rot_table_size(P);
-        const C *T = a.coax + (int64_t)tc * coax_table_size(a.PT);
+        const R *HT = a.frHT + (int64_t)tr * TF_FR_ROT + lane, *H = a.frH + (int64_t)tr * TF_FR_ROT + lane;
+        const R *T = a.frC + (int64_t)tc * TF_FR_COAX + lane;
         const int colw = 16 * wv + (lane & 15), kq = lane >> 4;
         const R swp = (colw & 1) ? R(1) : R(-1);
-        tf_rot_stage<R, LD>(X, HT, P, colw, kq, lane);
+        tf_rot_stage<R, LD>(X, HT, P, colw, kq);
         {
             TfCoax<R> ca, cb;
-            tf_load_coax(ca, T, 0, P, a.PT, lane);
+            tf_load_coax(ca, T, 0, P);
             for (int am = 0; am < P; am += 2) {
-                tf_load_coax(cb, T, min(am + 1, P - 1), P, a.PT, lane);
+                if (am + 1 < P) tf_load_coax(cb, T, am + 1, P);
                 tf_coax_step<R, LD>(X, ca, am, P, colw, kq, swp);
-                if (am + 2 < P) tf_load_coax(ca, T, am + 2, P, a.PT, lane);
+                if (am + 2 < P) tf_load_coax(ca, T, am + 2, P);
                 if (am + 1 < P) tf_coax_step<R, LD>(X, cb, am + 1, P, colw, kq, swp);
             }
         }
-        tf_rot_stage<R, LD>(X, H, P, colw, kq, lane);
+        tf_rot_stage<R, LD>(X, H, P, colw, kq);
     }
     __syncthreads();
     // back-rotated rows, phased (e^{-i m a}) and summed over the runs of one target, job-major
@@ -1362,6 +1376,43 @@ __global__ void __launch_bounds__(8 * J) k_tf_trans(TransArgsT<R> a) {
         }
         a.W1[(J0 + j) * (int64_t)P2 + c] = v;
     }
+}
+
+static_assert(TF_FR_STEP == 2 * 8 * 2 * 64 && TF_FR_ROT == (TF_PMAX / 2) * TF_FR_STEP, "rotation fragment layout");
+static_assert(TF_FR_ORDER == 4 * 2 * 64 && TF_FR_COAX == TF_PMAX * TF_FR_ORDER, "coaxial fragment layout");
+
+// Fragment-order rotation tables: element (class, k, d, i, b, lane) = A[16 b + lane % 16][4 i + lane / 16]
+// of degree n = 2k + d of the class's table M (A[r][q] = M[rot_block_off(n) + q (2n + 1) + r]),
+// zero past the block or for n >= P.
+__global__ void __launch_bounds__(256) k_fr_rot(int64_t ntot, int P, const double *M, double *out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ntot) return;
+    const int64_t cl = e / TF_FR_ROT;
+    const int rem = (int)(e - cl * TF_FR_ROT);
+    const int lane = rem & 63, b = (rem >> 6) & 1, i = (rem >> 7) & 7, d = (rem >> 10) & 1, k = rem >> 11;
+    const int n = 2 * k + d, r = 16 * b + (lane & 15), q = 4 * i + (lane >> 4);
+    double v = 0.0;
+    if (n < P && r < 2 * n + 1 && q < 2 * n + 1)
+        v = M[cl * rot_table_size(P) + rot_block_off(n) + (int64_t)q * (2 * n + 1) + r];
+    out[e] = v;
+}
+
+// Fragment-order coaxial tables: element (class, am, i, part, lane) = (-1)^{q+r} (re or im of)
+// T[q][r] of order |m| = am, q = 4 i + lane / 16 (source degree - am), r = lane % 16 (target
+// degree - am), zero past the block (P - am rows and columns).
+__global__ void __launch_bounds__(256) k_fr_coax(int64_t ntot, int P, int PT, const double2 *T, double *out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ntot) return;
+    const int64_t cl = e / TF_FR_COAX;
+    const int rem = (int)(e - cl * TF_FR_COAX);
+    const int lane = rem & 63, part = (rem >> 6) & 1, i = (rem >> 7) & 3, am = rem >> 9;
+    const int rows = P - am, q = 4 * i + (lane >> 4), r = lane & 15;
+    double v = 0.0;
+    if (am < P && q < rows && r < rows) {
+        const double2 t = T[cl * coax_table_size(PT) + coax_block_off(PT, am) + (int64_t)q * (PT - am) + r];
+        v = ((q + r) & 1 ? -1.0 : 1.0) * (part ? t.y : t.x);
+    }
+    out[e] = v;
 }
 
 // dst[t] += sum of the job rows of target t (W1, P^2 per job); jobs of t listed in CSR order.
@@ -1398,6 +1449,20 @@ __global__ void __launch_bounds__(256) k_tr_reduce(int64_t ntgt, int nr, int ptg
 // ------------------------------------------------------------------ host side
 int trans_fused_pmax() { return TF_PMAX; }
 
+// H, HT: nbeta rotation tables of degree < P; coax: ncoax coaxial tables of size PT; outputs hold
+// max(1, nbeta) TF_FR_ROT and max(1, ncoax) TF_FR_COAX values
+void build_fused_tables(int P, int PT, int nbeta, const double *H, const double *HT, int ncoax, const double2 *coax,
+                        double *frH, double *frHT, double *frC, hipStream_t st) {
+    if (P > TF_PMAX || PT < P) throw FmmError(-1, "fragment-order tables need p <= 16 and PT >= p");
+    const int64_t nr = (int64_t)std::max(1, nbeta) * TF_FR_ROT, nc = (int64_t)std::max(1, ncoax) * TF_FR_COAX;
+    k_fr_rot<<<(unsigned)((nr + 255) / 256), 256, 0, st>>>(nr, P, H, frH);
+    LAUNCH_OK();
+    k_fr_rot<<<(unsigned)((nr + 255) / 256), 256, 0, st>>>(nr, P, HT, frHT);
+    LAUNCH_OK();
+    k_fr_coax<<<(unsigned)((nc + 255) / 256), 256, 0, st>>>(nc, P, PT, coax, frC);
+    LAUNCH_OK();
+}
+
 int trans_pick_jt(int P, size_t lds_budget, int whole) {
     const size_t per = whole ? sizeof(double2) * (size_t)P * P : sizeof(double2) * (size_t)std::max(2 * P - 1, P);
     int jt = (int)std::min<size_t>(64, lds_budget / per);
@@ -1427,7 +1492,7 @@ const char *trans_stage(const TransBatch &b, const TransTables<R> &tb, int stage
                         typename Cx<R>::T *W2, hipStream_t st) {
     if (nr < 1 || b.JT % nr) throw FmmError(-1, "right-hand-side count must divide the tile size");
     TransArgsT<R> a{b.njob * nr, b.JT, b.psrc, b.ptgt, b.P, b.PT, PH, nr, src, dst, b.src, b.tgt, b.dir,
-                    b.tile_coax, b.tile_rot, tb.coax, tb.H, tb.HT, ph, W1, W2, b.seg};
+                    b.tile_coax, b.tile_rot, tb.coax, tb.H, tb.HT, ph, W1, W2, b.seg, tb.frH, tb.frHT, tb.frC};
     // classes are padded to whole tiles of JT real jobs, so a tile of JT virtual jobs never
     // mixes tables: virtual tile t uses the tables of real tile t / nr
     const unsigned ntile = (unsigned)((b.njob * nr + b.JT - 1) / b.JT);
@@ -1440,6 +1505,7 @@ const char *trans_stage(const TransBatch &b, const TransTables<R> &tb, int stage
         // a run of one target (at most SEG_ALIGN real jobs, aligned) lies in one workgroup's jobs
         if (b.JT != LANE_JT || b.psrc != b.ptgt || b.PT != b.P || b.P > TF_PMAX || 32 / nr < SEG_ALIGN)
             throw FmmError(-1, "fused translation tiles need 64-job tiles, p_src = p_tgt <= 16, <= 4 vectors");
+        if (!tb.frH || !tb.frHT || !tb.frC) throw FmmError(-1, "fused translation tiles need their fragment-order tables");
         if (stage != 0) return nullptr;
         if (16 / nr >= SEG_ALIGN)
             k_tf_trans<R, 16><<<dim3(ntile, LANE_JT / 16), 128, 0, st>>>(a);
