@@ -292,19 +292,19 @@ def main():
                         "krylov_storage": "fp32" if prec == F.FMMBEM_MIXED else "fp64"}
             log(f"FGMRES {name}: status {rc} iters {rep.iters} rel_res {rep.rel_res:.3e} t {rep.t_solve_s:.2f}s")
         if not args.no_coarse_inner:
-            # the paper's inner-outer scheme: FGMRES (mixed products, Krylov dimension 150) whose
-            # preconditioner is 8 GMRES steps (tolerance 0.1) on a second FMM with p_min 8 and
-            # excess 1.0, itself preconditioned by the leaf blocks
+            # the paper's inner-outer scheme: FGMRES (mixed products, Krylov dimension 200) whose
+            # preconditioner is 10 GMRES steps (tolerance 0.1) on a second FMM with p_min 4 and
+            # excess 0 (p = ceil(k d) per level), itself preconditioned by the leaf blocks
             ctx.fmmbem_release_workspace()
-            xs, rep, rc = ctx.fmmbem_solve(0, tol=1e-4, restart=150, maxit=150, precond=F.FMMBEM_PC_NEARBLOCK,
-                                           precision=F.FMMBEM_MIXED, inner_iters=8, inner_tol=0.1,
-                                           inner_p_min=8, inner_p_excess=1.0)
+            xs, rep, rc = ctx.fmmbem_solve(0, tol=1e-4, restart=200, maxit=200, precond=F.FMMBEM_PC_NEARBLOCK,
+                                           precision=F.FMMBEM_MIXED, inner_iters=10, inner_tol=0.1,
+                                           inner_p_min=4, inner_p_excess=0.0)
             fg["mixed_coarse_inner"] = {"status": rc, "iters": rep.iters, "inner_iters": rep.inner_iters,
                                         "rel_res_fp64": rep.rel_res, "t_solve_s": rep.t_solve_s,
                                         "t_setup_coarse_s": rep.t_setup_s, "matvecs_fp64": rep.matvecs_fp64,
                                         "matvecs_mixed": rep.matvecs_mixed, "matvecs_coarse": rep.matvecs_coarse,
-                                        "inner": {"iters": 8, "tol": 0.1, "p_min": 8, "p_excess": 1.0},
-                                        "restart": 150}
+                                        "inner": {"iters": 10, "tol": 0.1, "p_min": 4, "p_excess": 0.0},
+                                        "restart": 200}
             log(f"FGMRES mixed + coarse inner GMRES: status {rc} outer {rep.iters} inner {rep.inner_iters} "
                 f"rel_res {rep.rel_res:.3e} t {rep.t_solve_s:.2f}s (coarse setup {rep.t_setup_s:.2f}s)")
             ctx.fmmbem_release_workspace()
