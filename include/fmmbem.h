@@ -321,7 +321,8 @@ int fmmbem_mlp_loss_grad(fmmbem_ctx *ctx, int64_t m, const float *X, const float
 
 /* Free the per-call work arrays (Krylov bases, translation work rows, staging) now rather
  * than at fmmbem_destroy; they are allocated again when next needed.  Captured product graphs
- * are dropped with them. */
+ * are dropped with them, and so is the workspace of the coarser context that inner solves with
+ * inner_p_min > 0 keep (its tables stay). */
 int fmmbem_release_workspace(fmmbem_ctx *ctx);
 
 /* Arnoldi estimate of the relative residual after each outer iteration of the last solve:

@@ -1489,6 +1489,10 @@ int fmmbem_release_workspace(fmmbem_ctx *ctx) {
     HIP_OK(hipStreamSynchronize(ctx->stream));
     drop_graphs(ctx);
     ctx->scratch.release_all();
+    if (ctx->inner) {
+        if (int rc = fmmbem_release_workspace(ctx->inner)) return fail(ctx, rc, "inner context: " + ctx->inner->err);
+        HIP_OK(hipSetDevice(ctx->device));
+    }
     return FMMBEM_OK;
     GUARD_END
 }

@@ -149,6 +149,28 @@ def test_solve_inner_coarse_fmm_vs_oracle_lu(F, cfg1_dense):
     ctx.close()
 
 
+@pytest.mark.parametrize("form", ["dpsi", "bm", "indirect"])
+def test_solve_inner_coarse_fmm_other_formulations(F, cfg1_dense, form):
+    """The coarser inner operator follows the formulation (Eq. dbem5, the combined form, the
+    indirect Eq. ibem5): with it, FGMRES (diagonal preconditioner) reaches the solution of the
+    plain solve (both to 1e-8) in fewer outer iterations."""
+    room, k = cfg1_dense
+    ctx = make_ctx(F, room, k)
+    rs, _ = synth.source_and_receivers(room, 4)
+    ctx.fmmbem_set_sources(rs)
+    f = {"dpsi": F.FMMBEM_DIRECT_DPSI, "bm": F.FMMBEM_DIRECT_BM, "indirect": F.FMMBEM_INDIRECT}[form]
+    ctx.fmmbem_set_formulation(f)
+    kw = dict(tol=1e-8, restart=300, maxit=900, precond=F.FMMBEM_PC_DIAG, precision=F.FMMBEM_FP64)
+    x0, rep0, rc0 = ctx.fmmbem_solve(0, **kw)
+    x1, rep1, rc1 = ctx.fmmbem_solve(0, inner_iters=6, inner_tol=1e-2, inner_p_min=4, inner_p_excess=0.0, **kw)
+    print(f"{form}: plain {rep0.iters} its; coarse inner: outer {rep1.iters} inner {rep1.inner_iters} "
+          f"coarse products {rep1.matvecs_coarse} rel {rep1.rel_res:.2e}")
+    assert rc0 == 0 and rc1 == 0 and rep1.matvecs_coarse >= rep1.inner_iters > 0
+    assert rep1.iters < rep0.iters
+    assert np.linalg.norm(x1 - x0) / np.linalg.norm(x0) < 1e-5
+    ctx.close()
+
+
 def test_solve_inner_coarse_fmm_rejects_bad_opts(F, cfg1_dense):
     room, k = cfg1_dense
     ctx = make_ctx(F, room, k)
@@ -430,6 +452,29 @@ def test_fused_tiles_match_lane_tiles(F, prec):
             assert err < tol
     ctx0.close()
     ctx1.close()
+
+
+def test_mixed_products_run_lane_batches_fused(F):
+    """With `fused` on, mixed products run every lane batch that may use the fused tiles fused, even
+    where its shape is the three-pass lane kernels (as the FP64 autotuner may choose): lane shapes
+    replayed onto those batches give the fused context's mixed product bitwise, agree with the
+    all-lane mixed product to FP32 rounding (1e-5), and leave the FP64 product on the lane kernels
+    (bitwise the all-lane FP64 product)."""
+    room, k = synth.config_room(2)
+    ctx_l = make_ctx(F, room, k, lane_tiles=2, mfma=0, fused=0)
+    ctx_f = make_ctx(F, room, k, lane_tiles=2, mfma=0, fused=1)
+    ctx_r = make_ctx(F, room, k, lane_tiles=2, mfma=0, fused=1)
+    shapes = ctx_f.fmmbem_batch_shapes()
+    assert sum(d["mfma"] == 2 for d in shapes) >= 3
+    ctx_r.fmmbem_set_batch_shapes([dict(d, mfma=0) if d["mfma"] == 2 else d for d in shapes])
+    assert all(d["mfma"] != 2 for d in ctx_r.fmmbem_batch_shapes())
+    x = synth.complex_normal(room.n, 43)
+    y_l, y_f, y_r = (c.fmmbem_matvec(x, precision=F.FMMBEM_MIXED)[0] for c in (ctx_l, ctx_f, ctx_r))
+    assert np.array_equal(y_r, y_f)
+    assert np.linalg.norm(y_r - y_l) / np.linalg.norm(y_l) < 1e-5
+    assert np.array_equal(ctx_r.fmmbem_matvec(x)[0], ctx_l.fmmbem_matvec(x)[0])
+    for c in (ctx_l, ctx_f, ctx_r):
+        c.close()
 
 
 def test_replayed_tile_shapes_match_autotuned(F):
