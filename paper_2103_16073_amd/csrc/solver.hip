@@ -27,23 +27,35 @@ __device__ inline double2 ldc(const float2 *p, int64_t i) {
 __device__ inline void stc(double2 *p, int64_t i, double2 v) { p[i] = v; }
 __device__ inline void stc(float2 *p, int64_t i, double2 v) { p[i] = make_float2((float)v.x, (float)v.y); }
 
-// partial[v * DOT_BLOCKS + blk] = sum_{i in blk's stride} conj(V_v[i]) w[i]
+// partial[v * gridDim.x + blk] = sum_{i in blk's stride} conj(V_v[i]) w[i].  A workgroup takes
+// DOT_G vectors (blockIdx.y group): each element of w it loads serves all of them, so w is read
+// nv / DOT_G times rather than nv times (with FP32 Krylov vectors, w's 16 bytes per element would
+// otherwise be twice the vector's own 8).
+constexpr int DOT_G = 8;
 template <class S>
 __global__ void __launch_bounds__(256) k_dot_partial(int64_t n, const S *V, int64_t ldv, int nv, const double2 *w,
                                                      double2 *partial) {
-    const int v = blockIdx.y;
-    const S *x = V + (int64_t)v * ldv;
-    double2 s = cmk(0, 0);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        s = cadd(s, cmulc(w[i], ldc(x, i)));  // conj(x) w
-    __shared__ double2 red[256];
-    red[threadIdx.x] = s;
+    const int v0 = blockIdx.y * DOT_G, ng = min(DOT_G, nv - v0);
+    double2 s[DOT_G];
+#pragma unroll
+    for (int g = 0; g < DOT_G; ++g) s[g] = cmk(0, 0);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double2 wi = w[i];
+#pragma unroll
+        for (int g = 0; g < DOT_G; ++g)
+            if (g < ng) s[g] = cadd(s[g], cmulc(wi, ldc(V + (int64_t)(v0 + g) * ldv, i)));  // conj(V_v) w
+    }
+    __shared__ double2 red[DOT_G][256];
+#pragma unroll
+    for (int g = 0; g < DOT_G; ++g) red[g][threadIdx.x] = s[g];
     __syncthreads();
     for (int q = blockDim.x / 2; q > 0; q >>= 1) {
-        if ((int)threadIdx.x < q) red[threadIdx.x] = cadd(red[threadIdx.x], red[threadIdx.x + q]);
+        if ((int)threadIdx.x < q)
+#pragma unroll
+            for (int g = 0; g < DOT_G; ++g) red[g][threadIdx.x] = cadd(red[g][threadIdx.x], red[g][threadIdx.x + q]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) partial[(int64_t)v * gridDim.x + blockIdx.x] = red[0];
+    if ((int)threadIdx.x < ng) partial[(int64_t)(v0 + threadIdx.x) * gridDim.x + blockIdx.x] = red[threadIdx.x][0];
 }
 
 __global__ void __launch_bounds__(256) k_dot_final(int nblk, const double2 *partial, double2 *out) {
@@ -285,7 +297,7 @@ struct Blas {
         double2 *part = dget<double2>(scr, tag + "dot_part", (size_t)DOT_BLOCKS * std::max(nv, 1));
         double2 *res = dget<double2>(scr, tag + "dot_res", std::max(nv, 1));
         int nblk = (int)std::min<int64_t>(DOT_BLOCKS, std::max<int64_t>(1, (n + 255) / 256));
-        k_dot_partial<S><<<dim3(nblk, nv), 256, 0, st>>>(n, V, ldv, nv, w, part);
+        k_dot_partial<S><<<dim3(nblk, (nv + DOT_G - 1) / DOT_G), 256, 0, st>>>(n, V, ldv, nv, w, part);
         LAUNCH_OK();
         k_dot_final<<<nv, 256, 0, st>>>(nblk, part, res);
         LAUNCH_OK();
