@@ -221,6 +221,10 @@ typedef struct {
      * one of those changes); 0 (default): the inner GMRES applies the solve's own operator. */
     int inner_p_min;
     double inner_p_excess;
+    /* Classical Gram-Schmidt of the outer Arnoldi step (and of the batched solve): 0 one pass;
+     * 1 (default) a second pass when the first left less than 1/sqrt(2) of the new vector's norm;
+     * 2 always two passes.  Inner solves use 1. */
+    int reorth;
 } fmmbem_solve_opts;
 
 typedef struct {

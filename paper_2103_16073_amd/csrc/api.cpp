@@ -88,13 +88,13 @@ int fgmres_batch(int64_t n, hipStream_t st, DeviceBuffers &scr, int nv,
                  const std::function<void(int, const double2 *, double2 *)> &matvec_check,
                  const std::function<void(const double2 *, double2 *)> &precond, const double2 *B, double2 *X,
                  double tol, int m, int maxit, bool x0_given, std::vector<int> &iters, std::vector<int> &restarts,
-                 std::vector<double> &rel_res, std::vector<int> &status, bool basis32 = false);
+                 std::vector<double> &rel_res, std::vector<int> &status, bool basis32 = false, int reorth = 1);
 int fgmres(int64_t n, hipStream_t st, DeviceBuffers &scr, const char *tag,
            const std::function<void(const double2 *, double2 *)> &matvec,
            const std::function<void(const double2 *, double2 *)> &matvec_check,
            const std::function<void(const double2 *, double2 *)> &precond, const double2 *b, double2 *x, double tol,
            int m, int maxit, bool x0_given, bool final_residual, std::vector<double> *history, int &iters,
-           int &restarts, double &rel_res, const FgmresHooks *hooks, bool basis32 = false);
+           int &restarts, double &rel_res, const FgmresHooks *hooks, bool basis32 = false, int reorth = 1);
 
 void drop_graphs(fmmbem_ctx *c);
 static void autotune_batches(fmmbem_ctx *c);
@@ -1480,6 +1480,7 @@ void fmmbem_default_solve_opts(fmmbem_solve_opts *o) {
     o->inner_precision = FMMBEM_MIXED;
     o->inner_p_min = 0;
     o->inner_p_excess = 1.0;
+    o->reorth = 1;
 }
 
 int fmmbem_release_workspace(fmmbem_ctx *ctx) {
@@ -1989,6 +1990,7 @@ static int check_solve_opts(fmmbem_ctx *ctx, const fmmbem_solve_opts &o) {
     if (o.basis_fp32 < -1 || o.basis_fp32 > 1) return fail(ctx, FMMBEM_EINVAL, "basis_fp32 must be -1, 0 or 1");
     if (o.inner_p_min < 0 || (o.inner_p_min > 0 && !(o.inner_p_excess >= 0)))
         return fail(ctx, FMMBEM_EINVAL, "inner_p_min must be >= 0 and inner_p_excess >= 0");
+    if (o.reorth < 0 || o.reorth > 2) return fail(ctx, FMMBEM_EINVAL, "reorth must be 0, 1 or 2");
     if (o.precond < FMMBEM_PC_NONE || o.precond > FMMBEM_PC_LEARNED) return fail(ctx, FMMBEM_EINVAL, "unknown preconditioner");
     return FMMBEM_OK;
 }
@@ -2110,7 +2112,7 @@ int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, f
     }
     const bool b32 = o.basis_fp32 < 0 ? mixed : o.basis_fp32 != 0;
     int status = fgmres(n, st, ctx->scratch, "", mv, mv64, outer_pc, b, dx, o.tol, o.restart, o.maxit, o.use_x0 != 0,
-                        true, &ctx->history, iters, restarts, rel, &hk, b32);
+                        true, &ctx->history, iters, restarts, rel, &hk, b32, o.reorth);
     ctx->mlp_active = false;
     HIP_OK(hipMemcpyAsync(x, dx, sizeof(double2) * n, hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
@@ -2175,7 +2177,7 @@ int fmmbem_solve_batch(fmmbem_ctx *ctx, int32_t ns, const int32_t *isrc, const f
     std::vector<double> rel;
     const bool b32 = o.basis_fp32 < 0 ? mixed : o.basis_fp32 != 0;
     int rc = fgmres_batch(n, st, ctx->scratch, ns, mv, mv64, pc, B, X, o.tol, o.restart, o.maxit, o.use_x0 != 0,
-                          iters, restarts, rel, status, b32);
+                          iters, restarts, rel, status, b32, o.reorth);
     HIP_OK(hipMemcpyAsync(x, X, sizeof(double2) * n * ns, hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
     const double ts = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -356,7 +356,7 @@ static int fgmres_t(int64_t n, hipStream_t st, DeviceBuffers &scr, const char *t
                     const std::function<void(const double2 *, double2 *)> &matvec_check,
                     const std::function<void(const double2 *, double2 *)> &precond, const double2 *b, double2 *x,
                     double tol, int m, int maxit, bool x0_given, bool final_residual, std::vector<double> *history,
-                    int &iters, int &restarts, double &rel_res, const FgmresHooks *hooks) {
+                    int &iters, int &restarts, double &rel_res, const FgmresHooks *hooks, int reorth) {
     constexpr bool wide = std::is_same<S, double2>::value;
     const std::string tg(tag);
     Blas B{st, scr, n, tg};
@@ -423,13 +423,14 @@ static int fgmres_t(int64_t n, hipStream_t st, DeviceBuffers &scr, const char *t
             if constexpr (!wide) B.scale_copy(1.0, zj, zjs);
             matvec(zj, w);
             ++iters;
-            // classical Gram-Schmidt, repeated only when the first pass removed most of w
-            // (|w| fell below |w_0|/sqrt(2): the Daniel-Gragg-Kaufman-Stewart criterion)
-            const double w0 = B.nrm(w);
+            // classical Gram-Schmidt; reorth 1 repeats it only when the first pass removed most of w
+            // (|w| fell below |w_0|/sqrt(2): the Daniel-Gragg-Kaufman-Stewart criterion), 2 always,
+            // 0 never
+            const double w0 = reorth == 1 ? B.nrm(w) : 0.0;
             B.dots(V, n, j + 1, w, h1.data());
             B.sub_combo(V, n, j + 1, h1.data(), w);
             double hn = B.nrm(w);
-            if (!(hn > 0.7071067811865476 * w0)) {
+            if (reorth == 2 || (reorth == 1 && !(hn > 0.7071067811865476 * w0))) {
                 B.dots(V, n, j + 1, w, h2.data());
                 B.sub_combo(V, n, j + 1, h2.data(), w);
                 for (int i = 0; i <= j; ++i) h1[i] = cadd(h1[i], h2[i]);
@@ -488,12 +489,12 @@ int fgmres(int64_t n, hipStream_t st, DeviceBuffers &scr, const char *tag,
            const std::function<void(const double2 *, double2 *)> &matvec_check,
            const std::function<void(const double2 *, double2 *)> &precond, const double2 *b, double2 *x, double tol,
            int m, int maxit, bool x0_given, bool final_residual, std::vector<double> *history, int &iters,
-           int &restarts, double &rel_res, const FgmresHooks *hooks, bool basis32) {
+           int &restarts, double &rel_res, const FgmresHooks *hooks, bool basis32, int reorth) {
     if (basis32)
         return fgmres_t<float2>(n, st, scr, tag, matvec, matvec_check, precond, b, x, tol, m, maxit, x0_given,
-                                final_residual, history, iters, restarts, rel_res, hooks);
+                                final_residual, history, iters, restarts, rel_res, hooks, reorth);
     return fgmres_t<double2>(n, st, scr, tag, matvec, matvec_check, precond, b, x, tol, m, maxit, x0_given,
-                             final_residual, history, iters, restarts, rel_res, hooks);
+                             final_residual, history, iters, restarts, rel_res, hooks, reorth);
 }
 
 // Lock-step FGMRES over nv systems A x_s = b_s that share the operator: every step gathers the
@@ -516,7 +517,8 @@ static int fgmres_batch_t(int64_t n, hipStream_t st, DeviceBuffers &scr, int nv,
                           const std::function<void(int, const double2 *, double2 *)> &matvec_check,
                           const std::function<void(const double2 *, double2 *)> &precond, const double2 *B,
                           double2 *X, double tol, int m, int maxit, bool x0_given, std::vector<int> &iters,
-                          std::vector<int> &restarts, std::vector<double> &rel_res, std::vector<int> &status) {
+                          std::vector<int> &restarts, std::vector<double> &rel_res, std::vector<int> &status,
+                          int reorth) {
     constexpr bool wide = std::is_same<T, double2>::value;
     Blas Bl{st, scr, n, "bt_"};
     std::vector<BatchSys<T>> S(nv);
@@ -615,11 +617,11 @@ static int fgmres_batch_t(int64_t n, hipStream_t st, DeviceBuffers &scr, int nv,
             double2 *w = Sout + k * n;
             const int j = q.j;
             ++iters[s];
-            const double w0 = Bl.nrm(w);
+            const double w0 = reorth == 1 ? Bl.nrm(w) : 0.0;
             Bl.dots(q.V, n, j + 1, w, q.h1.data());
             Bl.sub_combo(q.V, n, j + 1, q.h1.data(), w);
             double hn = Bl.nrm(w);
-            if (!(hn > 0.7071067811865476 * w0)) {  // second pass only when needed (as in fgmres)
+            if (reorth == 2 || (reorth == 1 && !(hn > 0.7071067811865476 * w0))) {  // as in fgmres
                 Bl.dots(q.V, n, j + 1, w, q.h2.data());
                 Bl.sub_combo(q.V, n, j + 1, q.h2.data(), w);
                 for (int i = 0; i <= j; ++i) q.h1[i] = cadd(q.h1[i], q.h2[i]);
@@ -680,12 +682,12 @@ int fgmres_batch(int64_t n, hipStream_t st, DeviceBuffers &scr, int nv,
                  const std::function<void(int, const double2 *, double2 *)> &matvec_check,
                  const std::function<void(const double2 *, double2 *)> &precond, const double2 *B, double2 *X,
                  double tol, int m, int maxit, bool x0_given, std::vector<int> &iters, std::vector<int> &restarts,
-                 std::vector<double> &rel_res, std::vector<int> &status, bool basis32) {
+                 std::vector<double> &rel_res, std::vector<int> &status, bool basis32, int reorth) {
     if (basis32)
         return fgmres_batch_t<float2>(n, st, scr, nv, matvec, matvec_check, precond, B, X, tol, m, maxit, x0_given,
-                                      iters, restarts, rel_res, status);
+                                      iters, restarts, rel_res, status, reorth);
     return fgmres_batch_t<double2>(n, st, scr, nv, matvec, matvec_check, precond, B, X, tol, m, maxit, x0_given,
-                                   iters, restarts, rel_res, status);
+                                   iters, restarts, rel_res, status, reorth);
 }
 
 }  // namespace fmm

@@ -43,7 +43,7 @@ class SolveOpts(ctypes.Structure):
                 ("precond", ctypes.c_int), ("precision", ctypes.c_int), ("diag_shift", ctypes.c_double),
                 ("use_x0", ctypes.c_int), ("inner_iters", ctypes.c_int), ("inner_tol", ctypes.c_double),
                 ("inner_precision", ctypes.c_int), ("basis_fp32", ctypes.c_int), ("inner_p_min", ctypes.c_int),
-                ("inner_p_excess", ctypes.c_double)]
+                ("inner_p_excess", ctypes.c_double), ("reorth", ctypes.c_int)]
 
 
 class SolveReport(ctypes.Structure):

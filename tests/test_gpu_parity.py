@@ -124,6 +124,29 @@ def test_matvec_exact_far_vs_dense(F, cfg1_dense):
     ctx.close()
 
 
+@pytest.mark.parametrize("reorth", [0, 1, 2])
+def test_solve_gram_schmidt_passes_vs_oracle_lu(F, cfg1_dense, reorth):
+    """One classical Gram-Schmidt pass, a second one when needed, or always two: each solve
+    reaches the FP64 residual target and agrees with LU, single and batched."""
+    room, k = cfg1_dense
+    ctx = make_ctx(F, room, k)
+    rs, _ = synth.source_and_receivers(room, 4, nsrc=2)
+    ctx.fmmbem_set_sources(rs)
+    rc = ctx.fmmbem_get_info().rc
+    kw = dict(tol=1e-8, restart=200, maxit=200, precond=F.FMMBEM_PC_NEARBLOCK, reorth=reorth)
+    x, rep, rc_ = ctx.fmmbem_solve(0, **kw)
+    X, reps, rcb = ctx.fmmbem_solve_batch([0, 1], **kw)
+    print(f"reorth {reorth}: iters {rep.iters} rel {rep.rel_res:.2e}; batched {[r.iters for r in reps]}")
+    assert rc_ == 0 and rep.rel_res < 1e-8 and rcb == 0
+    for s, xs in ((0, x), (0, X[0]), (1, X[1])):
+        A, b, _, _ = bem.direct_system(room.vertices, room.triangles, k, room.beta, rs[s], rc)
+        x_ref = bem.solve_lu(A, b)
+        assert np.linalg.norm(xs - x_ref) / np.linalg.norm(x_ref) < 1e-5
+    with pytest.raises(F.FmmbemError):
+        ctx.fmmbem_solve(0, tol=1e-4, reorth=3)
+    ctx.close()
+
+
 def test_solve_inner_coarse_fmm_vs_oracle_lu(F, cfg1_dense):
     """The inner GMRES on a second FMM with a smaller truncation number (Section 4.3): the outer
     solve still reaches its FP64 target and agrees with LU; every inner product runs on the
