@@ -28,6 +28,9 @@ def log(*a):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_lroom_1M_fp64.json")
+# tile shapes of the run whose counters TRAFFIC_FILE holds: replayed by default on that workload, so
+# that the timed launches are the counted ones (the autotuner's near ties may fall either way)
+SHAPES_FILE = os.path.join(ROOT, "profiles", "tile_shapes_lroom_1M_fp64.json")
 
 
 def measured_traffic(kernel, launches_per_product):
@@ -77,7 +80,10 @@ def main():
     ap.add_argument("--fused", type=int, default=1, help="fused LDS-resident translation tiles for p <= 16: 0 never, 1 allowed")
     ap.add_argument("--shapes-out", default=None, help="write the batches' tile shapes (JSON) after setup")
     ap.add_argument("--shapes-in", default=None,
-                    help="replay tile shapes written by --shapes-out (no autotuning: the same launches as that run)")
+                    help="replay tile shapes written by --shapes-out (the same launches as that run); default on the "
+                         "L-room: the shapes of the committed counter run")
+    ap.add_argument("--fresh-shapes", action="store_true",
+                    help="keep this run's autotuned shapes instead of replaying the committed ones")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -96,7 +102,13 @@ def main():
     rs, rec = synth.source_and_receivers(room, 64, nsrc=4)
     n = room.n
     log(f"workload {args.workload}: N={n} k={k:.3f}")
-    ctx = F.Context(0, lds_budget=args.lds_budget, autotune=0 if (args.no_autotune or args.shapes_in) else 1,
+    shapes_in = args.shapes_in
+    if (shapes_in is None and args.workload == 3 and not args.fresh_shapes and not args.no_autotune
+            and os.path.exists(SHAPES_FILE)):
+        shapes_in = SHAPES_FILE
+    # autotuned even when shapes are replayed: the coarser context of the inner-outer solve
+    # inherits the options and tunes its own batches
+    ctx = F.Context(0, lds_budget=args.lds_budget, autotune=0 if args.no_autotune else 1,
                     mfma=args.mfma, fused=args.fused)
     ctx.fmmbem_set_mesh(room.vertices, room.triangles)
     ctx.fmmbem_set_wavenumber(k)
@@ -109,10 +121,18 @@ def main():
     ps = [info.p[l] for l in range(info.depth + 1)]
     log(f"setup {t_setup:.2f}s depth {info.depth} leaves {info.nleaf} p {ps} near_nnz {info.near_nnz} "
         f"lds_max {info.lds_max}")
-    if args.shapes_in:
-        with open(args.shapes_in) as fh:
-            ctx.fmmbem_set_batch_shapes(json.load(fh))
-        log(f"tile shapes replayed from {args.shapes_in}")
+    shapes_src = "autotuned" if not args.no_autotune else "fixed rule"
+    if shapes_in:
+        with open(shapes_in) as fh:
+            want = json.load(fh)
+        try:
+            ctx.fmmbem_set_batch_shapes(want)
+            shapes_src = "replayed from " + os.path.relpath(shapes_in, ROOT)
+            log(f"tile shapes {shapes_src}")
+        except F.FmmbemError as e:
+            if args.shapes_in:
+                raise
+            log(f"committed tile shapes do not fit this tree ({e}); keeping the autotuned ones")
     shapes = ctx.fmmbem_batch_shapes()
     if args.shapes_out:
         with open(args.shapes_out, "w") as fh:
@@ -272,6 +292,7 @@ def main():
                    "parallelism": "single GPU"},
         "setup_s": t_setup,
         "tile_shapes": shapes,
+        "tile_shapes_source": shapes_src,
         "phases_ms": phases,
         "roofline": roofline,
         "mixed_precision": mixed,
