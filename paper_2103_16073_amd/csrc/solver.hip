@@ -39,11 +39,24 @@ __global__ void __launch_bounds__(256) k_dot_partial(int64_t n, const S *V, int6
     double2 s[DOT_G];
 #pragma unroll
     for (int g = 0; g < DOT_G; ++g) s[g] = cmk(0, 0);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const double2 wi = w[i];
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, di = (int64_t)gridDim.x * blockDim.x;
+    if (ng == DOT_G) {
+        // whole group: the DOT_G loads of a row are issued before any of them is used
+        for (int64_t i = i0; i < n; i += di) {
+            const double2 wi = w[i];
+            double2 x[DOT_G];
 #pragma unroll
-        for (int g = 0; g < DOT_G; ++g)
-            if (g < ng) s[g] = cadd(s[g], cmulc(wi, ldc(V + (int64_t)(v0 + g) * ldv, i)));  // conj(V_v) w
+            for (int g = 0; g < DOT_G; ++g) x[g] = ldc(V + (int64_t)(v0 + g) * ldv, i);
+#pragma unroll
+            for (int g = 0; g < DOT_G; ++g) s[g] = cadd(s[g], cmulc(wi, x[g]));  // conj(V_v) w
+        }
+    } else {
+        for (int64_t i = i0; i < n; i += di) {
+            const double2 wi = w[i];
+#pragma unroll
+            for (int g = 0; g < DOT_G; ++g)
+                if (g < ng) s[g] = cadd(s[g], cmulc(wi, ldc(V + (int64_t)(v0 + g) * ldv, i)));
+        }
     }
     __shared__ double2 red[DOT_G][256];
 #pragma unroll
@@ -72,23 +85,42 @@ __global__ void __launch_bounds__(256) k_dot_final(int nblk, const double2 *part
     if (threadIdx.x == 0) out[v] = red[0];
 }
 
-// w -= sum_v h[v] V_v
+// w -= sum_v h[v] V_v, in the order of v; vectors are read COMBO_U at a time, all loads of a
+// group issued before the group's updates (one load per iteration would leave one 1 KB request in
+// flight per wavefront)
+constexpr int COMBO_U = 8;
 template <class S>
 __global__ void k_sub_combo(int64_t n, const S *V, int64_t ldv, int nv, const double2 *h, double2 *w) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double2 s = w[i];
-    for (int v = 0; v < nv; ++v) s = csub(s, cmul(h[v], ldc(V, (int64_t)v * ldv + i)));
+    int v = 0;
+    for (; v + COMBO_U <= nv; v += COMBO_U) {
+        double2 x[COMBO_U];
+#pragma unroll
+        for (int u = 0; u < COMBO_U; ++u) x[u] = ldc(V, (int64_t)(v + u) * ldv + i);
+#pragma unroll
+        for (int u = 0; u < COMBO_U; ++u) s = csub(s, cmul(h[v + u], x[u]));
+    }
+    for (; v < nv; ++v) s = csub(s, cmul(h[v], ldc(V, (int64_t)v * ldv + i)));
     w[i] = s;
 }
 
-// x += sum_v y[v] Z_v
+// x += sum_v y[v] Z_v (same grouping)
 template <class S>
 __global__ void k_add_combo(int64_t n, const S *Z, int64_t ldz, int nv, const double2 *y, double2 *x) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double2 s = x[i];
-    for (int v = 0; v < nv; ++v) s = cadd(s, cmul(y[v], ldc(Z, (int64_t)v * ldz + i)));
+    int v = 0;
+    for (; v + COMBO_U <= nv; v += COMBO_U) {
+        double2 z[COMBO_U];
+#pragma unroll
+        for (int u = 0; u < COMBO_U; ++u) z[u] = ldc(Z, (int64_t)(v + u) * ldz + i);
+#pragma unroll
+        for (int u = 0; u < COMBO_U; ++u) s = cadd(s, cmul(y[v + u], z[u]));
+    }
+    for (; v < nv; ++v) s = cadd(s, cmul(y[v], ldc(Z, (int64_t)v * ldz + i)));
     x[i] = s;
 }
 
