@@ -41,3 +41,35 @@ def test_create_without_device_fails_cleanly():
         pytest.skip("library not built")
     with pytest.raises(F.FmmbemError):
         F.Context(0)
+
+
+def test_binding_structs_match_header_layout(tmp_path):
+    """Every struct the binding mirrors has the header's field offsets and size (a C program built
+    from include/fmmbem.h prints them), so an option or report field never lands in another's slot."""
+    import ctypes
+    import shutil
+    import subprocess
+    from paper_2103_16073_amd import fmmbem as F
+    if not shutil.which("gcc"):
+        pytest.skip("no C compiler")
+    pairs = {"fmmbem_options": F.Options, "fmmbem_solve_opts": F.SolveOpts, "fmmbem_solve_report": F.SolveReport,
+             "fmmbem_train_opts": F.TrainOpts, "fmmbem_train_report": F.TrainReport, "fmmbem_info": F.Info,
+             "fmmbem_batch_shape": F.BatchShape, "fmmbem_kstat": F.KStat}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "fmmbem.h"', "int main(void) {"]
+    for cname, cls in pairs.items():
+        lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        cname, field, value = line.split()
+        got[(cname, field)] = int(value)
+    for cname, cls in pairs.items():
+        assert got[(cname, "sizeof")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
