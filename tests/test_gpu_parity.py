@@ -593,6 +593,42 @@ def test_matvec_fmm_sampled_rows_full_size(F, cfg, nrows):
     ctx.close()
 
 
+def test_matvec_sampled_rows_bench_configuration(F):
+    """The 1M L-room in the launch configuration the benchmark times: autotuned context with the
+    tile shapes of the committed counter run replayed, products on device vectors (captured-graph
+    replays) on a torch stream.  Seeded rows against the oracle's matrix-free rows (FP64 <= 1e-6,
+    mixed <= 1e-4); two replays give bitwise the same product."""
+    import json
+    import os
+    import torch
+    room, k = synth.config_room(3)
+    ctx = make_ctx(F, room, k, autotune=1)
+    shapes = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "profiles",
+                          "tile_shapes_lroom_1M_fp64.json")
+    if os.path.exists(shapes):
+        with open(shapes) as fh:
+            ctx.fmmbem_set_batch_shapes(json.load(fh))
+    info = ctx.fmmbem_get_info()
+    x = synth.complex_normal(room.n, 11)
+    rows = np.random.default_rng(5).choice(room.n, 64, replace=False)
+    ref = bem.direct_matvec_rows(room.vertices, room.triangles, k, room.beta, info.rc, x, rows)
+    st = torch.cuda.Stream()
+    xd = torch.from_numpy(x).to("cuda")
+    yd = torch.empty_like(xd)
+    torch.cuda.synchronize()
+    for prec, tol in ((F.FMMBEM_FP64, 1e-6), (F.FMMBEM_MIXED, 1e-4)):
+        ys = []
+        for _ in range(2):
+            ctx.fmmbem_matvec_dev(xd.data_ptr(), yd.data_ptr(), 1, precision=prec, stream=st.cuda_stream)
+            st.synchronize()
+            ys.append(yd.cpu().numpy())
+        assert np.array_equal(ys[0], ys[1])
+        err = np.linalg.norm(ys[0][rows] - ref) / np.linalg.norm(ref)
+        print(f"precision {prec}: sampled rows rel L2 {err:.3e}")
+        assert err < tol
+    ctx.close()
+
+
 def test_solve_many_frequencies_match_sequential(F):
     """Several frequencies of one room, each with its own mesh (about six elements per wavelength,
     so N and the octree differ), solved through fmmbem_solve_many give bitwise the solutions of
