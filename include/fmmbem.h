@@ -218,7 +218,9 @@ typedef struct {
      * > 0 (with inner_iters > 0): the inner GMRES applies an FMM with the truncation rule's p_min
      * and excess replaced by inner_p_min and inner_p_excess, set up once on the same mesh,
      * wavenumber, admittance and formulation (its own tables and near-field entries, kept until
-     * one of those changes); 0 (default): the inner GMRES applies the solve's own operator. */
+     * one of those changes); 0 (default): the inner GMRES applies the solve's own operator.
+     * inner_p_excess defaults to 1.0; a negative inner_p_min, or a negative excess with
+     * inner_p_min > 0, is FMMBEM_EINVAL.  The coarser context doubles the FMM's device memory. */
     int inner_p_min;
     double inner_p_excess;
     /* Classical Gram-Schmidt of the outer Arnoldi step (and of the batched solve): 0 one pass;
@@ -231,7 +233,7 @@ typedef struct {
     int iters;            /* FGMRES iterations (= matrix-vector products after the first residual) */
     int restarts;
     double rel_res;       /* final relative residual measured with the FP64 FMM operator */
-    double t_setup_s;     /* setup seconds spent inside this call */
+    double t_setup_s;     /* setup seconds spent inside this call (the coarser inner context's included) */
     double t_solve_s;     /* iteration seconds */
     int status;
     int64_t matvecs_fp64;  /* FMM products of the call, by arithmetic (outer, restart and inner) */
