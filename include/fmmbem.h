@@ -71,7 +71,8 @@ enum {
                              preconditioners FMMBEM_PC_NONE or FMMBEM_PC_DIAG; one vector per pass */
     FMMBEM_INDIRECT = 3 /* Eq. ibem5: every element two-sided, unknowns (psi-, psi+) = the field on
                            the side the normal leaves (the room) and on the side it points to
-                           (2N unknowns, psi- block first); FP64 products only */
+                           (2N unknowns, psi- block first); FP64 and MIXED products (MIXED: FP32
+                           translations, FP64 near field) */
 };
 
 /* arithmetic of the matrix-vector product */
@@ -148,15 +149,22 @@ const char *fmmbem_last_error(const fmmbem_ctx *ctx);
 /* Surface mesh.  xyz: nv*3 vertex coordinates (m).  tri: nt*3 vertex indices, each triangle
  * ordered so that (v1-v0)x(v2-v0) points out of the fluid.  EINVAL on an index out of range, a
  * degenerate (zero-area) triangle, or a closed mesh whose enclosed volume sum_j A_j (c_j.n_j)/3
- * is not positive (inward normals). */
+ * is not positive (inward normals).  There is no per-element two-sided mask: in the indirect
+ * formulation (Eq. ibem5) every element carries both unknowns (psi-, psi+), a closed wall's outer
+ * face taking the admittance beta_plus (by default the wall's own), a thin baffle being a
+ * zero-thickness plate and an open doorway a hole (its elements left out of the mesh). */
 int fmmbem_set_mesh(fmmbem_ctx *ctx, int64_t nv, const double *xyz, int64_t nt, const int64_t *tri);
 
 /* Wavenumber k = 2 pi f / c > 0 (Eq. sp2).  EINVAL if not finite and positive. */
 int fmmbem_set_wavenumber(fmmbem_ctx *ctx, double k);
 
-/* Admittance beta = 1/zeta per triangle (Eq. sp3/sp4), nt values; Re(beta) >= 0 (passive wall).
- * beta = 0 is a rigid wall (Eq. sp5), beta = 1 absorbs normal incidence fully. */
-int fmmbem_set_admittance(fmmbem_ctx *ctx, const fmmbem_c64 *beta);
+/* Admittance beta = 1/zeta per triangle (Eq. sp3/sp4), nt values each; Re(beta) >= 0 and finite
+ * (passive wall), else EINVAL naming the element.  beta = 0 is a rigid wall (Eq. sp5), beta = 1
+ * absorbs normal incidence fully.  beta_minus is the admittance of the face the normal leaves (the
+ * room side; the only one the direct formulations use); beta_plus that of the face it points to
+ * (indirect formulation, Eq. ibem4-ibem5), NULL for the same material on both faces.  Both arrays
+ * are copied; a later call replaces both. */
+int fmmbem_set_admittance(fmmbem_ctx *ctx, const fmmbem_c64 *beta_minus, const fmmbem_c64 *beta_plus);
 
 /* Unit monopole sources (Eq. sp6): ns positions rs (ns*3), optional complex amplitudes (NULL = 1). */
 int fmmbem_set_sources(fmmbem_ctx *ctx, int32_t ns, const double *rs, const fmmbem_c64 *amp);
@@ -166,11 +174,6 @@ int fmmbem_set_sources(fmmbem_ctx *ctx, int32_t ns, const double *rs, const fmmb
  * of the far field at every element; preconditioners: FMMBEM_PC_NONE or FMMBEM_PC_DIAG
  * (2x2 element blocks). */
 int fmmbem_set_formulation(fmmbem_ctx *ctx, int formulation);
-
-/* Admittance of the + faces for the indirect formulation (nt values, Re >= 0); NULL: the same
- * as fmmbem_set_admittance (one material on both faces).  A hole (open doorway) is modelled by
- * leaving its elements out of the mesh. */
-int fmmbem_set_admittance_plus(fmmbem_ctx *ctx, const fmmbem_c64 *beta_plus);
 
 /* Build what is out of date: octree and interaction lists (mesh), translation and rotation
  * tables and near-field entries (k), preconditioner data.  Idempotent; matvec/solve call it. */
@@ -184,6 +187,12 @@ int64_t fmmbem_num_unknowns(const fmmbem_ctx *ctx);
  * for Eq. ibem5 (L[g- + g+], (g+ - g-)/2 + L'[g- + g+]) with g-+ = -+ dpsi_in/dn + i k beta-+ psi_in. */
 int fmmbem_rhs(fmmbem_ctx *ctx, fmmbem_c64 *b);
 
+/* Same into device memory: b_dev holds ns x num_unknowns fmmbem_c64 values (the caller's
+ * allocation, e.g. a torch tensor).  The work runs on the library's stream after the work already
+ * enqueued on `stream` (hipStream_t, NULL = the null stream), and `stream` is made to wait for
+ * it; the call returns once everything is enqueued. */
+int fmmbem_rhs_dev(fmmbem_ctx *ctx, void *b_dev, void *stream);
+
 /* y = A x for nrhs vectors (x, y: nrhs*N, host memory).  precision: FMMBEM_FP64 / FMMBEM_MIXED
  * (direct: FP32 near-field kernel and translations; indirect: FP32 translations, FP64 near field;
  * both keep densities, P2M, L2P and the output FP64).
@@ -191,7 +200,11 @@ int fmmbem_rhs(fmmbem_ctx *ctx, fmmbem_c64 *b);
  * O(N^2) product, for validation; FP64 only). */
 int fmmbem_matvec(fmmbem_ctx *ctx, int32_t nrhs, const fmmbem_c64 *x, fmmbem_c64 *y, int precision, int exact_far);
 
-/* Same on device pointers, enqueued on `stream` (hipStream_t); returns after enqueueing. */
+/* Same on device pointers (nrhs*N fmmbem_c64 values each, caller-owned): the product runs on the
+ * library's streams after the work already enqueued on `stream` (hipStream_t, NULL = the null
+ * stream), and `stream` is made to wait for all of it, the copies into y_dev included, so work
+ * enqueued on `stream` afterwards sees the finished y.  Returns after enqueueing; exact_far is not
+ * offered here. */
 int fmmbem_matvec_dev(fmmbem_ctx *ctx, int32_t nrhs, const void *x_dev, void *y_dev, int precision, void *stream);
 
 typedef struct {
@@ -251,6 +264,13 @@ void fmmbem_default_solve_opts(fmmbem_solve_opts *o);
  * convergence, FMMBEM_ENOCONV at maxit (x still the best iterate), or an error. */
 int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, fmmbem_c64 *x,
                  fmmbem_solve_report *rep);
+
+/* Same with x in device memory (num_unknowns fmmbem_c64 values, caller-owned): the initial guess
+ * (use_x0) is read after the work already enqueued on `stream` (hipStream_t, NULL = the null
+ * stream), and `stream` is made to wait for the write of the solution.  The solve itself needs
+ * host decisions at every iteration, so the call returns when it has finished. */
+int fmmbem_solve_dev(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, void *x_dev,
+                     fmmbem_solve_report *rep, void *stream);
 
 /* Solve the systems of ns sources together (batching): isrc[s] names the source of system s;
  * x is ns*N (in: initial guesses if use_x0; out: solutions), rep has ns entries.  The systems
@@ -341,6 +361,13 @@ int fmmbem_solve_history(fmmbem_ctx *ctx, int32_t max, double *est, int32_t *cou
  * mu = psi+ - psi-.  psi: nr values. */
 int fmmbem_eval_field(fmmbem_ctx *ctx, int32_t isrc, int64_t nr, const double *r, const fmmbem_c64 *x,
                       fmmbem_c64 *psi);
+
+/* Same on device memory: r_dev nr*3 doubles, x_dev num_unknowns and psi_dev nr fmmbem_c64 values
+ * (caller-owned).  Runs on the library's stream after the work already enqueued on `stream`
+ * (hipStream_t, NULL = the null stream), which is made to wait for it; returns after enqueueing.
+ * nr < 2^31. */
+int fmmbem_eval_field_dev(fmmbem_ctx *ctx, int32_t isrc, int64_t nr, const void *r_dev, const void *x_dev,
+                          void *psi_dev, void *stream);
 
 /* ---- inspection (tests, benchmarks) ---------------------------------------------------- */
 

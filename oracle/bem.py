@@ -27,6 +27,7 @@ Definitions followed (paper, Sections 2-3):
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 
 import numpy as np
@@ -78,6 +79,14 @@ def geometry(V, T):
     c, nrm, a = np.empty((n, 3)), np.empty((n, 3)), np.empty(n)
     lib().oracle_geometry(n, _d(V), _i(T), _d(c), _d(nrm), _d(a))
     return c, nrm, a
+
+
+def near_cutoff(V, T, factor=1.8):
+    """Near cutoff r_c of the accurate-integration rule (reading of Section 3.3, which leaves it
+    unspecified): factor times the side sqrt(2 A_mean) of the square cell that two triangles of
+    the mean area make.  Pairs with |c_i - c_j|^2 < r_c^2 are integrated accurately."""
+    _, _, a = geometry(V, T)
+    return factor * math.sqrt(2.0 * math.fsum(a) / a.shape[0])
 
 
 def dense_LM(V, T, k, rc, eta=DEFAULT_ETA):

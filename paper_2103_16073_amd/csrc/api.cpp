@@ -33,6 +33,9 @@ __global__ void k_densities_ind(int64_t, const int32_t *, const double2 *, const
                                 double2 *, double2 *);
 __global__ void k_field_dens_ind(int64_t, const int32_t *, const double2 *, const double2 *, const double2 *,
                                  const double2 *, const double2 *, double, double2 *, double2 *);
+__global__ void k_field_dens(int64_t, int, const int32_t *, const double2 *, const double4 *, const double4 *,
+                             const double2 *, const double2 *, double, double, double, double, double2, double2 *,
+                             double2 *);
 __global__ void k_rhs_ind_local(int64_t, const int32_t *, const double2 *, const double2 *, double2 *);
 __global__ void k_bm_combine(int64_t, const int32_t *, const double2 *, const double2 *, double, double2,
                              const double2 *, double2 *);
@@ -133,7 +136,9 @@ static void setup_mesh(fmmbem_ctx *c) {
             vlo[d] = std::min(vlo[d], c->xyz[3 * v + d]);
             vhi[d] = std::max(vhi[d], c->xyz[3 * v + d]);
         }
-    double asum = 0.0;
+    // mean area by a compensated (Neumaier) sum: correct to about an ulp at any N, so the cutoff
+    // does not depend on the order of the triangles
+    double asum = 0.0, acomp = 0.0;
     for (int64_t j = 0; j < n; ++j) {
         const double *a = &c->xyz[3 * c->tri[3 * j]], *b = &c->xyz[3 * c->tri[3 * j + 1]], *e = &c->xyz[3 * c->tri[3 * j + 2]];
         double u[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]}, v[3] = {e[0] - a[0], e[1] - a[1], e[2] - a[2]};
@@ -144,8 +149,11 @@ static void setup_mesh(fmmbem_ctx *c) {
             nrm[3 * j + d] = w[d] / l;
         }
         area[j] = 0.5 * l;
-        asum += area[j];
+        const double t = asum + area[j];
+        acomp += std::fabs(asum) >= area[j] ? (asum - t) + area[j] : (area[j] - t) + asum;
+        asum = t;
     }
+    asum += acomp;
     c->rc = c->opt.rc > 0 ? c->opt.rc : c->opt.rc_factor * std::sqrt(2.0 * asum / (double)n);
     TreeHost &T = c->tree;
     c->tree_min_leaf = c->opt.kd_leaf_min > 0 ? c->opt.kd_leaf_min / c->k : 0.0;
@@ -920,6 +928,9 @@ static hipEvent_t fj_event(fmmbem_ctx *c, int slot) {
 }
 static void ev_record(fmmbem_ctx *c, int slot, hipStream_t s) { HIP_OK(hipEventRecord(fj_event(c, slot), s)); }
 static void ev_wait(fmmbem_ctx *c, int slot, hipStream_t s) { HIP_OK(hipStreamWaitEvent(s, fj_event(c, slot), 0)); }
+// completion of a *_dev call on the library's stream, waited for by the caller's stream (never
+// recorded inside a captured product)
+constexpr int EV_CALLER_IN = 39, EV_CALLER_DONE = 40;
 
 // Far-field translations of one product on two streams.  The main stream A runs the M2L of the
 // deepest levels (l >= L - 2: by far the most jobs), leaf level first, straight after P2M; the
@@ -1097,10 +1108,10 @@ static void matvec_graph(fmmbem_ctx *c, int nr, const double2 *x, double2 *y, bo
         drop_graphs(c);  // some captured pointer may be stale
         g = nullptr;
     }
-    if (g) {
+    const bool replay = g != nullptr;
+    if (replay) {
         rec(c, 0);
         HIP_OK(hipGraphLaunch(g->exec, st));
-        for (int e = 1; e <= 8; ++e) rec(c, e);
     } else {
         // eager product first: it allocates everything the product touches, then capture it
         matvec_chunk(c, nr, gx, gy, false, mixed);
@@ -1124,6 +1135,9 @@ static void matvec_graph(fmmbem_ctx *c, int nr, const double2 *x, double2 *y, bo
         c->graphs.push_back({nr, mixed, exec, c->buf.gen, c->scratch.gen});
     }
     HIP_OK(hipMemcpyAsync(y, gy, bytes, hipMemcpyDeviceToDevice, st));
+    // a replay records the phase events only around the whole product, after the copy into y
+    if (replay)
+        for (int e = 1; e <= 8; ++e) rec(c, e);
 }
 
 // any number of vectors, in chunks of 4, 2 and 1 (the kernels' right-hand-side counts)
@@ -1410,12 +1424,11 @@ static fmmbem_ctx *ensure_inner(fmmbem_ctx *c, int p_min, double p_excess) {
         chk(fmmbem_set_wavenumber(in, c->k));
         std::vector<fmmbem_c64> b(c->nt), bp;
         for (int64_t i = 0; i < c->nt; ++i) b[i] = {c->beta[i].x, c->beta[i].y};
-        chk(fmmbem_set_admittance(in, b.data()));
         if (!c->beta_plus.empty()) {
             bp.resize(c->nt);
             for (int64_t i = 0; i < c->nt; ++i) bp[i] = {c->beta_plus[i].x, c->beta_plus[i].y};
         }
-        chk(fmmbem_set_admittance_plus(in, bp.empty() ? nullptr : bp.data()));
+        chk(fmmbem_set_admittance(in, b.data(), bp.empty() ? nullptr : bp.data()));
         chk(fmmbem_set_formulation(in, c->formulation));
     }
     ensure_setup(in);
@@ -1610,15 +1623,28 @@ int fmmbem_set_wavenumber(fmmbem_ctx *ctx, double k) {
     return FMMBEM_OK;
 }
 
-int fmmbem_set_admittance(fmmbem_ctx *ctx, const fmmbem_c64 *beta) {
+static int check_admittance(fmmbem_ctx *ctx, const fmmbem_c64 *beta, const char *name) {
+    for (int64_t i = 0; i < ctx->nt; ++i)
+        if (!(beta[i].re >= 0.0) || !std::isfinite(beta[i].re) || !std::isfinite(beta[i].im))
+            return fail(ctx, FMMBEM_EINVAL,
+                        std::string(name) + "[" + std::to_string(i) + "]: Re(beta) must be finite and >= 0 (passive wall)");
+    return FMMBEM_OK;
+}
+
+int fmmbem_set_admittance(fmmbem_ctx *ctx, const fmmbem_c64 *beta_minus, const fmmbem_c64 *beta_plus) {
     if (!ctx) return FMMBEM_EINVAL;
     if (!ctx->have_mesh) return fail(ctx, FMMBEM_ENOTREADY, "set the mesh before the admittance");
-    if (!beta) return fail(ctx, FMMBEM_EINVAL, "beta is NULL");
-    for (int64_t i = 0; i < ctx->nt; ++i)
-        if (!(beta[i].re >= 0.0) || !std::isfinite(beta[i].im))
-            return fail(ctx, FMMBEM_EINVAL, "beta[" + std::to_string(i) + "]: Re(beta) must be >= 0 (passive wall)");
+    if (!beta_minus) return fail(ctx, FMMBEM_EINVAL, "beta_minus is NULL");
+    if (int e = check_admittance(ctx, beta_minus, "beta_minus")) return e;
+    if (beta_plus)
+        if (int e = check_admittance(ctx, beta_plus, "beta_plus")) return e;
     ctx->beta.resize(ctx->nt);
-    for (int64_t i = 0; i < ctx->nt; ++i) ctx->beta[i] = cmk(beta[i].re, beta[i].im);
+    for (int64_t i = 0; i < ctx->nt; ++i) ctx->beta[i] = cmk(beta_minus[i].re, beta_minus[i].im);
+    ctx->beta_plus.clear();
+    if (beta_plus) {
+        ctx->beta_plus.resize(ctx->nt);
+        for (int64_t i = 0; i < ctx->nt; ++i) ctx->beta_plus[i] = cmk(beta_plus[i].re, beta_plus[i].im);
+    }
     ctx->have_beta = true;
     ctx->beta_dirty = true;
     ++ctx->input_gen;
@@ -1651,23 +1677,6 @@ int fmmbem_set_formulation(fmmbem_ctx *ctx, int f) {
     return FMMBEM_OK;
 }
 
-int fmmbem_set_admittance_plus(fmmbem_ctx *ctx, const fmmbem_c64 *beta_plus) {
-    if (!ctx) return FMMBEM_EINVAL;
-    if (!ctx->have_mesh) return fail(ctx, FMMBEM_ENOTREADY, "set the mesh before the admittance");
-    if (!beta_plus) {
-        ctx->beta_plus.clear();
-    } else {
-        for (int64_t i = 0; i < ctx->nt; ++i)
-            if (!(beta_plus[i].re >= 0.0) || !std::isfinite(beta_plus[i].im))
-                return fail(ctx, FMMBEM_EINVAL, "beta_plus[" + std::to_string(i) + "]: Re(beta) must be >= 0");
-        ctx->beta_plus.resize(ctx->nt);
-        for (int64_t i = 0; i < ctx->nt; ++i) ctx->beta_plus[i] = cmk(beta_plus[i].re, beta_plus[i].im);
-    }
-    ctx->beta_dirty = true;
-    ++ctx->input_gen;
-    return FMMBEM_OK;
-}
-
 int fmmbem_setup(fmmbem_ctx *ctx) {
     if (!ctx) return FMMBEM_EINVAL;
     GUARD_BEGIN
@@ -1682,6 +1691,16 @@ int64_t fmmbem_num_unknowns(const fmmbem_ctx *ctx) {
     return ctx->formulation == FMMBEM_INDIRECT ? 2 * ctx->nt : ctx->nt;
 }
 
+// right-hand side of source s into the device vector b (num_unknowns values) on the library stream
+static void rhs_one(fmmbem_ctx *ctx, int s, double2 *b) {
+    if (indirect(ctx)) rhs_ind(ctx, s, b);
+    else if (burton_miller(ctx)) rhs_bm(ctx, s, b);
+    else if (dpsi(ctx)) {
+        check_dpsi_beta(ctx);
+        rhs_dpsi(ctx, s, b);
+    } else rhs_dev(ctx, s, b);
+}
+
 int fmmbem_rhs(fmmbem_ctx *ctx, fmmbem_c64 *b) {
     if (!ctx) return FMMBEM_EINVAL;
     if (!b) return fail(ctx, FMMBEM_EINVAL, "b is NULL");
@@ -1692,16 +1711,28 @@ int fmmbem_rhs(fmmbem_ctx *ctx, fmmbem_c64 *b) {
     const int64_t n = fmmbem_num_unknowns(ctx);
     double2 *db = dget<double2>(ctx->scratch, "rhs_out", n);
     for (size_t s = 0; s < ctx->src.size() / 3; ++s) {
-        if (indirect(ctx)) rhs_ind(ctx, (int)s, db);
-        else if (burton_miller(ctx)) rhs_bm(ctx, (int)s, db);
-        else if (dpsi(ctx)) {
-            check_dpsi_beta(ctx);
-            rhs_dpsi(ctx, (int)s, db);
-        }
-        else rhs_dev(ctx, (int)s, db);
+        rhs_one(ctx, (int)s, db);
         HIP_OK(hipMemcpyAsync(b + s * n, db, sizeof(double2) * n, hipMemcpyDeviceToHost, ctx->stream));
+        HIP_OK(hipStreamSynchronize(ctx->stream));
     }
-    HIP_OK(hipStreamSynchronize(ctx->stream));
+    return FMMBEM_OK;
+    GUARD_END
+}
+
+int fmmbem_rhs_dev(fmmbem_ctx *ctx, void *b_dev, void *stream) {
+    if (!ctx) return FMMBEM_EINVAL;
+    if (!b_dev) return fail(ctx, FMMBEM_EINVAL, "b is NULL");
+    GUARD_BEGIN
+    HIP_OK(hipSetDevice(ctx->device));
+    if (ctx->src.empty()) return fail(ctx, FMMBEM_ENOTREADY, "sources not set");
+    ensure_setup(ctx);
+    const int64_t n = fmmbem_num_unknowns(ctx);
+    hipStream_t caller = (hipStream_t)stream;
+    ev_record(ctx, EV_CALLER_IN, caller);
+    ev_wait(ctx, EV_CALLER_IN, ctx->stream);
+    for (size_t s = 0; s < ctx->src.size() / 3; ++s) rhs_one(ctx, (int)s, (double2 *)b_dev + s * n);
+    ev_record(ctx, EV_CALLER_DONE, ctx->stream);
+    ev_wait(ctx, EV_CALLER_DONE, caller);
     return FMMBEM_OK;
     GUARD_END
 }
@@ -1764,10 +1795,9 @@ int fmmbem_matvec_dev(fmmbem_ctx *ctx, int32_t nrhs, const void *x, void *y, int
     ensure_setup(ctx);
     const int64_t n = ctx->nt;
     hipStream_t caller = (hipStream_t)stream;
-    hipEvent_t e0 = ctx->ev[0];
     // order after the caller's stream, run on ours, then make the caller's stream wait
-    HIP_OK(hipEventRecord(e0, caller));
-    HIP_OK(hipStreamWaitEvent(ctx->stream, e0, 0));
+    ev_record(ctx, EV_CALLER_IN, caller);
+    ev_wait(ctx, EV_CALLER_IN, ctx->stream);
     if (indirect(ctx)) {
         for (int r = 0; r < nrhs; ++r)
             matvec_ind(ctx, (const double2 *)x + (int64_t)r * 2 * n, (double2 *)y + (int64_t)r * 2 * n, false,
@@ -1784,7 +1814,9 @@ int fmmbem_matvec_dev(fmmbem_ctx *ctx, int32_t nrhs, const void *x, void *y, int
     } else {
         matvec_dev(ctx, nrhs, (const double2 *)x, (double2 *)y, false, precision == FMMBEM_MIXED);
     }
-    HIP_OK(hipStreamWaitEvent(caller, ctx->ev[8], 0));
+    // the caller's stream waits for everything enqueued on ours, the copies into y included
+    ev_record(ctx, EV_CALLER_DONE, ctx->stream);
+    ev_wait(ctx, EV_CALLER_DONE, caller);
     return FMMBEM_OK;
     GUARD_END
 }
@@ -1995,7 +2027,9 @@ static int check_solve_opts(fmmbem_ctx *ctx, const fmmbem_solve_opts &o) {
     return FMMBEM_OK;
 }
 
-int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, fmmbem_c64 *x, fmmbem_solve_report *rep) {
+// x: host array (caller == nullptr) or device array ordered after / before the caller's stream
+static int solve_impl(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, void *x, bool dev,
+                      hipStream_t caller, fmmbem_solve_report *rep) {
     if (!ctx) return FMMBEM_EINVAL;
     if (!x) return fail(ctx, FMMBEM_EINVAL, "x is NULL");
     fmmbem_solve_opts o;
@@ -2043,7 +2077,11 @@ int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, f
     else if (bm) rhs_bm(ctx, isrc, b);
     else if (dp) rhs_dpsi(ctx, isrc, b);
     else rhs_dev(ctx, isrc, b);
-    if (o.use_x0) HIP_OK(hipMemcpyAsync(dx, x, sizeof(double2) * n, hipMemcpyHostToDevice, st));
+    if (dev) {
+        ev_record(ctx, EV_CALLER_IN, caller);
+        ev_wait(ctx, EV_CALLER_IN, st);
+    }
+    if (o.use_x0) HIP_OK(hipMemcpyAsync(dx, x, sizeof(double2) * n, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
     // the Krylov products run in the requested arithmetic; restart residuals always in FP64
     int64_t n64 = 0, nmx = 0;
     auto product = [&](const double2 *a, double2 *y, bool mixed) {
@@ -2114,7 +2152,11 @@ int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, f
     int status = fgmres(n, st, ctx->scratch, "", mv, mv64, outer_pc, b, dx, o.tol, o.restart, o.maxit, o.use_x0 != 0,
                         true, &ctx->history, iters, restarts, rel, &hk, b32, o.reorth);
     ctx->mlp_active = false;
-    HIP_OK(hipMemcpyAsync(x, dx, sizeof(double2) * n, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(x, dx, sizeof(double2) * n, dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+    if (dev) {
+        ev_record(ctx, EV_CALLER_DONE, st);
+        ev_wait(ctx, EV_CALLER_DONE, caller);
+    }
     HIP_OK(hipStreamSynchronize(st));
     if (rep) {
         rep->iters = iters;
@@ -2132,6 +2174,15 @@ int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, f
     if (status < 0) ctx->err = "solver failed";
     return status;
     GUARD_END
+}
+
+int fmmbem_solve(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, fmmbem_c64 *x, fmmbem_solve_report *rep) {
+    return solve_impl(ctx, isrc, opts, x, false, nullptr, rep);
+}
+
+int fmmbem_solve_dev(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opts, void *x_dev,
+                     fmmbem_solve_report *rep, void *stream) {
+    return solve_impl(ctx, isrc, opts, x_dev, true, (hipStream_t)stream, rep);
 }
 
 int fmmbem_solve_batch(fmmbem_ctx *ctx, int32_t ns, const int32_t *isrc, const fmmbem_solve_opts *opts,
@@ -2438,76 +2489,75 @@ int fmmbem_learned_train(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_train_opts 
     GUARD_END
 }
 
+// Field at nr receivers (device points pts, nr x 3) from the surface unknown x (device, caller
+// order) into psi (device), on stream st, with the two density arrays sigma, mu (n each) supplied
+// by the caller of this helper (the context's workspace or a fixed device array).
+static void eval_field_run(fmmbem_ctx *ctx, int isrc, int64_t nr, const double *pts, const double2 *x, double2 *psi,
+                           double2 *sigma, double2 *mu, hipStream_t st) {
+    const int64_t n = ctx->nt;
+    const double *rs = &ctx->src[3 * isrc];
+    const int form = indirect(ctx) ? 3 : dpsi(ctx) ? 1 : 0;
+    const double2 *bm = (const double2 *)ctx->buf.find("beta");
+    const double2 *bp = indirect(ctx) ? (const double2 *)ctx->buf.find("betap") : bm;
+    k_field_dens<<<ceil_div(n, 256), 256, 0, st>>>(n, form, (int32_t *)ctx->buf.find("perm"), x,
+                                                   (double4 *)ctx->buf.find("ec"), (double4 *)ctx->buf.find("en"), bm,
+                                                   bp, ctx->k, rs[0], rs[1], rs[2], ctx->src_amp[isrc], sigma, mu);
+    LAUNCH_OK();
+    k_field<<<(unsigned)nr, 256, 0, st>>>(n, pts, (double4 *)ctx->buf.find("ec"), (double4 *)ctx->buf.find("en"),
+                                          (double *)ctx->buf.find("ev"), sigma, mu, ctx->k, ctx->rc * ctx->rc, rs[0],
+                                          rs[1], rs[2], ctx->src_amp[isrc], psi);
+    LAUNCH_OK();
+}
+
+// checks shared by the host and device variants; 0 or an error status
+static int eval_field_prepare(fmmbem_ctx *ctx, int32_t isrc, int64_t nr) {
+    if (ctx->src.empty()) return fail(ctx, FMMBEM_ENOTREADY, "sources not set");
+    if (isrc < 0 || isrc >= (int)(ctx->src.size() / 3)) return fail(ctx, FMMBEM_EINVAL, "bad source index");
+    if (nr > 0x7fffffff) return fail(ctx, FMMBEM_EINVAL, "at most 2^31 - 1 receivers per call");
+    ensure_setup(ctx);
+    if (dpsi(ctx)) check_dpsi_beta(ctx);
+    return FMMBEM_OK;
+}
+
 int fmmbem_eval_field(fmmbem_ctx *ctx, int32_t isrc, int64_t nr, const double *r, const fmmbem_c64 *x, fmmbem_c64 *psi) {
     if (!ctx) return FMMBEM_EINVAL;
     if (!r || !x || !psi || nr < 0) return fail(ctx, FMMBEM_EINVAL, "bad arguments");
     GUARD_BEGIN
     HIP_OK(hipSetDevice(ctx->device));
-    if (ctx->src.empty()) return fail(ctx, FMMBEM_ENOTREADY, "sources not set");
-    if (isrc < 0 || isrc >= (int)(ctx->src.size() / 3)) return fail(ctx, FMMBEM_EINVAL, "bad source index");
-    ensure_setup(ctx);
+    if (int e = eval_field_prepare(ctx, isrc, nr)) return e;
     if (nr == 0) return FMMBEM_OK;
     hipStream_t st = ctx->stream;
-    const int64_t n = ctx->nt;
-    const double *rs = &ctx->src[3 * isrc];
-    if (indirect(ctx)) {
-        // sigma = g- + g+ + i k (beta- psi- + beta+ psi+), mu = psi+ - psi-  (Eq. ibem1, ibem4)
-        double2 *gm = dget<double2>(ctx->scratch, "ind_gm", n), *gp = dget<double2>(ctx->scratch, "ind_gp", n);
-        double2 *dxv = dget<double2>(ctx->scratch, "fe_x", 2 * n);
-        double2 *dsg = dget<double2>(ctx->scratch, "fe_sg", n), *dmu = dget<double2>(ctx->scratch, "fe_mu", n);
-        HIP_OK(hipMemcpyAsync(dxv, x, sizeof(double2) * 2 * n, hipMemcpyHostToDevice, st));
-        k_gamma_pm<<<ceil_div(n, 256), 256, 0, st>>>(n, (double4 *)ctx->buf.find("ec"), (double4 *)ctx->buf.find("en"),
-                                                     (double2 *)ctx->buf.find("beta"), (double2 *)ctx->buf.find("betap"),
-                                                     ctx->k, rs[0], rs[1], rs[2], ctx->src_amp[isrc], gm, gp);
-        LAUNCH_OK();
-        k_field_dens_ind<<<ceil_div(n, 256), 256, 0, st>>>(n, (int32_t *)ctx->buf.find("perm"), dxv, gm, gp,
-                                                           (double2 *)ctx->buf.find("beta"),
-                                                           (double2 *)ctx->buf.find("betap"), ctx->k, dsg, dmu);
-        LAUNCH_OK();
-        std::vector<double> pts(r, r + 3 * nr);
-        double *dp = upload(ctx->scratch, "fe_pts", pts, st);
-        double2 *dout = dget<double2>(ctx->scratch, "fe_out", nr);
-        k_field<<<(unsigned)nr, 256, 0, st>>>(n, dp, (double4 *)ctx->buf.find("ec"), (double4 *)ctx->buf.find("en"),
-                                              (double *)ctx->buf.find("ev"), dsg, dmu, ctx->k, ctx->rc * ctx->rc, rs[0],
-                                              rs[1], rs[2], ctx->src_amp[isrc], dout);
-        LAUNCH_OK();
-        HIP_OK(hipMemcpyAsync(psi, dout, sizeof(double2) * nr, hipMemcpyDeviceToHost, st));
-        HIP_OK(hipStreamSynchronize(st));
-        return FMMBEM_OK;
-    }
-    double2 *gam = dget<double2>(ctx->scratch, "fe_gam", n), *zero = dget<double2>(ctx->scratch, "fe_zero", n);
-    k_gamma<<<ceil_div(n, 256), 256, 0, st>>>(n, (double4 *)ctx->buf.find("ec"), (double4 *)ctx->buf.find("en"),
-                                              (double2 *)ctx->buf.find("beta"), ctx->k, rs[0], rs[1], rs[2],
-                                              ctx->src_amp[isrc], gam, zero);
-    LAUNCH_OK();
-    // sigma = gamma + i k beta x, mu = -x  (sorted order); Eq. (dbem5)'s unknown is the normal
-    // derivative v = sigma itself, with x = psi_sc = (v - gamma) / (i k beta)
-    std::vector<double2> xs(n), g(n), bet(n), sg(n), mu(n);
-    HIP_OK(hipMemcpyAsync(g.data(), gam, sizeof(double2) * n, hipMemcpyDeviceToHost, st));
-    HIP_OK(hipStreamSynchronize(st));
-    if (dpsi(ctx)) check_dpsi_beta(ctx);
-    for (int64_t i = 0; i < n; ++i) {
-        int j = ctx->tree.perm[i];
-        double2 xi = cmk(x[j].re, x[j].im), be = ctx->beta[j];
-        const double2 ikb = cmk(-ctx->k * be.y, ctx->k * be.x);
-        if (dpsi(ctx)) {
-            sg[i] = xi;
-            mu[i] = cscale(cdiv(csub(xi, g[i]), ikb), -1.0);
-        } else {
-            sg[i] = cadd(g[i], cmul(ikb, xi));
-            mu[i] = cscale(xi, -1.0);
-        }
-    }
-    double2 *dsg = upload(ctx->scratch, "fe_sg", sg, st), *dmu = upload(ctx->scratch, "fe_mu", mu, st);
-    std::vector<double> pts(r, r + 3 * nr);
-    double *dp = upload(ctx->scratch, "fe_pts", pts, st);
+    const int64_t n = ctx->nt, nu = fmmbem_num_unknowns(ctx);
+    double2 *dx = dget<double2>(ctx->scratch, "fe_x", nu);
+    double *dp = dget<double>(ctx->scratch, "fe_pts", 3 * nr);
     double2 *dout = dget<double2>(ctx->scratch, "fe_out", nr);
-    k_field<<<(unsigned)nr, 256, 0, st>>>(n, dp, (double4 *)ctx->buf.find("ec"), (double4 *)ctx->buf.find("en"),
-                                          (double *)ctx->buf.find("ev"), dsg, dmu, ctx->k, ctx->rc * ctx->rc, rs[0],
-                                          rs[1], rs[2], ctx->src_amp[isrc], dout);
-    LAUNCH_OK();
+    double2 *dsg = dget<double2>(ctx->scratch, "fe_sg", n), *dmu = dget<double2>(ctx->scratch, "fe_mu", n);
+    h2d_now(dx, x, sizeof(double2) * nu, st);
+    h2d_now(dp, r, sizeof(double) * 3 * nr, st);
+    eval_field_run(ctx, isrc, nr, dp, dx, dout, dsg, dmu, st);
     HIP_OK(hipMemcpyAsync(psi, dout, sizeof(double2) * nr, hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
+    return FMMBEM_OK;
+    GUARD_END
+}
+
+int fmmbem_eval_field_dev(fmmbem_ctx *ctx, int32_t isrc, int64_t nr, const void *r_dev, const void *x_dev,
+                          void *psi_dev, void *stream) {
+    if (!ctx) return FMMBEM_EINVAL;
+    if (!r_dev || !x_dev || !psi_dev || nr < 0) return fail(ctx, FMMBEM_EINVAL, "bad arguments");
+    GUARD_BEGIN
+    HIP_OK(hipSetDevice(ctx->device));
+    if (int e = eval_field_prepare(ctx, isrc, nr)) return e;
+    if (nr == 0) return FMMBEM_OK;
+    const int64_t n = ctx->nt;
+    double2 *dsg = dget<double2>(ctx->scratch, "fe_sg", n), *dmu = dget<double2>(ctx->scratch, "fe_mu", n);
+    hipStream_t caller = (hipStream_t)stream;
+    ev_record(ctx, EV_CALLER_IN, caller);
+    ev_wait(ctx, EV_CALLER_IN, ctx->stream);
+    eval_field_run(ctx, isrc, nr, (const double *)r_dev, (const double2 *)x_dev, (double2 *)psi_dev, dsg, dmu,
+                   ctx->stream);
+    ev_record(ctx, EV_CALLER_DONE, ctx->stream);
+    ev_wait(ctx, EV_CALLER_DONE, caller);
     return FMMBEM_OK;
     GUARD_END
 }

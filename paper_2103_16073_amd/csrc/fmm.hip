@@ -1026,6 +1026,46 @@ __global__ void k_field_dens_ind(int64_t n, const int32_t *perm, const double2 *
     mu[i] = csub(pp, pm);
 }
 
+// Densities of the receiver formula from the surface unknown x (caller order), in tree order, with
+// the incident field of a monopole of amplitude amp at s evaluated at each centroid (Eq. sp6-sp7):
+//   form 0, unknown psi_sc (Eq. dbem4 and the combined form): sigma = gamma + i k beta x,
+//           mu = -x (Eq. dbem1), gamma = -dpsi_in/dn + i k beta psi_in;
+//   form 1, unknown v = dpsi_sc/dn (Eq. dbem5): sigma = v, mu = -psi_sc = -(v - gamma)/(i k beta);
+//   form 3, unknowns (psi-, psi+) (Eq. ibem5): sigma = g- + g+ + i k (beta- psi- + beta+ psi+),
+//           mu = psi+ - psi- (Eq. ibem1, ibem4), g-+ = -+ dpsi_in/dn + i k beta-+ psi_in.
+__global__ void k_field_dens(int64_t n, int form, const int32_t *perm, const double2 *x, const double4 *ec,
+                             const double4 *en, const double2 *bm, const double2 *bp, double k, double sx, double sy,
+                             double sz, double2 amp, double2 *sigma, double2 *mu) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double4 c = ec[i], nv = en[i];
+    const double dx = c.x - sx, dy = c.y - sy, dz = c.z - sz;
+    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    double s, co;
+    sincos(k * r, &s, &co);
+    const double2 G = cmul(amp, cmk(co / (4 * FMM_PI * r), s / (4 * FMM_PI * r)));
+    const double proj = (dx * nv.x + dy * nv.y + dz * nv.z) / (r * r);
+    const double2 dG = cscale(cmul(G, cmk(-1.0, k * r)), proj);  // dpsi_in/dn
+    const int64_t u = perm[i];
+    const double2 ikbm = cmk(-k * bm[i].y, k * bm[i].x);
+    const double2 gm = csub(cmul(ikbm, G), dG);
+    if (form == 3) {
+        const double2 ikbp = cmk(-k * bp[i].y, k * bp[i].x);
+        const double2 gp = cadd(cmul(ikbp, G), dG);
+        const double2 pm = x[u], pp = x[n + u];
+        sigma[i] = cadd(cadd(gm, gp), cadd(cmul(ikbm, pm), cmul(ikbp, pp)));
+        mu[i] = csub(pp, pm);
+    } else if (form == 1) {
+        const double2 v = x[u];
+        sigma[i] = v;
+        mu[i] = cscale(cdiv(csub(v, gm), ikbm), -1.0);
+    } else {
+        const double2 xi = x[u];
+        sigma[i] = cadd(gm, cmul(ikbm, xi));
+        mu[i] = cscale(xi, -1.0);
+    }
+}
+
 // row 2 of the right-hand side gets (g+ - g-)/2
 __global__ void k_rhs_ind_local(int64_t n, const int32_t *perm, const double2 *gm, const double2 *gp, double2 *b) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -92,12 +92,17 @@ EXPORTS = {
     "fmmbem_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "fmmbem_set_mesh": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     "fmmbem_set_wavenumber": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double]),
-    "fmmbem_set_admittance": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "fmmbem_set_admittance": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "fmmbem_set_sources": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "fmmbem_set_formulation": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "fmmbem_setup": (ctypes.c_int, [ctypes.c_void_p]),
     "fmmbem_num_unknowns": (ctypes.c_int64, [ctypes.c_void_p]),
     "fmmbem_rhs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "fmmbem_rhs_dev": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "fmmbem_solve_dev": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(SolveOpts), ctypes.c_void_p,
+                                        ctypes.POINTER(SolveReport), ctypes.c_void_p]),
+    "fmmbem_eval_field_dev": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "fmmbem_solve_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(SolveOpts),
                                           ctypes.c_void_p, ctypes.c_void_p]),
     "fmmbem_release_workspace": (ctypes.c_int, [ctypes.c_void_p]),
@@ -106,7 +111,6 @@ EXPORTS = {
     "fmmbem_set_batch_shapes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "fmmbem_solve_many": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]),
-    "fmmbem_set_admittance_plus": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "fmmbem_near_entries_n": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p,
                                              ctypes.c_void_p]),
     "fmmbem_default_train_opts": (None, [ctypes.c_void_p]),
@@ -220,9 +224,10 @@ class Context:
     def fmmbem_set_wavenumber(self, k):
         self._check(lib().fmmbem_set_wavenumber(self.h, float(k)))
 
-    def fmmbem_set_admittance(self, beta):
+    def fmmbem_set_admittance(self, beta, beta_plus=None):
         b = _c(beta)
-        self._check(lib().fmmbem_set_admittance(self.h, _ptr(b)))
+        bp = None if beta_plus is None else _c(beta_plus)
+        self._check(lib().fmmbem_set_admittance(self.h, _ptr(b), None if bp is None else _ptr(bp)))
 
     def fmmbem_set_sources(self, rs, amp=None):
         rs = np.ascontiguousarray(np.atleast_2d(rs), np.float64)
@@ -255,6 +260,23 @@ class Context:
     def fmmbem_matvec_dev(self, x_ptr: int, y_ptr: int, nrhs=1, precision=FMMBEM_FP64, stream: int = 0):
         self._check(lib().fmmbem_matvec_dev(self.h, nrhs, ctypes.c_void_p(x_ptr), ctypes.c_void_p(y_ptr),
                                             int(precision), ctypes.c_void_p(stream)))
+
+    def fmmbem_rhs_dev(self, b_ptr: int, stream: int = 0):
+        self._check(lib().fmmbem_rhs_dev(self.h, ctypes.c_void_p(b_ptr), ctypes.c_void_p(stream)))
+
+    def fmmbem_solve_dev(self, isrc, x_ptr: int, use_x0=False, stream: int = 0, **kw):
+        o = default_solve_opts()
+        for k, v in kw.items():
+            setattr(o, k, v)
+        o.use_x0 = int(bool(use_x0))
+        rep = SolveReport()
+        rc = self._check(lib().fmmbem_solve_dev(self.h, isrc, ctypes.byref(o), ctypes.c_void_p(x_ptr),
+                                                ctypes.byref(rep), ctypes.c_void_p(stream)))
+        return rep, rc
+
+    def fmmbem_eval_field_dev(self, isrc, nr, r_ptr: int, x_ptr: int, psi_ptr: int, stream: int = 0):
+        self._check(lib().fmmbem_eval_field_dev(self.h, isrc, int(nr), ctypes.c_void_p(r_ptr), ctypes.c_void_p(x_ptr),
+                                                ctypes.c_void_p(psi_ptr), ctypes.c_void_p(stream)))
 
     def fmmbem_solve(self, isrc=0, x0=None, **kw):
         o = default_solve_opts()
@@ -322,13 +344,6 @@ class Context:
         g = np.empty(self.fmmbem_mlp_param_count(), np.float32)
         self._check(lib().fmmbem_mlp_loss_grad(self.h, X.shape[0], _ptr(X), _ptr(T), _ptr(loss), _ptr(g)))
         return float(loss[0]), g
-
-    def fmmbem_set_admittance_plus(self, beta_plus=None):
-        if beta_plus is None:
-            self._check(lib().fmmbem_set_admittance_plus(self.h, None))
-        else:
-            b = _c(beta_plus)
-            self._check(lib().fmmbem_set_admittance_plus(self.h, _ptr(b)))
 
     def fmmbem_near_entries_n(self):
         nnz = ctypes.c_int64()

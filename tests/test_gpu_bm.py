@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 from oracle import bem
+from rc_check import oracle_rc
 from paper_2103_16073_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -39,7 +40,7 @@ def test_bm_product_vs_dense(F, room1, leaf_max):
     room, k = room1
     ctx = make_ctx(F, room, k, leaf_max=leaf_max)
     assert ctx.fmmbem_num_unknowns() == room.n
-    rc = ctx.fmmbem_get_info().rc
+    rc = oracle_rc(ctx, room)
     A, _, _ = bem.bm_system(room.vertices, room.triangles, k, room.beta, np.array([1.0, 1.0, 1.0]), rc)
     for seed in (1, 2):
         x = synth.complex_normal(room.n, seed)
@@ -60,7 +61,7 @@ def test_bm_rhs_vs_oracle(F, room1):
     rs, _ = synth.source_and_receivers(room, 4)
     ctx = make_ctx(F, room, k, rs=rs)
     b = ctx.fmmbem_rhs()[0]
-    rc = ctx.fmmbem_get_info().rc
+    rc = oracle_rc(ctx, room)
     rows = np.arange(0, room.n, 7)
     ref = bem.bm_rhs_rows(room.vertices, room.triangles, k, room.beta, rs[0], rc, rows)
     assert np.linalg.norm(b[rows] - ref) / np.linalg.norm(ref) < 1e-6
@@ -79,7 +80,7 @@ def test_bm_solve_and_field_vs_lu(F, room1, precision):
     ctx = make_ctx(F, room, k, rs=rs)
     x, rep, rc_ = ctx.fmmbem_solve(0, tol=1e-8, restart=300, maxit=900, precond=F.FMMBEM_PC_DIAG,
                                    precision=precision)
-    rc = ctx.fmmbem_get_info().rc
+    rc = oracle_rc(ctx, room)
     A, b, _ = bem.bm_system(room.vertices, room.triangles, k, room.beta, rs[0], rc)
     x_ref = bem.solve_lu(A, b)
     ex = np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref)

@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 from oracle import bem
+from rc_check import oracle_rc
 from paper_2103_16073_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -37,7 +38,7 @@ def make_ctx(F, room, k, beta, form, rs=None, **opt):
 def test_dpsi_product_vs_dense(F, room1, leaf_max):
     room, k = room1
     ctx = make_ctx(F, room, k, room.beta, F.FMMBEM_DIRECT_DPSI, leaf_max=leaf_max)
-    rc = ctx.fmmbem_get_info().rc
+    rc = oracle_rc(ctx, room)
     A, _, _ = bem.dpsi_system(room.vertices, room.triangles, k, room.beta, np.array([1.0, 1.0, 1.0]), rc)
     for seed in (1, 2):
         v = synth.complex_normal(room.n, seed)
@@ -56,7 +57,7 @@ def test_dpsi_rhs_vs_oracle_and_zero_beta_rejected(F, room1):
     rs, _ = synth.source_and_receivers(room, 4)
     ctx = make_ctx(F, room, k, room.beta, F.FMMBEM_DIRECT_DPSI, rs=rs)
     b = ctx.fmmbem_rhs()[0]
-    rc = ctx.fmmbem_get_info().rc
+    rc = oracle_rc(ctx, room)
     rows = np.arange(0, room.n, 7)
     ref = bem.dpsi_rhs_rows(room.vertices, room.triangles, k, room.beta, rs[0], rc, rows)
     assert np.linalg.norm(b[rows] - ref) / np.linalg.norm(ref) < 1e-6
@@ -78,7 +79,7 @@ def test_dpsi_solve_and_field_vs_lu(F, room1, precond, precision):
     rs, rec = synth.source_and_receivers(room, 16)
     ctx = make_ctx(F, room, k, room.beta, F.FMMBEM_DIRECT_DPSI, rs=rs)
     v, rep, rc_ = ctx.fmmbem_solve(0, tol=1e-8, restart=200, maxit=600, precond=precond, precision=precision)
-    rc = ctx.fmmbem_get_info().rc
+    rc = oracle_rc(ctx, room)
     A, b, _ = bem.dpsi_system(room.vertices, room.triangles, k, room.beta, rs[0], rc)
     v_ref = bem.solve_lu(A, b)
     ev = np.linalg.norm(v - v_ref) / np.linalg.norm(v_ref)

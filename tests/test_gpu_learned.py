@@ -5,6 +5,7 @@ import pytest
 
 from mlp_ref import forward as ref_forward, loss_grad as ref_loss_grad
 from oracle import bem
+from rc_check import oracle_rc
 from paper_2103_16073_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -87,7 +88,7 @@ def test_training_reduces_loss_and_solves(F):
     assert rep.loss_last < rep.loss_first
     x, srep, rc_ = ctx.fmmbem_solve(0, tol=1e-8, restart=60, maxit=300, precond=F.FMMBEM_PC_LEARNED)
     assert rc_ == 0 and srep.rel_res < 1e-8
-    rc = ctx.fmmbem_get_info().rc
+    rc = oracle_rc(ctx, room)
     A, b, _, _ = bem.direct_system(room.vertices, room.triangles, k, room.beta, rs[0], rc)
     x_ref = bem.solve_lu(A, b)
     assert np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref) < 1e-5

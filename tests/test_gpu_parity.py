@@ -3,6 +3,7 @@ import numpy as np
 import pytest
 
 from oracle import bem
+from rc_check import oracle_rc
 from oracle import coeffs as OC
 from paper_2103_16073_amd import synth
 
@@ -86,7 +87,7 @@ def test_near_entries_vs_oracle(F):
     k = synth.wavenumber(250.0)
     ctx = make_ctx(F, room, k)
     rows, cols, L, M = ctx.fmmbem_near_entries()
-    rc = ctx.fmmbem_get_info().rc
+    rc = oracle_rc(ctx, room)
     c, _, _ = bem.geometry(room.vertices, room.triangles)
     # same pair set as the oracle's classification
     d2 = ((c[:, None, :] - c[None, :, :]) ** 2).sum(-1)
@@ -114,7 +115,7 @@ def cfg1_dense():
 def test_matvec_exact_far_vs_dense(F, cfg1_dense):
     room, k = cfg1_dense
     ctx = make_ctx(F, room, k)
-    rc = ctx.fmmbem_get_info().rc
+    rc = oracle_rc(ctx, room)
     L, M = bem.dense_LM(room.vertices, room.triangles, k, rc)
     for seed in (1, 2):
         x = synth.complex_normal(room.n, seed)
@@ -132,7 +133,7 @@ def test_solve_gram_schmidt_passes_vs_oracle_lu(F, cfg1_dense, reorth):
     ctx = make_ctx(F, room, k)
     rs, _ = synth.source_and_receivers(room, 4, nsrc=2)
     ctx.fmmbem_set_sources(rs)
-    rc = ctx.fmmbem_get_info().rc
+    rc = oracle_rc(ctx, room)
     kw = dict(tol=1e-8, restart=200, maxit=200, precond=F.FMMBEM_PC_NEARBLOCK, reorth=reorth)
     x, rep, rc_ = ctx.fmmbem_solve(0, **kw)
     X, reps, rcb = ctx.fmmbem_solve_batch([0, 1], **kw)
@@ -155,7 +156,7 @@ def test_solve_inner_coarse_fmm_vs_oracle_lu(F, cfg1_dense):
     ctx = make_ctx(F, room, k)
     rs, _ = synth.source_and_receivers(room, 4)
     ctx.fmmbem_set_sources(rs)
-    rc = ctx.fmmbem_get_info().rc
+    rc = oracle_rc(ctx, room)
     for beta in (room.beta, 0.5 * room.beta + 0.05):
         ctx.fmmbem_set_admittance(beta)
         x, rep, rc_ = ctx.fmmbem_solve(0, tol=1e-8, restart=20, maxit=60, inner_iters=8, inner_tol=1e-2,
@@ -219,7 +220,7 @@ def test_matvec_fmm_vs_dense(F, cfg1_dense, leaf_max, lds_budget, lane, mfma, fu
     if fused:
         assert any(s["mfma"] == 2 for s in ctx.fmmbem_batch_shapes())
     info = ctx.fmmbem_get_info()
-    L, M = bem.dense_LM(room.vertices, room.triangles, k, info.rc)
+    L, M = bem.dense_LM(room.vertices, room.triangles, k, oracle_rc(ctx, room))
     for seed in (1, 2):
         x = synth.complex_normal(room.n, seed)
         ref = 0.5 * x + M @ x - 1j * k * L @ (room.beta * x)
@@ -239,7 +240,7 @@ def test_matvec_mixed_vs_dense(F, cfg1_dense, leaf_max, lds_budget, lane, mfma, 
     room, k = cfg1_dense
     ctx = make_ctx(F, room, k, leaf_max=leaf_max, lds_budget=lds_budget, lane_tiles=lane, mfma=mfma, fused=fused)
     info = ctx.fmmbem_get_info()
-    L, M = bem.dense_LM(room.vertices, room.triangles, k, info.rc)
+    L, M = bem.dense_LM(room.vertices, room.triangles, k, oracle_rc(ctx, room))
     for seed in (1, 2):
         x = synth.complex_normal(room.n, seed)
         ref = 0.5 * x + M @ x - 1j * k * L @ (room.beta * x)
@@ -268,7 +269,7 @@ def test_matvec_large_leaf_p_vs_dense(F, cfg1_dense, kk, leaf_max, p_min, p_leaf
     ctx = make_ctx(F, room, k, leaf_max=leaf_max, p_min=p_min)
     info = ctx.fmmbem_get_info()
     assert info.p[info.depth] >= p_leaf
-    L, M = bem.dense_LM(room.vertices, room.triangles, k, info.rc)
+    L, M = bem.dense_LM(room.vertices, room.triangles, k, oracle_rc(ctx, room))
     X = np.stack([synth.complex_normal(room.n, 60 + s) for s in range(4)])
     Y = ctx.fmmbem_matvec(X)
     y1 = ctx.fmmbem_matvec(X[0])[0]
@@ -291,7 +292,7 @@ def test_solve_mixed_inner_vs_oracle_lu(F, cfg1_dense):
     x, rep, rc_ = ctx.fmmbem_solve(0, tol=1e-8, restart=40, maxit=400, precision=F.FMMBEM_MIXED)
     print(f"mixed-inner solve: iters {rep.iters} restarts {rep.restarts} rel {rep.rel_res:.2e}")
     assert rc_ == 0 and rep.rel_res < 1e-8
-    rc = ctx.fmmbem_get_info().rc
+    rc = oracle_rc(ctx, room)
     A, b, _, _ = bem.direct_system(room.vertices, room.triangles, k, room.beta, rs[0], rc)
     x_ref = bem.solve_lu(A, b)
     assert np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref) < 1e-5
@@ -307,7 +308,7 @@ def test_solve_fp32_basis_vs_fp64_basis(F, cfg1_dense, batched):
     ctx = make_ctx(F, room, k)
     rs, _ = synth.source_and_receivers(room, 4, nsrc=2)
     ctx.fmmbem_set_sources(rs)
-    rc = ctx.fmmbem_get_info().rc
+    rc = oracle_rc(ctx, room)
     A, b, _, _ = bem.direct_system(room.vertices, room.triangles, k, room.beta, rs[1], rc)
     x_ref = bem.solve_lu(A, b)
     its = {}
@@ -341,7 +342,7 @@ def test_solve_inner_outer_vs_oracle_lu(F, cfg1_dense):
     assert rc_ == 0 and rep.rel_res < 1e-8
     assert len(hist) == rep.iters and rep.matvecs_mixed == rep.inner_iters > 0
     assert rep.matvecs_fp64 == rep.iters + rep.restarts
-    rc = ctx.fmmbem_get_info().rc
+    rc = oracle_rc(ctx, room)
     A, b, _, _ = bem.direct_system(room.vertices, room.triangles, k, room.beta, rs[0], rc)
     x_ref = bem.solve_lu(A, b)
     assert np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref) < 1e-5
@@ -357,7 +358,7 @@ def test_matvec_multi_rhs(F, cfg1_dense, leaf_max, lds_budget, lane, mfma, fused
     room, k = cfg1_dense
     ctx = make_ctx(F, room, k, leaf_max=leaf_max, lds_budget=lds_budget, lane_tiles=lane, mfma=mfma, fused=fused)
     info = ctx.fmmbem_get_info()
-    L, M = bem.dense_LM(room.vertices, room.triangles, k, info.rc)
+    L, M = bem.dense_LM(room.vertices, room.triangles, k, oracle_rc(ctx, room))
     X = np.stack([synth.complex_normal(room.n, 20 + s) for s in range(7)])
     for prec, tol_single, tol_oracle in ((F.FMMBEM_FP64, 1e-12, 1e-6), (F.FMMBEM_MIXED, 1e-6, 1e-4)):
         Y = ctx.fmmbem_matvec(X, precision=prec)
@@ -384,7 +385,7 @@ def test_solve_batch_vs_single_and_lu(F, cfg1_dense):
     srcs = [0, 1, 2]
     Xb, reps, rc_ = ctx.fmmbem_solve_batch(srcs, tol=1e-8, restart=40, maxit=300)
     assert rc_ == 0
-    rc = ctx.fmmbem_get_info().rc
+    rc = oracle_rc(ctx, room)
     for s in srcs:
         assert reps[s].status == 0 and reps[s].rel_res < 1e-8
         x1, rep1, rc1 = ctx.fmmbem_solve(s, tol=1e-8, restart=40, maxit=300)
@@ -421,6 +422,34 @@ def test_matvec_graph_replays_match_eager(F, cfg1_dense, nr, prec):
         ctx.fmmbem_matvec(X[:1], precision=prec)
         ctx.fmmbem_matvec_dev(other.data_ptr(), oy.data_ptr(), nrhs=2, precision=1 - prec)
         torch.cuda.synchronize()
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("graphs", [0, 1])
+def test_matvec_dev_orders_the_callers_stream(F, cfg1_dense, prec, graphs):
+    """fmmbem_matvec_dev on a side stream: work enqueued afterwards on that same stream sees the
+    finished product (output first filled with NaN, consumed on the stream with no device-wide
+    synchronisation), eager and graph-replayed, equal to the host entry point's product."""
+    import torch
+    room, k = cfg1_dense
+    ctx = make_ctx(F, room, k, leaf_max=12, graphs=graphs)
+    X = np.stack([synth.complex_normal(room.n, 50 + s) for s in range(2)])
+    ref = ctx.fmmbem_matvec(X, precision=prec)
+    st = torch.cuda.Stream()
+    xd = torch.from_numpy(X).to("cuda")
+    torch.cuda.synchronize()
+    for rep in range(3):
+        with torch.cuda.stream(st):
+            yd = torch.full_like(xd, complex("nan+nanj"))
+            ctx.fmmbem_matvec_dev(xd.data_ptr(), yd.data_ptr(), nrhs=2, precision=prec, stream=st.cuda_stream)
+            z = yd * 1.0  # consumer on the caller's stream
+            zh = torch.empty(z.shape, dtype=z.dtype, pin_memory=True)
+            zh.copy_(z, non_blocking=True)
+        st.synchronize()
+        got = zh.numpy()
+        assert np.isfinite(got).all(), rep
+        assert np.linalg.norm(got - ref) <= 1e-13 * np.linalg.norm(ref), rep
     ctx.close()
 
 
@@ -532,7 +561,7 @@ def test_autotuned_tiles_vs_dense(F, cfg1_dense):
     print("tile shapes:", [(s["level"], s["kind"], s["lane"], s["whole"], s["jt"], round(s["ms"], 3)) for s in shapes])
     assert len(shapes) > 0 and all(s["ms"] > 0 for s in shapes)
     info = ctx.fmmbem_get_info()
-    L, M = bem.dense_LM(room.vertices, room.triangles, k, info.rc)
+    L, M = bem.dense_LM(room.vertices, room.triangles, k, oracle_rc(ctx, room))
     X = np.stack([synth.complex_normal(room.n, 60 + s) for s in range(3)])
     ref = np.stack([0.5 * x + M @ x - 1j * k * L @ (room.beta * x) for x in X])
     for prec, tol in ((F.FMMBEM_FP64, 1e-6), (F.FMMBEM_MIXED, 1e-4)):
@@ -548,7 +577,7 @@ def test_rhs_vs_oracle(F, cfg1_dense):
     rs, _ = synth.source_and_receivers(room, 4)
     ctx.fmmbem_set_sources(rs)
     b = ctx.fmmbem_rhs()[0]
-    rc = ctx.fmmbem_get_info().rc
+    rc = oracle_rc(ctx, room)
     rows = np.arange(0, room.n, 5)
     ref = bem.direct_rhs_rows(room.vertices, room.triangles, k, room.beta, rs[0], rc, rows)
     assert np.linalg.norm(b[rows] - ref) / np.linalg.norm(ref) < 1e-6
@@ -562,7 +591,7 @@ def test_solve_and_field_vs_oracle_lu(F, cfg1_dense):
     ctx.fmmbem_set_sources(rs)
     x, rep, rc_ = ctx.fmmbem_solve(0, tol=1e-9, restart=40, maxit=300)
     assert rc_ == 0 and rep.rel_res < 1e-9
-    rc = ctx.fmmbem_get_info().rc
+    rc = oracle_rc(ctx, room)
     A, b, _, _ = bem.direct_system(room.vertices, room.triangles, k, room.beta, rs[0], rc)
     x_ref = bem.solve_lu(A, b)
     assert np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref) < 1e-5
@@ -572,7 +601,7 @@ def test_solve_and_field_vs_oracle_lu(F, cfg1_dense):
     ctx.close()
 
 
-@pytest.mark.parametrize("cfg,nrows", [(2, 96), (3, 64)])
+@pytest.mark.parametrize("cfg,nrows", [(2, 1024), (3, 1024)])
 def test_matvec_fmm_sampled_rows_full_size(F, cfg, nrows):
     """Full-size rooms (N = 90,972 at 1 kHz; N = 1,009,576 at 2.5 kHz): the FMM product on seeded
     rows against the oracle's matrix-free rows, relative L2 <= 1e-6 in FP64 and <= 1e-4 mixed."""
@@ -582,7 +611,7 @@ def test_matvec_fmm_sampled_rows_full_size(F, cfg, nrows):
     x = synth.complex_normal(room.n, 11)
     y = ctx.fmmbem_matvec(x)[0]
     rows = np.random.default_rng(5).choice(room.n, nrows, replace=False)
-    ref = bem.direct_matvec_rows(room.vertices, room.triangles, k, room.beta, info.rc, x, rows)
+    ref = bem.direct_matvec_rows(room.vertices, room.triangles, k, room.beta, oracle_rc(ctx, room), x, rows)
     err = np.linalg.norm(y[rows] - ref) / np.linalg.norm(ref)
     ym = ctx.fmmbem_matvec(x, precision=F.FMMBEM_MIXED)[0]
     err_m = np.linalg.norm(ym[rows] - ref) / np.linalg.norm(ref)
@@ -610,8 +639,8 @@ def test_matvec_sampled_rows_bench_configuration(F):
             ctx.fmmbem_set_batch_shapes(json.load(fh))
     info = ctx.fmmbem_get_info()
     x = synth.complex_normal(room.n, 11)
-    rows = np.random.default_rng(5).choice(room.n, 64, replace=False)
-    ref = bem.direct_matvec_rows(room.vertices, room.triangles, k, room.beta, info.rc, x, rows)
+    rows = np.random.default_rng(5).choice(room.n, 1024, replace=False)
+    ref = bem.direct_matvec_rows(room.vertices, room.triangles, k, room.beta, oracle_rc(ctx, room), x, rows)
     st = torch.cuda.Stream()
     xd = torch.from_numpy(x).to("cuda")
     yd = torch.empty_like(xd)

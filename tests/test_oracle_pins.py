@@ -13,8 +13,7 @@ from paper_2103_16073_amd import synth
 
 
 def rc_for(V, T, factor=1.8):
-    c, n, a = bem.geometry(V, T)
-    return factor * np.sqrt(2.0 * a.mean())
+    return bem.near_cutoff(V, T, factor)
 
 
 # ----------------------------------------------------------------------------- quadrature pins
