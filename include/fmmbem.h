@@ -369,6 +369,18 @@ int fmmbem_eval_field(fmmbem_ctx *ctx, int32_t isrc, int64_t nr, const double *r
 int fmmbem_eval_field_dev(fmmbem_ctx *ctx, int32_t isrc, int64_t nr, const void *r_dev, const void *x_dev,
                           void *psi_dev, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): fmmbem_eval_field_dev with its two density arrays in a
+ * fixed device array of the library (32 MiB, held by every device the library runs on until the
+ * process ends) instead of the context's workspace.  It calls no hipMalloc, hipFree or other
+ * allocating routine and builds nothing: the context must be set up already (fmmbem_setup, or any
+ * earlier product, solve or field call, after the last setter), else FMMBEM_ENOTREADY.  At most
+ * 1,048,576 elements (FMMBEM_EINVAL beyond).  Arguments, stream ordering and results are those of
+ * fmmbem_eval_field_dev.  All calls on one device share the array: calls that overlap on one
+ * device (two host threads, or streams not ordered with each other) race and give wrong fields. */
+int fmmbem_eval_field_noalloc(fmmbem_ctx *ctx, int32_t isrc, int64_t nr, const void *r_dev, const void *x_dev,
+                              void *psi_dev, void *stream);
+
 /* ---- inspection (tests, benchmarks) ---------------------------------------------------- */
 
 typedef struct {

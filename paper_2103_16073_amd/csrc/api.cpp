@@ -9,6 +9,7 @@
 #include "internal.h"
 
 #include <atomic>
+#include <mutex>
 #include <set>
 #include <thread>
 
@@ -1401,6 +1402,32 @@ static void apply_operator(fmmbem_ctx *c, const double2 *x, double2 *y, bool mix
 
 using namespace fmm;
 
+// ------------------------------------------------------------------ fixed field workspace
+// Device workspace of fmmbem_eval_field_noalloc: the receiver formula's two density arrays
+// (sigma, mu) for at most NOALLOC_MAX_N elements, 32 MiB.  Every device the library runs on holds
+// its own copy until the process ends.  Host code never uses the array's name as an address: the
+// address on each device comes from hipGetSymbolAddress, taken once per device at context creation
+// with that device current.
+static constexpr int64_t NOALLOC_MAX_N = (int64_t)1 << 20;
+static __device__ __align__(256) double2 scratch[2 * NOALLOC_MAX_N];
+static std::mutex g_noalloc_mu;
+static std::map<int, double2 *> g_noalloc_ptr;  // device -> address of `scratch` there
+
+// with `device` current
+static void noalloc_init(int device) {
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (g_noalloc_ptr.count(device)) return;
+    double2 *ptr = nullptr;
+    HIP_OK(hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch)));
+    g_noalloc_ptr[device] = ptr;
+}
+
+static double2 *noalloc_scratch(int device) {
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    auto it = g_noalloc_ptr.find(device);
+    return it == g_noalloc_ptr.end() ? nullptr : it->second;
+}
+
 // The coarser FMM of the inner GMRES (Section 4.3): a context of its own with the truncation rule's
 // p_min and excess replaced, on the same inputs; rebuilt when those change.
 static fmmbem_ctx *ensure_inner(fmmbem_ctx *c, int p_min, double p_excess) {
@@ -1549,6 +1576,8 @@ int fmmbem_create(fmmbem_ctx **out, int hip_device, const fmmbem_options *opt) {
             }
         }
         for (auto &e : ctx->ev) HIP_OK(hipEventCreate(&e));
+        (void)fj_event(ctx, EV_CALLER_DONE);  // every fork/join and caller event exists from here on
+        noalloc_init(hip_device);
         *out = ctx;
         return FMMBEM_OK;
     } catch (const FmmError &e) {
@@ -2537,6 +2566,36 @@ int fmmbem_eval_field(fmmbem_ctx *ctx, int32_t isrc, int64_t nr, const double *r
     eval_field_run(ctx, isrc, nr, dp, dx, dout, dsg, dmu, st);
     HIP_OK(hipMemcpyAsync(psi, dout, sizeof(double2) * nr, hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
+    return FMMBEM_OK;
+    GUARD_END
+}
+
+int fmmbem_eval_field_noalloc(fmmbem_ctx *ctx, int32_t isrc, int64_t nr, const void *r_dev, const void *x_dev,
+                              void *psi_dev, void *stream) {
+    if (!ctx) return FMMBEM_EINVAL;
+    if (!r_dev || !x_dev || !psi_dev || nr < 0) return fail(ctx, FMMBEM_EINVAL, "bad arguments");
+    if (nr > 0x7fffffff) return fail(ctx, FMMBEM_EINVAL, "at most 2^31 - 1 receivers per call");
+    if (!ctx->have_mesh) return fail(ctx, FMMBEM_ENOTREADY, "mesh not set");
+    if (ctx->nt > NOALLOC_MAX_N)
+        return fail(ctx, FMMBEM_EINVAL, "fmmbem_eval_field_noalloc takes at most 1048576 elements (" +
+                                            std::to_string(ctx->nt) + " given)");
+    if (ctx->mesh_dirty || ctx->k_dirty || ctx->beta_dirty || !ctx->have_k)
+        return fail(ctx, FMMBEM_ENOTREADY, "set up first (fmmbem_setup): this call builds nothing");
+    if (ctx->src.empty()) return fail(ctx, FMMBEM_ENOTREADY, "sources not set");
+    if (isrc < 0 || isrc >= (int)(ctx->src.size() / 3)) return fail(ctx, FMMBEM_EINVAL, "bad source index");
+    GUARD_BEGIN
+    if (dpsi(ctx)) check_dpsi_beta(ctx);
+    if (nr == 0) return FMMBEM_OK;
+    HIP_OK(hipSetDevice(ctx->device));
+    double2 *ws = noalloc_scratch(ctx->device);
+    if (!ws) return fail(ctx, FMMBEM_EDEVICE, "no fixed workspace on this device");
+    hipStream_t caller = (hipStream_t)stream;
+    ev_record(ctx, EV_CALLER_IN, caller);
+    ev_wait(ctx, EV_CALLER_IN, ctx->stream);
+    eval_field_run(ctx, isrc, nr, (const double *)r_dev, (const double2 *)x_dev, (double2 *)psi_dev, ws,
+                   ws + NOALLOC_MAX_N, ctx->stream);
+    ev_record(ctx, EV_CALLER_DONE, ctx->stream);
+    ev_wait(ctx, EV_CALLER_DONE, caller);
     return FMMBEM_OK;
     GUARD_END
 }

@@ -103,6 +103,8 @@ EXPORTS = {
                                         ctypes.POINTER(SolveReport), ctypes.c_void_p]),
     "fmmbem_eval_field_dev": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p,
                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "fmmbem_eval_field_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p,
+                                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "fmmbem_solve_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(SolveOpts),
                                           ctypes.c_void_p, ctypes.c_void_p]),
     "fmmbem_release_workspace": (ctypes.c_int, [ctypes.c_void_p]),
@@ -277,6 +279,11 @@ class Context:
     def fmmbem_eval_field_dev(self, isrc, nr, r_ptr: int, x_ptr: int, psi_ptr: int, stream: int = 0):
         self._check(lib().fmmbem_eval_field_dev(self.h, isrc, int(nr), ctypes.c_void_p(r_ptr), ctypes.c_void_p(x_ptr),
                                                 ctypes.c_void_p(psi_ptr), ctypes.c_void_p(stream)))
+
+    def fmmbem_eval_field_noalloc(self, isrc, nr, r_ptr: int, x_ptr: int, psi_ptr: int, stream: int = 0):
+        self._check(lib().fmmbem_eval_field_noalloc(self.h, isrc, int(nr), ctypes.c_void_p(r_ptr),
+                                                    ctypes.c_void_p(x_ptr), ctypes.c_void_p(psi_ptr),
+                                                    ctypes.c_void_p(stream)))
 
     def fmmbem_solve(self, isrc=0, x0=None, **kw):
         o = default_solve_opts()
