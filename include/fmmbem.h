@@ -126,10 +126,13 @@ typedef struct {
                             rule, and the autotuner measures them for every lane batch; 2 for
                             every lane batch; 0 never; default 1 */
     int fused;           /* lane batches with p_src = p_tgt = p <= 16 may run all three stages in
-                            one kernel, the 32-job vectors resident in LDS and transformed on
-                            matrix cores: 1 under the fixed rule and as an autotuner candidate
-                            (timed in FP64), and in mixed-precision products for every such lane
-                            batch (faster in FP32 wherever measured); 0 never; default 1 */
+                            one kernel on matrix cores: with the jobs' vectors resident in LDS
+                            (any such p), or, for FP64 products of one vector at p = 16, resident
+                            in the registers of the wavefront that transforms them (fixed rule at
+                            p = 16).  1: under the fixed rule and as autotuner candidates (timed in
+                            FP64), and in mixed-precision products for every such lane batch (the
+                            LDS-resident kernel, faster in FP32 wherever measured); 0 never;
+                            default 1 */
     double kd_leaf_min;  /* lower bound on k times the leaf side: the octree stops refining before
                             its leaves get smaller than kd_leaf_min / k, because at small k tau the
                             singular coaxial tables lose their small entries to round-off (the
@@ -411,9 +414,10 @@ int fmmbem_near_entries(fmmbem_ctx *ctx, int64_t *nnz, int64_t *rows, int64_t *c
 /* Tile shape of every translation batch (from the fixed rule, or measured when the options
  * ask for autotuning): level, kind 0 = M2L at that level, 1 = M2M into it, 2 = L2L out of it,
  * one-job-per-lane flag, whole-vector flag, jobs per tile, matrix-core mode of a lane batch (0
- * lane kernels, 1 matrix-core tiles stage by stage, 2 the fused LDS-resident kernel), and the
- * measured FP64 time of the batch's four stages (0 when not
- * measured). */
+ * lane kernels, 1 matrix-core tiles stage by stage, 2 the fused LDS-resident kernel, 3 and 4 the
+ * fused register-resident kernel with registers for 1 or 2 wavefronts per SIMD; 3 and 4 apply to
+ * FP64 products of one vector, other products of the batch run mode 2), and the measured FP64
+ * time of the batch's four stages (0 when not measured). */
 typedef struct {
     int32_t level, kind, lane, whole, jt, mfma;
     int64_t jobs;
@@ -426,7 +430,7 @@ int fmmbem_batch_shapes(fmmbem_ctx *ctx, int32_t max, fmmbem_batch_shape *out, i
  * autotuner's choice, so that a second process times or profiles exactly the same launches).
  * Each entry names its batch by (level, kind) and gives lane, whole, jt and mfma; jobs and ms are
  * ignored; batches not listed keep their shape.  Lane shapes need jt = 64 and whole = 0 (mfma 2
- * only where p_src = p_tgt <= 16); LDS tiles need mfma = 0, jt a multiple of 4 in [4, 64] and
+ * only where p_src = p_tgt <= 16, mfma 3 and 4 only where p_src = p_tgt = 16); LDS tiles need mfma = 0, jt a multiple of 4 in [4, 64] and
  * tiles that fit the LDS.  Every entry is checked before any is applied: an unknown batch or a
  * shape that does not fit returns FMMBEM_EINVAL and changes nothing.  Shapes hold until the
  * tables are rebuilt (a new mesh or wavenumber). */

@@ -279,6 +279,9 @@ static void direction_phases(int PH, std::vector<double2> &A) {
 static bool fused_ok(const TransBatch &b) {
     return b.psrc == b.ptgt && b.PT == b.P && b.P <= trans_fused_pmax();
 }
+// the register-resident fused tiles (FP64 products of one vector; other products of such a batch
+// run the LDS-resident fused kernel)
+static bool rcr_ok(const TransBatch &b) { return fused_ok(b) && b.P == trans_rcr_p(); }
 
 // Tile layout of a sorted job list for the batch's shape (JT, whole, lane): classes padded to
 // whole tiles, per-tile table indices, per-target CSR of the (padded) job order.
@@ -393,7 +396,7 @@ static void make_batch(fmmbem_ctx *c, const std::string &name, std::vector<JobH>
         b.whole = 0;
         b.JT = 64;
         b.mfma = c->opt.mfma == 2 || (c->opt.mfma == 1 && b.P >= 24);
-        if (c->opt.fused && fused_ok(b)) b.mfma = 2;
+        if (c->opt.fused && fused_ok(b)) b.mfma = rcr_ok(b) ? 3 : 2;
     } else {
         b.whole = trans_pick_jt(b.P, budget, 1) >= 8 && (size_t)8 * 16 * b.P * b.P <= budget;
         b.JT = trans_pick_jt(b.P, budget, b.whole);
@@ -685,11 +688,11 @@ static void run_batch(fmmbem_ctx *c, int nrv, const TransBatch &b0, const typena
     const double by[4] = {nr * cs * (b.psrc * b.psrc + P2), nr * cs * 2 * P2, cs * P2 * (nr + no),
                           cs * (no * P2 + 2.0 * b.ntgt * nrv * b.ptgt * b.ptgt)};
     for (int stage = 0; stage < 4; ++stage) {
-        if (b.lane && b.mfma == 2 && (stage == 1 || stage == 2)) continue;  // inside the fused kernel
+        if (b.lane && b.mfma >= 2 && (stage == 1 || stage == 2)) continue;  // inside the fused kernel
         int e = prof_begin(c);
         const char *name = trans_stage<R>(b, tb, stage, nrv, src, dst, ph, c->delta_p, W1, W2, st);
         double f = fl[stage], y = by[stage];
-        if (b.lane && b.mfma == 2 && stage == 0) {  // fused: all three stages; sources in, run rows out
+        if (b.lane && b.mfma >= 2 && stage == 0) {  // fused: all three stages; sources in, run rows out
             f = fl[0] + fl[1] + fl[2];
             y = nr * cs * b.psrc * b.psrc + no * cs * P2;
         }
@@ -764,6 +767,10 @@ static void autotune_batches(fmmbem_ctx *c) {
             cand.push_back({1, 0, 64, 0});
             if (c->opt.mfma != 0) cand.push_back({1, 0, 64, 1});
             if (c->opt.fused && fused_ok(b)) cand.push_back({1, 0, 64, 2});
+            if (c->opt.fused && rcr_ok(b)) {
+                cand.push_back({1, 0, 64, 3});
+                cand.push_back({1, 0, 64, 4});
+            }
         }
         for (int whole = 0; whole < 2; ++whole)
             for (int jt : {4, 8, 12, 16, 24, 32, 48, 64})
@@ -2729,7 +2736,8 @@ int fmmbem_set_batch_shapes(fmmbem_ctx *ctx, int32_t count, const fmmbem_batch_s
         bool ok;
         if (sh.lane)
             ok = sh.jt == 64 && sh.whole == 0 &&
-                 (sh.mfma == 0 || sh.mfma == 1 || (sh.mfma == 2 && fused_ok(b)));
+                 (sh.mfma == 0 || sh.mfma == 1 || (sh.mfma == 2 && fused_ok(b)) ||
+                  ((sh.mfma == 3 || sh.mfma == 4) && rcr_ok(b)));
         else
             ok = sh.mfma == 0 && (sh.whole == 0 || sh.whole == 1) && sh.jt >= 4 && sh.jt <= 64 && sh.jt % 4 == 0 &&
                  trans_lds_bytes(sh.jt, b.P, sh.whole) <= cap;

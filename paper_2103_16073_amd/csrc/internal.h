@@ -132,7 +132,9 @@ struct TransBatch {
     float *H32 = nullptr, *HT32 = nullptr;              // FP32 copies (mixed precision)
     int whole = 0;                                      // whole-vector tiles (small p) or per-degree slices
     int lane = 0;                                       // one job per lane, 64-job tiles (many jobs per class)
-    int mfma = 0;                                       // lane batch on matrix cores: 1 stage by stage, 2 fused (p <= 16)
+    int mfma = 0;                                       // lane batch on matrix cores: 1 stage by stage, 2 fused in LDS
+                                                        // (p <= 16), 3 / 4 fused in registers (p = 16; held to 1 / 2
+                                                        // waves per SIMD)
     int64_t ntgt = 0;                                   // target boxes
     int32_t *tgt_start = nullptr, *tgt_jobs = nullptr;  // jobs of each target (CSR, padded job indices)
     // lane batches: consecutive jobs of one class with one target form a run (never crossing a
@@ -159,6 +161,7 @@ struct JobH {
 
 int trans_pick_jt(int P, size_t lds_budget, int whole);
 int trans_fused_pmax();
+int trans_rcr_p();  // the truncation number of the register-resident fused tiles
 // fragment-order tables of the fused tiles, per class: rotation 8 degree pairs x 2 degrees x
 // 8 K chunks x 2 row blocks x 64 lanes; coaxial 16 orders x 4 K chunks x (re, im) x 64 lanes
 constexpr int TF_FR_STEP = 2 * 8 * 2 * 64, TF_FR_ROT = 8 * TF_FR_STEP;

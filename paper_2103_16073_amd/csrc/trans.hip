@@ -15,6 +15,8 @@
 //   k_tr_rot_back applies H^T and the phase, accumulates into targets (FP64 atomics)
 // Threads compute 4 jobs x 4 rows each, so one table read feeds 8 (rotation) or 16 (coaxial)
 // fused multiply-adds; the tile's slice of the vectors sits in LDS.
+#include <utility>
+
 #include "internal.h"
 
 namespace fmm {
@@ -1378,6 +1380,282 @@ __global__ void __launch_bounds__(8 * J) k_tf_trans(TransArgsT<R> a) {
     }
 }
 
+// ------------------------------------------------------------------ register-resident RCR tiles (FP64, p = 16)
+// One wavefront takes 8 (virtual) jobs of one class and keeps their coefficient vectors in registers
+// through the three stages: 16 columns (job j = column / 2, real or imaginary part by the column's
+// parity), every vector of length w in the quad layout of the matrix cores -- element e in register
+// e / 4 of lane group e % 4 (lanes 16 g .. 16 g + 15).  That is at once the layout of the B operand of
+// v_mfma_f64_16x16x4f64 (K chunk e / 4, row g) and of its D output (rows 4 i + g), so a rotation's
+// outputs feed the next product where they are.  Between the rotations and the coaxial step the
+// vectors change from degree order (degree n: orders m = -n .. n) to order order (order m: degrees
+// |m| .. p - 1) and back; each element stays in its lane group or moves to the opposite one (g ^ 2),
+// so a change of layout is a select by lane group and at most one exchange between the two halves of
+// the wavefront.  LDS holds the jobs' phase factors and one degree of outputs on its way to the run
+// sums.  The tables are the fused tiles' fragment-order tables (one contiguous value per lane).
+constexpr int TQ_P = 16;
+
+template <class F, int... I>
+__device__ __forceinline__ void tq_for_impl(F &&f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+// f(integral_constant<int, i>) for i = 0 .. N-1, every index a compile-time constant (register arrays)
+template <int N, class F> __device__ __forceinline__ void tq_for(F &&f) {
+    tq_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+// registers of degree n (2n + 1 elements) and of order m (p - |m| elements) in the quad layout
+__host__ __device__ constexpr int tq_dreg(int n) { return (n + 2) / 2; }
+__host__ __device__ constexpr int tq_doff(int n) {
+    int s = 0;
+    for (int q = 0; q < n; ++q) s += tq_dreg(q);
+    return s;
+}
+__host__ __device__ constexpr int tq_oreg(int m) { return (TQ_P - (m < 0 ? -m : m) + 3) / 4; }
+__host__ __device__ constexpr int tq_ooff(int m) {
+    int s = 0;
+    for (int q = -(TQ_P - 1); q < m; ++q) s += tq_oreg(q);
+    return s;
+}
+constexpr int TQ_ND = tq_doff(TQ_P), TQ_NO = tq_ooff(TQ_P);
+static_assert(TQ_ND == 72 && TQ_NO == 76, "quad-layout register counts");
+
+// value of lane group g among four per-group candidates
+__device__ __forceinline__ double tq_sel(bool g1, bool g2, double a0, double a1, double a2, double a3) {
+    return g2 ? (g1 ? a3 : a2) : (g1 ? a1 : a0);
+}
+// the value of the partner column (lane ^ 1: the other part of the same job), DPP quad permutation
+__device__ __forceinline__ double tq_swap_pair(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0xB1, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0xB1, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+// the value of lane l ^ 32 (lane group g ^ 2, same column)
+__device__ __forceinline__ double tq_swap_halves(double v, int lane) {
+    const int addr = (lane ^ 32) << 2;
+    const int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(v));
+    const int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
+// element (n = |m| + 4 s + g, m) of the degree layout for lane group g (K chunk s of order m)
+template <int M, int S>
+__device__ __forceinline__ double tq_to_order(const double (&X)[TQ_ND], bool g1, bool g2, int lane) {
+    constexpr int AM = M < 0 ? -M : M;
+    auto cand = [&](auto gI) -> double {
+        constexpr int n = AM + 4 * S + decltype(gI)::value;
+        if constexpr (n < TQ_P) return X[tq_doff(n) + ((n + M) >> 2)];
+        else return 0.0;
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
+    if constexpr (((AM + M) & 3) == 0) {
+        // row n + m of degree n lies in lane group g itself
+        return tq_sel(g1, g2, cand(I0{}), cand(I1{}), cand(I2{}), cand(I3{}));
+    } else {
+        // odd m > 0: it lies in lane group g ^ 2, which selects what its partner group needs
+        return tq_swap_halves(tq_sel(g1, g2, cand(I2{}), cand(I3{}), cand(I0{}), cand(I1{})), lane);
+    }
+}
+
+// element (n, m = 4 s + g - n) of the order layout for lane group g (K chunk s of degree n)
+template <int N, int S>
+__device__ __forceinline__ double tq_to_degree(const double (&Y)[TQ_NO], bool g1, bool g2, int lane) {
+    // source of lane group G: order m, row k = n - |m| in lane group k % 4, register k / 4
+    auto valid = [](int G) { return 4 * S + G <= 2 * N; };
+    auto grp = [](int G) {
+        const int m = 4 * S + G - N, k = N - (m < 0 ? -m : m);
+        return k & 3;
+    };
+    auto val = [&](auto GI) -> double {  // the source element of lane group G, read where it lies
+        constexpr int G = decltype(GI)::value, m = 4 * S + G - N, k = N - (m < 0 ? -m : m);
+        if constexpr (4 * S + G <= 2 * N) return Y[tq_ooff(m) + (k >> 2)];
+        else return 0.0;
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
+    constexpr bool own0 = !valid(0) || grp(0) == 0, own1 = !valid(1) || grp(1) == 1;
+    constexpr bool own2 = !valid(2) || grp(2) == 2, own3 = !valid(3) || grp(3) == 3;
+    // lane group G keeps its own candidate when that lies in G, else takes what G ^ 2 gives it
+    const double mine = tq_sel(g1, g2, own0 ? val(I0{}) : 0.0, own1 ? val(I1{}) : 0.0, own2 ? val(I2{}) : 0.0,
+                               own3 ? val(I3{}) : 0.0);
+    if constexpr (own0 && own1 && own2 && own3) {
+        return mine;
+    } else {
+        // lane group H gives the candidate of group H ^ 2 when that lies in H
+        const double give = tq_sel(g1, g2, own2 ? 0.0 : val(I2{}), own3 ? 0.0 : val(I3{}), own0 ? 0.0 : val(I0{}),
+                                   own1 ? 0.0 : val(I1{}));
+        const double got = tq_swap_halves(give, lane);
+        return tq_sel(g1, g2, own0 ? mine : got, own1 ? mine : got, own2 ? mine : got, own3 ? mine : got);
+    }
+}
+
+// one wavefront = 8 jobs of a 64-job tile (grid: tiles x 8); one right-hand side; psrc = ptgt = P = PT = 16
+// OCC: waves per SIMD the register allocation is held to (1: no spills; 2: a few spilled values)
+template <int OCC>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, OCC))) k_tq_rcr(TransArgsT<double> a) {
+    using v4 = TmOp<double>::v4;
+    constexpr int P = TQ_P, P2 = P * P, NPH = 2 * P - 1;
+    __shared__ double2 phl[8][NPH];       // e^{i m a_j}, m = -(P-1) .. P-1
+    __shared__ double stg[2 * P - 1][17];  // one degree of phased outputs: rows, 16 columns
+    __shared__ int64_t soff[8];
+    __shared__ int segl[8];
+    int tile, part;
+    xcd_block(tile, part);
+    const int64_t J0 = (int64_t)tile * LANE_JT + part * 8;
+    if (J0 >= a.njob) return;  // the whole workgroup (one wavefront)
+    const int lane = threadIdx.x, g = lane >> 4, col = lane & 15, jl = col >> 1, im = col & 1;
+    const bool g1 = (g & 1) != 0, g2 = (g & 2) != 0;
+    const int phs = 2 * a.PH + 1;
+    if (lane < 8) {
+        const int64_t Jv = J0 + lane, Jc = Jv < a.njob ? Jv : a.njob - 1;
+        soff[lane] = (int64_t)a.jsrc[Jc] * P2;
+        segl[lane] = Jv < a.njob ? a.jseg[Jv] : 0;
+    }
+    for (int e = lane; e < 8 * NPH; e += 64) {
+        const int j = e / NPH, q = e - j * NPH;
+        const int64_t Jv = J0 + j, Jc = Jv < a.njob ? Jv : a.njob - 1;
+        phl[j][q] = a.ph[(int64_t)a.jdir[Jc] * phs + a.PH - (P - 1) + q];
+    }
+    __syncthreads();
+
+    // sources in the degree layout, then phased: e^{i m a_j} c^m_n
+    double X[TQ_ND];
+    {
+        const double *s = (const double *)a.src + 2 * soff[jl] + im;
+        tq_for<P>([&](auto nI) {
+            constexpr int n = decltype(nI)::value;
+            tq_for<tq_dreg(n)>([&](auto sI) {
+                constexpr int q = decltype(sI)::value;
+                const int r = 4 * q + g;
+                X[tq_doff(n) + q] = r <= 2 * n ? s[2 * (n * n + r)] : 0.0;
+            });
+        });
+        tq_for<P>([&](auto nI) {
+            constexpr int n = decltype(nI)::value;
+            tq_for<tq_dreg(n)>([&](auto sI) {
+                constexpr int q = decltype(sI)::value;
+                const int r = min(4 * q + g, 2 * n);
+                const double x = X[tq_doff(n) + q], y = tq_swap_pair(x);
+                const double re = im ? y : x, iv = im ? x : y;
+                const double2 e = phl[jl][r - n + P - 1];
+                X[tq_doff(n) + q] = im ? fma(e.x, iv, e.y * re) : fma(e.x, re, -e.y * iv);
+            });
+        });
+    }
+    const int tr = a.tile_rot[tile], tc = a.tile_coax[tile];
+    // forward rotation, degree by degree: Y_n = H_n X_n (A fragments from the HT table's fragment order)
+    {
+        const double *F = a.frHT + (int64_t)tr * TF_FR_ROT + lane;
+        tq_for<P>([&](auto nI) {
+            constexpr int n = decltype(nI)::value, KS = tq_dreg(n), RB = (2 * n + 16) / 16;
+            double A[RB][KS];
+            tq_for<RB>([&](auto bI) {
+                tq_for<KS>([&](auto iI) {
+                    A[decltype(bI)::value][decltype(iI)::value] =
+                        F[((n * 8 + decltype(iI)::value) * 2 + decltype(bI)::value) * 64];
+                });
+            });
+            v4 acc[RB];
+            tq_for<RB>([&](auto bI) { acc[decltype(bI)::value] = v4{0, 0, 0, 0}; });
+            tq_for<KS>([&](auto iI) {
+                tq_for<RB>([&](auto bI) {
+                    constexpr int b = decltype(bI)::value, i = decltype(iI)::value;
+                    acc[b] = TmOp<double>::mma(A[b][i], X[tq_doff(n) + i], acc[b]);
+                });
+            });
+            tq_for<KS>([&](auto sI) {
+                constexpr int q = decltype(sI)::value;
+                X[tq_doff(n) + q] = acc[q / 4][q % 4];
+            });
+        });
+    }
+    // coaxial step, order pair by order pair (one table block for +-|m|), into the order layout
+    double Y[TQ_NO];
+    {
+        const double *F = a.frC + (int64_t)tc * TF_FR_COAX + lane;
+        const double swp = im ? 1.0 : -1.0;
+        tq_for<P>([&](auto aI) {
+            constexpr int am = decltype(aI)::value, KS = tq_oreg(am);
+            double T[KS][2];
+            tq_for<KS>([&](auto iI) {
+                constexpr int i = decltype(iI)::value;
+                T[i][0] = F[((am * 4 + i) * 2) * 64];
+                T[i][1] = F[((am * 4 + i) * 2 + 1) * 64];
+            });
+            tq_for<(am > 0 ? 2 : 1)>([&](auto sgI) {
+                constexpr int m = decltype(sgI)::value == 0 ? am : -am;
+                double B[KS], Bw[KS];
+                tq_for<KS>([&](auto sI) {
+                    constexpr int q = decltype(sI)::value;
+                    B[q] = tq_to_order<m, q>(X, g1, g2, lane);
+                    Bw[q] = swp * tq_swap_pair(B[q]);
+                });
+                v4 acc = v4{0, 0, 0, 0};
+                tq_for<KS>([&](auto iI) {
+                    constexpr int i = decltype(iI)::value;
+                    acc = TmOp<double>::mma(T[i][0], B[i], acc);
+                    acc = TmOp<double>::mma(T[i][1], Bw[i], acc);
+                });
+                tq_for<KS>([&](auto qI) {
+                    constexpr int q = decltype(qI)::value;
+                    Y[tq_ooff(m) + q] = acc[q];
+                });
+            });
+        });
+    }
+    // back rotation, degree by degree: H_n^T, then e^{-i m a}, the run sums of one target and the
+    // job-major rows of the runs' first jobs
+    {
+        const double *F = a.frH + (int64_t)tr * TF_FR_ROT + lane;
+        tq_for<P>([&](auto nI) {
+            constexpr int n = decltype(nI)::value, KS = tq_dreg(n), RB = (2 * n + 16) / 16, w = 2 * n + 1;
+            double A[RB][KS], B[KS];
+            tq_for<RB>([&](auto bI) {
+                tq_for<KS>([&](auto iI) {
+                    A[decltype(bI)::value][decltype(iI)::value] =
+                        F[((n * 8 + decltype(iI)::value) * 2 + decltype(bI)::value) * 64];
+                });
+            });
+            tq_for<KS>([&](auto sI) {
+                constexpr int q = decltype(sI)::value;
+                B[q] = tq_to_degree<n, q>(Y, g1, g2, lane);
+            });
+            v4 acc[RB];
+            tq_for<RB>([&](auto bI) { acc[decltype(bI)::value] = v4{0, 0, 0, 0}; });
+            tq_for<KS>([&](auto iI) {
+                tq_for<RB>([&](auto bI) {
+                    constexpr int b = decltype(bI)::value, i = decltype(iI)::value;
+                    acc[b] = TmOp<double>::mma(A[b][i], B[i], acc[b]);
+                });
+            });
+            tq_for<KS>([&](auto qI) {
+                constexpr int q = decltype(qI)::value;
+                const int r = 4 * q + g, rc = min(r, 2 * n);
+                const double x = acc[q / 4][q % 4], y = tq_swap_pair(x);
+                const double re = im ? y : x, iv = im ? x : y;
+                const double2 e = phl[jl][rc - n + P - 1];  // times conj(e)
+                const double v = im ? fma(e.x, iv, -e.y * re) : fma(e.x, re, e.y * iv);
+                if (r < w) stg[r][col] = v;
+            });
+            __syncthreads();
+            for (int it = lane; it < 8 * w; it += 64) {
+                const int j = it / w, r = it - j * w, len = segl[j];
+                if (len == 0) continue;
+                double2 s = make_double2(0.0, 0.0);
+                for (int t = 0; t < len; ++t) {
+                    s.x += stg[r][2 * (j + t)];
+                    s.y += stg[r][2 * (j + t) + 1];
+                }
+                a.W1[(J0 + j) * (int64_t)P2 + n * n + r] = s;
+            }
+            __syncthreads();
+        });
+    }
+}
+
 static_assert(TF_FR_STEP == 2 * 8 * 2 * 64 && TF_FR_ROT == (TF_PMAX / 2) * TF_FR_STEP, "rotation fragment layout");
 static_assert(TF_FR_ORDER == 4 * 2 * 64 && TF_FR_COAX == TF_PMAX * TF_FR_ORDER, "coaxial fragment layout");
 
@@ -1448,6 +1726,7 @@ __global__ void __launch_bounds__(256) k_tr_reduce(int64_t ntgt, int nr, int ptg
 
 // ------------------------------------------------------------------ host side
 int trans_fused_pmax() { return TF_PMAX; }
+int trans_rcr_p() { return TQ_P; }
 
 // H, HT: nbeta rotation tables of degree < P; coax: ncoax coaxial tables of size PT; outputs hold
 // max(1, nbeta) TF_FR_ROT and max(1, ncoax) TF_FR_COAX values
@@ -1500,7 +1779,23 @@ const char *trans_stage(const TransBatch &b, const TransTables<R> &tb, int stage
     const size_t lds = trans_lds_bytes(b.JT, b.P, b.whole) / (sizeof(double) / sizeof(R));
     const bool f32 = sizeof(R) == 4;
     const char *name = "";
-    if (b.lane && b.mfma == 2 && stage < 3) {
+    if constexpr (sizeof(R) == 8) {
+        if (b.lane && b.mfma >= 3 && stage < 3 && nr == 1 && b.P == TQ_P) {
+            // register-resident fused tiles: FP64, one vector, p = 16
+            if (b.JT != LANE_JT || b.psrc != b.ptgt || b.PT != b.P)
+                throw FmmError(-1, "register-resident translation tiles need 64-job tiles and p_src = p_tgt = 16");
+            if (!tb.frH || !tb.frHT || !tb.frC)
+                throw FmmError(-1, "fused translation tiles need their fragment-order tables");
+            if (stage != 0) return nullptr;
+            if (b.mfma == 3) k_tq_rcr<1><<<dim3(ntile, LANE_JT / 8), 64, 0, st>>>(a);
+            else k_tq_rcr<2><<<dim3(ntile, LANE_JT / 8), 64, 0, st>>>(a);
+            LAUNCH_OK();
+            return b.mfma == 3 ? "k_tq_rcr" : "k_tq_rcr_o2";
+        }
+    }
+    if (b.lane && b.mfma >= 2 && stage < 3) {
+        // the fused LDS-resident kernel (and the register-resident shape in FP32 or with several
+        // vectors, where it takes its place)
         // the fused kernel takes the three stages at stage 0
         // a run of one target (at most SEG_ALIGN real jobs, aligned) lies in one workgroup's jobs
         if (b.JT != LANE_JT || b.psrc != b.ptgt || b.PT != b.P || b.P > TF_PMAX || 32 / nr < SEG_ALIGN)

@@ -218,7 +218,7 @@ def test_matvec_fmm_vs_dense(F, cfg1_dense, leaf_max, lds_budget, lane, mfma, fu
     room, k = cfg1_dense
     ctx = make_ctx(F, room, k, leaf_max=leaf_max, lds_budget=lds_budget, lane_tiles=lane, mfma=mfma, fused=fused)
     if fused:
-        assert any(s["mfma"] == 2 for s in ctx.fmmbem_batch_shapes())
+        assert any(s["mfma"] in (2, 3) for s in ctx.fmmbem_batch_shapes())
     info = ctx.fmmbem_get_info()
     L, M = bem.dense_LM(room.vertices, room.triangles, k, oracle_rc(ctx, room))
     for seed in (1, 2):
@@ -490,6 +490,8 @@ def test_fused_tiles_match_lane_tiles(F, prec):
     room, k = synth.config_room(2)
     ctx0 = make_ctx(F, room, k, lane_tiles=2, mfma=0, fused=0)
     ctx1 = make_ctx(F, room, k, lane_tiles=2, mfma=0, fused=1)
+    # the LDS-resident kernel also where the fixed rule picks the register-resident one (p = 16)
+    ctx1.fmmbem_set_batch_shapes([dict(d, mfma=2) for d in ctx1.fmmbem_batch_shapes() if d["mfma"] == 3])
     sh = ctx1.fmmbem_batch_shapes()
     print("fused batches:", [(s["level"], s["kind"], s["jobs"]) for s in sh if s["mfma"] == 2])
     assert sum(s["mfma"] == 2 for s in sh) >= 3
@@ -506,6 +508,47 @@ def test_fused_tiles_match_lane_tiles(F, prec):
     ctx1.close()
 
 
+@pytest.mark.parametrize("mode", [3, 4])
+def test_register_resident_tiles_vs_lane_tiles_and_oracle(F, mode):
+    """The register-resident fused translation tiles (p = 16; modes 3 and 4 differ only in the
+    registers the compiler may use) against the three-pass lane kernels on the 6x5x3 m room at
+    1 kHz: FP64 products of one vector agree to rounding (1e-12) and with the oracle's rows (1e-6);
+    products of 2 and 4 vectors and mixed products of such batches run the LDS-resident fused
+    kernel instead (1e-12 / FP32 rounding against the lane kernels)."""
+    room, k = synth.config_room(2)
+    ctx_l = make_ctx(F, room, k, lane_tiles=2, mfma=0, fused=0)
+    ctx_r = make_ctx(F, room, k, lane_tiles=2, mfma=0, fused=1)
+    shapes = ctx_r.fmmbem_batch_shapes()
+    regs = [d for d in shapes if d["mfma"] == 3]
+    print("register-resident batches:", [(d["level"], d["kind"], d["jobs"]) for d in regs])
+    assert len(regs) >= 3
+    if mode == 4:
+        ctx_r.fmmbem_set_batch_shapes([dict(d, mfma=4) for d in regs])
+        assert sum(d["mfma"] == 4 for d in ctx_r.fmmbem_batch_shapes()) == len(regs)
+    X = np.stack([synth.complex_normal(room.n, 120 + s) for s in range(4)])
+    y_l = ctx_l.fmmbem_matvec(X[0])[0]
+    y_r = ctx_r.fmmbem_matvec(X[0])[0]
+    err = np.linalg.norm(y_r - y_l) / np.linalg.norm(y_l)
+    print(f"mode {mode}: one vector vs lane kernels {err:.2e}")
+    assert err < 1e-12
+    rows = np.random.default_rng(9).choice(room.n, 256, replace=False)
+    ref = bem.direct_matvec_rows(room.vertices, room.triangles, k, room.beta, oracle_rc(ctx_r, room), X[0], rows)
+    assert np.linalg.norm(y_r[rows] - ref) / np.linalg.norm(ref) < 1e-6
+    for nr in (2, 4):
+        Yl, Yr = ctx_l.fmmbem_matvec(X[:nr]), ctx_r.fmmbem_matvec(X[:nr])
+        assert np.linalg.norm(Yr - Yl) / np.linalg.norm(Yl) < 1e-12, nr
+    ym_l = ctx_l.fmmbem_matvec(X[0], precision=F.FMMBEM_MIXED)[0]
+    ym_r = ctx_r.fmmbem_matvec(X[0], precision=F.FMMBEM_MIXED)[0]
+    assert np.linalg.norm(ym_r - ym_l) / np.linalg.norm(ym_l) < 1e-5
+    # a register-resident shape where p != 16 is rejected
+    bad = [dict(d, mfma=3) for d in shapes if d["lane"] and d["mfma"] != 3][:1]
+    if bad:
+        with pytest.raises(F.FmmbemError):
+            ctx_r.fmmbem_set_batch_shapes(bad)
+    ctx_l.close()
+    ctx_r.close()
+
+
 def test_mixed_products_run_lane_batches_fused(F):
     """With `fused` on, mixed products run every lane batch that may use the fused tiles fused, even
     where its shape is the three-pass lane kernels (as the FP64 autotuner may choose): lane shapes
@@ -517,9 +560,9 @@ def test_mixed_products_run_lane_batches_fused(F):
     ctx_f = make_ctx(F, room, k, lane_tiles=2, mfma=0, fused=1)
     ctx_r = make_ctx(F, room, k, lane_tiles=2, mfma=0, fused=1)
     shapes = ctx_f.fmmbem_batch_shapes()
-    assert sum(d["mfma"] == 2 for d in shapes) >= 3
-    ctx_r.fmmbem_set_batch_shapes([dict(d, mfma=0) if d["mfma"] == 2 else d for d in shapes])
-    assert all(d["mfma"] != 2 for d in ctx_r.fmmbem_batch_shapes())
+    assert sum(d["mfma"] >= 2 for d in shapes) >= 3
+    ctx_r.fmmbem_set_batch_shapes([dict(d, mfma=0) if d["mfma"] >= 2 else d for d in shapes])
+    assert all(d["mfma"] < 2 for d in ctx_r.fmmbem_batch_shapes())
     x = synth.complex_normal(room.n, 43)
     y_l, y_f, y_r = (c.fmmbem_matvec(x, precision=F.FMMBEM_MIXED)[0] for c in (ctx_l, ctx_f, ctx_r))
     assert np.array_equal(y_r, y_f)
