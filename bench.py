@@ -56,6 +56,82 @@ def measured_traffic(kernel, launches_per_product):
     return None
 
 
+# kernels whose arithmetic runs on the matrix cores (the others use the vector ALUs)
+MFMA_KERNELS = ("k_tq_rcr", "k_tf_trans", "k_tm_")
+
+
+def kernel_roofline(st, steps, counted):
+    """Roofline position of one kernel class from the library's per-launch algorithmic work: the
+    method's flops (rotation, coaxial step and back rotation of every translation job; pair kernel
+    evaluations) and its compulsory HBM bytes (each distinct input expansion and table once, targets
+    once).  The bound is the one the kernel's intensity (flops / compulsory bytes) reaches first
+    against the FP64 ridge point (peak FP64 flops / peak HBM bandwidth); achieved = the bound's
+    quantity per launch / the average launch time (HIP events on the launch's own stream).
+    `traffic` is the measured HBM bytes per launch (committed counter summary) when those counters
+    were taken on these very launches; its excess over the compulsory bytes is what the
+    implementation adds (work rows between kernels, re-reads)."""
+    avg_s = st["ms"] / st["launches"] * 1e-3
+    fl = st["flops"] / st["launches"]
+    by = st["bytes"] / st["launches"]
+    ridge = PEAKS["fp64"] / PEAKS["hbm"]
+    intensity = fl / by if by > 0 else float("inf")
+    if intensity >= ridge:
+        bound = "mfma" if st["name"].startswith(MFMA_KERNELS) else "alu"
+        rl = {"kernel": st["name"], "bound": bound, "achieved": fl / avg_s / 1e12, "peak": PEAKS["fp64"] / 1e12,
+              "unit": "TFLOP/s", "frac": fl / avg_s / PEAKS["fp64"]}
+    else:
+        rl = {"kernel": st["name"], "bound": "hbm", "achieved": by / avg_s / 1e9, "peak": PEAKS["hbm"] / 1e9,
+              "unit": "GB/s", "frac": by / avg_s / PEAKS["hbm"]}
+    traffic = measured_traffic(st["name"], st["launches"] / steps) if counted else None
+    rl.update({"traffic": traffic,
+               "traffic_GBps": None if traffic is None else traffic / avg_s / 1e9,
+               "traffic_over_compulsory": None if traffic is None else traffic / by,
+               "algorithmic_flops_per_launch": fl, "compulsory_bytes_per_launch": by,
+               "intensity_flop_per_byte": intensity, "fp64_ridge_flop_per_byte": ridge,
+               "achieved_TFLOPs": fl / avg_s / 1e12, "compulsory_GBps": by / avg_s / 1e9,
+               "avg_launch_ms": 1e3 * avg_s, "launches_per_step": st["launches"] / steps,
+               "formula": "frac = algorithmic_flops_per_launch / (avg_launch_ms * 1e-3) / (peak * 1e12)"
+               if rl["unit"] == "TFLOP/s" else
+               "frac = compulsory_bytes_per_launch / (avg_launch_ms * 1e-3) / (peak * 1e9)"})
+    return rl
+
+
+def one_core_rows(workload, R):
+    """Seconds the oracle takes for R seeded rows of the workload's product on one OpenMP thread (a
+    child process, so that the parent's thread pool is untouched); None if the child fails."""
+    import subprocess
+    code = ("import sys, time; sys.path.insert(0, %r)\n"
+            "import numpy as np\n"
+            "from oracle import bem\n"
+            "from paper_2103_16073_amd import synth\n"
+            "room, k = synth.config_room(%d)\n"
+            "x = synth.complex_normal(room.n, 11)\n"
+            "rc = bem.near_cutoff(room.vertices, room.triangles)\n"
+            "rows = np.random.default_rng(6).choice(room.n, %d, replace=False)\n"
+            "bem.direct_matvec_rows(room.vertices, room.triangles, k, room.beta, rc, x, rows[:2])\n"
+            "t = time.perf_counter()\n"
+            "bem.direct_matvec_rows(room.vertices, room.triangles, k, room.beta, rc, x, rows)\n"
+            "print(time.perf_counter() - t)\n") % (ROOT, workload, R)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
+        return float(r.stdout.strip().splitlines()[-1])
+    except Exception as e:  # noqa: BLE001 -- a baseline that failed is reported as missing
+        log(f"one-core oracle run failed: {e}")
+        return None
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -192,34 +268,28 @@ def main():
         log(f"  {s['name']:16s} {s['ms'] / args.steps:9.3f} ms/step  {s['launches'] / args.steps:5.1f} launches  "
             f"{s['flops'] / max(s['ms'], 1e-9) / 1e9:8.2f} TFLOP/s")
     dom = max(stats, key=lambda s: s["ms"])
-    avg_ms = dom["ms"] / dom["launches"]
-    flops_per_launch = dom["flops"] / dom["launches"]
-    achieved = flops_per_launch / (avg_ms * 1e-3)
-    traffic = (measured_traffic(dom["name"], dom["launches"] / args.steps)
-               if (args.workload == 3 and not args.no_autotune) else None)
-    if traffic is None and args.workload == 3:
-        log(f"traffic of {dom['name']}: none for these launches in the committed counter summary")
-    # bound from the kernel's arithmetic intensity against the FP64 ridge point (peak flops over
-    # peak HBM bandwidth): below it the HBM roofline is the one that bounds the kernel
-    bytes_per_launch = dom["bytes"] / dom["launches"]
-    intensity = flops_per_launch / bytes_per_launch
-    ridge = PEAKS["fp64"] / PEAKS["hbm"]
-    bw = bytes_per_launch / (avg_ms * 1e-3)
-    if intensity < ridge:
-        roofline = {"kernel": dom["name"], "bound": "hbm", "achieved": bw / 1e9, "peak": PEAKS["hbm"] / 1e9,
-                    "unit": "GB/s", "frac": bw / PEAKS["hbm"]}
-    else:
-        roofline = {"kernel": dom["name"], "bound": "alu", "achieved": achieved / 1e12,
-                    "peak": PEAKS["fp64"] / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAKS["fp64"]}
-    roofline.update({"traffic": traffic,
-                     "traffic_GBps": None if traffic is None else traffic / (avg_ms * 1e-3) / 1e9,
-                     "algorithmic_bytes_per_launch": bytes_per_launch,
-                     "algorithmic_flops_per_launch": flops_per_launch,
-                     "arithmetic_intensity_flop_per_byte": intensity, "fp64_ridge_flop_per_byte": ridge,
-                     "alu_frac": achieved / PEAKS["fp64"], "hbm_frac": bw / PEAKS["hbm"],
-                     "avg_launch_ms": avg_ms, "launches_per_step": dom["launches"] / args.steps})
-    log(f"dominant kernel {dom['name']}: {avg_ms:.3f} ms/launch, {achieved/1e12:.3f} TFLOP/s, {bw/1e9:.0f} GB/s "
-        f"(intensity {intensity:.2f} flop/B, ridge {ridge:.2f}): {roofline['bound']} bound, frac {roofline['frac']:.3f}")
+    roofline = kernel_roofline(dom, args.steps, args.workload == 3 and not args.no_autotune)
+    log(f"dominant kernel {dom['name']}: {roofline['avg_launch_ms']:.3f} ms/launch, "
+        f"{roofline['achieved_TFLOPs']:.3f} TFLOP/s of the method's flops, "
+        f"{roofline['compulsory_GBps']:.0f} GB/s of its compulsory bytes: {roofline['bound']} bound, "
+        f"frac {roofline['frac']:.3f}")
+    p2p = next((s for s in stats if s["name"] == "k_p2p"), None)
+    p2p_line = None
+    if p2p is not None:
+        t = p2p["ms"] / p2p["launches"] * 1e-3
+        p2p_traffic = (measured_traffic("k_p2p", p2p["launches"] / args.steps)
+                       if (args.workload == 3 and not args.no_autotune) else None)
+        p2p_line = {"kernel": "k_p2p", "avg_launch_ms": 1e3 * t, "pairs_per_s": info.p2p_pairs / t,
+                    "algorithmic_bytes_per_launch": p2p["bytes"] / p2p["launches"],
+                    "achieved_GBps": p2p["bytes"] / p2p["launches"] / t / 1e9,
+                    "hbm_frac": p2p["bytes"] / p2p["launches"] / t / PEAKS["hbm"],
+                    "traffic": p2p_traffic,
+                    "traffic_GBps": None if p2p_traffic is None else p2p_traffic / t / 1e9,
+                    "traffic_hbm_frac": None if p2p_traffic is None else p2p_traffic / t / PEAKS["hbm"],
+                    "alu_TFLOPs": p2p["flops"] / p2p["launches"] / t / 1e12,
+                    "alu_frac": p2p["flops"] / p2p["launches"] / t / PEAKS["fp64"]}
+        log(f"P2P: {p2p_line['pairs_per_s']:.3e} pairs/s, {p2p_line['achieved_GBps']:.0f} GB/s algorithmic "
+            f"({p2p_line['hbm_frac']:.3f} of HBM), {p2p_line['alu_TFLOPs']:.2f} TFLOP/s")
 
     y_h = y.cpu().numpy()
 
@@ -295,6 +365,7 @@ def main():
         "tile_shapes_source": shapes_src,
         "phases_ms": phases,
         "roofline": roofline,
+        "p2p": p2p_line,
         "mixed_precision": mixed,
         "four_vector_products": batched,
     }
@@ -383,21 +454,30 @@ def main():
         rng = np.random.default_rng(5)
         cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
         # calibrate on a few rows, then run a bounded sample of about cpu_seconds
+        rc = bem.near_cutoff(room.vertices, room.triangles)
+        assert abs(rc - info.rc) <= 1e-14 * rc, (rc, info.rc)
         probe = rng.choice(n, 16, replace=False)
         tp = time.perf_counter()
-        bem.direct_matvec_rows(room.vertices, room.triangles, k, room.beta, info.rc, x_h, probe)
+        bem.direct_matvec_rows(room.vertices, room.triangles, k, room.beta, rc, x_h, probe)
         per_row = (time.perf_counter() - tp) / 16
         R = int(min(8192, max(32, args.cpu_seconds / max(per_row, 1e-6))))
         rows = rng.choice(n, R, replace=False)
         tc = time.perf_counter()
-        ref = bem.direct_matvec_rows(room.vertices, room.triangles, k, room.beta, info.rc, x_h, rows)
+        ref = bem.direct_matvec_rows(room.vertices, room.triangles, k, room.beta, rc, x_h, rows)
         tcpu = time.perf_counter() - tc
         t_matvec = tcpu * n / R
+        # the same oracle on one core (a child process with one OpenMP thread), on a smaller sample
+        R1 = max(4, min(R, int(R / max(1, cores))))
+        one = one_core_rows(args.workload, R1)
         err = float(np.linalg.norm(y_h[rows] - ref) / np.linalg.norm(ref))
         mixed["rel_l2_vs_oracle_on_sample"] = float(np.linalg.norm(ym_h[rows] - ref) / np.linalg.norm(ref))
         result["cpu_baseline"] = {"value": 1.0 / t_matvec, "unit": "matvec/s", "cores": cores, "kind": "oracle",
                                   "sample": f"{R} seeded rows x all {n} columns in {tcpu:.1f} s, "
-                                            f"scaled by N/R"}
+                                            f"scaled by N/R",
+                                  "cpu_model": cpu_model(),
+                                  "value_1core": None if one is None else 1.0 / (one * n / R1),
+                                  "sample_1core": None if one is None else
+                                  f"{R1} seeded rows x all {n} columns in {one:.1f} s on 1 thread, scaled by N/R"}
         result["gpu_vs_oracle_rel_l2_on_sample"] = err
         log(f"oracle: {R} rows in {tcpu:.1f}s -> {1.0 / t_matvec:.3e} matvec/s; GPU vs oracle rel L2 {err:.3e}")
 

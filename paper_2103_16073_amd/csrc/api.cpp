@@ -363,6 +363,16 @@ static void make_batch(fmmbem_ctx *c, const std::string &name, std::vector<JobH>
     b.PT = PT;
     b.P = std::max(psrc, ptgt);
     b.nreal = (int64_t)jobs.size();
+    {
+        std::vector<int32_t> srcs;
+        srcs.reserve(jobs.size());
+        for (auto &j : jobs) srcs.push_back(j.src);
+        std::sort(srcs.begin(), srcs.end());
+        b.nsrc = std::unique(srcs.begin(), srcs.end()) - srcs.begin();
+        int tmax = 0;
+        for (auto &j : jobs) tmax = std::max(tmax, j.tab);
+        b.ncoax = tmax + 1;
+    }
     size_t budget = c->opt.lds_budget > 0 ? (size_t)c->opt.lds_budget : (size_t)32768;
     budget = std::min(budget, c->lds_max - 1024);
     b.ntgt = ntgt;
@@ -396,7 +406,7 @@ static void make_batch(fmmbem_ctx *c, const std::string &name, std::vector<JobH>
         b.whole = 0;
         b.JT = 64;
         b.mfma = c->opt.mfma == 2 || (c->opt.mfma == 1 && b.P >= 24);
-        if (c->opt.fused && fused_ok(b)) b.mfma = rcr_ok(b) ? 3 : 2;
+        if (c->opt.fused && fused_ok(b)) b.mfma = rcr_ok(b) ? 4 : 2;
     } else {
         b.whole = trans_pick_jt(b.P, budget, 1) >= 8 && (size_t)8 * 16 * b.P * b.P <= budget;
         b.JT = trans_pick_jt(b.P, budget, b.whole);
@@ -682,19 +692,25 @@ static void run_batch(fmmbem_ctx *c, int nrv, const TransBatch &b0, const typena
     C *W1 = (C *)c->scratch.get(side ? "W1s" : "W1", sizeof(C) * (size_t)b.njob * nrv * b.P * b.P);
     C *W2 = (C *)c->scratch.get(side ? "W2s" : "W2", sizeof(C) * (size_t)b.njob * nrv * b.P * b.P);
     const double nr = (double)b.nreal * nrv, P2 = (double)b.P * b.P, cs = (double)sizeof(C);
-    const double no = (double)b.nout * nrv;  // output rows of the back rotation (runs or jobs)
-    // algorithmic work per stage: flops of the matrices applied; bytes of the rows moved once
+    // Algorithmic work per stage, the method's own: flops of the matrices applied (rotation,
+    // coaxial step, rotation; the reduction's additions) and compulsory HBM bytes -- every distinct
+    // source expansion read once, the tables the stage applies read once, the target expansions
+    // read and written once by the reduction.  The work rows between the stages and the run rows
+    // into the reduction exist only because the method is split into kernels; the bench reports
+    // them as the difference between the measured traffic and these bytes.
+    const double rs = sizeof(R), nbeta = std::max(1, b.nbeta);
+    const double rot_tab = nbeta * rot_table_size(b.P) * rs, coax_tab = b.ncoax * coax_table_size(b.PT) * 2 * rs;
+    const double src_by = (double)b.nsrc * nrv * b.psrc * b.psrc * cs;
     const double fl[4] = {nr * rot_flops(b.psrc), nr * coax_flops(b.psrc, b.ptgt), nr * rot_flops(b.ptgt), nr * P2 * 2};
-    const double by[4] = {nr * cs * (b.psrc * b.psrc + P2), nr * cs * 2 * P2, cs * P2 * (nr + no),
-                          cs * (no * P2 + 2.0 * b.ntgt * nrv * b.ptgt * b.ptgt)};
+    const double by[4] = {src_by + rot_tab, coax_tab, rot_tab, 2.0 * b.ntgt * nrv * b.ptgt * b.ptgt * cs};
     for (int stage = 0; stage < 4; ++stage) {
         if (b.lane && b.mfma >= 2 && (stage == 1 || stage == 2)) continue;  // inside the fused kernel
         int e = prof_begin(c);
         const char *name = trans_stage<R>(b, tb, stage, nrv, src, dst, ph, c->delta_p, W1, W2, st);
         double f = fl[stage], y = by[stage];
-        if (b.lane && b.mfma >= 2 && stage == 0) {  // fused: all three stages; sources in, run rows out
+        if (b.lane && b.mfma >= 2 && stage == 0) {  // fused: all three stages, each table once
             f = fl[0] + fl[1] + fl[2];
-            y = nr * cs * b.psrc * b.psrc + no * cs * P2;
+            y = src_by + rot_tab + coax_tab;
         }
         prof_end(c, e, name, f, y);
     }

@@ -142,6 +142,8 @@ struct TransBatch {
     // rotation stores each run's sum in the first job's row and the CSR lists first jobs only.
     int8_t *seg = nullptr;
     int64_t nout = 0;  // rows the back rotation stores (runs of lane batches, else jobs)
+    int64_t nsrc = 0;  // distinct source expansions the batch reads
+    int ncoax = 1;     // coaxial tables the batch's classes use
     // fused tiles: the rotation tables and the batch's coaxial tables in the order in which the
     // lanes hold matrix-core fragments, zero past every block (built when p_src = p_tgt <= 16)
     double *frH = nullptr, *frHT = nullptr, *frC = nullptr;

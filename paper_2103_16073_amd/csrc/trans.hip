@@ -1492,15 +1492,65 @@ __device__ __forceinline__ double tq_to_degree(const double (&Y)[TQ_NO], bool g1
     }
 }
 
-// one wavefront = 8 jobs of a 64-job tile (grid: tiles x 8); one right-hand side; psrc = ptgt = P = PT = 16
-// OCC: waves per SIMD the register allocation is held to (1: no spills; 2: a few spilled values)
+// sum of a value over the run of one target that starts at this column's job (runs never cross the
+// wavefront's 8 jobs): segmented sums over the columns 2 (j + t) + part, t < len, by three shifts
+// of 2, 4 and 8 columns within the lane group (DPP row shifts); end = first job past the run
+__device__ __forceinline__ double tq_dpp_shl(double v, int ctrl_sel) {
+    int lo = __double2loint(v), hi = __double2hiint(v);
+    switch (ctrl_sel) {  // row_shl:2 / 4 / 8 (lane i takes lane i + d of its row of 16; 0 past the row)
+    case 2: lo = __builtin_amdgcn_update_dpp(0, lo, 0x102, 0xF, 0xF, true), hi = __builtin_amdgcn_update_dpp(0, hi, 0x102, 0xF, 0xF, true); break;
+    case 4: lo = __builtin_amdgcn_update_dpp(0, lo, 0x104, 0xF, 0xF, true), hi = __builtin_amdgcn_update_dpp(0, hi, 0x104, 0xF, 0xF, true); break;
+    default: lo = __builtin_amdgcn_update_dpp(0, lo, 0x108, 0xF, 0xF, true), hi = __builtin_amdgcn_update_dpp(0, hi, 0x108, 0xF, 0xF, true);
+    }
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double tq_run_sum(double v, int col, int end2) {
+    // end2 = 2 * (end of this column's run in jobs): columns c + d with c + d < end2 belong to it
+    double s = v;
+    const double s2 = tq_dpp_shl(s, 2);
+    s += (col + 2 < end2) ? s2 : 0.0;
+    const double s4 = tq_dpp_shl(s, 4);
+    s += (col + 4 < end2) ? s4 : 0.0;
+    const double s8 = tq_dpp_shl(s, 8);
+    s += (col + 8 < end2) ? s8 : 0.0;
+    return s;
+}
+
+// A fragments of the rotation of degree n (K chunks x row blocks), one value per lane
+template <int N>
+__device__ __forceinline__ void tq_load_rot(double (&A)[16], const double *F) {
+    constexpr int KS = tq_dreg(N), RB = (2 * N + 16) / 16;
+    tq_for<RB>([&](auto bI) {
+        tq_for<KS>([&](auto iI) {
+            constexpr int b = decltype(bI)::value, i = decltype(iI)::value;
+            A[b * 8 + i] = F[((N * 8 + i) * 2 + b) * 64];
+        });
+    });
+}
+// rotation of degree n on the quad-layout vector B (tq_dreg(n) registers) into acc (row blocks)
+template <int N>
+__device__ __forceinline__ void tq_rotate(const double (&A)[16], const double *B, TmOp<double>::v4 (&acc)[2]) {
+    using v4 = TmOp<double>::v4;
+    constexpr int KS = tq_dreg(N), RB = (2 * N + 16) / 16;
+    tq_for<RB>([&](auto bI) { acc[decltype(bI)::value] = v4{0, 0, 0, 0}; });
+    tq_for<KS>([&](auto iI) {
+        tq_for<RB>([&](auto bI) {
+            constexpr int b = decltype(bI)::value, i = decltype(iI)::value;
+            acc[b] = TmOp<double>::mma(A[b * 8 + i], B[i], acc[b]);
+        });
+    });
+}
+
+// one wavefront = 8 jobs of a 64-job tile (grid: tiles x 8); one right-hand side; psrc = ptgt = P = PT = 16.
+// OCC: waves per SIMD the register allocation is held to.  The table fragments of a step are loaded
+// one step (for small degrees several) ahead of the step that uses them.
 template <int OCC>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, OCC))) k_tq_rcr(TransArgsT<double> a) {
     using v4 = TmOp<double>::v4;
     constexpr int P = TQ_P, P2 = P * P, NPH = 2 * P - 1;
-    __shared__ double2 phl[8][NPH];       // e^{i m a_j}, m = -(P-1) .. P-1
-    __shared__ double stg[2 * P - 1][17];  // one degree of phased outputs: rows, 16 columns
+    __shared__ double2 phl[8][NPH];  // e^{i m a_j}, m = -(P-1) .. P-1
     __shared__ int64_t soff[8];
+    __shared__ int sgend[8];  // per job: first job past the run it belongs to (within the wavefront)
     __shared__ int segl[8];
     int tile, part;
     xcd_block(tile, part);
@@ -1520,8 +1570,20 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, OC
         phl[j][q] = a.ph[(int64_t)a.jdir[Jc] * phs + a.PH - (P - 1) + q];
     }
     __syncthreads();
+    if (lane < 8) {
+        // run of job `lane`: it starts at the nearest start at or before it (runs are contiguous)
+        int st = lane;
+        while (st > 0 && segl[st] == 0) --st;
+        sgend[lane] = segl[st] > 0 ? st + segl[st] : lane + 1;
+    }
+    const int tr = a.tile_rot[tile], tc = a.tile_coax[tile];
+    const double *FF = a.frHT + (int64_t)tr * TF_FR_ROT + lane;  // forward: H (from HT's fragments)
+    const double *FB = a.frH + (int64_t)tr * TF_FR_ROT + lane;   // back: H^T
+    const double *FC = a.frC + (int64_t)tc * TF_FR_COAX + lane;
+    double AF[P][16];  // rotation fragments per degree (only the live ones take registers)
+    double TF[P][8];   // coaxial fragments per order |m|: 4 K chunks x (re, im)
 
-    // sources in the degree layout, then phased: e^{i m a_j} c^m_n
+    // sources in the degree layout; the fragments of the small degrees loaded behind them
     double X[TQ_ND];
     {
         const double *s = (const double *)a.src + 2 * soff[jl] + im;
@@ -1530,9 +1592,12 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, OC
             tq_for<tq_dreg(n)>([&](auto sI) {
                 constexpr int q = decltype(sI)::value;
                 const int r = 4 * q + g;
-                X[tq_doff(n) + q] = r <= 2 * n ? s[2 * (n * n + r)] : 0.0;
+                const double v = s[2 * (n * n + min(r, 2 * n))];  // clamped: no masked load
+                X[tq_doff(n) + q] = r <= 2 * n ? v : 0.0;
             });
         });
+        tq_for<4>([&](auto nI) { tq_load_rot<decltype(nI)::value>(AF[decltype(nI)::value], FF); });
+        __syncthreads();  // sgend
         tq_for<P>([&](auto nI) {
             constexpr int n = decltype(nI)::value;
             tq_for<tq_dreg(n)>([&](auto sI) {
@@ -1545,46 +1610,45 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, OC
             });
         });
     }
-    const int tr = a.tile_rot[tile], tc = a.tile_coax[tile];
-    // forward rotation, degree by degree: Y_n = H_n X_n (A fragments from the HT table's fragment order)
-    {
-        const double *F = a.frHT + (int64_t)tr * TF_FR_ROT + lane;
-        tq_for<P>([&](auto nI) {
-            constexpr int n = decltype(nI)::value, KS = tq_dreg(n), RB = (2 * n + 16) / 16;
-            double A[RB][KS];
-            tq_for<RB>([&](auto bI) {
-                tq_for<KS>([&](auto iI) {
-                    A[decltype(bI)::value][decltype(iI)::value] =
-                        F[((n * 8 + decltype(iI)::value) * 2 + decltype(bI)::value) * 64];
+    const int end2 = 2 * sgend[jl];
+    const bool starts = segl[jl] > 0;
+    // forward rotation, degree by degree: Y_n = H_n X_n
+    tq_for<P>([&](auto nI) {
+        constexpr int n = decltype(nI)::value;
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (n >= 3 && n + 1 < P) tq_load_rot<n + 1>(AF[n + 1], FF);
+        if constexpr (n == P - 1) {
+            tq_for<2>([&](auto aI) {
+                constexpr int am = decltype(aI)::value;
+                tq_for<tq_oreg(am)>([&](auto iI) {
+                    constexpr int i = decltype(iI)::value;
+                    TF[am][2 * i] = FC[((am * 4 + i) * 2) * 64];
+                    TF[am][2 * i + 1] = FC[((am * 4 + i) * 2 + 1) * 64];
                 });
             });
-            v4 acc[RB];
-            tq_for<RB>([&](auto bI) { acc[decltype(bI)::value] = v4{0, 0, 0, 0}; });
-            tq_for<KS>([&](auto iI) {
-                tq_for<RB>([&](auto bI) {
-                    constexpr int b = decltype(bI)::value, i = decltype(iI)::value;
-                    acc[b] = TmOp<double>::mma(A[b][i], X[tq_doff(n) + i], acc[b]);
-                });
-            });
-            tq_for<KS>([&](auto sI) {
-                constexpr int q = decltype(sI)::value;
-                X[tq_doff(n) + q] = acc[q / 4][q % 4];
-            });
+        }
+        v4 acc[2];
+        tq_rotate<n>(AF[n], &X[tq_doff(n)], acc);
+        tq_for<tq_dreg(n)>([&](auto sI) {
+            constexpr int q = decltype(sI)::value;
+            X[tq_doff(n) + q] = acc[q / 4][q % 4];
         });
-    }
+    });
     // coaxial step, order pair by order pair (one table block for +-|m|), into the order layout
     double Y[TQ_NO];
     {
-        const double *F = a.frC + (int64_t)tc * TF_FR_COAX + lane;
         const double swp = im ? 1.0 : -1.0;
         tq_for<P>([&](auto aI) {
             constexpr int am = decltype(aI)::value, KS = tq_oreg(am);
-            double T[KS][2];
-            tq_for<KS>([&](auto iI) {
-                constexpr int i = decltype(iI)::value;
-                T[i][0] = F[((am * 4 + i) * 2) * 64];
-                T[i][1] = F[((am * 4 + i) * 2 + 1) * 64];
-            });
+            __builtin_amdgcn_sched_barrier(0);
+            if constexpr (am + 2 < P) {
+                tq_for<tq_oreg(am + 2)>([&](auto iI) {
+                    constexpr int i = decltype(iI)::value;
+                    TF[am + 2][2 * i] = FC[(((am + 2) * 4 + i) * 2) * 64];
+                    TF[am + 2][2 * i + 1] = FC[(((am + 2) * 4 + i) * 2 + 1) * 64];
+                });
+            }
+            if constexpr (am == P - 3) tq_load_rot<P - 1>(AF[P - 1], FB);
             tq_for<(am > 0 ? 2 : 1)>([&](auto sgI) {
                 constexpr int m = decltype(sgI)::value == 0 ? am : -am;
                 double B[KS], Bw[KS];
@@ -1596,8 +1660,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, OC
                 v4 acc = v4{0, 0, 0, 0};
                 tq_for<KS>([&](auto iI) {
                     constexpr int i = decltype(iI)::value;
-                    acc = TmOp<double>::mma(T[i][0], B[i], acc);
-                    acc = TmOp<double>::mma(T[i][1], Bw[i], acc);
+                    acc = TmOp<double>::mma(TF[am][2 * i], B[i], acc);
+                    acc = TmOp<double>::mma(TF[am][2 * i + 1], Bw[i], acc);
                 });
                 tq_for<KS>([&](auto qI) {
                     constexpr int q = decltype(qI)::value;
@@ -1606,54 +1670,31 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, OC
             });
         });
     }
-    // back rotation, degree by degree: H_n^T, then e^{-i m a}, the run sums of one target and the
-    // job-major rows of the runs' first jobs
-    {
-        const double *F = a.frH + (int64_t)tr * TF_FR_ROT + lane;
-        tq_for<P>([&](auto nI) {
-            constexpr int n = decltype(nI)::value, KS = tq_dreg(n), RB = (2 * n + 16) / 16, w = 2 * n + 1;
-            double A[RB][KS], B[KS];
-            tq_for<RB>([&](auto bI) {
-                tq_for<KS>([&](auto iI) {
-                    A[decltype(bI)::value][decltype(iI)::value] =
-                        F[((n * 8 + decltype(iI)::value) * 2 + decltype(bI)::value) * 64];
-                });
-            });
-            tq_for<KS>([&](auto sI) {
-                constexpr int q = decltype(sI)::value;
-                B[q] = tq_to_degree<n, q>(Y, g1, g2, lane);
-            });
-            v4 acc[RB];
-            tq_for<RB>([&](auto bI) { acc[decltype(bI)::value] = v4{0, 0, 0, 0}; });
-            tq_for<KS>([&](auto iI) {
-                tq_for<RB>([&](auto bI) {
-                    constexpr int b = decltype(bI)::value, i = decltype(iI)::value;
-                    acc[b] = TmOp<double>::mma(A[b][i], B[i], acc[b]);
-                });
-            });
-            tq_for<KS>([&](auto qI) {
-                constexpr int q = decltype(qI)::value;
-                const int r = 4 * q + g, rc = min(r, 2 * n);
-                const double x = acc[q / 4][q % 4], y = tq_swap_pair(x);
-                const double re = im ? y : x, iv = im ? x : y;
-                const double2 e = phl[jl][rc - n + P - 1];  // times conj(e)
-                const double v = im ? fma(e.x, iv, -e.y * re) : fma(e.x, re, e.y * iv);
-                if (r < w) stg[r][col] = v;
-            });
-            __syncthreads();
-            for (int it = lane; it < 8 * w; it += 64) {
-                const int j = it / w, r = it - j * w, len = segl[j];
-                if (len == 0) continue;
-                double2 s = make_double2(0.0, 0.0);
-                for (int t = 0; t < len; ++t) {
-                    s.x += stg[r][2 * (j + t)];
-                    s.y += stg[r][2 * (j + t) + 1];
-                }
-                a.W1[(J0 + j) * (int64_t)P2 + n * n + r] = s;
-            }
-            __syncthreads();
+    // back rotation, degree by degree from the largest: H_n^T, then e^{-i m a} and the run sums of
+    // one target; the runs' first jobs store their rows (job-major, for the per-target reduction)
+    double2 *out = a.W1 + J0 * (int64_t)P2;
+    tq_for<P>([&](auto dI) {
+        constexpr int n = P - 1 - decltype(dI)::value, KS = tq_dreg(n), w = 2 * n + 1;
+        __builtin_amdgcn_sched_barrier(0);  // one degree's outputs at a time (register pressure)
+        if constexpr (n - 1 >= 7) tq_load_rot<n - 1>(AF[n - 1], FB);
+        if constexpr (n == 8) tq_for<7>([&](auto kI) { tq_load_rot<decltype(kI)::value>(AF[decltype(kI)::value], FB); });
+        double B[KS];
+        tq_for<KS>([&](auto sI) {
+            constexpr int q = decltype(sI)::value;
+            B[q] = tq_to_degree<n, q>(Y, g1, g2, lane);
         });
-    }
+        v4 acc[2];
+        tq_rotate<n>(AF[n], B, acc);
+        tq_for<KS>([&](auto qI) {
+            constexpr int q = decltype(qI)::value;
+            const int r = 4 * q + g, rc = min(r, 2 * n);
+            const double x = acc[q / 4][q % 4], y = tq_swap_pair(x);
+            const double re = im ? y : x, iv = im ? x : y;
+            const double2 e = phl[jl][rc - n + P - 1];  // times conj(e)
+            const double v = tq_run_sum(im ? fma(e.x, iv, -e.y * re) : fma(e.x, re, e.y * iv), col, end2);
+            if (starts && r < w) ((double *)(out + (int64_t)jl * P2 + n * n + r))[im] = v;
+        });
+    });
 }
 
 static_assert(TF_FR_STEP == 2 * 8 * 2 * 64 && TF_FR_ROT == (TF_PMAX / 2) * TF_FR_STEP, "rotation fragment layout");

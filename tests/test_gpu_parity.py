@@ -218,7 +218,7 @@ def test_matvec_fmm_vs_dense(F, cfg1_dense, leaf_max, lds_budget, lane, mfma, fu
     room, k = cfg1_dense
     ctx = make_ctx(F, room, k, leaf_max=leaf_max, lds_budget=lds_budget, lane_tiles=lane, mfma=mfma, fused=fused)
     if fused:
-        assert any(s["mfma"] in (2, 3) for s in ctx.fmmbem_batch_shapes())
+        assert any(s["mfma"] in (2, 4) for s in ctx.fmmbem_batch_shapes())
     info = ctx.fmmbem_get_info()
     L, M = bem.dense_LM(room.vertices, room.triangles, k, oracle_rc(ctx, room))
     for seed in (1, 2):
@@ -491,7 +491,7 @@ def test_fused_tiles_match_lane_tiles(F, prec):
     ctx0 = make_ctx(F, room, k, lane_tiles=2, mfma=0, fused=0)
     ctx1 = make_ctx(F, room, k, lane_tiles=2, mfma=0, fused=1)
     # the LDS-resident kernel also where the fixed rule picks the register-resident one (p = 16)
-    ctx1.fmmbem_set_batch_shapes([dict(d, mfma=2) for d in ctx1.fmmbem_batch_shapes() if d["mfma"] == 3])
+    ctx1.fmmbem_set_batch_shapes([dict(d, mfma=2) for d in ctx1.fmmbem_batch_shapes() if d["mfma"] == 4])
     sh = ctx1.fmmbem_batch_shapes()
     print("fused batches:", [(s["level"], s["kind"], s["jobs"]) for s in sh if s["mfma"] == 2])
     assert sum(s["mfma"] == 2 for s in sh) >= 3
@@ -519,12 +519,12 @@ def test_register_resident_tiles_vs_lane_tiles_and_oracle(F, mode):
     ctx_l = make_ctx(F, room, k, lane_tiles=2, mfma=0, fused=0)
     ctx_r = make_ctx(F, room, k, lane_tiles=2, mfma=0, fused=1)
     shapes = ctx_r.fmmbem_batch_shapes()
-    regs = [d for d in shapes if d["mfma"] == 3]
+    regs = [d for d in shapes if d["mfma"] == 4]
     print("register-resident batches:", [(d["level"], d["kind"], d["jobs"]) for d in regs])
     assert len(regs) >= 3
-    if mode == 4:
-        ctx_r.fmmbem_set_batch_shapes([dict(d, mfma=4) for d in regs])
-        assert sum(d["mfma"] == 4 for d in ctx_r.fmmbem_batch_shapes()) == len(regs)
+    if mode == 3:
+        ctx_r.fmmbem_set_batch_shapes([dict(d, mfma=3) for d in regs])
+        assert sum(d["mfma"] == 3 for d in ctx_r.fmmbem_batch_shapes()) == len(regs)
     X = np.stack([synth.complex_normal(room.n, 120 + s) for s in range(4)])
     y_l = ctx_l.fmmbem_matvec(X[0])[0]
     y_r = ctx_r.fmmbem_matvec(X[0])[0]
@@ -541,7 +541,7 @@ def test_register_resident_tiles_vs_lane_tiles_and_oracle(F, mode):
     ym_r = ctx_r.fmmbem_matvec(X[0], precision=F.FMMBEM_MIXED)[0]
     assert np.linalg.norm(ym_r - ym_l) / np.linalg.norm(ym_l) < 1e-5
     # a register-resident shape where p != 16 is rejected
-    bad = [dict(d, mfma=3) for d in shapes if d["lane"] and d["mfma"] != 3][:1]
+    bad = [dict(d, mfma=3) for d in shapes if d["lane"] and d["mfma"] != 4][:1]
     if bad:
         with pytest.raises(F.FmmbemError):
             ctx_r.fmmbem_set_batch_shapes(bad)
