@@ -285,16 +285,22 @@ int fmmbem_solve_dev(fmmbem_ctx *ctx, int32_t isrc, const fmmbem_solve_opts *opt
 int fmmbem_solve_batch(fmmbem_ctx *ctx, int32_t ns, const int32_t *isrc, const fmmbem_solve_opts *opts,
                        fmmbem_c64 *x, fmmbem_solve_report *rep);
 
-/* Solve independent systems (batching over frequencies, rooms, formulations): system i is source
- * isrc[i] of context ctxs[i] (distinct contexts, each with its own mesh, wavenumber, formulation
- * and options), solved by fmmbem_solve.  `threads` is reserved for solving the systems from
- * several host threads; that mode is switched off in this version (a 16-thread run crashed the
- * process) and the systems run one after another on the calling thread.  x[i] holds fmmbem_num_unknowns(ctxs[i]) values (in: initial guess if use_x0; out:
- * solution); opts is NULL (defaults) or holds count entries; rep[i] and status[i] receive each
- * solve's report and return code.  Every system runs; the result is FMMBEM_OK when all converged,
- * FMMBEM_ENOCONV when some reached maxit, else the error of the first failed system.  A repeated
- * or NULL context or a NULL argument returns FMMBEM_EINVAL before anything runs.  A context must
- * not be used by another host thread meanwhile. */
+/* Solve many systems together from the calling thread (batching over frequencies, sources, rooms,
+ * formulations): system i is source isrc[i] of context ctxs[i].  Systems of one context form a
+ * group that runs flexible GMRES in lock step with one batched product per step (as
+ * fmmbem_solve_batch; other formulations than Eq. dbem4 apply one product per system); the groups
+ * -- contexts of other frequencies or rooms, each with its own mesh, N, octree depth and truncation
+ * numbers -- advance in turn, each group's next product enqueued on its own streams as soon as its
+ * Arnoldi step is done and each Arnoldi step waiting for its own group's stream only, so several
+ * contexts' products are in flight on the device at once.  x[i] holds fmmbem_num_unknowns(ctxs[i])
+ * values (in: initial guess if use_x0; out: solution); opts is NULL (defaults) or holds count
+ * entries, equal for the systems of one context (else FMMBEM_EINVAL); inner_iters must be 0 and
+ * precond not FMMBEM_PC_LEARNED.  rep[i] and status[i] receive each system's report and code;
+ * rep[i].t_solve_s is the wall time of the whole call and the product counts are those of the
+ * system's context.  threads must be 0 or 1 (EINVAL otherwise: one host thread keeps every system
+ * in flight).  The result is FMMBEM_OK when all converged, FMMBEM_ENOCONV when some reached
+ * maxit, else the first error.  An argument error returns before anything runs.  The contexts
+ * must not be used by another host thread meanwhile. */
 int fmmbem_solve_many(int32_t count, fmmbem_ctx *const *ctxs, const int32_t *isrc, const fmmbem_solve_opts *opts,
                       fmmbem_c64 *const *x, fmmbem_solve_report *rep, int32_t *status, int32_t threads);
 

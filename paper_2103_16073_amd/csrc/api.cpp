@@ -2706,31 +2706,156 @@ int fmmbem_batch_shapes(fmmbem_ctx *ctx, int32_t max, fmmbem_batch_shape *out, i
 int fmmbem_solve_many(int32_t count, fmmbem_ctx *const *ctxs, const int32_t *isrc, const fmmbem_solve_opts *opts,
                       fmmbem_c64 *const *x, fmmbem_solve_report *rep, int32_t *status, int32_t threads) {
     if (count < 0 || (count > 0 && (!ctxs || !isrc || !x || !rep || !status))) return FMMBEM_EINVAL;
-    std::set<fmmbem_ctx *> seen;
-    for (int32_t i = 0; i < count; ++i)
-        if (!ctxs[i] || !x[i] || !seen.insert(ctxs[i]).second) return FMMBEM_EINVAL;  // one thread per context
-    // Concurrent solving from several host threads is switched off: a run with 16 threads crashed
-    // the process (host segmentation fault) while 4 threads had passed, and no cause in this
-    // library has been shown.  The systems run one after another on the calling thread.
-    (void)threads;
-    const int nt = count > 0 ? 1 : 0;
-    std::atomic<int> next{0};
-    auto work = [&]() {
-        for (;;) {
-            const int i = next.fetch_add(1);
-            if (i >= count) break;
-            status[i] = fmmbem_solve(ctxs[i], isrc[i], opts ? &opts[i] : nullptr, x[i], &rep[i]);
+    if (threads > 1) return FMMBEM_EINVAL;  // one host thread keeps every system in flight
+    for (int32_t i = 0; i < count; ++i) {
+        if (!ctxs[i] || !x[i]) return FMMBEM_EINVAL;
+        status[i] = FMMBEM_OK;
+    }
+    if (count == 0) return FMMBEM_OK;
+    // systems grouped by context, in order of first appearance; a group shares one set of options
+    std::vector<fmmbem_ctx *> order;
+    std::map<fmmbem_ctx *, std::vector<int>> members;
+    for (int32_t i = 0; i < count; ++i) {
+        if (!members.count(ctxs[i])) order.push_back(ctxs[i]);
+        members[ctxs[i]].push_back(i);
+    }
+    std::vector<fmmbem_solve_opts> gopt(order.size());
+    for (size_t q = 0; q < order.size(); ++q) {
+        fmmbem_ctx *ctx = order[q];
+        fmmbem_default_solve_opts(&gopt[q]);
+        const std::vector<int> &mem = members[ctx];
+        if (opts) gopt[q] = opts[mem[0]];
+        for (int i : mem)
+            if (opts && std::memcmp(&opts[i], &gopt[q], sizeof(fmmbem_solve_opts)) != 0) {
+                status[i] = fail(ctx, FMMBEM_EINVAL, "systems of one context need the same solve options");
+                return FMMBEM_EINVAL;
+            }
+        const fmmbem_solve_opts &o = gopt[q];
+        if (int e = check_solve_opts(ctx, o)) {
+            status[mem[0]] = e;
+            return e;
         }
-    };
-    std::vector<std::thread> pool;
-    for (int t = 1; t < nt; ++t) pool.emplace_back(work);
-    if (nt > 0) work();
-    for (auto &th : pool) th.join();
-    int rc = FMMBEM_OK;
-    for (int32_t i = 0; i < count; ++i)
-        if (status[i] < 0) return status[i];
-        else if (status[i] == FMMBEM_ENOCONV) rc = FMMBEM_ENOCONV;
-    return rc;
+        if (o.inner_iters > 0 || o.precond == FMMBEM_PC_LEARNED) {
+            status[mem[0]] = fail(ctx, FMMBEM_EINVAL, "fmmbem_solve_many has no inner-outer scheme and no learned guard");
+            return FMMBEM_EINVAL;
+        }
+        if (ctx->src.empty()) {
+            status[mem[0]] = fail(ctx, FMMBEM_ENOTREADY, "sources not set");
+            return FMMBEM_ENOTREADY;
+        }
+        for (int i : mem)
+            if (isrc[i] < 0 || isrc[i] >= (int)(ctx->src.size() / 3)) {
+                status[i] = fail(ctx, FMMBEM_EINVAL, "bad source index");
+                return FMMBEM_EINVAL;
+            }
+    }
+    fmmbem_ctx *ctx = nullptr;  // the context a failure is reported on
+    GUARD_BEGIN
+    std::vector<double> t_setup(order.size(), 0.0);
+    std::vector<FgmresGroup> groups(order.size());
+    std::vector<int64_t> n64(order.size(), 0), nmx(order.size(), 0);
+    std::vector<std::function<void(const double2 *, double2 *)>> pcs(order.size());
+    for (size_t q = 0; q < order.size(); ++q) {
+        ctx = order[q];
+        HIP_OK(hipSetDevice(ctx->device));
+        const bool dirty = ctx->mesh_dirty || ctx->k_dirty || ctx->beta_dirty;
+        ensure_setup(ctx);
+        if (dirty) t_setup[q] = ctx->t_setup_last;
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    for (size_t q = 0; q < order.size(); ++q) {
+        ctx = order[q];
+        fmmbem_ctx *c = ctx;
+        const fmmbem_solve_opts &o = gopt[q];
+        const std::vector<int> &mem = members[ctx];
+        const int nv = (int)mem.size();
+        const int64_t n = fmmbem_num_unknowns(ctx);
+        hipStream_t st = ctx->stream;
+        FgmresGroup &G = groups[q];
+        G.n = n;
+        G.st = st;
+        G.scr = &ctx->scratch;
+        G.tag = "many_";
+        G.nv = nv;
+        double2 *B = dget<double2>(ctx->scratch, "mb_b", (size_t)nv * n);
+        double2 *X = dget<double2>(ctx->scratch, "mb_x", (size_t)nv * n);
+        if (dpsi(ctx)) check_dpsi_beta(ctx);
+        for (int s = 0; s < nv; ++s) {
+            rhs_one(ctx, isrc[mem[s]], B + (int64_t)s * n);
+            if (o.use_x0) h2d_now(X + (int64_t)s * n, x[mem[s]], sizeof(double2) * n, st);
+        }
+        const bool mixed = o.precision == FMMBEM_MIXED;
+        const bool direct = !indirect(ctx) && !burton_miller(ctx) && !dpsi(ctx);
+        int64_t *c64 = &n64[q], *cmx = &nmx[q];
+        auto product = [c, direct, n](int nr, const double2 *a, double2 *y, bool mx) {
+            if (direct) matvec_dev(c, nr, a, y, false, mx);
+            else
+                for (int r = 0; r < nr; ++r) apply_operator(c, a + (int64_t)r * n, y + (int64_t)r * n, mx);
+        };
+        G.matvec = [product, mixed, c64, cmx](int nr, const double2 *a, double2 *y) {
+            product(nr, a, y, mixed);
+            (mixed ? *cmx : *c64) += nr;
+        };
+        G.matvec_check = [product, c64](int nr, const double2 *a, double2 *y) {
+            product(nr, a, y, false);
+            *c64 += nr;
+        };
+        pcs[q] = make_precond(ctx, o);
+        if (dpsi(ctx) && o.precond == FMMBEM_PC_NEARBLOCK) {
+            // Eq. (dbem5): leaf blocks of Eq. (dbem4) under the similarity diag(beta), as in fmmbem_solve
+            auto p4 = pcs[q];
+            double2 *tmp = dget<double2>(ctx->scratch, "d5_pc", n);
+            const int32_t *pm = (int32_t *)ctx->buf.find("perm");
+            const double2 *be = (double2 *)ctx->buf.find("beta");
+            pcs[q] = [=](const double2 *v, double2 *z) {
+                k_scale_beta<<<ceil_div(n, 256), 256, 0, st>>>(n, pm, be, 1, v, tmp);
+                LAUNCH_OK();
+                p4(tmp, z);
+                k_scale_beta<<<ceil_div(n, 256), 256, 0, st>>>(n, pm, be, 0, z, z);
+                LAUNCH_OK();
+            };
+        }
+        G.precond = pcs[q];
+        G.B = B;
+        G.X = X;
+        G.tol = o.tol;
+        G.m = o.restart;
+        G.maxit = o.maxit;
+        G.reorth = o.reorth;
+        G.x0_given = o.use_x0 != 0;
+        G.basis32 = o.basis_fp32 < 0 ? mixed : o.basis_fp32 != 0;
+    }
+    ctx = order[0];
+    fgmres_groups(groups);
+    const double ts = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    int worst = FMMBEM_OK;
+    for (size_t q = 0; q < order.size(); ++q) {
+        ctx = order[q];
+        const std::vector<int> &mem = members[ctx];
+        const int64_t n = fmmbem_num_unknowns(ctx);
+        const double2 *X = groups[q].X;
+        for (int s = 0; s < (int)mem.size(); ++s) {
+            const int i = mem[s];
+            HIP_OK(hipMemcpyAsync(x[i], X + (int64_t)s * n, sizeof(double2) * n, hipMemcpyDeviceToHost, ctx->stream));
+            status[i] = groups[q].status[s];
+            rep[i].iters = groups[q].iters[s];
+            rep[i].restarts = groups[q].restarts[s];
+            rep[i].rel_res = groups[q].rel_res[s];
+            rep[i].t_setup_s = t_setup[q];
+            rep[i].t_solve_s = ts;  // wall time of the whole call
+            rep[i].status = status[i];
+            rep[i].matvecs_fp64 = n64[q];  // products of the system's context
+            rep[i].matvecs_mixed = nmx[q];
+            rep[i].inner_iters = 0;
+            rep[i].pc_fallback_at = -1;
+            rep[i].matvecs_coarse = 0;
+            if (status[i] < 0) worst = status[i];
+            else if (status[i] == FMMBEM_ENOCONV && worst == FMMBEM_OK) worst = FMMBEM_ENOCONV;
+        }
+        HIP_OK(hipStreamSynchronize(ctx->stream));
+    }
+    return worst;
+    GUARD_END
 }
 
 int fmmbem_set_batch_shapes(fmmbem_ctx *ctx, int32_t count, const fmmbem_batch_shape *shapes) {

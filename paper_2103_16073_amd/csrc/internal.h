@@ -234,6 +234,26 @@ void gather_rows(int64_t B, int width, const int64_t *idx, const float *src, flo
 void vec_sub(int64_t n, const double2 *a, const double2 *b, double2 *out, hipStream_t st);
 void vec_add(int64_t n, const double2 *a, const double2 *b, double2 *out, hipStream_t st);
 
+// one group of systems of the lock-step FGMRES (fgmres_groups): nv systems sharing an operator,
+// their right-hand sides B and iterates X (nv x n, device), the products on stream st
+struct FgmresGroup {
+    int64_t n = 0;
+    hipStream_t st = nullptr;
+    DeviceBuffers *scr = nullptr;
+    std::string tag;  // scratch-name prefix of the group's Krylov bases
+    int nv = 0;
+    std::function<void(int, const double2 *, double2 *)> matvec, matvec_check;
+    std::function<void(const double2 *, double2 *)> precond;
+    const double2 *B = nullptr;
+    double2 *X = nullptr;
+    double tol = 1e-6;
+    int m = 30, maxit = 500, reorth = 1;
+    bool x0_given = false, basis32 = false;
+    std::vector<int> iters, restarts, status;  // per system (outputs)
+    std::vector<double> rel_res;
+};
+void fgmres_groups(std::vector<FgmresGroup> &groups);
+
 // optional observers of a flexible GMRES run
 struct FgmresHooks {
     std::function<void(const double2 *x, const double2 *r, double rel)> on_restart;  // true residual

@@ -529,10 +529,15 @@ int fgmres(int64_t n, hipStream_t st, DeviceBuffers &scr, const char *tag,
                              final_residual, history, iters, restarts, rel_res, hooks, reorth);
 }
 
-// Lock-step FGMRES over nv systems A x_s = b_s that share the operator: every step gathers the
-// preconditioned vectors of the systems still iterating and applies one batched product, so the
-// kernel evaluations, basis functions and translation tables of the FMM are shared between them.
-// Each system keeps its own Krylov basis, Hessenberg matrix and restarts, exactly as fgmres().
+// Lock-step FGMRES over groups of systems.  A group is nv systems A x_s = b_s that share one
+// operator (one context: the same mesh, wavenumber and admittance, one source each): every step of
+// a group gathers the preconditioned vectors of its systems still iterating and applies one batched
+// product, so the kernel evaluations, basis functions and translation tables of the FMM are shared
+// between them.  Each system keeps its own Krylov basis, Hessenberg matrix and restarts, exactly as
+// fgmres().  Several groups (contexts of other frequencies or rooms, each with its own N, octree and
+// truncation numbers) advance in turn from one host thread: a group's next product is enqueued on
+// its own streams as soon as its Arnoldi step is done, and a group's Arnoldi step waits for its own
+// stream only, so the products of the other groups keep the device busy meanwhile.
 template <class S>
 struct BatchSys {
     S *V = nullptr, *Z = nullptr;
@@ -544,169 +549,218 @@ struct BatchSys {
 };
 
 template <class T>
-static int fgmres_batch_t(int64_t n, hipStream_t st, DeviceBuffers &scr, int nv,
-                          const std::function<void(int, const double2 *, double2 *)> &matvec,
-                          const std::function<void(int, const double2 *, double2 *)> &matvec_check,
-                          const std::function<void(const double2 *, double2 *)> &precond, const double2 *B,
-                          double2 *X, double tol, int m, int maxit, bool x0_given, std::vector<int> &iters,
-                          std::vector<int> &restarts, std::vector<double> &rel_res, std::vector<int> &status,
-                          int reorth) {
-    constexpr bool wide = std::is_same<T, double2>::value;
-    Blas Bl{st, scr, n, "bt_"};
-    std::vector<BatchSys<T>> S(nv);
-    double2 *tv = wide ? nullptr : dget<double2>(scr, "bt_tv", n);
-    iters.assign(nv, 0);
-    restarts.assign(nv, 0);
-    rel_res.assign(nv, 1.0);
-    status.assign(nv, FMMBEM_ENOCONV);
-    double2 *Sin = dget<double2>(scr, "bt_in", (size_t)nv * n), *Sout = dget<double2>(scr, "bt_out", (size_t)nv * n);
-    for (int s = 0; s < nv; ++s) {
-        BatchSys<T> &q = S[s];
-        q.V = dget<T>(scr, (wide ? "bt_V" : "bt_V32_") + std::to_string(s), (size_t)(m + 1) * n);
-        q.Z = dget<T>(scr, (wide ? "bt_Z" : "bt_Z32_") + std::to_string(s), (size_t)m * n);
-        q.r = dget<double2>(scr, "bt_r" + std::to_string(s), n);
-        q.H.assign((size_t)(m + 1) * m, cmk(0, 0));
-        q.g.assign(m + 1, cmk(0, 0));
-        q.cs.assign(m, cmk(0, 0));
-        q.sn.assign(m, cmk(0, 0));
-        q.h1.assign(m + 1, cmk(0, 0));
-        q.h2.assign(m + 1, cmk(0, 0));
-        q.y.assign(m, cmk(0, 0));
-        double2 *x = X + (int64_t)s * n;
-        if (!x0_given) HIP_OK(hipMemsetAsync(x, 0, sizeof(double2) * n, st));
-        q.bn = Bl.nrm(B + (int64_t)s * n);
-        if (!(q.bn > 0.0)) {
-            HIP_OK(hipMemsetAsync(x, 0, sizeof(double2) * n, st));
-            rel_res[s] = 0.0;
-            status[s] = FMMBEM_OK;
-            q.done = true;
-        }
-    }
-    while (true) {
-        // 1. systems between cycles: true residual (batched FP64 product), convergence test, new cycle
-        std::vector<int> need;
-        for (int s = 0; s < nv; ++s)
-            if (!S[s].done && !S[s].in_cycle) need.push_back(s);
-        if (!need.empty()) {
-            std::vector<int> prod;
-            for (int s : need)
-                if (x0_given || S[s].cycle > 0) prod.push_back(s);
-            for (size_t k = 0; k < prod.size(); ++k)
-                HIP_OK(hipMemcpyAsync(Sin + k * n, X + (int64_t)prod[k] * n, sizeof(double2) * n,
-                                      hipMemcpyDeviceToDevice, st));
-            if (!prod.empty()) matvec_check((int)prod.size(), Sin, Sout);
-            for (size_t k = 0; k < prod.size(); ++k)
-                Bl.sub(B + (int64_t)prod[k] * n, Sout + k * n, S[prod[k]].r);
-            for (int s : need) {
-                BatchSys<T> &q = S[s];
-                if (!(x0_given || q.cycle > 0))
-                    HIP_OK(hipMemcpyAsync(q.r, B + (int64_t)s * n, sizeof(double2) * n, hipMemcpyDeviceToDevice, st));
-                const double beta = Bl.nrm(q.r);
-                rel_res[s] = beta / q.bn;
-                if (!std::isfinite(beta)) {
-                    status[s] = FMMBEM_ENAN;
-                    q.done = true;
-                    continue;
-                }
-                if (rel_res[s] < tol) {
-                    status[s] = FMMBEM_OK;
-                    q.done = true;
-                    continue;
-                }
-                if (iters[s] >= maxit) {
-                    q.done = true;
-                    continue;
-                }
-                Bl.scale_copy(1.0 / beta, q.r, q.V);
-                std::fill(q.g.begin(), q.g.end(), cmk(0, 0));
-                q.g[0] = cmk(beta, 0);
-                q.j = 0;
-                q.in_cycle = true;
+struct GroupSolver {
+    static constexpr bool wide = std::is_same<T, double2>::value;
+    FgmresGroup &G;
+    Blas Bl;
+    std::vector<BatchSys<T>> S;
+    double2 *tv = nullptr, *Sin = nullptr, *Sout = nullptr;
+    std::vector<int> act;  // systems whose product is in flight, in Sin/Sout order
+    bool started = false;
+    explicit GroupSolver(FgmresGroup &g) : G(g), Bl{g.st, *g.scr, g.n, g.tag + "bt_"} {}
+
+    void init() {
+        const int64_t n = G.n;
+        const int nv = G.nv, m = G.m;
+        S.assign(nv, BatchSys<T>());
+        tv = wide ? nullptr : dget<double2>(*G.scr, G.tag + "bt_tv", n);
+        G.iters.assign(nv, 0);
+        G.restarts.assign(nv, 0);
+        G.rel_res.assign(nv, 1.0);
+        G.status.assign(nv, FMMBEM_ENOCONV);
+        Sin = dget<double2>(*G.scr, G.tag + "bt_in", (size_t)nv * n);
+        Sout = dget<double2>(*G.scr, G.tag + "bt_out", (size_t)nv * n);
+        for (int s = 0; s < nv; ++s) {
+            BatchSys<T> &q = S[s];
+            const std::string id = G.tag + std::to_string(s);
+            q.V = dget<T>(*G.scr, (wide ? "bt_V" : "bt_V32_") + id, (size_t)(m + 1) * n);
+            q.Z = dget<T>(*G.scr, (wide ? "bt_Z" : "bt_Z32_") + id, (size_t)m * n);
+            q.r = dget<double2>(*G.scr, "bt_r" + id, n);
+            q.H.assign((size_t)(m + 1) * m, cmk(0, 0));
+            q.g.assign(m + 1, cmk(0, 0));
+            q.cs.assign(m, cmk(0, 0));
+            q.sn.assign(m, cmk(0, 0));
+            q.h1.assign(m + 1, cmk(0, 0));
+            q.h2.assign(m + 1, cmk(0, 0));
+            q.y.assign(m, cmk(0, 0));
+            double2 *x = G.X + (int64_t)s * n;
+            if (!G.x0_given) HIP_OK(hipMemsetAsync(x, 0, sizeof(double2) * n, G.st));
+            q.bn = Bl.nrm(G.B + (int64_t)s * n);
+            if (!(q.bn > 0.0)) {
+                HIP_OK(hipMemsetAsync(x, 0, sizeof(double2) * n, G.st));
+                G.rel_res[s] = 0.0;
+                G.status[s] = FMMBEM_OK;
+                q.done = true;
             }
         }
-        std::vector<int> act;
-        for (int s = 0; s < nv; ++s)
+    }
+
+    // systems between cycles: true residual (one batched FP64 product), convergence test, new cycle
+    void restarts() {
+        const int64_t n = G.n;
+        std::vector<int> need, prod;
+        for (int s = 0; s < G.nv; ++s)
+            if (!S[s].done && !S[s].in_cycle) need.push_back(s);
+        if (need.empty()) return;
+        for (int s : need)
+            if (G.x0_given || S[s].cycle > 0) prod.push_back(s);
+        for (size_t k = 0; k < prod.size(); ++k)
+            HIP_OK(hipMemcpyAsync(Sin + k * n, G.X + (int64_t)prod[k] * n, sizeof(double2) * n,
+                                  hipMemcpyDeviceToDevice, G.st));
+        if (!prod.empty()) G.matvec_check((int)prod.size(), Sin, Sout);
+        for (size_t k = 0; k < prod.size(); ++k) Bl.sub(G.B + (int64_t)prod[k] * n, Sout + k * n, S[prod[k]].r);
+        for (int s : need) {
+            BatchSys<T> &q = S[s];
+            if (!(G.x0_given || q.cycle > 0))
+                HIP_OK(hipMemcpyAsync(q.r, G.B + (int64_t)s * n, sizeof(double2) * n, hipMemcpyDeviceToDevice, G.st));
+            const double beta = Bl.nrm(q.r);
+            G.rel_res[s] = beta / q.bn;
+            if (!std::isfinite(beta)) {
+                G.status[s] = FMMBEM_ENAN;
+                q.done = true;
+                continue;
+            }
+            if (G.rel_res[s] < G.tol) {
+                G.status[s] = FMMBEM_OK;
+                q.done = true;
+                continue;
+            }
+            if (G.iters[s] >= G.maxit) {
+                q.done = true;
+                continue;
+            }
+            Bl.scale_copy(1.0 / beta, q.r, q.V);
+            std::fill(q.g.begin(), q.g.end(), cmk(0, 0));
+            q.g[0] = cmk(beta, 0);
+            q.j = 0;
+            q.in_cycle = true;
+        }
+    }
+
+    // Arnoldi step of system s on its product w; returns an error status or FMMBEM_OK
+    int arnoldi(int s, double2 *w) {
+        const int64_t n = G.n;
+        const int m = G.m;
+        BatchSys<T> &q = S[s];
+        auto Hc = [&](int i, int jj) -> double2 & { return q.H[(size_t)i * m + jj]; };
+        const int j = q.j;
+        ++G.iters[s];
+        const double w0 = G.reorth == 1 ? Bl.nrm(w) : 0.0;
+        Bl.dots(q.V, n, j + 1, w, q.h1.data());
+        Bl.sub_combo(q.V, n, j + 1, q.h1.data(), w);
+        double hn = Bl.nrm(w);
+        if (G.reorth == 2 || (G.reorth == 1 && !(hn > 0.7071067811865476 * w0))) {  // as in fgmres
+            Bl.dots(q.V, n, j + 1, w, q.h2.data());
+            Bl.sub_combo(q.V, n, j + 1, q.h2.data(), w);
+            for (int i = 0; i <= j; ++i) q.h1[i] = cadd(q.h1[i], q.h2[i]);
+            hn = Bl.nrm(w);
+        }
+        for (int i = 0; i <= j; ++i) Hc(i, j) = q.h1[i];
+        if (!std::isfinite(hn)) {
+            G.status[s] = FMMBEM_ENAN;
+            q.done = true;
+            q.in_cycle = false;
+            return FMMBEM_OK;
+        }
+        Hc(j + 1, j) = cmk(hn, 0);
+        if (hn > 0) Bl.scale_copy(1.0 / hn, w, q.V + (size_t)(j + 1) * n);
+        for (int i = 0; i < j; ++i) {
+            double2 a = Hc(i, j), c = Hc(i + 1, j);
+            Hc(i, j) = cadd(cscale(a, q.cs[i].x), cmul(q.sn[i], c));
+            Hc(i + 1, j) = csub(cscale(c, q.cs[i].x), cmul(cconj(q.sn[i]), a));
+        }
+        double2 a = Hc(j, j), c = Hc(j + 1, j);
+        const double den = hypot(cabs_(a), cabs_(c));
+        if (den == 0) {
+            q.cs[j] = cmk(1, 0);
+            q.sn[j] = cmk(0, 0);
+        } else {
+            const double aa = cabs_(a);
+            q.cs[j] = cmk(aa / den, 0);
+            const double2 ph = aa > 0 ? cscale(a, 1.0 / aa) : cmk(1, 0);
+            q.sn[j] = cscale(cmul(ph, cconj(c)), 1.0 / den);
+        }
+        Hc(j, j) = cadd(cscale(a, q.cs[j].x), cmul(q.sn[j], c));
+        Hc(j + 1, j) = cmk(0, 0);
+        q.g[j + 1] = cscale(cmul(cconj(q.sn[j]), q.g[j]), -1.0);
+        q.g[j] = cscale(q.g[j], q.cs[j].x);
+        q.est = cabs_(q.g[j + 1]) / q.bn;
+        q.j = j + 1;
+        if (q.est < G.tol || hn == 0 || q.j == m || G.iters[s] >= G.maxit) {
+            // end of cycle: x += Z y with y = H^{-1} g
+            const int jj = q.j;
+            for (int i = jj - 1; i >= 0; --i) {
+                double2 sum = q.g[i];
+                for (int t = i + 1; t < jj; ++t) sum = csub(sum, cmul(Hc(i, t), q.y[t]));
+                if (cabs_(Hc(i, i)) == 0) return FMMBEM_EBREAKDOWN;
+                q.y[i] = cdiv(sum, Hc(i, i));
+            }
+            Bl.add_combo(q.Z, n, jj, q.y.data(), G.X + (int64_t)s * n);
+            q.in_cycle = false;
+            ++q.cycle;
+            G.restarts[s] = q.cycle;
+        }
+        return FMMBEM_OK;
+    }
+
+    // One advance: the Arnoldi steps of the products in flight, restarts, and the next batched
+    // product enqueued.  Returns false once every system of the group has finished.
+    bool step() {
+        if (!started) {
+            init();
+            started = true;
+        }
+        for (size_t k = 0; k < act.size(); ++k)
+            if (int e = arnoldi(act[k], Sout + k * G.n)) throw FmmError(e, "batched solver breakdown");
+        act.clear();
+        restarts();
+        const int64_t n = G.n;
+        for (int s = 0; s < G.nv; ++s)
             if (S[s].in_cycle) act.push_back(s);
-        if (act.empty()) break;
-        // 2. one Arnoldi step for every active system, with a single batched product
+        if (act.empty()) return false;
         for (size_t k = 0; k < act.size(); ++k) {
             BatchSys<T> &q = S[act[k]];
             if constexpr (wide) {
-                precond(q.V + (size_t)q.j * n, q.Z + (size_t)q.j * n);
+                G.precond(q.V + (size_t)q.j * n, q.Z + (size_t)q.j * n);
                 HIP_OK(hipMemcpyAsync(Sin + k * n, q.Z + (size_t)q.j * n, sizeof(double2) * n,
-                                      hipMemcpyDeviceToDevice, st));
+                                      hipMemcpyDeviceToDevice, G.st));
             } else {
                 Bl.widen(q.V + (size_t)q.j * n, tv);
-                precond(tv, Sin + k * n);
+                G.precond(tv, Sin + k * n);
                 Bl.scale_copy(1.0, Sin + k * n, q.Z + (size_t)q.j * n);
             }
         }
-        matvec((int)act.size(), Sin, Sout);
-        for (size_t k = 0; k < act.size(); ++k) {
-            const int s = act[k];
-            BatchSys<T> &q = S[s];
-            auto Hc = [&](int i, int jj) -> double2 & { return q.H[(size_t)i * m + jj]; };
-            double2 *w = Sout + k * n;
-            const int j = q.j;
-            ++iters[s];
-            const double w0 = reorth == 1 ? Bl.nrm(w) : 0.0;
-            Bl.dots(q.V, n, j + 1, w, q.h1.data());
-            Bl.sub_combo(q.V, n, j + 1, q.h1.data(), w);
-            double hn = Bl.nrm(w);
-            if (reorth == 2 || (reorth == 1 && !(hn > 0.7071067811865476 * w0))) {  // as in fgmres
-                Bl.dots(q.V, n, j + 1, w, q.h2.data());
-                Bl.sub_combo(q.V, n, j + 1, q.h2.data(), w);
-                for (int i = 0; i <= j; ++i) q.h1[i] = cadd(q.h1[i], q.h2[i]);
-                hn = Bl.nrm(w);
-            }
-            for (int i = 0; i <= j; ++i) Hc(i, j) = q.h1[i];
-            if (!std::isfinite(hn)) {
-                status[s] = FMMBEM_ENAN;
-                q.done = true;
-                q.in_cycle = false;
-                continue;
-            }
-            Hc(j + 1, j) = cmk(hn, 0);
-            if (hn > 0) Bl.scale_copy(1.0 / hn, w, q.V + (size_t)(j + 1) * n);
-            for (int i = 0; i < j; ++i) {
-                double2 a = Hc(i, j), c = Hc(i + 1, j);
-                Hc(i, j) = cadd(cscale(a, q.cs[i].x), cmul(q.sn[i], c));
-                Hc(i + 1, j) = csub(cscale(c, q.cs[i].x), cmul(cconj(q.sn[i]), a));
-            }
-            double2 a = Hc(j, j), c = Hc(j + 1, j);
-            const double den = hypot(cabs_(a), cabs_(c));
-            if (den == 0) {
-                q.cs[j] = cmk(1, 0);
-                q.sn[j] = cmk(0, 0);
-            } else {
-                const double aa = cabs_(a);
-                q.cs[j] = cmk(aa / den, 0);
-                const double2 ph = aa > 0 ? cscale(a, 1.0 / aa) : cmk(1, 0);
-                q.sn[j] = cscale(cmul(ph, cconj(c)), 1.0 / den);
-            }
-            Hc(j, j) = cadd(cscale(a, q.cs[j].x), cmul(q.sn[j], c));
-            Hc(j + 1, j) = cmk(0, 0);
-            q.g[j + 1] = cscale(cmul(cconj(q.sn[j]), q.g[j]), -1.0);
-            q.g[j] = cscale(q.g[j], q.cs[j].x);
-            q.est = cabs_(q.g[j + 1]) / q.bn;
-            q.j = j + 1;
-            if (q.est < tol || hn == 0 || q.j == m || iters[s] >= maxit) {
-                // end of cycle: x += Z y with y = H^{-1} g
-                const int jj = q.j;
-                for (int i = jj - 1; i >= 0; --i) {
-                    double2 sum = q.g[i];
-                    for (int t = i + 1; t < jj; ++t) sum = csub(sum, cmul(Hc(i, t), q.y[t]));
-                    if (cabs_(Hc(i, i)) == 0) return FMMBEM_EBREAKDOWN;
-                    q.y[i] = cdiv(sum, Hc(i, i));
-                }
-                Bl.add_combo(q.Z, n, jj, q.y.data(), X + (int64_t)s * n);
-                q.in_cycle = false;
-                ++q.cycle;
-                restarts[s] = q.cycle;
-            }
+        G.matvec((int)act.size(), Sin, Sout);
+        return true;
+    }
+};
+
+void fgmres_groups(std::vector<FgmresGroup> &groups) {
+    std::vector<GroupSolver<double2>> wide;
+    std::vector<GroupSolver<float2>> narrow;
+    wide.reserve(groups.size());
+    narrow.reserve(groups.size());
+    std::vector<std::function<bool()>> steps;
+    for (auto &g : groups) {
+        if (g.basis32) {
+            narrow.emplace_back(g);
+            GroupSolver<float2> *p = &narrow.back();
+            steps.push_back([p]() { return p->step(); });
+        } else {
+            wide.emplace_back(g);
+            GroupSolver<double2> *p = &wide.back();
+            steps.push_back([p]() { return p->step(); });
         }
     }
-    return FMMBEM_OK;
+    std::vector<char> live(groups.size(), 1);
+    for (bool any = true; any;) {
+        any = false;
+        for (size_t q = 0; q < steps.size(); ++q)
+            if (live[q]) {
+                live[q] = steps[q]() ? 1 : 0;
+                any = any || live[q];
+            }
+    }
 }
 
 int fgmres_batch(int64_t n, hipStream_t st, DeviceBuffers &scr, int nv,
@@ -715,11 +769,29 @@ int fgmres_batch(int64_t n, hipStream_t st, DeviceBuffers &scr, int nv,
                  const std::function<void(const double2 *, double2 *)> &precond, const double2 *B, double2 *X,
                  double tol, int m, int maxit, bool x0_given, std::vector<int> &iters, std::vector<int> &restarts,
                  std::vector<double> &rel_res, std::vector<int> &status, bool basis32, int reorth) {
-    if (basis32)
-        return fgmres_batch_t<float2>(n, st, scr, nv, matvec, matvec_check, precond, B, X, tol, m, maxit, x0_given,
-                                      iters, restarts, rel_res, status, reorth);
-    return fgmres_batch_t<double2>(n, st, scr, nv, matvec, matvec_check, precond, B, X, tol, m, maxit, x0_given,
-                                   iters, restarts, rel_res, status, reorth);
+    std::vector<FgmresGroup> g(1);
+    FgmresGroup &q = g[0];
+    q.n = n;
+    q.st = st;
+    q.scr = &scr;
+    q.nv = nv;
+    q.matvec = matvec;
+    q.matvec_check = matvec_check;
+    q.precond = precond;
+    q.B = B;
+    q.X = X;
+    q.tol = tol;
+    q.m = m;
+    q.maxit = maxit;
+    q.x0_given = x0_given;
+    q.basis32 = basis32;
+    q.reorth = reorth;
+    fgmres_groups(g);
+    iters = q.iters;
+    restarts = q.restarts;
+    rel_res = q.rel_res;
+    status = q.status;
+    return FMMBEM_OK;
 }
 
 }  // namespace fmm

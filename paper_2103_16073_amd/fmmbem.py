@@ -428,9 +428,9 @@ class Context:
 
 
 def fmmbem_solve_many(ctxs, isrc, threads=0, **kw):
-    """Solve source isrc[i] of context ctxs[i] for every i (one after another: the library's
-    multi-threaded mode is switched off).  Returns (solutions, reports, per-system codes, overall
-    code)."""
+    """Solve source isrc[i] of context ctxs[i] for every i, all systems in flight together from the
+    calling thread (systems of one context in lock step with batched products).  Returns
+    (solutions, reports, per-system codes, overall code)."""
     count = len(ctxs)
     o = default_solve_opts()
     for k, v in kw.items():

@@ -120,6 +120,33 @@ def test_indirect_product_vs_dense(F, dense_ind, leaf_max):
     ctx.close()
 
 
+def test_indirect_full_size_rows_vs_oracle(F):
+    """The 6x5x3 m room at 1 kHz (N = 90,972, 181,944 unknowns) in the indirect formulation, a
+    different admittance on the + faces: both block rows of the FMM product (FP64 <= 1e-6, mixed
+    <= 1e-4) and of the right-hand side (1e-6) on 256 seeded rows against the oracle's matrix-free
+    rows of Eq. ibem5."""
+    room, k = synth.config_room(2)
+    n = room.n
+    beta_p = 0.5 * room.beta + 0.05
+    rs, _ = synth.source_and_receivers(room, 4)
+    ctx = make_ctx(F, room.vertices, room.triangles, k, room.beta, beta_p, rs=rs)
+    rc = oracle_rc(ctx, room)
+    x = synth.complex_normal(2 * n, 17)
+    rows = np.random.default_rng(12).choice(n, 256, replace=False)
+    r1, r2 = bem.indirect_matvec_rows(room.vertices, room.triangles, k, room.beta, beta_p, rc, x, rows)
+    for prec, tol in ((F.FMMBEM_FP64, 1e-6), (F.FMMBEM_MIXED, 1e-4)):
+        y = ctx.fmmbem_matvec(x, precision=prec)[0]
+        e1 = np.linalg.norm(y[rows] - r1) / np.linalg.norm(r1)
+        e2 = np.linalg.norm(y[n + rows] - r2) / np.linalg.norm(r2)
+        print(f"precision {prec}: row-1 {e1:.2e}, row-2 {e2:.2e}")
+        assert e1 < tol and e2 < tol
+    b = ctx.fmmbem_rhs()[0]
+    b1, b2 = bem.indirect_rhs_rows(room.vertices, room.triangles, k, room.beta, beta_p, rs[0], rc, rows)
+    assert np.linalg.norm(b[rows] - b1) / np.linalg.norm(b1) < 1e-6
+    assert np.linalg.norm(b[n + rows] - b2) / np.linalg.norm(b2) < 1e-6
+    ctx.close()
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_indirect_two_streams_match_one_stream(F, prec):
     """The indirect product on two streams (near field beside P2M and the translations) adds every
