@@ -121,6 +121,114 @@ def one_core_rows(workload, R):
         return None
 
 
+def sweep_workload(args):
+    """The frequency sweep of one room: the L-room at 64 frequencies log-spaced over 100 Hz - 2 kHz,
+    each meshed at 7 elements per wavelength (its own N, octree depth and truncation numbers:
+    N = 1,922 ... 612,540) with 4 source positions, 256 FGMRES solves to relative residual 1e-4
+    (mixed-precision products, FP32 Krylov vectors, FP64 restart and final residuals, near-field
+    leaf blocks).  The contexts, sorted by N, are solved in waves of at most `sweep_wave_n` elements
+    by fmmbem_solve_many: every system of a wave in flight from this one thread (the 4 sources of a
+    frequency in lock step with 4-vector products, the frequencies advancing in turn on their own
+    streams).  A few solutions are checked against the oracle's rows of Eq. dbem4."""
+    import numpy as np
+    from paper_2103_16073_amd import fmmbem as F
+    from paper_2103_16073_amd import synth
+    fs = [100.0 * 20.0 ** (i / 63.0) for i in range(64)]
+    rooms, ctxs = [], []
+    t_setup = 0.0
+    for f in fs:
+        room = synth.lroom(synth.SOUND_SPEED / (7.0 * f))
+        rs, _ = synth.source_and_receivers(room, 4, nsrc=4)
+        ctx = F.Context(0, autotune=0)
+        ctx.fmmbem_set_mesh(room.vertices, room.triangles)
+        ctx.fmmbem_set_wavenumber(synth.wavenumber(f))
+        ctx.fmmbem_set_admittance(room.beta)
+        ctx.fmmbem_set_sources(rs)
+        t0 = time.perf_counter()
+        ctx.fmmbem_setup()
+        t_setup += time.perf_counter() - t0
+        rooms.append((room, rs, f))
+        ctxs.append(ctx)
+    log(f"sweep: 64 contexts set up in {t_setup:.1f} s, N = {rooms[0][0].n} ... {rooms[-1][0].n}")
+    kw = dict(tol=1e-4, restart=args.sweep_restart, maxit=2 * args.sweep_restart, precision=F.FMMBEM_MIXED,
+              precond=F.FMMBEM_PC_NEARBLOCK)
+    waves, cur, ncur = [], [], 0
+    for i, (room, _, _) in enumerate(rooms):
+        if cur and ncur + room.n > args.sweep_wave_n:
+            waves.append(cur)
+            cur, ncur = [], 0
+        cur.append(i)
+        ncur += room.n
+    waves.append(cur)
+    sols, reports, t_solve = {}, {}, 0.0
+    for w in waves:
+        sc = [ctxs[i] for i in w for _ in range(4)]
+        ss = [s for _ in w for s in range(4)]
+        torch_sync()
+        t0 = time.perf_counter()
+        xs, reps, status, rc = F.fmmbem_solve_many(sc, ss, **kw)
+        dt = time.perf_counter() - t0
+        t_solve += dt
+        for q, (i, s) in enumerate(zip([i for i in w for _ in range(4)], ss)):
+            sols[(i, s)] = xs[q]
+            reports[(i, s)] = (status[q], reps[q].iters, reps[q].rel_res)
+        log(f"  wave of {len(w)} frequencies (N {rooms[w[0]][0].n}..{rooms[w[-1]][0].n}): {dt:.2f} s, "
+            f"iterations {min(r.iters for r in reps)}..{max(r.iters for r in reps)}, code {rc}")
+        for i in w:
+            ctxs[i].fmmbem_release_workspace()
+    # one wave of the small frequencies again, one context after another (fmmbem_solve_batch), for
+    # the gain of keeping several contexts in flight
+    w0 = waves[0]
+    for _ in range(2):  # the second round of each, with the work arrays already in place
+        torch_sync()
+        t0 = time.perf_counter()
+        for i in w0:
+            ctxs[i].fmmbem_solve_batch([0, 1, 2, 3], **kw)
+        t_seq0 = time.perf_counter() - t0
+        torch_sync()
+        t0 = time.perf_counter()
+        F.fmmbem_solve_many([ctxs[i] for i in w0 for _ in range(4)], [s for _ in w0 for s in range(4)], **kw)
+        t_many0 = time.perf_counter() - t0
+    log(f"first wave ({len(w0)} frequencies): one context at a time {t_seq0:.2f} s, all in flight {t_many0:.2f} s")
+    checks = []
+    if not args.no_cpu_baseline:
+        from oracle import bem
+        for i, s in ((0, 0), (31, 1), (63, 2)):
+            room, rs, f = rooms[i]
+            k = synth.wavenumber(f)
+            rc = bem.near_cutoff(room.vertices, room.triangles)
+            rows = np.random.default_rng(20 + i).choice(room.n, min(256, room.n), replace=False)
+            ax = bem.direct_matvec_rows(room.vertices, room.triangles, k, room.beta, rc, sols[(i, s)], rows)
+            b = bem.direct_rhs_rows(room.vertices, room.triangles, k, room.beta, rs[s], rc, rows)
+            r = float(np.linalg.norm(ax - b) / np.linalg.norm(b))
+            checks.append({"f_hz": f, "n": room.n, "source": s, "oracle_rows": int(len(rows)),
+                           "rel_residual_on_rows": r, "rel_residual_fp64_fmm": reports[(i, s)][2]})
+            log(f"  oracle rows, {f:.0f} Hz N {room.n} source {s}: |A x - b| / |b| = {r:.2e} "
+                f"(FMM FP64 residual {reports[(i, s)][2]:.2e})")
+    its = [v[1] for v in reports.values()]
+    ok = sum(1 for v in reports.values() if v[0] == 0)
+    result = {"metric": "FGMRES sweep: 64 frequencies x 4 sources to rel. residual 1e-4",
+              "value": t_solve, "unit": "s", "n_gpus": 1, "higher_is_better": False, "vs_baseline": None,
+              "dtype": "f64 residuals, f32 products", "data": "synthetic",
+              "config": {"workload": "L-room 6x5x3 + 4x3x3 m, baffle slab + doorway; 64 frequencies 100 Hz - 2 kHz "
+                                     "log-spaced, 7 elements per wavelength, 4 sources, direct BIE",
+                         "n_min": rooms[0][0].n, "n_max": rooms[-1][0].n, "n_total": sum(r[0].n for r in rooms),
+                         "restart": args.sweep_restart, "wave_n": args.sweep_wave_n, "waves": len(waves)},
+              "solves": len(reports), "converged": ok, "iterations": {"min": min(its), "max": max(its),
+                                                                       "mean": sum(its) / len(its)},
+              "setup_s": t_setup, "first_wave": {"frequencies": len(w0), "one_context_at_a_time_s": t_seq0,
+                                                 "all_in_flight_s": t_many0},
+              "oracle_checks": checks}
+    for c in ctxs:
+        c.close()
+    print(json.dumps(result))
+
+
+def torch_sync():
+    import torch
+    torch.cuda.synchronize()
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -137,7 +245,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", type=int, default=3, help="named room: 1, 2 or 3")
+    ap.add_argument("--workload", type=int, default=3,
+                    help="named room: 1, 2 or 3 (products and solves); 4: the 64-frequency, 4-source sweep")
+    ap.add_argument("--sweep-restart", type=int, default=120, help="Krylov dimension of the sweep's solves")
+    ap.add_argument("--sweep-wave-n", type=int, default=1000000,
+                    help="elements per wave of the sweep (contexts solved together by fmmbem_solve_many)")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -167,6 +279,9 @@ def main():
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(frequency/source sharding across GPUs is a design note only)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == 4:
+        sweep_workload(args)
+        return
 
     import numpy as np
     import torch

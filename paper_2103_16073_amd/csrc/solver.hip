@@ -555,14 +555,46 @@ struct GroupSolver {
     Blas Bl;
     std::vector<BatchSys<T>> S;
     double2 *tv = nullptr, *Sin = nullptr, *Sout = nullptr;
-    std::vector<int> act;  // systems whose product is in flight, in Sin/Sout order
-    bool started = false;
+    double2 *part = nullptr;             // partial sums of the inner products (one stream: shared)
+    double2 *dres = nullptr;             // per system: inner products (m + 1), |w_0|^2, |w|^2
+    double2 *dy = nullptr;               // per system: the coefficients y of x += Z y
+    double2 *hres = nullptr, *hy = nullptr;  // pinned host copies
+    std::vector<int> act;                // systems whose product is in flight, in Sin/Sout order
+    std::vector<char> second;            // per system: a second Gram-Schmidt pass this step
+    std::vector<int> need;               // systems whose true residual is being formed
+    bool pending = false;                // work enqueued whose results the host reads next
     explicit GroupSolver(FgmresGroup &g) : G(g), Bl{g.st, *g.scr, g.n, g.tag + "bt_"} {}
+    ~GroupSolver() {
+        if (hres) (void)hipHostFree(hres);
+        if (hy) (void)hipHostFree(hy);
+    }
+    int RS() const { return G.m + 3; }  // stride of dres / hres per system
+    double2 *res(int s) { return dres + (size_t)s * RS(); }
+    double2 *hr(int s) { return hres + (size_t)s * RS(); }
+
+    // inner products conj(V_v) w, v < nv, into out (device), enqueued only
+    template <class SV>
+    void dots_to(const SV *V, int64_t ldv, int nv, const double2 *w, double2 *out) {
+        const int nblk = (int)std::min<int64_t>(DOT_BLOCKS, std::max<int64_t>(1, (G.n + 255) / 256));
+        k_dot_partial<SV><<<dim3(nblk, (nv + DOT_G - 1) / DOT_G), 256, 0, G.st>>>(G.n, V, ldv, nv, w, part);
+        LAUNCH_OK();
+        k_dot_final<<<nv, 256, 0, G.st>>>(nblk, part, out);
+        LAUNCH_OK();
+    }
+    void to_host(int s) {  // the system's inner products and norms to the pinned copy
+        HIP_OK(hipMemcpyAsync(hr(s), res(s), sizeof(double2) * RS(), hipMemcpyDeviceToHost, G.st));
+        pending = true;
+    }
+    void wait() {
+        if (pending) HIP_OK(hipStreamSynchronize(G.st));
+        pending = false;
+    }
 
     void init() {
         const int64_t n = G.n;
         const int nv = G.nv, m = G.m;
         S.assign(nv, BatchSys<T>());
+        second.assign(nv, 0);
         tv = wide ? nullptr : dget<double2>(*G.scr, G.tag + "bt_tv", n);
         G.iters.assign(nv, 0);
         G.restarts.assign(nv, 0);
@@ -570,6 +602,11 @@ struct GroupSolver {
         G.status.assign(nv, FMMBEM_ENOCONV);
         Sin = dget<double2>(*G.scr, G.tag + "bt_in", (size_t)nv * n);
         Sout = dget<double2>(*G.scr, G.tag + "bt_out", (size_t)nv * n);
+        part = dget<double2>(*G.scr, G.tag + "bt_part", (size_t)DOT_BLOCKS * (m + 1));
+        dres = dget<double2>(*G.scr, G.tag + "bt_res", (size_t)nv * RS());
+        dy = dget<double2>(*G.scr, G.tag + "bt_y", (size_t)nv * (m + 1));
+        HIP_OK(hipHostMalloc((void **)&hres, sizeof(double2) * nv * RS()));
+        HIP_OK(hipHostMalloc((void **)&hy, sizeof(double2) * nv * (m + 1)));
         for (int s = 0; s < nv; ++s) {
             BatchSys<T> &q = S[s];
             const std::string id = G.tag + std::to_string(s);
@@ -585,9 +622,16 @@ struct GroupSolver {
             q.y.assign(m, cmk(0, 0));
             double2 *x = G.X + (int64_t)s * n;
             if (!G.x0_given) HIP_OK(hipMemsetAsync(x, 0, sizeof(double2) * n, G.st));
-            q.bn = Bl.nrm(G.B + (int64_t)s * n);
+            dots_to(G.B + (int64_t)s * n, 0, 1, G.B + (int64_t)s * n, res(s) + m + 2);
+            to_host(s);
+        }
+    }
+    void init_done() {
+        for (int s = 0; s < G.nv; ++s) {
+            BatchSys<T> &q = S[s];
+            q.bn = sqrt(std::max(hr(s)[G.m + 2].x, 0.0));
             if (!(q.bn > 0.0)) {
-                HIP_OK(hipMemsetAsync(x, 0, sizeof(double2) * n, G.st));
+                HIP_OK(hipMemsetAsync(G.X + (int64_t)s * G.n, 0, sizeof(double2) * G.n, G.st));
                 G.rel_res[s] = 0.0;
                 G.status[s] = FMMBEM_OK;
                 q.done = true;
@@ -595,10 +639,11 @@ struct GroupSolver {
         }
     }
 
-    // systems between cycles: true residual (one batched FP64 product), convergence test, new cycle
-    void restarts() {
+    // ---- restarts: systems between cycles get their true residual (one batched FP64 product)
+    void restart_products() {
         const int64_t n = G.n;
-        std::vector<int> need, prod;
+        need.clear();
+        std::vector<int> prod;
         for (int s = 0; s < G.nv; ++s)
             if (!S[s].done && !S[s].in_cycle) need.push_back(s);
         if (need.empty()) return;
@@ -613,7 +658,14 @@ struct GroupSolver {
             BatchSys<T> &q = S[s];
             if (!(G.x0_given || q.cycle > 0))
                 HIP_OK(hipMemcpyAsync(q.r, G.B + (int64_t)s * n, sizeof(double2) * n, hipMemcpyDeviceToDevice, G.st));
-            const double beta = Bl.nrm(q.r);
+            dots_to(q.r, 0, 1, q.r, res(s) + G.m + 2);
+            to_host(s);
+        }
+    }
+    void restart_decide() {
+        for (int s : need) {
+            BatchSys<T> &q = S[s];
+            const double beta = sqrt(std::max(hr(s)[G.m + 2].x, 0.0));
             G.rel_res[s] = beta / q.bn;
             if (!std::isfinite(beta)) {
                 G.status[s] = FMMBEM_ENAN;
@@ -635,86 +687,13 @@ struct GroupSolver {
             q.j = 0;
             q.in_cycle = true;
         }
+        need.clear();
     }
 
-    // Arnoldi step of system s on its product w; returns an error status or FMMBEM_OK
-    int arnoldi(int s, double2 *w) {
+    // ---- the next batched product of the systems in a cycle
+    bool products() {
         const int64_t n = G.n;
-        const int m = G.m;
-        BatchSys<T> &q = S[s];
-        auto Hc = [&](int i, int jj) -> double2 & { return q.H[(size_t)i * m + jj]; };
-        const int j = q.j;
-        ++G.iters[s];
-        const double w0 = G.reorth == 1 ? Bl.nrm(w) : 0.0;
-        Bl.dots(q.V, n, j + 1, w, q.h1.data());
-        Bl.sub_combo(q.V, n, j + 1, q.h1.data(), w);
-        double hn = Bl.nrm(w);
-        if (G.reorth == 2 || (G.reorth == 1 && !(hn > 0.7071067811865476 * w0))) {  // as in fgmres
-            Bl.dots(q.V, n, j + 1, w, q.h2.data());
-            Bl.sub_combo(q.V, n, j + 1, q.h2.data(), w);
-            for (int i = 0; i <= j; ++i) q.h1[i] = cadd(q.h1[i], q.h2[i]);
-            hn = Bl.nrm(w);
-        }
-        for (int i = 0; i <= j; ++i) Hc(i, j) = q.h1[i];
-        if (!std::isfinite(hn)) {
-            G.status[s] = FMMBEM_ENAN;
-            q.done = true;
-            q.in_cycle = false;
-            return FMMBEM_OK;
-        }
-        Hc(j + 1, j) = cmk(hn, 0);
-        if (hn > 0) Bl.scale_copy(1.0 / hn, w, q.V + (size_t)(j + 1) * n);
-        for (int i = 0; i < j; ++i) {
-            double2 a = Hc(i, j), c = Hc(i + 1, j);
-            Hc(i, j) = cadd(cscale(a, q.cs[i].x), cmul(q.sn[i], c));
-            Hc(i + 1, j) = csub(cscale(c, q.cs[i].x), cmul(cconj(q.sn[i]), a));
-        }
-        double2 a = Hc(j, j), c = Hc(j + 1, j);
-        const double den = hypot(cabs_(a), cabs_(c));
-        if (den == 0) {
-            q.cs[j] = cmk(1, 0);
-            q.sn[j] = cmk(0, 0);
-        } else {
-            const double aa = cabs_(a);
-            q.cs[j] = cmk(aa / den, 0);
-            const double2 ph = aa > 0 ? cscale(a, 1.0 / aa) : cmk(1, 0);
-            q.sn[j] = cscale(cmul(ph, cconj(c)), 1.0 / den);
-        }
-        Hc(j, j) = cadd(cscale(a, q.cs[j].x), cmul(q.sn[j], c));
-        Hc(j + 1, j) = cmk(0, 0);
-        q.g[j + 1] = cscale(cmul(cconj(q.sn[j]), q.g[j]), -1.0);
-        q.g[j] = cscale(q.g[j], q.cs[j].x);
-        q.est = cabs_(q.g[j + 1]) / q.bn;
-        q.j = j + 1;
-        if (q.est < G.tol || hn == 0 || q.j == m || G.iters[s] >= G.maxit) {
-            // end of cycle: x += Z y with y = H^{-1} g
-            const int jj = q.j;
-            for (int i = jj - 1; i >= 0; --i) {
-                double2 sum = q.g[i];
-                for (int t = i + 1; t < jj; ++t) sum = csub(sum, cmul(Hc(i, t), q.y[t]));
-                if (cabs_(Hc(i, i)) == 0) return FMMBEM_EBREAKDOWN;
-                q.y[i] = cdiv(sum, Hc(i, i));
-            }
-            Bl.add_combo(q.Z, n, jj, q.y.data(), G.X + (int64_t)s * n);
-            q.in_cycle = false;
-            ++q.cycle;
-            G.restarts[s] = q.cycle;
-        }
-        return FMMBEM_OK;
-    }
-
-    // One advance: the Arnoldi steps of the products in flight, restarts, and the next batched
-    // product enqueued.  Returns false once every system of the group has finished.
-    bool step() {
-        if (!started) {
-            init();
-            started = true;
-        }
-        for (size_t k = 0; k < act.size(); ++k)
-            if (int e = arnoldi(act[k], Sout + k * G.n)) throw FmmError(e, "batched solver breakdown");
         act.clear();
-        restarts();
-        const int64_t n = G.n;
         for (int s = 0; s < G.nv; ++s)
             if (S[s].in_cycle) act.push_back(s);
         if (act.empty()) return false;
@@ -733,34 +712,174 @@ struct GroupSolver {
         G.matvec((int)act.size(), Sin, Sout);
         return true;
     }
+
+    // ---- Arnoldi step of every system in flight, in phases (the host reads between phases)
+    // 1: first classical Gram-Schmidt pass: h = V^H w (and |w|^2 for the second-pass test)
+    void gs_dots() {
+        for (size_t k = 0; k < act.size(); ++k) {
+            const int s = act[k];
+            BatchSys<T> &q = S[s];
+            double2 *w = Sout + k * G.n;
+            ++G.iters[s];
+            if (G.reorth == 1) dots_to(w, 0, 1, w, res(s) + G.m + 1);
+            dots_to(q.V, G.n, q.j + 1, w, res(s));
+            to_host(s);
+        }
+    }
+    // 2: w -= V h, then |w|^2
+    void gs_update() {
+        for (size_t k = 0; k < act.size(); ++k) {
+            const int s = act[k];
+            BatchSys<T> &q = S[s];
+            double2 *w = Sout + k * G.n;
+            for (int i = 0; i <= q.j; ++i) q.h1[i] = hr(s)[i];
+            k_sub_combo<T><<<ceil_div(G.n, 256), 256, 0, G.st>>>(G.n, q.V, G.n, q.j + 1, res(s), w);
+            LAUNCH_OK();
+            dots_to(w, 0, 1, w, res(s) + G.m + 2);
+            to_host(s);
+        }
+    }
+    // 3: a second pass where the first removed most of w (Daniel-Gragg-Kaufman-Stewart), as in fgmres
+    bool gs_second_dots() {
+        bool any = false;
+        for (size_t k = 0; k < act.size(); ++k) {
+            const int s = act[k];
+            BatchSys<T> &q = S[s];
+            const double w0 = sqrt(std::max(hr(s)[G.m + 1].x, 0.0)), hn = sqrt(std::max(hr(s)[G.m + 2].x, 0.0));
+            second[s] = G.reorth == 2 || (G.reorth == 1 && !(hn > 0.7071067811865476 * w0));
+            if (!second[s]) continue;
+            dots_to(q.V, G.n, q.j + 1, Sout + k * G.n, res(s));
+            to_host(s);
+            any = true;
+        }
+        return any;
+    }
+    void gs_second_update() {
+        for (size_t k = 0; k < act.size(); ++k) {
+            const int s = act[k];
+            if (!second[s]) continue;
+            BatchSys<T> &q = S[s];
+            double2 *w = Sout + k * G.n;
+            for (int i = 0; i <= q.j; ++i) q.h2[i] = hr(s)[i];
+            k_sub_combo<T><<<ceil_div(G.n, 256), 256, 0, G.st>>>(G.n, q.V, G.n, q.j + 1, res(s), w);
+            LAUNCH_OK();
+            dots_to(w, 0, 1, w, res(s) + G.m + 2);
+            to_host(s);
+        }
+    }
+    // 4: Hessenberg column, Givens rotations, the next basis vector; at the end of a cycle x += Z y
+    void gs_finish() {
+        const int m = G.m;
+        for (size_t k = 0; k < act.size(); ++k) {
+            const int s = act[k];
+            BatchSys<T> &q = S[s];
+            auto Hc = [&](int i, int jj) -> double2 & { return q.H[(size_t)i * m + jj]; };
+            const int j = q.j;
+            double2 *w = Sout + k * G.n;
+            if (second[s])
+                for (int i = 0; i <= j; ++i) q.h1[i] = cadd(q.h1[i], q.h2[i]);
+            const double hn = sqrt(std::max(hr(s)[m + 2].x, 0.0));
+            for (int i = 0; i <= j; ++i) Hc(i, j) = q.h1[i];
+            if (!std::isfinite(hn) || !std::isfinite(hr(s)[m + 2].x)) {
+                G.status[s] = FMMBEM_ENAN;
+                q.done = true;
+                q.in_cycle = false;
+                continue;
+            }
+            Hc(j + 1, j) = cmk(hn, 0);
+            if (hn > 0) Bl.scale_copy(1.0 / hn, w, q.V + (size_t)(j + 1) * G.n);
+            for (int i = 0; i < j; ++i) {
+                double2 a = Hc(i, j), c = Hc(i + 1, j);
+                Hc(i, j) = cadd(cscale(a, q.cs[i].x), cmul(q.sn[i], c));
+                Hc(i + 1, j) = csub(cscale(c, q.cs[i].x), cmul(cconj(q.sn[i]), a));
+            }
+            double2 a = Hc(j, j), c = Hc(j + 1, j);
+            const double den = hypot(cabs_(a), cabs_(c));
+            if (den == 0) {
+                q.cs[j] = cmk(1, 0);
+                q.sn[j] = cmk(0, 0);
+            } else {
+                const double aa = cabs_(a);
+                q.cs[j] = cmk(aa / den, 0);
+                const double2 ph = aa > 0 ? cscale(a, 1.0 / aa) : cmk(1, 0);
+                q.sn[j] = cscale(cmul(ph, cconj(c)), 1.0 / den);
+            }
+            Hc(j, j) = cadd(cscale(a, q.cs[j].x), cmul(q.sn[j], c));
+            Hc(j + 1, j) = cmk(0, 0);
+            q.g[j + 1] = cscale(cmul(cconj(q.sn[j]), q.g[j]), -1.0);
+            q.g[j] = cscale(q.g[j], q.cs[j].x);
+            q.est = cabs_(q.g[j + 1]) / q.bn;
+            q.j = j + 1;
+            if (q.est < G.tol || hn == 0 || q.j == m || G.iters[s] >= G.maxit) {
+                // end of cycle: x += Z y with y = H^{-1} g
+                const int jj = q.j;
+                for (int i = jj - 1; i >= 0; --i) {
+                    double2 sum = q.g[i];
+                    for (int t = i + 1; t < jj; ++t) sum = csub(sum, cmul(Hc(i, t), q.y[t]));
+                    if (cabs_(Hc(i, i)) == 0) throw FmmError(FMMBEM_EBREAKDOWN, "batched solver breakdown");
+                    q.y[i] = cdiv(sum, Hc(i, i));
+                }
+                double2 *hys = hy + (size_t)s * (m + 1);
+                for (int i = 0; i < jj; ++i) hys[i] = q.y[i];
+                double2 *dys = dy + (size_t)s * (m + 1);
+                HIP_OK(hipMemcpyAsync(dys, hys, sizeof(double2) * jj, hipMemcpyHostToDevice, G.st));
+                k_add_combo<T><<<ceil_div(G.n, 256), 256, 0, G.st>>>(G.n, q.Z, G.n, jj, dys, G.X + (int64_t)s * G.n);
+                LAUNCH_OK();
+                q.in_cycle = false;
+                ++q.cycle;
+                G.restarts[s] = q.cycle;
+            }
+        }
+        // the pinned coefficients of a cycle's end are read by the copies above before the next
+        // phase that could rewrite them (a later cycle of the same system, after several waits)
+    }
 };
 
+// Every phase is enqueued for all groups before the host waits for any, so one host round trip
+// serves every system of every group and the groups' kernels overlap on the device.
 void fgmres_groups(std::vector<FgmresGroup> &groups) {
     std::vector<GroupSolver<double2>> wide;
     std::vector<GroupSolver<float2>> narrow;
     wide.reserve(groups.size());
     narrow.reserve(groups.size());
-    std::vector<std::function<bool()>> steps;
     for (auto &g : groups) {
-        if (g.basis32) {
-            narrow.emplace_back(g);
-            GroupSolver<float2> *p = &narrow.back();
-            steps.push_back([p]() { return p->step(); });
-        } else {
-            wide.emplace_back(g);
-            GroupSolver<double2> *p = &wide.back();
-            steps.push_back([p]() { return p->step(); });
+        if (g.basis32) narrow.emplace_back(g);
+        else wide.emplace_back(g);
+    }
+    auto all = [&](auto &&f) {
+        for (auto &g : wide) f(g);
+        for (auto &g : narrow) f(g);
+    };
+    auto any_of = [&](auto &&f) {
+        bool r = false;
+        for (auto &g : wide) r = f(g) || r;
+        for (auto &g : narrow) r = f(g) || r;
+        return r;
+    };
+    auto wait_all = [&]() { all([](auto &g) { g.wait(); }); };
+    all([](auto &g) { g.init(); });
+    wait_all();
+    all([](auto &g) { g.init_done(); });
+    all([](auto &g) { g.restart_products(); });
+    wait_all();
+    all([](auto &g) { g.restart_decide(); });
+    while (any_of([](auto &g) { return g.products(); })) {
+        all([](auto &g) { g.gs_dots(); });
+        wait_all();
+        all([](auto &g) { g.gs_update(); });
+        wait_all();
+        if (any_of([](auto &g) { return g.gs_second_dots(); })) {
+            wait_all();
+            all([](auto &g) { g.gs_second_update(); });
+            wait_all();
         }
+        all([](auto &g) { g.gs_finish(); });
+        all([](auto &g) { g.restart_products(); });
+        wait_all();
+        all([](auto &g) { g.restart_decide(); });
     }
-    std::vector<char> live(groups.size(), 1);
-    for (bool any = true; any;) {
-        any = false;
-        for (size_t q = 0; q < steps.size(); ++q)
-            if (live[q]) {
-                live[q] = steps[q]() ? 1 : 0;
-                any = any || live[q];
-            }
-    }
+    wait_all();
+    all([](auto &g) { HIP_OK(hipStreamSynchronize(g.G.st)); });
 }
 
 int fgmres_batch(int64_t n, hipStream_t st, DeviceBuffers &scr, int nv,
