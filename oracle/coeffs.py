@@ -42,6 +42,27 @@ def legendre_bar(nmax, x):
     return P
 
 
+def legendre_order(nmax, m, x):
+    """Column m of legendre_bar: P[n] = P_n^m for n = 0..nmax (zero for n < m), the same
+    recurrences evaluated for one order only."""
+    x = np.asarray(x, float)
+    s = np.sqrt(np.maximum(0.0, 1.0 - x * x))
+    P = np.zeros((nmax + 1,) + x.shape)
+    pmm = np.full(x.shape, 1.0 / np.sqrt(4 * np.pi))
+    for q in range(1, m + 1):
+        pmm = np.sqrt((2 * q + 1) / (2.0 * q)) * s * pmm
+    if m > nmax:
+        return P
+    P[m] = pmm
+    if m + 1 <= nmax:
+        P[m + 1] = np.sqrt(2 * m + 3.0) * x * pmm
+    for n in range(m + 2, nmax + 1):
+        a = np.sqrt((4.0 * n * n - 1) / (n * n - m * m))
+        b = np.sqrt(((n - 1.0) ** 2 - m * m) * (2 * n + 1) / ((2 * n - 3) * (n * n - m * m)))
+        P[n] = a * x * P[n - 1] - b * P[n - 2]
+    return P
+
+
 def Y(nmax, pts):
     """Y[..., idx(n,m)] for points (..., 3) (direction only)."""
     pts = np.asarray(pts, float)
@@ -116,6 +137,37 @@ def coaxial_projection(kind, k, tau, p, m, rows=None):
             jj = jn(nn, k * rho)
             for n in range(m, p):
                 out[nn, n] = 2 * np.pi * np.sum(wg * B[:, idx(n, m)] * np.conj(Yr[:, idx(nn, m)])) / jj
+    return out
+
+
+def coaxial_projection_order(kind, k, tau, p, m, rows=None):
+    """coaxial_projection evaluated with order m of the basis only (the projection points lie at
+    azimuth 0, where Y_n^m reduces to P_n^m(cos theta)): the same definition at a cost linear in
+    p per point, for the high truncation numbers of the top octree levels."""
+    m = abs(m)
+    rows = list(range(m, p)) if rows is None else list(rows)
+    rho_max = 0.6 * tau if kind == "SR" else max(1.5 * tau, (p + 10) / k)
+    cands = rho_max * np.linspace(0.15, 1.0, 12)
+    out = np.zeros((p, p), np.complex128)
+    choice = {}
+    for nn in rows:
+        vals = np.abs(jn(nn, k * cands))
+        choice.setdefault(int(np.argmax(vals)), []).append(nn)
+    for ci, nns in choice.items():
+        rho = cands[ci]
+        Q = 2 * p + int(2 * k * (rho + tau)) + 80
+        xg, wg = np.polynomial.legendre.leggauss(Q)
+        # points in the x-z half plane (azimuth 0): Y_n^m there is P_n^m(cos theta) alone, so only
+        # order m of the basis is needed, at the points and at the points shifted by tau along z
+        sh_z = rho * xg + tau
+        sh_r = np.sqrt(rho * rho * (1 - xg ** 2) + sh_z ** 2)
+        Psh = legendre_order(p - 1, m, sh_z / sh_r)
+        Pr = legendre_order(p - 1, m, xg)
+        f = jn if kind == "RR" else hn
+        for nn in nns:
+            jj = jn(nn, k * rho)
+            for n in range(m, p):
+                out[nn, n] = 2 * np.pi * np.sum(wg * f(n, k * sh_r) * Psh[n] * Pr[nn]) / jj
     return out
 
 

@@ -690,7 +690,9 @@ static void run_batch(fmmbem_ctx *c, int nrv, const TransBatch &b0, const typena
     // work rows per stream, so that batches on the two streams never share them
     const bool side = st == c->side;
     C *W1 = (C *)c->scratch.get(side ? "W1s" : "W1", sizeof(C) * (size_t)b.njob * nrv * b.P * b.P);
-    C *W2 = (C *)c->scratch.get(side ? "W2s" : "W2", sizeof(C) * (size_t)b.njob * nrv * b.P * b.P);
+    // the fused kernels keep the intermediate rows on chip: no second work array
+    const bool fused = b.lane && b.mfma >= 2;
+    C *W2 = fused ? nullptr : (C *)c->scratch.get(side ? "W2s" : "W2", sizeof(C) * (size_t)b.njob * nrv * b.P * b.P);
     const double nr = (double)b.nreal * nrv, P2 = (double)b.P * b.P, cs = (double)sizeof(C);
     // Algorithmic work per stage, the method's own: flops of the matrices applied (rotation,
     // coaxial step, rotation; the reduction's additions) and compulsory HBM bytes -- every distinct

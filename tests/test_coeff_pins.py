@@ -66,3 +66,24 @@ def test_rotation_degree_one_explicit():
     Binv = np.linalg.inv(B)
     T_exp = B @ Q.T @ Binv
     assert np.max(np.abs(T - T_exp)) < 1e-13
+
+
+def test_order_only_projection_equals_full_projection():
+    """The order-only evaluation of the projection agrees with the full one (p = 14, several m)."""
+    for kind, ktau in (("SR", 5.0), ("RR", 3.0), ("SR", 12.0)):
+        for m in (0, 3, 9):
+            A = C.coaxial_projection(kind, 1.0, ktau, 14, m)
+            B = C.coaxial_projection_order(kind, 1.0, ktau, 14, m)
+            assert np.max(np.abs(A - B)) < 1e-9 * np.max(np.abs(A)), (kind, ktau, m)
+
+
+def test_order_only_projection_zonal_closed_form_high_degree():
+    """Eq. (shft1) at the truncation numbers of the top level of the 5 kHz room (p = 255,
+    k tau = 600): (S|R)^0_{n'0} = (-1)^n' sqrt(2n'+1) h_n'(k tau) and the (R|R) analogue."""
+    p, kt = 255, 600.0
+    rows = [0, 97, 180, 254]
+    for kind, f in (("SR", C.hn), ("RR", C.jn)):
+        T = C.coaxial_projection_order(kind, 1.0, kt, p, 0, rows=rows)
+        for nn in rows:
+            ref = (-1) ** nn * np.sqrt(2 * nn + 1) * f(nn, kt)
+            assert abs(T[nn, 0] - ref) < 1e-8 * abs(ref), (kind, nn, T[nn, 0], ref)

@@ -65,6 +65,22 @@ def test_coaxial_stable_at_high_ktau(F):
     assert np.max(np.abs(orig[m] - ref)) > 1.0
 
 
+@pytest.mark.parametrize("kind,ktau,ms", [("SR", 600.0, (0, 100, 200)), ("RR", 100.0, (0, 120, 230))])
+def test_coaxial_table_top_level_of_5khz_room(F, kind, ktau, ms):
+    """The stabilised recursion at the truncation number of the top level of the 5 kHz L-room (p =
+    255; M2L k tau from about 460, M2M/L2L k tau about 100) against the projection definition on a
+    few rows of several orders (errors against the table's scale, as above)."""
+    p = 255
+    blocks = F.fmmbem_coaxial_table(0 if kind == "SR" else 1, ktau, p)
+    scale = np.max(np.abs(blocks[0]))
+    for m in ms:
+        rows = sorted({m, m + 40, m + 90, p - 1} & set(range(m, p)))
+        ref = OC.coaxial_projection_order(kind, 1.0, ktau, p, m, rows=rows)
+        for nn in rows:
+            err = np.max(np.abs(blocks[m][nn - m] - ref[nn, m:]))
+            assert err < 1e-8 * scale, (m, nn, err / scale)
+
+
 def test_rotation_table_vs_projection(F):
     p = 10
     D = F.fmmbem_rotation_table(p)
@@ -662,6 +678,28 @@ def test_matvec_fmm_sampled_rows_full_size(F, cfg, nrows):
           f"mixed {err_m:.3e}")
     assert err < 1e-6
     assert err_m < 1e-4
+    ctx.close()
+
+
+def test_matvec_sampled_rows_6M_5khz(F):
+    """The L-room at 5 kHz meshed at 0.779 cm (N = 6,032,304; k D > 1,100; octree depth 8, p = 255 at
+    the top level): FP64 and mixed products on 256 seeded rows against the oracle's rows of Eq.
+    dbem4 (FP64 <= 1e-6, mixed <= 1e-4), fixed-rule tile shapes."""
+    room, k = synth.config_room(5)
+    assert room.n > 6_000_000
+    ctx = make_ctx(F, room, k, autotune=0)
+    info = ctx.fmmbem_get_info()
+    print(f"N {room.n} depth {info.depth} p {list(info.p)[:info.depth + 1]}")
+    assert info.p[2] >= 250
+    x = synth.complex_normal(room.n, 11)
+    rows = np.random.default_rng(7).choice(room.n, 256, replace=False)
+    ref = bem.direct_matvec_rows(room.vertices, room.triangles, k, room.beta, oracle_rc(ctx, room), x, rows)
+    for prec, tol in ((F.FMMBEM_FP64, 1e-6), (F.FMMBEM_MIXED, 1e-4)):
+        y = ctx.fmmbem_matvec(x, precision=prec)[0]
+        assert np.isfinite(y).all()
+        err = np.linalg.norm(y[rows] - ref) / np.linalg.norm(ref)
+        print(f"precision {prec}: sampled rows rel L2 {err:.3e}")
+        assert err < tol
     ctx.close()
 
 
