@@ -958,15 +958,16 @@ static void ev_wait(fmmbem_ctx *c, int slot, hipStream_t s) { HIP_OK(hipStreamWa
 // recorded inside a captured product)
 constexpr int EV_CALLER_IN = 39, EV_CALLER_DONE = 40;
 
-// Far-field translations of one product on two streams.  The main stream A runs the M2L of the
-// deepest levels (l >= L - 2: by far the most jobs), leaf level first, straight after P2M; the
-// side stream B runs the M2M chain, the M2L of the upper levels and then the L2L chain.
-//   M2M chain (B)         waits for P2M (A)
-//   M2L(l), l < L (A)     waits for M(l) from the chain
-//   L2L into l >= lsplit  waits for A's last M2L (level lsplit): A runs its levels in order, so
-//   (B)                   then L(l-1) is complete and no M2L still adds into L(l) (which the
-//                         stream running M2L(l) zeroes first); B's own order covers the rest
-//   join                  A waits for B's last L2L
+// Far-field translations of one product on two streams.  The main stream A runs, straight after
+// P2M, the M2M chain (short: it feeds every level's M2L, so it goes first) and then the M2L of the
+// deepest levels (l >= L - 2: by far the most jobs), leaf level first; the side stream B, after the
+// near field, runs the M2L of the upper levels and then the L2L chain.
+//   M2L(l), l < lsplit (B)  waits for M(l) from the chain (A)
+//   L2L into l >= lsplit    waits for A's last M2L (level lsplit): A runs its levels in order, so
+//   (B)                     then L(l-1) is complete and no M2L still adds into L(l) (which the
+//                           stream running M2L(l) zeroes first); B's own order covers the rest
+//   join                    A waits for B's last L2L
+// Every level's local expansions receive M2L and then L2L in the same order as on one stream.
 template <class R>
 static void far_field(fmmbem_ctx *c, int nr, bool mixed) {
     using C = typename Cx<R>::T;
@@ -981,31 +982,28 @@ static void far_field(fmmbem_ctx *c, int nr, bool mixed) {
     };
     auto bytes = [&](int l) { return sizeof(C) * (size_t)c->lev[l].nbox * nr * c->lev[l].p * c->lev[l].p; };
     const int lsplit = std::max(2, L - 2);  // levels >= lsplit: M2L on A
-    const int EV_P2M = 1, EV_M2L = 2, EV_B = 3, EV_M = 4;  // EV_M + l: M(l) ready
-    ev_record(c, EV_P2M, A);
-    // B: M2M chain
-    c->cur = B;
-    ev_wait(c, EV_P2M, B);
+    const int EV_M2L = 2, EV_B = 3, EV_M = 4;  // EV_M + l: M(l) ready
+    // A: M2M chain
+    c->cur = A;
     for (int l = L - 1; l >= 2; --l) {
         LevelDev &P_ = c->lev[l];
         zero_dev(c, M(l), bytes(l));
         run_batch<R>(c, nr, P_.up, M(l + 1), M(l), tab(P_.up, P_.coax_up, P_.coax_up32), ph);
-        if (l >= lsplit) ev_record(c, EV_M + l, B);
+        if (l < lsplit) ev_record(c, EV_M + l, A);
     }
     rec(c, 4);
     // A: M2L of the deep levels
-    c->cur = A;
     for (int l = L; l >= lsplit; --l) {
         LevelDev &D = c->lev[l];
-        if (l < L) ev_wait(c, EV_M + l, A);
         zero_dev(c, Lc(l), bytes(l));
         run_batch<R>(c, nr, D.m2l, M(l), Lc(l), tab(D.m2l, D.coax_m2l, D.coax_m2l32), ph);
     }
     ev_record(c, EV_M2L, A);
     // B: M2L of the upper levels, then the L2L chain top-down
     c->cur = B;
-    for (int l = 2; l < lsplit; ++l) {
+    for (int l = lsplit - 1; l >= 2; --l) {
         LevelDev &D = c->lev[l];
+        ev_wait(c, EV_M + l, B);
         zero_dev(c, Lc(l), bytes(l));
         run_batch<R>(c, nr, D.m2l, M(l), Lc(l), tab(D.m2l, D.coax_m2l, D.coax_m2l32), ph);
     }
@@ -1018,6 +1016,7 @@ static void far_field(fmmbem_ctx *c, int nr, bool mixed) {
         }
         run_batch<R>(c, nr, P_.down, Lc(l - 1), Lc(l), tab(P_.down, P_.coax_up, P_.coax_up32), ph);
     }
+    if (!a_done) ev_wait(c, EV_M2L, B);
     ev_record(c, EV_B, B);
     c->cur = A;
     ev_wait(c, EV_B, A);
