@@ -64,11 +64,10 @@ void launch_p2p(int nr, bool fp32, int nleaf, const int32_t *leaf_start, const i
                 const int32_t *nbr_list, int all_leaves, const double4 *ec, const double4 *en, const double2 *sigma,
                 const double2 *mu, double k, double rc2, const int32_t *near_start, const int32_t *near_col,
                 const void *nL, const void *nM, double2 *y, hipStream_t st);
-size_t p2m_stage_bytes(int nr, int p);
-size_t p2m_fixed_bytes(int p);
-void launch_p2m(int nr, int nleaf, int p, int CH, const int32_t *leaf_start, const double4 *center,
-                const double4 *ec, const double4 *en, const double2 *sigma, const double2 *mu, double k,
-                const double *leg, double2 *Mout, hipStream_t st);
+bool p2m_fits(int nr, int p);
+void launch_p2m(int nr, int nleaf, int p, const int32_t *leaf_start, const double4 *center, const double4 *ec,
+                const double4 *en, const double2 *sigma, const double2 *mu, double k, const double *leg,
+                double2 *Mout, hipStream_t st);
 void launch_l2p(int nr, int nleaf, int p, const int32_t *leaf_start, const double4 *center, const double4 *ec,
                 const double2 *Lc, double k, const double *leg, const double2 *ynear, double half,
                 const int32_t *perm, int64_t n, const double2 *x, double2 *y, int has_far, hipStream_t st);
@@ -121,11 +120,9 @@ static T *upload(DeviceBuffers &b, const std::string &name, const std::vector<T>
 // Legendre recurrence table (built with the rotation tables, degrees up to the largest p + 1)
 static const double *leg_table(fmmbem_ctx *c) { return (const double *)c->buf.find("legtab"); }
 
-// sources staged per P2M chunk (about 60 KB of LDS per workgroup)
-static int p2m_chunk(int nr, int p) {
-    const size_t per = p2m_stage_bytes(nr, p), fixed = p2m_fixed_bytes(p);
-    if (per + fixed > 60000) throw FmmError(FMMBEM_EINVAL, "leaf truncation number too large for P2M staging");
-    return (int)std::max<size_t>(1, std::min<size_t>(32, (60000 - fixed) / per));
+// P2M stages a chunk of sources and the leaf's basis in LDS
+static void check_p2m(int nr, int p) {
+    if (!p2m_fits(nr, p)) throw FmmError(FMMBEM_EINVAL, "leaf truncation number too large for P2M staging");
 }
 
 static void setup_mesh(fmmbem_ctx *c) {
@@ -1062,10 +1059,10 @@ static void fmm_pass(fmmbem_ctx *c, int nr, const double2 *sigma, const double2 
     if (!exact_far) {
         LevelDev &LL = c->lev[L];
         const int p = LL.p;
-        const int CH = p2m_chunk(nr, p);
+        check_p2m(nr, p);
         const size_t pp = (size_t)p * p;
         pe = prof_begin(c);
-        launch_p2m(nr, nleaf, p, CH, I32("leaf_start"), LL.center, ec, en, sigma, mu, c->k, leg_table(c), LL.M, A);
+        launch_p2m(nr, nleaf, p, I32("leaf_start"), LL.center, ec, en, sigma, mu, c->k, leg_table(c), LL.M, A);
         prof_end(c, pe, "k_p2m", (double)n * pp * 2 * 8.0 * nr, 112.0 * n + 32.0 * n * nr + 16.0 * nleaf * pp * nr);
         if (mixed) {
             // FP32 translations between an FP64 P2M and an FP64 L2P
@@ -1271,8 +1268,8 @@ static void fmm_pass_ind(fmmbem_ctx *c, const double2 *sigma, const double2 *mu,
             *Dm = dget<double2>(c->scratch, "ind_Dm", LL.nbox * q1);
     if (!exact_far) {
         pe = prof_begin(c);
-        launch_p2m(1, nleaf, p, p2m_chunk(1, p), I32("leaf_start"), LL.center, ec, en, sigma, mu, c->k, leg_table(c),
-                   LL.M, A);
+        check_p2m(1, p);
+        launch_p2m(1, nleaf, p, I32("leaf_start"), LL.center, ec, en, sigma, mu, c->k, leg_table(c), LL.M, A);
         prof_end(c, pe, "k_p2m", (double)n * pp * 2 * 8.0, 112.0 * n + 32.0 * n + 16.0 * nleaf * pp);
         if (mixed) {
             pe = prof_begin(c);

@@ -716,7 +716,7 @@ struct P2mSlotSums {
 };
 
 template <int NR>
-__global__ void __launch_bounds__(256) k_p2m(int nleaf, int p, int CH, const int32_t *leaf_start,
+__global__ void __launch_bounds__(256) k_p2m_wide(int nleaf, int p, int CH, const int32_t *leaf_start,
                                              const double4 *center, const double4 *ec, const double4 *en,
                                              const double2 *sigma, const double2 *mu, double k, const double *leg,
                                              double2 *Mout) {
@@ -859,23 +859,196 @@ __global__ void __launch_bounds__(256) k_p2m(int nleaf, int p, int CH, const int
     }
 }
 
+// j_0(x) .. j_N(x) for the expansion kernels: the sequence of bessel_j_seq, with Miller's
+// normalised downward recurrence (x >= 4) taking one multiplication by 1/x per step instead of a
+// division, and its values kept in registers until the final scaling.
+__device__ inline void bessel_j_seq_fast(double x, int N, double *j) {
+    if (x < 4.0 && N <= 40) {
+        bessel_j_seq(x, N, j);
+        return;
+    }
+    const int top = N > (int)x ? N : (int)x;
+    const int start = top + 40 + (int)(4.0 * sqrt((double)top + 1.0));
+    const double ix = rcp_nr(x);
+    double fp1 = 0.0, f = 1e-300;
+    for (int n = start; n >= 1; --n) {
+        const double fm1 = fma((2.0 * n + 1.0) * ix, f, -fp1);
+        fp1 = f;
+        f = fm1;
+        if (n - 1 <= N) j[n - 1] = f;
+        if (fabs(f) > 1e250) {  // rescale everything stored so far
+            f *= 1e-250;
+            fp1 *= 1e-250;
+            for (int q = n - 1; q <= N; ++q) j[q] *= 1e-250;
+        }
+    }
+    double sn, cn;
+    sincos(x, &sn, &cn);
+    const double j0 = sn * ix, j1 = (sn * ix - cn) * ix;
+    const double scale = (fabs(j0) >= fabs(j1) || N < 1) ? j0 / j[0] : j1 / j[1];
+    for (int n = 0; n <= N; ++n) j[n] *= scale;
+}
+
+// P2M with one thread per basis slot.  A workgroup takes one leaf; per chunk of CH sources:
+//  1. one thread per source: frame, j_0..j_p(k r), the phase powers E_m' = (sin(th) e^{i phi})^m'
+//     and the slot weights al_k of every vector;
+//  2. the real part of the basis, R~_n^m' = j_n(k r) P_n^m'(cos th) / sin^m'(th), one recurrence in
+//     n per (source, m'), the orders m' and p - m' paired so that each item is p + 2 steps long;
+//  3. one thread per slot (n, m'), m' >= 0: R_n^m' = E_m' R~_n^m' and, for every k, the four real
+//     sums of Re/Im al_k times Re/Im R, which give both sum_s al_k R (P) and sum_s conj(al_k) R (Q)
+//     (the same slot sums as the wide kernel, at half its multiplications);
+//  4. every coefficient from seven factor-weighted slot sums, through LDS.
+// Needs (p + 1)(p + 2)/2 <= 256 (p <= 20); launch_p2m takes the wide kernel beyond.
+template <int NR>
+__global__ void __launch_bounds__(256) k_p2m(int nleaf, int p, int CH, const int32_t *leaf_start,
+                                             const double4 *center, const double4 *ec, const double4 *en,
+                                             const double2 *sigma, const double2 *mu, double k, const double *leg,
+                                             double2 *Mout) {
+    extern __shared__ double2 smem[];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const int TB = (p + 1) * (p + 2) / 2, TS = TB + 1, p1 = p + 1;
+    double2 *E = smem;                          // CH * (p+1)
+    double2 *al = E + CH * p1;                  // CH * 4 * NR
+    double *Rb = (double *)(al + CH * 4 * NR);  // CH * TB
+    double *jb = Rb + CH * TB;                  // CH * (p+2)
+    double *cth = jb + CH * (p + 2);            // CH
+    double *lt = cth + CH;                      // 3 TB: Legendre recurrence table
+    double2 *SL = smem;                         // after the last chunk: [8][TS] slot sums of one vector
+    for (int e = tid; e < 3 * TB; e += blockDim.x) lt[e] = leg[e];
+    const double4 C = center[b];
+    const int ss = leaf_start[b], se = leaf_start[b + 1];
+    // this thread's slot
+    int sn = 0, sm = 0;
+    if (tid < TB) {
+        while ((sn + 1) * (sn + 2) / 2 <= tid) ++sn;
+        sm = tid - sn * (sn + 1) / 2;
+    }
+    double acc[4][NR][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int rr = 0; rr < NR; ++rr)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[q][rr][u] = 0.0;
+    const int npair = p / 2 + 1;
+    for (int j0 = ss; j0 < se; j0 += CH) {
+        const int cnt = min(CH, se - j0);
+        __syncthreads();  // the previous chunk's readers are done (and lt is in place)
+        if (tid < cnt) {
+            const int j = j0 + tid;
+            const double4 c = ec[j], nv = en[j];
+            double r, ct, st;
+            double2 eph;
+            sph_frame(c.x - C.x, c.y - C.y, c.z - C.z, r, ct, st, eph);
+            cth[tid] = ct;
+            bessel_j_seq_fast(k * r, p, jb + tid * (p + 2));
+            const double2 u = cscale(eph, st);
+            double2 e = cmk(1.0, 0.0);
+            for (int m = 0; m <= p; ++m) {
+                E[tid * p1 + m] = e;
+                e = cmul(e, u);
+            }
+#pragma unroll
+            for (int rr = 0; rr < NR; ++rr) {
+                const double2 q = cscale(sigma[(int64_t)j * NR + rr], c.w), w = cscale(mu[(int64_t)j * NR + rr], c.w);
+                al[(tid * 4) * NR + rr] = q;
+                al[(tid * 4 + 1) * NR + rr] = cscale(w, nv.z);
+                al[(tid * 4 + 2) * NR + rr] = cmul(w, cmk(0.5 * nv.x, -0.5 * nv.y));
+                al[(tid * 4 + 3) * NR + rr] = cmul(w, cmk(0.5 * nv.x, 0.5 * nv.y));
+            }
+        }
+        __syncthreads();
+        for (int w = tid; w < cnt * npair; w += blockDim.x) {
+            const int s = w / npair, pr = w - s * npair;
+            const double ct = cth[s];
+            const double *js = jb + s * (p + 2);
+            double *out = Rb + s * TB;
+            for (int h = 0; h < 2; ++h) {
+                const int mp = h == 0 ? pr : p - pr;
+                if (h == 1 && mp == pr) break;
+                double P1 = lt[3 * leg_tri(mp, mp) + 2], P2 = 0.0;
+                out[leg_tri(mp, mp)] = js[mp] * P1;
+                for (int n = mp + 1; n <= p; ++n) {
+                    const int t = leg_tri(n, mp);
+                    const double P = fma(lt[3 * t] * ct, P1, -lt[3 * t + 1] * P2);
+                    P2 = P1;
+                    P1 = P;
+                    out[t] = js[n] * P;
+                }
+            }
+        }
+        __syncthreads();
+        if (tid < TB)
+            for (int s = 0; s < cnt; ++s) {
+                const double2 B = cscale(E[s * p1 + sm], Rb[s * TB + tid]);
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int rr = 0; rr < NR; ++rr) {
+                        const double2 a = al[(s * 4 + q) * NR + rr];
+                        acc[q][rr][0] = fma(a.x, B.x, acc[q][rr][0]);
+                        acc[q][rr][1] = fma(a.y, B.y, acc[q][rr][1]);
+                        acc[q][rr][2] = fma(a.x, B.y, acc[q][rr][2]);
+                        acc[q][rr][3] = fma(a.y, B.x, acc[q][rr][3]);
+                    }
+            }
+    }
+    // coefficient c = seven factor-weighted slot sums (entry i of term t from sum type k(t):
+    // t = 0 monopole, 1-2 n_z d_z, 3-4 (d_x + i d_y), 5-6 (d_x - i d_y)), one vector at a time
+    const int kt[7] = {0, 1, 1, 2, 2, 3, 3};
+    const int ncoef = p * p;
+    double2 *Mb = Mout + (int64_t)b * NR * ncoef;
+#pragma unroll
+    for (int rr = 0; rr < NR; ++rr) {
+        __syncthreads();
+        if (tid < TB)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double A = acc[q][rr][0], Bq = acc[q][rr][1], Cq = acc[q][rr][2], D = acc[q][rr][3];
+                SL[(2 * q) * TS + tid] = cmk(A - Bq, Cq + D);      // sum al_k R
+                SL[(2 * q + 1) * TS + tid] = cmk(A + Bq, Cq - D);  // sum conj(al_k) R
+            }
+        if (tid < 8) SL[tid * TS + TB] = cmk(0.0, 0.0);
+        __syncthreads();
+        for (int c = tid; c < ncoef; c += blockDim.x) {
+            P2mTerms T;
+            p2m_terms(p, TB, c, k, T);
+            double2 a = cmk(0, 0);
+#pragma unroll
+            for (int t = 0; t < 7; ++t) {
+                const bool cj = T.fy[t] != T.fx[t];  // conjugated entry: conj of the Q sum
+                const double2 v = SL[(2 * kt[t] + (cj ? 1 : 0)) * TS + T.i[t]];
+                a = cadd(a, cmk(T.fx[t] * v.x, T.fy[t] * v.y));
+            }
+            Mb[rr * ncoef + c] = cmuli(cscale(a, k));  // i k sum
+        }
+    }
+}
+
 // ------------------------------------------------------------------ L2P + combine
 // y[perm[i]] = half * x[perm[i]] + y_near[i] + sum_{n,m} D_n^m R_n^m(c_i - C).
-template <int NR>
+// One thread per target; the recurrence table and (STAGE) the leaf's expansions are staged in LDS
+// (every thread reads the same entry at once: broadcasts), the degree loop unrolled so that its
+// reads overlap.  Without STAGE (expansions too large for LDS) they are read from global memory.
+template <int NR, bool STAGE>
 __global__ void __launch_bounds__(64) k_l2p(int nleaf, int p, const int32_t *leaf_start, const double4 *center,
                                             const double4 *ec, const double2 *Lc, double k, const double *leg,
                                             const double2 *ynear, double half, const int32_t *perm, int64_t n,
                                             const double2 *x, double2 *y, int has_far) {
-    extern __shared__ double jbuf[];
+    extern __shared__ double2 l2p_sm[];
     const int b = blockIdx.x, tid = threadIdx.x;
     const double4 C = center[b];
     const int ts = leaf_start[b], te = leaf_start[b + 1];
-    const double2 *D = Lc + (int64_t)b * NR * p * p;  // NR expansions of this leaf
     const int pp = p * p, TB = p * (p + 1) / 2;
-    double *lt = jbuf;                        // 3 TB: Legendre recurrence table (degrees < p)
-    double *jb = jbuf + 3 * TB + tid * (p + 2);
+    const double2 *Dg = Lc + (int64_t)b * NR * pp;   // NR expansions of this leaf
+    double2 *Dl = l2p_sm;
+    double *lt = STAGE ? (double *)(Dl + NR * pp) : (double *)l2p_sm;  // 3 TB: Legendre recurrence (degrees < p)
+    double *jb = lt + 3 * TB + tid * (p + 2);
+    const double2 *D = STAGE ? (const double2 *)Dl : Dg;
     if (has_far) {
         for (int e = tid; e < 3 * TB; e += blockDim.x) lt[e] = leg[e];
+        if (STAGE)
+            for (int e = tid; e < NR * pp; e += blockDim.x) Dl[e] = Dg[e];
         __syncthreads();
     }
     for (int t = ts + tid; t < te; t += 64) {
@@ -887,7 +1060,7 @@ __global__ void __launch_bounds__(64) k_l2p(int nleaf, int p, const int32_t *lea
             double r, ct, st;
             double2 eph;
             sph_frame(c.x - C.x, c.y - C.y, c.z - C.z, r, ct, st, eph);
-            bessel_j_seq(k * r, p - 1, jb);
+            bessel_j_seq_fast(k * r, p - 1, jb);
             double2 e = cmk(1.0, 0.0);
             double sp = 1.0;
             for (int mp = 0; mp < p; ++mp) {
@@ -898,15 +1071,17 @@ __global__ void __launch_bounds__(64) k_l2p(int nleaf, int p, const int32_t *lea
                 double P1 = lt[3 * leg_tri(mp, mp) + 2] * sp, P2 = 0.0;
                 double2 sa[NR], sb[NR];
 #pragma unroll
-                for (int rr = 0; rr < NR; ++rr) sa[rr] = sb[rr] = cmk(0, 0);
-                for (int nn = mp; nn < p; ++nn) {
-                    if (nn > mp) {
-                        const int q = leg_tri(nn, mp);
-                        const double P = fma(lt[3 * q] * ct, P1, -lt[3 * q + 1] * P2);
-                        P2 = P1;
-                        P1 = P;
-                    }
-                    const double R = jb[nn] * P1;
+                for (int rr = 0; rr < NR; ++rr) {
+                    sa[rr] = cscale(D[rr * pp + cidx(mp, mp)], jb[mp] * P1);
+                    sb[rr] = mp > 0 ? cscale(D[rr * pp + cidx(mp, -mp)], jb[mp] * P1) : cmk(0, 0);
+                }
+#pragma unroll 4
+                for (int nn = mp + 1; nn < p; ++nn) {
+                    const int q = leg_tri(nn, mp);
+                    const double P = fma(lt[3 * q] * ct, P1, -lt[3 * q + 1] * P2);
+                    P2 = P1;
+                    P1 = P;
+                    const double R = jb[nn] * P;
 #pragma unroll
                     for (int rr = 0; rr < NR; ++rr) {
                         sa[rr] = cadd(sa[rr], cscale(D[rr * pp + cidx(nn, mp)], R));
@@ -1407,25 +1582,75 @@ size_t p2m_stage_bytes(int nr, int p) {
 }
 size_t p2m_fixed_bytes(int p) { return (size_t)3 * (p + 1) * (p + 2) / 2 * sizeof(double); }
 
-void launch_p2m(int nr, int nleaf, int p, int CH, const int32_t *leaf_start, const double4 *center,
-                const double4 *ec, const double4 *en, const double2 *sigma, const double2 *mu, double k,
-                const double *leg, double2 *Mout, hipStream_t st) {
-    const size_t sh = (size_t)CH * p2m_stage_bytes(nr, p) + p2m_fixed_bytes(p);
+// LDS of the slot-owner kernel: per staged source E (p+1 complex), the weights (4 NR complex), the
+// real basis (TB), j_n (p+2) and cos(th); the recurrence table; the slot sums of one vector
+// ([8][TB+1] complex) reuse the staging area after the last chunk.
+static size_t p2m_slot_stage(int nr, int p) {
+    const int TB = (p + 1) * (p + 2) / 2;
+    return (size_t)(p + 1) * 16 + (size_t)nr * 64 + (size_t)TB * 8 + (size_t)(p + 2) * 8 + 8;
+}
+static bool p2m_slot_ok(int p) { return (p + 1) * (p + 2) / 2 <= 256; }
+static int p2m_slot_chunk(int nr, int p, size_t &sh) {
+    const int TB = (p + 1) * (p + 2) / 2;
+    const size_t per = p2m_slot_stage(nr, p), fixed = (size_t)3 * TB * 8, sums = (size_t)8 * (TB + 1) * 16;
+    // about 40 KB per workgroup (four resident per CU), at least the slot sums' area
+    int CH = (int)std::max<size_t>(1, std::min<size_t>(64, (40000 - std::min<size_t>(fixed, 39000)) / per));
+    while ((size_t)CH * per < sums) ++CH;
+    sh = (size_t)CH * per + fixed;
+    return CH;
+}
+
+bool p2m_fits(int nr, int p) {
+    if (p2m_slot_ok(p)) {
+        size_t sh;
+        p2m_slot_chunk(nr, p, sh);
+        return sh <= 65536;
+    }
+    return p2m_stage_bytes(nr, p) + p2m_fixed_bytes(p) <= 60000;
+}
+
+void launch_p2m(int nr, int nleaf, int p, const int32_t *leaf_start, const double4 *center, const double4 *ec,
+                const double4 *en, const double2 *sigma, const double2 *mu, double k, const double *leg,
+                double2 *Mout, hipStream_t st) {
+    if (nleaf <= 0) return;
+    if (p2m_slot_ok(p)) {
+        size_t sh;
+        const int CH = p2m_slot_chunk(nr, p, sh);
 #define P2M_CALL(R) \
     k_p2m<R><<<nleaf, 256, sh, st>>>(nleaf, p, CH, leaf_start, center, ec, en, sigma, mu, k, leg, Mout)
-    FMM_NR_DISPATCH(nr, P2M_CALL)
+        FMM_NR_DISPATCH(nr, P2M_CALL)
 #undef P2M_CALL
+    } else {
+        const size_t per = p2m_stage_bytes(nr, p), fixed = p2m_fixed_bytes(p);
+        const int CH = (int)std::max<size_t>(1, std::min<size_t>(32, (60000 - fixed) / per));
+        const size_t sh = (size_t)CH * per + fixed;
+#define P2M_CALL(R) \
+    k_p2m_wide<R><<<nleaf, 256, sh, st>>>(nleaf, p, CH, leaf_start, center, ec, en, sigma, mu, k, leg, Mout)
+        FMM_NR_DISPATCH(nr, P2M_CALL)
+#undef P2M_CALL
+    }
     LAUNCH_OK();
 }
 
 void launch_l2p(int nr, int nleaf, int p, const int32_t *leaf_start, const double4 *center, const double4 *ec,
                 const double2 *Lc, double k, const double *leg, const double2 *ynear, double half,
                 const int32_t *perm, int64_t n, const double2 *x, double2 *y, int has_far, hipStream_t st) {
-    const size_t sh = ((size_t)64 * (p + 2) + (size_t)3 * p * (p + 1) / 2) * sizeof(double);
-#define L2P_CALL(R) \
-    k_l2p<R><<<nleaf, 64, sh, st>>>(nleaf, p, leaf_start, center, ec, Lc, k, leg, ynear, half, perm, n, x, y, has_far)
-    FMM_NR_DISPATCH(nr, L2P_CALL)
+    if (nleaf <= 0) return;
+    const size_t base = ((size_t)64 * (p + 2) + (size_t)3 * p * (p + 1) / 2) * sizeof(double);
+    const size_t staged = base + (size_t)nr * p * p * 16;
+    if (staged <= 48 * 1024) {
+#define L2P_CALL(R)                                                                                                   \
+    k_l2p<R, true><<<nleaf, 64, staged, st>>>(nleaf, p, leaf_start, center, ec, Lc, k, leg, ynear, half, perm, n, x, y, \
+                                              has_far)
+        FMM_NR_DISPATCH(nr, L2P_CALL)
 #undef L2P_CALL
+    } else {
+#define L2P_CALL(R)                                                                                                  \
+    k_l2p<R, false><<<nleaf, 64, base, st>>>(nleaf, p, leaf_start, center, ec, Lc, k, leg, ynear, half, perm, n, x, y, \
+                                             has_far)
+        FMM_NR_DISPATCH(nr, L2P_CALL)
+#undef L2P_CALL
+    }
     LAUNCH_OK();
 }
 

@@ -1736,7 +1736,8 @@ __global__ void __launch_bounds__(256) k_fr_coax(int64_t ntot, int P, int PT, co
 
 // dst[t] += sum of the job rows of target t (W1, P^2 per job); jobs of t listed in CSR order.
 // With nr vectors, virtual target t is real target t / nr, vector t % nr, and the job rows of
-// that vector are (job * nr + t % nr).
+// that vector are (job * nr + t % nr).  Workgroup (t, y) takes coefficients 256 y .. 256 y + 255
+// of target t, so that the large expansions of the upper levels spread over many workgroups.
 template <class C>
 __global__ void __launch_bounds__(256) k_tr_reduce(int64_t ntgt, int nr, int ptgt, int P, const int32_t *start,
                                                    const int32_t *jobs, const C *W, C *dst) {
@@ -1748,21 +1749,21 @@ __global__ void __launch_bounds__(256) k_tr_reduce(int64_t ntgt, int nr, int ptg
     if (j0 == j1) return;
     const int pt2 = ptgt * ptgt;
     const int64_t P2 = (int64_t)P * P;
-    for (int c = threadIdx.x; c < pt2; c += blockDim.x) {
-        // four independent partial sums keep four row loads in flight
-        C s0 = dst[t * pt2 + c], s1 = mkc<C>(0, 0), s2 = mkc<C>(0, 0), s3 = mkc<C>(0, 0);
-        int q = j0;
-        for (; q + 4 <= j1; q += 4) {
-            const C a0 = W[((int64_t)jobs[q] * nr + r) * P2 + c], a1 = W[((int64_t)jobs[q + 1] * nr + r) * P2 + c];
-            const C a2 = W[((int64_t)jobs[q + 2] * nr + r) * P2 + c], a3 = W[((int64_t)jobs[q + 3] * nr + r) * P2 + c];
-            s0 = addc(s0, a0);
-            s1 = addc(s1, a1);
-            s2 = addc(s2, a2);
-            s3 = addc(s3, a3);
-        }
-        for (; q < j1; ++q) s0 = addc(s0, W[((int64_t)jobs[q] * nr + r) * P2 + c]);
-        dst[t * pt2 + c] = addc(addc(s0, s1), addc(s2, s3));
+    const int c = blockIdx.y * 256 + threadIdx.x;
+    if (c >= pt2) return;
+    // four independent partial sums keep four row loads in flight
+    C s0 = dst[t * pt2 + c], s1 = mkc<C>(0, 0), s2 = mkc<C>(0, 0), s3 = mkc<C>(0, 0);
+    int q = j0;
+    for (; q + 4 <= j1; q += 4) {
+        const C a0 = W[((int64_t)jobs[q] * nr + r) * P2 + c], a1 = W[((int64_t)jobs[q + 1] * nr + r) * P2 + c];
+        const C a2 = W[((int64_t)jobs[q + 2] * nr + r) * P2 + c], a3 = W[((int64_t)jobs[q + 3] * nr + r) * P2 + c];
+        s0 = addc(s0, a0);
+        s1 = addc(s1, a1);
+        s2 = addc(s2, a2);
+        s3 = addc(s3, a3);
     }
+    for (; q < j1; ++q) s0 = addc(s0, W[((int64_t)jobs[q] * nr + r) * P2 + c]);
+    dst[t * pt2 + c] = addc(addc(s0, s1), addc(s2, s3));
 }
 
 // ------------------------------------------------------------------ host side
@@ -1894,8 +1895,8 @@ const char *trans_stage(const TransBatch &b, const TransTables<R> &tb, int stage
         else k_tr_rot_back<R><<<dim3(ntile, b.ptgt), 256, lds, st>>>(a), name = f32 ? "k_tr_rot_back_f32" : "k_tr_rot_back";
         break;
     default:
-        k_tr_reduce<typename Cx<R>::T><<<(unsigned)(b.ntgt * nr), 256, 0, st>>>(b.ntgt, nr, b.ptgt, b.P, b.tgt_start,
-                                                                                b.tgt_jobs, W1, dst);
+        k_tr_reduce<typename Cx<R>::T><<<dim3((unsigned)(b.ntgt * nr), (unsigned)ceil_div(b.ptgt * b.ptgt, 256)), 256, 0,
+                                         st>>>(b.ntgt, nr, b.ptgt, b.P, b.tgt_start, b.tgt_jobs, W1, dst);
         name = f32 ? "k_tr_reduce_f32" : "k_tr_reduce";
     }
     LAUNCH_OK();
