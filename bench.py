@@ -224,6 +224,79 @@ def sweep_workload(args):
     print(json.dumps(result))
 
 
+def ir_workload(args):
+    """Impulse responses of Section 4.1: the 8 x 6 x 3 m shoebox with impedance zeta = 9 on every wall,
+    a monopole at (3, 2, 1.75) m, the total field on a receiver plane at z = 1.75 m over the whole
+    floor area for 128 frequencies 20, 40, ..., 2560 Hz (T = 50 ms), turned into pressure on 256 time
+    steps of T / 256 by the pulse of Eq. (an3) and one inverse FFT per receiver.  Meshes per octave
+    band (320, 640, 1280, 2560 Hz tops) at 6.7 elements per wavelength at the band's top frequency,
+    the paper's resolution criterion; FGMRES to 1e-4 per frequency.  The image-source solution
+    (Eq. an2, R = 0.8, images within c T) is compared on a sample of the plane's receivers in the
+    frequency and the time domain."""
+    import numpy as np
+    from paper_2103_16073_amd import ir, synth
+    L, zeta, rs = (8.0, 6.0, 3.0), 9.0, np.array([3.0, 2.0, 1.75])
+    df, nf, nt = 20.0, args.ir_freqs, 256
+    freqs = df * np.arange(1, nf + 1)
+    rec, (nx, ny) = ir.receiver_plane(L[0], L[1], 1.75, args.ir_spacing)
+    bands = [b for b in (320.0, 640.0, 1280.0, 2560.0) if b < freqs[-1]] + [float(freqs[-1])]
+    log(f"impulse responses: {nf} frequencies {freqs[0]:.0f}-{freqs[-1]:.0f} Hz, plane of {nx} x {ny} = "
+        f"{len(rec)} receivers, bands {bands}")
+    torch_sync()
+    t0 = time.perf_counter()
+    H, iters, summary = ir.sweep_plane(L, zeta, rs, freqs, rec, bands, tol=1e-4, wave_n=args.sweep_wave_n, log=log)
+    T = 1.0 / df
+    dt = T / nt
+    spec = ir.an3_spectrum(freqs, dt)
+    p = ir.synthesize_fft(H, spec, nt)  # nt x receivers
+    t_total = time.perf_counter() - t0
+    log(f"sweep + synthesis {t_total:.1f} s, iterations {iters.min()}..{iters.max()}")
+    checks = {}
+    if not args.no_cpu_baseline:
+        from oracle import analytic
+        R = (zeta - 1.0) / (zeta + 1.0)
+        rng = np.random.default_rng(41)
+        # receivers at least 0.3 m from the walls and 0.2 m from the source
+        ok = np.where((rec[:, 0] > 0.3) & (rec[:, 0] < L[0] - 0.3) & (rec[:, 1] > 0.3) & (rec[:, 1] < L[1] - 0.3)
+                      & (np.linalg.norm(rec - rs, axis=1) > 0.2))[0]
+        pick = rng.choice(ok, min(args.ir_check, len(ok)), replace=False)
+        t1 = time.perf_counter()
+        Hi = np.stack([analytic.image_sum_box(L, rs, rec[pick], 2 * np.pi * f / synth.SOUND_SPEED, R,
+                                              r_max=synth.SOUND_SPEED * T) for f in freqs])
+        ef = np.linalg.norm(H[:, pick] - Hi, axis=1) / np.linalg.norm(Hi, axis=1)
+        pi = ir.synthesize_fft(Hi, spec, nt)
+        pb = p[:, pick]
+        times = np.arange(nt) * dt
+        out = {}
+        for name, sel in (("first_25ms", times < T / 2), ("all_50ms", times < T)):
+            a, b = pb[sel], pi[sel]
+            out[name] = {"rel_l2": float(np.linalg.norm(a - b) / np.linalg.norm(b)),
+                         "correlation": float(np.sum(a * b) / np.sqrt(np.sum(a * a) * np.sum(b * b)))}
+        checks = {"receivers": int(len(pick)), "image_method_s": time.perf_counter() - t1,
+                  "freq_rel_diff_median": float(np.median(ef)), "freq_rel_diff_max": float(ef.max()),
+                  "freq_rel_diff_by_band": {f"{s['band_hz'][0]:.0f}-{s['band_hz'][1]:.0f}":
+                                            float(np.median(ef[(freqs >= s['band_hz'][0]) & (freqs <= s['band_hz'][1])]))
+                                            for s in summary},
+                  "time_domain": out}
+        log(f"image sources on {len(pick)} receivers: per-frequency relative difference median "
+            f"{checks['freq_rel_diff_median']:.3f}; time domain first 25 ms: rel L2 {out['first_25ms']['rel_l2']:.3f}, "
+            f"correlation {out['first_25ms']['correlation']:.4f}; 50 ms: rel L2 {out['all_50ms']['rel_l2']:.3f}, "
+            f"correlation {out['all_50ms']['correlation']:.4f}")
+    result = {"metric": f"impulse responses: {nf} frequency solves + receiver-plane fields + FFT synthesis",
+              "value": t_total, "unit": "s", "n_gpus": 1, "higher_is_better": False, "vs_baseline": None,
+              "dtype": "f64 residuals, f32 products", "data": "synthetic",
+              "config": {"workload": "shoebox 8x6x3 m, zeta = 9, source (3, 2, 1.75) m, receiver plane z = 1.75 m",
+                         "frequencies": nf, "df_hz": df, "time_steps": nt, "dt_ms": 1e3 * dt,
+                         "receivers": int(len(rec)), "plane_grid": [nx, ny], "spacing_m": args.ir_spacing,
+                         "elements_per_wavelength": 6.7},
+              "bands": summary, "iterations": {"min": int(iters.min()), "max": int(iters.max()),
+                                               "mean": float(iters.mean())},
+              "image_source_checks": checks}
+    if args.ir_out:
+        np.savez_compressed(args.ir_out, freqs=freqs, receivers=rec, plane=np.array([nx, ny]), H=H, p=p, dt=dt)
+    print(json.dumps(result))
+
+
 def torch_sync():
     import torch
     torch.cuda.synchronize()
@@ -247,7 +320,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", type=int, default=3,
                     help="named room: 1, 2, 3 or 5 (products and solves; 5: the 6M room at 5 kHz, fixed tile "
-                         "rule, the inner-outer solve only); 4: the 64-frequency, 4-source sweep")
+                         "rule, the inner-outer solve only); 4: the 64-frequency, 4-source sweep; 6: the impulse "
+                         "responses of the shoebox (frequency sweep, receiver plane, pulse, FFT)")
+    ap.add_argument("--ir-freqs", type=int, default=128, help="frequencies of the impulse-response sweep (20 Hz apart)")
+    ap.add_argument("--ir-spacing", type=float, default=0.05, help="receiver-plane grid spacing (m)")
+    ap.add_argument("--ir-check", type=int, default=400, help="plane receivers compared with the image sources")
+    ap.add_argument("--ir-out", default=None, help="write H, the receivers and the pressure frames (.npz)")
     ap.add_argument("--sweep-restart", type=int, default=120, help="Krylov dimension of the sweep's solves")
     ap.add_argument("--sweep-wave-n", type=int, default=1000000,
                     help="elements per wave of the sweep (contexts solved together by fmmbem_solve_many)")
@@ -282,6 +360,9 @@ def main():
         sys.exit(2)
     if args.workload == 4:
         sweep_workload(args)
+        return
+    if args.workload == 6:
+        ir_workload(args)
         return
 
     import numpy as np

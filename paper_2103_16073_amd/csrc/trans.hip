@@ -831,7 +831,7 @@ constexpr int TM_LDS = 4 * TM_KC * TM_LD;
 //   !FWD: Y = H^T X, X = W2 rows, A[r][k] = H[k][r]; the pass's outputs go through LDS, are
 //         phased (e^{-i m a}), summed over the runs of one target and stored job-major in W1.
 template <class R, bool FWD, int RBG>
-__global__ void __launch_bounds__(256) k_tm_rot(TransArgsT<R> a) {
+__global__ void __launch_bounds__(256) k_tm_rot(TransArgsT<R> a, int npass) {
     using C = typename Cx<R>::T;
     using Op = TmOp<R>;
     using v4 = typename Op::v4;
@@ -843,8 +843,9 @@ __global__ void __launch_bounds__(256) k_tm_rot(TransArgsT<R> a) {
     __shared__ int segl[LANE_JT];
     auto As = [&](int buf, int k, int r) -> R & { return lds[(buf * TM_KC + k) * TM_LD + r]; };
     auto Bs = [&](int buf, int k, int c) -> R & { return lds[((2 + buf) * TM_KC + k) * TM_LD + c]; };
-    int tile, n;
-    xcd_block(tile, n);
+    int tile, nq;
+    xcd_block(tile, nq);
+    const int n = nq / npass, pass = nq - n * npass;  // degree, and the pass's share of its row groups
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t J0 = (int64_t)tile * LANE_JT;
     const int P2 = a.P * a.P, phs = 2 * a.PH + 1, ps2 = a.psrc * a.psrc;
@@ -862,7 +863,7 @@ __global__ void __launch_bounds__(256) k_tm_rot(TransArgsT<R> a) {
     const int colw = 32 * wv + (lane & 15), kq = lane >> 4;
     const int nch = (w + TM_KC - 1) / TM_KC;
     constexpr int NA = TM_KC * RG / 256;  // A values staged per thread
-    for (int rb0 = 0; rb0 < RB; rb0 += RBG) {
+    for (int rb0 = pass * RBG; rb0 < RB; rb0 += npass * RBG) {
         const int r0 = rb0 * 16;
         R ra[NA], rbv[8];
         auto gload = [&](int kc) {
@@ -982,7 +983,7 @@ __global__ void __launch_bounds__(256) k_tm_rot(TransArgsT<R> a) {
 // columns swapped and the new real one negated (read from the partner column of X in LDS),
 // Y = Re(T) X + Im(T) X' column by column, so one accumulator set takes both real GEMMs.
 template <class R>
-__global__ void __launch_bounds__(256) k_tm_coax(TransArgsT<R> a) {
+__global__ void __launch_bounds__(256) k_tm_coax(TransArgsT<R> a, int npass) {
     using C = typename Cx<R>::T;
     using Op = TmOp<R>;
     using v4 = typename Op::v4;
@@ -993,8 +994,9 @@ __global__ void __launch_bounds__(256) k_tm_coax(TransArgsT<R> a) {
     auto Ar = [&](int buf, int k, int r) -> R & { return ldsA[(buf * TM_KC + k) * LA + r]; };
     auto Ai = [&](int buf, int k, int r) -> R & { return ldsA[((2 + buf) * TM_KC + k) * LA + r]; };
     auto Bs = [&](int buf, int k, int c) -> R & { return ldsB[(buf * TM_KC + k) * TM_LD + c]; };
-    int tile, mi;
-    xcd_block(tile, mi);
+    int tile, mq;
+    xcd_block(tile, mq);
+    const int mi = mq / npass, pass = mq - mi * npass;  // order index, and the pass's share of its row groups
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int P2 = a.P * a.P, pt = a.ptgt, pm = min(a.psrc, a.ptgt);
     const int m = mi - (pt - 1), am = m < 0 ? -m : m;
@@ -1002,6 +1004,7 @@ __global__ void __launch_bounds__(256) k_tm_coax(TransArgsT<R> a) {
     R *Wout = (R *)a.W2;
     const C *Xin = a.W1;
     if (am >= pm) {  // no source of this order
+        if (pass != 0) return;
         for (int e = tid; e < rows * 128; e += 256) {
             const int nn = am + e / 128;
             Wout[((int64_t)tile * P2 + nn * nn + nn + m) * 128 + e % 128] = R(0);
@@ -1013,7 +1016,7 @@ __global__ void __launch_bounds__(256) k_tm_coax(TransArgsT<R> a) {
     const int colw = 32 * wv + (lane & 15), kq = lane >> 4;
     const R swp = (colw & 1) ? R(1) : R(-1);
     const int nch = (cin + TM_KC - 1) / TM_KC;
-    for (int rb0 = 0; rb0 < RB; rb0 += RBG) {
+    for (int rb0 = pass * RBG; rb0 < RB; rb0 += npass * RBG) {
         const int r0 = rb0 * 16;
         C ta[TM_KC * RG / 256];
         C xb[4];  // (re, im) of 4 (k, job) inputs
@@ -1854,10 +1857,25 @@ const char *trans_stage(const TransBatch &b, const TransTables<R> &tb, int stage
     if (b.lane && b.mfma == 1 && stage < 3) {
         // stages of a lane batch on matrix cores (FP64, or FP32 for mixed products)
         if (b.JT != LANE_JT) throw FmmError(-1, "lane batches use 64-job tiles");
+        // A small batch (few workgroups per CU) also spreads the row groups of a degree (order)
+        // over workgroups, so that the largest degrees do not run as one long workgroup each.
+        auto passes = [&](int rows, int rbg, int nd) {
+            const int np = ((rows + 15) / 16 + rbg - 1) / rbg;
+            return (int64_t)ntile * nd >= 2048 ? 1 : np;
+        };
+        int np;
         switch (stage) {
-        case 0: k_tm_rot<R, true, 8><<<dim3(ntile, b.psrc), 256, 0, st>>>(a), name = f32 ? "k_tm_rot_fwd_f32" : "k_tm_rot_fwd"; break;
-        case 1: k_tm_coax<R><<<dim3(ntile, 2 * b.ptgt - 1), 256, 0, st>>>(a), name = f32 ? "k_tm_coax_f32" : "k_tm_coax"; break;
-        default: k_tm_rot<R, false, 4><<<dim3(ntile, b.ptgt), 256, 0, st>>>(a), name = f32 ? "k_tm_rot_back_f32" : "k_tm_rot_back";
+        case 0:
+            np = passes(2 * b.psrc - 1, 8, b.psrc);
+            k_tm_rot<R, true, 8><<<dim3(ntile, b.psrc * np), 256, 0, st>>>(a, np), name = f32 ? "k_tm_rot_fwd_f32" : "k_tm_rot_fwd";
+            break;
+        case 1:
+            np = passes(b.ptgt, 4, 2 * b.ptgt - 1);
+            k_tm_coax<R><<<dim3(ntile, (2 * b.ptgt - 1) * np), 256, 0, st>>>(a, np), name = f32 ? "k_tm_coax_f32" : "k_tm_coax";
+            break;
+        default:
+            np = passes(2 * b.ptgt - 1, 4, b.ptgt);
+            k_tm_rot<R, false, 4><<<dim3(ntile, b.ptgt * np), 256, 0, st>>>(a, np), name = f32 ? "k_tm_rot_back_f32" : "k_tm_rot_back";
         }
         LAUNCH_OK();
         return name;

@@ -49,3 +49,38 @@ def test_impulse_response_vs_image_sources():
     # so late reverberation beyond 50 ms folds back into the BEM's window (not into the truncated
     # image sum); the frequency-domain differences (median 0.46) carry both effects.
     assert np.all(np.isfinite(H)) and corr > 0.95 and et < 0.35
+
+
+def test_impulse_response_plane_two_bands_vs_image_sources():
+    # 32 frequencies to 640 Hz on two band meshes (6.7 elements per wavelength at 320 and 640 Hz),
+    # every frequency's field on a receiver plane at the source height, the pulse of Eq. (an3) by one
+    # inverse FFT per receiver (256 steps of T / 256), and the image sources on the plane's receivers
+    # at least 0.3 m from the walls
+    from paper_2103_16073_amd import ir
+    L = (8.0, 6.0, 3.0)
+    zeta = 9.0
+    rs = np.array([3.0, 2.0, 1.75])
+    df, nt = 20.0, 256
+    freqs = df * np.arange(1, 33)
+    rec, (nx, ny) = ir.receiver_plane(L[0], L[1], 1.75, 0.25)
+    H, iters, summary = ir.sweep_plane(L, zeta, rs, freqs, rec, [320.0, 640.0], tol=1e-4)
+    assert [s["frequencies"] for s in summary] == [16, 16] and np.all(iters > 0)
+    T = 1.0 / df
+    dt = T / nt
+    spec = ir.an3_spectrum(freqs, dt)
+    pb = ir.synthesize_fft(H, spec, nt)
+    inner = np.where((rec[:, 0] > 0.3) & (rec[:, 0] < 7.7) & (rec[:, 1] > 0.3) & (rec[:, 1] < 5.7)
+                     & (np.linalg.norm(rec - rs, axis=1) > 0.2))[0]
+    Hi = np.stack([analytic.image_sum_box(L, rs, rec[inner], 2 * np.pi * f / synth.SOUND_SPEED, 0.8,
+                                          r_max=synth.SOUND_SPEED * T) for f in freqs])
+    pi = ir.synthesize_fft(Hi, spec, nt)
+    times = np.arange(nt) * dt
+    early = times < T / 2
+    a, b = pb[early][:, inner], pi[early]
+    et = np.linalg.norm(a - b) / np.linalg.norm(b)
+    corr = np.sum(a * b) / np.sqrt(np.sum(a * a) * np.sum(b * b))
+    ef = np.linalg.norm(H[:, inner] - Hi, axis=1) / np.linalg.norm(Hi, axis=1)
+    print("bands:", [(s["n"], s["contexts"], min(s["iterations"]), max(s["iterations"])) for s in summary])
+    print(f"{len(inner)} receivers; per-frequency median relative difference {np.median(ef):.3f}; "
+          f"first 25 ms: relative L2 {et:.3f}, correlation {corr:.4f}")
+    assert np.all(np.isfinite(pb)) and corr > 0.9 and et < 0.5
