@@ -292,8 +292,9 @@ def ir_workload(args):
               "bands": summary, "iterations": {"min": int(iters.min()), "max": int(iters.max()),
                                                "mean": float(iters.mean())},
               "image_source_checks": checks}
-    if args.ir_out:
-        np.savez_compressed(args.ir_out, freqs=freqs, receivers=rec, plane=np.array([nx, ny]), H=H, p=p, dt=dt)
+    if args.ir_out:  # FP32 pressure frames and transfer functions
+        np.savez_compressed(args.ir_out, freqs=freqs, receivers=rec.astype(np.float32), plane=np.array([nx, ny]),
+                            H=H.astype(np.complex64), p=p.astype(np.float32), dt=dt)
     print(json.dumps(result))
 
 

@@ -83,4 +83,6 @@ def test_impulse_response_plane_two_bands_vs_image_sources():
     print("bands:", [(s["n"], s["contexts"], min(s["iterations"]), max(s["iterations"])) for s in summary])
     print(f"{len(inner)} receivers; per-frequency median relative difference {np.median(ef):.3f}; "
           f"first 25 ms: relative L2 {et:.3f}, correlation {corr:.4f}")
-    assert np.all(np.isfinite(pb)) and corr > 0.9 and et < 0.5
+    # measured: 656 receivers, correlation 0.984, relative L2 0.179 over the first 25 ms; iterations
+    # 9..26 (14,516 elements) and 25..27 (57,608 elements)
+    assert np.all(np.isfinite(pb)) and corr > 0.97 and et < 0.25
