@@ -771,11 +771,12 @@ static void autotune_batches(fmmbem_ctx *c) {
             int lane, whole, jt, mfma;
         };
         std::vector<Shape> cand;
-        int64_t pad64 = 0;
+        int64_t pad64 = 0, pad32 = 0;
         for (size_t q = 0; q < jobs.size();) {
             size_t e = q;
             while (e < jobs.size() && jobs[e].tab == jobs[q].tab && jobs[e].rot == jobs[q].rot) ++e;
             pad64 += (int64_t)((e - q + 63) / 64) * 64;
+            pad32 += (int64_t)((e - q + 31) / 32) * 32;
             q = e;
         }
         if (pad64 <= 2 * (int64_t)jobs.size()) {
@@ -787,6 +788,8 @@ static void autotune_batches(fmmbem_ctx *c) {
                 cand.push_back({1, 0, 64, 4});
             }
         }
+        // matrix-core tiles of 32 jobs where classes are small (less padding, less reuse per tile)
+        if (c->opt.mfma != 0 && pad32 < pad64 && pad32 <= 2 * (int64_t)jobs.size()) cand.push_back({1, 0, 32, 1});
         for (int whole = 0; whole < 2; ++whole)
             for (int jt : {4, 8, 12, 16, 24, 32, 48, 64})
                 if (trans_lds_bytes(jt, b.P, whole) <= cap && (whole == 0 || jt >= 4)) cand.push_back({0, whole, jt, 0});
@@ -2874,9 +2877,10 @@ int fmmbem_set_batch_shapes(fmmbem_ctx *ctx, int32_t count, const fmmbem_batch_s
         const TransBatch &b = *refs[q].b;
         bool ok;
         if (sh.lane)
-            ok = sh.jt == 64 && sh.whole == 0 &&
-                 (sh.mfma == 0 || sh.mfma == 1 || (sh.mfma == 2 && fused_ok(b)) ||
-                  ((sh.mfma == 3 || sh.mfma == 4) && rcr_ok(b)));
+            ok = sh.whole == 0 &&
+                 ((sh.jt == 64 && (sh.mfma == 0 || sh.mfma == 1 || (sh.mfma == 2 && fused_ok(b)) ||
+                                   ((sh.mfma == 3 || sh.mfma == 4) && rcr_ok(b)))) ||
+                  (sh.jt == 32 && sh.mfma == 1));
         else
             ok = sh.mfma == 0 && (sh.whole == 0 || sh.whole == 1) && sh.jt >= 4 && sh.jt <= 64 && sh.jt % 4 == 0 &&
                  trans_lds_bytes(sh.jt, b.P, sh.whole) <= cap;

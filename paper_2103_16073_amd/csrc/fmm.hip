@@ -892,6 +892,53 @@ __device__ inline void bessel_j_seq_fast(double x, int N, double *j) {
     for (int n = 0; n <= N; ++n) j[n] *= scale;
 }
 
+// Coefficients of the power series of x^{-n} (2n+1)!! j_n(x) (t_q = t_{q-1} h c_q) for the orders N
+// and N - 1: c[o BS_TERMS + q - 1] = 1 / (q (2n + 2q + 1)), n = N - o, q = 1 .. BS_TERMS.  Computed
+// once per workgroup, so that each series term costs two multiplications.
+constexpr int BS_TERMS = 40;
+__device__ inline void bessel_series_coeffs(int N, double *c, int tid, int nthreads) {
+    for (int e = tid; e < 2 * BS_TERMS; e += nthreads) {
+        const int o = e / BS_TERMS, q = e % BS_TERMS + 1, n = N - o;
+        c[e] = 1.0 / ((double)q * (2.0 * n + 2.0 * q + 1.0));
+    }
+}
+
+// j_0(x) .. j_N(x): for 1e-2 <= x < 4 and 1 <= N <= 40 the method of bessel_j_seq (j_N and j_{N-1}
+// from their series, then the downward recurrence) with both series summed in one loop from the
+// coefficients c of bessel_series_coeffs(N); otherwise bessel_j_seq_fast.
+__device__ inline void bessel_j_seq_tab(double x, int N, double *j, const double *c) {
+    if (x < 1e-2 || x >= 4.0 || N > 40 || N < 1) {
+        bessel_j_seq_fast(x, N, j);
+        return;
+    }
+    const double h = -0.5 * x * x;
+    double sh = 1.0, th = 1.0, sl = 1.0, tl = 1.0;  // orders N and N - 1
+    for (int q = 0; q < BS_TERMS; ++q) {
+        th *= h * c[q];
+        tl *= h * c[BS_TERMS + q];
+        sh += th;
+        sl += tl;
+        if (fabs(th) <= 1e-17 * fabs(sh) && fabs(tl) <= 1e-17 * fabs(sl)) break;
+    }
+    double xn = 1.0, df = 1.0;  // x^{N-1} and (2N-1)!!
+    for (int n = 1; n < N; ++n) {
+        xn *= x;
+        df *= 2.0 * n + 1.0;
+    }
+    const double pre = xn / df;
+    double jh = pre * x / (2.0 * N + 1.0) * sh;
+    double jl = pre * sl;
+    j[N] = jh;
+    j[N - 1] = jl;
+    const double ix = 1.0 / x;
+    for (int n = N - 1; n >= 1; --n) {
+        const double jm = fma((2.0 * n + 1.0) * ix, jl, -jh);
+        j[n - 1] = jm;
+        jh = jl;
+        jl = jm;
+    }
+}
+
 // P2M with one thread per basis slot.  A workgroup takes one leaf; per chunk of CH sources:
 //  1. one thread per source: frame, j_0..j_p(k r), the phase powers E_m' = (sin(th) e^{i phi})^m'
 //     and the slot weights al_k of every vector;
@@ -916,10 +963,28 @@ __global__ void __launch_bounds__(256) k_p2m(int nleaf, int p, int CH, const int
     double *jb = Rb + CH * TB;                  // CH * (p+2)
     double *cth = jb + CH * (p + 2);            // CH
     double *lt = cth + CH;                      // 3 TB: Legendre recurrence table
+    double *bc = lt + 3 * TB;                   // 2 BS_TERMS: series coefficients of j_p, j_{p-1}
     double2 *SL = smem;                         // after the last chunk: [8][TS] slot sums of one vector
     for (int e = tid; e < 3 * TB; e += blockDim.x) lt[e] = leg[e];
+    bessel_series_coeffs(p, bc, tid, blockDim.x);
     const double4 C = center[b];
     const int ss = leaf_start[b], se = leaf_start[b + 1];
+    // a chunk's source data is loaded while the previous chunk is summed
+    double4 pc = make_double4(0, 0, 0, 0), pn = pc;
+    double2 pq[NR], pw[NR];
+    auto fetch = [&](int j0n) {
+        const int j = j0n + tid;
+        if (tid < CH && j < se) {
+            pc = ec[j];
+            pn = en[j];
+#pragma unroll
+            for (int rr = 0; rr < NR; ++rr) {
+                pq[rr] = sigma[(int64_t)j * NR + rr];
+                pw[rr] = mu[(int64_t)j * NR + rr];
+            }
+        }
+    };
+    fetch(ss);
     // this thread's slot
     int sn = 0, sm = 0;
     if (tid < TB) {
@@ -938,13 +1003,12 @@ __global__ void __launch_bounds__(256) k_p2m(int nleaf, int p, int CH, const int
         const int cnt = min(CH, se - j0);
         __syncthreads();  // the previous chunk's readers are done (and lt is in place)
         if (tid < cnt) {
-            const int j = j0 + tid;
-            const double4 c = ec[j], nv = en[j];
+            const double4 c = pc, nv = pn;
             double r, ct, st;
             double2 eph;
             sph_frame(c.x - C.x, c.y - C.y, c.z - C.z, r, ct, st, eph);
             cth[tid] = ct;
-            bessel_j_seq_fast(k * r, p, jb + tid * (p + 2));
+            bessel_j_seq_tab(k * r, p, jb + tid * (p + 2), bc);
             const double2 u = cscale(eph, st);
             double2 e = cmk(1.0, 0.0);
             for (int m = 0; m <= p; ++m) {
@@ -953,7 +1017,7 @@ __global__ void __launch_bounds__(256) k_p2m(int nleaf, int p, int CH, const int
             }
 #pragma unroll
             for (int rr = 0; rr < NR; ++rr) {
-                const double2 q = cscale(sigma[(int64_t)j * NR + rr], c.w), w = cscale(mu[(int64_t)j * NR + rr], c.w);
+                const double2 q = cscale(pq[rr], c.w), w = cscale(pw[rr], c.w);
                 al[(tid * 4) * NR + rr] = q;
                 al[(tid * 4 + 1) * NR + rr] = cscale(w, nv.z);
                 al[(tid * 4 + 2) * NR + rr] = cmul(w, cmk(0.5 * nv.x, -0.5 * nv.y));
@@ -961,6 +1025,7 @@ __global__ void __launch_bounds__(256) k_p2m(int nleaf, int p, int CH, const int
             }
         }
         __syncthreads();
+        fetch(j0 + CH);
         for (int w = tid; w < cnt * npair; w += blockDim.x) {
             const int s = w / npair, pr = w - s * npair;
             const double ct = cth[s];
@@ -1046,10 +1111,12 @@ __global__ void __launch_bounds__(64) k_l2p(int nleaf, int p, const int32_t *lea
     const double2 *Dg = Lc + (int64_t)b * NR * pp;   // NR expansions of this leaf
     double2 *Dl = l2p_sm;
     double *lt = STAGE ? (double *)(Dl + NR * pp) : (double *)l2p_sm;  // 3 TB: Legendre recurrence (degrees < p)
-    double *jb = lt + 3 * TB + tid * (p + 2);
+    double *bc = lt + 3 * TB;                                           // series coefficients of j_{p-1}, j_{p-2}
+    double *jb = bc + 2 * BS_TERMS + tid * (p + 2);
     const double2 *D = STAGE ? (const double2 *)Dl : Dg;
     if (has_far) {
         for (int e = tid; e < 3 * TB; e += blockDim.x) lt[e] = leg[e];
+        bessel_series_coeffs(p - 1, bc, tid, blockDim.x);
         if (STAGE)
             for (int e = tid; e < NR * pp; e += blockDim.x) Dl[e] = Dg[e];
         __syncthreads();
@@ -1063,7 +1130,7 @@ __global__ void __launch_bounds__(64) k_l2p(int nleaf, int p, const int32_t *lea
             double r, ct, st;
             double2 eph;
             sph_frame(c.x - C.x, c.y - C.y, c.z - C.z, r, ct, st, eph);
-            bessel_j_seq_fast(k * r, p - 1, jb);
+            bessel_j_seq_tab(k * r, p - 1, jb, bc);
             double2 e = cmk(1.0, 0.0);
             double sp = 1.0;
             for (int mp = 0; mp < p; ++mp) {
@@ -1595,7 +1662,7 @@ static size_t p2m_slot_stage(int nr, int p) {
 static bool p2m_slot_ok(int p) { return (p + 1) * (p + 2) / 2 <= 256; }
 static int p2m_slot_chunk(int nr, int p, size_t &sh) {
     const int TB = (p + 1) * (p + 2) / 2;
-    const size_t per = p2m_slot_stage(nr, p), fixed = (size_t)3 * TB * 8, sums = (size_t)8 * (TB + 1) * 16;
+    const size_t per = p2m_slot_stage(nr, p), fixed = (size_t)(3 * TB + 2 * BS_TERMS) * 8, sums = (size_t)8 * (TB + 1) * 16;
     // about 40 KB per workgroup (four resident per CU), at least the slot sums' area
     int CH = (int)std::max<size_t>(1, std::min<size_t>(64, (40000 - std::min<size_t>(fixed, 39000)) / per));
     while ((size_t)CH * per < sums) ++CH;
@@ -1639,7 +1706,7 @@ void launch_l2p(int nr, int nleaf, int p, const int32_t *leaf_start, const doubl
                 const double2 *Lc, double k, const double *leg, const double2 *ynear, double half,
                 const int32_t *perm, int64_t n, const double2 *x, double2 *y, int has_far, hipStream_t st) {
     if (nleaf <= 0) return;
-    const size_t base = ((size_t)64 * (p + 2) + (size_t)3 * p * (p + 1) / 2) * sizeof(double);
+    const size_t base = ((size_t)64 * (p + 2) + (size_t)3 * p * (p + 1) / 2 + 2 * BS_TERMS) * sizeof(double);
     const size_t staged = base + (size_t)nr * p * p * 16;
     if (staged <= 48 * 1024) {
 #define L2P_CALL(R)                                                                                                   \

@@ -211,7 +211,8 @@ struct Timings {
 constexpr int MLP_IN = 140, MLP_H = 128, MLP_OUT = 128;
 struct Mlp {
     float *w32 = nullptr, *m1 = nullptr, *m2 = nullptr;  // master weights and Adam moments (packed)
-    __half *w16 = nullptr;                                // forward copy
+    __half *w16 = nullptr;                                // FP16 copy (the backward pass)
+    __half *w16t = nullptr;  // FP16 copy per layer transposed, out x in padded to 16 (matrix-core forward)
     int64_t step = 0;
     bool ready = false;
     void init(DeviceBuffers &buf, uint64_t seed, hipStream_t st);

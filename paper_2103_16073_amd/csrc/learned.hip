@@ -106,58 +106,56 @@ __global__ void __launch_bounds__(64) k_mlp_target(int64_t nchunk, const int32_t
 }
 
 // ------------------------------------------------------------------ dense layers
-// Y[M x NO] = act(X[M x K] W[K x NO] + b), W in FP16, FP32 accumulation.  64 rows per block,
-// 256 threads: thread (ty, tx) computes rows 8 ty .. 8 ty + 7 and columns tx, tx+32, tx+64, tx+96.
-constexpr int LT_M = 64, LT_K = 32;
+constexpr int LT_M = 64;  // rows per workgroup
 
-__global__ void __launch_bounds__(256) k_lin_fwd(int64_t M, int K, int NO, const float *X, const __half *W,
-                                                 const float *b, float *Y, int relu) {
-    __shared__ float xs[LT_M][LT_K + 1];
-    __shared__ float ws[LT_K][MLP_H];
-    const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;  // ty 0..7 -> 8 rows each
-    const int64_t m0 = (int64_t)blockIdx.x * LT_M;
-    float acc[8][4];
+// Y[M x NO] = act(X[M x K] W[K x NO] + b) on matrix cores (the forward pass: the solve's
+// preconditioner and training): v_mfma_f32_16x16x16f16 takes FP16 inputs (the layer's input rounded to FP16) and FP16 weights
+// and accumulates in FP32.  Wt holds W transposed, NO x Kp with Kp = K rounded up to 16 and zeros
+// past K, so that a lane's four consecutive K values are one 8-byte load.  Operand layouts of the
+// instruction, lane l = 16 g + c: A[c][4 g + j] and B[4 g + j][c] (j = 0..3), D[4 g + i][c].
+// 64 rows per workgroup, wavefront w rows 16 w .. 16 w + 15 and all NO = 128 columns (8 blocks).
+typedef _Float16 mlp_h4 __attribute__((ext_vector_type(4)));
+typedef float mlp_f4 __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(256) k_lin_fwd_mfma(int64_t M, int K, int Kp, const float *X, const __half *Wt,
+                                                      const float *b, float *Y, int relu) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, g = lane >> 4, c = lane & 15;
+    const int64_t r0 = (int64_t)blockIdx.x * LT_M + 16 * wv, ra = r0 + c;
+    const _Float16 *W = (const _Float16 *)Wt;
+    mlp_f4 acc[MLP_H / 16];
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = 0.f;
-    for (int k0 = 0; k0 < K; k0 += LT_K) {
-        __syncthreads();
-        for (int e = tid; e < LT_M * LT_K; e += 256) {
-            const int r = e / LT_K, kk = e % LT_K;
-            const int64_t m = m0 + r;
-            xs[r][kk] = (m < M && k0 + kk < K) ? X[m * K + k0 + kk] : 0.f;
+    for (int cb = 0; cb < MLP_H / 16; ++cb) acc[cb] = mlp_f4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < Kp; k0 += 16) {
+        const int kk = k0 + 4 * g;  // K % 4 == 0: the four values lie on the same side of K
+        mlp_h4 a = {0, 0, 0, 0};
+        if (ra < M && kk < K) {
+            const float4 x = *(const float4 *)(X + ra * K + kk);
+            a = mlp_h4{(_Float16)x.x, (_Float16)x.y, (_Float16)x.z, (_Float16)x.w};
         }
-        for (int e = tid; e < LT_K * MLP_H; e += 256) {
-            const int kk = e / MLP_H, o = e % MLP_H;
-            ws[kk][o] = (k0 + kk < K && o < NO) ? __half2float(W[(int64_t)(k0 + kk) * NO + o]) : 0.f;
-        }
-        __syncthreads();
-        for (int kk = 0; kk < LT_K; ++kk) {
-            float w[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) w[j] = ws[kk][tx + 32 * j];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const float xv = xs[ty * 8 + i][kk];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(xv, w[j], acc[i][j]);
-            }
+        for (int cb = 0; cb < MLP_H / 16; ++cb) {
+            const mlp_h4 bv = *(const mlp_h4 *)(W + (int64_t)(16 * cb + c) * Kp + kk);
+            acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(a, bv, acc[cb], 0, 0, 0);
         }
     }
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const int64_t m = m0 + ty * 8 + i;
-        if (m >= M) continue;
+    for (int cb = 0; cb < MLP_H / 16; ++cb)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int o = tx + 32 * j;
-            if (o >= NO) continue;
-            float v = acc[i][j] + b[o];
+        for (int i = 0; i < 4; ++i) {
+            const int64_t m = r0 + 4 * g + i;
+            const int o = 16 * cb + c;
+            if (m >= M) continue;
+            float v = acc[cb][i] + b[o];
             if (relu) v = fmaxf(v, 0.f);
-            Y[m * NO + o] = v;
+            Y[m * MLP_H + o] = v;
         }
-    }
+}
+
+// the transposed, padded FP16 copy of one layer: Wt[o][k] = W[k][o] (k < K), 0 (K <= k < Kp)
+__global__ void k_half_t(int K, int Kp, int NO, const float *W, __half *Wt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)NO * Kp) return;
+    const int o = (int)(i / Kp), k = (int)(i % Kp);
+    Wt[i] = __float2half(k < K ? W[(int64_t)k * NO + o] : 0.f);
 }
 
 // dX[M x K] = (dY[M x NO] W^T) masked by (Xact > 0) when mask is set (ReLU of the layer below)
@@ -272,6 +270,20 @@ static int64_t layer_w_off(int l) {
     for (int q = 0; q < l; ++q) s += (int64_t)LAYER_IN[q] * LAYER_OUT[q] + LAYER_OUT[q];
     return s;
 }
+static int layer_kp(int l) { return (LAYER_IN[l] + 15) / 16 * 16; }
+static int64_t layer_wt_off(int l) {  // offsets in the transposed FP16 copy
+    int64_t s = 0;
+    for (int q = 0; q < l; ++q) s += (int64_t)LAYER_OUT[q] * layer_kp(q);
+    return s;
+}
+static void make_half_t(const float *w32, __half *w16t, hipStream_t st) {
+    for (int l = 0; l < 4; ++l) {
+        const int64_t n = (int64_t)LAYER_OUT[l] * layer_kp(l);
+        k_half_t<<<ceil_div(n, 256), 256, 0, st>>>(LAYER_IN[l], layer_kp(l), LAYER_OUT[l], w32 + layer_w_off(l),
+                                                   w16t + layer_wt_off(l));
+        LAUNCH_OK();
+    }
+}
 
 void Mlp::init(DeviceBuffers &buf, uint64_t seed, hipStream_t st) {
     const int64_t np = mlp_param_count();
@@ -293,6 +305,7 @@ void Mlp::init(DeviceBuffers &buf, uint64_t seed, hipStream_t st) {
     }
     w32 = dget<float>(buf, "mlp_w32", np);
     w16 = dget<__half>(buf, "mlp_w16", np);
+    w16t = dget<__half>(buf, "mlp_w16t", layer_wt_off(4 - 1) + (int64_t)LAYER_OUT[3] * layer_kp(3));
     m1 = dget<float>(buf, "mlp_m1", np);
     m2 = dget<float>(buf, "mlp_m2", np);
     h2d_now(w32, h.data(), sizeof(float) * np, st);  // h is a temporary
@@ -307,6 +320,7 @@ void Mlp::sync_half(hipStream_t st) {
     const int64_t np = mlp_param_count();
     k_to_half<<<ceil_div(np, 256), 256, 0, st>>>(np, w32, w16);
     LAUNCH_OK();
+    make_half_t(w32, w16t, st);
 }
 
 // forward over M samples; A[l] receives the output of layer l (A[3] = network output)
@@ -314,9 +328,10 @@ void Mlp::forward(int64_t M, const float *X, float *const A[4], hipStream_t st) 
     const float *in = X;
     for (int l = 0; l < 4; ++l) {
         const int64_t off = layer_w_off(l);
-        const __half *W = w16 + off;
         const float *b = w32 + off + (int64_t)LAYER_IN[l] * LAYER_OUT[l];
-        k_lin_fwd<<<ceil_div(M, LT_M), 256, 0, st>>>(M, LAYER_IN[l], LAYER_OUT[l], in, W, b, A[l], l < 3 ? 1 : 0);
+        static_assert(MLP_IN % 4 == 0 && MLP_H % 4 == 0 && MLP_OUT == MLP_H, "matrix-core layer shapes");
+        k_lin_fwd_mfma<<<ceil_div(M, LT_M), 256, 0, st>>>(M, LAYER_IN[l], layer_kp(l), in, w16t + layer_wt_off(l), b,
+                                                          A[l], l < 3 ? 1 : 0);
         LAUNCH_OK();
         in = A[l];
     }
@@ -361,6 +376,7 @@ void Mlp::adam_step(const float *grad, float lr, hipStream_t st) {
     const float c1 = 1.f - std::pow(b1, (float)step), c2 = 1.f - std::pow(b2, (float)step);
     k_adam<<<ceil_div(np, 256), 256, 0, st>>>(np, w32, grad, m1, m2, lr, b1, b2, 1e-8f, c1, c2, w16);
     LAUNCH_OK();
+    make_half_t(w32, w16t, st);
 }
 
 void gather_rows(int64_t B, int width, const int64_t *idx, const float *src, float *dst, hipStream_t st) {

@@ -824,32 +824,37 @@ constexpr int TM_LD = 130;  // LDS row stride (doubles) of the staged A and B ch
 // output rows of 128 columns)
 constexpr int TM_LDS = 4 * TM_KC * TM_LD;
 
-// Rotation of degree n for one tile, as a GEMM over K chunks staged in LDS (double-buffered: the
-// global loads of chunk c+1 are issued before the matrix-core work on chunk c).  RBG row blocks
-// of 16 rows per pass.
+// Rotation of degree n for one tile of TMJ jobs (64 or 32: 2 TMJ columns, the four wavefronts owning
+// TMJ / 2 columns each, in NCB = TMJ / 32 blocks of 16), as a GEMM over K chunks staged in LDS
+// (double-buffered: the global loads of chunk c+1 are issued before the matrix-core work on chunk
+// c).  RBG row blocks of 16 rows per pass; a workgroup takes the passes pass, pass + npass, ... of
+// its degree.
 //   FWD:  Y = H X, X = e^{i m a} c_n of the sources, A[r][k] = H[r][k] = HT[k][r]; rows -> W1.
 //   !FWD: Y = H^T X, X = W2 rows, A[r][k] = H[k][r]; the pass's outputs go through LDS, are
 //         phased (e^{-i m a}), summed over the runs of one target and stored job-major in W1.
-template <class R, bool FWD, int RBG>
+template <class R, bool FWD, int RBG, int TMJ>
 __global__ void __launch_bounds__(256) k_tm_rot(TransArgsT<R> a, int npass) {
     using C = typename Cx<R>::T;
     using Op = TmOp<R>;
     using v4 = typename Op::v4;
-    constexpr int RG = 16 * RBG;  // rows per pass
+    constexpr int RG = 16 * RBG;            // rows per pass
+    constexpr int NCOL = 2 * TMJ;           // real columns of a tile
+    constexpr int NCB = TMJ / 32;           // 16-column blocks per wavefront
     static_assert(RG <= 128 && (FWD || RG * TM_LD <= TM_LDS), "pass too large for the LDS block");
+    static_assert(TMJ == 64 || TMJ == 32, "tiles of 64 or 32 jobs");
     __shared__ R lds[TM_LDS];
-    __shared__ int64_t soff[LANE_JT];
-    __shared__ int32_t sdir[LANE_JT];
-    __shared__ int segl[LANE_JT];
+    __shared__ int64_t soff[TMJ];
+    __shared__ int32_t sdir[TMJ];
+    __shared__ int segl[TMJ];
     auto As = [&](int buf, int k, int r) -> R & { return lds[(buf * TM_KC + k) * TM_LD + r]; };
     auto Bs = [&](int buf, int k, int c) -> R & { return lds[((2 + buf) * TM_KC + k) * TM_LD + c]; };
     int tile, nq;
     xcd_block(tile, nq);
     const int n = nq / npass, pass = nq - n * npass;  // degree, and the pass's share of its row groups
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int64_t J0 = (int64_t)tile * LANE_JT;
+    const int64_t J0 = (int64_t)tile * TMJ;
     const int P2 = a.P * a.P, phs = 2 * a.PH + 1, ps2 = a.psrc * a.psrc;
-    if (tid < LANE_JT) {
+    if (tid < TMJ) {
         const int64_t J = J0 + tid, Jc = J < a.njob ? J : a.njob - 1;
         soff[tid] = FWD ? src_row(a, Jc) * ps2 : 0;
         sdir[tid] = a.jdir[Jc / a.nr] * phs + a.PH;
@@ -860,12 +865,13 @@ __global__ void __launch_bounds__(256) k_tm_rot(TransArgsT<R> a, int npass) {
     const int tr = a.tile_rot[tile / a.nr];
     const R *Mn = (FWD ? a.HT : a.H) + (int64_t)tr * rot_table_size(a.P) + rot_block_off(n);
     const R *Xin = (const R *)a.W2;
-    const int colw = 32 * wv + (lane & 15), kq = lane >> 4;
+    const int colw = (NCOL / 4) * wv + (lane & 15), kq = lane >> 4;
     const int nch = (w + TM_KC - 1) / TM_KC;
-    constexpr int NA = TM_KC * RG / 256;  // A values staged per thread
+    constexpr int NA = TM_KC * RG / 256;   // A values staged per thread
+    constexpr int NB = TM_KC * NCOL / 256;  // B values staged per thread
     for (int rb0 = pass * RBG; rb0 < RB; rb0 += npass * RBG) {
         const int r0 = rb0 * 16;
-        R ra[NA], rbv[8];
+        R ra[NA], rbv[NB];
         auto gload = [&](int kc) {
 #pragma unroll
             for (int i = 0; i < NA; ++i) {
@@ -874,8 +880,8 @@ __global__ void __launch_bounds__(256) k_tm_rot(TransArgsT<R> a, int npass) {
             }
             if (FWD) {
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int e = tid + 256 * i, kk = e / LANE_JT, j = e % LANE_JT, k = kc + kk;
+                for (int i = 0; i < NB / 2; ++i) {
+                    const int e = tid + 256 * i, kk = e / TMJ, j = e % TMJ, k = kc + kk;
                     C x = mkc<C>(0, 0);
                     if (k < w) x = mulc(a.ph[sdir[j] + k - n], a.src[soff[j] + n * n + k]);  // e^{i m a} c_n^m
                     rbv[2 * i] = x.x;
@@ -883,9 +889,9 @@ __global__ void __launch_bounds__(256) k_tm_rot(TransArgsT<R> a, int npass) {
                 }
             } else {
 #pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    const int e = tid + 256 * i, kk = e / 128, col = e % 128, k = kc + kk;
-                    rbv[i] = k < w ? Xin[((int64_t)tile * P2 + n * n + k) * 128 + col] : R(0);
+                for (int i = 0; i < NB; ++i) {
+                    const int e = tid + 256 * i, kk = e / NCOL, col = e % NCOL, k = kc + kk;
+                    rbv[i] = k < w ? Xin[((int64_t)tile * P2 + n * n + k) * NCOL + col] : R(0);
                 }
             }
         };
@@ -897,22 +903,24 @@ __global__ void __launch_bounds__(256) k_tm_rot(TransArgsT<R> a, int npass) {
             }
             if (FWD) {
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int e = tid + 256 * i, kk = e / LANE_JT, j = e % LANE_JT;
+                for (int i = 0; i < NB / 2; ++i) {
+                    const int e = tid + 256 * i, kk = e / TMJ, j = e % TMJ;
                     Bs(buf, kk, 2 * j) = rbv[2 * i];
                     Bs(buf, kk, 2 * j + 1) = rbv[2 * i + 1];
                 }
             } else {
 #pragma unroll
-                for (int i = 0; i < 8; ++i) {
+                for (int i = 0; i < NB; ++i) {
                     const int e = tid + 256 * i;
-                    Bs(buf, e / 128, e % 128) = rbv[i];
+                    Bs(buf, e / NCOL, e % NCOL) = rbv[i];
                 }
             }
         };
-        v4 acc[RBG][2];
+        v4 acc[RBG][NCB];
 #pragma unroll
-        for (int q = 0; q < RBG; ++q) acc[q][0] = acc[q][1] = v4{0, 0, 0, 0};
+        for (int q = 0; q < RBG; ++q)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) acc[q][cb] = v4{0, 0, 0, 0};
         gload(0);
         __syncthreads();  // the previous pass's readers of the LDS block are done
         lstore(0);
@@ -922,13 +930,15 @@ __global__ void __launch_bounds__(256) k_tm_rot(TransArgsT<R> a, int npass) {
             if (c + 1 < nch) gload((c + 1) * TM_KC);
             const int kn = min(TM_KC, w - c * TM_KC);
             for (int ks = 0; ks < kn; ks += 4) {
-                const R b0 = Bs(buf, ks + kq, colw), b1 = Bs(buf, ks + kq, colw + 16);
+                R bv[NCB];
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) bv[cb] = Bs(buf, ks + kq, colw + 16 * cb);
 #pragma unroll
                 for (int q = 0; q < RBG; ++q) {
                     if (rb0 + q >= RB) break;
                     const R av = As(buf, ks + kq, q * 16 + (lane & 15));
-                    acc[q][0] = Op::mma(av, b0, acc[q][0]);
-                    acc[q][1] = Op::mma(av, b1, acc[q][1]);
+#pragma unroll
+                    for (int cb = 0; cb < NCB; ++cb) acc[q][cb] = Op::mma(av, bv[cb], acc[q][cb]);
                 }
             }
             if (c + 1 < nch) {
@@ -942,26 +952,26 @@ __global__ void __launch_bounds__(256) k_tm_rot(TransArgsT<R> a, int npass) {
             for (int q = 0; q < RBG; ++q) {
                 if (rb0 + q >= RB) break;
 #pragma unroll
-                for (int cb = 0; cb < 2; ++cb)
+                for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         const int r = (rb0 + q) * 16 + Op::row(kq, i);
-                        if (r < w) Wout[((int64_t)tile * P2 + n * n + r) * 128 + colw + 16 * cb] = acc[q][cb][i];
+                        if (r < w) Wout[((int64_t)tile * P2 + n * n + r) * NCOL + colw + 16 * cb] = acc[q][cb][i];
                     }
             }
         } else {
-            // the pass's RG output rows x 128 columns through the LDS block, then phase, run sums
+            // the pass's RG output rows x NCOL columns through the LDS block, then phase, run sums
             // and job-major stores (consecutive threads: consecutive rows of one job)
             __syncthreads();
 #pragma unroll
             for (int q = 0; q < RBG; ++q)
 #pragma unroll
-                for (int cb = 0; cb < 2; ++cb)
+                for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
                     for (int i = 0; i < 4; ++i) lds[(q * 16 + Op::row(kq, i)) * TM_LD + colw + 16 * cb] = acc[q][cb][i];
             __syncthreads();
             const int nrow = min(RG, w - r0);
-            for (int e = tid; e < RG * LANE_JT; e += 256) {
+            for (int e = tid; e < RG * TMJ; e += 256) {
                 const int j = e / RG, rr = e % RG, r = r0 + rr;
                 const int len = segl[j];
                 if (rr >= nrow || len == 0) continue;
@@ -977,17 +987,19 @@ __global__ void __launch_bounds__(256) k_tm_rot(TransArgsT<R> a, int npass) {
     }
 }
 
-// Coaxial step of order m for one tile: Y = T X with the complex (p-|m|)^2 block T (entries
-// (-1)^{n+n'} (E|F)_{n n'}, as in the lane kernel) applied to the W1 rows of order m, K chunks
-// staged in LDS as for the rotations.  With X' the input with each job's real and imaginary
+// Coaxial step of order m for one tile of TMJ jobs: Y = T X with the complex (p-|m|)^2 block T
+// (entries (-1)^{n+n'} (E|F)_{n n'}, as in the lane kernel) applied to the W1 rows of order m, K
+// chunks staged in LDS as for the rotations.  With X' the input with each job's real and imaginary
 // columns swapped and the new real one negated (read from the partner column of X in LDS),
 // Y = Re(T) X + Im(T) X' column by column, so one accumulator set takes both real GEMMs.
-template <class R>
+template <class R, int TMJ>
 __global__ void __launch_bounds__(256) k_tm_coax(TransArgsT<R> a, int npass) {
     using C = typename Cx<R>::T;
     using Op = TmOp<R>;
     using v4 = typename Op::v4;
     constexpr int RBG = 4, RG = 16 * RBG, LA = RG + 2;
+    constexpr int NCOL = 2 * TMJ, NCB = TMJ / 32, NX = TM_KC * TMJ / 256;
+    static_assert(TMJ == 64 || TMJ == 32, "tiles of 64 or 32 jobs");
     // A: real part (chunks 0, 1) and imaginary part (2, 3), RG + 2 columns; B: X (2 chunks)
     __shared__ R ldsA[4 * TM_KC * LA];
     __shared__ R ldsB[2 * TM_KC * TM_LD];
@@ -1005,21 +1017,21 @@ __global__ void __launch_bounds__(256) k_tm_coax(TransArgsT<R> a, int npass) {
     const C *Xin = a.W1;
     if (am >= pm) {  // no source of this order
         if (pass != 0) return;
-        for (int e = tid; e < rows * 128; e += 256) {
-            const int nn = am + e / 128;
-            Wout[((int64_t)tile * P2 + nn * nn + nn + m) * 128 + e % 128] = R(0);
+        for (int e = tid; e < rows * NCOL; e += 256) {
+            const int nn = am + e / NCOL;
+            Wout[((int64_t)tile * P2 + nn * nn + nn + m) * NCOL + e % NCOL] = R(0);
         }
         return;
     }
     const int B = a.PT - am, cin = a.psrc - am, RB = (rows + 15) / 16;
     const C *Tm = a.coax + (int64_t)a.tile_coax[tile / a.nr] * coax_table_size(a.PT) + coax_block_off(a.PT, am);
-    const int colw = 32 * wv + (lane & 15), kq = lane >> 4;
+    const int colw = (NCOL / 4) * wv + (lane & 15), kq = lane >> 4;
     const R swp = (colw & 1) ? R(1) : R(-1);
     const int nch = (cin + TM_KC - 1) / TM_KC;
     for (int rb0 = pass * RBG; rb0 < RB; rb0 += npass * RBG) {
         const int r0 = rb0 * 16;
         C ta[TM_KC * RG / 256];
-        C xb[4];  // (re, im) of 4 (k, job) inputs
+        C xb[NX];  // (re, im) of NX (k, job) inputs
         auto gload = [&](int kc) {
 #pragma unroll
             for (int i = 0; i < TM_KC * RG / 256; ++i) {
@@ -1029,9 +1041,9 @@ __global__ void __launch_bounds__(256) k_tm_coax(TransArgsT<R> a, int npass) {
                 ta[i] = t;
             }
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int e = tid + 256 * i, kk = e / LANE_JT, j = e % LANE_JT, k = kc + kk, nb = am + k;
-                xb[i] = k < cin ? Xin[((int64_t)tile * P2 + nb * nb + nb + m) * 64 + j] : mkc<C>(0, 0);
+            for (int i = 0; i < NX; ++i) {
+                const int e = tid + 256 * i, kk = e / TMJ, j = e % TMJ, k = kc + kk, nb = am + k;
+                xb[i] = k < cin ? Xin[((int64_t)tile * P2 + nb * nb + nb + m) * TMJ + j] : mkc<C>(0, 0);
             }
         };
         auto lstore = [&](int buf) {
@@ -1042,15 +1054,17 @@ __global__ void __launch_bounds__(256) k_tm_coax(TransArgsT<R> a, int npass) {
                 Ai(buf, e / RG, e % RG) = ta[i].y;
             }
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int e = tid + 256 * i, kk = e / LANE_JT, j = e % LANE_JT;
+            for (int i = 0; i < NX; ++i) {
+                const int e = tid + 256 * i, kk = e / TMJ, j = e % TMJ;
                 Bs(buf, kk, 2 * j) = xb[i].x;
                 Bs(buf, kk, 2 * j + 1) = xb[i].y;
             }
         };
-        v4 acc[RBG][2];
+        v4 acc[RBG][NCB];
 #pragma unroll
-        for (int q = 0; q < RBG; ++q) acc[q][0] = acc[q][1] = v4{0, 0, 0, 0};
+        for (int q = 0; q < RBG; ++q)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) acc[q][cb] = v4{0, 0, 0, 0};
         gload(0);
         __syncthreads();
         lstore(0);
@@ -1060,18 +1074,23 @@ __global__ void __launch_bounds__(256) k_tm_coax(TransArgsT<R> a, int npass) {
             if (c + 1 < nch) gload((c + 1) * TM_KC);
             const int kn = min(TM_KC, cin - c * TM_KC);
             for (int ks = 0; ks < kn; ks += 4) {
-                const R b0 = Bs(buf, ks + kq, colw), b1 = Bs(buf, ks + kq, colw + 16);
-                // X': column 2j holds -Im x_j, column 2j+1 holds Re x_j (the partner column)
-                const R w0 = swp * Bs(buf, ks + kq, colw ^ 1), w1 = swp * Bs(buf, ks + kq, (colw + 16) ^ 1);
+                R bv[NCB], wv2[NCB];
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) {
+                    bv[cb] = Bs(buf, ks + kq, colw + 16 * cb);
+                    // X': column 2j holds -Im x_j, column 2j+1 holds Re x_j (the partner column)
+                    wv2[cb] = swp * Bs(buf, ks + kq, (colw + 16 * cb) ^ 1);
+                }
 #pragma unroll
                 for (int q = 0; q < RBG; ++q) {
                     if (rb0 + q >= RB) break;
                     const R ar = Ar(buf, ks + kq, q * 16 + (lane & 15));
                     const R ai = Ai(buf, ks + kq, q * 16 + (lane & 15));
-                    acc[q][0] = Op::mma(ar, b0, acc[q][0]);
-                    acc[q][1] = Op::mma(ar, b1, acc[q][1]);
-                    acc[q][0] = Op::mma(ai, w0, acc[q][0]);
-                    acc[q][1] = Op::mma(ai, w1, acc[q][1]);
+#pragma unroll
+                    for (int cb = 0; cb < NCB; ++cb) {
+                        acc[q][cb] = Op::mma(ar, bv[cb], acc[q][cb]);
+                        acc[q][cb] = Op::mma(ai, wv2[cb], acc[q][cb]);
+                    }
                 }
             }
             if (c + 1 < nch) {
@@ -1083,11 +1102,11 @@ __global__ void __launch_bounds__(256) k_tm_coax(TransArgsT<R> a, int npass) {
         for (int q = 0; q < RBG; ++q) {
             if (rb0 + q >= RB) break;
 #pragma unroll
-            for (int cb = 0; cb < 2; ++cb)
+            for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int r = (rb0 + q) * 16 + Op::row(kq, i), nn = am + r;
-                    if (r < rows) Wout[((int64_t)tile * P2 + nn * nn + nn + m) * 128 + colw + 16 * cb] = acc[q][cb][i];
+                    if (r < rows) Wout[((int64_t)tile * P2 + nn * nn + nn + m) * NCOL + colw + 16 * cb] = acc[q][cb][i];
                 }
         }
     }
@@ -1855,8 +1874,9 @@ const char *trans_stage(const TransBatch &b, const TransTables<R> &tb, int stage
         return f32 ? "k_tf_trans_f32" : "k_tf_trans";
     }
     if (b.lane && b.mfma == 1 && stage < 3) {
-        // stages of a lane batch on matrix cores (FP64, or FP32 for mixed products)
-        if (b.JT != LANE_JT) throw FmmError(-1, "lane batches use 64-job tiles");
+        // stages of a lane batch on matrix cores (FP64, or FP32 for mixed products), tiles of 64 or
+        // 32 jobs
+        if (b.JT != LANE_JT && b.JT != LANE_JT / 2) throw FmmError(-1, "matrix-core tiles take 64 or 32 jobs");
         // A small batch (few workgroups per CU) also spreads the row groups of a degree (order)
         // over workgroups, so that the largest degrees do not run as one long workgroup each.
         auto passes = [&](int rows, int rbg, int nd) {
@@ -1867,15 +1887,21 @@ const char *trans_stage(const TransBatch &b, const TransTables<R> &tb, int stage
         switch (stage) {
         case 0:
             np = passes(2 * b.psrc - 1, 8, b.psrc);
-            k_tm_rot<R, true, 8><<<dim3(ntile, b.psrc * np), 256, 0, st>>>(a, np), name = f32 ? "k_tm_rot_fwd_f32" : "k_tm_rot_fwd";
+            if (b.JT == LANE_JT) k_tm_rot<R, true, 8, 64><<<dim3(ntile, b.psrc * np), 256, 0, st>>>(a, np);
+            else k_tm_rot<R, true, 8, 32><<<dim3(ntile, b.psrc * np), 256, 0, st>>>(a, np);
+            name = f32 ? "k_tm_rot_fwd_f32" : "k_tm_rot_fwd";
             break;
         case 1:
             np = passes(b.ptgt, 4, 2 * b.ptgt - 1);
-            k_tm_coax<R><<<dim3(ntile, (2 * b.ptgt - 1) * np), 256, 0, st>>>(a, np), name = f32 ? "k_tm_coax_f32" : "k_tm_coax";
+            if (b.JT == LANE_JT) k_tm_coax<R, 64><<<dim3(ntile, (2 * b.ptgt - 1) * np), 256, 0, st>>>(a, np);
+            else k_tm_coax<R, 32><<<dim3(ntile, (2 * b.ptgt - 1) * np), 256, 0, st>>>(a, np);
+            name = f32 ? "k_tm_coax_f32" : "k_tm_coax";
             break;
         default:
             np = passes(2 * b.ptgt - 1, 4, b.ptgt);
-            k_tm_rot<R, false, 4><<<dim3(ntile, b.ptgt * np), 256, 0, st>>>(a, np), name = f32 ? "k_tm_rot_back_f32" : "k_tm_rot_back";
+            if (b.JT == LANE_JT) k_tm_rot<R, false, 4, 64><<<dim3(ntile, b.ptgt * np), 256, 0, st>>>(a, np);
+            else k_tm_rot<R, false, 4, 32><<<dim3(ntile, b.ptgt * np), 256, 0, st>>>(a, np);
+            name = f32 ? "k_tm_rot_back_f32" : "k_tm_rot_back";
         }
         LAUNCH_OK();
         return name;

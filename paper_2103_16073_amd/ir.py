@@ -136,6 +136,9 @@ def sweep_plane(L, zeta, rs, freqs, receivers, bands, epw=6.7, tol=1e-4, wave_n=
                 for q, i in enumerate(rnd):
                     H[i] = ctxs[q].fmmbem_eval_field(0, receivers, xs[q])
                 t_field += time.perf_counter() - ts
+                if log:
+                    log(f"    {', '.join(f'{freqs[i]:.0f}' for i in rnd)} Hz: iterations "
+                        f"{', '.join(str(int(iters[i])) for i in rnd)}")
         finally:
             for c in ctxs:
                 c.close()

@@ -1,9 +1,10 @@
 """Plain numpy reference of the learned preconditioner's network (test infrastructure).
 
 Layers 140 -> 128 -> 128 -> 128 (ReLU) -> 128 (linear); parameters packed per layer as W
-(in x out, row-major) then b (out).  The device forward pass multiplies by FP16-rounded W
-and adds FP32 b; the reference does the same arithmetic in float64 so that only the
-accumulation order differs.
+(in x out, row-major) then b (out).  The device forward pass (matrix cores, FP16 inputs) multiplies
+each layer's input rounded to FP16 by FP16-rounded W and adds FP32 b; the reference does the same
+arithmetic in float64 so that only the accumulation order differs.  The backward pass takes the
+layers' unrounded outputs, as the device's does.
 """
 import numpy as np
 
@@ -31,7 +32,8 @@ def forward(w, X, half=True):
     acts = [np.asarray(X, np.float64)]
     layers = unpack(w, half)
     for l, (W, b) in enumerate(layers):
-        z = acts[-1] @ W + b
+        x = acts[-1].astype(np.float16).astype(np.float64) if half else acts[-1]
+        z = x @ W + b
         acts.append(np.maximum(z, 0.0) if l < 3 else z)
     return acts
 

@@ -565,6 +565,40 @@ def test_register_resident_tiles_vs_lane_tiles_and_oracle(F, mode):
     ctx_r.close()
 
 
+def test_matrix_core_tiles_of_32_jobs_vs_64(F):
+    """Matrix-core translation tiles of 32 jobs (classes padded to 32, each wavefront one 16-column
+    block) against the 64-job tiles on the 6x5x3 m room at 1 kHz with every batch on one-job-per-lane
+    tiles and matrix cores: products of 1, 2 and 4 vectors agree to rounding (1e-12), mixed products
+    to FP32 rounding (1e-5), and the 32-job product matches the oracle's rows (1e-6)."""
+    room, k = synth.config_room(2)
+    ctx64 = make_ctx(F, room, k, lane_tiles=2, mfma=2, fused=0)
+    ctx32 = make_ctx(F, room, k, lane_tiles=2, mfma=2, fused=0)
+    shapes = ctx32.fmmbem_batch_shapes()
+    tm = [d for d in shapes if d["lane"] and d["mfma"] == 1]
+    assert len(tm) >= 6
+    ctx32.fmmbem_set_batch_shapes([dict(d, jt=32) for d in tm])
+    got = ctx32.fmmbem_batch_shapes()
+    assert sum(d["jt"] == 32 for d in got) == len(tm)
+    X = np.stack([synth.complex_normal(room.n, 130 + s) for s in range(4)])
+    for nr in (1, 2, 4):
+        Y64, Y32 = ctx64.fmmbem_matvec(X[:nr]), ctx32.fmmbem_matvec(X[:nr])
+        err = np.linalg.norm(Y32 - Y64) / np.linalg.norm(Y64)
+        print(f"{nr} vectors: 32-job vs 64-job tiles {err:.2e}")
+        assert err < 1e-12, nr
+    y = ctx32.fmmbem_matvec(X[0])[0]
+    rows = np.random.default_rng(10).choice(room.n, 256, replace=False)
+    ref = bem.direct_matvec_rows(room.vertices, room.triangles, k, room.beta, oracle_rc(ctx32, room), X[0], rows)
+    assert np.linalg.norm(y[rows] - ref) / np.linalg.norm(ref) < 1e-6
+    ym64 = ctx64.fmmbem_matvec(X[0], precision=F.FMMBEM_MIXED)[0]
+    ym32 = ctx32.fmmbem_matvec(X[0], precision=F.FMMBEM_MIXED)[0]
+    assert np.linalg.norm(ym32 - ym64) / np.linalg.norm(ym64) < 1e-5
+    # 32-job tiles exist only on matrix cores
+    with pytest.raises(F.FmmbemError):
+        ctx32.fmmbem_set_batch_shapes([dict(tm[0], jt=32, mfma=0)])
+    ctx64.close()
+    ctx32.close()
+
+
 def test_mixed_products_run_lane_batches_fused(F):
     """With `fused` on, mixed products run every lane batch that may use the fused tiles fused, even
     where its shape is the three-pass lane kernels (as the FP64 autotuner may choose): lane shapes
