@@ -672,11 +672,19 @@ static double coax_flops(int ps, int pt) {
 // In FP32 the fused tiles beat the three lane passes at every batch that may use them (they are
 // issue-bound there, not bound by the LDS-limited occupancy of FP64), so mixed products run such
 // batches fused whatever the FP64 shape chosen for them, unless `fused` is off.
+static void zero_dev(fmmbem_ctx *c, void *ptr, size_t bytes);
+
+// accumulate: add into dst; otherwise the batch overwrites every target of dst (an empty batch
+// clears it)
 template <class R>
 static void run_batch(fmmbem_ctx *c, int nrv, const TransBatch &b0, const typename Cx<R>::T *src,
-                      typename Cx<R>::T *dst, const TransTables<R> &tb, const typename Cx<R>::T *ph) {
+                      typename Cx<R>::T *dst, const TransTables<R> &tb, const typename Cx<R>::T *ph,
+                      bool accumulate = true) {
     using C = typename Cx<R>::T;
-    if (b0.njob == 0) return;
+    if (b0.njob == 0) {
+        if (!accumulate) zero_dev(c, dst, sizeof(C) * (size_t)b0.ntgt * nrv * b0.ptgt * b0.ptgt);
+        return;
+    }
     TransBatch b32;
     if (sizeof(R) == 4 && c->opt.fused && b0.lane && b0.mfma == 0 && fused_ok(b0) && tb.frH) {
         b32 = b0;
@@ -705,7 +713,7 @@ static void run_batch(fmmbem_ctx *c, int nrv, const TransBatch &b0, const typena
     for (int stage = 0; stage < 4; ++stage) {
         if (b.lane && b.mfma >= 2 && (stage == 1 || stage == 2)) continue;  // inside the fused kernel
         int e = prof_begin(c);
-        const char *name = trans_stage<R>(b, tb, stage, nrv, src, dst, ph, c->delta_p, W1, W2, st);
+        const char *name = trans_stage<R>(b, tb, stage, nrv, src, dst, ph, c->delta_p, W1, W2, st, accumulate);
         double f = fl[stage], y = by[stage];
         if (b.lane && b.mfma >= 2 && stage == 0) {  // fused: all three stages, each table once
             f = fl[0] + fl[1] + fl[2];
@@ -980,23 +988,20 @@ static void far_field(fmmbem_ctx *c, int nr, bool mixed) {
         if constexpr (sizeof(R) == 8) return tables64(b, coax64);
         else return tables32(b, coax32);
     };
-    auto bytes = [&](int l) { return sizeof(C) * (size_t)c->lev[l].nbox * nr * c->lev[l].p * c->lev[l].p; };
     const int lsplit = std::max(2, L - 2);  // levels >= lsplit: M2L on A
     const int EV_M2L = 2, EV_B = 3, EV_M = 4;  // EV_M + l: M(l) ready
     // A: M2M chain
     c->cur = A;
     for (int l = L - 1; l >= 2; --l) {
         LevelDev &P_ = c->lev[l];
-        zero_dev(c, M(l), bytes(l));
-        run_batch<R>(c, nr, P_.up, M(l + 1), M(l), tab(P_.up, P_.coax_up, P_.coax_up32), ph);
+        run_batch<R>(c, nr, P_.up, M(l + 1), M(l), tab(P_.up, P_.coax_up, P_.coax_up32), ph, false);
         if (l < lsplit) ev_record(c, EV_M + l, A);
     }
     rec(c, 4);
     // A: M2L of the deep levels
     for (int l = L; l >= lsplit; --l) {
         LevelDev &D = c->lev[l];
-        zero_dev(c, Lc(l), bytes(l));
-        run_batch<R>(c, nr, D.m2l, M(l), Lc(l), tab(D.m2l, D.coax_m2l, D.coax_m2l32), ph);
+        run_batch<R>(c, nr, D.m2l, M(l), Lc(l), tab(D.m2l, D.coax_m2l, D.coax_m2l32), ph, false);
     }
     ev_record(c, EV_M2L, A);
     // B: M2L of the upper levels, then the L2L chain top-down
@@ -1004,8 +1009,7 @@ static void far_field(fmmbem_ctx *c, int nr, bool mixed) {
     for (int l = lsplit - 1; l >= 2; --l) {
         LevelDev &D = c->lev[l];
         ev_wait(c, EV_M + l, B);
-        zero_dev(c, Lc(l), bytes(l));
-        run_batch<R>(c, nr, D.m2l, M(l), Lc(l), tab(D.m2l, D.coax_m2l, D.coax_m2l32), ph);
+        run_batch<R>(c, nr, D.m2l, M(l), Lc(l), tab(D.m2l, D.coax_m2l, D.coax_m2l32), ph, false);
     }
     bool a_done = false;
     for (int l = 3; l <= L; ++l) {

@@ -175,7 +175,7 @@ void trans_configure_lds(size_t lds_max);
 template <class R>
 const char *trans_stage(const TransBatch &b, const TransTables<R> &tb, int stage, int nr, const typename Cx<R>::T *src,
                         typename Cx<R>::T *dst, const typename Cx<R>::T *ph, int PH, typename Cx<R>::T *W1,
-                        typename Cx<R>::T *W2, hipStream_t st);
+                        typename Cx<R>::T *W2, hipStream_t st, bool accumulate = true);
 void build_rot_tables(const std::vector<double> &betas, int P, const double *D, double *H, double *HT,
                       DeviceBuffers &scratch, hipStream_t st);
 

@@ -819,6 +819,7 @@ template <> struct TmOp<float> {
     static __device__ inline int row(int kq, int i) { return 4 * kq + i; }
 };
 constexpr int TM_KC = 16;   // K rows per LDS chunk (double-buffered)
+constexpr int TMC_KC = 8;   // the same for the coaxial step: its 33 KB of LDS let four workgroups share a CU
 constexpr int TM_LD = 130;  // LDS row stride (doubles) of the staged A and B chunks
 // LDS of a rotation block: two A chunks and two B chunks (the back rotation reuses it for 64
 // output rows of 128 columns)
@@ -998,14 +999,14 @@ __global__ void __launch_bounds__(256) k_tm_coax(TransArgsT<R> a, int npass) {
     using Op = TmOp<R>;
     using v4 = typename Op::v4;
     constexpr int RBG = 4, RG = 16 * RBG, LA = RG + 2;
-    constexpr int NCOL = 2 * TMJ, NCB = TMJ / 32, NX = TM_KC * TMJ / 256;
+    constexpr int NCOL = 2 * TMJ, NCB = TMJ / 32, NX = TMC_KC * TMJ / 256;
     static_assert(TMJ == 64 || TMJ == 32, "tiles of 64 or 32 jobs");
     // A: real part (chunks 0, 1) and imaginary part (2, 3), RG + 2 columns; B: X (2 chunks)
-    __shared__ R ldsA[4 * TM_KC * LA];
-    __shared__ R ldsB[2 * TM_KC * TM_LD];
-    auto Ar = [&](int buf, int k, int r) -> R & { return ldsA[(buf * TM_KC + k) * LA + r]; };
-    auto Ai = [&](int buf, int k, int r) -> R & { return ldsA[((2 + buf) * TM_KC + k) * LA + r]; };
-    auto Bs = [&](int buf, int k, int c) -> R & { return ldsB[(buf * TM_KC + k) * TM_LD + c]; };
+    __shared__ R ldsA[4 * TMC_KC * LA];
+    __shared__ R ldsB[2 * TMC_KC * TM_LD];
+    auto Ar = [&](int buf, int k, int r) -> R & { return ldsA[(buf * TMC_KC + k) * LA + r]; };
+    auto Ai = [&](int buf, int k, int r) -> R & { return ldsA[((2 + buf) * TMC_KC + k) * LA + r]; };
+    auto Bs = [&](int buf, int k, int c) -> R & { return ldsB[(buf * TMC_KC + k) * TM_LD + c]; };
     int tile, mq;
     xcd_block(tile, mq);
     const int mi = mq / npass, pass = mq - mi * npass;  // order index, and the pass's share of its row groups
@@ -1027,14 +1028,14 @@ __global__ void __launch_bounds__(256) k_tm_coax(TransArgsT<R> a, int npass) {
     const C *Tm = a.coax + (int64_t)a.tile_coax[tile / a.nr] * coax_table_size(a.PT) + coax_block_off(a.PT, am);
     const int colw = (NCOL / 4) * wv + (lane & 15), kq = lane >> 4;
     const R swp = (colw & 1) ? R(1) : R(-1);
-    const int nch = (cin + TM_KC - 1) / TM_KC;
+    const int nch = (cin + TMC_KC - 1) / TMC_KC;
     for (int rb0 = pass * RBG; rb0 < RB; rb0 += npass * RBG) {
         const int r0 = rb0 * 16;
-        C ta[TM_KC * RG / 256];
+        C ta[TMC_KC * RG / 256];
         C xb[NX];  // (re, im) of NX (k, job) inputs
         auto gload = [&](int kc) {
 #pragma unroll
-            for (int i = 0; i < TM_KC * RG / 256; ++i) {
+            for (int i = 0; i < TMC_KC * RG / 256; ++i) {
                 const int e = tid + 256 * i, kk = e / RG, rr = e % RG, k = kc + kk, r = r0 + rr;
                 C t = (k < cin && r < rows) ? Tm[(int64_t)k * B + r] : mkc<C>(0, 0);
                 if ((k + r) & 1) t = mkc<C>(-t.x, -t.y);
@@ -1048,7 +1049,7 @@ __global__ void __launch_bounds__(256) k_tm_coax(TransArgsT<R> a, int npass) {
         };
         auto lstore = [&](int buf) {
 #pragma unroll
-            for (int i = 0; i < TM_KC * RG / 256; ++i) {
+            for (int i = 0; i < TMC_KC * RG / 256; ++i) {
                 const int e = tid + 256 * i;
                 Ar(buf, e / RG, e % RG) = ta[i].x;
                 Ai(buf, e / RG, e % RG) = ta[i].y;
@@ -1071,8 +1072,8 @@ __global__ void __launch_bounds__(256) k_tm_coax(TransArgsT<R> a, int npass) {
         __syncthreads();
         for (int c = 0; c < nch; ++c) {
             const int buf = c & 1;
-            if (c + 1 < nch) gload((c + 1) * TM_KC);
-            const int kn = min(TM_KC, cin - c * TM_KC);
+            if (c + 1 < nch) gload((c + 1) * TMC_KC);
+            const int kn = min(TMC_KC, cin - c * TMC_KC);
             for (int ks = 0; ks < kn; ks += 4) {
                 R bv[NCB], wv2[NCB];
 #pragma unroll
@@ -1756,36 +1757,39 @@ __global__ void __launch_bounds__(256) k_fr_coax(int64_t ntot, int P, int PT, co
     out[e] = v;
 }
 
-// dst[t] += sum of the job rows of target t (W1, P^2 per job); jobs of t listed in CSR order.
+// dst[t] (+)= sum of the job rows of target t (W1, P^2 per job); jobs of t listed in CSR order.
 // With nr vectors, virtual target t is real target t / nr, vector t % nr, and the job rows of
 // that vector are (job * nr + t % nr).  Workgroup (t, y) takes coefficients 256 y .. 256 y + 255
 // of target t, so that the large expansions of the upper levels spread over many workgroups.
+// Without acc the sums overwrite dst, targets without jobs included (the batch writes every
+// target: no clearing of dst beforehand).  Eight row loads in flight per thread.
 template <class C>
 __global__ void __launch_bounds__(256) k_tr_reduce(int64_t ntgt, int nr, int ptgt, int P, const int32_t *start,
-                                                   const int32_t *jobs, const C *W, C *dst) {
+                                                   const int32_t *jobs, const C *W, C *dst, int acc) {
     const int64_t t = blockIdx.x;
     if (t >= ntgt * nr) return;
     const int64_t tr = t / nr;
     const int r = (int)(t - tr * nr);
     const int j0 = start[tr], j1 = start[tr + 1];
-    if (j0 == j1) return;
+    if (j0 == j1 && acc) return;
     const int pt2 = ptgt * ptgt;
     const int64_t P2 = (int64_t)P * P;
     const int c = blockIdx.y * 256 + threadIdx.x;
     if (c >= pt2) return;
-    // four independent partial sums keep four row loads in flight
-    C s0 = dst[t * pt2 + c], s1 = mkc<C>(0, 0), s2 = mkc<C>(0, 0), s3 = mkc<C>(0, 0);
+    C s[8];
+    s[0] = acc ? dst[t * pt2 + c] : mkc<C>(0, 0);
+#pragma unroll
+    for (int u = 1; u < 8; ++u) s[u] = mkc<C>(0, 0);
     int q = j0;
-    for (; q + 4 <= j1; q += 4) {
-        const C a0 = W[((int64_t)jobs[q] * nr + r) * P2 + c], a1 = W[((int64_t)jobs[q + 1] * nr + r) * P2 + c];
-        const C a2 = W[((int64_t)jobs[q + 2] * nr + r) * P2 + c], a3 = W[((int64_t)jobs[q + 3] * nr + r) * P2 + c];
-        s0 = addc(s0, a0);
-        s1 = addc(s1, a1);
-        s2 = addc(s2, a2);
-        s3 = addc(s3, a3);
+    for (; q + 8 <= j1; q += 8) {
+        C a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = W[((int64_t)jobs[q + u] * nr + r) * P2 + c];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s[u] = addc(s[u], a[u]);
     }
-    for (; q < j1; ++q) s0 = addc(s0, W[((int64_t)jobs[q] * nr + r) * P2 + c]);
-    dst[t * pt2 + c] = addc(addc(s0, s1), addc(s2, s3));
+    for (; q < j1; ++q) s[0] = addc(s[0], W[((int64_t)jobs[q] * nr + r) * P2 + c]);
+    dst[t * pt2 + c] = addc(addc(addc(s[0], s[1]), addc(s[2], s[3])), addc(addc(s[4], s[5]), addc(s[6], s[7])));
 }
 
 // ------------------------------------------------------------------ host side
@@ -1832,7 +1836,7 @@ void trans_configure_lds(size_t lds_max) {
 template <class R>
 const char *trans_stage(const TransBatch &b, const TransTables<R> &tb, int stage, int nr, const typename Cx<R>::T *src,
                         typename Cx<R>::T *dst, const typename Cx<R>::T *ph, int PH, typename Cx<R>::T *W1,
-                        typename Cx<R>::T *W2, hipStream_t st) {
+                        typename Cx<R>::T *W2, hipStream_t st, bool accumulate) {
     if (nr < 1 || b.JT % nr) throw FmmError(-1, "right-hand-side count must divide the tile size");
     TransArgsT<R> a{b.njob * nr, b.JT, b.psrc, b.ptgt, b.P, b.PT, PH, nr, src, dst, b.src, b.tgt, b.dir,
                     b.tile_coax, b.tile_rot, tb.coax, tb.H, tb.HT, ph, W1, W2, b.seg, tb.frH, tb.frHT, tb.frC};
@@ -1940,7 +1944,7 @@ const char *trans_stage(const TransBatch &b, const TransTables<R> &tb, int stage
         break;
     default:
         k_tr_reduce<typename Cx<R>::T><<<dim3((unsigned)(b.ntgt * nr), (unsigned)ceil_div(b.ptgt * b.ptgt, 256)), 256, 0,
-                                         st>>>(b.ntgt, nr, b.ptgt, b.P, b.tgt_start, b.tgt_jobs, W1, dst);
+                                         st>>>(b.ntgt, nr, b.ptgt, b.P, b.tgt_start, b.tgt_jobs, W1, dst, accumulate ? 1 : 0);
         name = f32 ? "k_tr_reduce_f32" : "k_tr_reduce";
     }
     LAUNCH_OK();
@@ -1948,8 +1952,8 @@ const char *trans_stage(const TransBatch &b, const TransTables<R> &tb, int stage
 }
 
 template const char *trans_stage<double>(const TransBatch &, const TransTables<double> &, int, int, const double2 *,
-                                         double2 *, const double2 *, int, double2 *, double2 *, hipStream_t);
+                                         double2 *, const double2 *, int, double2 *, double2 *, hipStream_t, bool);
 template const char *trans_stage<float>(const TransBatch &, const TransTables<float> &, int, int, const float2 *, float2 *,
-                                        const float2 *, int, float2 *, float2 *, hipStream_t);
+                                        const float2 *, int, float2 *, float2 *, hipStream_t, bool);
 
 }  // namespace fmm
