@@ -389,21 +389,31 @@ static void make_batch(fmmbem_ctx *c, const std::string &name, std::vector<JobH>
         return x.tgt < y.tgt;
     });
     // Tile shape: one job per lane (64-job tiles) when the classes are large enough that padding
-    // them to 64 wastes at most a quarter of the work; otherwise whole-vector tiles while at
-    // least 8 jobs fit the LDS budget, per-degree slices beyond.
-    int64_t pad64 = 0;
+    // them to 64 wastes at most a quarter of the work, or, for matrix-core tiles (p >= 24, several
+    // times faster than the LDS tiles there), at most half of it (32-job tiles where the 64-job
+    // padding would exceed a third); otherwise whole-vector tiles while at least 8 jobs fit the
+    // LDS budget, per-degree slices beyond.
+    int64_t pad64 = 0, pad32 = 0;
     for (size_t q = 0; q < jobs.size();) {
         size_t e = q;
         while (e < jobs.size() && jobs[e].tab == jobs[q].tab && jobs[e].rot == jobs[q].rot) ++e;
         pad64 += (int64_t)((e - q + 63) / 64) * 64;
+        pad32 += (int64_t)((e - q + 31) / 32) * 32;
         q = e;
     }
-    b.lane = !jobs.empty() && (c->opt.lane_tiles == 2 || (c->opt.lane_tiles == 1 && pad64 * 4 <= (int64_t)jobs.size() * 5));
+    const int64_t nj = (int64_t)jobs.size();
+    const bool mf = c->opt.mfma == 2 || (c->opt.mfma == 1 && b.P >= 24);
+    b.lane = !jobs.empty() && (c->opt.lane_tiles == 2 ||
+                               (c->opt.lane_tiles == 1 && (pad64 * 4 <= nj * 5 || (mf && pad32 <= 2 * nj))));
     if (b.lane) {
         b.whole = 0;
         b.JT = 64;
-        b.mfma = c->opt.mfma == 2 || (c->opt.mfma == 1 && b.P >= 24);
-        if (c->opt.fused && fused_ok(b)) b.mfma = rcr_ok(b) ? 4 : 2;
+        b.mfma = mf;
+        if (mf && pad64 * 2 > nj * 3) b.JT = 32;
+        if (c->opt.fused && fused_ok(b)) {
+            b.JT = 64;
+            b.mfma = rcr_ok(b) ? 4 : 2;
+        }
     } else {
         b.whole = trans_pick_jt(b.P, budget, 1) >= 8 && (size_t)8 * 16 * b.P * b.P <= budget;
         b.JT = trans_pick_jt(b.P, budget, b.whole);

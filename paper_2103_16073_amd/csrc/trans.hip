@@ -818,12 +818,9 @@ template <> struct TmOp<float> {
     static __device__ inline v4 mma(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
     static __device__ inline int row(int kq, int i) { return 4 * kq + i; }
 };
-constexpr int TM_KC = 16;   // K rows per LDS chunk (double-buffered)
+constexpr int TM_KC = 8;    // K rows per LDS chunk (double-buffered) of the rotations
 constexpr int TMC_KC = 8;   // the same for the coaxial step: its 33 KB of LDS let four workgroups share a CU
 constexpr int TM_LD = 130;  // LDS row stride (doubles) of the staged A and B chunks
-// LDS of a rotation block: two A chunks and two B chunks (the back rotation reuses it for 64
-// output rows of 128 columns)
-constexpr int TM_LDS = 4 * TM_KC * TM_LD;
 
 // Rotation of degree n for one tile of TMJ jobs (64 or 32: 2 TMJ columns, the four wavefronts owning
 // TMJ / 2 columns each, in NCB = TMJ / 32 blocks of 16), as a GEMM over K chunks staged in LDS
@@ -841,14 +838,19 @@ __global__ void __launch_bounds__(256) k_tm_rot(TransArgsT<R> a, int npass) {
     constexpr int RG = 16 * RBG;            // rows per pass
     constexpr int NCOL = 2 * TMJ;           // real columns of a tile
     constexpr int NCB = TMJ / 32;           // 16-column blocks per wavefront
-    static_assert(RG <= 128 && (FWD || RG * TM_LD <= TM_LDS), "pass too large for the LDS block");
+    // K chunks of 8 and passes of 64 (forward) or 32 (back) rows: 33 KB of LDS, four workgroups per
+    // CU (measured at levels 2-5 of the 1M L-room against chunks of 16 and passes of 128 / 64 rows:
+    // back rotation 1.51 -> 1.15 ms, forward rotation 1.90 -> 1.66 ms per product)
+    constexpr int KC = TM_KC;
+    constexpr int LDSN = FWD ? 4 * KC * TM_LD : (4 * KC > RG ? 4 * KC : RG) * TM_LD;
+    static_assert(RG <= 128 && (FWD || RG * TM_LD <= LDSN), "pass too large for the LDS block");
     static_assert(TMJ == 64 || TMJ == 32, "tiles of 64 or 32 jobs");
-    __shared__ R lds[TM_LDS];
+    __shared__ R lds[LDSN];
     __shared__ int64_t soff[TMJ];
     __shared__ int32_t sdir[TMJ];
     __shared__ int segl[TMJ];
-    auto As = [&](int buf, int k, int r) -> R & { return lds[(buf * TM_KC + k) * TM_LD + r]; };
-    auto Bs = [&](int buf, int k, int c) -> R & { return lds[((2 + buf) * TM_KC + k) * TM_LD + c]; };
+    auto As = [&](int buf, int k, int r) -> R & { return lds[(buf * KC + k) * TM_LD + r]; };
+    auto Bs = [&](int buf, int k, int c) -> R & { return lds[((2 + buf) * KC + k) * TM_LD + c]; };
     int tile, nq;
     xcd_block(tile, nq);
     const int n = nq / npass, pass = nq - n * npass;  // degree, and the pass's share of its row groups
@@ -867,9 +869,9 @@ __global__ void __launch_bounds__(256) k_tm_rot(TransArgsT<R> a, int npass) {
     const R *Mn = (FWD ? a.HT : a.H) + (int64_t)tr * rot_table_size(a.P) + rot_block_off(n);
     const R *Xin = (const R *)a.W2;
     const int colw = (NCOL / 4) * wv + (lane & 15), kq = lane >> 4;
-    const int nch = (w + TM_KC - 1) / TM_KC;
-    constexpr int NA = TM_KC * RG / 256;   // A values staged per thread
-    constexpr int NB = TM_KC * NCOL / 256;  // B values staged per thread
+    const int nch = (w + KC - 1) / KC;
+    constexpr int NA = KC * RG / 256;   // A values staged per thread
+    constexpr int NB = KC * NCOL / 256;  // B values staged per thread
     for (int rb0 = pass * RBG; rb0 < RB; rb0 += npass * RBG) {
         const int r0 = rb0 * 16;
         R ra[NA], rbv[NB];
@@ -928,8 +930,8 @@ __global__ void __launch_bounds__(256) k_tm_rot(TransArgsT<R> a, int npass) {
         __syncthreads();
         for (int c = 0; c < nch; ++c) {
             const int buf = c & 1;
-            if (c + 1 < nch) gload((c + 1) * TM_KC);
-            const int kn = min(TM_KC, w - c * TM_KC);
+            if (c + 1 < nch) gload((c + 1) * KC);
+            const int kn = min(KC, w - c * KC);
             for (int ks = 0; ks < kn; ks += 4) {
                 R bv[NCB];
 #pragma unroll
@@ -1890,9 +1892,9 @@ const char *trans_stage(const TransBatch &b, const TransTables<R> &tb, int stage
         int np;
         switch (stage) {
         case 0:
-            np = passes(2 * b.psrc - 1, 8, b.psrc);
-            if (b.JT == LANE_JT) k_tm_rot<R, true, 8, 64><<<dim3(ntile, b.psrc * np), 256, 0, st>>>(a, np);
-            else k_tm_rot<R, true, 8, 32><<<dim3(ntile, b.psrc * np), 256, 0, st>>>(a, np);
+            np = passes(2 * b.psrc - 1, 4, b.psrc);
+            if (b.JT == LANE_JT) k_tm_rot<R, true, 4, 64><<<dim3(ntile, b.psrc * np), 256, 0, st>>>(a, np);
+            else k_tm_rot<R, true, 4, 32><<<dim3(ntile, b.psrc * np), 256, 0, st>>>(a, np);
             name = f32 ? "k_tm_rot_fwd_f32" : "k_tm_rot_fwd";
             break;
         case 1:
@@ -1902,9 +1904,9 @@ const char *trans_stage(const TransBatch &b, const TransTables<R> &tb, int stage
             name = f32 ? "k_tm_coax_f32" : "k_tm_coax";
             break;
         default:
-            np = passes(2 * b.ptgt - 1, 4, b.ptgt);
-            if (b.JT == LANE_JT) k_tm_rot<R, false, 4, 64><<<dim3(ntile, b.ptgt * np), 256, 0, st>>>(a, np);
-            else k_tm_rot<R, false, 4, 32><<<dim3(ntile, b.ptgt * np), 256, 0, st>>>(a, np);
+            np = passes(2 * b.ptgt - 1, 2, b.ptgt);
+            if (b.JT == LANE_JT) k_tm_rot<R, false, 2, 64><<<dim3(ntile, b.ptgt * np), 256, 0, st>>>(a, np);
+            else k_tm_rot<R, false, 2, 32><<<dim3(ntile, b.ptgt * np), 256, 0, st>>>(a, np);
             name = f32 ? "k_tm_rot_back_f32" : "k_tm_rot_back";
         }
         LAUNCH_OK();

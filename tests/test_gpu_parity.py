@@ -576,6 +576,8 @@ def test_matrix_core_tiles_of_32_jobs_vs_64(F):
     shapes = ctx32.fmmbem_batch_shapes()
     tm = [d for d in shapes if d["lane"] and d["mfma"] == 1]
     assert len(tm) >= 6
+    ctx64.fmmbem_set_batch_shapes([dict(d, jt=64) for d in tm])
+    assert sum(d["jt"] == 64 for d in ctx64.fmmbem_batch_shapes() if d["lane"] and d["mfma"] == 1) == len(tm)
     ctx32.fmmbem_set_batch_shapes([dict(d, jt=32) for d in tm])
     got = ctx32.fmmbem_batch_shapes()
     assert sum(d["jt"] == 32 for d in got) == len(tm)
