@@ -338,6 +338,9 @@ def main():
     ap.add_argument("--no-coarse-inner", action="store_true",
                     help="skip the solve preconditioned by an inner GMRES on a coarser FMM")
     ap.add_argument("--no-batched-solve", action="store_true", help="skip the 4-source batched solve")
+    ap.add_argument("--outer", type=int, default=0,
+                    help="Krylov dimension (= iteration cap) of the inner-outer solve (0: 200, 400 for workload 5)")
+    ap.add_argument("--inner-steps", type=int, default=10, help="GMRES steps of the inner solve on the coarse FMM")
     ap.add_argument("--batch-restart", type=int, default=850, help="Krylov dimension of the batched solve")
     ap.add_argument("--no-autotune", action="store_true", help="fixed tile-shape rule instead of measured shapes")
     ap.add_argument("--copy-calib", action="store_true",
@@ -602,15 +605,16 @@ def main():
             # preconditioner is 10 GMRES steps (tolerance 0.1) on a second FMM with p_min 4 and
             # excess 0 (p = ceil(k d) per level), itself preconditioned by the leaf blocks
             ctx.fmmbem_release_workspace()
-            outer = 400 if big else 200
+            outer = args.outer if args.outer > 0 else (400 if big else 200)
+            ni = args.inner_steps
             xs, rep, rc = ctx.fmmbem_solve(0, tol=1e-4, restart=outer, maxit=outer, precond=F.FMMBEM_PC_NEARBLOCK,
-                                           precision=F.FMMBEM_MIXED, inner_iters=10, inner_tol=0.1,
+                                           precision=F.FMMBEM_MIXED, inner_iters=ni, inner_tol=0.1,
                                            inner_p_min=4, inner_p_excess=0.0)
             fg["mixed_coarse_inner"] = {"status": rc, "iters": rep.iters, "inner_iters": rep.inner_iters,
                                         "rel_res_fp64": rep.rel_res, "t_solve_s": rep.t_solve_s,
                                         "t_setup_coarse_s": rep.t_setup_s, "matvecs_fp64": rep.matvecs_fp64,
                                         "matvecs_mixed": rep.matvecs_mixed, "matvecs_coarse": rep.matvecs_coarse,
-                                        "inner": {"iters": 10, "tol": 0.1, "p_min": 4, "p_excess": 0.0},
+                                        "inner": {"iters": ni, "tol": 0.1, "p_min": 4, "p_excess": 0.0},
                                         "restart": outer}
             log(f"FGMRES mixed + coarse inner GMRES: status {rc} outer {rep.iters} inner {rep.inner_iters} "
                 f"rel_res {rep.rel_res:.3e} t {rep.t_solve_s:.2f}s (coarse setup {rep.t_setup_s:.2f}s)")
