@@ -340,7 +340,8 @@ def main():
     ap.add_argument("--no-batched-solve", action="store_true", help="skip the 4-source batched solve")
     ap.add_argument("--outer", type=int, default=0,
                     help="Krylov dimension (= iteration cap) of the inner-outer solve (0: 200, 400 for workload 5)")
-    ap.add_argument("--inner-steps", type=int, default=10, help="GMRES steps of the inner solve on the coarse FMM")
+    ap.add_argument("--inner-steps", type=int, default=0,
+                    help="GMRES steps of the inner solve on the coarse FMM (0: 10, 20 for workload 5)")
     ap.add_argument("--batch-restart", type=int, default=850, help="Krylov dimension of the batched solve")
     ap.add_argument("--no-autotune", action="store_true", help="fixed tile-shape rule instead of measured shapes")
     ap.add_argument("--copy-calib", action="store_true",
@@ -606,7 +607,7 @@ def main():
             # excess 0 (p = ceil(k d) per level), itself preconditioned by the leaf blocks
             ctx.fmmbem_release_workspace()
             outer = args.outer if args.outer > 0 else (400 if big else 200)
-            ni = args.inner_steps
+            ni = args.inner_steps if args.inner_steps > 0 else (20 if big else 10)
             xs, rep, rc = ctx.fmmbem_solve(0, tol=1e-4, restart=outer, maxit=outer, precond=F.FMMBEM_PC_NEARBLOCK,
                                            precision=F.FMMBEM_MIXED, inner_iters=ni, inner_tol=0.1,
                                            inner_p_min=4, inner_p_excess=0.0)

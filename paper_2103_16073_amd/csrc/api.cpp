@@ -987,7 +987,7 @@ constexpr int EV_CALLER_IN = 39, EV_CALLER_DONE = 40;
 //   join                    A waits for B's last L2L
 // Every level's local expansions receive M2L and then L2L in the same order as on one stream.
 template <class R>
-static void far_field(fmmbem_ctx *c, int nr, bool mixed) {
+static void far_field(fmmbem_ctx *c, int nr, bool mixed, const std::function<void()> &after_m2l = nullptr) {
     using C = typename Cx<R>::T;
     const int L = c->tree.depth;
     hipStream_t A = c->stream, B = c->opt.streams >= 2 ? c->side : c->stream;
@@ -1014,6 +1014,8 @@ static void far_field(fmmbem_ctx *c, int nr, bool mixed) {
         run_batch<R>(c, nr, D.m2l, M(l), Lc(l), tab(D.m2l, D.coax_m2l, D.coax_m2l32), ph, false);
     }
     ev_record(c, EV_M2L, A);
+    // A: whatever the caller runs beside the L2L chain (the near field of a product)
+    if (after_m2l) after_m2l();
     // B: M2L of the upper levels, then the L2L chain top-down
     c->cur = B;
     for (int l = lsplit - 1; l >= 2; --l) {
@@ -1051,15 +1053,8 @@ static void fmm_pass(fmmbem_ctx *c, int nr, const double2 *sigma, const double2 
         fmmbem_ctx *c;
         ~CurGuard() { c->cur = c->stream; }
     } guard{c};
-    // fork: the near field runs on the side stream beside P2M and the translations
-    rec(c, 1);
-    if (!exact_far) {
-        ev_record(c, 0, A);
-        ev_wait(c, 0, B);
-        c->cur = B;
-    }
-    int pe = prof_begin(c);
-    {
+    auto near_field = [&]() {
+        int pe = prof_begin(c);
         const double pairs = exact_far ? (double)n * n : (double)c->p2p_pairs;
         launch_p2p(nr, mixed, nleaf, I32("leaf_start"), I32("nbr_start"), I32("nbr_list"), exact_far ? 1 : 0, ec, en,
                    sigma, mu, c->k, c->rc * c->rc, I32("near_start"), I32("near_col"),
@@ -1070,9 +1065,15 @@ static void fmm_pass(fmmbem_ctx *c, int nr, const double2 *sigma, const double2 
         const double tb = mixed ? 16.0 : 32.0;
         prof_end(c, pe, mixed ? "k_p2p32" : "k_p2p", (40.0 + 16.0 * (nr - 1)) * pairs + 16.0 * nr * c->near_nnz,
                  80.0 * n + 48.0 * n * nr + (8.0 + tb) * c->near_nnz);
-    }
+    };
+    // The near field of a product runs on the main stream after the M2L of the deep levels, beside
+    // the side stream's L2L chain (few workgroups per level), and L2P follows both; P2M and the M2M
+    // chain at the start have the device to themselves.
+    rec(c, 1);
+    if (exact_far) near_field();
     rec(c, 2);
     c->cur = A;
+    int pe = 0;
     if (!exact_far) {
         LevelDev &LL = c->lev[L];
         const int p = LL.p;
@@ -1088,8 +1089,8 @@ static void fmm_pass(fmmbem_ctx *c, int nr, const double2 *sigma, const double2 
             prof_end(c, pe, "k_cvt", 0.0, 24.0 * LL.nbox * pp * nr);
         }
         rec(c, 3);
-        if (mixed) far_field<float>(c, nr, true);
-        else far_field<double>(c, nr, false);
+        if (mixed) far_field<float>(c, nr, true, near_field);
+        else far_field<double>(c, nr, false, near_field);
         if (mixed) {
             pe = prof_begin(c);
             convert(c, (int64_t)LL.nbox * nr * pp, (const float2 *)LL.L32, LL.L);

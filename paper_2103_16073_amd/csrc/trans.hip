@@ -831,7 +831,7 @@ constexpr int TM_LD = 130;  // LDS row stride (doubles) of the staged A and B ch
 //   !FWD: Y = H^T X, X = W2 rows, A[r][k] = H[k][r]; the pass's outputs go through LDS, are
 //         phased (e^{-i m a}), summed over the runs of one target and stored job-major in W1.
 template <class R, bool FWD, int RBG, int TMJ>
-__global__ void __launch_bounds__(256) k_tm_rot(TransArgsT<R> a, int npass) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) k_tm_rot(TransArgsT<R> a, int npass) {
     using C = typename Cx<R>::T;
     using Op = TmOp<R>;
     using v4 = typename Op::v4;
@@ -874,7 +874,11 @@ __global__ void __launch_bounds__(256) k_tm_rot(TransArgsT<R> a, int npass) {
     constexpr int NB = KC * NCOL / 256;  // B values staged per thread
     for (int rb0 = pass * RBG; rb0 < RB; rb0 += npass * RBG) {
         const int r0 = rb0 * 16;
-        R ra[NA], rbv[NB];
+        // the forward rotation keeps the loaded phases and source coefficients until the LDS store,
+        // so that the next chunk's loads stay in flight through the matrix-core work (1.66 -> 1.35 ms
+        // per product at levels 2-5 of the 1M L-room, against multiplying them as they arrive)
+        R ra[NA], rbv[FWD ? 1 : NB];
+        C rph[FWD ? NB / 2 : 1], rsr[FWD ? NB / 2 : 1];
         auto gload = [&](int kc) {
 #pragma unroll
             for (int i = 0; i < NA; ++i) {
@@ -885,10 +889,8 @@ __global__ void __launch_bounds__(256) k_tm_rot(TransArgsT<R> a, int npass) {
 #pragma unroll
                 for (int i = 0; i < NB / 2; ++i) {
                     const int e = tid + 256 * i, kk = e / TMJ, j = e % TMJ, k = kc + kk;
-                    C x = mkc<C>(0, 0);
-                    if (k < w) x = mulc(a.ph[sdir[j] + k - n], a.src[soff[j] + n * n + k]);  // e^{i m a} c_n^m
-                    rbv[2 * i] = x.x;
-                    rbv[2 * i + 1] = x.y;
+                    rph[i] = k < w ? a.ph[sdir[j] + k - n] : mkc<C>(0, 0);
+                    rsr[i] = k < w ? a.src[soff[j] + n * n + k] : mkc<C>(0, 0);
                 }
             } else {
 #pragma unroll
@@ -908,8 +910,9 @@ __global__ void __launch_bounds__(256) k_tm_rot(TransArgsT<R> a, int npass) {
 #pragma unroll
                 for (int i = 0; i < NB / 2; ++i) {
                     const int e = tid + 256 * i, kk = e / TMJ, j = e % TMJ;
-                    Bs(buf, kk, 2 * j) = rbv[2 * i];
-                    Bs(buf, kk, 2 * j + 1) = rbv[2 * i + 1];
+                    const C x = mulc(rph[i], rsr[i]);  // e^{i m a} c_n^m
+                    Bs(buf, kk, 2 * j) = x.x;
+                    Bs(buf, kk, 2 * j + 1) = x.y;
                 }
             } else {
 #pragma unroll
