@@ -68,7 +68,8 @@ enum {
     FMMBEM_DIRECT_BM = 2, /* combined (Burton-Miller) direct equation: Eq. dbem3 plus alpha = i/k
                              times its normal derivative (Section 3.2 jump relations), the same
                              unknown and field as Eq. dbem4; adds the near entries of L' and M';
-                             preconditioners FMMBEM_PC_NONE or FMMBEM_PC_DIAG; one vector per pass */
+                             preconditioners FMMBEM_PC_NONE, FMMBEM_PC_DIAG or FMMBEM_PC_NEARBLOCK;
+                             one vector per pass */
     FMMBEM_INDIRECT = 3 /* Eq. ibem5: every element two-sided, unknowns (psi-, psi+) = the field on
                            the side the normal leaves (the room) and on the side it points to
                            (2N unknowns, psi- block first); FP64 and MIXED products (MIXED: FP32
@@ -174,8 +175,8 @@ int fmmbem_set_sources(fmmbem_ctx *ctx, int32_t ns, const double *rs, const fmmb
 
 /* FMMBEM_DIRECT, FMMBEM_DIRECT_DPSI, FMMBEM_DIRECT_BM or FMMBEM_INDIRECT.  The indirect formulation adds the near entries of L'
  * and the hypersingular M' (Eq. ibem3; built on first use) and evaluates the normal derivative
- * of the far field at every element; preconditioners: FMMBEM_PC_NONE or FMMBEM_PC_DIAG
- * (2x2 element blocks). */
+ * of the far field at every element; preconditioners: FMMBEM_PC_NONE, FMMBEM_PC_DIAG (2x2
+ * element blocks) or FMMBEM_PC_NEARBLOCK (the operator on each leaf's 2 n_b unknowns, inverted). */
 int fmmbem_set_formulation(fmmbem_ctx *ctx, int formulation);
 
 /* Build what is out of date: octree and interaction lists (mesh), translation and rotation

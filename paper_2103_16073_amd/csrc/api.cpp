@@ -82,9 +82,15 @@ __global__ void k_mul_diag(int64_t, const double2 *, const double2 *, double2 *)
 __global__ void k_leaf_blocks(int, const int32_t *, const int64_t *, const double4 *, const double4 *,
                               const double2 *, double, double, const int32_t *, const int32_t *, const double2 *,
                               const double2 *, double2 *);
-__global__ void k_leaf_invert(int, const int32_t *, const int64_t *, double2 *, int32_t *, int *);
+__global__ void k_leaf_blocks_ind(int, const int32_t *, const int64_t *, const double4 *, const double4 *,
+                                  const double2 *, const double2 *, double, double, const int32_t *, const int32_t *,
+                                  const double2 *, const double2 *, const double2 *, const double2 *, double2 *);
+__global__ void k_leaf_blocks_bm(int, const int32_t *, const int64_t *, const double4 *, const double4 *,
+                                 const double2 *, double, double2, double, const int32_t *, const int32_t *,
+                                 const double2 *, const double2 *, const double2 *, const double2 *, double2 *);
+__global__ void k_leaf_invert(int, const int32_t *, const int64_t *, double2 *, int32_t *, int *, int);
 __global__ void k_leaf_apply(int, const int32_t *, const int64_t *, const double2 *, const int32_t *,
-                             const double2 *, double2 *);
+                             const double2 *, double2 *, int, int64_t);
 void box_center(const TreeHost &T, int l, uint64_t code, double *c);
 int fgmres_batch(int64_t n, hipStream_t st, DeviceBuffers &scr, int nv,
                  const std::function<void(int, const double2 *, double2 *)> &matvec,
@@ -1740,6 +1746,8 @@ int fmmbem_set_formulation(fmmbem_ctx *ctx, int f) {
     if (f != ctx->formulation) {
         drop_graphs(ctx);
         ++ctx->input_gen;
+        // the leaf blocks and diagonals are the operator's: another formulation rebuilds them
+        ctx->precond_ready_nb = ctx->precond_ready_diag = false;
     }
     ctx->formulation = f;
     return FMMBEM_OK;
@@ -1959,6 +1967,44 @@ static void mlp_run(fmmbem_ctx *c, const double2 *v, float **out, float **scale)
     *scale = sc;
 }
 
+// Leaf blocks of m n_b unknowns each (m = 1: one unknown per element; 2: the indirect pair): `fill`
+// writes the operator's blocks at the offsets, then every block is inverted in place and the
+// preconditioner applies blockdiag(A_BB^{-1}).
+static std::function<void(const double2 *, double2 *)> leaf_block_pc(
+    fmmbem_ctx *ctx, int m, const std::function<void(const int64_t *, double2 *)> &fill) {
+    hipStream_t st = ctx->stream;
+    const int64_t n = ctx->nt;
+    const int nleaf = (int)ctx->tree.leaf_start.size() - 1;
+    if (!ctx->precond_ready_nb) {
+        std::vector<int64_t> off(nleaf + 1, 0);
+        for (int b = 0; b < nleaf; ++b) {
+            const int64_t nb = (int64_t)m * (ctx->tree.leaf_start[b + 1] - ctx->tree.leaf_start[b]);
+            if (nb > 1024) throw FmmError(FMMBEM_EINVAL, "leaf too full for the block preconditioner");
+            off[b + 1] = off[b] + nb * nb;
+        }
+        int64_t *doff = upload(ctx->buf, "pc_off", off, st);
+        double2 *A = dget<double2>(ctx->buf, "pc_blocks", off[nleaf]);
+        int32_t *piv = dget<int32_t>(ctx->scratch, "pc_piv", (size_t)m * n);
+        int *status = dget<int>(ctx->scratch, "pc_status", 1);
+        HIP_OK(hipMemsetAsync(status, 0, sizeof(int), st));
+        fill(doff, A);
+        k_leaf_invert<<<nleaf, 256, 0, st>>>(nleaf, (int32_t *)ctx->buf.find("leaf_start"), doff, A, piv, status, m);
+        LAUNCH_OK();
+        int hs = 0;
+        HIP_OK(hipMemcpyAsync(&hs, status, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+        if (hs) throw FmmError(FMMBEM_EBREAKDOWN, "singular leaf block in the near-field preconditioner");
+        ctx->precond_ready_nb = true;
+    }
+    const int32_t *ls = (int32_t *)ctx->buf.find("leaf_start"), *pm = (int32_t *)ctx->buf.find("perm");
+    const int64_t *doff = (int64_t *)ctx->buf.find("pc_off");
+    const double2 *A = (double2 *)ctx->buf.find("pc_blocks");
+    return [=](const double2 *v, double2 *z) {
+        k_leaf_apply<<<nleaf, 128, 0, st>>>(nleaf, ls, doff, A, pm, v, z, m, n);
+        LAUNCH_OK();
+    };
+}
+
 static std::function<void(const double2 *, double2 *)> make_precond(fmmbem_ctx *ctx, const fmmbem_solve_opts &o) {
     hipStream_t st = ctx->stream;
     const int64_t n = ctx->nt;
@@ -1970,8 +2016,22 @@ static std::function<void(const double2 *, double2 *)> make_precond(fmmbem_ctx *
             return [=](const double2 *v, double2 *z) {
                 HIP_OK(hipMemcpyAsync(z, v, sizeof(double2) * 2 * n, hipMemcpyDeviceToDevice, st));
             };
+        if (o.precond == FMMBEM_PC_NEARBLOCK) {
+            // near-field leaf blocks of the two-sided operator (2 n_b unknowns per leaf)
+            ensure_indirect(ctx);
+            return leaf_block_pc(ctx, 2, [&](const int64_t *doff, double2 *A) {
+                k_leaf_blocks_ind<<<nleaf, 256, 0, st>>>(
+                    nleaf, (int32_t *)ctx->buf.find("leaf_start"), doff, (double4 *)ctx->buf.find("ec"),
+                    (double4 *)ctx->buf.find("en"), (double2 *)ctx->buf.find("beta"), (double2 *)ctx->buf.find("betap"),
+                    ctx->k, ctx->rc * ctx->rc, (int32_t *)ctx->buf.find("near_start"), (int32_t *)ctx->buf.find("near_col"),
+                    (double2 *)ctx->buf.find("near_L"), (double2 *)ctx->buf.find("near_M"),
+                    (double2 *)ctx->buf.find("near_Lp"), (double2 *)ctx->buf.find("near_Mp"), A);
+                LAUNCH_OK();
+            });
+        }
         if (o.precond != FMMBEM_PC_DIAG)
-            throw FmmError(FMMBEM_EINVAL, "the indirect formulation takes FMMBEM_PC_NONE or FMMBEM_PC_DIAG");
+            throw FmmError(FMMBEM_EINVAL, "the indirect formulation takes FMMBEM_PC_NONE, FMMBEM_PC_DIAG or "
+                                          "FMMBEM_PC_NEARBLOCK");
         ensure_indirect(ctx);
         double2 *inv = dget<double2>(ctx->buf, "pc_dinv2", 4 * n);
         k_diag2_inv<<<ceil_div(n, 256), 256, 0, st>>>(n, (int32_t *)ctx->buf.find("near_start"),
@@ -1990,8 +2050,21 @@ static std::function<void(const double2 *, double2 *)> make_precond(fmmbem_ctx *
             return [=](const double2 *v, double2 *z) {
                 HIP_OK(hipMemcpyAsync(z, v, sizeof(double2) * n, hipMemcpyDeviceToDevice, st));
             };
+        if (o.precond == FMMBEM_PC_NEARBLOCK) {
+            ensure_indirect(ctx);
+            return leaf_block_pc(ctx, 1, [&](const int64_t *doff, double2 *A) {
+                k_leaf_blocks_bm<<<nleaf, 256, 0, st>>>(
+                    nleaf, (int32_t *)ctx->buf.find("leaf_start"), doff, (double4 *)ctx->buf.find("ec"),
+                    (double4 *)ctx->buf.find("en"), (double2 *)ctx->buf.find("beta"), ctx->k, bm_alpha(ctx),
+                    ctx->rc * ctx->rc, (int32_t *)ctx->buf.find("near_start"), (int32_t *)ctx->buf.find("near_col"),
+                    (double2 *)ctx->buf.find("near_L"), (double2 *)ctx->buf.find("near_M"),
+                    (double2 *)ctx->buf.find("near_Lp"), (double2 *)ctx->buf.find("near_Mp"), A);
+                LAUNCH_OK();
+            });
+        }
         if (o.precond != FMMBEM_PC_DIAG)
-            throw FmmError(FMMBEM_EINVAL, "the combined direct formulation takes FMMBEM_PC_NONE or FMMBEM_PC_DIAG");
+            throw FmmError(FMMBEM_EINVAL, "the combined direct formulation takes FMMBEM_PC_NONE, FMMBEM_PC_DIAG or "
+                                          "FMMBEM_PC_NEARBLOCK");
         ensure_indirect(ctx);
         double2 *dinv = dget<double2>(ctx->buf, "pc_dinv_bm", n);
         k_diag_bm_inv<<<ceil_div(n, 256), 256, 0, st>>>(
@@ -2050,7 +2123,7 @@ static std::function<void(const double2 *, double2 *)> make_precond(fmmbem_ctx *
                                              (int32_t *)ctx->buf.find("near_col"), (double2 *)ctx->buf.find("near_L"),
                                              (double2 *)ctx->buf.find("near_M"), A);
         LAUNCH_OK();
-        k_leaf_invert<<<nleaf, 256, 0, st>>>(nleaf, (int32_t *)ctx->buf.find("leaf_start"), doff, A, piv, status);
+        k_leaf_invert<<<nleaf, 256, 0, st>>>(nleaf, (int32_t *)ctx->buf.find("leaf_start"), doff, A, piv, status, 1);
         LAUNCH_OK();
         int hs = 0;
         HIP_OK(hipMemcpyAsync(&hs, status, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -2070,7 +2143,7 @@ static std::function<void(const double2 *, double2 *)> make_precond(fmmbem_ctx *
         const int64_t *doff = (int64_t *)ctx->buf.find("pc_off");
         const double2 *A = (double2 *)ctx->buf.find("pc_blocks");
         pc = [=](const double2 *v, double2 *z) {
-            k_leaf_apply<<<nleaf, 128, 0, st>>>(nleaf, ls, doff, A, pm, v, z);
+            k_leaf_apply<<<nleaf, 128, 0, st>>>(nleaf, ls, doff, A, pm, v, z, 1, n);
             LAUNCH_OK();
         };
     } else {

@@ -220,13 +220,146 @@ __global__ void __launch_bounds__(256) k_leaf_blocks(int nleaf, const int32_t *l
     }
 }
 
-// in-place Gauss-Jordan inversion with partial pivoting, one workgroup per leaf block
-__global__ void __launch_bounds__(256) k_leaf_invert(int nleaf, const int32_t *leaf_start, const int64_t *blk_off,
-                                                     double2 *A, int32_t *piv_ws, int *status) {
+// dense block of the indirect operator (Eq. ibem5) on each leaf's unknowns, row-major
+// 2 n_b x 2 n_b at blk_off[b]: rows (psi- equation of the leaf's elements, then psi+ equation),
+// columns (psi- of the leaf's elements, then psi+), elements in sorted order.  With
+// sigma_j = -i k (beta-_j psi-_j + beta+_j psi+_j) and mu_j = psi-_j - psi+_j, the equations are
+//   V_i + (psi-_i + psi+_i) / 2                            (V = sum_j L_ij sigma_j + M_ij mu_j)
+//   W_i + i k (beta-_i psi-_i - beta+_i psi+_i) / 2        (W = sum_j L'_ij sigma_j + M'_ij mu_j)
+// the pair entries L, M, L', M' from the near tables where |c_i - c_j| < r_c, from the one-point
+// rule of the near field elsewhere.
+__global__ void __launch_bounds__(256) k_leaf_blocks_ind(int nleaf, const int32_t *leaf_start, const int64_t *blk_off,
+                                                         const double4 *ec, const double4 *en, const double2 *bm,
+                                                         const double2 *bp, double k, double rc2,
+                                                         const int32_t *near_start, const int32_t *near_col,
+                                                         const double2 *nL, const double2 *nM, const double2 *nLp,
+                                                         const double2 *nMp, double2 *A) {
     const int b = blockIdx.x;
-    const int nb = leaf_start[b + 1] - leaf_start[b];
+    const int s = leaf_start[b], nb = leaf_start[b + 1] - s, n2 = 2 * nb;
+    double2 *Ab = A + blk_off[b];
+    const double inv4pi = 1.0 / (4.0 * FMM_PI);
+    // the four entries of pair (i, j) into the 2 x 2 sub-block (rows i, i + nb; columns j, j + nb)
+    auto put = [&](int r, int q, double2 L, double2 M, double2 Lp, double2 Mp, bool add) {
+        const int j = s + q;
+        const double2 ikm = cscale(cmuli(bm[j]), k), ikp = cscale(cmuli(bp[j]), k);  // i k beta-+_j
+        const double2 e00 = csub(M, cmul(ikm, L)), e01 = csub(cscale(M, -1.0), cmul(ikp, L));
+        const double2 e10 = csub(Mp, cmul(ikm, Lp)), e11 = csub(cscale(Mp, -1.0), cmul(ikp, Lp));
+        double2 *r0 = Ab + (int64_t)r * n2, *r1 = Ab + (int64_t)(r + nb) * n2;
+        if (add) {
+            r0[q] = cadd(r0[q], e00);
+            r0[q + nb] = cadd(r0[q + nb], e01);
+            r1[q] = cadd(r1[q], e10);
+            r1[q + nb] = cadd(r1[q + nb], e11);
+        } else {
+            r0[q] = e00;
+            r0[q + nb] = e01;
+            r1[q] = e10;
+            r1[q + nb] = e11;
+        }
+    };
+    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
+        const int r = e / nb, q = e % nb, i = s + r, j = s + q;
+        const double4 ci = ec[i], cj = ec[j];
+        const double d2 = dist2_exact(ci.x, ci.y, ci.z, cj.x, cj.y, cj.z);
+        double2 L = cmk(0, 0), M = L, Lp = L, Mp = L;
+        if (i != j && d2 >= rc2) {
+            const double4 ni = en[i], nj = en[j];
+            const double dx = cj.x - ci.x, dy = cj.y - ci.y, dz = cj.z - ci.z;
+            const double r1 = sqrt(d2), ir = 1.0 / r1, ir2 = ir * ir;
+            double sn, cs;
+            sincos(k * r1, &sn, &cs);
+            const double2 E = cmk(cs * inv4pi * cj.w, sn * inv4pi * cj.w);  // A_j e^{ikr} / 4 pi
+            const double2 G = cscale(E, ir);
+            const double dny = dx * nj.x + dy * nj.y + dz * nj.z, dnx = dx * ni.x + dy * ni.y + dz * ni.z;
+            const double nn = ni.x * nj.x + ni.y * nj.y + ni.z * nj.z;
+            const double2 g1 = cmul(G, cmk(-1.0, k * r1));  // G (ikr - 1)
+            L = G;
+            M = cscale(g1, dny * ir2);
+            Lp = cscale(g1, -dnx * ir2);
+            const double2 k3 = cmul(E, cmk(3.0 - k * k * d2, -3.0 * k * r1));
+            Mp = csub(cscale(k3, -dnx * dny * ir2 * ir2 * ir), cscale(cmul(E, cmk(-1.0, k * r1)), nn * ir2 * ir));
+        }
+        put(r, q, L, M, Lp, Mp, false);
+    }
+    __syncthreads();
+    // near-table entries (each row's entries belong to one thread: no two threads touch one row)
+    for (int r = threadIdx.x; r < nb; r += blockDim.x) {
+        const int i = s + r;
+        for (int e = near_start[i]; e < near_start[i + 1]; ++e) {
+            const int j = near_col[e];
+            if (j < s || j >= s + nb) continue;
+            put(r, j - s, nL[e], nM[e], nLp[e], nMp[e], true);
+        }
+        // local terms
+        const double2 ikm = cscale(cmuli(bm[i]), k), ikp = cscale(cmuli(bp[i]), k);
+        double2 *r0 = Ab + (int64_t)r * n2, *r1 = Ab + (int64_t)(r + nb) * n2;
+        r0[r] = cadd(r0[r], cmk(0.5, 0.0));
+        r0[r + nb] = cadd(r0[r + nb], cmk(0.5, 0.0));
+        r1[r] = cadd(r1[r], cscale(ikm, 0.5));
+        r1[r + nb] = cadd(r1[r + nb], cscale(ikp, -0.5));
+    }
+}
+
+// dense block of the combined (Burton-Miller) direct operator on each leaf, row-major n_b x n_b:
+//   1/2 delta_ij + (alpha i k / 2) beta_i delta_ij + M_ij - i k beta_j L_ij + alpha (M'_ij - i k beta_j L'_ij)
+// pair entries from the near tables or the near field's one-point rule, as for the indirect blocks
+__global__ void __launch_bounds__(256) k_leaf_blocks_bm(int nleaf, const int32_t *leaf_start, const int64_t *blk_off,
+                                                        const double4 *ec, const double4 *en, const double2 *beta,
+                                                        double k, double2 alpha, double rc2, const int32_t *near_start,
+                                                        const int32_t *near_col, const double2 *nL, const double2 *nM,
+                                                        const double2 *nLp, const double2 *nMp, double2 *A) {
+    const int b = blockIdx.x;
+    const int s = leaf_start[b], nb = leaf_start[b + 1] - s;
+    double2 *Ab = A + blk_off[b];
+    const double inv4pi = 1.0 / (4.0 * FMM_PI);
+    auto entry = [&](int j, double2 L, double2 M, double2 Lp, double2 Mp) {
+        const double2 ikb = cscale(cmuli(beta[j]), k);
+        return cadd(csub(M, cmul(ikb, L)), cmul(alpha, csub(Mp, cmul(ikb, Lp))));
+    };
+    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
+        const int r = e / nb, q = e % nb, i = s + r, j = s + q;
+        const double4 ci = ec[i], cj = ec[j];
+        const double d2 = dist2_exact(ci.x, ci.y, ci.z, cj.x, cj.y, cj.z);
+        double2 v = cmk(0, 0);
+        if (i != j && d2 >= rc2) {
+            const double4 ni = en[i], nj = en[j];
+            const double dx = cj.x - ci.x, dy = cj.y - ci.y, dz = cj.z - ci.z;
+            const double r1 = sqrt(d2), ir = 1.0 / r1, ir2 = ir * ir;
+            double sn, cs;
+            sincos(k * r1, &sn, &cs);
+            const double2 E = cmk(cs * inv4pi * cj.w, sn * inv4pi * cj.w);  // A_j e^{ikr} / 4 pi
+            const double2 G = cscale(E, ir);
+            const double dny = dx * nj.x + dy * nj.y + dz * nj.z, dnx = dx * ni.x + dy * ni.y + dz * ni.z;
+            const double nn = ni.x * nj.x + ni.y * nj.y + ni.z * nj.z;
+            const double2 g1 = cmul(G, cmk(-1.0, k * r1));  // G (ikr - 1)
+            const double2 k3 = cmul(E, cmk(3.0 - k * k * d2, -3.0 * k * r1));
+            const double2 Mp =
+                csub(cscale(k3, -dnx * dny * ir2 * ir2 * ir), cscale(cmul(E, cmk(-1.0, k * r1)), nn * ir2 * ir));
+            v = entry(j, G, cscale(g1, dny * ir2), cscale(g1, -dnx * ir2), Mp);
+        }
+        Ab[e] = v;
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < nb; r += blockDim.x) {
+        const int i = s + r;
+        for (int e = near_start[i]; e < near_start[i + 1]; ++e) {
+            const int j = near_col[e];
+            if (j < s || j >= s + nb) continue;
+            Ab[(int64_t)r * nb + (j - s)] = cadd(Ab[(int64_t)r * nb + (j - s)], entry(j, nL[e], nM[e], nLp[e], nMp[e]));
+        }
+        const double2 ikb = cscale(cmuli(beta[i]), k);
+        Ab[(int64_t)r * nb + r] = cadd(Ab[(int64_t)r * nb + r], cadd(cmk(0.5, 0.0), cscale(cmul(alpha, ikb), 0.5)));
+    }
+}
+
+// in-place Gauss-Jordan inversion with partial pivoting, one workgroup per leaf block
+// (block dimension m n_b: m unknowns per element; at most 1024)
+__global__ void __launch_bounds__(256) k_leaf_invert(int nleaf, const int32_t *leaf_start, const int64_t *blk_off,
+                                                     double2 *A, int32_t *piv_ws, int *status, int m) {
+    const int b = blockIdx.x;
+    const int nb = m * (leaf_start[b + 1] - leaf_start[b]);
     double2 *M = A + blk_off[b];
-    int32_t *piv = piv_ws + leaf_start[b];
+    int32_t *piv = piv_ws + (int64_t)m * leaf_start[b];
     __shared__ int sp;
     __shared__ double sbest[256];
     __shared__ int sidx[256];
@@ -301,20 +434,22 @@ __global__ void __launch_bounds__(256) k_leaf_invert(int nleaf, const int32_t *l
     }
 }
 
-// z = blockdiag(A_BB^{-1}) v, vectors in caller order
+// z = blockdiag(A_BB^{-1}) v, vectors in caller order; m unknowns per element (block index
+// q of element s + (q mod n_b) is unknown (q / n_b) n + perm[s + q mod n_b])
 __global__ void __launch_bounds__(128) k_leaf_apply(int nleaf, const int32_t *leaf_start, const int64_t *blk_off,
                                                     const double2 *Ainv, const int32_t *perm, const double2 *v,
-                                                    double2 *z) {
+                                                    double2 *z, int m, int64_t n) {
     const int b = blockIdx.x;
-    const int s = leaf_start[b], nb = leaf_start[b + 1] - s;
+    const int s = leaf_start[b], ne = leaf_start[b + 1] - s, nb = m * ne;
     const double2 *M = Ainv + blk_off[b];
     __shared__ double2 vs[1024];
-    for (int q = threadIdx.x; q < nb; q += blockDim.x) vs[q] = v[perm[s + q]];
+    auto idx = [&](int q) -> int64_t { return (int64_t)(q / ne) * n + perm[s + q % ne]; };
+    for (int q = threadIdx.x; q < nb; q += blockDim.x) vs[q] = v[idx(q)];
     __syncthreads();
     for (int r = threadIdx.x; r < nb; r += blockDim.x) {
         double2 acc = cmk(0, 0);
         for (int q = 0; q < nb; ++q) acc = cfma(M[(int64_t)r * nb + q], vs[q], acc);
-        z[perm[s + r]] = acc;
+        z[idx(r)] = acc;
     }
 }
 
