@@ -115,17 +115,19 @@ typedef struct {
     int autotune;        /* nonzero: at setup, time each translation batch under the candidate tile
                             shapes and keep the fastest (adds setup time); default 0 */
     int lane_tiles;      /* 1: translation batches whose table classes hold many jobs (padding to
-                            64-job tiles wastes at most a quarter) run one job per lane, tables
+                            64-job tiles wastes at most a fifth, or, for batches on matrix-core
+                            tiles, padding to 32 at most doubles the jobs) run job tiles, tables
                             read as wave-uniform values; 2: every batch does; 0: LDS tile kernels
                             everywhere; default 1 */
-    int streams;         /* 2: the near field, the M2M chain, the upper levels' M2L and the L2L
-                            chain of a product run on a second stream beside P2M and the leaf
-                            levels' M2L; 1: one stream; default 2 */
-    int mfma;            /* matrix-core tiles for the FP64 stages of one-job-per-lane batches
-                            (each degree/order of a 64-job tile as a real GEMM on
-                            v_mfma_f64_16x16x4f64): 1 for batches with p >= 24 under the fixed
-                            rule, and the autotuner measures them for every lane batch; 2 for
-                            every lane batch; 0 never; default 1 */
+    int streams;         /* 2: the upper levels' M2L and the L2L chain of a product run on a
+                            second stream beside the M2M chain, the deep levels' M2L and the near
+                            field; 1: one stream; default 2 */
+    int mfma;            /* matrix-core tiles for the stages of job-tile batches (each
+                            degree/order of a 64- or 32-job tile as a real GEMM on
+                            v_mfma_f64_16x16x4f64, FP32: v_mfma_f32_16x16x4f32): 1 for batches with
+                            p >= 24 under the fixed rule (32-job tiles where the classes are
+                            small), and the autotuner measures them for every job-tile batch; 2
+                            for every job-tile batch; 0 never; default 1 */
     int fused;           /* lane batches with p_src = p_tgt = p <= 16 may run all three stages in
                             one kernel on matrix cores: with the jobs' vectors resident in LDS
                             (any such p), or, for FP64 products of one vector at p = 16, resident
@@ -436,11 +438,14 @@ int fmmbem_batch_shapes(fmmbem_ctx *ctx, int32_t max, fmmbem_batch_shape *out, i
  * fmmbem_batch_shapes reported for the same mesh, wavenumber and options in an earlier run (the
  * autotuner's choice, so that a second process times or profiles exactly the same launches).
  * Each entry names its batch by (level, kind) and gives lane, whole, jt and mfma; jobs and ms are
- * ignored; batches not listed keep their shape.  Lane shapes need jt = 64 and whole = 0 (mfma 2
- * only where p_src = p_tgt <= 16, mfma 3 and 4 only where p_src = p_tgt = 16); LDS tiles need mfma = 0, jt a multiple of 4 in [4, 64] and
+ * ignored; batches not listed keep their shape.  Lane shapes need whole = 0 and jt = 64 (mfma 2
+ * only where p_src = p_tgt <= 16, mfma 3 and 4 only where p_src = p_tgt = 16), or jt = 32 with
+ * mfma = 1; LDS tiles need mfma = 0, jt a multiple of 4 in [4, 64] and
  * tiles that fit the LDS.  Every entry is checked before any is applied: an unknown batch or a
  * shape that does not fit returns FMMBEM_EINVAL and changes nothing.  Shapes hold until the
- * tables are rebuilt (a new mesh or wavenumber). */
+ * batches are rebuilt: a new mesh, or a wavenumber that changes the truncation number of the
+ * batch's level or of the level below (a new wavenumber with the same truncation numbers keeps
+ * each level's batches, shapes included). */
 int fmmbem_set_batch_shapes(fmmbem_ctx *ctx, int32_t count, const fmmbem_batch_shape *shapes);
 
 /* The L' and M' near entries (Eq. ibem3) in the order of fmmbem_near_entries (count via *nnz

@@ -133,6 +133,7 @@ static void check_p2m(int nr, int p) {
 
 static void setup_mesh(fmmbem_ctx *c) {
     const int64_t n = c->nt;
+    c->batch_p.clear();  // a new octree: every level's batches are rebuilt
     std::vector<double> cen(3 * n), nrm(3 * n), area(n);
     double vlo[3] = {1e300, 1e300, 1e300}, vhi[3] = {-1e300, -1e300, -1e300};
     for (int64_t v = 0; v < c->nv; ++v)
@@ -450,6 +451,10 @@ static void fused_tables(fmmbem_ctx *c, const std::string &name, TransBatch &b, 
     build_fused_tables(b.P, b.PT, b.nbeta, b.H, b.HT, ncoax, coax, b.frH, b.frHT, b.frC, c->stream);
 }
 
+// Batches of every level.  A level whose octree and truncation numbers (its own and the next
+// level's) are those its batches were built with keeps them -- job order, tiles, rotation tables
+// and tile shapes do not depend on k -- and only the fused tiles' coaxial fragments follow the new
+// coaxial tables (a frequency sweep on one mesh rebuilds only the levels whose p moved).
 static void build_batches(fmmbem_ctx *c) {
     TreeHost &T = c->tree;
     const int L = T.depth;
@@ -457,6 +462,17 @@ static void build_batches(fmmbem_ctx *c) {
         LevelHost &H = T.lv[l];
         LevelDev &D = c->lev[l];
         std::string s = "L" + std::to_string(l) + "_";
+        const std::pair<int, int> key(D.p, l < L ? c->lev[l + 1].p : -1);
+        auto kept = c->batch_p.find(l);
+        if (kept != c->batch_p.end() && kept->second == key) {
+            fused_tables(c, s + "m2l", D.m2l, D.coax_m2l, D.ntau);
+            if (l < L) {
+                fused_tables(c, s + "up", D.up, D.coax_up, 1);
+                fused_tables(c, s + "down", D.down, D.coax_up, 1);
+            }
+            continue;
+        }
+        c->batch_p.erase(l);
         std::vector<JobH> jobs;
         for (int64_t b = 0; b < D.nbox; ++b)
             for (int q = H.m2l_start[b]; q < H.m2l_start[b + 1]; ++q)
@@ -477,6 +493,7 @@ static void build_batches(fmmbem_ctx *c) {
             fused_tables(c, s + "up", D.up, D.coax_up, 1);
             fused_tables(c, s + "down", D.down, D.coax_up, 1);
         }
+        c->batch_p[l] = key;
     }
     HIP_OK(hipStreamSynchronize(c->stream));
 }

@@ -318,6 +318,8 @@ struct fmmbem_ctx {
     std::vector<double> history;  // Arnoldi residual estimate per outer iteration of the last solve
     bool mixed_ready = false;
     std::map<std::string, std::vector<fmm::JobH>> batch_jobs;  // sorted jobs per batch (re-layout)
+    // truncation numbers (p_l, p_{l+1}) each level's batches were built with; cleared with the octree
+    std::map<int, std::pair<int, int>> batch_p;
     std::vector<fmmbem_batch_shape> shapes;                      // tile shape chosen per batch
     std::vector<double2> beta_plus;  // admittance of the + faces (indirect formulation); empty: = beta
     bool indirect_ready = false;     // L' and M' near entries exist for the current (mesh, k)

@@ -880,3 +880,25 @@ def test_low_frequency_products_follow_k(F):
         assert err < 1e-6
     assert depths[0] == depths[2] < depths[1]
     ctx.close()
+
+
+def test_new_wavenumber_keeps_batches_of_unchanged_levels(F):
+    """A new wavenumber on the same mesh keeps the translation batches of every level whose
+    truncation numbers did not move (only the coaxial tables and the fused tiles' coaxial fragments
+    are rebuilt): products after 1000 -> 1005 Hz (few levels' p move) and 1005 -> 1300 Hz (most
+    move) equal, bitwise, those of a context set up at the new frequency from scratch (FP64 and
+    mixed)."""
+    room, _ = synth.config_room(2)
+    x = synth.complex_normal(room.n, 57)
+    ctx = make_ctx(F, room, synth.wavenumber(1000.0))
+    ctx.fmmbem_matvec(x)
+    for f in (1005.0, 1300.0):
+        k = synth.wavenumber(f)
+        ctx.fmmbem_set_wavenumber(k)
+        fresh = make_ctx(F, room, k)
+        ps = [ctx.fmmbem_get_info().p[l] for l in range(ctx.fmmbem_get_info().depth + 1)]
+        print(f"{f:.0f} Hz: p per level {ps}")
+        for prec in (0, 1):
+            assert np.array_equal(ctx.fmmbem_matvec(x, precision=prec), fresh.fmmbem_matvec(x, precision=prec)), (f, prec)
+        fresh.close()
+    ctx.close()
