@@ -331,9 +331,25 @@ __device__ inline void sincos_red(double x, double &s, double &c) {
 // ------------------------------------------------------------------ P2P + near table
 // y_i = sum_{j in neighbour leaves, |c_i - c_j| >= r_c} [G q_j + dG/dn_y w_j] + sum_near [L sigma + M mu]
 // with q_j = A_j sigma_j, w_j = A_j mu_j.  One workgroup (one wavefront) per target leaf,
-// source tiles staged in LDS.  A leaf of at most 32 (16) targets splits every source tile over
-// 2 (4) groups of lanes, one target per lane of a group, and adds the groups' sums at the end.
-__device__ inline int p2p_splits(int nt) { return nt <= 16 ? 4 : nt <= 32 ? 2 : 1; }
+// source tiles staged in LDS.  A small leaf splits every source tile over S groups of lanes, one
+// target per lane of a group, and adds the groups' sums at the end.
+// Source splits S of a leaf of nt targets: lane groups of TP = floor(64 / S) targets, each group
+// summing every S-th source, ceil(nt / TP) passes over the sources; S in 1..8 minimises the lane
+// work ceil(nt / TP) / S (ties to the smaller S, which adds fewer partial sums).  Lanes past S TP
+// (S = 3, 5, 6, 7) stay idle.
+__device__ inline int p2p_splits(int nt) {
+    int best = 1;
+    double bc = 1e30;
+    for (int S = 1; S <= 8; ++S) {
+        const int TP = 64 / S;
+        const double c = (double)((nt + TP - 1) / TP) / S;
+        if (c < bc - 1e-12) {
+            bc = c;
+            best = S;
+        }
+    }
+    return best;
+}
 
 template <int NR>
 __global__ void __launch_bounds__(64) k_p2p(int nleaf, const int32_t *leaf_start, const int32_t *nbr_start,
@@ -352,7 +368,7 @@ __global__ void __launch_bounds__(64) k_p2p(int nleaf, const int32_t *leaf_start
     const int h = tid / TP;
     for (int t0 = ts; t0 < te; t0 += TP) {
         const int t = t0 + tid % TP;
-        const bool act = t < te;
+        const bool act = t < te && h < S;
         double4 ct = act ? ec[t] : make_double4(0, 0, 0, 0);
         double2 acc[NR];
 #pragma unroll
@@ -456,7 +472,7 @@ __global__ void __launch_bounds__(64) k_p2p32(int nleaf, const int32_t *leaf_sta
     const int h = tid / TP;
     for (int t0 = ts; t0 < te; t0 += TP) {
         const int t = t0 + tid % TP;
-        const bool act = t < te;
+        const bool act = t < te && h < S;
         double4 ct = act ? ec[t] : make_double4(0, 0, 0, 0);
         float ar[NR], ai[NR], cr[NR], ci[NR];
 #pragma unroll
