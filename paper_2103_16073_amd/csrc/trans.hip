@@ -977,6 +977,24 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))
                     for (int i = 0; i < 4; ++i) lds[(q * 16 + Op::row(kq, i)) * TM_LD + colw + 16 * cb] = acc[q][cb][i];
             __syncthreads();
             const int nrow = min(RG, w - r0);
+            // phase every (row, job) in place first, all its phase loads in flight together, so that
+            // the run sums below read LDS only
+            constexpr int NE = RG * TMJ / 256;
+            C phv[NE];
+#pragma unroll
+            for (int i = 0; i < NE; ++i) {
+                const int e = tid + 256 * i, j = e / RG, rr = e % RG;
+                phv[i] = rr < nrow ? a.ph[sdir[j] + r0 + rr - n] : mkc<C>(0, 0);
+            }
+#pragma unroll
+            for (int i = 0; i < NE; ++i) {
+                const int e = tid + 256 * i, j = e / RG, rr = e % RG;
+                R *x = &lds[rr * TM_LD + 2 * j];
+                const C v = mulcc(mkc<C>(x[0], x[1]), phv[i]);  // e^{-i m a}
+                x[0] = v.x;
+                x[1] = v.y;
+            }
+            __syncthreads();
             for (int e = tid; e < RG * TMJ; e += 256) {
                 const int j = e / RG, rr = e % RG, r = r0 + rr;
                 const int len = segl[j];
@@ -984,8 +1002,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))
                 C v = mkc<C>(0, 0);
                 for (int t = 0; t < len; ++t) {
                     const int jj = j + t * a.nr;
-                    v = addc(v, mulcc(mkc<C>(lds[rr * TM_LD + 2 * jj], lds[rr * TM_LD + 2 * jj + 1]),
-                                      a.ph[sdir[jj] + r - n]));  // e^{-i m a}
+                    v = addc(v, mkc<C>(lds[rr * TM_LD + 2 * jj], lds[rr * TM_LD + 2 * jj + 1]));
                 }
                 a.W1[(J0 + j) * (int64_t)P2 + n * n + r] = v;
             }
@@ -1767,7 +1784,8 @@ __global__ void __launch_bounds__(256) k_fr_coax(int64_t ntot, int P, int PT, co
 // that vector are (job * nr + t % nr).  Workgroup (t, y) takes coefficients 256 y .. 256 y + 255
 // of target t, so that the large expansions of the upper levels spread over many workgroups.
 // Without acc the sums overwrite dst, targets without jobs included (the batch writes every
-// target: no clearing of dst beforehand).  Eight row loads in flight per thread.
+// target: no clearing of dst beforehand).  Rows are loaded eight at a time (a partial group
+// included), all in flight together.
 template <class C>
 __global__ void __launch_bounds__(256) k_tr_reduce(int64_t ntgt, int nr, int ptgt, int P, const int32_t *start,
                                                    const int32_t *jobs, const C *W, C *dst, int acc) {
@@ -1785,15 +1803,13 @@ __global__ void __launch_bounds__(256) k_tr_reduce(int64_t ntgt, int nr, int ptg
     s[0] = acc ? dst[t * pt2 + c] : mkc<C>(0, 0);
 #pragma unroll
     for (int u = 1; u < 8; ++u) s[u] = mkc<C>(0, 0);
-    int q = j0;
-    for (; q + 8 <= j1; q += 8) {
+    for (int q = j0; q < j1; q += 8) {  // a target has ~5-8 rows: the last group is partial, not serial
         C a[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) a[u] = W[((int64_t)jobs[q + u] * nr + r) * P2 + c];
+        for (int u = 0; u < 8; ++u) a[u] = q + u < j1 ? W[((int64_t)jobs[q + u] * nr + r) * P2 + c] : mkc<C>(0, 0);
 #pragma unroll
         for (int u = 0; u < 8; ++u) s[u] = addc(s[u], a[u]);
     }
-    for (; q < j1; ++q) s[0] = addc(s[0], W[((int64_t)jobs[q] * nr + r) * P2 + c]);
     dst[t * pt2 + c] = addc(addc(addc(s[0], s[1]), addc(s[2], s[3])), addc(addc(s[4], s[5]), addc(s[6], s[7])));
 }
 
