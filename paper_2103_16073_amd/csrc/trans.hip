@@ -838,12 +838,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))
     constexpr int RG = 16 * RBG;            // rows per pass
     constexpr int NCOL = 2 * TMJ;           // real columns of a tile
     constexpr int NCB = TMJ / 32;           // 16-column blocks per wavefront
-    // K chunks of 8 and passes of 64 (forward) or 32 (back) rows: 33 KB of LDS, four workgroups per
-    // CU (measured at levels 2-5 of the 1M L-room against chunks of 16 and passes of 128 / 64 rows:
-    // back rotation 1.51 -> 1.15 ms, forward rotation 1.90 -> 1.66 ms per product)
+    // K chunks of 8 and passes of 64 rows: 33 KB of LDS, four workgroups per CU (measured at levels
+    // 2-5 of the 1M L-room against chunks of 16 and passes of 128 / 64 rows: back rotation 1.51 ->
+    // 1.15 ms, forward rotation 1.90 -> 1.66 ms per product).  The back rotation's outputs leave
+    // through the same LDS block 32 rows at a time (64-row passes instead of 32: FP64 product
+    // 10.97 -> 10.88 ms, mixed 9.00 -> 8.86 ms).
     constexpr int KC = TM_KC;
-    constexpr int LDSN = FWD ? 4 * KC * TM_LD : (4 * KC > RG ? 4 * KC : RG) * TM_LD;
-    static_assert(RG <= 128 && (FWD || RG * TM_LD <= LDSN), "pass too large for the LDS block");
+    constexpr int EQ = RBG < 2 ? RBG : 2;  // back: row blocks per epilogue step (32 rows through LDS)
+    constexpr int LDSN = FWD ? 4 * KC * TM_LD : (4 * KC > 16 * EQ ? 4 * KC : 16 * EQ) * TM_LD;
+    static_assert(RG <= 128 && RBG % EQ == 0, "pass too large for the LDS block");
     static_assert(TMJ == 64 || TMJ == 32, "tiles of 64 or 32 jobs");
     __shared__ R lds[LDSN];
     __shared__ int64_t soff[TMJ];
@@ -966,45 +969,55 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))
                     }
             }
         } else {
-            // the pass's RG output rows x NCOL columns through the LDS block, then phase, run sums
-            // and job-major stores (consecutive threads: consecutive rows of one job)
-            __syncthreads();
+            // the pass's output rows go through the LDS block EQ row blocks (ER rows x NCOL columns)
+            // at a time: phase, run sums and job-major stores (consecutive threads: consecutive rows
+            // of one job)
+            constexpr int ER = 16 * EQ, NE = ER * TMJ / 256;
 #pragma unroll
-            for (int q = 0; q < RBG; ++q)
+            for (int q0 = 0; q0 < RBG; q0 += EQ) {
+                if (rb0 + q0 >= RB) break;
+                __syncthreads();
 #pragma unroll
-                for (int cb = 0; cb < NCB; ++cb)
+                for (int q = 0; q < EQ; ++q)
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) lds[(q * 16 + Op::row(kq, i)) * TM_LD + colw + 16 * cb] = acc[q][cb][i];
-            __syncthreads();
-            const int nrow = min(RG, w - r0);
-            // phase every (row, job) in place first, all its phase loads in flight together, so that
-            // the run sums below read LDS only
-            constexpr int NE = RG * TMJ / 256;
-            C phv[NE];
+                    for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-            for (int i = 0; i < NE; ++i) {
-                const int e = tid + 256 * i, j = e / RG, rr = e % RG;
-                phv[i] = rr < nrow ? a.ph[sdir[j] + r0 + rr - n] : mkc<C>(0, 0);
-            }
+                        for (int i = 0; i < 4; ++i)
+                            lds[(q * 16 + Op::row(kq, i)) * TM_LD + colw + 16 * cb] = acc[q0 + q][cb][i];
+                __syncthreads();
+                const int rs = r0 + 16 * q0, nrow = min(ER, w - rs);
+                // phase every (row, job) in place first, four phase loads in flight at a time, so
+                // that the run sums below read LDS only
+                constexpr int NG = NE < 4 ? NE : 4;
 #pragma unroll
-            for (int i = 0; i < NE; ++i) {
-                const int e = tid + 256 * i, j = e / RG, rr = e % RG;
-                R *x = &lds[rr * TM_LD + 2 * j];
-                const C v = mulcc(mkc<C>(x[0], x[1]), phv[i]);  // e^{-i m a}
-                x[0] = v.x;
-                x[1] = v.y;
-            }
-            __syncthreads();
-            for (int e = tid; e < RG * TMJ; e += 256) {
-                const int j = e / RG, rr = e % RG, r = r0 + rr;
-                const int len = segl[j];
-                if (rr >= nrow || len == 0) continue;
-                C v = mkc<C>(0, 0);
-                for (int t = 0; t < len; ++t) {
-                    const int jj = j + t * a.nr;
-                    v = addc(v, mkc<C>(lds[rr * TM_LD + 2 * jj], lds[rr * TM_LD + 2 * jj + 1]));
+                for (int i0 = 0; i0 < NE; i0 += NG) {
+                    C phv[NG];
+#pragma unroll
+                    for (int i = 0; i < NG; ++i) {
+                        const int e = tid + 256 * (i0 + i), j = e / ER, rr = e % ER;
+                        phv[i] = rr < nrow ? a.ph[sdir[j] + rs + rr - n] : mkc<C>(0, 0);
+                    }
+#pragma unroll
+                    for (int i = 0; i < NG; ++i) {
+                        const int e = tid + 256 * (i0 + i), j = e / ER, rr = e % ER;
+                        R *x = &lds[rr * TM_LD + 2 * j];
+                        const C v = mulcc(mkc<C>(x[0], x[1]), phv[i]);  // e^{-i m a}
+                        x[0] = v.x;
+                        x[1] = v.y;
+                    }
                 }
-                a.W1[(J0 + j) * (int64_t)P2 + n * n + r] = v;
+                __syncthreads();
+                for (int e = tid; e < ER * TMJ; e += 256) {
+                    const int j = e / ER, rr = e % ER, r = rs + rr;
+                    const int len = segl[j];
+                    if (rr >= nrow || len == 0) continue;
+                    C v = mkc<C>(0, 0);
+                    for (int t = 0; t < len; ++t) {
+                        const int jj = j + t * a.nr;
+                        v = addc(v, mkc<C>(lds[rr * TM_LD + 2 * jj], lds[rr * TM_LD + 2 * jj + 1]));
+                    }
+                    a.W1[(J0 + j) * (int64_t)P2 + n * n + r] = v;
+                }
             }
         }
     }
@@ -1923,9 +1936,9 @@ const char *trans_stage(const TransBatch &b, const TransTables<R> &tb, int stage
             name = f32 ? "k_tm_coax_f32" : "k_tm_coax";
             break;
         default:
-            np = passes(2 * b.ptgt - 1, 2, b.ptgt);
-            if (b.JT == LANE_JT) k_tm_rot<R, false, 2, 64><<<dim3(ntile, b.ptgt * np), 256, 0, st>>>(a, np);
-            else k_tm_rot<R, false, 2, 32><<<dim3(ntile, b.ptgt * np), 256, 0, st>>>(a, np);
+            np = passes(2 * b.ptgt - 1, 4, b.ptgt);
+            if (b.JT == LANE_JT) k_tm_rot<R, false, 4, 64><<<dim3(ntile, b.ptgt * np), 256, 0, st>>>(a, np);
+            else k_tm_rot<R, false, 4, 32><<<dim3(ntile, b.ptgt * np), 256, 0, st>>>(a, np);
             name = f32 ? "k_tm_rot_back_f32" : "k_tm_rot_back";
         }
         LAUNCH_OK();
