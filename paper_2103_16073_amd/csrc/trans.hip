@@ -819,7 +819,6 @@ template <> struct TmOp<float> {
     static __device__ inline int row(int kq, int i) { return 4 * kq + i; }
 };
 constexpr int TM_KC = 8;    // K rows per LDS chunk (double-buffered) of the rotations
-constexpr int TMC_KC = 8;   // the same for the coaxial step: its 33 KB of LDS let four workgroups share a CU
 constexpr int TM_LD = 130;  // LDS row stride (doubles) of the staged A and B chunks
 
 // Rotation of degree n for one tile of TMJ jobs (64 or 32: 2 TMJ columns, the four wavefronts owning
@@ -1028,20 +1027,23 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))
 // chunks staged in LDS as for the rotations.  With X' the input with each job's real and imaginary
 // columns swapped and the new real one negated (read from the partner column of X in LDS),
 // Y = Re(T) X + Im(T) X' column by column, so one accumulator set takes both real GEMMs.
-template <class R, int TMJ>
+// RBG row blocks of 16 rows per pass, K chunks of KC rows.
+template <class R, int TMJ, int RBG, int KC>
 __global__ void __launch_bounds__(256) k_tm_coax(TransArgsT<R> a, int npass) {
     using C = typename Cx<R>::T;
     using Op = TmOp<R>;
     using v4 = typename Op::v4;
-    constexpr int RBG = 4, RG = 16 * RBG, LA = RG + 2;
-    constexpr int NCOL = 2 * TMJ, NCB = TMJ / 32, NX = TMC_KC * TMJ / 256;
+    constexpr int RG = 16 * RBG, LA = RG + 2;
+    constexpr int NCOL = 2 * TMJ, NCB = TMJ / 32;
+    constexpr int NA = (KC * RG + 255) / 256, NX = (KC * TMJ + 255) / 256;  // staged values per thread
     static_assert(TMJ == 64 || TMJ == 32, "tiles of 64 or 32 jobs");
+    static_assert(KC % 4 == 0 && (KC * RG) % 64 == 0 && (KC * TMJ) % 64 == 0, "whole wavefronts per staged chunk");
     // A: real part (chunks 0, 1) and imaginary part (2, 3), RG + 2 columns; B: X (2 chunks)
-    __shared__ R ldsA[4 * TMC_KC * LA];
-    __shared__ R ldsB[2 * TMC_KC * TM_LD];
-    auto Ar = [&](int buf, int k, int r) -> R & { return ldsA[(buf * TMC_KC + k) * LA + r]; };
-    auto Ai = [&](int buf, int k, int r) -> R & { return ldsA[((2 + buf) * TMC_KC + k) * LA + r]; };
-    auto Bs = [&](int buf, int k, int c) -> R & { return ldsB[(buf * TMC_KC + k) * TM_LD + c]; };
+    __shared__ R ldsA[4 * KC * LA];
+    __shared__ R ldsB[2 * KC * TM_LD];
+    auto Ar = [&](int buf, int k, int r) -> R & { return ldsA[(buf * KC + k) * LA + r]; };
+    auto Ai = [&](int buf, int k, int r) -> R & { return ldsA[((2 + buf) * KC + k) * LA + r]; };
+    auto Bs = [&](int buf, int k, int c) -> R & { return ldsB[(buf * KC + k) * TM_LD + c]; };
     int tile, mq;
     xcd_block(tile, mq);
     const int mi = mq / npass, pass = mq - mi * npass;  // order index, and the pass's share of its row groups
@@ -1063,37 +1065,41 @@ __global__ void __launch_bounds__(256) k_tm_coax(TransArgsT<R> a, int npass) {
     const C *Tm = a.coax + (int64_t)a.tile_coax[tile / a.nr] * coax_table_size(a.PT) + coax_block_off(a.PT, am);
     const int colw = (NCOL / 4) * wv + (lane & 15), kq = lane >> 4;
     const R swp = (colw & 1) ? R(1) : R(-1);
-    const int nch = (cin + TMC_KC - 1) / TMC_KC;
+    const int nch = (cin + KC - 1) / KC;
     for (int rb0 = pass * RBG; rb0 < RB; rb0 += npass * RBG) {
         const int r0 = rb0 * 16;
-        C ta[TMC_KC * RG / 256];
+        C ta[NA];
         C xb[NX];  // (re, im) of NX (k, job) inputs
         auto gload = [&](int kc) {
 #pragma unroll
-            for (int i = 0; i < TMC_KC * RG / 256; ++i) {
+            for (int i = 0; i < NA; ++i) {
                 const int e = tid + 256 * i, kk = e / RG, rr = e % RG, k = kc + kk, r = r0 + rr;
-                C t = (k < cin && r < rows) ? Tm[(int64_t)k * B + r] : mkc<C>(0, 0);
+                C t = (e < KC * RG && k < cin && r < rows) ? Tm[(int64_t)k * B + r] : mkc<C>(0, 0);
                 if ((k + r) & 1) t = mkc<C>(-t.x, -t.y);
                 ta[i] = t;
             }
 #pragma unroll
             for (int i = 0; i < NX; ++i) {
                 const int e = tid + 256 * i, kk = e / TMJ, j = e % TMJ, k = kc + kk, nb = am + k;
-                xb[i] = k < cin ? Xin[((int64_t)tile * P2 + nb * nb + nb + m) * TMJ + j] : mkc<C>(0, 0);
+                xb[i] = (e < KC * TMJ && k < cin) ? Xin[((int64_t)tile * P2 + nb * nb + nb + m) * TMJ + j] : mkc<C>(0, 0);
             }
         };
         auto lstore = [&](int buf) {
 #pragma unroll
-            for (int i = 0; i < TMC_KC * RG / 256; ++i) {
+            for (int i = 0; i < NA; ++i) {
                 const int e = tid + 256 * i;
-                Ar(buf, e / RG, e % RG) = ta[i].x;
-                Ai(buf, e / RG, e % RG) = ta[i].y;
+                if (e < KC * RG) {
+                    Ar(buf, e / RG, e % RG) = ta[i].x;
+                    Ai(buf, e / RG, e % RG) = ta[i].y;
+                }
             }
 #pragma unroll
             for (int i = 0; i < NX; ++i) {
                 const int e = tid + 256 * i, kk = e / TMJ, j = e % TMJ;
-                Bs(buf, kk, 2 * j) = xb[i].x;
-                Bs(buf, kk, 2 * j + 1) = xb[i].y;
+                if (e < KC * TMJ) {
+                    Bs(buf, kk, 2 * j) = xb[i].x;
+                    Bs(buf, kk, 2 * j + 1) = xb[i].y;
+                }
             }
         };
         v4 acc[RBG][NCB];
@@ -1107,8 +1113,8 @@ __global__ void __launch_bounds__(256) k_tm_coax(TransArgsT<R> a, int npass) {
         __syncthreads();
         for (int c = 0; c < nch; ++c) {
             const int buf = c & 1;
-            if (c + 1 < nch) gload((c + 1) * TMC_KC);
-            const int kn = min(TMC_KC, cin - c * TMC_KC);
+            if (c + 1 < nch) gload((c + 1) * KC);
+            const int kn = min(KC, cin - c * KC);
             for (int ks = 0; ks < kn; ks += 4) {
                 R bv[NCB], wv2[NCB];
 #pragma unroll
@@ -1562,15 +1568,13 @@ __device__ __forceinline__ double tq_dpp_shl(double v, int ctrl_sel) {
     }
     return __hiloint2double(hi, lo);
 }
-__device__ __forceinline__ double tq_run_sum(double v, int col, int end2) {
-    // end2 = 2 * (end of this column's run in jobs): columns c + d with c + d < end2 belong to it
+// md = 1 where column c + d still belongs to column c's run, else 0 (multipliers: one FMA per shift
+// instead of a select and an add)
+__device__ __forceinline__ double tq_run_sum(double v, double m2, double m4, double m8) {
     double s = v;
-    const double s2 = tq_dpp_shl(s, 2);
-    s += (col + 2 < end2) ? s2 : 0.0;
-    const double s4 = tq_dpp_shl(s, 4);
-    s += (col + 4 < end2) ? s4 : 0.0;
-    const double s8 = tq_dpp_shl(s, 8);
-    s += (col + 8 < end2) ? s8 : 0.0;
+    s = fma(tq_dpp_shl(s, 2), m2, s);
+    s = fma(tq_dpp_shl(s, 4), m4, s);
+    s = fma(tq_dpp_shl(s, 8), m8, s);
     return s;
 }
 
@@ -1606,7 +1610,10 @@ template <int OCC>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, OCC))) k_tq_rcr(TransArgsT<double> a) {
     using v4 = TmOp<double>::v4;
     constexpr int P = TQ_P, P2 = P * P, NPH = 2 * P - 1;
-    __shared__ double2 phl[8][NPH];  // e^{i m a_j}, m = -(P-1) .. P-1
+    // e^{i m a_j}, m = -(P-1) .. P-1, with the imaginary part negated ([0]) or not ([1]): the
+    // phase of a complex value held as (re, im) in partner columns is then fma(e.x, x, e.y * y) for
+    // either part (x its own value, y the partner's), with no select on the part
+    __shared__ double2 phg[2][8][NPH];
     __shared__ int64_t soff[8];
     __shared__ int sgend[8];  // per job: first job past the run it belongs to (within the wavefront)
     __shared__ int segl[8];
@@ -1625,7 +1632,9 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, OC
     for (int e = lane; e < 8 * NPH; e += 64) {
         const int j = e / NPH, q = e - j * NPH;
         const int64_t Jv = J0 + j, Jc = Jv < a.njob ? Jv : a.njob - 1;
-        phl[j][q] = a.ph[(int64_t)a.jdir[Jc] * phs + a.PH - (P - 1) + q];
+        const double2 ph = a.ph[(int64_t)a.jdir[Jc] * phs + a.PH - (P - 1) + q];
+        phg[1][j][q] = ph;
+        phg[0][j][q] = make_double2(ph.x, -ph.y);
     }
     __syncthreads();
     if (lane < 8) {
@@ -1662,14 +1671,14 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, OC
                 constexpr int q = decltype(sI)::value;
                 const int r = min(4 * q + g, 2 * n);
                 const double x = X[tq_doff(n) + q], y = tq_swap_pair(x);
-                const double re = im ? y : x, iv = im ? x : y;
-                const double2 e = phl[jl][r - n + P - 1];
-                X[tq_doff(n) + q] = im ? fma(e.x, iv, e.y * re) : fma(e.x, re, -e.y * iv);
+                const double2 e = phg[im][jl][r - n + P - 1];  // e: re x_r - im x_i, re x_i + im x_r
+                X[tq_doff(n) + q] = fma(e.x, x, e.y * y);
             });
         });
     }
     const int end2 = 2 * sgend[jl];
     const bool starts = segl[jl] > 0;
+    const double rm2 = col + 2 < end2 ? 1.0 : 0.0, rm4 = col + 4 < end2 ? 1.0 : 0.0, rm8 = col + 8 < end2 ? 1.0 : 0.0;
     // forward rotation, degree by degree: Y_n = H_n X_n
     tq_for<P>([&](auto nI) {
         constexpr int n = decltype(nI)::value;
@@ -1747,9 +1756,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, OC
             constexpr int q = decltype(qI)::value;
             const int r = 4 * q + g, rc = min(r, 2 * n);
             const double x = acc[q / 4][q % 4], y = tq_swap_pair(x);
-            const double re = im ? y : x, iv = im ? x : y;
-            const double2 e = phl[jl][rc - n + P - 1];  // times conj(e)
-            const double v = tq_run_sum(im ? fma(e.x, iv, -e.y * re) : fma(e.x, re, e.y * iv), col, end2);
+            const double2 e = phg[1 - im][jl][rc - n + P - 1];  // conj(e)
+            const double v = tq_run_sum(fma(e.x, x, e.y * y), rm2, rm4, rm8);
             if (starts && r < w) ((double *)(out + (int64_t)jl * P2 + n * n + r))[im] = v;
         });
     });
@@ -1931,8 +1939,9 @@ const char *trans_stage(const TransBatch &b, const TransTables<R> &tb, int stage
             break;
         case 1:
             np = passes(b.ptgt, 4, 2 * b.ptgt - 1);
-            if (b.JT == LANE_JT) k_tm_coax<R, 64><<<dim3(ntile, (2 * b.ptgt - 1) * np), 256, 0, st>>>(a, np);
-            else k_tm_coax<R, 32><<<dim3(ntile, (2 * b.ptgt - 1) * np), 256, 0, st>>>(a, np);
+            // 64-row passes, K chunks of 8: 33 KB of LDS, four workgroups per CU
+            if (b.JT == LANE_JT) k_tm_coax<R, 64, 4, 8><<<dim3(ntile, (2 * b.ptgt - 1) * np), 256, 0, st>>>(a, np);
+            else k_tm_coax<R, 32, 4, 8><<<dim3(ntile, (2 * b.ptgt - 1) * np), 256, 0, st>>>(a, np);
             name = f32 ? "k_tm_coax_f32" : "k_tm_coax";
             break;
         default:
