@@ -1739,7 +1739,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, OC
     }
     // back rotation, degree by degree from the largest: H_n^T, then e^{-i m a} and the run sums of
     // one target; the runs' first jobs store their rows (job-major, for the per-target reduction)
-    double2 *out = a.W1 + J0 * (int64_t)P2;
+    double *const orow = (double *)(a.W1 + (J0 + jl) * (int64_t)P2 + g) + im;  // element r = 4 q + g: 2 (n^2 + 4 q)
     tq_for<P>([&](auto dI) {
         constexpr int n = P - 1 - decltype(dI)::value, KS = tq_dreg(n), w = 2 * n + 1;
         __builtin_amdgcn_sched_barrier(0);  // one degree's outputs at a time (register pressure)
@@ -1758,7 +1758,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, OC
             const double x = acc[q / 4][q % 4], y = tq_swap_pair(x);
             const double2 e = phg[1 - im][jl][rc - n + P - 1];  // conj(e)
             const double v = tq_run_sum(fma(e.x, x, e.y * y), rm2, rm4, rm8);
-            if (starts && r < w) ((double *)(out + (int64_t)jl * P2 + n * n + r))[im] = v;
+            if (starts && r < w) orow[2 * (n * n + 4 * q)] = v;
         });
     });
 }
