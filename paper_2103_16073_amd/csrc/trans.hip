@@ -890,7 +890,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))
             if (FWD) {
 #pragma unroll
                 for (int i = 0; i < NB / 2; ++i) {
-                    const int e = tid + 256 * i, kk = e / TMJ, j = e % TMJ, k = kc + kk;
+                    const int e = tid + 256 * i, kk = e % KC, j = e / KC, k = kc + kk;  // a job's KC rows: one segment
                     rph[i] = k < w ? a.ph[sdir[j] + k - n] : mkc<C>(0, 0);
                     rsr[i] = k < w ? a.src[soff[j] + n * n + k] : mkc<C>(0, 0);
                 }
@@ -911,7 +911,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))
             if (FWD) {
 #pragma unroll
                 for (int i = 0; i < NB / 2; ++i) {
-                    const int e = tid + 256 * i, kk = e / TMJ, j = e % TMJ;
+                    const int e = tid + 256 * i, kk = e % KC, j = e / KC;
                     const C x = mulc(rph[i], rsr[i]);  // e^{i m a} c_n^m
                     Bs(buf, kk, 2 * j) = x.x;
                     Bs(buf, kk, 2 * j + 1) = x.y;
