@@ -721,7 +721,7 @@ static void run_batch(fmmbem_ctx *c, int nrv, const TransBatch &b0, const typena
     TransBatch b32;
     if (sizeof(R) == 4 && c->opt.fused && b0.lane && b0.mfma == 0 && fused_ok(b0) && tb.frH) {
         b32 = b0;
-        b32.mfma = 2;
+        b32.mfma = rcr_ok(b0) ? 4 : 2;  // p = 16: the FP32 register-resident shape (one vector)
     }
     const TransBatch &b = b32.njob ? b32 : b0;
     hipStream_t st = c->cur;

@@ -1579,8 +1579,8 @@ __device__ __forceinline__ double tq_run_sum(double v, double m2, double m4, dou
 }
 
 // A fragments of the rotation of degree n (K chunks x row blocks), one value per lane
-template <int N>
-__device__ __forceinline__ void tq_load_rot(double (&A)[16], const double *F) {
+template <int N, class T>
+__device__ __forceinline__ void tq_load_rot(T (&A)[16], const T *F) {
     constexpr int KS = tq_dreg(N), RB = (2 * N + 16) / 16;
     tq_for<RB>([&](auto bI) {
         tq_for<KS>([&](auto iI) {
@@ -1763,6 +1763,185 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, OC
     });
 }
 
+// FP32 variant for mixed products (p = 16, one vector): one wavefront = 8 jobs of a 64-job tile as
+// in k_tq_rcr, but the jobs' vectors live in LDS (256 coefficients x 16 columns, 16 KB) instead of
+// registers: every step reads its B operands from LDS in the matrix-core layout (K row 4 i + g of
+// chunk i in lane group g), the partner column (the other part of a job) included, and writes its
+// outputs back in place (rows 4 g + i of a 16-row block in lane group g, the FP32 output layout), so
+// the changes between degree and order order are only addresses.  FP32 matrix instructions overlap
+// the vector work.  Phases, run sums and stores as in k_tq_rcr; tables: the FP32 fragment-order
+// tables of the fused tiles.
+__device__ __forceinline__ float tq_swap_pair32(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float tq_dpp_shl32(float v, int d) {
+    const int x = __float_as_int(v);
+    switch (d) {  // row_shl:2 / 4 / 8 (lane i takes lane i + d of its row of 16; 0 past the row)
+    case 2: return __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x102, 0xF, 0xF, true));
+    case 4: return __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x104, 0xF, 0xF, true));
+    default: return __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x108, 0xF, 0xF, true));
+    }
+}
+
+__global__ void __launch_bounds__(64) k_tq_rcr32(TransArgsT<float> a) {
+    using v4 = TmOp<float>::v4;
+    constexpr int P = TQ_P, P2 = P * P, NPH = 2 * P - 1;
+    __shared__ float Xs[P2][16];      // coefficient (n, m) at row n^2 + n + m, column 2 job + part
+    __shared__ float2 phg[2][8][NPH];  // e^{i m a_j} with the imaginary part negated ([0]) or not ([1])
+    __shared__ int64_t soff[8];
+    __shared__ int sgend[8];
+    __shared__ int segl[8];
+    int tile, part;
+    xcd_block(tile, part);
+    const int64_t J0 = (int64_t)tile * LANE_JT + part * 8;
+    if (J0 >= a.njob) return;  // the whole workgroup (one wavefront)
+    const int lane = threadIdx.x, g = lane >> 4, col = lane & 15, jl = col >> 1, im = col & 1;
+    const int phs = 2 * a.PH + 1;
+    if (lane < 8) {
+        const int64_t Jv = J0 + lane, Jc = Jv < a.njob ? Jv : a.njob - 1;
+        soff[lane] = (int64_t)a.jsrc[Jc] * P2;
+        segl[lane] = Jv < a.njob ? a.jseg[Jv] : 0;
+    }
+    for (int e = lane; e < 8 * NPH; e += 64) {
+        const int j = e / NPH, q = e - j * NPH;
+        const int64_t Jv = J0 + j, Jc = Jv < a.njob ? Jv : a.njob - 1;
+        const float2 ph = a.ph[(int64_t)a.jdir[Jc] * phs + a.PH - (P - 1) + q];
+        phg[1][j][q] = ph;
+        phg[0][j][q] = make_float2(ph.x, -ph.y);
+    }
+    __syncthreads();
+    if (lane < 8) {
+        // run of job `lane`: it starts at the nearest start at or before it (runs are contiguous)
+        int st = lane;
+        while (st > 0 && segl[st] == 0) --st;
+        sgend[lane] = segl[st] > 0 ? st + segl[st] : lane + 1;
+    }
+    const int tr = a.tile_rot[tile], tc = a.tile_coax[tile];
+    const float *FF = a.frHT + (int64_t)tr * TF_FR_ROT + lane;  // forward: H (from HT's fragments)
+    const float *FB = a.frH + (int64_t)tr * TF_FR_ROT + lane;   // back: H^T
+    const float *FC = a.frC + (int64_t)tc * TF_FR_COAX + lane;
+    float AF[P][16];  // rotation fragments per degree (only the live ones take registers)
+    float TF[P][8];   // coaxial fragments per order |m|: 4 K chunks x (re, im)
+    // sources times e^{i m a}: lanes 8 j .. 8 j + 7 read job j's coefficients 8 at a time
+    {
+        const int j = lane >> 3;
+        const float2 *src = a.src + soff[j];
+#pragma unroll 4
+        for (int e = lane & 7; e < P2; e += 8) {
+            int n = (int)sqrtf((float)e);
+            n -= n * n > e;
+            n += (n + 1) * (n + 1) <= e;
+            const int m = e - n * n - n;
+            const float2 x = src[e], ph = phg[1][j][m + P - 1];
+            Xs[e][2 * j] = ph.x * x.x - ph.y * x.y;
+            Xs[e][2 * j + 1] = ph.x * x.y + ph.y * x.x;
+        }
+    }
+    tq_for<4>([&](auto nI) { tq_load_rot<decltype(nI)::value>(AF[decltype(nI)::value], FF); });
+    __syncthreads();  // Xs, sgend
+    const int end2 = 2 * sgend[jl];
+    const bool starts = segl[jl] > 0;
+    const float rm2 = col + 2 < end2 ? 1.0f : 0.0f, rm4 = col + 4 < end2 ? 1.0f : 0.0f, rm8 = col + 8 < end2 ? 1.0f : 0.0f;
+    // rotation of degree n on the rows of Xs, in place
+    auto rotate = [&](auto nI, const float (&A)[16]) {
+        constexpr int n = decltype(nI)::value, KS = tq_dreg(n), RB = (2 * n + 16) / 16, w = 2 * n + 1;
+        float B[KS];
+        tq_for<KS>([&](auto iI) {
+            constexpr int i = decltype(iI)::value;
+            B[i] = 4 * i + g < w ? Xs[n * n + 4 * i + g][col] : 0.0f;
+        });
+        v4 acc[RB];
+        tq_for<RB>([&](auto bI) { acc[decltype(bI)::value] = v4{0, 0, 0, 0}; });
+        tq_for<KS>([&](auto iI) {
+            tq_for<RB>([&](auto bI) {
+                constexpr int b = decltype(bI)::value, i = decltype(iI)::value;
+                acc[b] = TmOp<float>::mma(A[b * 8 + i], B[i], acc[b]);
+            });
+        });
+        return [=](auto &&sink) {
+            tq_for<RB>([&](auto bI) {
+                constexpr int b = decltype(bI)::value;
+                tq_for<4>([&](auto iI) {
+                    constexpr int i = decltype(iI)::value;
+                    sink(16 * b + 4 * g + i, acc[b][i]);
+                });
+            });
+        };
+    };
+    // forward rotation, degree by degree: Y_n = H_n X_n
+    tq_for<P>([&](auto nI) {
+        constexpr int n = decltype(nI)::value, w = 2 * n + 1;
+        if constexpr (n >= 3 && n + 1 < P) tq_load_rot<n + 1>(AF[n + 1], FF);
+        if constexpr (n == P - 1) {
+            tq_for<2>([&](auto aI) {
+                constexpr int am = decltype(aI)::value;
+                tq_for<tq_oreg(am)>([&](auto iI) {
+                    constexpr int i = decltype(iI)::value;
+                    TF[am][2 * i] = FC[((am * 4 + i) * 2) * 64];
+                    TF[am][2 * i + 1] = FC[((am * 4 + i) * 2 + 1) * 64];
+                });
+            });
+        }
+        rotate(nI, AF[n])([&](int r, float v) {
+            if (r < w) Xs[n * n + r][col] = v;
+        });
+    });
+    // coaxial step, order by order (one table block for +-|m|)
+    {
+        const float swp = im ? 1.0f : -1.0f;
+        tq_for<P>([&](auto aI) {
+            constexpr int am = decltype(aI)::value, KS = tq_oreg(am), rows = P - am;
+            if constexpr (am + 2 < P) {
+                tq_for<tq_oreg(am + 2)>([&](auto iI) {
+                    constexpr int i = decltype(iI)::value;
+                    TF[am + 2][2 * i] = FC[(((am + 2) * 4 + i) * 2) * 64];
+                    TF[am + 2][2 * i + 1] = FC[(((am + 2) * 4 + i) * 2 + 1) * 64];
+                });
+            }
+            if constexpr (am == P - 3) tq_load_rot<P - 1>(AF[P - 1], FB);
+            tq_for<(am > 0 ? 2 : 1)>([&](auto sgI) {
+                constexpr int m = decltype(sgI)::value == 0 ? am : -am;
+                float B[KS], Bw[KS];
+                tq_for<KS>([&](auto iI) {
+                    constexpr int i = decltype(iI)::value;
+                    const int k = 4 * i + g, nn = am + k, row = nn * nn + nn + m;
+                    // X': column 2j holds -Im x_j, column 2j+1 holds Re x_j (the partner column)
+                    B[i] = k < rows ? Xs[row][col] : 0.0f;
+                    Bw[i] = k < rows ? swp * Xs[row][col ^ 1] : 0.0f;
+                });
+                v4 acc = v4{0, 0, 0, 0};
+                tq_for<KS>([&](auto iI) {
+                    constexpr int i = decltype(iI)::value;
+                    acc = TmOp<float>::mma(TF[am][2 * i], B[i], acc);
+                    acc = TmOp<float>::mma(TF[am][2 * i + 1], Bw[i], acc);
+                });
+                tq_for<4>([&](auto iI) {
+                    constexpr int i = decltype(iI)::value;
+                    const int r = 4 * g + i, nn = am + r;
+                    if (r < rows) Xs[nn * nn + nn + m][col] = acc[i];
+                });
+            });
+        });
+    }
+    // back rotation, degree by degree from the largest: H_n^T, then e^{-i m a} and the run sums of
+    // one target; the runs' first jobs store their rows (job-major, for the per-target reduction)
+    float *const orow = (float *)(a.W1 + (J0 + jl) * (int64_t)P2) + im;
+    tq_for<P>([&](auto dI) {
+        constexpr int n = P - 1 - decltype(dI)::value, w = 2 * n + 1;
+        if constexpr (n - 1 >= 7) tq_load_rot<n - 1>(AF[n - 1], FB);
+        if constexpr (n == 8) tq_for<7>([&](auto kI) { tq_load_rot<decltype(kI)::value>(AF[decltype(kI)::value], FB); });
+        rotate(std::integral_constant<int, n>{}, AF[n])([&](int r, float x) {
+            const float y = tq_swap_pair32(x);
+            const float2 e = phg[1 - im][jl][min(r, 2 * n) - n + P - 1];  // conj(e)
+            float v = fmaf(e.x, x, e.y * y);
+            v = fmaf(tq_dpp_shl32(v, 2), rm2, v);
+            v = fmaf(tq_dpp_shl32(v, 4), rm4, v);
+            v = fmaf(tq_dpp_shl32(v, 8), rm8, v);
+            if (starts && r < w) orow[2 * (n * n + r)] = v;
+        });
+    });
+}
+
 static_assert(TF_FR_STEP == 2 * 8 * 2 * 64 && TF_FR_ROT == (TF_PMAX / 2) * TF_FR_STEP, "rotation fragment layout");
 static_assert(TF_FR_ORDER == 4 * 2 * 64 && TF_FR_COAX == TF_PMAX * TF_FR_ORDER, "coaxial fragment layout");
 
@@ -1903,9 +2082,22 @@ const char *trans_stage(const TransBatch &b, const TransTables<R> &tb, int stage
             return b.mfma == 3 ? "k_tq_rcr" : "k_tq_rcr_o2";
         }
     }
+    if constexpr (sizeof(R) == 4) {
+        if (b.lane && b.mfma >= 3 && stage < 3 && nr == 1 && b.P == TQ_P) {
+            // register-resident shape in FP32 (mixed products, one vector): vectors in LDS
+            if (b.JT != LANE_JT || b.psrc != b.ptgt || b.PT != b.P)
+                throw FmmError(-1, "register-resident translation tiles need 64-job tiles and p_src = p_tgt = 16");
+            if (!tb.frH || !tb.frHT || !tb.frC)
+                throw FmmError(-1, "fused translation tiles need their fragment-order tables");
+            if (stage != 0) return nullptr;
+            k_tq_rcr32<<<dim3(ntile, LANE_JT / 8), 64, 0, st>>>(a);
+            LAUNCH_OK();
+            return "k_tq_rcr32";
+        }
+    }
     if (b.lane && b.mfma >= 2 && stage < 3) {
-        // the fused LDS-resident kernel (and the register-resident shape in FP32 or with several
-        // vectors, where it takes its place)
+        // the fused LDS-resident kernel (and the register-resident shape with several vectors,
+        // where it takes its place)
         // the fused kernel takes the three stages at stage 0
         // a run of one target (at most SEG_ALIGN real jobs, aligned) lies in one workgroup's jobs
         if (b.JT != LANE_JT || b.psrc != b.ptgt || b.PT != b.P || b.P > TF_PMAX || 32 / nr < SEG_ALIGN)
