@@ -10,11 +10,14 @@ BUILD = os.path.join(HERE, "_build")
 SOURCES = ["api.cpp", "tree.cpp", "tables.hip", "fmm.hip", "trans.hip", "solver.hip", "learned.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# translation tiles: matrix-core results written to ordinary vector registers (no copies out of the
+# accumulation registers before their LDS stores; 1M L-room mixed product 7.51 -> 7.34 ms)
+EXTRA = {"trans.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def _compile(src):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = ["hipcc", *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = ["hipcc", *FLAGS, *EXTRA.get(src, []), "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")

@@ -1769,33 +1769,23 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, OC
 // chunk i in lane group g), the partner column (the other part of a job) included, and writes its
 // outputs back in place (rows 4 g + i of a 16-row block in lane group g, the FP32 output layout), so
 // the changes between degree and order order are only addresses.  FP32 matrix instructions overlap
-// the vector work.  Phases, run sums and stores as in k_tq_rcr; tables: the FP32 fragment-order
-// tables of the fused tiles.
-__device__ __forceinline__ float tq_swap_pair32(float v) {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
-}
-__device__ __forceinline__ float tq_dpp_shl32(float v, int d) {
-    const int x = __float_as_int(v);
-    switch (d) {  // row_shl:2 / 4 / 8 (lane i takes lane i + d of its row of 16; 0 past the row)
-    case 2: return __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x102, 0xF, 0xF, true));
-    case 4: return __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x104, 0xF, 0xF, true));
-    default: return __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x108, 0xF, 0xF, true));
-    }
-}
+// the vector work.  The phases of the sources and, after the back rotation, the conjugate phases
+// and the sums over each target's run are taken with each lane owning coefficients (both parts of
+// a job read from LDS at once): no partner-column moves, and only the runs' first jobs do the sums.
+// Tables: the FP32 fragment-order tables of the fused tiles.
 
 __global__ void __launch_bounds__(64) k_tq_rcr32(TransArgsT<float> a) {
     using v4 = TmOp<float>::v4;
     constexpr int P = TQ_P, P2 = P * P, NPH = 2 * P - 1;
     __shared__ float Xs[P2][16];      // coefficient (n, m) at row n^2 + n + m, column 2 job + part
-    __shared__ float2 phg[2][8][NPH];  // e^{i m a_j} with the imaginary part negated ([0]) or not ([1])
+    __shared__ float2 phg[8][NPH];  // e^{i m a_j}
     __shared__ int64_t soff[8];
-    __shared__ int sgend[8];
     __shared__ int segl[8];
     int tile, part;
     xcd_block(tile, part);
     const int64_t J0 = (int64_t)tile * LANE_JT + part * 8;
     if (J0 >= a.njob) return;  // the whole workgroup (one wavefront)
-    const int lane = threadIdx.x, g = lane >> 4, col = lane & 15, jl = col >> 1, im = col & 1;
+    const int lane = threadIdx.x, g = lane >> 4, col = lane & 15, im = col & 1;
     const int phs = 2 * a.PH + 1;
     if (lane < 8) {
         const int64_t Jv = J0 + lane, Jc = Jv < a.njob ? Jv : a.njob - 1;
@@ -1806,42 +1796,38 @@ __global__ void __launch_bounds__(64) k_tq_rcr32(TransArgsT<float> a) {
         const int j = e / NPH, q = e - j * NPH;
         const int64_t Jv = J0 + j, Jc = Jv < a.njob ? Jv : a.njob - 1;
         const float2 ph = a.ph[(int64_t)a.jdir[Jc] * phs + a.PH - (P - 1) + q];
-        phg[1][j][q] = ph;
-        phg[0][j][q] = make_float2(ph.x, -ph.y);
+        phg[j][q] = ph;
     }
     __syncthreads();
-    if (lane < 8) {
-        // run of job `lane`: it starts at the nearest start at or before it (runs are contiguous)
-        int st = lane;
-        while (st > 0 && segl[st] == 0) --st;
-        sgend[lane] = segl[st] > 0 ? st + segl[st] : lane + 1;
-    }
     const int tr = a.tile_rot[tile], tc = a.tile_coax[tile];
     const float *FF = a.frHT + (int64_t)tr * TF_FR_ROT + lane;  // forward: H (from HT's fragments)
     const float *FB = a.frH + (int64_t)tr * TF_FR_ROT + lane;   // back: H^T
     const float *FC = a.frC + (int64_t)tc * TF_FR_COAX + lane;
     float AF[P][16];  // rotation fragments per degree (only the live ones take registers)
     float TF[P][8];   // coaxial fragments per order |m|: 4 K chunks x (re, im)
-    // sources times e^{i m a}: lanes 8 j .. 8 j + 7 read job j's coefficients 8 at a time
-    {
-        const int j = lane >> 3;
+    // lane l owns coefficients e = l + 64 u (u < 4) in the first and last steps; their orders m
+    int mo[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int e = lane + 64 * u;
+        int n = (int)sqrtf((float)e);
+        n -= n * n > e;
+        n += (n + 1) * (n + 1) <= e;
+        mo[u] = e - n * n - n;
+    }
+    // sources times e^{i m a}, one job after the other (64 consecutive coefficients per load)
+#pragma unroll 2
+    for (int j = 0; j < 8; ++j) {
         const float2 *src = a.src + soff[j];
-#pragma unroll 4
-        for (int e = lane & 7; e < P2; e += 8) {
-            int n = (int)sqrtf((float)e);
-            n -= n * n > e;
-            n += (n + 1) * (n + 1) <= e;
-            const int m = e - n * n - n;
-            const float2 x = src[e], ph = phg[1][j][m + P - 1];
-            Xs[e][2 * j] = ph.x * x.x - ph.y * x.y;
-            Xs[e][2 * j + 1] = ph.x * x.y + ph.y * x.x;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = lane + 64 * u;
+            const float2 x = src[e], ph = phg[j][mo[u] + P - 1];
+            *(float2 *)&Xs[e][2 * j] = make_float2(ph.x * x.x - ph.y * x.y, ph.x * x.y + ph.y * x.x);
         }
     }
     tq_for<4>([&](auto nI) { tq_load_rot<decltype(nI)::value>(AF[decltype(nI)::value], FF); });
-    __syncthreads();  // Xs, sgend
-    const int end2 = 2 * sgend[jl];
-    const bool starts = segl[jl] > 0;
-    const float rm2 = col + 2 < end2 ? 1.0f : 0.0f, rm4 = col + 4 < end2 ? 1.0f : 0.0f, rm8 = col + 8 < end2 ? 1.0f : 0.0f;
+    __syncthreads();  // Xs
     // rotation of degree n on the rows of Xs, in place
     auto rotate = [&](auto nI, const float (&A)[16]) {
         constexpr int n = decltype(nI)::value, KS = tq_dreg(n), RB = (2 * n + 16) / 16, w = 2 * n + 1;
@@ -1923,23 +1909,34 @@ __global__ void __launch_bounds__(64) k_tq_rcr32(TransArgsT<float> a) {
             });
         });
     }
-    // back rotation, degree by degree from the largest: H_n^T, then e^{-i m a} and the run sums of
-    // one target; the runs' first jobs store their rows (job-major, for the per-target reduction)
-    float *const orow = (float *)(a.W1 + (J0 + jl) * (int64_t)P2) + im;
+    // back rotation, degree by degree from the largest: H_n^T, in place
     tq_for<P>([&](auto dI) {
         constexpr int n = P - 1 - decltype(dI)::value, w = 2 * n + 1;
         if constexpr (n - 1 >= 7) tq_load_rot<n - 1>(AF[n - 1], FB);
         if constexpr (n == 8) tq_for<7>([&](auto kI) { tq_load_rot<decltype(kI)::value>(AF[decltype(kI)::value], FB); });
-        rotate(std::integral_constant<int, n>{}, AF[n])([&](int r, float x) {
-            const float y = tq_swap_pair32(x);
-            const float2 e = phg[1 - im][jl][min(r, 2 * n) - n + P - 1];  // conj(e)
-            float v = fmaf(e.x, x, e.y * y);
-            v = fmaf(tq_dpp_shl32(v, 2), rm2, v);
-            v = fmaf(tq_dpp_shl32(v, 4), rm4, v);
-            v = fmaf(tq_dpp_shl32(v, 8), rm8, v);
-            if (starts && r < w) orow[2 * (n * n + r)] = v;
+        rotate(std::integral_constant<int, n>{}, AF[n])([&](int r, float v) {
+            if (r < w) Xs[n * n + r][col] = v;
         });
     });
+    // e^{-i m a} and the sums over the runs of one target: each run's first job stores its row
+    // (job-major, for the per-target reduction), lane l the coefficients l + 64 u
+#pragma unroll 1
+    for (int j = 0; j < 8; ++j) {
+        const int len = segl[j];
+        if (len == 0) continue;  // uniform: not a run's first job
+        float2 *orow = a.W1 + (J0 + j) * (int64_t)P2;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = lane + 64 * u;
+            float2 s = make_float2(0.0f, 0.0f);
+            for (int t = 0; t < len; ++t) {
+                const float2 x = *(const float2 *)&Xs[e][2 * (j + t)], ph = phg[j + t][mo[u] + P - 1];
+                s.x += ph.x * x.x + ph.y * x.y;  // conj(e) x
+                s.y += ph.x * x.y - ph.y * x.x;
+            }
+            orow[e] = s;
+        }
+    }
 }
 
 static_assert(TF_FR_STEP == 2 * 8 * 2 * 64 && TF_FR_ROT == (TF_PMAX / 2) * TF_FR_STEP, "rotation fragment layout");
