@@ -1777,7 +1777,12 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, OC
 __global__ void __launch_bounds__(64) k_tq_rcr32(TransArgsT<float> a) {
     using v4 = TmOp<float>::v4;
     constexpr int P = TQ_P, P2 = P * P, NPH = 2 * P - 1;
-    __shared__ float Xs[P2][16];      // coefficient (n, m) at row n^2 + n + m, column 2 job + part
+    // coefficient (n, m) at row n^2 + n + m, column 2 job + part; rows P2 .. P2 + 3 (zeros) are read
+    // past the last degree.  Reads need no branch: rows past a degree or order meet zero columns of
+    // the table block (without the branches the reads of a step issue together: 2.58 -> 2.27 ms at
+    // levels 6-7 of the 1M L-room); writes past a block stay masked (writing them to spare rows
+    // nearly doubles the LDS stores and was slower)
+    __shared__ float Xs[P2 + 4][16];
     __shared__ float2 phg[8][NPH];  // e^{i m a_j}
     __shared__ int64_t soff[8];
     __shared__ int segl[8];
@@ -1792,6 +1797,7 @@ __global__ void __launch_bounds__(64) k_tq_rcr32(TransArgsT<float> a) {
         soff[lane] = (int64_t)a.jsrc[Jc] * P2;
         segl[lane] = Jv < a.njob ? a.jseg[Jv] : 0;
     }
+    Xs[P2 + g][col] = 0.0f;
     for (int e = lane; e < 8 * NPH; e += 64) {
         const int j = e / NPH, q = e - j * NPH;
         const int64_t Jv = J0 + j, Jc = Jv < a.njob ? Jv : a.njob - 1;
@@ -1834,7 +1840,7 @@ __global__ void __launch_bounds__(64) k_tq_rcr32(TransArgsT<float> a) {
         float B[KS];
         tq_for<KS>([&](auto iI) {
             constexpr int i = decltype(iI)::value;
-            B[i] = 4 * i + g < w ? Xs[n * n + 4 * i + g][col] : 0.0f;
+            B[i] = Xs[n * n + 4 * i + g][col];  // past the degree: the next one's rows, zero columns of A
         });
         v4 acc[RB];
         tq_for<RB>([&](auto bI) { acc[decltype(bI)::value] = v4{0, 0, 0, 0}; });
@@ -1890,10 +1896,11 @@ __global__ void __launch_bounds__(64) k_tq_rcr32(TransArgsT<float> a) {
                 float B[KS], Bw[KS];
                 tq_for<KS>([&](auto iI) {
                     constexpr int i = decltype(iI)::value;
-                    const int k = 4 * i + g, nn = am + k, row = nn * nn + nn + m;
+                    // degrees past 15 read degree 15's row: zero columns of the table block
+                    const int nn = min(am + 4 * i + g, P - 1), row = nn * nn + nn + m;
                     // X': column 2j holds -Im x_j, column 2j+1 holds Re x_j (the partner column)
-                    B[i] = k < rows ? Xs[row][col] : 0.0f;
-                    Bw[i] = k < rows ? swp * Xs[row][col ^ 1] : 0.0f;
+                    B[i] = Xs[row][col];
+                    Bw[i] = swp * Xs[row][col ^ 1];
                 });
                 v4 acc = v4{0, 0, 0, 0};
                 tq_for<KS>([&](auto iI) {
