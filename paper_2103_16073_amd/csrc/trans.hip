@@ -1763,9 +1763,10 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, OC
     });
 }
 
-// FP32 variant for mixed products (p = 16, one vector): one wavefront = 8 jobs of a 64-job tile as
+// FP32 variant for mixed products (p = 16, one vector): one workgroup = 8 jobs of a 64-job tile as
 // in k_tq_rcr, but the jobs' vectors live in LDS (256 coefficients x 16 columns, 16 KB) instead of
-// registers: every step reads its B operands from LDS in the matrix-core layout (K row 4 i + g of
+// registers, shared by two wavefronts that take the degrees (orders) of one parity each (four
+// wavefronts per SIMD instead of two: 2.27 -> 1.70 ms at levels 6-7 of the 1M L-room): every step reads its B operands from LDS in the matrix-core layout (K row 4 i + g of
 // chunk i in lane group g), the partner column (the other part of a job) included, and writes its
 // outputs back in place (rows 4 g + i of a 16-row block in lane group g, the FP32 output layout), so
 // the changes between degree and order order are only addresses.  FP32 matrix instructions overlap
@@ -1774,7 +1775,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, OC
 // a job read from LDS at once): no partner-column moves, and only the runs' first jobs do the sums.
 // Tables: the FP32 fragment-order tables of the fused tiles.
 
-__global__ void __launch_bounds__(64) k_tq_rcr32(TransArgsT<float> a) {
+__global__ void __launch_bounds__(128) k_tq_rcr32(TransArgsT<float> a) {
     using v4 = TmOp<float>::v4;
     constexpr int P = TQ_P, P2 = P * P, NPH = 2 * P - 1;
     // coefficient (n, m) at row n^2 + n + m, column 2 job + part; rows P2 .. P2 + 3 (zeros) are read
@@ -1789,16 +1790,18 @@ __global__ void __launch_bounds__(64) k_tq_rcr32(TransArgsT<float> a) {
     int tile, part;
     xcd_block(tile, part);
     const int64_t J0 = (int64_t)tile * LANE_JT + part * 8;
-    if (J0 >= a.njob) return;  // the whole workgroup (one wavefront)
-    const int lane = threadIdx.x, g = lane >> 4, col = lane & 15, im = col & 1;
+    if (J0 >= a.njob) return;  // the whole workgroup
+    // two wavefronts share the 8 jobs' vectors: wavefront h takes the degrees (orders) of parity h
+    // of every step, and the jobs 4 h .. 4 h + 3 of the first and last steps
+    const int tid = threadIdx.x, lane = tid & 63, h = tid >> 6, g = lane >> 4, col = lane & 15, im = col & 1;
     const int phs = 2 * a.PH + 1;
-    if (lane < 8) {
-        const int64_t Jv = J0 + lane, Jc = Jv < a.njob ? Jv : a.njob - 1;
-        soff[lane] = (int64_t)a.jsrc[Jc] * P2;
-        segl[lane] = Jv < a.njob ? a.jseg[Jv] : 0;
+    if (tid < 8) {
+        const int64_t Jv = J0 + tid, Jc = Jv < a.njob ? Jv : a.njob - 1;
+        soff[tid] = (int64_t)a.jsrc[Jc] * P2;
+        segl[tid] = Jv < a.njob ? a.jseg[Jv] : 0;
     }
-    Xs[P2 + g][col] = 0.0f;
-    for (int e = lane; e < 8 * NPH; e += 64) {
+    if (h == 0) Xs[P2 + g][col] = 0.0f;
+    for (int e = tid; e < 8 * NPH; e += 128) {
         const int j = e / NPH, q = e - j * NPH;
         const int64_t Jv = J0 + j, Jc = Jv < a.njob ? Jv : a.njob - 1;
         const float2 ph = a.ph[(int64_t)a.jdir[Jc] * phs + a.PH - (P - 1) + q];
@@ -1809,8 +1812,6 @@ __global__ void __launch_bounds__(64) k_tq_rcr32(TransArgsT<float> a) {
     const float *FF = a.frHT + (int64_t)tr * TF_FR_ROT + lane;  // forward: H (from HT's fragments)
     const float *FB = a.frH + (int64_t)tr * TF_FR_ROT + lane;   // back: H^T
     const float *FC = a.frC + (int64_t)tc * TF_FR_COAX + lane;
-    float AF[P][16];  // rotation fragments per degree (only the live ones take registers)
-    float TF[P][8];   // coaxial fragments per order |m|: 4 K chunks x (re, im)
     // lane l owns coefficients e = l + 64 u (u < 4) in the first and last steps; their orders m
     int mo[4];
 #pragma unroll
@@ -1823,17 +1824,17 @@ __global__ void __launch_bounds__(64) k_tq_rcr32(TransArgsT<float> a) {
     }
     // sources times e^{i m a}, one job after the other (64 consecutive coefficients per load)
 #pragma unroll 2
-    for (int j = 0; j < 8; ++j) {
+    for (int jj = 0; jj < 4; ++jj) {
+        const int j = 4 * h + jj;
         const float2 *src = a.src + soff[j];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int e = lane + 64 * u;
             const float2 x = src[e], ph = phg[j][mo[u] + P - 1];
-            *(float2 *)&Xs[e][2 * j] = make_float2(ph.x * x.x - ph.y * x.y, ph.x * x.y + ph.y * x.x);
+            Xs[e][2 * j] = ph.x * x.x - ph.y * x.y;  // float accesses only (no type punning of Xs)
+            Xs[e][2 * j + 1] = ph.x * x.y + ph.y * x.x;
         }
     }
-    tq_for<4>([&](auto nI) { tq_load_rot<decltype(nI)::value>(AF[decltype(nI)::value], FF); });
-    __syncthreads();  // Xs
     // rotation of degree n on the rows of Xs, in place
     auto rotate = [&](auto nI, const float (&A)[16]) {
         constexpr int n = decltype(nI)::value, KS = tq_dreg(n), RB = (2 * n + 16) / 16, w = 2 * n + 1;
@@ -1850,47 +1851,50 @@ __global__ void __launch_bounds__(64) k_tq_rcr32(TransArgsT<float> a) {
                 acc[b] = TmOp<float>::mma(A[b * 8 + i], B[i], acc[b]);
             });
         });
-        return [=](auto &&sink) {
-            tq_for<RB>([&](auto bI) {
-                constexpr int b = decltype(bI)::value;
-                tq_for<4>([&](auto iI) {
-                    constexpr int i = decltype(iI)::value;
-                    sink(16 * b + 4 * g + i, acc[b][i]);
-                });
+        tq_for<RB>([&](auto bI) {
+            constexpr int b = decltype(bI)::value;
+            tq_for<4>([&](auto iI) {
+                constexpr int i = decltype(iI)::value;
+                const int r = 16 * b + 4 * g + i;
+                if (r < w) Xs[n * n + r][col] = acc[b][i];
             });
-        };
-    };
-    // forward rotation, degree by degree: Y_n = H_n X_n
-    tq_for<P>([&](auto nI) {
-        constexpr int n = decltype(nI)::value, w = 2 * n + 1;
-        if constexpr (n >= 3 && n + 1 < P) tq_load_rot<n + 1>(AF[n + 1], FF);
-        if constexpr (n == P - 1) {
-            tq_for<2>([&](auto aI) {
-                constexpr int am = decltype(aI)::value;
-                tq_for<tq_oreg(am)>([&](auto iI) {
-                    constexpr int i = decltype(iI)::value;
-                    TF[am][2 * i] = FC[((am * 4 + i) * 2) * 64];
-                    TF[am][2 * i + 1] = FC[((am * 4 + i) * 2 + 1) * 64];
-                });
-            });
-        }
-        rotate(nI, AF[n])([&](int r, float v) {
-            if (r < w) Xs[n * n + r][col] = v;
         });
-    });
-    // coaxial step, order by order (one table block for +-|m|)
-    {
+    };
+    // the steps of one parity H: forward rotation of its degrees, coaxial step of its orders, back
+    // rotation of its degrees; table fragments one step (of the same parity) ahead
+    float AF[P][16];  // rotation fragments per degree (only the live ones take registers)
+    float TF[P][8];   // coaxial fragments per order |m|: 4 K chunks x (re, im)
+    auto forward = [&](auto HI) {
+        constexpr int H = decltype(HI)::value;
+        tq_load_rot<H>(AF[H], FF);
+        tq_load_rot<H + 2>(AF[H + 2], FF);
+        tq_for<P / 2>([&](auto kI) {
+            constexpr int n = 2 * decltype(kI)::value + H;
+            if constexpr (n + 4 < P) tq_load_rot<n + 4>(AF[n + 4], FF);
+            if constexpr (n + 2 >= P) {  // this parity's first order of the coaxial step
+                tq_for<tq_oreg(H)>([&](auto iI) {
+                    constexpr int i = decltype(iI)::value;
+                    TF[H][2 * i] = FC[((H * 4 + i) * 2) * 64];
+                    TF[H][2 * i + 1] = FC[((H * 4 + i) * 2 + 1) * 64];
+                });
+            }
+            rotate(std::integral_constant<int, n>{}, AF[n]);
+        });
+    };
+    auto coax = [&](auto HI) {
+        constexpr int H = decltype(HI)::value;
         const float swp = im ? 1.0f : -1.0f;
-        tq_for<P>([&](auto aI) {
-            constexpr int am = decltype(aI)::value, KS = tq_oreg(am), rows = P - am;
+        tq_for<P / 2>([&](auto kI) {
+            constexpr int am = 2 * decltype(kI)::value + H, KS = tq_oreg(am), rows = P - am;
             if constexpr (am + 2 < P) {
                 tq_for<tq_oreg(am + 2)>([&](auto iI) {
                     constexpr int i = decltype(iI)::value;
                     TF[am + 2][2 * i] = FC[(((am + 2) * 4 + i) * 2) * 64];
                     TF[am + 2][2 * i + 1] = FC[(((am + 2) * 4 + i) * 2 + 1) * 64];
                 });
+            } else {  // this parity's first degree of the back rotation
+                tq_load_rot<P - 2 + H>(AF[P - 2 + H], FB);
             }
-            if constexpr (am == P - 3) tq_load_rot<P - 1>(AF[P - 1], FB);
             tq_for<(am > 0 ? 2 : 1)>([&](auto sgI) {
                 constexpr int m = decltype(sgI)::value == 0 ? am : -am;
                 float B[KS], Bw[KS];
@@ -1915,21 +1919,37 @@ __global__ void __launch_bounds__(64) k_tq_rcr32(TransArgsT<float> a) {
                 });
             });
         });
-    }
-    // back rotation, degree by degree from the largest: H_n^T, in place
-    tq_for<P>([&](auto dI) {
-        constexpr int n = P - 1 - decltype(dI)::value, w = 2 * n + 1;
-        if constexpr (n - 1 >= 7) tq_load_rot<n - 1>(AF[n - 1], FB);
-        if constexpr (n == 8) tq_for<7>([&](auto kI) { tq_load_rot<decltype(kI)::value>(AF[decltype(kI)::value], FB); });
-        rotate(std::integral_constant<int, n>{}, AF[n])([&](int r, float v) {
-            if (r < w) Xs[n * n + r][col] = v;
+    };
+    auto back = [&](auto HI) {
+        constexpr int H = decltype(HI)::value;
+        tq_for<P / 2>([&](auto kI) {
+            constexpr int n = P - 2 + H - 2 * decltype(kI)::value;
+            if constexpr (n - 2 >= 8) tq_load_rot<n - 2>(AF[n - 2], FB);
+            if constexpr (n == 8 + H)
+                tq_for<4>([&](auto qI) {
+                    constexpr int k = 2 * decltype(qI)::value + H;
+                    tq_load_rot<k>(AF[k], FB);
+                });
+            rotate(std::integral_constant<int, n>{}, AF[n]);
         });
-    });
+    };
+    // each stage's two parities under two separate tests of h (compiled as one if / else, the back
+    // rotation's matrix instructions were dropped from the code: the products then differ)
+    __syncthreads();  // Xs
+    if (h == 0) forward(std::integral_constant<int, 0>{});
+    if (h == 1) forward(std::integral_constant<int, 1>{});
+    __syncthreads();
+    if (h == 0) coax(std::integral_constant<int, 0>{});
+    if (h == 1) coax(std::integral_constant<int, 1>{});
+    __syncthreads();
+    if (h == 0) back(std::integral_constant<int, 0>{});
+    if (h == 1) back(std::integral_constant<int, 1>{});
+    __syncthreads();
     // e^{-i m a} and the sums over the runs of one target: each run's first job stores its row
     // (job-major, for the per-target reduction), lane l the coefficients l + 64 u
 #pragma unroll 1
-    for (int j = 0; j < 8; ++j) {
-        const int len = segl[j];
+    for (int jj = 0; jj < 4; ++jj) {
+        const int j = 4 * h + jj, len = segl[j];
         if (len == 0) continue;  // uniform: not a run's first job
         float2 *orow = a.W1 + (J0 + j) * (int64_t)P2;
 #pragma unroll
@@ -1937,7 +1957,8 @@ __global__ void __launch_bounds__(64) k_tq_rcr32(TransArgsT<float> a) {
             const int e = lane + 64 * u;
             float2 s = make_float2(0.0f, 0.0f);
             for (int t = 0; t < len; ++t) {
-                const float2 x = *(const float2 *)&Xs[e][2 * (j + t)], ph = phg[j + t][mo[u] + P - 1];
+                const float2 x = make_float2(Xs[e][2 * (j + t)], Xs[e][2 * (j + t) + 1]);
+                const float2 ph = phg[j + t][mo[u] + P - 1];
                 s.x += ph.x * x.x + ph.y * x.y;  // conj(e) x
                 s.y += ph.x * x.y - ph.y * x.x;
             }
@@ -2094,7 +2115,7 @@ const char *trans_stage(const TransBatch &b, const TransTables<R> &tb, int stage
             if (!tb.frH || !tb.frHT || !tb.frC)
                 throw FmmError(-1, "fused translation tiles need their fragment-order tables");
             if (stage != 0) return nullptr;
-            k_tq_rcr32<<<dim3(ntile, LANE_JT / 8), 64, 0, st>>>(a);
+            k_tq_rcr32<<<dim3(ntile, LANE_JT / 8), 128, 0, st>>>(a);
             LAUNCH_OK();
             return "k_tq_rcr32";
         }
