@@ -57,7 +57,7 @@ def measured_traffic(kernel, launches_per_product):
 
 
 # kernels whose arithmetic runs on the matrix cores (the others use the vector ALUs)
-MFMA_KERNELS = ("k_tq_rcr", "k_tf_trans", "k_tm_")
+MFMA_KERNELS = ("k_tq_rcr", "k_tq_lds", "k_tf_trans", "k_tm_")
 
 
 def kernel_roofline(st, steps, counted):

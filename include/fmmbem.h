@@ -130,12 +130,13 @@ typedef struct {
                             for every job-tile batch; 0 never; default 1 */
     int fused;           /* lane batches with p_src = p_tgt = p <= 16 may run all three stages in
                             one kernel on matrix cores: with the jobs' vectors resident in LDS
-                            (any such p), or, for FP64 products of one vector at p = 16, resident
-                            in the registers of the wavefront that transforms them (fixed rule at
-                            p = 16).  1: under the fixed rule and as autotuner candidates (timed in
-                            FP64), and in mixed-precision products for every such lane batch (the
-                            LDS-resident kernel, faster in FP32 wherever measured); 0 never;
-                            default 1 */
+                            (any such p; at p = 16 for products of one vector, 8 jobs' vectors
+                            shared by the wavefronts of a workgroup, fixed rule at p = 16), or,
+                            for FP64 products of one vector at p = 16, resident in the registers
+                            of the wavefront that transforms them.  1: under the fixed rule and
+                            as autotuner candidates (timed in FP64), and in mixed-precision
+                            products for every such lane batch (an LDS-resident kernel, faster
+                            in FP32 wherever measured); 0 never; default 1 */
     double kd_leaf_min;  /* lower bound on k times the leaf side: the octree stops refining before
                             its leaves get smaller than kd_leaf_min / k, because at small k tau the
                             singular coaxial tables lose their small entries to round-off (the
@@ -423,10 +424,12 @@ int fmmbem_near_entries(fmmbem_ctx *ctx, int64_t *nnz, int64_t *rows, int64_t *c
 /* Tile shape of every translation batch (from the fixed rule, or measured when the options
  * ask for autotuning): level, kind 0 = M2L at that level, 1 = M2M into it, 2 = L2L out of it,
  * one-job-per-lane flag, whole-vector flag, jobs per tile, matrix-core mode of a lane batch (0
- * lane kernels, 1 matrix-core tiles stage by stage, 2 the fused LDS-resident kernel, 3 and 4 the
- * fused register-resident kernel with registers for 1 or 2 wavefronts per SIMD; 3 and 4 apply to
- * FP64 products of one vector, other products of the batch run mode 2), and the measured FP64
- * time of the batch's four stages (0 when not measured). */
+ * lane kernels, 1 matrix-core tiles stage by stage, 2 the fused LDS-resident kernel of 16 or 32
+ * jobs per workgroup, 3 the fused kernel with each wavefront's 8 jobs' vectors in its registers
+ * (FP64 products of one vector), 4 the fused kernel with 8 jobs' vectors in LDS shared by four
+ * wavefronts; 3 and 4 apply to products of one vector at p = 16, other
+ * products of the batch run mode 2, and FP32 products run mode 4 for mode 3), and the measured
+ * FP64 time of the batch's four stages (0 when not measured). */
 typedef struct {
     int32_t level, kind, lane, whole, jt, mfma;
     int64_t jobs;

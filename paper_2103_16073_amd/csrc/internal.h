@@ -133,8 +133,8 @@ struct TransBatch {
     int whole = 0;                                      // whole-vector tiles (small p) or per-degree slices
     int lane = 0;                                       // one job per lane, 64-job tiles (many jobs per class)
     int mfma = 0;                                       // lane batch on matrix cores: 1 stage by stage, 2 fused in LDS
-                                                        // (p <= 16), 3 / 4 fused in registers (p = 16; held to 1 / 2
-                                                        // waves per SIMD)
+                                                        // (p <= 16), 3 fused in registers, 4 fused with 8 jobs'
+                                                        // vectors in LDS shared by 4 waves (p = 16)
     int64_t ntgt = 0;                                   // target boxes
     int32_t *tgt_start = nullptr, *tgt_jobs = nullptr;  // jobs of each target (CSR, padded job indices)
     // lane batches: consecutive jobs of one class with one target form a run (never crossing a

@@ -1763,36 +1763,44 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, OC
     });
 }
 
-// FP32 variant for mixed products (p = 16, one vector): one workgroup = 8 jobs of a 64-job tile as
-// in k_tq_rcr, but the jobs' vectors live in LDS (256 coefficients x 16 columns, 16 KB) instead of
-// registers, shared by two wavefronts that take the degrees (orders) of one parity each (four
-// wavefronts per SIMD instead of two: 2.27 -> 1.70 ms at levels 6-7 of the 1M L-room): every step reads its B operands from LDS in the matrix-core layout (K row 4 i + g of
-// chunk i in lane group g), the partner column (the other part of a job) included, and writes its
-// outputs back in place (rows 4 g + i of a 16-row block in lane group g, the FP32 output layout), so
-// the changes between degree and order order are only addresses.  FP32 matrix instructions overlap
-// the vector work.  The phases of the sources and, after the back rotation, the conjugate phases
-// and the sums over each target's run are taken with each lane owning coefficients (both parts of
-// a job read from LDS at once): no partner-column moves, and only the runs' first jobs do the sums.
-// Tables: the FP32 fragment-order tables of the fused tiles.
+// The same fused translation with the vectors in LDS (p = 16, one vector; FP64 and FP32): one
+// workgroup = 8 jobs of a 64-job tile as in k_tq_rcr, but the jobs' vectors live in LDS (256
+// coefficients x 16 columns: 33 KB in FP64, 16 KB in FP32) instead of registers, shared by NW
+// wavefronts that take the degrees (orders) n = h mod NW each.  Every step reads its B operands
+// from LDS in the matrix-core layout (K row 4 i + g of chunk i in lane group g), the partner column
+// (the other part of a job) included, and writes its outputs back in place in the output layout of
+// the instruction (rows g + 4 i in FP64, 4 g + i in FP32, of a 16-row block), so that the changes
+// between degree and order order are only addresses: no selects, no exchanges between lanes.  The
+// phases of the sources and, after the back rotation, the conjugate phases and the sums over each
+// target's run are taken with each lane owning coefficients (both parts of a job read from LDS at
+// once); only the runs' first jobs do the sums.  Tables: the fragment-order tables of the fused
+// tiles.  Measured at levels 6-7 of the 1M L-room: FP32 (mixed products) 2.77 ms with one
+// wavefront per workgroup and the partner moves of k_tq_rcr, 2.27 ms with lanes owning
+// coefficients in the first and last steps, 1.70 ms with two wavefronts, 1.71 -> 1.70 with four;
+// FP64 3.29 ms in registers (k_tq_rcr, two wavefronts per SIMD), 2.88 ms here with four.
 
-__global__ void __launch_bounds__(128) k_tq_rcr32(TransArgsT<float> a) {
-    using v4 = TmOp<float>::v4;
-    constexpr int P = TQ_P, P2 = P * P, NPH = 2 * P - 1;
+template <class R, int NW>
+__global__ void __launch_bounds__(64 * NW) k_tq_lds(TransArgsT<R> a) {
+    using C = typename Cx<R>::T;
+    using Op = TmOp<R>;
+    using v4 = typename Op::v4;
+    constexpr int P = TQ_P, P2 = P * P, NPH = 2 * P - 1, JW = 8 / NW;
+    static_assert(NW == 2 || NW == 4, "two or four wavefronts per workgroup");
     // coefficient (n, m) at row n^2 + n + m, column 2 job + part; rows P2 .. P2 + 3 (zeros) are read
     // past the last degree.  Reads need no branch: rows past a degree or order meet zero columns of
     // the table block (without the branches the reads of a step issue together: 2.58 -> 2.27 ms at
     // levels 6-7 of the 1M L-room); writes past a block stay masked (writing them to spare rows
     // nearly doubles the LDS stores and was slower)
-    __shared__ float Xs[P2 + 4][16];
-    __shared__ float2 phg[8][NPH];  // e^{i m a_j}
+    __shared__ R Xs[P2 + 4][16];
+    __shared__ C phg[8][NPH];  // e^{i m a_j}
     __shared__ int64_t soff[8];
     __shared__ int segl[8];
     int tile, part;
     xcd_block(tile, part);
     const int64_t J0 = (int64_t)tile * LANE_JT + part * 8;
     if (J0 >= a.njob) return;  // the whole workgroup
-    // two wavefronts share the 8 jobs' vectors: wavefront h takes the degrees (orders) of parity h
-    // of every step, and the jobs 4 h .. 4 h + 3 of the first and last steps
+    // NW wavefronts share the 8 jobs' vectors: wavefront h takes the degrees (orders) n = h mod NW of
+    // every step, and the jobs JW h .. JW h + JW - 1 of the first and last steps
     const int tid = threadIdx.x, lane = tid & 63, h = tid >> 6, g = lane >> 4, col = lane & 15, im = col & 1;
     const int phs = 2 * a.PH + 1;
     if (tid < 8) {
@@ -1800,18 +1808,17 @@ __global__ void __launch_bounds__(128) k_tq_rcr32(TransArgsT<float> a) {
         soff[tid] = (int64_t)a.jsrc[Jc] * P2;
         segl[tid] = Jv < a.njob ? a.jseg[Jv] : 0;
     }
-    if (h == 0) Xs[P2 + g][col] = 0.0f;
-    for (int e = tid; e < 8 * NPH; e += 128) {
+    if (h == 0) Xs[P2 + g][col] = R(0);
+    for (int e = tid; e < 8 * NPH; e += 64 * NW) {
         const int j = e / NPH, q = e - j * NPH;
         const int64_t Jv = J0 + j, Jc = Jv < a.njob ? Jv : a.njob - 1;
-        const float2 ph = a.ph[(int64_t)a.jdir[Jc] * phs + a.PH - (P - 1) + q];
-        phg[j][q] = ph;
+        phg[j][q] = a.ph[(int64_t)a.jdir[Jc] * phs + a.PH - (P - 1) + q];
     }
     __syncthreads();
     const int tr = a.tile_rot[tile], tc = a.tile_coax[tile];
-    const float *FF = a.frHT + (int64_t)tr * TF_FR_ROT + lane;  // forward: H (from HT's fragments)
-    const float *FB = a.frH + (int64_t)tr * TF_FR_ROT + lane;   // back: H^T
-    const float *FC = a.frC + (int64_t)tc * TF_FR_COAX + lane;
+    const R *FF = a.frHT + (int64_t)tr * TF_FR_ROT + lane;  // forward: H (from HT's fragments)
+    const R *FB = a.frH + (int64_t)tr * TF_FR_ROT + lane;   // back: H^T
+    const R *FC = a.frC + (int64_t)tc * TF_FR_COAX + lane;
     // lane l owns coefficients e = l + 64 u (u < 4) in the first and last steps; their orders m
     int mo[4];
 #pragma unroll
@@ -1823,22 +1830,22 @@ __global__ void __launch_bounds__(128) k_tq_rcr32(TransArgsT<float> a) {
         mo[u] = e - n * n - n;
     }
     // sources times e^{i m a}, one job after the other (64 consecutive coefficients per load)
-#pragma unroll 2
-    for (int jj = 0; jj < 4; ++jj) {
-        const int j = 4 * h + jj;
-        const float2 *src = a.src + soff[j];
+#pragma unroll
+    for (int jj = 0; jj < JW; ++jj) {
+        const int j = JW * h + jj;
+        const C *src = a.src + soff[j];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int e = lane + 64 * u;
-            const float2 x = src[e], ph = phg[j][mo[u] + P - 1];
-            Xs[e][2 * j] = ph.x * x.x - ph.y * x.y;  // float accesses only (no type punning of Xs)
+            const C x = src[e], ph = phg[j][mo[u] + P - 1];
+            Xs[e][2 * j] = ph.x * x.x - ph.y * x.y;  // scalar accesses only (no type punning of Xs)
             Xs[e][2 * j + 1] = ph.x * x.y + ph.y * x.x;
         }
     }
     // rotation of degree n on the rows of Xs, in place
-    auto rotate = [&](auto nI, const float (&A)[16]) {
+    auto rotate = [&](auto nI, const R (&A)[16]) {
         constexpr int n = decltype(nI)::value, KS = tq_dreg(n), RB = (2 * n + 16) / 16, w = 2 * n + 1;
-        float B[KS];
+        R B[KS];
         tq_for<KS>([&](auto iI) {
             constexpr int i = decltype(iI)::value;
             B[i] = Xs[n * n + 4 * i + g][col];  // past the degree: the next one's rows, zero columns of A
@@ -1848,30 +1855,32 @@ __global__ void __launch_bounds__(128) k_tq_rcr32(TransArgsT<float> a) {
         tq_for<KS>([&](auto iI) {
             tq_for<RB>([&](auto bI) {
                 constexpr int b = decltype(bI)::value, i = decltype(iI)::value;
-                acc[b] = TmOp<float>::mma(A[b * 8 + i], B[i], acc[b]);
+                acc[b] = Op::mma(A[b * 8 + i], B[i], acc[b]);
             });
         });
         tq_for<RB>([&](auto bI) {
             constexpr int b = decltype(bI)::value;
             tq_for<4>([&](auto iI) {
                 constexpr int i = decltype(iI)::value;
-                const int r = 16 * b + 4 * g + i;
+                const int r = 16 * b + Op::row(g, i);
                 if (r < w) Xs[n * n + r][col] = acc[b][i];
             });
         });
     };
-    // the steps of one parity H: forward rotation of its degrees, coaxial step of its orders, back
-    // rotation of its degrees; table fragments one step (of the same parity) ahead
-    float AF[P][16];  // rotation fragments per degree (only the live ones take registers)
-    float TF[P][8];   // coaxial fragments per order |m|: 4 K chunks x (re, im)
+    // the steps of one residue H (mod NW): forward rotation of its degrees, coaxial step of its
+    // orders, back rotation of its degrees; table fragments one step (of the same residue) ahead
+    R AF[P][16];  // rotation fragments per degree (only the live ones take registers)
+    R TF[P][8];   // coaxial fragments per order |m|: 4 K chunks x (re, im)
     auto forward = [&](auto HI) {
         constexpr int H = decltype(HI)::value;
-        tq_load_rot<H>(AF[H], FF);
-        tq_load_rot<H + 2>(AF[H + 2], FF);
-        tq_for<P / 2>([&](auto kI) {
-            constexpr int n = 2 * decltype(kI)::value + H;
+        tq_for<4 / NW>([&](auto qI) {
+            constexpr int n = H + NW * decltype(qI)::value;
+            tq_load_rot<n>(AF[n], FF);
+        });
+        tq_for<P / NW>([&](auto kI) {
+            constexpr int n = NW * decltype(kI)::value + H;
             if constexpr (n + 4 < P) tq_load_rot<n + 4>(AF[n + 4], FF);
-            if constexpr (n + 2 >= P) {  // this parity's first order of the coaxial step
+            if constexpr (n + NW >= P) {  // this residue's first order of the coaxial step
                 tq_for<tq_oreg(H)>([&](auto iI) {
                     constexpr int i = decltype(iI)::value;
                     TF[H][2 * i] = FC[((H * 4 + i) * 2) * 64];
@@ -1883,21 +1892,19 @@ __global__ void __launch_bounds__(128) k_tq_rcr32(TransArgsT<float> a) {
     };
     auto coax = [&](auto HI) {
         constexpr int H = decltype(HI)::value;
-        const float swp = im ? 1.0f : -1.0f;
-        tq_for<P / 2>([&](auto kI) {
-            constexpr int am = 2 * decltype(kI)::value + H, KS = tq_oreg(am), rows = P - am;
-            if constexpr (am + 2 < P) {
-                tq_for<tq_oreg(am + 2)>([&](auto iI) {
+        const R swp = im ? R(1) : R(-1);
+        tq_for<P / NW>([&](auto kI) {
+            constexpr int am = NW * decltype(kI)::value + H, KS = tq_oreg(am), rows = P - am;
+            if constexpr (am + NW < P) {
+                tq_for<tq_oreg(am + NW)>([&](auto iI) {
                     constexpr int i = decltype(iI)::value;
-                    TF[am + 2][2 * i] = FC[(((am + 2) * 4 + i) * 2) * 64];
-                    TF[am + 2][2 * i + 1] = FC[(((am + 2) * 4 + i) * 2 + 1) * 64];
+                    TF[am + NW][2 * i] = FC[(((am + NW) * 4 + i) * 2) * 64];
+                    TF[am + NW][2 * i + 1] = FC[(((am + NW) * 4 + i) * 2 + 1) * 64];
                 });
-            } else {  // this parity's first degree of the back rotation
-                tq_load_rot<P - 2 + H>(AF[P - 2 + H], FB);
             }
             tq_for<(am > 0 ? 2 : 1)>([&](auto sgI) {
                 constexpr int m = decltype(sgI)::value == 0 ? am : -am;
-                float B[KS], Bw[KS];
+                R B[KS], Bw[KS];
                 tq_for<KS>([&](auto iI) {
                     constexpr int i = decltype(iI)::value;
                     // degrees past 15 read degree 15's row: zero columns of the table block
@@ -1909,60 +1916,63 @@ __global__ void __launch_bounds__(128) k_tq_rcr32(TransArgsT<float> a) {
                 v4 acc = v4{0, 0, 0, 0};
                 tq_for<KS>([&](auto iI) {
                     constexpr int i = decltype(iI)::value;
-                    acc = TmOp<float>::mma(TF[am][2 * i], B[i], acc);
-                    acc = TmOp<float>::mma(TF[am][2 * i + 1], Bw[i], acc);
+                    acc = Op::mma(TF[am][2 * i], B[i], acc);
+                    acc = Op::mma(TF[am][2 * i + 1], Bw[i], acc);
                 });
                 tq_for<4>([&](auto iI) {
                     constexpr int i = decltype(iI)::value;
-                    const int r = 4 * g + i, nn = am + r;
+                    const int r = Op::row(g, i), nn = am + r;
                     if (r < rows) Xs[nn * nn + nn + m][col] = acc[i];
                 });
             });
         });
     };
     auto back = [&](auto HI) {
-        constexpr int H = decltype(HI)::value;
-        tq_for<P / 2>([&](auto kI) {
-            constexpr int n = P - 2 + H - 2 * decltype(kI)::value;
-            if constexpr (n - 2 >= 8) tq_load_rot<n - 2>(AF[n - 2], FB);
-            if constexpr (n == 8 + H)
-                tq_for<4>([&](auto qI) {
-                    constexpr int k = 2 * decltype(qI)::value + H;
+        constexpr int H = decltype(HI)::value, N0 = P - NW + H;  // this residue's largest degree
+        tq_load_rot<N0>(AF[N0], FB);
+        tq_for<P / NW>([&](auto kI) {
+            constexpr int n = N0 - NW * decltype(kI)::value;
+            if constexpr (n - NW >= 8) tq_load_rot<n - NW>(AF[n - NW], FB);
+            if constexpr (n >= 8 && n - NW < 8)  // the rest of this residue's degrees
+                tq_for<8 / NW>([&](auto qI) {
+                    constexpr int k = NW * decltype(qI)::value + H;
                     tq_load_rot<k>(AF[k], FB);
                 });
             rotate(std::integral_constant<int, n>{}, AF[n]);
         });
     };
-    // each stage's two parities under two separate tests of h (compiled as one if / else, the back
+    // each stage's residues under separate tests of h (compiled as one if / else chain, the back
     // rotation's matrix instructions were dropped from the code: the products then differ)
+    auto stage = [&](auto f) {
+        tq_for<NW>([&](auto HI) {
+            if (h == decltype(HI)::value) f(HI);
+        });
+    };
     __syncthreads();  // Xs
-    if (h == 0) forward(std::integral_constant<int, 0>{});
-    if (h == 1) forward(std::integral_constant<int, 1>{});
+    stage(forward);
     __syncthreads();
-    if (h == 0) coax(std::integral_constant<int, 0>{});
-    if (h == 1) coax(std::integral_constant<int, 1>{});
+    stage(coax);
     __syncthreads();
-    if (h == 0) back(std::integral_constant<int, 0>{});
-    if (h == 1) back(std::integral_constant<int, 1>{});
+    stage(back);
     __syncthreads();
     // e^{-i m a} and the sums over the runs of one target: each run's first job stores its row
     // (job-major, for the per-target reduction), lane l the coefficients l + 64 u
 #pragma unroll 1
-    for (int jj = 0; jj < 4; ++jj) {
-        const int j = 4 * h + jj, len = segl[j];
+    for (int jj = 0; jj < JW; ++jj) {
+        const int j = JW * h + jj, len = segl[j];
         if (len == 0) continue;  // uniform: not a run's first job
-        float2 *orow = a.W1 + (J0 + j) * (int64_t)P2;
+        C *orow = a.W1 + (J0 + j) * (int64_t)P2;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int e = lane + 64 * u;
-            float2 s = make_float2(0.0f, 0.0f);
+            R sx = R(0), sy = R(0);
             for (int t = 0; t < len; ++t) {
-                const float2 x = make_float2(Xs[e][2 * (j + t)], Xs[e][2 * (j + t) + 1]);
-                const float2 ph = phg[j + t][mo[u] + P - 1];
-                s.x += ph.x * x.x + ph.y * x.y;  // conj(e) x
-                s.y += ph.x * x.y - ph.y * x.x;
+                const R xr = Xs[e][2 * (j + t)], xi = Xs[e][2 * (j + t) + 1];
+                const C ph = phg[j + t][mo[u] + P - 1];
+                sx += ph.x * xr + ph.y * xi;  // conj(e) x
+                sy += ph.x * xi - ph.y * xr;
             }
-            orow[e] = s;
+            orow[e] = mkc<C>(sx, sy);
         }
     }
 }
@@ -2101,10 +2111,13 @@ const char *trans_stage(const TransBatch &b, const TransTables<R> &tb, int stage
             if (!tb.frH || !tb.frHT || !tb.frC)
                 throw FmmError(-1, "fused translation tiles need their fragment-order tables");
             if (stage != 0) return nullptr;
+            // mode 3: vectors in registers (one wavefront per SIMD); mode 4: vectors in LDS shared by
+            // four wavefronts (levels 6-7 of the 1M L-room: 3.29 ms with the vectors in registers at
+            // two wavefronts per SIMD, 2.88 ms in LDS)
             if (b.mfma == 3) k_tq_rcr<1><<<dim3(ntile, LANE_JT / 8), 64, 0, st>>>(a);
-            else k_tq_rcr<2><<<dim3(ntile, LANE_JT / 8), 64, 0, st>>>(a);
+            else k_tq_lds<double, 4><<<dim3(ntile, LANE_JT / 8), 256, 0, st>>>(a);
             LAUNCH_OK();
-            return b.mfma == 3 ? "k_tq_rcr" : "k_tq_rcr_o2";
+            return b.mfma == 3 ? "k_tq_rcr" : "k_tq_lds";
         }
     }
     if constexpr (sizeof(R) == 4) {
@@ -2115,9 +2128,9 @@ const char *trans_stage(const TransBatch &b, const TransTables<R> &tb, int stage
             if (!tb.frH || !tb.frHT || !tb.frC)
                 throw FmmError(-1, "fused translation tiles need their fragment-order tables");
             if (stage != 0) return nullptr;
-            k_tq_rcr32<<<dim3(ntile, LANE_JT / 8), 128, 0, st>>>(a);
+            k_tq_lds<float, 4><<<dim3(ntile, LANE_JT / 8), 256, 0, st>>>(a);
             LAUNCH_OK();
-            return "k_tq_rcr32";
+            return "k_tq_lds_f32";
         }
     }
     if (b.lane && b.mfma >= 2 && stage < 3) {

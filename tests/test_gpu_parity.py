@@ -555,7 +555,7 @@ def test_register_resident_tiles_vs_lane_tiles_and_oracle(F, mode):
     for nr in (2, 4):
         Yl, Yr = ctx_l.fmmbem_matvec(X[:nr]), ctx_r.fmmbem_matvec(X[:nr])
         assert np.linalg.norm(Yr - Yl) / np.linalg.norm(Yl) < 1e-12, nr
-    # mixed products of one vector: the FP32 kernel with the vectors in LDS (k_tq_rcr32)
+    # mixed products of one vector: the FP32 kernel with the vectors in LDS (k_tq_lds)
     ym_l = ctx_l.fmmbem_matvec(X[0], precision=F.FMMBEM_MIXED)[0]
     ym_r = ctx_r.fmmbem_matvec(X[0], precision=F.FMMBEM_MIXED)[0]
     errm = np.linalg.norm(ym_r - ym_l) / np.linalg.norm(ym_l)
