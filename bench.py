@@ -419,7 +419,7 @@ def main():
         with open(args.shapes_out, "w") as fh:
             json.dump(shapes, fh)
     for s in shapes:
-        log(f"  tiles L{s['level']} {s['kind']}: {(('mfma', 'fused', 'fused-reg', 'fused-reg-o2')[s['mfma'] - 1] if s['mfma'] else 'lane') if s['lane'] else ('whole' if s['whole'] else 'degree')} "
+        log(f"  tiles L{s['level']} {s['kind']}: {(('mfma', 'fused', 'fused-reg', 'fused-lds')[s['mfma'] - 1] if s['mfma'] else 'lane') if s['lane'] else ('whole' if s['whole'] else 'degree')} "
             f"JT {s['jt']} jobs {s['jobs']} {s['ms']:.3f} ms")
 
     dev = torch.device("cuda:0")
