@@ -526,9 +526,10 @@ def test_fused_tiles_match_lane_tiles(F, prec):
 
 @pytest.mark.parametrize("mode", [3, 4])
 def test_register_resident_tiles_vs_lane_tiles_and_oracle(F, mode):
-    """The register-resident fused translation tiles (p = 16; modes 3 and 4 differ only in the
-    registers the compiler may use) against the three-pass lane kernels on the 6x5x3 m room at
-    1 kHz: FP64 products of one vector agree to rounding (1e-12) and with the oracle's rows (1e-6);
+    """The fused p = 16 translation tiles (mode 3: each wavefront's 8 jobs' vectors in its
+    registers; mode 4: 8 jobs' vectors in LDS shared by four wavefronts) against the three-pass lane
+    kernels on the 6x5x3 m room at 1 kHz: FP64 products of one vector agree to rounding (1e-12) and
+    with the oracle's rows (1e-6);
     products of 2 and 4 vectors and mixed products of such batches run the LDS-resident fused
     kernel instead (1e-12 / FP32 rounding against the lane kernels); a mixed product of one vector
     runs the FP32 register-resident shape (vectors in LDS): FP32 rounding against the lane kernels,
