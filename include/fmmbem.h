@@ -130,8 +130,8 @@ typedef struct {
                             for every job-tile batch; 0 never; default 1 */
     int fused;           /* lane batches with p_src = p_tgt = p <= 16 may run all three stages in
                             one kernel on matrix cores: with the jobs' vectors resident in LDS
-                            (any such p; at p = 16 for products of one vector, 8 jobs' vectors
-                            shared by the wavefronts of a workgroup, fixed rule at p = 16), or,
+                            (any such p; at p = 16, 8 jobs' vectors of one right-hand side shared
+                            by the wavefronts of a workgroup, fixed rule at p = 16), or,
                             for FP64 products of one vector at p = 16, resident in the registers
                             of the wavefront that transforms them.  1: under the fixed rule and
                             as autotuner candidates (timed in FP64), and in mixed-precision
@@ -427,8 +427,8 @@ int fmmbem_near_entries(fmmbem_ctx *ctx, int64_t *nnz, int64_t *rows, int64_t *c
  * lane kernels, 1 matrix-core tiles stage by stage, 2 the fused LDS-resident kernel of 16 or 32
  * jobs per workgroup, 3 the fused kernel with each wavefront's 8 jobs' vectors in its registers
  * (FP64 products of one vector), 4 the fused kernel with 8 jobs' vectors in LDS shared by four
- * wavefronts; 3 and 4 apply to products of one vector at p = 16, other
- * products of the batch run mode 2, and FP32 products run mode 4 for mode 3), and the measured
+ * wavefronts, one right-hand side per workgroup; 3 and 4 apply at p = 16, products of several
+ * vectors run mode 2 for mode 3, and FP32 products run mode 4 for mode 3), and the measured
  * FP64 time of the batch's four stages (0 when not measured). */
 typedef struct {
     int32_t level, kind, lane, whole, jt, mfma;

@@ -283,8 +283,8 @@ static void direction_phases(int PH, std::vector<double2> &A) {
 static bool fused_ok(const TransBatch &b) {
     return b.psrc == b.ptgt && b.PT == b.P && b.P <= trans_fused_pmax();
 }
-// the register-resident fused tiles (FP64 products of one vector; other products of such a batch
-// run the LDS-resident fused kernel)
+// the p = 16 fused tiles (mode 3: FP64 products of one vector in registers, other products of such
+// a batch in LDS; mode 4: every product, the vectors in LDS)
 static bool rcr_ok(const TransBatch &b) { return fused_ok(b) && b.P == trans_rcr_p(); }
 
 // Tile layout of a sorted job list for the batch's shape (JT, whole, lane): classes padded to

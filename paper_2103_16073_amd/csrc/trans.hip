@@ -1763,8 +1763,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, OC
     });
 }
 
-// The same fused translation with the vectors in LDS (p = 16, one vector; FP64 and FP32): one
-// workgroup = 8 jobs of a 64-job tile as in k_tq_rcr, but the jobs' vectors live in LDS (256
+// The same fused translation with the vectors in LDS (p = 16, FP64 and FP32, any number of
+// right-hand sides: a workgroup per vector): one workgroup = 8 jobs of a 64-job tile as in k_tq_rcr, but the jobs' vectors live in LDS (256
 // coefficients x 16 columns: 33 KB in FP64, 16 KB in FP32) instead of registers, shared by NW
 // wavefronts that take the degrees (orders) n = h mod NW each.  Every step reads its B operands
 // from LDS in the matrix-core layout (K row 4 i + g of chunk i in lane group g), the partner column
@@ -1797,25 +1797,28 @@ __global__ void __launch_bounds__(64 * NW) k_tq_lds(TransArgsT<R> a) {
     __shared__ int segl[8];
     int tile, part;
     xcd_block(tile, part);
-    const int64_t J0 = (int64_t)tile * LANE_JT + part * 8;
-    if (J0 >= a.njob) return;  // the whole workgroup
+    // several right-hand sides: virtual tile t holds vector t % nr of the 64 real jobs of tile t / nr
+    // (a workgroup takes 8 real jobs of one vector, so a run of one target stays in its LDS)
+    const int nr = a.nr, rt = tile / nr, rv = tile - rt * nr;
+    const int64_t nj = a.njob / nr, J0 = (int64_t)rt * LANE_JT + part * 8;
+    if (J0 >= nj) return;  // the whole workgroup
     // NW wavefronts share the 8 jobs' vectors: wavefront h takes the degrees (orders) n = h mod NW of
     // every step, and the jobs JW h .. JW h + JW - 1 of the first and last steps
     const int tid = threadIdx.x, lane = tid & 63, h = tid >> 6, g = lane >> 4, col = lane & 15, im = col & 1;
     const int phs = 2 * a.PH + 1;
     if (tid < 8) {
-        const int64_t Jv = J0 + tid, Jc = Jv < a.njob ? Jv : a.njob - 1;
-        soff[tid] = (int64_t)a.jsrc[Jc] * P2;
-        segl[tid] = Jv < a.njob ? a.jseg[Jv] : 0;
+        const int64_t Jv = J0 + tid, Jc = Jv < nj ? Jv : nj - 1;
+        soff[tid] = ((int64_t)a.jsrc[Jc] * nr + rv) * P2;  // sources: nr vectors per box
+        segl[tid] = Jv < nj ? a.jseg[Jv] : 0;
     }
     if (h == 0) Xs[P2 + g][col] = R(0);
     for (int e = tid; e < 8 * NPH; e += 64 * NW) {
         const int j = e / NPH, q = e - j * NPH;
-        const int64_t Jv = J0 + j, Jc = Jv < a.njob ? Jv : a.njob - 1;
+        const int64_t Jv = J0 + j, Jc = Jv < nj ? Jv : nj - 1;
         phg[j][q] = a.ph[(int64_t)a.jdir[Jc] * phs + a.PH - (P - 1) + q];
     }
     __syncthreads();
-    const int tr = a.tile_rot[tile], tc = a.tile_coax[tile];
+    const int tr = a.tile_rot[rt], tc = a.tile_coax[rt];
     const R *FF = a.frHT + (int64_t)tr * TF_FR_ROT + lane;  // forward: H (from HT's fragments)
     const R *FB = a.frH + (int64_t)tr * TF_FR_ROT + lane;   // back: H^T
     const R *FC = a.frC + (int64_t)tc * TF_FR_COAX + lane;
@@ -1961,7 +1964,7 @@ __global__ void __launch_bounds__(64 * NW) k_tq_lds(TransArgsT<R> a) {
     for (int jj = 0; jj < JW; ++jj) {
         const int j = JW * h + jj, len = segl[j];
         if (len == 0) continue;  // uniform: not a run's first job
-        C *orow = a.W1 + (J0 + j) * (int64_t)P2;
+        C *orow = a.W1 + ((J0 + j) * nr + rv) * (int64_t)P2;  // the row of virtual job (J0 + j) nr + rv
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int e = lane + 64 * u;
@@ -2104,8 +2107,8 @@ const char *trans_stage(const TransBatch &b, const TransTables<R> &tb, int stage
     const bool f32 = sizeof(R) == 4;
     const char *name = "";
     if constexpr (sizeof(R) == 8) {
-        if (b.lane && b.mfma >= 3 && stage < 3 && nr == 1 && b.P == TQ_P) {
-            // register-resident fused tiles: FP64, one vector, p = 16
+        if (b.lane && b.mfma >= 3 && stage < 3 && (nr == 1 || b.mfma == 4) && b.P == TQ_P) {
+            // register-resident fused tiles: FP64, p = 16 (mode 3 one vector, mode 4 any count)
             if (b.JT != LANE_JT || b.psrc != b.ptgt || b.PT != b.P)
                 throw FmmError(-1, "register-resident translation tiles need 64-job tiles and p_src = p_tgt = 16");
             if (!tb.frH || !tb.frHT || !tb.frC)
@@ -2121,8 +2124,8 @@ const char *trans_stage(const TransBatch &b, const TransTables<R> &tb, int stage
         }
     }
     if constexpr (sizeof(R) == 4) {
-        if (b.lane && b.mfma >= 3 && stage < 3 && nr == 1 && b.P == TQ_P) {
-            // register-resident shape in FP32 (mixed products, one vector): vectors in LDS
+        if (b.lane && b.mfma >= 3 && stage < 3 && b.P == TQ_P) {
+            // register-resident shape in FP32 (mixed products): vectors in LDS
             if (b.JT != LANE_JT || b.psrc != b.ptgt || b.PT != b.P)
                 throw FmmError(-1, "register-resident translation tiles need 64-job tiles and p_src = p_tgt = 16");
             if (!tb.frH || !tb.frHT || !tb.frC)
@@ -2134,8 +2137,7 @@ const char *trans_stage(const TransBatch &b, const TransTables<R> &tb, int stage
         }
     }
     if (b.lane && b.mfma >= 2 && stage < 3) {
-        // the fused LDS-resident kernel (and the register-resident shape with several vectors,
-        // where it takes its place)
+        // the fused LDS-resident kernel (and mode 3 with several vectors, where it takes its place)
         // the fused kernel takes the three stages at stage 0
         // a run of one target (at most SEG_ALIGN real jobs, aligned) lies in one workgroup's jobs
         if (b.JT != LANE_JT || b.psrc != b.ptgt || b.PT != b.P || b.P > TF_PMAX || 32 / nr < SEG_ALIGN)

@@ -530,8 +530,9 @@ def test_register_resident_tiles_vs_lane_tiles_and_oracle(F, mode):
     registers; mode 4: 8 jobs' vectors in LDS shared by four wavefronts) against the three-pass lane
     kernels on the 6x5x3 m room at 1 kHz: FP64 products of one vector agree to rounding (1e-12) and
     with the oracle's rows (1e-6);
-    products of 2 and 4 vectors and mixed products of such batches run the LDS-resident fused
-    kernel instead (1e-12 / FP32 rounding against the lane kernels); a mixed product of one vector
+    products of 2 and 4 vectors agree with the lane kernels to 1e-12 (mode 3 runs the LDS-resident
+    fused kernel for them; mode 4 runs itself, one workgroup per vector, so that each vector of a
+    batched product, FP64 or mixed, equals its product alone); a mixed product of one vector
     runs the FP32 register-resident shape (vectors in LDS): FP32 rounding against the lane kernels,
     1e-4 against the oracle's rows."""
     room, k = synth.config_room(2)
@@ -556,6 +557,14 @@ def test_register_resident_tiles_vs_lane_tiles_and_oracle(F, mode):
     for nr in (2, 4):
         Yl, Yr = ctx_l.fmmbem_matvec(X[:nr]), ctx_r.fmmbem_matvec(X[:nr])
         assert np.linalg.norm(Yr - Yl) / np.linalg.norm(Yl) < 1e-12, nr
+    if mode == 4:
+        for prec, tol in ((F.FMMBEM_FP64, 1e-15), (F.FMMBEM_MIXED, 1e-7)):
+            Y4 = ctx_r.fmmbem_matvec(X, precision=prec)
+            for s in range(4):
+                y1 = ctx_r.fmmbem_matvec(X[s], precision=prec)[0]
+                d = np.linalg.norm(Y4[s] - y1) / np.linalg.norm(y1)
+                print(f"mode 4 precision {prec}: vector {s} of 4 vs alone {d:.1e}")
+                assert d <= tol, (prec, s)
     # mixed products of one vector: the FP32 kernel with the vectors in LDS (k_tq_lds)
     ym_l = ctx_l.fmmbem_matvec(X[0], precision=F.FMMBEM_MIXED)[0]
     ym_r = ctx_r.fmmbem_matvec(X[0], precision=F.FMMBEM_MIXED)[0]
