@@ -1764,7 +1764,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, OC
 }
 
 // The same fused translation with the vectors in LDS (p = 16, FP64 and FP32, any number of
-// right-hand sides: a workgroup per vector): one workgroup = 8 jobs of a 64-job tile as in k_tq_rcr, but the jobs' vectors live in LDS (256
+// right-hand sides: a workgroup per vector): one workgroup = 8 jobs (CB = 1) or 16 jobs (CB = 2:
+// two 16-column blocks, each table fragment feeding two products) of a 64-job tile as in k_tq_rcr, but the jobs' vectors live in LDS (256
 // coefficients x 16 columns: 33 KB in FP64, 16 KB in FP32) instead of registers, shared by NW
 // wavefronts that take the degrees (orders) n = h mod NW each.  Every step reads its B operands
 // from LDS in the matrix-core layout (K row 4 i + g of chunk i in lane group g), the partner column
@@ -1779,40 +1780,42 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC, OC
 // coefficients in the first and last steps, 1.70 ms with two wavefronts, 1.71 -> 1.70 with four;
 // FP64 3.29 ms in registers (k_tq_rcr, two wavefronts per SIMD), 2.88 ms here with four.
 
-template <class R, int NW>
+template <class R, int NW, int CB>
 __global__ void __launch_bounds__(64 * NW) k_tq_lds(TransArgsT<R> a) {
     using C = typename Cx<R>::T;
     using Op = TmOp<R>;
     using v4 = typename Op::v4;
-    constexpr int P = TQ_P, P2 = P * P, NPH = 2 * P - 1, JW = 8 / NW;
+    // CB blocks of 8 jobs (16 columns) per workgroup: every table fragment feeds CB products
+    constexpr int P = TQ_P, P2 = P * P, NPH = 2 * P - 1, NJ = 8 * CB, JW = NJ / NW;
     static_assert(NW == 2 || NW == 4, "two or four wavefronts per workgroup");
+    static_assert(CB == 1 || CB == 2, "one or two column blocks");
     // coefficient (n, m) at row n^2 + n + m, column 2 job + part; rows P2 .. P2 + 3 (zeros) are read
     // past the last degree.  Reads need no branch: rows past a degree or order meet zero columns of
     // the table block (without the branches the reads of a step issue together: 2.58 -> 2.27 ms at
     // levels 6-7 of the 1M L-room); writes past a block stay masked (writing them to spare rows
     // nearly doubles the LDS stores and was slower)
-    __shared__ R Xs[P2 + 4][16];
-    __shared__ C phg[8][NPH];  // e^{i m a_j}
-    __shared__ int64_t soff[8];
-    __shared__ int segl[8];
+    __shared__ R Xs[CB][P2 + 4][16];
+    __shared__ C phg[NJ][NPH];  // e^{i m a_j}
+    __shared__ int64_t soff[NJ];
+    __shared__ int segl[NJ];
     int tile, part;
     xcd_block(tile, part);
     // several right-hand sides: virtual tile t holds vector t % nr of the 64 real jobs of tile t / nr
-    // (a workgroup takes 8 real jobs of one vector, so a run of one target stays in its LDS)
+    // (a workgroup takes 8 CB real jobs of one vector, so a run of one target stays in its LDS)
     const int nr = a.nr, rt = tile / nr, rv = tile - rt * nr;
-    const int64_t nj = a.njob / nr, J0 = (int64_t)rt * LANE_JT + part * 8;
+    const int64_t nj = a.njob / nr, J0 = (int64_t)rt * LANE_JT + part * NJ;
     if (J0 >= nj) return;  // the whole workgroup
     // NW wavefronts share the 8 jobs' vectors: wavefront h takes the degrees (orders) n = h mod NW of
     // every step, and the jobs JW h .. JW h + JW - 1 of the first and last steps
     const int tid = threadIdx.x, lane = tid & 63, h = tid >> 6, g = lane >> 4, col = lane & 15, im = col & 1;
     const int phs = 2 * a.PH + 1;
-    if (tid < 8) {
+    if (tid < NJ) {
         const int64_t Jv = J0 + tid, Jc = Jv < nj ? Jv : nj - 1;
         soff[tid] = ((int64_t)a.jsrc[Jc] * nr + rv) * P2;  // sources: nr vectors per box
         segl[tid] = Jv < nj ? a.jseg[Jv] : 0;
     }
-    if (h == 0) Xs[P2 + g][col] = R(0);
-    for (int e = tid; e < 8 * NPH; e += 64 * NW) {
+    if (h < CB) Xs[h][P2 + g][col] = R(0);
+    for (int e = tid; e < NJ * NPH; e += 64 * NW) {
         const int j = e / NPH, q = e - j * NPH;
         const int64_t Jv = J0 + j, Jc = Jv < nj ? Jv : nj - 1;
         phg[j][q] = a.ph[(int64_t)a.jdir[Jc] * phs + a.PH - (P - 1) + q];
@@ -1835,38 +1838,46 @@ __global__ void __launch_bounds__(64 * NW) k_tq_lds(TransArgsT<R> a) {
     // sources times e^{i m a}, one job after the other (64 consecutive coefficients per load)
 #pragma unroll
     for (int jj = 0; jj < JW; ++jj) {
-        const int j = JW * h + jj;
+        const int j = JW * h + jj, cb = j >> 3, jl = j & 7;
         const C *src = a.src + soff[j];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int e = lane + 64 * u;
             const C x = src[e], ph = phg[j][mo[u] + P - 1];
-            Xs[e][2 * j] = ph.x * x.x - ph.y * x.y;  // scalar accesses only (no type punning of Xs)
-            Xs[e][2 * j + 1] = ph.x * x.y + ph.y * x.x;
+            Xs[cb][e][2 * jl] = ph.x * x.x - ph.y * x.y;  // scalar accesses only (no type punning of Xs)
+            Xs[cb][e][2 * jl + 1] = ph.x * x.y + ph.y * x.x;
         }
     }
     // rotation of degree n on the rows of Xs, in place
     auto rotate = [&](auto nI, const R (&A)[16]) {
         constexpr int n = decltype(nI)::value, KS = tq_dreg(n), RB = (2 * n + 16) / 16, w = 2 * n + 1;
-        R B[KS];
-        tq_for<KS>([&](auto iI) {
-            constexpr int i = decltype(iI)::value;
-            B[i] = Xs[n * n + 4 * i + g][col];  // past the degree: the next one's rows, zero columns of A
-        });
-        v4 acc[RB];
-        tq_for<RB>([&](auto bI) { acc[decltype(bI)::value] = v4{0, 0, 0, 0}; });
-        tq_for<KS>([&](auto iI) {
-            tq_for<RB>([&](auto bI) {
-                constexpr int b = decltype(bI)::value, i = decltype(iI)::value;
-                acc[b] = Op::mma(A[b * 8 + i], B[i], acc[b]);
+        R B[CB][KS];
+        tq_for<CB>([&](auto cI) {
+            tq_for<KS>([&](auto iI) {
+                constexpr int c = decltype(cI)::value, i = decltype(iI)::value;
+                B[c][i] = Xs[c][n * n + 4 * i + g][col];  // past the degree: the next one's rows, zero columns of A
             });
         });
-        tq_for<RB>([&](auto bI) {
-            constexpr int b = decltype(bI)::value;
-            tq_for<4>([&](auto iI) {
-                constexpr int i = decltype(iI)::value;
-                const int r = 16 * b + Op::row(g, i);
-                if (r < w) Xs[n * n + r][col] = acc[b][i];
+        v4 acc[CB][RB];
+        tq_for<CB>([&](auto cI) {
+            tq_for<RB>([&](auto bI) { acc[decltype(cI)::value][decltype(bI)::value] = v4{0, 0, 0, 0}; });
+        });
+        tq_for<KS>([&](auto iI) {
+            tq_for<RB>([&](auto bI) {
+                tq_for<CB>([&](auto cI) {
+                    constexpr int b = decltype(bI)::value, i = decltype(iI)::value, c = decltype(cI)::value;
+                    acc[c][b] = Op::mma(A[b * 8 + i], B[c][i], acc[c][b]);
+                });
+            });
+        });
+        tq_for<CB>([&](auto cI) {
+            tq_for<RB>([&](auto bI) {
+                constexpr int c = decltype(cI)::value, b = decltype(bI)::value;
+                tq_for<4>([&](auto iI) {
+                    constexpr int i = decltype(iI)::value;
+                    const int r = 16 * b + Op::row(g, i);
+                    if (r < w) Xs[c][n * n + r][col] = acc[c][b][i];
+                });
             });
         });
     };
@@ -1907,25 +1918,35 @@ __global__ void __launch_bounds__(64 * NW) k_tq_lds(TransArgsT<R> a) {
             }
             tq_for<(am > 0 ? 2 : 1)>([&](auto sgI) {
                 constexpr int m = decltype(sgI)::value == 0 ? am : -am;
-                R B[KS], Bw[KS];
-                tq_for<KS>([&](auto iI) {
-                    constexpr int i = decltype(iI)::value;
-                    // degrees past 15 read degree 15's row: zero columns of the table block
-                    const int nn = min(am + 4 * i + g, P - 1), row = nn * nn + nn + m;
-                    // X': column 2j holds -Im x_j, column 2j+1 holds Re x_j (the partner column)
-                    B[i] = Xs[row][col];
-                    Bw[i] = swp * Xs[row][col ^ 1];
+                R B[CB][KS], Bw[CB][KS];
+                tq_for<CB>([&](auto cI) {
+                    tq_for<KS>([&](auto iI) {
+                        constexpr int c = decltype(cI)::value, i = decltype(iI)::value;
+                        // degrees past 15 read degree 15's row: zero columns of the table block
+                        const int nn = min(am + 4 * i + g, P - 1), row = nn * nn + nn + m;
+                        // X': column 2j holds -Im x_j, column 2j+1 holds Re x_j (the partner column)
+                        B[c][i] = Xs[c][row][col];
+                        Bw[c][i] = swp * Xs[c][row][col ^ 1];
+                    });
                 });
-                v4 acc = v4{0, 0, 0, 0};
+                v4 acc[CB];
+                tq_for<CB>([&](auto cI) { acc[decltype(cI)::value] = v4{0, 0, 0, 0}; });
                 tq_for<KS>([&](auto iI) {
-                    constexpr int i = decltype(iI)::value;
-                    acc = Op::mma(TF[am][2 * i], B[i], acc);
-                    acc = Op::mma(TF[am][2 * i + 1], Bw[i], acc);
+                    tq_for<CB>([&](auto cI) {
+                        constexpr int c = decltype(cI)::value, i = decltype(iI)::value;
+                        acc[c] = Op::mma(TF[am][2 * i], B[c][i], acc[c]);
+                    });
+                    tq_for<CB>([&](auto cI) {
+                        constexpr int c = decltype(cI)::value, i = decltype(iI)::value;
+                        acc[c] = Op::mma(TF[am][2 * i + 1], Bw[c][i], acc[c]);
+                    });
                 });
-                tq_for<4>([&](auto iI) {
-                    constexpr int i = decltype(iI)::value;
-                    const int r = Op::row(g, i), nn = am + r;
-                    if (r < rows) Xs[nn * nn + nn + m][col] = acc[i];
+                tq_for<CB>([&](auto cI) {
+                    tq_for<4>([&](auto iI) {
+                        constexpr int c = decltype(cI)::value, i = decltype(iI)::value;
+                        const int r = Op::row(g, i), nn = am + r;
+                        if (r < rows) Xs[c][nn * nn + nn + m][col] = acc[c][i];
+                    });
                 });
             });
         });
@@ -1962,7 +1983,7 @@ __global__ void __launch_bounds__(64 * NW) k_tq_lds(TransArgsT<R> a) {
     // (job-major, for the per-target reduction), lane l the coefficients l + 64 u
 #pragma unroll 1
     for (int jj = 0; jj < JW; ++jj) {
-        const int j = JW * h + jj, len = segl[j];
+        const int j = JW * h + jj, len = segl[j], cb = j >> 3, jl = j & 7;  // runs stay in 8-job blocks
         if (len == 0) continue;  // uniform: not a run's first job
         C *orow = a.W1 + ((J0 + j) * nr + rv) * (int64_t)P2;  // the row of virtual job (J0 + j) nr + rv
 #pragma unroll
@@ -1970,7 +1991,7 @@ __global__ void __launch_bounds__(64 * NW) k_tq_lds(TransArgsT<R> a) {
             const int e = lane + 64 * u;
             R sx = R(0), sy = R(0);
             for (int t = 0; t < len; ++t) {
-                const R xr = Xs[e][2 * (j + t)], xi = Xs[e][2 * (j + t) + 1];
+                const R xr = Xs[cb][e][2 * (jl + t)], xi = Xs[cb][e][2 * (jl + t) + 1];
                 const C ph = phg[j + t][mo[u] + P - 1];
                 sx += ph.x * xr + ph.y * xi;  // conj(e) x
                 sy += ph.x * xi - ph.y * xr;
@@ -2118,7 +2139,7 @@ const char *trans_stage(const TransBatch &b, const TransTables<R> &tb, int stage
             // four wavefronts (levels 6-7 of the 1M L-room: 3.29 ms with the vectors in registers at
             // two wavefronts per SIMD, 2.88 ms in LDS)
             if (b.mfma == 3) k_tq_rcr<1><<<dim3(ntile, LANE_JT / 8), 64, 0, st>>>(a);
-            else k_tq_lds<double, 4><<<dim3(ntile, LANE_JT / 8), 256, 0, st>>>(a);
+            else k_tq_lds<double, 4, 1><<<dim3(ntile, LANE_JT / 8), 256, 0, st>>>(a);
             LAUNCH_OK();
             return b.mfma == 3 ? "k_tq_rcr" : "k_tq_lds";
         }
@@ -2131,7 +2152,10 @@ const char *trans_stage(const TransBatch &b, const TransTables<R> &tb, int stage
             if (!tb.frH || !tb.frHT || !tb.frC)
                 throw FmmError(-1, "fused translation tiles need their fragment-order tables");
             if (stage != 0) return nullptr;
-            k_tq_lds<float, 4><<<dim3(ntile, LANE_JT / 8), 256, 0, st>>>(a);
+            // two column blocks: 16 jobs per workgroup (37 KB of LDS, four workgroups per CU); in
+            // FP64 two blocks (75 KB, two workgroups per CU) measured slower than one (3.30 against
+            // 2.92 ms at levels 6-7 of the 1M L-room), in FP32 the mixed product 6.93 -> 6.73 ms
+            k_tq_lds<float, 4, 2><<<dim3(ntile, LANE_JT / 16), 256, 0, st>>>(a);
             LAUNCH_OK();
             return "k_tq_lds_f32";
         }
