@@ -1142,11 +1142,18 @@ __global__ void __launch_bounds__(64) k_l2p(int nleaf, int p, const int32_t *lea
             for (int e = tid; e < NR * pp; e += blockDim.x) Dl[e] = Dg[e];
         __syncthreads();
     }
-    for (int t = ts + tid; t < te; t += 64) {
+    // A leaf of at most 32 (16) targets splits the orders m over 2 (4) lane groups of 32 (16)
+    // targets, group g taking m = g, g + S, ..., and adds the groups' sums at the end (leaves hold
+    // about 34 targets on average: one target per lane leaves half the lanes idle)
+    __shared__ double2 red[64 * NR];
+    const int nt = te - ts, S = nt <= 16 ? 4 : (nt <= 32 ? 2 : 1), TP = 64 / S, g = tid / TP;
+    for (int t0 = ts; t0 < te; t0 += TP) {
+        const int t = t0 + tid % TP;
+        const bool act = t < te;
         double2 far[NR];
 #pragma unroll
         for (int rr = 0; rr < NR; ++rr) far[rr] = cmk(0, 0);
-        if (has_far) {
+        if (has_far && act) {
             const double4 c = ec[t];
             double r, ct, st;
             double2 eph;
@@ -1154,11 +1161,16 @@ __global__ void __launch_bounds__(64) k_l2p(int nleaf, int p, const int32_t *lea
             bessel_j_seq_tab(k * r, p - 1, jb, bc);
             double2 e = cmk(1.0, 0.0);
             double sp = 1.0;
-            for (int mp = 0; mp < p; ++mp) {
-                if (mp > 0) {
-                    e = cmul(e, eph);
-                    sp *= st;
-                }
+            for (int q = 0; q < g; ++q) {
+                e = cmul(e, eph);
+                sp *= st;
+            }
+            for (int mp = g; mp < p; mp += S) {
+                if (mp > g)
+                    for (int q = 0; q < S; ++q) {  // e^{i m phi} and sin^m by the same products as for S = 1
+                        e = cmul(e, eph);
+                        sp *= st;
+                    }
                 double P1 = lt[3 * leg_tri(mp, mp) + 2] * sp, P2 = 0.0;
                 double2 sa[NR], sb[NR];
 #pragma unroll
@@ -1187,6 +1199,17 @@ __global__ void __launch_bounds__(64) k_l2p(int nleaf, int p, const int32_t *lea
                 }
             }
         }
+        if (S > 1) {  // group 0 adds the other groups' sums
+            __syncthreads();
+#pragma unroll
+            for (int rr = 0; rr < NR; ++rr) red[tid * NR + rr] = far[rr];
+            __syncthreads();
+            if (g == 0)
+                for (int gg = 1; gg < S; ++gg)
+#pragma unroll
+                    for (int rr = 0; rr < NR; ++rr) far[rr] = cadd(far[rr], red[(tid + gg * TP) * NR + rr]);
+        }
+        if (!act || g > 0) continue;
         const int64_t u = perm[t];
 #pragma unroll
         for (int rr = 0; rr < NR; ++rr) {
