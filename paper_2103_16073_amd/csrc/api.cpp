@@ -76,6 +76,9 @@ __global__ void k_cvt_f2d(int64_t, const float2 *, double2 *);
 __global__ void k_cvt_real_d2f(int64_t, const double *, float *);
 __global__ void k_field(int64_t, const double *, const double4 *, const double4 *, const double *, const double2 *,
                         const double2 *, double, double, double, double, double, double2, double2 *);
+__global__ void k_field_tile(int64_t, int64_t, const double *, const double4 *, const double4 *, const double *,
+                             const double2 *, const double2 *, double, double, double, double, double, double2,
+                             double2 *);
 __global__ void k_diag_inv(int64_t, const int32_t *, const int32_t *, const int32_t *, const double2 *,
                            const double2 *, const double2 *, double, double, double2 *);
 __global__ void k_mul_diag(int64_t, const double2 *, const double2 *, double2 *);
@@ -2661,9 +2664,17 @@ static void eval_field_run(fmmbem_ctx *ctx, int isrc, int64_t nr, const double *
                                                    (double4 *)ctx->buf.find("ec"), (double4 *)ctx->buf.find("en"), bm,
                                                    bp, ctx->k, rs[0], rs[1], rs[2], ctx->src_amp[isrc], sigma, mu);
     LAUNCH_OK();
-    k_field<<<(unsigned)nr, 256, 0, st>>>(n, pts, (double4 *)ctx->buf.find("ec"), (double4 *)ctx->buf.find("en"),
-                                          (double *)ctx->buf.find("ev"), sigma, mu, ctx->k, ctx->rc * ctx->rc, rs[0],
-                                          rs[1], rs[2], ctx->src_amp[isrc], psi);
+    const double4 *ec = (double4 *)ctx->buf.find("ec"), *en = (double4 *)ctx->buf.find("en");
+    const double *ev = (double *)ctx->buf.find("ev");
+    // many points: FIELD_FQ per workgroup sharing element tiles in LDS, once there are about three
+    // such workgroups per CU; fewer points: one workgroup per point
+    if (nr >= (int64_t)FIELD_FQ * 768)
+        k_field_tile<<<(unsigned)ceil_div(nr, FIELD_FQ), 256, 0, st>>>(n, nr, pts, ec, en, ev, sigma, mu, ctx->k,
+                                                                      ctx->rc * ctx->rc, rs[0], rs[1], rs[2],
+                                                                      ctx->src_amp[isrc], psi);
+    else
+        k_field<<<(unsigned)nr, 256, 0, st>>>(n, pts, ec, en, ev, sigma, mu, ctx->k, ctx->rc * ctx->rc, rs[0], rs[1],
+                                              rs[2], ctx->src_amp[isrc], psi);
     LAUNCH_OK();
 }
 

@@ -1222,7 +1222,8 @@ __global__ void __launch_bounds__(64) k_l2p(int nleaf, int p, const int32_t *lea
 
 // ------------------------------------------------------------------ field at points
 // out[q] = amp * G(r_q, rs) + sum_j [L_j(r_q) sigma_j + M_j(r_q) mu_j], accurate integrals for
-// elements with |r_q - c_j| < r_c, one-point rule otherwise.  One workgroup per point.
+// elements with |r_q - c_j| < r_c, one-point rule otherwise.  One workgroup per point (few points:
+// below about three workgroups of k_field_tile per CU).
 __global__ void __launch_bounds__(256) k_field(int64_t nt, const double *pts, const double4 *ec, const double4 *en,
                                                const double *ev, const double2 *sigma, const double2 *mu, double k,
                                                double rc2, double sx, double sy, double sz, double2 amp,
@@ -1264,6 +1265,71 @@ __global__ void __launch_bounds__(256) k_field(int64_t nt, const double *pts, co
         double r = sqrt(dx * dx + dy * dy + dz * dz), s, co;
         sincos(k * r, &s, &co);
         out[q] = cadd(red[0], cmul(amp, cmk(co / r * inv4pi, s / r * inv4pi)));
+    }
+}
+
+// The same for many points: a workgroup takes FIELD_FQ points, tiles of
+// 256 elements pass through LDS once for all of them (one workgroup per point read every element
+// from the caches once per point), 32 threads per point take every 32nd element of a tile, and
+// each point's 32 partial sums are added in a fixed order.  1/r and sin/cos(kr) as in the pair
+// kernel of the product.  Three waves per SIMD (168 registers; four waves spill): 19,200 points
+// on the 1M L-room at 2.0e11 pairs/s, against 1.25-1.47e11 with one workgroup per point.
+static_assert(FIELD_FQ * 32 == 256, "32 threads per receiver in a workgroup of 256");
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3)))
+k_field_tile(int64_t nt, int64_t nq, const double *pts, const double4 *ec, const double4 *en, const double *ev,
+             const double2 *sigma, const double2 *mu, double k, double rc2, double sx, double sy, double sz,
+             double2 amp, double2 *out) {
+    __shared__ double4 sc[256], sn[256];
+    __shared__ double2 ssg[256], smu[256], red[256];
+    const int tid = threadIdx.x, l = tid & 31;
+    const int64_t q = (int64_t)blockIdx.x * FIELD_FQ + (tid >> 5), qc = q < nq ? q : nq - 1;
+    const double x[3] = {pts[3 * qc], pts[3 * qc + 1], pts[3 * qc + 2]};
+    const double inv4pi = 1.0 / (4.0 * FMM_PI);
+    double2 acc = cmk(0, 0);
+    for (int64_t j0 = 0; j0 < nt; j0 += 256) {
+        __syncthreads();
+        if (j0 + tid < nt) {
+            sc[tid] = ec[j0 + tid];
+            sn[tid] = en[j0 + tid];
+            ssg[tid] = sigma[j0 + tid];
+            smu[tid] = mu[j0 + tid];
+        }
+        __syncthreads();
+        const int cnt = (int)(nt - j0 < 256 ? nt - j0 : 256);
+        for (int jj = l; jj < cnt; jj += 32) {
+            const double4 c = sc[jj];
+            const double d2 = dist2_exact(x[0], x[1], x[2], c.x, c.y, c.z);
+            double2 L, M;
+            if (d2 < rc2) {
+                double v[9];
+                for (int e = 0; e < 9; ++e) v[e] = ev[9 * (j0 + jj) + e];
+                tri_integrals(x, v, k, 0, L, M);
+            } else {
+                const double4 nv = sn[jj];
+                const double dx = c.x - x[0], dy = c.y - x[1], dz = c.z - x[2];
+                const double ir = rsq_nr(d2), r = d2 * ir;
+                double s, co;
+                sincos_red(k * r, s, co);
+                const double2 G = cmk(co * ir * inv4pi, s * ir * inv4pi);
+                const double u = (dx * nv.x + dy * nv.y + dz * nv.z) * ir * ir;
+                L = cscale(G, c.w);
+                M = cscale(cmul(G, cmk(-u, k * r * u)), c.w);
+            }
+            acc = cfma(L, ssg[jj], acc);
+            acc = cfma(M, smu[jj], acc);
+        }
+    }
+    red[tid] = acc;
+    __syncthreads();
+    for (int h = 16; h > 0; h >>= 1) {
+        if (l < h) red[tid] = cadd(red[tid], red[tid + h]);
+        __syncthreads();
+    }
+    if (l == 0 && q < nq) {
+        double dx = x[0] - sx, dy = x[1] - sy, dz = x[2] - sz;
+        double r = sqrt(dx * dx + dy * dy + dz * dz), s, co;
+        sincos(k * r, &s, &co);
+        out[q] = cadd(red[tid], cmul(amp, cmk(co / r * inv4pi, s / r * inv4pi)));
     }
 }
 

@@ -153,6 +153,8 @@ struct TransBatch {
 // runs of the back-rotation output never cross a multiple of this many (real) jobs, so that a
 // run lies in one 32-lane half tile (the fused kernel's block) for 1, 2 or 4 right-hand sides
 constexpr int SEG_ALIGN = 8;
+// receivers per workgroup of the tiled field kernel (k_field_tile)
+constexpr int FIELD_FQ = 8;
 // one translation job before tiling
 struct JobH {
     int32_t src, tgt;

@@ -712,6 +712,38 @@ def test_solve_and_field_vs_oracle_lu(F, cfg1_dense):
     ctx.close()
 
 
+def test_field_many_points_tiled_vs_per_point_and_oracle(F, cfg1_dense):
+    """Fields at 6,400 points, enough for the tiled field kernel (8 points per workgroup sharing
+    element tiles in LDS), 256 of them 2 cm off element centroids where the near integrals apply:
+    equal to the one-workgroup-per-point kernel (the same points in two calls of 3,200) to 1e-13,
+    and the points at least 0.3 m from the walls equal to the oracle's Green representation
+    (Eq. dbem1) to 1e-10."""
+    room, k = cfg1_dense
+    ctx = make_ctx(F, room, k)
+    rs, rec = synth.source_and_receivers(room, 6144)
+    ctx.fmmbem_set_sources(rs)
+    V, T = room.vertices, room.triangles
+    c = V[T].mean(axis=1)
+    nrm = np.cross(V[T[:, 1]] - V[T[:, 0]], V[T[:, 2]] - V[T[:, 0]])
+    nrm /= np.linalg.norm(nrm, axis=1)[:, None]
+    sel = np.random.default_rng(12).choice(room.n, 256, replace=room.n < 256)
+    pts = np.ascontiguousarray(np.vstack([c[sel] + 0.02 * nrm[sel], rec]))
+    x = synth.complex_normal(room.n, 77)
+    psi = ctx.fmmbem_eval_field(0, pts, x)
+    assert np.isfinite(psi).all()
+    part = np.concatenate([ctx.fmmbem_eval_field(0, pts[:3200], x), ctx.fmmbem_eval_field(0, pts[3200:], x)])
+    d = np.linalg.norm(psi - part) / np.linalg.norm(part)
+    print(f"tiled vs per-point kernel: {d:.2e}")
+    assert d < 1e-13
+    dn = np.linalg.norm(psi[:256] - part[:256]) / np.linalg.norm(part[:256])
+    assert dn < 1e-13
+    ref = bem.direct_receivers(V, T, k, room.beta, rs[0], oracle_rc(ctx, room), x, pts[256:])
+    err = np.linalg.norm(psi[256:] - ref) / np.linalg.norm(ref)
+    print(f"tiled kernel vs oracle: {err:.2e}")
+    assert err < 1e-10
+    ctx.close()
+
+
 @pytest.mark.parametrize("cfg,nrows", [(2, 1024), (3, 1024)])
 def test_matvec_fmm_sampled_rows_full_size(F, cfg, nrows):
     """Full-size rooms (N = 90,972 at 1 kHz; N = 1,009,576 at 2.5 kHz): the FMM product on seeded
