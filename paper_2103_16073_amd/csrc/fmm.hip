@@ -31,17 +31,51 @@ __constant__ double GL8W[8] = {0.10122853629037669, 0.22238103445337434, 0.31370
                                0.36268378337836177, 0.36268378337836177, 0.31370664587788705,
                                0.22238103445337434, 0.10122853629037669};
 
-// ------------------------------------------------------------------ accurate element integrals
-// (e^{iz} - 1)/(iz)
-__device__ inline double2 expm1_i_over(double z) {
-    if (fabs(z) < 1e-3) {
-        double z2 = z * z;
-        return cmk(1.0 - z2 / 6.0 + z2 * z2 / 120.0, z / 2.0 - z * z2 / 24.0 + z2 * z2 * z / 720.0);
+// sin and cos of x for |x| <= 1e5 (k r of element pairs): x = q pi/2 + y with pi/2 split in two
+// parts (Cody-Waite), |y| <= pi/4, then the Taylor polynomials of sin y through y^17 and of cos y
+// through y^16 (truncation below 1e-17); the absolute error is a few 1e-16.  Larger arguments use
+// the library routine.
+__device__ inline void sincos_red(double x, double &s, double &c) {
+    if (!(fabs(x) <= 1e5)) {
+        sincos(x, &s, &c);
+        return;
     }
-    double sh = sin(0.5 * z);
-    return cmk(sin(z) / z, 2.0 * sh * sh / z);
+    const double q = rint(x * 0.63661977236758134308);
+    double y = fma(-q, 1.5707963267948966, x);
+    y = fma(-q, 6.123233995736766e-17, y);
+    // sum_i w^i / (2i+1)!  and  sum_i w^i / (2i)!, w = -y^2, as sums of coefficient x power from the
+    // smallest term up: the powers are shared by both sums, and every step adds into its own
+    // accumulator (Horner's steps add a constant held in a register, which the generated code copied
+    // into the destination first: one more instruction per step); same accuracy (1.5e-16 absolute
+    // against extended precision for |x| <= 1e5)
+    const double w = -y * y, w2 = w * w, w3 = w2 * w, w4 = w2 * w2, w5 = w4 * w, w6 = w3 * w3, w7 = w4 * w3,
+                 w8 = w4 * w4;
+    double ts = w8 * (1.0 / 355687428096000.0);
+    ts = fma(1.0 / 1307674368000.0, w7, ts);
+    ts = fma(1.0 / 6227020800.0, w6, ts);
+    ts = fma(1.0 / 39916800.0, w5, ts);
+    ts = fma(1.0 / 362880.0, w4, ts);
+    ts = fma(1.0 / 5040.0, w3, ts);
+    ts = fma(1.0 / 120.0, w2, ts);
+    ts = fma(1.0 / 6.0, w, ts);
+    ts += 1.0;
+    double tc = w8 * (1.0 / 20922789888000.0);
+    tc = fma(1.0 / 87178291200.0, w7, tc);
+    tc = fma(1.0 / 479001600.0, w6, tc);
+    tc = fma(1.0 / 3628800.0, w5, tc);
+    tc = fma(1.0 / 40320.0, w4, tc);
+    tc = fma(1.0 / 720.0, w3, tc);
+    tc = fma(1.0 / 24.0, w2, tc);
+    tc = fma(0.5, w, tc);
+    tc += 1.0;
+    const double sy = y * ts, cy = tc;
+    const int iq = (int)q & 3;
+    const double a = (iq & 1) ? cy : sy, b = (iq & 1) ? sy : cy;  // sin and cos before the signs
+    s = (iq & 2) ? -a : a;
+    c = ((iq + 1) & 2) ? -b : b;
 }
 
+// ------------------------------------------------------------------ accurate element integrals
 // L = int_T G(x,y) dS_y and M = int_T dG/dn_y dS_y for a flat triangle, by polar coordinates
 // about the projection x_p of x on the triangle's plane.  With h the signed height of x and
 // r^2 = rho^2 + h^2 the radial integrals are exact:
@@ -93,23 +127,26 @@ __device__ void tri_integrals(const double *x, const double *v, double k, int se
                 double rho = d * ch;
                 double R = sqrt(rho * rho + h * h);
                 double dR = R - ah;
-                double2 E = expm1_i_over(k * dR);
-                Lacc = cadd(Lacc, cscale(E, w * dR));
-                double sn, cs;
-                sincos(k * R, &sn, &cs);
-                Macc = cadd(Macc, cscale(cmk(cs, sn), w / R));
+                // z = k dR from its half angle: sin z = 2 s c and 1 - cos z = 2 s^2 (no cancellation
+                // at small z); the radial L integral is e^{ik|h|} (sin z + i (1 - cos z)) / k and
+                // e^{ikR} = e^{ik|h|} e^{iz}, the common factor e^{ik|h|} taken once at the end
+                double s, c;
+                sincos_red(0.5 * k * dR, s, c);
+                const double sz = 2.0 * s * c, omc = 2.0 * s * s;
+                Lacc = cadd(Lacc, cmk(w * sz, w * omc));
+                Macc = cadd(Macc, cscale(cmk(1.0 - omc, sz), w / R));
             }
         }
     }
     double sh, ch;
     sincos(k * ah, &sh, &ch);
     double2 eh_ = cmk(ch, sh);
-    Lout = cscale(cmul(eh_, Lacc), 1.0 / (4.0 * FMM_PI));
+    Lout = cscale(cmul(eh_, Lacc), 1.0 / (4.0 * FMM_PI * k));
     if (h == 0.0) {
         Mout = cmk(0, 0);
     } else {
         double sgh = h > 0 ? 1.0 : -1.0;
-        Mout = cadd(cscale(Macc, -h / (4.0 * FMM_PI)), cscale(eh_, sgh * span / (4.0 * FMM_PI)));
+        Mout = cadd(cscale(cmul(eh_, Macc), -h / (4.0 * FMM_PI)), cscale(eh_, sgh * span / (4.0 * FMM_PI)));
     }
 }
 
@@ -287,50 +324,6 @@ __device__ inline double rsq_nr(double d) {
     y = fma(0.5 * y, e, y);
     e = fma(-d * y, y, 1.0);
     return fma(0.5 * y, e, y);
-}
-
-// sin and cos of x for |x| <= 1e5 (k r of element pairs): x = q pi/2 + y with pi/2 split in two
-// parts (Cody-Waite), |y| <= pi/4, then the Taylor polynomials of sin y through y^17 and of cos y
-// through y^16 (truncation below 1e-17); the absolute error is a few 1e-16.  Larger arguments use
-// the library routine.
-__device__ inline void sincos_red(double x, double &s, double &c) {
-    if (!(fabs(x) <= 1e5)) {
-        sincos(x, &s, &c);
-        return;
-    }
-    const double q = rint(x * 0.63661977236758134308);
-    double y = fma(-q, 1.5707963267948966, x);
-    y = fma(-q, 6.123233995736766e-17, y);
-    // sum_i w^i / (2i+1)!  and  sum_i w^i / (2i)!, w = -y^2, as sums of coefficient x power from the
-    // smallest term up: the powers are shared by both sums, and every step adds into its own
-    // accumulator (Horner's steps add a constant held in a register, which the generated code copied
-    // into the destination first: one more instruction per step); same accuracy (1.5e-16 absolute
-    // against extended precision for |x| <= 1e5)
-    const double w = -y * y, w2 = w * w, w3 = w2 * w, w4 = w2 * w2, w5 = w4 * w, w6 = w3 * w3, w7 = w4 * w3,
-                 w8 = w4 * w4;
-    double ts = w8 * (1.0 / 355687428096000.0);
-    ts = fma(1.0 / 1307674368000.0, w7, ts);
-    ts = fma(1.0 / 6227020800.0, w6, ts);
-    ts = fma(1.0 / 39916800.0, w5, ts);
-    ts = fma(1.0 / 362880.0, w4, ts);
-    ts = fma(1.0 / 5040.0, w3, ts);
-    ts = fma(1.0 / 120.0, w2, ts);
-    ts = fma(1.0 / 6.0, w, ts);
-    ts += 1.0;
-    double tc = w8 * (1.0 / 20922789888000.0);
-    tc = fma(1.0 / 87178291200.0, w7, tc);
-    tc = fma(1.0 / 479001600.0, w6, tc);
-    tc = fma(1.0 / 3628800.0, w5, tc);
-    tc = fma(1.0 / 40320.0, w4, tc);
-    tc = fma(1.0 / 720.0, w3, tc);
-    tc = fma(1.0 / 24.0, w2, tc);
-    tc = fma(0.5, w, tc);
-    tc += 1.0;
-    const double sy = y * ts, cy = tc;
-    const int iq = (int)q & 3;
-    const double a = (iq & 1) ? cy : sy, b = (iq & 1) ? sy : cy;  // sin and cos before the signs
-    s = (iq & 2) ? -a : a;
-    c = ((iq + 1) & 2) ? -b : b;
 }
 
 // ------------------------------------------------------------------ P2P + near table
